@@ -1,0 +1,88 @@
+"""Boundary-value problems the oracle solves.
+
+Test infrastructure (see the package docstring).  A Problem bundles the
+discrete model (``fem.Model``) with its Dirichlet data, the optional thermal
+eigenstrain and the damage bounds:
+
+* 2D tension (the traction-type load of Sec. 4.2 on a notched square):
+  u_y = 0 on the bottom edge, u_y = t on the top edge, lateral edges free.
+  The x-translation left free by these conditions is removed by u_x = 0 at
+  the node (0, 0).
+* 3D thermal shock with an exponential temperature profile through x
+  (a variant of Sec. 4.3, eqs. (energytshock), (tempfielderfc)): eps0 =
+  -DT exp(-x / depth) I evaluated at each tetrahedron's centroid (beta = 1),
+  u_x = 0 on the face x = lx; the y/z translations and the rotation about x
+  that remain are removed by u_y = u_z = 0 at (lx, 0, 0) and u_z = 0 at
+  (lx, ly, 0).
+
+Damage bounds, Sec. 1.1 (the set D): alpha_prev <= alpha <= 1.  Nodes of an
+initial notch carry alpha = alpha_prev = 1, so they are fixed.  No damage
+Dirichlet condition is imposed anywhere else.
+"""
+
+import numpy as np
+
+from . import fem, mesh
+
+
+class Problem:
+    def __init__(self, model, fixed, dirichlet, eps0=None):
+        self.model = model
+        self.fixed = fixed                  # bool over d*N displacement DOFs
+        self.free = ~fixed
+        self._dirichlet = dirichlet         # load -> values over d*N (used on fixed DOFs)
+        self._eps0 = eps0                   # load -> [E, nvoigt] or None
+
+    def dirichlet_values(self, load):
+        return self._dirichlet(load)
+
+    def eps0(self, load):
+        return None if self._eps0 is None else self._eps0(load)
+
+
+def tension_2d(nx, ny, lx=1.0, ly=1.0, E=1.0, nu=0.3, Gc=1.0, ell=0.05, k_ell=1e-6,
+               model="AT1", plane_stress=False):
+    X, T = mesh.structured_mesh_2d(nx, ny, lx, ly)
+    M = fem.Model(X, T, E=E, nu=nu, Gc=Gc, ell=ell, k_ell=k_ell, model=model,
+                  plane_stress=plane_stress)
+    N = M.N
+    fixed = np.zeros(2 * N, dtype=bool)
+    bottom = np.flatnonzero(np.isclose(X[:, 1], 0.0))
+    top = np.flatnonzero(np.isclose(X[:, 1], ly))
+    fixed[N + bottom] = True
+    fixed[N + top] = True
+    fixed[0] = True                                         # u_x at node (0,0)
+
+    def dirichlet(t):
+        v = np.zeros(2 * N)
+        v[N + top] = t
+        return v
+
+    return Problem(M, fixed, dirichlet)
+
+
+def thermal_3d(nx, ny, nz, lx=1.0, ly=1.0, lz=0.25, E=1.0, nu=0.3, Gc=1.0, ell=None,
+               k_ell=1e-6, model="AT1", depth=0.05):
+    if ell is None:
+        ell = 4.0 * lx / nx
+    X, T = mesh.structured_mesh_3d(nx, ny, nz, lx, ly, lz)
+    M = fem.Model(X, T, E=E, nu=nu, Gc=Gc, ell=ell, k_ell=k_ell, model=model)
+    N = M.N
+    fixed = np.zeros(3 * N, dtype=bool)
+    right = np.flatnonzero(np.isclose(X[:, 0], lx))
+    fixed[right] = True
+    p0 = mesh.node_id_3d(nx, 0, 0, nx, ny)
+    p1 = mesh.node_id_3d(nx, ny, 0, nx, ny)
+    fixed[N + p0] = True
+    fixed[2 * N + p0] = True
+    fixed[2 * N + p1] = True
+    xc = X[T].mean(axis=1)[:, 0]
+    shape = np.exp(-xc / depth)
+
+    def dirichlet(dT):
+        return np.zeros(3 * N)
+
+    def eps0(dT):
+        return fem.isotropic_eigenstrain(-dT * shape, 3)
+
+    return Problem(M, fixed, dirichlet, eps0)
