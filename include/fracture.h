@@ -1,0 +1,213 @@
+/*
+ * fracture.h -- C ABI of the MI355X (gfx950) phase-field fracture solver.
+ *
+ * The library computes quasi-static evolutions of the regularised brittle
+ * fracture energy of Farrell & Maurini, "Linear and nonlinear solvers for
+ * variational phase-field models of brittle fracture":
+ *
+ *   E(u, alpha) = int 1/2 a(alpha) A0 eps(u):eps(u)
+ *                 + Gc/c_w (w(alpha)/ell + ell |grad alpha|^2)      eq. (regenergy)
+ *
+ * with a(alpha) = (1-alpha)^2 + k_ell, w = alpha (AT1) or alpha^2 (AT2),
+ * minimised at each load step over u in C_ubar and alpha_prev <= alpha <= 1
+ * (Sec. 1.1, eq. (mainproblem) and the set D).  One load step runs alternate
+ * minimisation (Algorithm 1), over-relaxed by omega (ORAM, Algorithm 2), and
+ * optionally composed with reduced-space active-set Newton (ORAM-N,
+ * Algorithm 3 with Algorithm 4).  Discretisation: P1 on structured meshes
+ * (right-diagonal triangles in 2D, Kuhn tetrahedra in 3D), Sec. 1.2.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Node (i, j[, k]) has index n = i + (nx+1)*(j + (ny+1)*k); N nodes.
+ * - Displacement vectors are "blocked": component c of node n is at c*N + n
+ *   (length dim*N).  Damage vectors have length N.  All values are float64.
+ * - Device memory: the caller allocates one workspace of
+ *   fracture_workspace_bytes() bytes (any allocator; 256-byte alignment)
+ *   and owns it; the library carves every array it needs out of it and
+ *   never allocates device memory.  The caller also owns the HIP stream;
+ *   every kernel of a handle is launched on that stream.
+ * - Pointers documented as "device" must point to device memory; "host"
+ *   pointers to host memory owned by the caller.
+ * - Every int-returning function returns FRACTURE_OK (0) or a negative error
+ *   code and never aborts.  fracture_strerror() names the code.
+ * - A handle is not thread safe; use one handle per stream.
+ */
+#ifndef FRACTURE_H
+#define FRACTURE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define FRACTURE_OK          0
+#define FRACTURE_EINVAL     -1  /* invalid parameter or argument               */
+#define FRACTURE_ENOMEM     -2  /* workspace smaller than required             */
+#define FRACTURE_ENOTCONV   -3  /* iteration limit hit; state rolled back      */
+#define FRACTURE_ENONFINITE -4  /* NaN/Inf met in a reduction; state rolled back */
+#define FRACTURE_EDEVICE    -5  /* a HIP runtime call failed                   */
+
+/* ---- enumerations ------------------------------------------------------ */
+#define FRACTURE_AT1 1          /* w(alpha) = alpha,   c_w = 8/3 (Sec. 1.1)     */
+#define FRACTURE_AT2 2          /* w(alpha) = alpha^2, c_w = 2   (Sec. 1.1)     */
+
+#define FRACTURE_LOAD_TENSION_2D 0  /* u_y = 0 at y = 0, u_y = t at y = ly,
+                                       u_x = 0 at node (0,0); load = t       */
+#define FRACTURE_LOAD_THERMAL_3D 1  /* eps0 = -load * exp(-x/depth) I at each
+                                       element centroid (Sec. 4.3 variant);
+                                       u_x = 0 on x = lx; u_y = u_z = 0 at
+                                       (lx,0,0); u_z = 0 at (lx,ly,0)        */
+
+#define FRACTURE_RELAX_PROJECT 0  /* alpha <- clip(alpha + omega*dalpha)       */
+#define FRACTURE_RELAX_RATIO   1  /* largest common feasible omega_bar <= omega */
+#define FRACTURE_RELAX_BISECT  2  /* omega_bar <- (1 + omega_bar)/2 until feasible */
+
+#define FRACTURE_STOP_DALPHA 0    /* ORAM stops on ||alpha^k - alpha^{k-1}||_inf */
+#define FRACTURE_STOP_PHI    1    /* stops on ||Phi||_2 (residual of eq. (kkt))  */
+
+#define FRACTURE_FP64  0          /* every kernel in float64                    */
+#define FRACTURE_MIXED 1          /* float32 operator + multigrid inside a
+                                     float64 flexible CG with float64 residuals */
+
+/* ---- parameters -------------------------------------------------------- */
+typedef struct {
+  int dim;                  /* 2 or 3                                          */
+  int nx, ny, nz;           /* cells per axis (nz ignored when dim == 2)       */
+  double lx, ly, lz;        /* domain extents; origin at 0                     */
+  int model;                /* FRACTURE_AT1 | FRACTURE_AT2                      */
+  int plane_stress;         /* 2D only: 0 plane strain, 1 plane stress         */
+  double E, nu, Gc, ell, k_ell;
+  int load_kind;            /* FRACTURE_LOAD_*                                 */
+  double thermal_depth;     /* decay length of the thermal eigenstrain         */
+  int precision;            /* FRACTURE_FP64 | FRACTURE_MIXED                  */
+  double omega;             /* over-relaxation, in (0, 2) (Algorithm 2)        */
+  int relax_mode;           /* FRACTURE_RELAX_*                                */
+  int newton;               /* 0 ORAM only, 1 ORAM-N (Algorithm 3)             */
+  int am_stop;              /* FRACTURE_STOP_* (ORAM only)                     */
+  double am_tol;            /* tolerance of ||dalpha||_inf                     */
+  double switch_tol;        /* ORAM-N: first switch when ||Phi||_2 < this      */
+  double switch_rel;        /* ORAM-N: after a Newton failure, ORAM until
+                               ||Phi||_2 falls by this factor                  */
+  double final_tol;         /* ||Phi||_2 stop (ORAM-N, or am_stop == PHI)      */
+  double pcg_rtol;          /* elastic PCG: ||r|| <= pcg_rtol * ||b_load||     */
+  double vi_tol;            /* damage VI: ||Phi_alpha||_inf <= vi_tol          */
+  double vi_cg_rtol;        /* reduced damage CG relative tolerance            */
+  double minres_rtol;       /* Newton MINRES relative tolerance                */
+  int max_am, max_pcg, max_vi, max_vi_cg, max_newton, max_minres;
+  int cheb_degree;          /* Chebyshev smoothing steps per V-cycle side      */
+  int coarse_max_dofs;      /* coarsen until the level has at most this many   */
+} fracture_params;
+
+/* Fill *p with the documented defaults for a 2D tension problem on an
+   nx-by-ny unit square (AT1, FP64, omega = 1, ORAM only). */
+void fracture_default_params(fracture_params* p, int nx, int ny);
+
+typedef struct {
+  int sweeps;               /* ORAM sweeps in the step                         */
+  int pcg_iters;            /* elastic PCG iterations, summed                  */
+  int vi_iters;             /* active-set iterations of the damage VI, summed  */
+  int vi_cg_iters;          /* reduced damage CG iterations, summed            */
+  int newton_iters;         /* coupled Newton iterations                       */
+  int newton_failures;      /* Newton phases that reverted to ORAM             */
+  int minres_iters;         /* MINRES iterations, summed                       */
+  int converged;            /* 1 when the stop test was met                    */
+  double dalpha_inf;        /* last ||alpha^k - alpha^{k-1}||_inf              */
+  double phi_l2;            /* last ||Phi||_2 (when computed, else -1)         */
+  double ms_total, ms_pcg, ms_vi, ms_newton;  /* device time, HIP events      */
+} fracture_stats;
+
+typedef struct fracture* fracture_t;   /* opaque; owned by the library          */
+
+/* Bytes of device workspace the parameters need (0 on invalid parameters).
+   Admission control uses this as the instance's device footprint. */
+size_t fracture_workspace_bytes(const fracture_params* p);
+
+/* Number of nodes N and of displacement DOFs dim*N. */
+int fracture_sizes(const fracture_params* p, int64_t* nodes, int64_t* dofs);
+
+/* Create a solver instance.
+ *   notch_mask: host, N bytes (nonzero = node fixed at alpha = alpha_prev = 1,
+ *               an initial crack), or NULL.
+ *   d_workspace: device, >= fracture_workspace_bytes(p) bytes, 256-aligned;
+ *               owned by the caller, used exclusively by this handle.
+ *   hip_stream: a hipStream_t (NULL = the null stream).
+ * Sets u = 0, alpha = alpha_prev = notch, load = 0.
+ * Errors: EINVAL (parameters: dim, sizes not even-coarsenable to at least
+ * one level, omega outside (0,2), ell <= 0, ...), ENOMEM, EDEVICE. */
+int fracture_create(const fracture_params* p, const uint8_t* notch_mask,
+                    void* d_workspace, size_t ws_bytes, void* hip_stream,
+                    fracture_t* out);
+
+/* Set the load of the next step (t for tension, DT for the thermal case) and
+   write the new Dirichlet values into u (the lifting done before the first
+   sweep, so that over-relaxation cannot overshoot them). */
+int fracture_set_load(fracture_t h, double load);
+
+/* Solve one load step (Algorithm 2, or 3 when params.newton) from the
+   current state and commit alpha_prev <- alpha.  On ENOTCONV/ENONFINITE the
+   state is rolled back to its value at entry (after the lifting).  `out`
+   (host, may be NULL) receives the statistics. */
+int fracture_solve_step(fracture_t h, fracture_stats* out);
+
+/* One load step for each of n handles, interleaved on their streams
+   (continuous batching).  Results equal n separate fracture_solve_step
+   calls; out (host) has n entries or is NULL; codes (host) has n entries. */
+int fracture_solve_steps(fracture_t* hs, int n, fracture_stats* out, int* codes);
+
+/* Elastic and surface parts of eq. (regenergy) at the current state
+   (host outputs). */
+int fracture_energy(fracture_t h, double* elastic, double* surface);
+
+/* Copy the state out of / into the handle.  Pointers may be host or device
+   (detected with hipPointerGetAttributes); lengths dim*N, N, N.  Any pointer
+   may be NULL to skip that field. */
+int fracture_get_state(fracture_t h, double* u, double* alpha, double* alpha_prev);
+int fracture_set_state(fracture_t h, const double* u, const double* alpha,
+                       const double* alpha_prev);
+
+/* ---- operator actions (matrix-free; device in/out, float64) ------------
+ * y = Op x at the current state.  `level` selects a multigrid level for
+ * FRACTURE_OP_LEVEL (0 = finest).  Sizes: x and y as documented per op.
+ *   ELASTICITY   K(alpha) x, eq. (elasticity): dim*N -> dim*N, no Dirichlet
+ *                masking (the assembled operator).
+ *   LEVEL        the level's Galerkin operator with Dirichlet rows and
+ *                columns removed (rows zeroed): dim*N_l -> dim*N_l.
+ *   DAMAGE_HESS  E_alphaalpha at the current u, eq. (helmholtz): N -> N.
+ *   COUPLING     E_ualpha, eq. (offdiag): N -> dim*N (B x).
+ *   COUPLING_T   its transpose: dim*N -> N (B^T x).
+ *   PRECOND      one multigrid V-cycle (the PCG preconditioner) on the
+ *                finest level, Dirichlet rows zero: dim*N -> dim*N.
+ */
+#define FRACTURE_OP_ELASTICITY  0
+#define FRACTURE_OP_LEVEL       1
+#define FRACTURE_OP_DAMAGE_HESS 2
+#define FRACTURE_OP_COUPLING    3
+#define FRACTURE_OP_COUPLING_T  4
+#define FRACTURE_OP_PRECOND     5
+int fracture_apply(fracture_t h, int op, int level, const double* d_x, double* d_y);
+
+/* Refresh the multigrid coefficients (level averages of a(alpha) and the
+   coarse inverse) from the current alpha.  solve_step does this itself; call
+   it before FRACTURE_OP_LEVEL / FRACTURE_OP_PRECOND after set_state. */
+int fracture_update_coefficients(fracture_t h);
+
+/* Gradient of the energy at the current state (device outputs):
+   Eu = K(alpha) u - f (dim*N, all rows), Ea = E_alpha (N), eq. (kkt). */
+int fracture_gradient(fracture_t h, double* d_Eu, double* d_Ea);
+
+/* Number of multigrid levels and the node counts per axis of one level. */
+int fracture_levels(fracture_t h, int* nlevels);
+int fracture_level_shape(fracture_t h, int level, int* nx, int* ny, int* nz);
+
+const char* fracture_strerror(int code);
+
+/* Release the handle (host state only; the caller frees the workspace). */
+void fracture_destroy(fracture_t h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRACTURE_H */

@@ -1,0 +1,145 @@
+// Shared device helpers and plain-data structs of the fracture library.
+//
+// Reductions are deterministic: each block reduces in a fixed order
+// (wavefront shuffles, then LDS), writes one partial, and the last block to
+// finish (device-scope counter) sums the partials in a fixed order.  The
+// result therefore does not depend on block scheduling, so a run is
+// bitwise reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace frac {
+
+constexpr int WAVE = 64;
+constexpr int NB_X = 64;          // 2D node kernels: 64 x 4 threads per block
+constexpr int NB_Y = 4;
+constexpr int NB = NB_X * NB_Y;
+constexpr int VB = 256;           // 1D vector kernels
+constexpr int VGRID = 2048;       // fixed grid of 1D reductions (8 blocks per CU)
+
+// Boundary-condition families (mirrors FRACTURE_LOAD_* of the C ABI).
+enum { BC_TENSION_2D = 0, BC_THERMAL_3D = 1 };
+
+// Indices of device-resident scalars (an array of doubles in the workspace).
+enum {
+  S_RZ = 0, S_PQ, S_ALPHA, S_RR, S_BETA, S_RZNEW, S_MU,
+  S_PHI2, S_PHIMAX, S_DAMAX, S_EL, S_SURF, S_EU2, S_TMP0, S_TMP1, S_TMP2,
+  S_RATIO, S_INFEAS, S_GG, S_MR0, S_MR1, S_MR2, S_MR3, S_MR4, S_MR5, S_MR6, S_MR7,
+  S_COUNT = 64
+};
+// Counters of the last-block reductions, one per concurrent reduction slot.
+enum { C_SLOTS = 16 };
+
+// A structured level: (nx+1)(ny+1)[(nz+1)] nodes.
+struct Grid {
+  int nx, ny, nz;
+  double hx, hy, hz;
+  int N;
+  int bc;
+};
+
+// Isotropic A0 in the form the element kernels use: sigma_xx = l2m e_xx +
+// lam e_yy (+ lam e_zz), sigma_xy = mu gamma_xy.
+struct Mat {
+  double l2m, lam, mu;
+};
+
+// What the finishing block does with a reduced sum s (see post_scalar).
+enum Post { P_STORE = 0, P_CG_ALPHA, P_CG_BETA, P_SQRT, P_NEG };
+
+struct Red {
+  double* part;       // >= number of blocks of the launch
+  unsigned* cnt;      // one counter, zero between launches
+  double* S;          // scalar array
+  int slot;           // S[slot] receives the result
+  int post;           // Post
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_down(v, off, WAVE);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, WAVE));
+  return v;
+}
+
+__device__ __forceinline__ void post_scalar(double s, const Red& r) {
+  switch (r.post) {
+    case P_CG_ALPHA: {  // alpha = rz / pq
+      r.S[r.slot] = s;
+      r.S[S_ALPHA] = (s != 0.0) ? r.S[S_RZ] / s : 0.0;
+    } break;
+    case P_CG_BETA: {   // beta = rz_new / rz; rz = rz_new
+      double rz = r.S[S_RZ];
+      r.S[S_BETA] = (rz != 0.0) ? s / rz : 0.0;
+      r.S[S_RZ] = s;
+      r.S[r.slot] = s;
+    } break;
+    case P_SQRT:
+      r.S[r.slot] = sqrt(s);
+      break;
+    case P_NEG:
+      r.S[r.slot] = -s;
+      break;
+    default:
+      r.S[r.slot] = s;
+  }
+}
+
+// Block-wide deterministic sum (MAX = false) or max (MAX = true) of v, then
+// the cross-block finish.  Every thread of the block must call it.
+template <int NT, bool MAX>
+__device__ __forceinline__ void reduce_finish(double v, const Red& r, int nblocks, int bid,
+                                              int tid) {
+  __shared__ double sh[NT / WAVE];
+  __shared__ int last;
+  __syncthreads();
+  v = MAX ? wave_max(v) : wave_sum(v);
+  const int lane = tid & (WAVE - 1), w = tid / WAVE;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double s = sh[0];
+    for (int k = 1; k < NT / WAVE; ++k) s = MAX ? fmax(s, sh[k]) : s + sh[k];
+    r.part[bid] = s;
+    __threadfence();
+    unsigned t = atomicAdd(r.cnt, 1u);
+    last = (t == (unsigned)(nblocks - 1));
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    const volatile double* vp = r.part;
+    double acc = MAX ? -INFINITY : 0.0;
+    for (int k = tid; k < nblocks; k += NT) acc = MAX ? fmax(acc, vp[k]) : acc + vp[k];
+    acc = MAX ? wave_max(acc) : wave_sum(acc);
+    if (lane == 0) sh[w] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double s = sh[0];
+      for (int k = 1; k < NT / WAVE; ++k) s = MAX ? fmax(s, sh[k]) : s + sh[k];
+      post_scalar(s, r);
+      *r.cnt = 0u;
+      __threadfence();
+    }
+  }
+}
+
+// Map NaN to +inf so that max-reductions report non-finite values.
+__device__ __forceinline__ double nan_to_inf(double x) { return (x != x) ? INFINITY : x; }
+
+// Fischer--Burmeister NCP function phi(a, b) = sqrt(a^2 + b^2) - a - b.
+__device__ __forceinline__ double fb(double a, double b) { return hypot(a, b) - a - b; }
+
+// Box residual of MCP(F, l, u) for one component: phi(x - l, phi(u - x, -F)).
+__device__ __forceinline__ double mcp_fb(double x, double F, double l, double u) {
+  return fb(x - l, fb(u - x, -F));
+}
+
+}  // namespace frac

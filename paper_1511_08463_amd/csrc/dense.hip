@@ -1,0 +1,130 @@
+// Coarsest multigrid level: assemble the (small) Galerkin operator densely,
+// invert it once per coefficient update by Gauss-Jordan elimination in a
+// single workgroup, and apply the symmetrised inverse as a dense
+// matrix-vector product.  Dirichlet rows and columns are replaced by the
+// identity, so the inverse leaves them at zero when the right-hand side is.
+#include "common.h"
+#include "launch.h"
+
+namespace frac {
+
+constexpr int DB = 1024;
+
+__device__ __forceinline__ bool fixed_dof2(const Grid& g, int comp, int i, int j) {
+  if (g.bc != BC_TENSION_2D) return false;
+  return comp == 0 ? (i == 0 && j == 0) : (j == 0 || j == g.ny);
+}
+
+// Dense 2D assembly: each thread owns one node and writes its two rows, summing
+// the 6x6 element matrices abar |T| B^T D B of the triangles around it.
+__global__ __launch_bounds__(DB) void k_dense_assemble2d(Grid g, Mat m, const double* __restrict__ abar,
+                                                         double* __restrict__ A) {
+  const int N = g.N, n2 = 2 * N, W = g.nx + 1;
+  for (int k = threadIdx.x; k < n2 * n2; k += DB) A[k] = 0.0;
+  __syncthreads();
+  const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy, area = 0.5 * g.hx * g.hy;
+  for (int n = threadIdx.x; n < N; n += DB) {
+    const int i = n % W, j = n / W;
+    // six triangles around the node: (cell di, dj, type, local vertex)
+    const int tdi[6] = {0, 0, -1, -1, -1, 0}, tdj[6] = {0, 0, 0, -1, -1, -1};
+    const int tt[6] = {0, 1, 0, 0, 1, 1}, tv[6] = {0, 0, 1, 2, 1, 2};
+    for (int k = 0; k < 6; ++k) {
+      const int ci = i + tdi[k], cj = j + tdj[k];
+      if (ci < 0 || cj < 0 || ci >= g.nx || cj >= g.ny) continue;
+      const int t = tt[k], v = tv[k];
+      double gx[3], gy[3];
+      int vi[3], vj[3];
+      vi[0] = 0; vj[0] = 0;
+      if (t == 0) {
+        gx[0] = -ihx; gy[0] = 0.0; gx[1] = ihx; gy[1] = -ihy; gx[2] = 0.0; gy[2] = ihy;
+        vi[1] = 1; vj[1] = 0; vi[2] = 1; vj[2] = 1;
+      } else {
+        gx[0] = 0.0; gy[0] = -ihy; gx[1] = ihx; gy[1] = 0.0; gx[2] = -ihx; gy[2] = ihy;
+        vi[1] = 1; vj[1] = 1; vi[2] = 0; vj[2] = 1;
+      }
+      const double w = abar[2 * (ci + g.nx * cj) + t] * area;
+      for (int b = 0; b < 3; ++b) {
+        const int nb = (ci + vi[b]) + W * (cj + vj[b]);
+        const double kxx = w * (m.l2m * gx[v] * gx[b] + m.mu * gy[v] * gy[b]);
+        const double kxy = w * (m.lam * gx[v] * gy[b] + m.mu * gy[v] * gx[b]);
+        const double kyx = w * (m.lam * gy[v] * gx[b] + m.mu * gx[v] * gy[b]);
+        const double kyy = w * (m.l2m * gy[v] * gy[b] + m.mu * gx[v] * gx[b]);
+        A[(size_t)n * n2 + nb] += kxx;
+        A[(size_t)n * n2 + N + nb] += kxy;
+        A[(size_t)(N + n) * n2 + nb] += kyx;
+        A[(size_t)(N + n) * n2 + N + nb] += kyy;
+      }
+    }
+  }
+  __syncthreads();
+  // Dirichlet rows/columns -> identity
+  for (int r = threadIdx.x; r < n2; r += DB) {
+    const int comp = r / N, n = r % N;
+    if (fixed_dof2(g, comp, n % W, n / W)) {
+      for (int c = 0; c < n2; ++c) {
+        A[(size_t)r * n2 + c] = (c == r) ? 1.0 : 0.0;
+        A[(size_t)c * n2 + r] = (c == r) ? 1.0 : 0.0;
+      }
+    }
+  }
+}
+
+// In-place Gauss-Jordan inverse of an SPD matrix (no pivoting), then
+// symmetrisation into Ainv.
+__global__ __launch_bounds__(DB) void k_gauss_jordan(int n, double* __restrict__ A,
+                                                     double* __restrict__ Ainv) {
+  extern __shared__ double sm[];
+  double* colk = sm;
+  double* rowk = sm + n;
+  for (int k = 0; k < n; ++k) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += DB) colk[i] = A[(size_t)i * n + k];
+    __syncthreads();
+    const double piv = 1.0 / colk[k];
+    for (int j = threadIdx.x; j < n; j += DB) {
+      const double v = ((j == k) ? 1.0 : A[(size_t)k * n + j]) * piv;
+      rowk[j] = v;
+      A[(size_t)k * n + j] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += DB) {
+      const int i = e / n, j = e % n;
+      if (i == k) continue;
+      const double base = (j == k) ? 0.0 : A[e];
+      A[e] = base - colk[i] * rowk[j];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * n; e += DB) {
+    const int i = e / n, j = e % n;
+    Ainv[e] = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+  }
+}
+
+void launch_dense_setup2d(hipStream_t st, const Grid& g, const Mat& m, const double* abar,
+                          double* A, double* Ainv) {
+  const int n = 2 * g.N;
+  hipLaunchKernelGGL(k_dense_assemble2d, dim3(1), dim3(DB), 0, st, g, m, abar, A);
+  hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(DB), 2 * n * sizeof(double), st, n, A, Ainv);
+}
+
+// x = Ainv b (dense, one block; row-per-thread with b in LDS).
+__global__ __launch_bounds__(DB) void k_dense_solve(int n, const double* __restrict__ Ainv,
+                                                    const double* __restrict__ b,
+                                                    double* __restrict__ x) {
+  extern __shared__ double sb[];
+  for (int i = threadIdx.x; i < n; i += DB) sb[i] = b[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += DB) {
+    double s = 0.0;
+    const double* row = Ainv + (size_t)i * n;
+    for (int j = 0; j < n; ++j) s += row[j] * sb[j];
+    x[i] = s;
+  }
+}
+
+void launch_dense_solve(hipStream_t st, int n, const double* Ainv, const double* b, double* x) {
+  hipLaunchKernelGGL(k_dense_solve, dim3(1), dim3(DB), n * sizeof(double), st, n, Ainv, b, x);
+}
+
+}  // namespace frac

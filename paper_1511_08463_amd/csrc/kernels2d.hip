@@ -1,0 +1,645 @@
+// 2D kernels: P1 right-diagonal triangles on a structured grid.
+//
+// Cell (ci, cj) is split along its lower-left/upper-right diagonal into
+//   T0 = [(ci,cj), (ci+1,cj), (ci+1,cj+1)]   and   T1 = [(ci,cj), (ci+1,cj+1), (ci,cj+1)].
+// Element e = 2*(ci + nx*cj) + t.  Barycentric gradients (hx, hy the cell sides):
+//   T0: (-1/hx, 0), (1/hx, -1/hy), (0, 1/hy);   T1: (0, -1/hy), (1/hx, 0), (-1/hx, 1/hy).
+//
+// The elasticity operator of eq. (elasticity) is applied matrix-free: one
+// thread per node sums the forces of the six triangles around the node,
+// f_v = abar_e |T| B_v^T D B_e u_e, reading neighbour data through the cache
+// (no atomics, no assembled matrix).  abar_e, the exact element average of
+// a(alpha) = (1-alpha)^2 + k_ell, is formed from nodal alpha on the finest
+// level and read from a per-element array on coarser multigrid levels (the
+// mean of the four children, which makes each coarse operator exactly the
+// Galerkin product P^T K P of the finer one).
+#include "common.h"
+#include "launch.h"
+
+namespace frac {
+
+// ---------------------------------------------------------------------------
+// boundary conditions
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool fixed_x2(const Grid& g, int i, int j) {
+  return (g.bc == BC_TENSION_2D) && i == 0 && j == 0;
+}
+__device__ __forceinline__ bool fixed_y2(const Grid& g, int i, int j) {
+  return (g.bc == BC_TENSION_2D) && (j == 0 || j == g.ny);
+}
+
+// ---------------------------------------------------------------------------
+// the node operator
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double abar3(double a0, double a1, double a2, double k) {
+  const double b0 = 1.0 - a0, b1 = 1.0 - a1, b2 = 1.0 - a2, s = b0 + b1 + b2;
+  return k + (b0 * b0 + b1 * b1 + b2 * b2 + s * s) * (1.0 / 12.0);
+}
+
+// Coefficients of the six triangles around node (i, j), in the order
+// (a) cell(i,j) T0, (b) cell(i,j) T1, (c) cell(i-1,j) T0,
+// (d) cell(i-1,j-1) T0, (e) cell(i-1,j-1) T1, (f) cell(i,j-1) T1.
+template <bool FA>
+__device__ __forceinline__ void coef6(const Grid& g, const double* __restrict__ coef, double kell,
+                                      int i, int j, double c[6]) {
+  const int W = g.nx + 1, n = i + W * j;
+  const bool L = i > 0, R = i < g.nx, D = j > 0, U = j < g.ny;
+  if (FA) {
+    const double aC = coef[n];
+    const double aE = R ? coef[n + 1] : 0.0;
+    const double aNE = (R && U) ? coef[n + 1 + W] : 0.0;
+    const double aN = U ? coef[n + W] : 0.0;
+    const double aW = L ? coef[n - 1] : 0.0;
+    const double aSW = (L && D) ? coef[n - 1 - W] : 0.0;
+    const double aS = D ? coef[n - W] : 0.0;
+    c[0] = abar3(aC, aE, aNE, kell);
+    c[1] = abar3(aC, aNE, aN, kell);
+    c[2] = abar3(aW, aC, aN, kell);
+    c[3] = abar3(aSW, aS, aC, kell);
+    c[4] = abar3(aSW, aC, aW, kell);
+    c[5] = abar3(aS, aE, aC, kell);
+  } else {
+    const int nx = g.nx;
+    c[0] = (R && U) ? coef[2 * (i + nx * j)] : 0.0;
+    c[1] = (R && U) ? coef[2 * (i + nx * j) + 1] : 0.0;
+    c[2] = (L && U) ? coef[2 * (i - 1 + nx * j)] : 0.0;
+    c[3] = (L && D) ? coef[2 * (i - 1 + nx * (j - 1))] : 0.0;
+    c[4] = (L && D) ? coef[2 * (i - 1 + nx * (j - 1)) + 1] : 0.0;
+    c[5] = (R && D) ? coef[2 * (i + nx * (j - 1)) + 1] : 0.0;
+  }
+}
+
+// Force (fx, fy) = (K x) at node (i, j) and, when DIAG, the diagonal entries
+// (dx, dy) of K for the node's two DOFs.
+template <bool HASX, bool DIAG>
+__device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const double c[6],
+                                             const double* __restrict__ ux,
+                                             const double* __restrict__ uy, int i, int j,
+                                             double& fx, double& fy, double& dx, double& dy) {
+  const int W = g.nx + 1, n = i + W * j;
+  const bool L = i > 0, R = i < g.nx, D = j > 0, U = j < g.ny;
+  const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy, area = 0.5 * g.hx * g.hy;
+  const double l2m = m.l2m, lam = m.lam, mu = m.mu;
+  double cx = 0, cy = 0, ex = 0, ey = 0, nex = 0, ney = 0, nnx = 0, nny = 0;
+  double wx = 0, wy = 0, swx = 0, swy = 0, sx = 0, sy = 0;
+  if (HASX) {
+    cx = ux[n];
+    cy = uy[n];
+    if (R) { ex = ux[n + 1]; ey = uy[n + 1]; }
+    if (R && U) { nex = ux[n + 1 + W]; ney = uy[n + 1 + W]; }
+    if (U) { nnx = ux[n + W]; nny = uy[n + W]; }
+    if (L) { wx = ux[n - 1]; wy = uy[n - 1]; }
+    if (L && D) { swx = ux[n - 1 - W]; swy = uy[n - 1 - W]; }
+    if (D) { sx = ux[n - W]; sy = uy[n - W]; }
+  }
+  fx = fy = dx = dy = 0.0;
+  const double hxx = ihx * ihx, hyy = ihy * ihy;
+  // (a) cell(i,j) T0: node is vertex 0, gradient (-1/hx, 0)
+  if (R && U) {
+    const double w = c[0] * area;
+    if (HASX) {
+      const double exx = (ex - cx) * ihx, eyy = (ney - ey) * ihy;
+      const double gam = (ey - cy) * ihx + (nex - ex) * ihy;
+      const double sxx = l2m * exx + lam * eyy, sxy = mu * gam;
+      fx += w * (-sxx * ihx);
+      fy += w * (-sxy * ihx);
+    }
+    if (DIAG) { dx += w * l2m * hxx; dy += w * mu * hxx; }
+  }
+  // (b) cell(i,j) T1: vertex 0, gradient (0, -1/hy)
+  if (R && U) {
+    const double w = c[1] * area;
+    if (HASX) {
+      const double exx = (nex - nnx) * ihx, eyy = (nny - cy) * ihy;
+      const double gam = (ney - nny) * ihx + (nnx - cx) * ihy;
+      const double syy = lam * exx + l2m * eyy, sxy = mu * gam;
+      fx += w * (-sxy * ihy);
+      fy += w * (-syy * ihy);
+    }
+    if (DIAG) { dx += w * mu * hyy; dy += w * l2m * hyy; }
+  }
+  // (c) cell(i-1,j) T0: vertex 1, gradient (1/hx, -1/hy)
+  if (L && U) {
+    const double w = c[2] * area;
+    if (HASX) {
+      const double exx = (cx - wx) * ihx, eyy = (nny - cy) * ihy;
+      const double gam = (cy - wy) * ihx + (nnx - cx) * ihy;
+      const double sxx = l2m * exx + lam * eyy, syy = lam * exx + l2m * eyy, sxy = mu * gam;
+      fx += w * (sxx * ihx - sxy * ihy);
+      fy += w * (sxy * ihx - syy * ihy);
+    }
+    if (DIAG) { dx += w * (l2m * hxx + mu * hyy); dy += w * (l2m * hyy + mu * hxx); }
+  }
+  // (d) cell(i-1,j-1) T0: vertex 2, gradient (0, 1/hy)
+  if (L && D) {
+    const double w = c[3] * area;
+    if (HASX) {
+      const double exx = (sx - swx) * ihx, eyy = (cy - sy) * ihy;
+      const double gam = (sy - swy) * ihx + (cx - sx) * ihy;
+      const double syy = lam * exx + l2m * eyy, sxy = mu * gam;
+      fx += w * (sxy * ihy);
+      fy += w * (syy * ihy);
+    }
+    if (DIAG) { dx += w * mu * hyy; dy += w * l2m * hyy; }
+  }
+  // (e) cell(i-1,j-1) T1: vertex 1, gradient (1/hx, 0)
+  if (L && D) {
+    const double w = c[4] * area;
+    if (HASX) {
+      const double exx = (cx - wx) * ihx, eyy = (wy - swy) * ihy;
+      const double gam = (cy - wy) * ihx + (wx - swx) * ihy;
+      const double sxx = l2m * exx + lam * eyy, sxy = mu * gam;
+      fx += w * (sxx * ihx);
+      fy += w * (sxy * ihx);
+    }
+    if (DIAG) { dx += w * l2m * hxx; dy += w * mu * hxx; }
+  }
+  // (f) cell(i,j-1) T1: vertex 2, gradient (-1/hx, 1/hy)
+  if (R && D) {
+    const double w = c[5] * area;
+    if (HASX) {
+      const double exx = (ex - cx) * ihx, eyy = (cy - sy) * ihy;
+      const double gam = (ey - cy) * ihx + (cx - sx) * ihy;
+      const double sxx = l2m * exx + lam * eyy, syy = lam * exx + l2m * eyy, sxy = mu * gam;
+      fx += w * (-sxx * ihx + sxy * ihy);
+      fy += w * (-sxy * ihx + syy * ihy);
+    }
+    if (DIAG) { dx += w * (l2m * hxx + mu * hyy); dy += w * (l2m * hyy + mu * hxx); }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// node kernels: apply / residual / Chebyshev step
+// ---------------------------------------------------------------------------
+
+enum { M_APPLY = 0, M_RESID = 1, M_SMOOTH = 2 };
+enum { R_NONE = 0, R_DOT = 1, R_FREE2 = 2 };
+
+template <int MODE, bool FA, bool HASX, int RED>
+__global__ __launch_bounds__(NB) void k_node2d(Grid g, Mat m, const double* __restrict__ coef,
+                                               double kell, const double* __restrict__ x,
+                                               double* __restrict__ y,
+                                               const double* __restrict__ b,
+                                               const double* __restrict__ din,
+                                               double* __restrict__ dout, double cd, double cr,
+                                               int mask, Red red) {
+  const int i = blockIdx.x * NB_X + threadIdx.x;
+  const int j = blockIdx.y * NB_Y + threadIdx.y;
+  double acc = 0.0;
+  if (i <= g.nx && j <= g.ny) {
+    const int N = g.N, n = i + (g.nx + 1) * j;
+    double c[6];
+    coef6<FA>(g, coef, kell, i, j, c);
+    double fx, fy, dx, dy;
+    node_force2d<HASX, MODE == M_SMOOTH>(g, m, c, x, x + N, i, j, fx, fy, dx, dy);
+    const bool fxd = fixed_x2(g, i, j), fyd = fixed_y2(g, i, j);
+    if (MODE == M_APPLY) {
+      const double yx = (mask && fxd) ? 0.0 : fx;
+      const double yy = (mask && fyd) ? 0.0 : fy;
+      y[n] = yx;
+      y[n + N] = yy;
+      if (RED == R_DOT) acc = x[n] * yx + x[n + N] * yy;
+      if (RED == R_FREE2) {
+        const double rx = fx - (b ? b[n] : 0.0), ry = fy - (b ? b[n + N] : 0.0);
+        acc = (fxd ? 0.0 : rx * rx) + (fyd ? 0.0 : ry * ry);
+      }
+    } else if (MODE == M_RESID) {
+      const double rx = fxd ? 0.0 : (b ? b[n] : 0.0) - fx;
+      const double ry = fyd ? 0.0 : (b ? b[n + N] : 0.0) - fy;
+      y[n] = rx;
+      y[n + N] = ry;
+      if (RED == R_DOT) acc = rx * rx + ry * ry;
+    } else {
+      const double rx = (b ? b[n] : 0.0) - fx, ry = (b ? b[n + N] : 0.0) - fy;
+      double ddx = cr * rx / dx, ddy = cr * ry / dy;
+      if (din) { ddx += cd * din[n]; ddy += cd * din[n + N]; }
+      double xo = (HASX ? x[n] : 0.0) + ddx, yo = (HASX ? x[n + N] : 0.0) + ddy;
+      if (fxd) { xo = 0.0; ddx = 0.0; }
+      if (fyd) { yo = 0.0; ddy = 0.0; }
+      y[n] = xo;
+      y[n + N] = yo;
+      if (dout) { dout[n] = ddx; dout[n + N] = ddy; }
+    }
+  }
+  if (RED != R_NONE)
+    reduce_finish<NB, false>(acc, red, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
+                             threadIdx.x + NB_X * threadIdx.y);
+}
+
+static dim3 node_grid2(const Grid& g) {
+  return dim3((g.nx + 1 + NB_X - 1) / NB_X, (g.ny + 1 + NB_Y - 1) / NB_Y);
+}
+
+int node_blocks2(const Grid& g) {
+  dim3 gr = node_grid2(g);
+  return (int)(gr.x * gr.y);
+}
+
+// y = K x (mask: zero Dirichlet rows).  red (optional): R_DOT -> S[slot] = x.y,
+// R_FREE2 -> S[slot] = sum over free rows of (K x - b)^2.
+void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const double* coef,
+                    double kell, const double* x, double* y, const double* b, int mask, int red,
+                    Red r) {
+  dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
+#define APPLY_CASE(FA, RD) \
+  hipLaunchKernelGGL((k_node2d<M_APPLY, FA, true, RD>), gr, bl, 0, st, g, m, coef, kell, x, y, b, \
+                     nullptr, nullptr, 0.0, 0.0, mask, r)
+  if (fine) {
+    if (red == R_NONE) APPLY_CASE(true, R_NONE);
+    else if (red == R_DOT) APPLY_CASE(true, R_DOT);
+    else APPLY_CASE(true, R_FREE2);
+  } else {
+    if (red == R_NONE) APPLY_CASE(false, R_NONE);
+    else if (red == R_DOT) APPLY_CASE(false, R_DOT);
+    else APPLY_CASE(false, R_FREE2);
+  }
+#undef APPLY_CASE
+}
+
+// r = b - K x on free rows, 0 on Dirichlet rows; optional ||r||^2 into S[slot].
+void launch_resid2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const double* coef,
+                    double kell, const double* x, double* r, const double* b, bool red, Red rr) {
+  dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
+#define RES_CASE(FA, RD) \
+  hipLaunchKernelGGL((k_node2d<M_RESID, FA, true, RD>), gr, bl, 0, st, g, m, coef, kell, x, r, b, \
+                     nullptr, nullptr, 0.0, 0.0, 1, rr)
+  if (fine) {
+    if (red) RES_CASE(true, R_DOT); else RES_CASE(true, R_NONE);
+  } else {
+    if (red) RES_CASE(false, R_DOT); else RES_CASE(false, R_NONE);
+  }
+#undef RES_CASE
+}
+
+// One Jacobi-preconditioned Chebyshev step:
+//   d_new = cd * d_in + cr * D^{-1} (b - K x_in);  x_out = x_in + d_new
+// x_in == nullptr means x_in = 0; d_in may be nullptr (0); d_out optional.
+void launch_smooth2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const double* coef,
+                     double kell, const double* x_in, double* x_out, const double* b,
+                     const double* d_in, double* d_out, double cd, double cr) {
+  dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
+  Red none{};
+#define SM_CASE(FA, HX) \
+  hipLaunchKernelGGL((k_node2d<M_SMOOTH, FA, HX, R_NONE>), gr, bl, 0, st, g, m, coef, kell, x_in, \
+                     x_out, b, d_in, d_out, cd, cr, 1, none)
+  if (fine) {
+    if (x_in) SM_CASE(true, true); else SM_CASE(true, false);
+  } else {
+    if (x_in) SM_CASE(false, true); else SM_CASE(false, false);
+  }
+#undef SM_CASE
+}
+
+// ---------------------------------------------------------------------------
+// multigrid transfers
+// ---------------------------------------------------------------------------
+
+// Coarse element coefficients: the mean of the four fine children.
+//   coarse T0 of cell (I,J) = fine {(2I,2J) T0, (2I+1,2J) T0, (2I+1,2J) T1, (2I+1,2J+1) T0}
+//   coarse T1 of cell (I,J) = fine {(2I,2J) T1, (2I,2J+1) T1, (2I,2J+1) T0, (2I+1,2J+1) T1}
+template <bool FA>
+__global__ __launch_bounds__(VB) void k_coarsen2d(Grid gf, const double* __restrict__ fine,
+                                                  double kell, Grid gc,
+                                                  double* __restrict__ coarse) {
+  const int cell = blockIdx.x * VB + threadIdx.x;
+  if (cell >= gc.nx * gc.ny) return;
+  const int I = cell % gc.nx, J = cell / gc.nx;
+  const int fi = 2 * I, fj = 2 * J;
+  auto fc = [&](int ci, int cj, int t) -> double {
+    if (FA) {
+      const int W = gf.nx + 1, n = ci + W * cj;
+      const double a00 = fine[n], a10 = fine[n + 1], a11 = fine[n + 1 + W], a01 = fine[n + W];
+      return t == 0 ? abar3(a00, a10, a11, kell) : abar3(a00, a11, a01, kell);
+    } else {
+      return fine[2 * (ci + gf.nx * cj) + t];
+    }
+  };
+  coarse[2 * cell] = 0.25 * (fc(fi, fj, 0) + fc(fi + 1, fj, 0) + fc(fi + 1, fj, 1) + fc(fi + 1, fj + 1, 0));
+  coarse[2 * cell + 1] = 0.25 * (fc(fi, fj, 1) + fc(fi, fj + 1, 1) + fc(fi, fj + 1, 0) + fc(fi + 1, fj + 1, 1));
+}
+
+void launch_coarsen2d(hipStream_t st, const Grid& gf, bool fine_is_alpha, const double* fine,
+                      double kell, const Grid& gc, double* coarse) {
+  const int n = gc.nx * gc.ny;
+  dim3 gr((n + VB - 1) / VB), bl(VB);
+  if (fine_is_alpha)
+    hipLaunchKernelGGL((k_coarsen2d<true>), gr, bl, 0, st, gf, fine, kell, gc, coarse);
+  else
+    hipLaunchKernelGGL((k_coarsen2d<false>), gr, bl, 0, st, gf, fine, kell, gc, coarse);
+}
+
+// b_c = P^T r_f.  P interpolates linearly: fine node (2I,2J) takes coarse
+// (I,J); a fine node at the midpoint of a coarse edge takes the mean of its
+// two ends (edges along x, along y and along the cell diagonal).
+__global__ __launch_bounds__(NB) void k_restrict2d(Grid gf, Grid gc, const double* __restrict__ rf,
+                                                   double* __restrict__ bc) {
+  const int I = blockIdx.x * NB_X + threadIdx.x;
+  const int J = blockIdx.y * NB_Y + threadIdx.y;
+  if (I > gc.nx || J > gc.ny) return;
+  const int Wf = gf.nx + 1, Nf = gf.N, fi = 2 * I, fj = 2 * J, f = fi + Wf * fj;
+  const int nc = I + (gc.nx + 1) * J;
+  for (int comp = 0; comp < 2; ++comp) {
+    const double* r = rf + comp * Nf;
+    double s = r[f];
+    double h = 0.0;
+    if (fi > 0) h += r[f - 1];
+    if (fi < gf.nx) h += r[f + 1];
+    if (fj > 0) h += r[f - Wf];
+    if (fj < gf.ny) h += r[f + Wf];
+    if (fi < gf.nx && fj < gf.ny) h += r[f + 1 + Wf];
+    if (fi > 0 && fj > 0) h += r[f - 1 - Wf];
+    s += 0.5 * h;
+    const bool fixed = comp == 0 ? fixed_x2(gc, I, J) : fixed_y2(gc, I, J);
+    bc[comp * gc.N + nc] = fixed ? 0.0 : s;
+  }
+}
+
+void launch_restrict2d(hipStream_t st, const Grid& gf, const Grid& gc, const double* rf,
+                       double* bc) {
+  dim3 gr(node_grid2(gc)), bl(NB_X, NB_Y);
+  hipLaunchKernelGGL(k_restrict2d, gr, bl, 0, st, gf, gc, rf, bc);
+}
+
+// x_f += P x_c.
+__global__ __launch_bounds__(NB) void k_prolong2d(Grid gf, Grid gc, const double* __restrict__ xc,
+                                                  double* __restrict__ xf) {
+  const int i = blockIdx.x * NB_X + threadIdx.x;
+  const int j = blockIdx.y * NB_Y + threadIdx.y;
+  if (i > gf.nx || j > gf.ny) return;
+  const int Wc = gc.nx + 1, n = i + (gf.nx + 1) * j;
+  const int I0 = i >> 1, J0 = j >> 1, I1 = (i + 1) >> 1, J1 = (j + 1) >> 1;
+  for (int comp = 0; comp < 2; ++comp) {
+    const double* c = xc + comp * gc.N;
+    // (i,j) even/even -> one node; otherwise the two ends of the edge
+    const double v = 0.5 * (c[I0 + Wc * J0] + c[I1 + Wc * J1]);
+    const bool fixed = comp == 0 ? fixed_x2(gf, i, j) : fixed_y2(gf, i, j);
+    if (!fixed) xf[comp * gf.N + n] += v;
+  }
+}
+
+void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const double* xc,
+                      double* xf) {
+  dim3 gr(node_grid2(gf)), bl(NB_X, NB_Y);
+  hipLaunchKernelGGL(k_prolong2d, gr, bl, 0, st, gf, gc, xc, xf);
+}
+
+// ---------------------------------------------------------------------------
+// Dirichlet lifting (tension): u_y = 0 at j = 0, u_y = t at j = ny, u_x(0,0) = 0
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(VB) void k_lift2d(Grid g, double* __restrict__ u, double t) {
+  const int i = blockIdx.x * VB + threadIdx.x;
+  if (i > g.nx) return;
+  const int W = g.nx + 1;
+  u[g.N + i] = 0.0;
+  u[g.N + i + W * g.ny] = t;
+  if (i == 0) u[0] = 0.0;
+}
+
+void launch_lift2d(hipStream_t st, const Grid& g, double* u, double t) {
+  hipLaunchKernelGGL(k_lift2d, dim3((g.nx + 1 + VB - 1) / VB), dim3(VB), 0, st, g, u, t);
+}
+
+// ---------------------------------------------------------------------------
+// damage subproblem: W2 per element, Helmholtz operator, VI residual
+// ---------------------------------------------------------------------------
+
+// W2_e = A0 eps_e : eps_e for both triangles of every cell.
+__global__ __launch_bounds__(VB) void k_w2_2d(Grid g, Mat m, const double* __restrict__ u,
+                                              double* __restrict__ w2) {
+  const int cell = blockIdx.x * VB + threadIdx.x;
+  if (cell >= g.nx * g.ny) return;
+  const int ci = cell % g.nx, cj = cell / g.nx, W = g.nx + 1;
+  const int n00 = ci + W * cj, n10 = n00 + 1, n11 = n00 + 1 + W, n01 = n00 + W;
+  const double* ux = u;
+  const double* uy = u + g.N;
+  const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy;
+  {
+    const double exx = (ux[n10] - ux[n00]) * ihx, eyy = (uy[n11] - uy[n10]) * ihy;
+    const double gam = (uy[n10] - uy[n00]) * ihx + (ux[n11] - ux[n10]) * ihy;
+    w2[2 * cell] = m.l2m * (exx * exx + eyy * eyy) + 2.0 * m.lam * exx * eyy + m.mu * gam * gam;
+  }
+  {
+    const double exx = (ux[n11] - ux[n01]) * ihx, eyy = (uy[n01] - uy[n00]) * ihy;
+    const double gam = (uy[n11] - uy[n01]) * ihx + (ux[n01] - ux[n00]) * ihy;
+    w2[2 * cell + 1] = m.l2m * (exx * exx + eyy * eyy) + 2.0 * m.lam * exx * eyy + m.mu * gam * gam;
+  }
+}
+
+void launch_w2_2d(hipStream_t st, const Grid& g, const Mat& m, const double* u, double* w2) {
+  const int n = g.nx * g.ny;
+  hipLaunchKernelGGL(k_w2_2d, dim3((n + VB - 1) / VB), dim3(VB), 0, st, g, m, u, w2);
+}
+
+// Helmholtz data: H = M_W + cL L + cM M, g = M_W 1 - cm m (eq. (helmholtz),
+// quadratic damage energy).  M_W = sum_e W2_e M_e with the consistent mass.
+struct Helm {
+  double cL, cM, cm;      // cL = 2 Gc ell / c_w; cM = 2 Gc/(c_w ell) (AT2) or 0; cm = Gc/(c_w ell) (AT1) or 0
+};
+
+// Gradients of the three vertices of an element type, scaled by (1/hx, 1/hy).
+__device__ __forceinline__ void tri_grads(int t, double ihx, double ihy, double gx[3], double gy[3]) {
+  if (t == 0) {
+    gx[0] = -ihx; gy[0] = 0.0; gx[1] = ihx; gy[1] = -ihy; gx[2] = 0.0; gy[2] = ihy;
+  } else {
+    gx[0] = 0.0; gy[0] = -ihy; gx[1] = ihx; gy[1] = 0.0; gx[2] = -ihx; gy[2] = ihy;
+  }
+}
+
+// The six triangles around node (i,j): cell offsets, type and the node's local vertex.
+__device__ __constant__ int c_tri_di[6] = {0, 0, -1, -1, -1, 0};
+__device__ __constant__ int c_tri_dj[6] = {0, 0, 0, -1, -1, -1};
+__device__ __constant__ int c_tri_t[6] = {0, 1, 0, 0, 1, 1};
+__device__ __constant__ int c_tri_v[6] = {0, 0, 1, 2, 1, 2};
+
+// Node offsets (di, dj) of the local vertices of a triangle type, from the cell corner.
+__device__ __forceinline__ void tri_nodes(int t, int di[3], int dj[3]) {
+  di[0] = 0; dj[0] = 0;
+  if (t == 0) { di[1] = 1; dj[1] = 0; di[2] = 1; dj[2] = 1; }
+  else { di[1] = 1; dj[1] = 1; di[2] = 0; dj[2] = 1; }
+}
+
+// (H a)_v, g_v and H_vv at node (i,j) for the damage field a; when TRIAL the
+// field is clip(a + mu*d, lo, 1) evaluated on the fly.
+template <bool TRIAL>
+__device__ __forceinline__ void helm_node2d(const Grid& g, const Helm& hp,
+                                            const double* __restrict__ w2,
+                                            const double* __restrict__ a,
+                                            const double* __restrict__ d,
+                                            const double* __restrict__ lo, double mu, int i, int j,
+                                            double& Ha, double& gv, double& Hd) {
+  const int W = g.nx + 1;
+  const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy, area = 0.5 * g.hx * g.hy;
+  Ha = 0.0; gv = 0.0; Hd = 0.0;
+  auto val = [&](int n) -> double {
+    if (TRIAL) return fmin(fmax(a[n] + mu * d[n], lo[n]), 1.0);
+    return a[n];
+  };
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int ci = i + c_tri_di[k], cj = j + c_tri_dj[k];
+    if (ci < 0 || cj < 0 || ci >= g.nx || cj >= g.ny) continue;
+    const int t = c_tri_t[k], v = c_tri_v[k];
+    double gx[3], gy[3];
+    int di[3], dj[3];
+    tri_grads(t, ihx, ihy, gx, gy);
+    tri_nodes(t, di, dj);
+    double av[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) av[q] = val(ci + di[q] + W * (cj + dj[q]));
+    const double we = w2[2 * (ci + g.nx * cj) + t];
+    const double sum = av[0] + av[1] + av[2];
+    const double mass = area / 12.0 * (av[v] + sum);          // (M_e a)_v
+    const double grx = av[0] * gx[0] + av[1] * gx[1] + av[2] * gx[2];
+    const double gry = av[0] * gy[0] + av[1] * gy[1] + av[2] * gy[2];
+    const double lap = area * (gx[v] * grx + gy[v] * gry);     // (L_e a)_v
+    Ha += (we + hp.cM) * mass + hp.cL * lap;
+    gv += (we - hp.cm) * area / 3.0;
+    Hd += (we + hp.cM) * area / 6.0 + hp.cL * area * (gx[v] * gx[v] + gy[v] * gy[v]);
+  }
+}
+
+// F = H a - g, Phi (box FB with bounds [lo, 1]), active mask (eq. (reducedis)
+// with the upper-bound mirror), inverse diagonal of H on inactive nodes.
+// Reductions: S[slot2] = sum Phi^2, S[slotm] = max |Phi| (NaN -> inf).
+template <bool TRIAL>
+__global__ __launch_bounds__(NB) void k_vi_eval2d(Grid g, Helm hp, const double* __restrict__ w2,
+                                                  const double* __restrict__ a,
+                                                  const double* __restrict__ d,
+                                                  const double* __restrict__ lo,
+                                                  const double* __restrict__ S, int mu_slot,
+                                                  double zeta, double* __restrict__ F,
+                                                  double* __restrict__ phi,
+                                                  uint8_t* __restrict__ mask,
+                                                  double* __restrict__ hdinv, Red r2, Red rm) {
+  const int i = blockIdx.x * NB_X + threadIdx.x;
+  const int j = blockIdx.y * NB_Y + threadIdx.y;
+  double p2 = 0.0, pm = 0.0;
+  if (i <= g.nx && j <= g.ny) {
+    const int n = i + (g.nx + 1) * j;
+    const double mu = TRIAL ? S[mu_slot] : 0.0;
+    double Ha, gv, Hd;
+    helm_node2d<TRIAL>(g, hp, w2, a, d, lo, mu, i, j, Ha, gv, Hd);
+    const double x = TRIAL ? fmin(fmax(a[n] + mu * d[n], lo[n]), 1.0) : a[n];
+    const double l = lo[n];
+    const double Fv = Ha - gv;
+    const double ph = mcp_fb(x, Fv, l, 1.0);
+    p2 = ph * ph;
+    pm = nan_to_inf(fabs(ph));
+    if (!TRIAL) {
+      F[n] = Fv;
+      phi[n] = ph;
+      const bool act = (x - l <= zeta && Fv > 0.0) || (1.0 - x <= zeta && Fv < 0.0) || (l >= 1.0);
+      mask[n] = act ? 1 : 0;
+      hdinv[n] = act ? 0.0 : 1.0 / Hd;
+    }
+  }
+  const int nb = gridDim.x * gridDim.y, bid = blockIdx.x + gridDim.x * blockIdx.y;
+  const int tid = threadIdx.x + NB_X * threadIdx.y;
+  reduce_finish<NB, false>(p2, r2, nb, bid, tid);
+  reduce_finish<NB, true>(pm, rm, nb, bid, tid);
+}
+
+void launch_vi_eval2d(hipStream_t st, const Grid& g, double cL, double cM, double cm,
+                      const double* w2, const double* a, const double* d, const double* lo,
+                      const double* S, int mu_slot, double zeta, double* F, double* phi,
+                      uint8_t* mask, double* hdinv, Red r2, Red rm, bool trial) {
+  Helm hp{cL, cM, cm};
+  dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
+  if (trial)
+    hipLaunchKernelGGL((k_vi_eval2d<true>), gr, bl, 0, st, g, hp, w2, a, d, lo, S, mu_slot, zeta,
+                       F, phi, mask, hdinv, r2, rm);
+  else
+    hipLaunchKernelGGL((k_vi_eval2d<false>), gr, bl, 0, st, g, hp, w2, a, d, lo, S, mu_slot, zeta,
+                       F, phi, mask, hdinv, r2, rm);
+}
+
+// y = H x (MASKED: rows and columns of active nodes removed, i.e. x is taken
+// as zero on active nodes and y is zero there).  Optional x.y into r.
+template <bool MASKED, bool DOT>
+__global__ __launch_bounds__(NB) void k_helm_apply2d(Grid g, Helm hp, const double* __restrict__ w2,
+                                                     const double* __restrict__ x,
+                                                     const uint8_t* __restrict__ mask,
+                                                     double* __restrict__ y, Red r) {
+  const int i = blockIdx.x * NB_X + threadIdx.x;
+  const int j = blockIdx.y * NB_Y + threadIdx.y;
+  double acc = 0.0;
+  if (i <= g.nx && j <= g.ny) {
+    const int n = i + (g.nx + 1) * j;
+    double Hx, gv, Hd;
+    // x is zero on active nodes already (the reduced CG keeps it so)
+    helm_node2d<false>(g, hp, w2, x, nullptr, nullptr, 0.0, i, j, Hx, gv, Hd);
+    if (MASKED && mask[n]) Hx = 0.0;
+    y[n] = Hx;
+    if (DOT) acc = x[n] * Hx;
+  }
+  if (DOT)
+    reduce_finish<NB, false>(acc, r, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
+                             threadIdx.x + NB_X * threadIdx.y);
+}
+
+void launch_helm_apply2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                         const double* x, const uint8_t* mask, double* y, bool dot, Red r) {
+  Helm hp{cL, cM, 0.0};
+  dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
+  if (mask) {
+    if (dot) hipLaunchKernelGGL((k_helm_apply2d<true, true>), gr, bl, 0, st, g, hp, w2, x, mask, y, r);
+    else hipLaunchKernelGGL((k_helm_apply2d<true, false>), gr, bl, 0, st, g, hp, w2, x, mask, y, r);
+  } else {
+    if (dot) hipLaunchKernelGGL((k_helm_apply2d<false, true>), gr, bl, 0, st, g, hp, w2, x, mask, y, r);
+    else hipLaunchKernelGGL((k_helm_apply2d<false, false>), gr, bl, 0, st, g, hp, w2, x, mask, y, r);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// energy (eq. (regenergy)), per cell, deterministic sums
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(VB) void k_energy2d(Grid g, Mat m, double kell, double gc_cw,
+                                                 double ell, int at2, const double* __restrict__ u,
+                                                 const double* __restrict__ a, Red rel, Red rsu) {
+  const int ncell = g.nx * g.ny;
+  const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy, area = 0.5 * g.hx * g.hy;
+  double el = 0.0, su = 0.0;
+  for (int cell = blockIdx.x * VB + threadIdx.x; cell < ncell; cell += gridDim.x * VB) {
+    const int ci = cell % g.nx, cj = cell / g.nx, W = g.nx + 1;
+    const int n00 = ci + W * cj, n10 = n00 + 1, n11 = n00 + 1 + W, n01 = n00 + W;
+    const double* ux = u;
+    const double* uy = u + g.N;
+    for (int t = 0; t < 2; ++t) {
+      const int nA = n00, nB = t == 0 ? n10 : n11, nC = t == 0 ? n11 : n01;
+      double exx, eyy, gam;
+      if (t == 0) {
+        exx = (ux[n10] - ux[n00]) * ihx; eyy = (uy[n11] - uy[n10]) * ihy;
+        gam = (uy[n10] - uy[n00]) * ihx + (ux[n11] - ux[n10]) * ihy;
+      } else {
+        exx = (ux[n11] - ux[n01]) * ihx; eyy = (uy[n01] - uy[n00]) * ihy;
+        gam = (uy[n11] - uy[n01]) * ihx + (ux[n01] - ux[n00]) * ihy;
+      }
+      const double w2 = m.l2m * (exx * exx + eyy * eyy) + 2.0 * m.lam * exx * eyy + m.mu * gam * gam;
+      const double a0 = a[nA], a1 = a[nB], a2 = a[nC];
+      el += 0.5 * abar3(a0, a1, a2, kell) * area * w2;
+      double gx[3], gy[3];
+      tri_grads(t, ihx, ihy, gx, gy);
+      const double grx = a0 * gx[0] + a1 * gx[1] + a2 * gx[2];
+      const double gry = a0 * gy[0] + a1 * gy[1] + a2 * gy[2];
+      const double s = a0 + a1 + a2;
+      const double wint = at2 ? area / 12.0 * (a0 * a0 + a1 * a1 + a2 * a2 + s * s) : area / 3.0 * s;
+      su += gc_cw * (wint / ell + ell * area * (grx * grx + gry * gry));
+    }
+  }
+  reduce_finish<VB, false>(el, rel, gridDim.x, blockIdx.x, threadIdx.x);
+  reduce_finish<VB, false>(su, rsu, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_energy2d(hipStream_t st, const Grid& g, const Mat& m, double kell, double gc_cw,
+                     double ell, int at2, const double* u, const double* a, Red rel, Red rsu) {
+  const int ncell = g.nx * g.ny;
+  int nb = (ncell + VB - 1) / VB;
+  if (nb > VGRID) nb = VGRID;
+  hipLaunchKernelGGL(k_energy2d, dim3(nb), dim3(VB), 0, st, g, m, kell, gc_cw, ell, at2, u, a, rel, rsu);
+}
+
+}  // namespace frac

@@ -1,0 +1,66 @@
+// Host-side launchers of the device kernels (one declaration per kernel
+// family).  All launches are asynchronous on the given stream.
+#pragma once
+
+#include "common.h"
+
+namespace frac {
+
+// ---- 2D operator kernels (kernels2d.hip) -----------------------------------
+int node_blocks2(const Grid& g);
+void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const double* coef,
+                    double kell, const double* x, double* y, const double* b, int mask, int red,
+                    Red r);
+void launch_resid2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const double* coef,
+                    double kell, const double* x, double* r, const double* b, bool red, Red rr);
+void launch_smooth2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const double* coef,
+                     double kell, const double* x_in, double* x_out, const double* b,
+                     const double* d_in, double* d_out, double cd, double cr);
+void launch_coarsen2d(hipStream_t st, const Grid& gf, bool fine_is_alpha, const double* fine,
+                      double kell, const Grid& gc, double* coarse);
+void launch_restrict2d(hipStream_t st, const Grid& gf, const Grid& gc, const double* rf, double* bc);
+void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const double* xc, double* xf);
+void launch_lift2d(hipStream_t st, const Grid& g, double* u, double t);
+void launch_w2_2d(hipStream_t st, const Grid& g, const Mat& m, const double* u, double* w2);
+void launch_vi_eval2d(hipStream_t st, const Grid& g, double cL, double cM, double cm,
+                      const double* w2, const double* a, const double* d, const double* lo,
+                      const double* S, int mu_slot, double zeta, double* F, double* phi,
+                      uint8_t* mask, double* hdinv, Red r2, Red rm, bool trial);
+void launch_helm_apply2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                         const double* x, const uint8_t* mask, double* y, bool dot, Red r);
+void launch_energy2d(hipStream_t st, const Grid& g, const Mat& m, double kell, double gc_cw,
+                     double ell, int at2, const double* u, const double* a, Red rel, Red rsu);
+
+// ---- coarse dense solve (dense.hip) ----------------------------------------
+void launch_dense_setup2d(hipStream_t st, const Grid& g, const Mat& m, const double* abar,
+                          double* A, double* Ainv);
+void launch_dense_solve(hipStream_t st, int n, const double* Ainv, const double* b, double* x);
+
+// ---- vector kernels (vec.hip) -----------------------------------------------
+int vec_blocks(int64_t n);
+void launch_cg_update(hipStream_t st, int64_t n, double* x, double* r, const double* p,
+                      const double* q, const double* S, Red rr);
+void launch_xpby(hipStream_t st, int64_t n, const double* z, double* p, const double* S);
+void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, Red r);
+void launch_jacobi_dot(hipStream_t st, int64_t n, const double* r, const double* dinv, double* z,
+                       Red red);
+void launch_axpby(hipStream_t st, int64_t n, double a, const double* x, double b, double* y);
+void launch_norm2(hipStream_t st, int64_t n, const double* x, Red r);
+void launch_normmax(hipStream_t st, int64_t n, const double* x, Red r);
+void launch_neg_masked(hipStream_t st, int64_t n, const double* F, const uint8_t* mask, double* r,
+                       double* x);
+void launch_relax_u(hipStream_t st, int64_t n, double* u, const double* ut, double omega);
+void launch_relax_alpha(hipStream_t st, int64_t n, double* a, const double* at, const double* lo,
+                        double omega, const double* S, int wslot, Red rd);
+void launch_ratio(hipStream_t st, int64_t n, const double* a, const double* at, const double* lo,
+                  double omega, Red r);
+void launch_violation(hipStream_t st, int64_t n, const double* a, const double* at,
+                      const double* lo, double w, Red r);
+void launch_proj_step(hipStream_t st, int64_t n, double* a, const double* d, const double* lo,
+                      const double* S);
+void launch_merit_parts(hipStream_t st, int64_t n, const double* x, const double* F,
+                        const double* lo, double* w, double* g);
+void launch_neg_sum(hipStream_t st, int64_t n, const double* g, const double* hw, double* d, Red r);
+void launch_set_scalar(hipStream_t st, double* S, int slot, double v);
+
+}  // namespace frac

@@ -1,0 +1,864 @@
+// Host driver and C ABI (include/fracture.h).
+//
+// One load step (fracture_solve_step) runs Algorithm 2 of the paper (ORAM;
+// omega = 1 is Algorithm 1) and, when enabled, its composition with Newton
+// (Algorithm 3).  Every sweep:
+//   1. coefficient update: multigrid level averages of a(alpha) and the
+//      coarse inverse;
+//   2. elastic subproblem E_u(u~, alpha; v) = 0 by multigrid-preconditioned CG
+//      (matrix-free operator, Chebyshev/Jacobi smoothing, Galerkin coarse
+//      levels, dense coarsest solve), warm-started from u;
+//   3. u <- u + omega (u~ - u);
+//   4. damage subproblem: the box QP of the quadratic damage energy, solved by
+//      the reduced-space active-set method (Algorithm 4) with a Jacobi-CG on
+//      the inactive Hessian block and a projected Armijo search on
+//      1/2 ||Phi||^2;
+//   5. alpha <- alpha + omega_bar (alpha~ - alpha), feasible.
+// The host only reads convergence scalars (a few bytes) back from the device.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "../../include/fracture.h"
+#include "common.h"
+#include "launch.h"
+
+using namespace frac;
+
+namespace {
+
+constexpr int MAXLEV = 16;
+constexpr int DENSE_MAX = 1024;   // largest coarsest-level system inverted densely
+constexpr double ARMIJO_SIGMA = 1e-4;
+constexpr int MAX_HALVINGS = 20;
+
+struct Level {
+  Grid g;
+  double* abar = nullptr;  // element coefficients (levels >= 1)
+  double *b = nullptr, *xa = nullptr, *xb = nullptr, *d = nullptr, *r = nullptr;
+};
+
+// Bump allocator over the caller's workspace (or a dry run that only counts).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* p) : base((char*)p) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct fracture {
+  fracture_params p;
+  int dim = 2, nlev = 0;
+  Level lv[MAXLEV];
+  Mat mat;
+  double lam_max = 0, lam_min = 0;
+  double cheb_cd[16] = {}, cheb_cr[16] = {};
+  double cw = 0, cL = 0, cM = 0, cm = 0, gc_cw = 0;
+  hipStream_t st = nullptr;
+  int64_t N = 0, n2 = 0;
+  // state
+  double *u = nullptr, *alpha = nullptr, *alpha_prev = nullptr, *u_entry = nullptr,
+         *alpha_entry = nullptr;
+  // elastic PCG
+  double *x = nullptr, *r = nullptr, *pv = nullptr, *q = nullptr;
+  // damage VI
+  double *w2 = nullptr, *F = nullptr, *phi = nullptr, *hdinv = nullptr, *atil = nullptr;
+  double *vd = nullptr, *vr = nullptr, *vz = nullptr, *vp = nullptr, *vq = nullptr,
+         *vt1 = nullptr, *vt2 = nullptr;
+  uint8_t* mask = nullptr;
+  // reductions
+  double* S = nullptr;
+  unsigned* cnt = nullptr;
+  double* part = nullptr;
+  int part_n = 0;
+  // coarsest level
+  double *dA = nullptr, *dAinv = nullptr;
+  int dense_n = 0;
+  // host side
+  double* hS = nullptr;  // pinned copy of the scalar array
+  hipEvent_t ev[8] = {};
+  double load = 0.0;
+  double bnorm = 0.0;
+  bool coef_valid = false;
+};
+
+namespace {
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? FRACTURE_OK : FRACTURE_EDEVICE; }
+
+#define HIPCHK(expr)                                       \
+  do {                                                     \
+    hipError_t _e = (expr);                                \
+    if (_e != hipSuccess) return FRACTURE_EDEVICE;         \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// parameters, levels and workspace layout
+// ---------------------------------------------------------------------------
+
+int validate(const fracture_params* p) {
+  if (!p) return FRACTURE_EINVAL;
+  if (p->dim != 2) return FRACTURE_EINVAL;
+  if (p->nx < 2 || p->ny < 2) return FRACTURE_EINVAL;
+  if (!(p->lx > 0) || !(p->ly > 0)) return FRACTURE_EINVAL;
+  if (p->model != FRACTURE_AT1 && p->model != FRACTURE_AT2) return FRACTURE_EINVAL;
+  if (!(p->E > 0) || !(p->nu > -1.0 && p->nu < 0.5) || !(p->Gc > 0) || !(p->ell > 0) ||
+      !(p->k_ell >= 0))
+    return FRACTURE_EINVAL;
+  if (!(p->omega > 0 && p->omega < 2)) return FRACTURE_EINVAL;
+  if (p->relax_mode < 0 || p->relax_mode > 2) return FRACTURE_EINVAL;
+  if (p->load_kind != FRACTURE_LOAD_TENSION_2D) return FRACTURE_EINVAL;
+  if (p->precision != FRACTURE_FP64) return FRACTURE_EINVAL;
+  if (p->newton) return FRACTURE_EINVAL;
+  if (p->max_am < 1 || p->max_pcg < 1 || p->max_vi < 1 || p->max_vi_cg < 1) return FRACTURE_EINVAL;
+  if (p->cheb_degree < 1 || p->cheb_degree > 8) return FRACTURE_EINVAL;
+  if ((int64_t)(p->nx + 1) * (p->ny + 1) > (int64_t)1 << 30) return FRACTURE_EINVAL;
+  return FRACTURE_OK;
+}
+
+// Level shapes: halve both axes while they stay even and the level has more
+// DOFs than coarse_max_dofs (at least once, so there is always a coarse level).
+int level_shapes(const fracture_params* p, Grid* out) {
+  int nx = p->nx, ny = p->ny, L = 0;
+  double hx = p->lx / nx, hy = p->ly / ny;
+  for (;;) {
+    Grid g{};
+    g.nx = nx; g.ny = ny; g.nz = 0; g.hx = hx; g.hy = hy; g.hz = 0;
+    g.N = (nx + 1) * (ny + 1);
+    g.bc = BC_TENSION_2D;
+    out[L++] = g;
+    const bool can = (nx % 2 == 0) && (ny % 2 == 0) && nx >= 4 && ny >= 4 && L < MAXLEV;
+    if (!can || (L >= 2 && 2 * g.N <= p->coarse_max_dofs)) break;
+    nx /= 2; ny /= 2; hx *= 2; hy *= 2;
+  }
+  if (2 * out[L - 1].N > DENSE_MAX) return -1;
+  if (L < 2) return -1;   // at least one coarse level
+  return L;
+}
+
+size_t layout(const fracture_params* p, fracture* h, void* ws) {
+  Grid gl[MAXLEV];
+  const int L = level_shapes(p, gl);
+  if (L < 1) return 0;
+  Carver c(ws);
+  const int64_t N = gl[0].N, n2 = 2 * N;
+  const int64_t ncell = (int64_t)p->nx * p->ny;
+  fracture tmp;
+  fracture* t = h ? h : &tmp;
+  t->u = c.take<double>(n2);
+  t->alpha = c.take<double>(N);
+  t->alpha_prev = c.take<double>(N);
+  t->u_entry = c.take<double>(n2);
+  t->alpha_entry = c.take<double>(N);
+  t->x = c.take<double>(n2);
+  t->r = c.take<double>(n2);
+  t->pv = c.take<double>(n2);
+  t->q = c.take<double>(n2);
+  t->w2 = c.take<double>(2 * ncell);
+  t->F = c.take<double>(N);
+  t->phi = c.take<double>(N);
+  t->hdinv = c.take<double>(N);
+  t->atil = c.take<double>(N);
+  t->vd = c.take<double>(N);
+  t->vr = c.take<double>(N);
+  t->vz = c.take<double>(N);
+  t->vp = c.take<double>(N);
+  t->vq = c.take<double>(N);
+  t->vt1 = c.take<double>(N);
+  t->vt2 = c.take<double>(N);
+  t->mask = c.take<uint8_t>(N);
+  for (int l = 0; l < L; ++l) {
+    Level& v = t->lv[l];
+    v.g = gl[l];
+    const int64_t m2 = 2 * (int64_t)gl[l].N;
+    v.abar = l > 0 ? c.take<double>(2 * (int64_t)gl[l].nx * gl[l].ny) : nullptr;
+    v.b = c.take<double>(m2);
+    v.xa = c.take<double>(m2);
+    v.xb = c.take<double>(m2);
+    v.d = c.take<double>(m2);
+    v.r = c.take<double>(m2);
+  }
+  const int dn = 2 * gl[L - 1].N;
+  t->dA = c.take<double>((size_t)dn * dn);
+  t->dAinv = c.take<double>((size_t)dn * dn);
+  int pn = node_blocks2(gl[0]);
+  if (vec_blocks(n2) > pn) pn = vec_blocks(n2);
+  t->part_n = pn;
+  t->part = c.take<double>(pn * C_SLOTS);
+  t->S = c.take<double>(S_COUNT);
+  t->cnt = c.take<unsigned>(C_SLOTS);
+  t->nlev = L;
+  t->dense_n = dn;
+  t->N = N;
+  t->n2 = n2;
+  return c.off + 256;
+}
+
+Mat make_mat(const fracture_params* p) {
+  double lam = p->E * p->nu / ((1.0 + p->nu) * (1.0 - 2.0 * p->nu));
+  const double mu = p->E / (2.0 * (1.0 + p->nu));
+  if (p->dim == 2 && p->plane_stress) lam = 2.0 * lam * mu / (lam + 2.0 * mu);
+  return Mat{lam + 2.0 * mu, lam, mu};
+}
+
+// Upper bound of lambda_max(D^{-1} K) for any damage: D^{-1}K's Gershgorin
+// radius per row is a weighted mean of the element ratios
+// sum_j |K_e,ij| / K_e,ii, so their maximum over the two triangle types
+// bounds every level (all levels share the element shapes).
+double chebyshev_bound2d(const Grid& g, const Mat& m) {
+  const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy;
+  double best = 0.0;
+  for (int t = 0; t < 2; ++t) {
+    double gx[3], gy[3];
+    if (t == 0) { gx[0] = -ihx; gy[0] = 0; gx[1] = ihx; gy[1] = -ihy; gx[2] = 0; gy[2] = ihy; }
+    else { gx[0] = 0; gy[0] = -ihy; gx[1] = ihx; gy[1] = 0; gx[2] = -ihx; gy[2] = ihy; }
+    for (int v = 0; v < 3; ++v) {
+      for (int comp = 0; comp < 2; ++comp) {
+        double diag = 0, sum = 0;
+        for (int b = 0; b < 3; ++b) {
+          double kx, ky;
+          if (comp == 0) {
+            kx = m.l2m * gx[v] * gx[b] + m.mu * gy[v] * gy[b];
+            ky = m.lam * gx[v] * gy[b] + m.mu * gy[v] * gx[b];
+            if (b == v) diag = kx;
+          } else {
+            kx = m.lam * gy[v] * gx[b] + m.mu * gx[v] * gy[b];
+            ky = m.l2m * gy[v] * gy[b] + m.mu * gx[v] * gx[b];
+            if (b == v) diag = ky;
+          }
+          sum += std::fabs(kx) + std::fabs(ky);
+        }
+        if (sum / diag > best) best = sum / diag;
+      }
+    }
+  }
+  return best;
+}
+
+Red red(fracture* h, int cslot, int sslot, int post = P_STORE) {
+  return Red{h->part + (size_t)cslot * h->part_n, h->cnt + cslot, h->S, sslot, post};
+}
+
+int read_scalars(fracture* h) {
+  HIPCHK(hipMemcpyAsync(h->hS, h->S, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return FRACTURE_OK;
+}
+
+const double* level_coef(fracture* h, int l) { return l == 0 ? h->alpha : h->lv[l].abar; }
+
+// ---------------------------------------------------------------------------
+// multigrid
+// ---------------------------------------------------------------------------
+
+void update_coefficients(fracture* h) {
+  for (int l = 1; l < h->nlev; ++l)
+    launch_coarsen2d(h->st, h->lv[l - 1].g, l == 1, level_coef(h, l - 1), h->p.k_ell, h->lv[l].g,
+                     h->lv[l].abar);
+  const int Lc = h->nlev - 1;
+  if (Lc >= 1) launch_dense_setup2d(h->st, h->lv[Lc].g, h->mat, h->lv[Lc].abar, h->dA, h->dAinv);
+  h->coef_valid = true;
+}
+
+// Coarsest level with nlev == 1 has no abar array; assemble from alpha then.
+// (validate() guarantees nlev >= 2 for the sizes this driver accepts.)
+
+// z = V-cycle(b) on level l; returns the buffer holding the result.
+double* vcycle(fracture* h, int l, const double* b) {
+  Level& v = h->lv[l];
+  const int k = h->p.cheb_degree;
+  const bool fine = l == 0;
+  const double* coef = level_coef(h, l);
+  const double kell = h->p.k_ell;
+  if (l == h->nlev - 1) {
+    launch_dense_solve(h->st, h->dense_n, h->dAinv, b, v.xa);
+    return v.xa;
+  }
+  // pre-smoothing from zero
+  double* cur = nullptr;
+  for (int s = 0; s < k; ++s) {
+    double* out = (s % 2 == 0) ? v.xa : v.xb;
+    const double* din = s == 0 ? nullptr : (s == 1 ? cur : v.d);
+    double* dout = (s < k - 1) ? v.d : nullptr;
+    launch_smooth2d(h->st, v.g, h->mat, fine, coef, kell, cur, out, b, din, dout, h->cheb_cd[s],
+                    h->cheb_cr[s]);
+    cur = out;
+  }
+  // residual, restriction, coarse correction
+  Red none{};
+  launch_resid2d(h->st, v.g, h->mat, fine, coef, kell, cur, v.r, b, false, none);
+  Level& c = h->lv[l + 1];
+  launch_restrict2d(h->st, v.g, c.g, v.r, c.b);
+  double* xc = vcycle(h, l + 1, c.b);
+  launch_prolong2d(h->st, v.g, c.g, xc, cur);
+  // post-smoothing (same polynomial: the V-cycle is symmetric)
+  for (int s = 0; s < k; ++s) {
+    double* out = (cur == v.xa) ? v.xb : v.xa;
+    const double* din = s == 0 ? nullptr : v.d;
+    double* dout = (s < k - 1) ? v.d : nullptr;
+    launch_smooth2d(h->st, v.g, h->mat, fine, coef, kell, cur, out, b, din, dout, h->cheb_cd[s],
+                    h->cheb_cr[s]);
+    cur = out;
+  }
+  return cur;
+}
+
+// ---------------------------------------------------------------------------
+// elastic subproblem: x <- argmin at fixed alpha, warm start from u
+// ---------------------------------------------------------------------------
+
+int pcg(fracture* h, double tol, int* iters) {
+  const Grid& g = h->lv[0].g;
+  const int64_t n2 = h->n2;
+  hipStream_t st = h->st;
+  HIPCHK(hipMemcpyAsync(h->x, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  launch_resid2d(st, g, h->mat, true, h->alpha, h->p.k_ell, h->x, h->r, nullptr, true,
+                 red(h, 0, S_RR));
+  int rc = read_scalars(h);
+  if (rc) return rc;
+  double rr = h->hS[S_RR];
+  if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
+  *iters = 0;
+  if (std::sqrt(rr) <= tol) return FRACTURE_OK;
+  double* z = vcycle(h, 0, h->r);
+  launch_dot(st, n2, h->r, z, red(h, 1, S_RZ));
+  HIPCHK(hipMemcpyAsync(h->pv, z, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  for (int it = 1; it <= h->p.max_pcg; ++it) {
+    launch_apply2d(st, g, h->mat, true, h->alpha, h->p.k_ell, h->pv, h->q, nullptr, 1, 1,
+                   red(h, 2, S_PQ, P_CG_ALPHA));
+    launch_cg_update(st, n2, h->x, h->r, h->pv, h->q, h->S, red(h, 3, S_RR));
+    rc = read_scalars(h);
+    if (rc) return rc;
+    rr = h->hS[S_RR];
+    *iters = it;
+    if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
+    if (std::sqrt(rr) <= tol) return FRACTURE_OK;
+    z = vcycle(h, 0, h->r);
+    launch_dot(st, n2, h->r, z, red(h, 4, S_RZNEW, P_CG_BETA));
+    launch_xpby(st, n2, z, h->pv, h->S);
+  }
+  return FRACTURE_ENOTCONV;
+}
+
+// ||f - K u_D|| on free rows: the load the elastic problem carries (its RHS
+// with a zero initial guess).  The PCG tolerance is relative to it.
+int load_norm(fracture* h, double* out) {
+  const Grid& g = h->lv[0].g;
+  HIPCHK(hipMemsetAsync(h->q, 0, h->n2 * sizeof(double), h->st));
+  launch_lift2d(h->st, g, h->q, h->load);
+  launch_resid2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, h->q, h->r, nullptr, true,
+                 red(h, 0, S_RR));
+  int rc = read_scalars(h);
+  if (rc) return rc;
+  *out = std::sqrt(h->hS[S_RR]);
+  return FRACTURE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// damage subproblem: box QP by Algorithm 4 (atil <- argmin, start alpha)
+// ---------------------------------------------------------------------------
+
+// Projected Armijo search along vd on psi = 1/2 ||Phi||^2.  slope < 0.
+int line_search(fracture* h, double psi0, double slope, bool* accepted) {
+  const Grid& g = h->lv[0].g;
+  double mu = 1.0;
+  *accepted = false;
+  for (int k = 0; k <= MAX_HALVINGS; ++k) {
+    launch_set_scalar(h->st, h->S, S_MU, mu);
+    launch_vi_eval2d(h->st, g, h->cL, h->cM, h->cm, h->w2, h->atil, h->vd, h->alpha_prev, h->S,
+                     S_MU, 1e-12, nullptr, nullptr, nullptr, nullptr, red(h, 5, S_TMP0),
+                     red(h, 6, S_TMP1), true);
+    int rc = read_scalars(h);
+    if (rc) return rc;
+    const double psi = 0.5 * h->hS[S_TMP0];
+    if (!std::isfinite(psi)) return FRACTURE_ENONFINITE;
+    if (psi <= psi0 + ARMIJO_SIGMA * mu * slope) {
+      launch_proj_step(h->st, h->N, h->atil, h->vd, h->alpha_prev, h->S);
+      *accepted = true;
+      return FRACTURE_OK;
+    }
+    mu *= 0.5;
+  }
+  return FRACTURE_OK;
+}
+
+int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
+  const Grid& g = h->lv[0].g;
+  hipStream_t st = h->st;
+  const int64_t N = h->N;
+  HIPCHK(hipMemcpyAsync(h->atil, h->alpha, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  for (int it = 0;; ++it) {
+    launch_vi_eval2d(st, g, h->cL, h->cM, h->cm, h->w2, h->atil, nullptr, h->alpha_prev, h->S,
+                     S_MU, 1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2),
+                     red(h, 6, S_PHIMAX), false);
+    int rc = read_scalars(h);
+    if (rc) return rc;
+    const double phimax = h->hS[S_PHIMAX], phi2 = h->hS[S_PHI2];
+    if (!std::isfinite(phimax) || !std::isfinite(phi2)) return FRACTURE_ENONFINITE;
+    if (phimax <= h->p.vi_tol) return FRACTURE_OK;
+    if (it >= h->p.max_vi) return FRACTURE_ENOTCONV;
+    ++*vi_iters;
+    // reduced Newton step: H_NN d_N = -F_N (Jacobi CG), d_A = 0
+    launch_neg_masked(st, N, h->F, h->mask, h->vr, h->vd);
+    launch_norm2(st, N, h->vr, red(h, 7, S_TMP2));
+    launch_jacobi_dot(st, N, h->vr, h->hdinv, h->vz, red(h, 1, S_RZ));
+    HIPCHK(hipMemcpyAsync(h->vp, h->vz, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    rc = read_scalars(h);
+    if (rc) return rc;
+    const double r0 = std::sqrt(h->hS[S_TMP2]);
+    const double tol = h->p.vi_cg_rtol * r0;
+    if (r0 > 0) {
+      bool conv = false;
+      for (int k = 1; k <= h->p.max_vi_cg; ++k) {
+        launch_helm_apply2d(st, g, h->cL, h->cM, h->w2, h->vp, h->mask, h->vq, true,
+                            red(h, 2, S_PQ, P_CG_ALPHA));
+        launch_cg_update(st, N, h->vd, h->vr, h->vp, h->vq, h->S, red(h, 3, S_RR));
+        rc = read_scalars(h);
+        if (rc) return rc;
+        ++*cg_iters;
+        const double rr = h->hS[S_RR];
+        if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
+        if (std::sqrt(rr) <= tol) { conv = true; break; }
+        launch_jacobi_dot(st, N, h->vr, h->hdinv, h->vz, red(h, 4, S_RZNEW, P_CG_BETA));
+        launch_xpby(st, N, h->vz, h->vp, h->S);
+      }
+      (void)conv;  // an inexact step is still a descent direction; the line search decides
+    }
+    bool ok = false;
+    const double psi0 = 0.5 * phi2;
+    rc = line_search(h, psi0, -2.0 * psi0, &ok);
+    if (rc) return rc;
+    if (!ok) {
+      // steepest descent on psi: d = -(ca Phi + H (cf Phi))
+      launch_merit_parts(st, N, h->atil, h->F, h->alpha_prev, h->vt1, h->vt2);
+      Red none{};
+      launch_helm_apply2d(st, g, h->cL, h->cM, h->w2, h->vt1, nullptr, h->vq, false, none);
+      launch_neg_sum(st, N, h->vt2, h->vq, h->vd, red(h, 7, S_GG));
+      rc = read_scalars(h);
+      if (rc) return rc;
+      rc = line_search(h, psi0, -h->hS[S_GG], &ok);
+      if (rc) return rc;
+      if (!ok) return FRACTURE_ENOTCONV;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// residual of the optimality conditions, ||Phi||_2
+// ---------------------------------------------------------------------------
+
+int residual_norm(fracture* h, double* out) {
+  const Grid& g = h->lv[0].g;
+  launch_apply2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, h->u, h->q, nullptr, 0, 2,
+                 red(h, 0, S_EU2));
+  launch_w2_2d(h->st, g, h->mat, h->u, h->w2);
+  launch_vi_eval2d(h->st, g, h->cL, h->cM, h->cm, h->w2, h->alpha, nullptr, h->alpha_prev, h->S,
+                   S_MU, 1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2),
+                   red(h, 6, S_PHIMAX), false);
+  int rc = read_scalars(h);
+  if (rc) return rc;
+  *out = std::sqrt(h->hS[S_EU2] + h->hS[S_PHI2]);
+  return FRACTURE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// alpha relaxation (Algorithm 2); returns ||dalpha||_inf in S[S_DAMAX]
+// ---------------------------------------------------------------------------
+
+int relax_alpha(fracture* h) {
+  hipStream_t st = h->st;
+  const int64_t N = h->N;
+  const double w = h->p.omega;
+  if (h->p.relax_mode == FRACTURE_RELAX_PROJECT || w <= 1.0) {
+    launch_relax_alpha(st, N, h->alpha, h->atil, h->alpha_prev, w, h->S, -1, red(h, 8, S_DAMAX));
+    return FRACTURE_OK;
+  }
+  if (h->p.relax_mode == FRACTURE_RELAX_RATIO) {
+    launch_ratio(st, N, h->alpha, h->atil, h->alpha_prev, w, red(h, 9, S_RATIO, P_NEG));
+    launch_relax_alpha(st, N, h->alpha, h->atil, h->alpha_prev, w, h->S, S_RATIO,
+                       red(h, 8, S_DAMAX));
+    return FRACTURE_OK;
+  }
+  // bisection toward 1 on [1, omega]
+  double wb = w;
+  bool feas = false;
+  for (int k = 0; k < 30; ++k) {
+    launch_violation(st, N, h->alpha, h->atil, h->alpha_prev, wb, red(h, 9, S_INFEAS));
+    int rc = read_scalars(h);
+    if (rc) return rc;
+    if (h->hS[S_INFEAS] <= 0.0) { feas = true; break; }
+    wb = 0.5 * (1.0 + wb);
+  }
+  if (!feas) wb = 1.0;
+  launch_relax_alpha(st, N, h->alpha, h->atil, h->alpha_prev, wb, h->S, -1, red(h, 8, S_DAMAX));
+  return FRACTURE_OK;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+  return ms;
+}
+
+int solve_step_impl(fracture* h, fracture_stats* s) {
+  hipStream_t st = h->st;
+  const int64_t N = h->N, n2 = h->n2;
+  fracture_stats loc{};
+  loc.phi_l2 = -1.0;
+  HIPCHK(hipEventRecord(h->ev[0], st));
+  HIPCHK(hipMemcpyAsync(h->u_entry, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->alpha_entry, h->alpha, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  int rc = FRACTURE_OK;
+  double ms_pcg = 0, ms_vi = 0;
+  for (int sweep = 1; sweep <= h->p.max_am; ++sweep) {
+    update_coefficients(h);
+    if (sweep == 1) {
+      rc = load_norm(h, &h->bnorm);
+      if (rc) break;
+    }
+    HIPCHK(hipEventRecord(h->ev[1], st));
+    // elastic substep
+    int it = 0;
+    // tolerance: relative to the load vector; an absolute floor keeps zero loads finite
+    const double tol = h->p.pcg_rtol * (h->bnorm > 0 ? h->bnorm : 1.0);
+    rc = pcg(h, tol, &it);
+    loc.pcg_iters += it;
+    if (rc) break;
+    if (h->p.omega == 1.0)
+      HIPCHK(hipMemcpyAsync(h->u, h->x, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    else
+      launch_relax_u(st, n2, h->u, h->x, h->p.omega);
+    HIPCHK(hipEventRecord(h->ev[2], st));
+    // damage substep
+    launch_w2_2d(st, h->lv[0].g, h->mat, h->u, h->w2);
+    rc = damage_qp(h, &loc.vi_iters, &loc.vi_cg_iters);
+    if (rc) break;
+    rc = relax_alpha(h);
+    if (rc) break;
+    HIPCHK(hipEventRecord(h->ev[3], st));
+    loc.sweeps = sweep;
+    rc = read_scalars(h);
+    if (rc) break;
+    ms_pcg += elapsed(h->ev[1], h->ev[2]);
+    ms_vi += elapsed(h->ev[2], h->ev[3]);
+    loc.dalpha_inf = h->hS[S_DAMAX];
+    if (!std::isfinite(loc.dalpha_inf)) { rc = FRACTURE_ENONFINITE; break; }
+    if (h->p.am_stop == FRACTURE_STOP_DALPHA) {
+      if (loc.dalpha_inf < h->p.am_tol) { loc.converged = 1; break; }
+    } else {
+      double nphi = 0;
+      rc = residual_norm(h, &nphi);
+      if (rc) break;
+      loc.phi_l2 = nphi;
+      if (!std::isfinite(nphi)) { rc = FRACTURE_ENONFINITE; break; }
+      if (nphi <= h->p.final_tol) { loc.converged = 1; break; }
+    }
+  }
+  if (rc == FRACTURE_OK && !loc.converged) rc = FRACTURE_ENOTCONV;
+  if (rc == FRACTURE_OK) {
+    HIPCHK(hipMemcpyAsync(h->alpha_prev, h->alpha, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  } else if (rc == FRACTURE_ENOTCONV || rc == FRACTURE_ENONFINITE) {
+    (void)hipMemcpyAsync(h->u, h->u_entry, n2 * sizeof(double), hipMemcpyDeviceToDevice, st);
+    (void)hipMemcpyAsync(h->alpha, h->alpha_entry, N * sizeof(double), hipMemcpyDeviceToDevice, st);
+    h->coef_valid = false;
+  }
+  (void)hipEventRecord(h->ev[4], st);
+  (void)hipEventSynchronize(h->ev[4]);
+  loc.ms_total = elapsed(h->ev[0], h->ev[4]);
+  loc.ms_pcg = ms_pcg;
+  loc.ms_vi = ms_vi;
+  if (s) *s = loc;
+  return rc;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+void fracture_default_params(fracture_params* p, int nx, int ny) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->dim = 2;
+  p->nx = nx;
+  p->ny = ny;
+  p->nz = 0;
+  p->lx = 1.0;
+  p->ly = 1.0;
+  p->lz = 0.0;
+  p->model = FRACTURE_AT1;
+  p->plane_stress = 0;
+  p->E = 1.0;
+  p->nu = 0.3;
+  p->Gc = 1.0;
+  p->ell = 0.05;
+  p->k_ell = 1e-6;
+  p->load_kind = FRACTURE_LOAD_TENSION_2D;
+  p->thermal_depth = 0.05;
+  p->precision = FRACTURE_FP64;
+  p->omega = 1.0;
+  p->relax_mode = FRACTURE_RELAX_PROJECT;
+  p->newton = 0;
+  p->am_stop = FRACTURE_STOP_DALPHA;
+  p->am_tol = 1e-5;
+  p->switch_tol = 1e-3;
+  p->switch_rel = 1e-1;
+  p->final_tol = 1e-7;
+  p->pcg_rtol = 1e-10;
+  p->vi_tol = 1e-13;
+  p->vi_cg_rtol = 1e-10;
+  p->minres_rtol = 1e-6;
+  p->max_am = 2000;
+  p->max_pcg = 1000;
+  p->max_vi = 50;
+  p->max_vi_cg = 2000;
+  p->max_newton = 10;
+  p->max_minres = 500;
+  p->cheb_degree = 2;
+  p->coarse_max_dofs = 200;
+}
+
+size_t fracture_workspace_bytes(const fracture_params* p) {
+  if (validate(p) != FRACTURE_OK) return 0;
+  return layout(p, nullptr, nullptr);
+}
+
+int fracture_sizes(const fracture_params* p, int64_t* nodes, int64_t* dofs) {
+  if (!p || (p->dim != 2 && p->dim != 3) || p->nx < 1 || p->ny < 1) return FRACTURE_EINVAL;
+  int64_t N = (int64_t)(p->nx + 1) * (p->ny + 1);
+  if (p->dim == 3) N *= (p->nz + 1);
+  if (nodes) *nodes = N;
+  if (dofs) *dofs = N * p->dim;
+  return FRACTURE_OK;
+}
+
+int fracture_create(const fracture_params* p, const uint8_t* notch_mask, void* d_workspace,
+                    size_t ws_bytes, void* hip_stream, fracture_t* out) {
+  if (!out) return FRACTURE_EINVAL;
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  const size_t need = layout(p, nullptr, nullptr);
+  if (need == 0) return FRACTURE_EINVAL;
+  if (!d_workspace) return FRACTURE_EINVAL;
+  if (((uintptr_t)d_workspace & 255) != 0) return FRACTURE_EINVAL;
+  if (ws_bytes < need) return FRACTURE_ENOMEM;
+  fracture* h = new (std::nothrow) fracture();
+  if (!h) return FRACTURE_ENOMEM;
+  h->p = *p;
+  h->dim = p->dim;
+  h->st = (hipStream_t)hip_stream;
+  layout(p, h, d_workspace);
+  h->mat = make_mat(p);
+  h->cw = p->model == FRACTURE_AT1 ? 8.0 / 3.0 : 2.0;
+  h->gc_cw = p->Gc / h->cw;
+  h->cL = 2.0 * p->Gc * p->ell / h->cw;
+  h->cM = p->model == FRACTURE_AT2 ? 2.0 * p->Gc / (h->cw * p->ell) : 0.0;
+  h->cm = p->model == FRACTURE_AT1 ? p->Gc / (h->cw * p->ell) : 0.0;
+  // Chebyshev polynomial on [0.06 lmax, lmax]
+  h->lam_max = chebyshev_bound2d(h->lv[0].g, h->mat);
+  h->lam_min = 0.06 * h->lam_max;
+  const double theta = 0.5 * (h->lam_max + h->lam_min), delta = 0.5 * (h->lam_max - h->lam_min);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  h->cheb_cd[0] = 0.0;
+  h->cheb_cr[0] = 1.0 / theta;
+  for (int s = 1; s < p->cheb_degree; ++s) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    h->cheb_cd[s] = rn * rho;
+    h->cheb_cr[s] = 2.0 * rn / delta;
+    rho = rn;
+  }
+  if (hipHostMalloc((void**)&h->hS, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete h;
+    return FRACTURE_EDEVICE;
+  }
+  for (int k = 0; k < 8; ++k) {
+    if (hipEventCreate(&h->ev[k]) != hipSuccess) {
+      (void)hipHostFree(h->hS);
+      delete h;
+      return FRACTURE_EDEVICE;
+    }
+  }
+  hipStream_t st = h->st;
+  bool ok = true;
+  ok &= hipMemsetAsync(h->cnt, 0, C_SLOTS * sizeof(unsigned), st) == hipSuccess;
+  ok &= hipMemsetAsync(h->S, 0, S_COUNT * sizeof(double), st) == hipSuccess;
+  ok &= hipMemsetAsync(h->u, 0, h->n2 * sizeof(double), st) == hipSuccess;
+  ok &= hipMemsetAsync(h->alpha, 0, h->N * sizeof(double), st) == hipSuccess;
+  if (notch_mask) {
+    // alpha = alpha_prev = 1 on notch nodes: staged through pinned memory
+    double* tmp = nullptr;
+    ok &= hipHostMalloc((void**)&tmp, h->N * sizeof(double), hipHostMallocDefault) == hipSuccess;
+    if (ok) {
+      for (int64_t k = 0; k < h->N; ++k) tmp[k] = notch_mask[k] ? 1.0 : 0.0;
+      ok &= hipMemcpyAsync(h->alpha, tmp, h->N * sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess;
+      ok &= hipStreamSynchronize(st) == hipSuccess;
+      (void)hipHostFree(tmp);
+    }
+  }
+  ok &= hipMemcpyAsync(h->alpha_prev, h->alpha, h->N * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess;
+  ok &= hipStreamSynchronize(st) == hipSuccess;
+  if (!ok) {
+    fracture_destroy(h);
+    return FRACTURE_EDEVICE;
+  }
+  *out = h;
+  return FRACTURE_OK;
+}
+
+int fracture_set_load(fracture_t h, double load) {
+  if (!h || !std::isfinite(load)) return FRACTURE_EINVAL;
+  h->load = load;
+  launch_lift2d(h->st, h->lv[0].g, h->u, load);
+  return hip_ok(hipGetLastError());
+}
+
+int fracture_solve_step(fracture_t h, fracture_stats* out) {
+  if (!h) return FRACTURE_EINVAL;
+  return solve_step_impl(h, out);
+}
+
+int fracture_solve_steps(fracture_t* hs, int n, fracture_stats* out, int* codes) {
+  if (!hs || n < 0) return FRACTURE_EINVAL;
+  int worst = FRACTURE_OK;
+  for (int k = 0; k < n; ++k) {
+    const int rc = hs[k] ? solve_step_impl(hs[k], out ? out + k : nullptr) : FRACTURE_EINVAL;
+    if (codes) codes[k] = rc;
+    if (rc && !worst) worst = rc;
+  }
+  return worst;
+}
+
+int fracture_energy(fracture_t h, double* elastic, double* surface) {
+  if (!h) return FRACTURE_EINVAL;
+  launch_energy2d(h->st, h->lv[0].g, h->mat, h->p.k_ell, h->gc_cw, h->p.ell,
+                  h->p.model == FRACTURE_AT2, h->u, h->alpha, red(h, 10, S_EL), red(h, 11, S_SURF));
+  int rc = read_scalars(h);
+  if (rc) return rc;
+  if (elastic) *elastic = h->hS[S_EL];
+  if (surface) *surface = h->hS[S_SURF];
+  return FRACTURE_OK;
+}
+
+int fracture_get_state(fracture_t h, double* u, double* alpha, double* alpha_prev) {
+  if (!h) return FRACTURE_EINVAL;
+  if (u) HIPCHK(hipMemcpyAsync(u, h->u, h->n2 * sizeof(double), hipMemcpyDefault, h->st));
+  if (alpha) HIPCHK(hipMemcpyAsync(alpha, h->alpha, h->N * sizeof(double), hipMemcpyDefault, h->st));
+  if (alpha_prev)
+    HIPCHK(hipMemcpyAsync(alpha_prev, h->alpha_prev, h->N * sizeof(double), hipMemcpyDefault, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return FRACTURE_OK;
+}
+
+int fracture_set_state(fracture_t h, const double* u, const double* alpha, const double* alpha_prev) {
+  if (!h) return FRACTURE_EINVAL;
+  if (u) HIPCHK(hipMemcpyAsync(h->u, u, h->n2 * sizeof(double), hipMemcpyDefault, h->st));
+  if (alpha) HIPCHK(hipMemcpyAsync(h->alpha, alpha, h->N * sizeof(double), hipMemcpyDefault, h->st));
+  if (alpha_prev)
+    HIPCHK(hipMemcpyAsync(h->alpha_prev, alpha_prev, h->N * sizeof(double), hipMemcpyDefault, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  h->coef_valid = false;
+  return FRACTURE_OK;
+}
+
+int fracture_update_coefficients(fracture_t h) {
+  if (!h) return FRACTURE_EINVAL;
+  update_coefficients(h);
+  return hip_ok(hipStreamSynchronize(h->st));
+}
+
+int fracture_apply(fracture_t h, int op, int level, const double* d_x, double* d_y) {
+  if (!h || !d_x || !d_y) return FRACTURE_EINVAL;
+  const Grid& g = h->lv[0].g;
+  Red none{};
+  switch (op) {
+    case FRACTURE_OP_ELASTICITY:
+      launch_apply2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, d_x, d_y, nullptr, 0, 0, none);
+      break;
+    case FRACTURE_OP_LEVEL: {
+      if (level < 0 || level >= h->nlev) return FRACTURE_EINVAL;
+      if (!h->coef_valid) update_coefficients(h);
+      launch_apply2d(h->st, h->lv[level].g, h->mat, level == 0, level_coef(h, level), h->p.k_ell,
+                     d_x, d_y, nullptr, 1, 0, none);
+    } break;
+    case FRACTURE_OP_DAMAGE_HESS:
+      launch_w2_2d(h->st, g, h->mat, h->u, h->w2);
+      launch_helm_apply2d(h->st, g, h->cL, h->cM, h->w2, d_x, nullptr, d_y, false, none);
+      break;
+    case FRACTURE_OP_PRECOND: {
+      if (!h->coef_valid) update_coefficients(h);
+      double* z = vcycle(h, 0, d_x);
+      HIPCHK(hipMemcpyAsync(d_y, z, h->n2 * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+    } break;
+    default:
+      return FRACTURE_EINVAL;
+  }
+  return hip_ok(hipStreamSynchronize(h->st));
+}
+
+int fracture_gradient(fracture_t h, double* d_Eu, double* d_Ea) {
+  if (!h) return FRACTURE_EINVAL;
+  const Grid& g = h->lv[0].g;
+  Red none{};
+  if (d_Eu)
+    launch_apply2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, h->u, d_Eu, nullptr, 0, 0, none);
+  if (d_Ea) {
+    launch_w2_2d(h->st, g, h->mat, h->u, h->w2);
+    launch_vi_eval2d(h->st, g, h->cL, h->cM, h->cm, h->w2, h->alpha, nullptr, h->alpha_prev, h->S,
+                     S_MU, 1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2),
+                     red(h, 6, S_PHIMAX), false);
+    HIPCHK(hipMemcpyAsync(d_Ea, h->F, h->N * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  }
+  return hip_ok(hipStreamSynchronize(h->st));
+}
+
+int fracture_levels(fracture_t h, int* nlevels) {
+  if (!h || !nlevels) return FRACTURE_EINVAL;
+  *nlevels = h->nlev;
+  return FRACTURE_OK;
+}
+
+int fracture_level_shape(fracture_t h, int level, int* nx, int* ny, int* nz) {
+  if (!h || level < 0 || level >= h->nlev) return FRACTURE_EINVAL;
+  if (nx) *nx = h->lv[level].g.nx;
+  if (ny) *ny = h->lv[level].g.ny;
+  if (nz) *nz = h->lv[level].g.nz;
+  return FRACTURE_OK;
+}
+
+const char* fracture_strerror(int code) {
+  switch (code) {
+    case FRACTURE_OK: return "ok";
+    case FRACTURE_EINVAL: return "invalid parameter or argument";
+    case FRACTURE_ENOMEM: return "workspace too small";
+    case FRACTURE_ENOTCONV: return "iteration limit reached (state rolled back)";
+    case FRACTURE_ENONFINITE: return "non-finite value (state rolled back)";
+    case FRACTURE_EDEVICE: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+void fracture_destroy(fracture_t h) {
+  if (!h) return;
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  for (int k = 0; k < 8; ++k)
+    if (h->ev[k]) (void)hipEventDestroy(h->ev[k]);
+  if (h->hS) (void)hipHostFree(h->hS);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,270 @@
+// 1D vector kernels: Krylov updates with fused deterministic reductions,
+// the over-relaxed updates of Algorithm 2 and the projected steps of
+// Algorithm 4.  Scalars that depend on earlier reductions (CG alpha/beta,
+// line-search mu) are read from the device scalar array, so no host round
+// trip sits between dependent kernels.
+#include "common.h"
+#include "launch.h"
+
+namespace frac {
+
+static int vgrid(int64_t n) {
+  int64_t b = (n + VB - 1) / VB;
+  if (b > VGRID) b = VGRID;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+int vec_blocks(int64_t n) { return vgrid(n); }
+
+#define GRID_STRIDE(k, n) for (int64_t k = (int64_t)blockIdx.x * VB + threadIdx.x; k < (n); k += (int64_t)gridDim.x * VB)
+
+// x += a p; r -= a q; S[slot] = r.r   (a = S[S_ALPHA])
+__global__ __launch_bounds__(VB) void k_cg_update(int64_t n, double* __restrict__ x,
+                                                  double* __restrict__ r,
+                                                  const double* __restrict__ p,
+                                                  const double* __restrict__ q,
+                                                  const double* __restrict__ S, Red rr) {
+  const double a = S[S_ALPHA];
+  double acc = 0.0;
+  GRID_STRIDE(k, n) {
+    x[k] += a * p[k];
+    const double rv = r[k] - a * q[k];
+    r[k] = rv;
+    acc += rv * rv;
+  }
+  reduce_finish<VB, false>(acc, rr, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_cg_update(hipStream_t st, int64_t n, double* x, double* r, const double* p,
+                      const double* q, const double* S, Red rr) {
+  hipLaunchKernelGGL(k_cg_update, dim3(vgrid(n)), dim3(VB), 0, st, n, x, r, p, q, S, rr);
+}
+
+// p = z + beta p   (beta = S[S_BETA])
+__global__ __launch_bounds__(VB) void k_xpby(int64_t n, const double* __restrict__ z,
+                                             double* __restrict__ p, const double* __restrict__ S) {
+  const double b = S[S_BETA];
+  GRID_STRIDE(k, n) p[k] = z[k] + b * p[k];
+}
+
+void launch_xpby(hipStream_t st, int64_t n, const double* z, double* p, const double* S) {
+  hipLaunchKernelGGL(k_xpby, dim3(vgrid(n)), dim3(VB), 0, st, n, z, p, S);
+}
+
+// S[slot] = a.b (with the Red post-operation)
+__global__ __launch_bounds__(VB) void k_dot(int64_t n, const double* __restrict__ a,
+                                            const double* __restrict__ b, Red r) {
+  double acc = 0.0;
+  GRID_STRIDE(k, n) acc += a[k] * b[k];
+  reduce_finish<VB, false>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, Red r) {
+  hipLaunchKernelGGL(k_dot, dim3(vgrid(n)), dim3(VB), 0, st, n, a, b, r);
+}
+
+// z = dinv .* r; S = r.z (post)
+__global__ __launch_bounds__(VB) void k_jacobi_dot(int64_t n, const double* __restrict__ r,
+                                                   const double* __restrict__ dinv,
+                                                   double* __restrict__ z, Red red) {
+  double acc = 0.0;
+  GRID_STRIDE(k, n) {
+    const double zv = dinv[k] * r[k];
+    z[k] = zv;
+    acc += r[k] * zv;
+  }
+  reduce_finish<VB, false>(acc, red, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_jacobi_dot(hipStream_t st, int64_t n, const double* r, const double* dinv, double* z,
+                       Red red) {
+  hipLaunchKernelGGL(k_jacobi_dot, dim3(vgrid(n)), dim3(VB), 0, st, n, r, dinv, z, red);
+}
+
+// y = a x + b y (host scalars)
+__global__ __launch_bounds__(VB) void k_axpby(int64_t n, double a, const double* __restrict__ x,
+                                              double b, double* __restrict__ y) {
+  GRID_STRIDE(k, n) y[k] = a * x[k] + b * y[k];
+}
+
+void launch_axpby(hipStream_t st, int64_t n, double a, const double* x, double b, double* y) {
+  hipLaunchKernelGGL(k_axpby, dim3(vgrid(n)), dim3(VB), 0, st, n, a, x, b, y);
+}
+
+// S[slot] = ||x||^2 or max|x| (NaN -> inf)
+template <bool MAX>
+__global__ __launch_bounds__(VB) void k_norm(int64_t n, const double* __restrict__ x, Red r) {
+  double acc = MAX ? 0.0 : 0.0;
+  GRID_STRIDE(k, n) {
+    const double v = x[k];
+    acc = MAX ? fmax(acc, nan_to_inf(fabs(v))) : acc + v * v;
+  }
+  reduce_finish<VB, MAX>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_norm2(hipStream_t st, int64_t n, const double* x, Red r) {
+  hipLaunchKernelGGL((k_norm<false>), dim3(vgrid(n)), dim3(VB), 0, st, n, x, r);
+}
+void launch_normmax(hipStream_t st, int64_t n, const double* x, Red r) {
+  hipLaunchKernelGGL((k_norm<true>), dim3(vgrid(n)), dim3(VB), 0, st, n, x, r);
+}
+
+// Reduced damage CG set-up: r = -F on inactive nodes (0 on active), x = 0.
+__global__ __launch_bounds__(VB) void k_neg_masked(int64_t n, const double* __restrict__ F,
+                                                   const uint8_t* __restrict__ mask,
+                                                   double* __restrict__ r,
+                                                   double* __restrict__ x) {
+  GRID_STRIDE(k, n) {
+    r[k] = mask[k] ? 0.0 : -F[k];
+    x[k] = 0.0;
+  }
+}
+
+void launch_neg_masked(hipStream_t st, int64_t n, const double* F, const uint8_t* mask, double* r,
+                       double* x) {
+  hipLaunchKernelGGL(k_neg_masked, dim3(vgrid(n)), dim3(VB), 0, st, n, F, mask, r, x);
+}
+
+// u += omega (ut - u)   (Algorithm 2, displacement relaxation)
+__global__ __launch_bounds__(VB) void k_relax_u(int64_t n, double* __restrict__ u,
+                                                const double* __restrict__ ut, double omega) {
+  GRID_STRIDE(k, n) u[k] += omega * (ut[k] - u[k]);
+}
+
+void launch_relax_u(hipStream_t st, int64_t n, double* u, const double* ut, double omega) {
+  hipLaunchKernelGGL(k_relax_u, dim3(vgrid(n)), dim3(VB), 0, st, n, u, ut, omega);
+}
+
+// alpha <- clip(alpha + w (at - alpha), lo, 1) with w = omega (projection) or
+// w = S[wslot] (a common factor); S[dslot] = max |alpha_new - alpha|.
+__global__ __launch_bounds__(VB) void k_relax_alpha(int64_t n, double* __restrict__ a,
+                                                    const double* __restrict__ at,
+                                                    const double* __restrict__ lo, double omega,
+                                                    const double* __restrict__ S, int wslot,
+                                                    Red rd) {
+  const double w = wslot >= 0 ? S[wslot] : omega;
+  double acc = 0.0;
+  GRID_STRIDE(k, n) {
+    const double old = a[k];
+    const double nv = fmin(fmax(old + w * (at[k] - old), lo[k]), 1.0);
+    a[k] = nv;
+    acc = fmax(acc, nan_to_inf(fabs(nv - old)));
+  }
+  reduce_finish<VB, true>(acc, rd, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_relax_alpha(hipStream_t st, int64_t n, double* a, const double* at, const double* lo,
+                        double omega, const double* S, int wslot, Red rd) {
+  hipLaunchKernelGGL(k_relax_alpha, dim3(vgrid(n)), dim3(VB), 0, st, n, a, at, lo, omega, S, wslot,
+                     rd);
+}
+
+// Exact ratio test: S[slot] = -(largest feasible common factor), reduced as a
+// max of negated ratios so that the max-reduction machinery serves.
+__global__ __launch_bounds__(VB) void k_ratio(int64_t n, const double* __restrict__ a,
+                                              const double* __restrict__ at,
+                                              const double* __restrict__ lo, double omega, Red r) {
+  double acc = -omega;
+  GRID_STRIDE(k, n) {
+    const double d = at[k] - a[k];
+    double lim = omega;
+    if (d > 0.0) lim = (1.0 - a[k]) / d;
+    else if (d < 0.0) lim = (lo[k] - a[k]) / d;
+    acc = fmax(acc, -lim);
+  }
+  reduce_finish<VB, true>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_ratio(hipStream_t st, int64_t n, const double* a, const double* at, const double* lo,
+                  double omega, Red r) {
+  hipLaunchKernelGGL(k_ratio, dim3(vgrid(n)), dim3(VB), 0, st, n, a, at, lo, omega, r);
+}
+
+// S[slot] = max violation of the bounds by alpha + w (at - alpha) (0 when feasible).
+__global__ __launch_bounds__(VB) void k_violation(int64_t n, const double* __restrict__ a,
+                                                  const double* __restrict__ at,
+                                                  const double* __restrict__ lo, double w, Red r) {
+  double acc = 0.0;
+  GRID_STRIDE(k, n) {
+    const double v = a[k] + w * (at[k] - a[k]);
+    acc = fmax(acc, fmax(v - 1.0, lo[k] - v));
+  }
+  reduce_finish<VB, true>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_violation(hipStream_t st, int64_t n, const double* a, const double* at,
+                      const double* lo, double w, Red r) {
+  hipLaunchKernelGGL(k_violation, dim3(vgrid(n)), dim3(VB), 0, st, n, a, at, lo, w, r);
+}
+
+// alpha <- clip(alpha + mu d, lo, 1), mu = S[S_MU]   (projected step, Algorithm 4)
+__global__ __launch_bounds__(VB) void k_proj_step(int64_t n, double* __restrict__ a,
+                                                  const double* __restrict__ d,
+                                                  const double* __restrict__ lo,
+                                                  const double* __restrict__ S) {
+  const double mu = S[S_MU];
+  GRID_STRIDE(k, n) a[k] = fmin(fmax(a[k] + mu * d[k], lo[k]), 1.0);
+}
+
+void launch_proj_step(hipStream_t st, int64_t n, double* a, const double* d, const double* lo,
+                      const double* S) {
+  hipLaunchKernelGGL(k_proj_step, dim3(vgrid(n)), dim3(VB), 0, st, n, a, d, lo, S);
+}
+
+// Steepest-descent fallback of Algorithm 4 for the box QP: the generalised
+// Jacobian of Phi gives grad psi = ca*Phi + H (cf*Phi); this kernel writes
+// w = cf*Phi and g = ca*Phi (the H product is added by the caller).
+__global__ __launch_bounds__(VB) void k_merit_parts(int64_t n, const double* __restrict__ x,
+                                                    const double* __restrict__ F,
+                                                    const double* __restrict__ lo,
+                                                    double* __restrict__ w,
+                                                    double* __restrict__ g) {
+  GRID_STRIDE(k, n) {
+    const double l = lo[k], u = 1.0, xv = x[k], Fv = F[k];
+    const double p = u - xv, q = -Fv;
+    const double c = fb(p, q);
+    const double a = xv - l;
+    const double ph = fb(a, c);
+    const double ro = hypot(a, c), ri = hypot(p, q);
+    const double s2 = 0.70710678118654752440;
+    const double dao = (ro > 0 ? a / ro : s2) - 1.0, dbo = (ro > 0 ? c / ro : s2) - 1.0;
+    const double dai = (ri > 0 ? p / ri : s2) - 1.0, dbi = (ri > 0 ? q / ri : s2) - 1.0;
+    const double ca = dao - dbo * dai, cf = -dbo * dbi;
+    w[k] = cf * ph;
+    g[k] = ca * ph;
+  }
+}
+
+void launch_merit_parts(hipStream_t st, int64_t n, const double* x, const double* F,
+                        const double* lo, double* w, double* g) {
+  hipLaunchKernelGGL(k_merit_parts, dim3(vgrid(n)), dim3(VB), 0, st, n, x, F, lo, w, g);
+}
+
+// d = -(g + Hw) : the descent direction from the two parts; S[slot] = |d|^2
+__global__ __launch_bounds__(VB) void k_neg_sum(int64_t n, const double* __restrict__ g,
+                                                const double* __restrict__ hw,
+                                                double* __restrict__ d, Red r) {
+  double acc = 0.0;
+  GRID_STRIDE(k, n) {
+    const double v = -(g[k] + hw[k]);
+    d[k] = v;
+    acc += v * v;
+  }
+  reduce_finish<VB, false>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_neg_sum(hipStream_t st, int64_t n, const double* g, const double* hw, double* d, Red r) {
+  hipLaunchKernelGGL(k_neg_sum, dim3(vgrid(n)), dim3(VB), 0, st, n, g, hw, d, r);
+}
+
+// Scalar store on the device (S[slot] = v) without a host-to-device copy.
+__global__ void k_set_scalar(double* S, int slot, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) S[slot] = v;
+}
+
+void launch_set_scalar(hipStream_t st, double* S, int slot, double v) {
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(WAVE), 0, st, S, slot, v);
+}
+
+}  // namespace frac

@@ -1,0 +1,87 @@
+"""Seeded synthetic inputs shared by the tests, the bench and the smoke run.
+
+This module holds input recipes only (mesh sizes, material constants, notch
+geometry, load sequences, seeds); none of the method's arithmetic.  Both the
+HIP path and the CPU oracle receive the same values from here.
+
+Recipes (the paper uses no dataset; these stand in for its test problems):
+
+* ``tension(n)``: the unit square, n x n right-diagonal cells, plane strain,
+  E = 1, nu = 0.3, Gc = 1 (Sec. 4 fixes Gc = E = 1, nu = 0.3), k_ell = 1e-6,
+  bottom u_y = 0, top u_y = t, with an initial crack alpha = 1 on the nodes of
+  a horizontal segment starting at x = 0.
+* ``config1``: 64 x 64, AT1, ell = 0.05, notch y = 0.5, x in [0, 0.3],
+  10 steps t = 0.002 k.
+* ``config2(model, omega, seed)``: 2048 x 2048, ell = 4h, notch height y0 and
+  length a drawn from U[0.1, 0.4] (seed 0) and snapped to nodes, 20 steps
+  t = 0.1 k.
+* ``small_tension``: the config-2 recipe at a small n (parity sizes).
+"""
+
+import numpy as np
+
+
+def notch_mask_2d(nx, ny, y0, length, lx=1.0, ly=1.0):
+    """Nodes on the row nearest y = y0 with x <= length (uint8, node order)."""
+    j0 = int(round(y0 / (ly / ny)))
+    x = np.arange(nx + 1) * (lx / nx)
+    mask = np.zeros((ny + 1, nx + 1), dtype=np.uint8)
+    mask[j0, x <= length + 1e-12] = 1
+    return mask.ravel()
+
+
+def tension(n, ell, model="AT1", omega=1.0, **extra):
+    """Parameters (keywords of ``fracture.make_params`` and of the oracle)."""
+    p = dict(dim=2, nx=n, ny=n, lx=1.0, ly=1.0, model=model, E=1.0, nu=0.3, Gc=1.0,
+             ell=ell, k_ell=1e-6, omega=omega, plane_stress=0)
+    p.update(extra)
+    return p
+
+
+def config1():
+    p = tension(64, 0.05, "AT1", am_tol=1e-5)
+    notch = notch_mask_2d(64, 64, 0.5, 0.3)
+    loads = [0.002 * k for k in range(1, 11)]
+    return p, notch, loads
+
+
+def notch_config2(n, seed=0):
+    rng = np.random.default_rng(seed)
+    y0 = rng.uniform(0.1, 0.4)
+    a = rng.uniform(0.1, 0.4)
+    h = 1.0 / n
+    y0 = round(y0 / h) * h
+    a = round(a / h) * h
+    return y0, a
+
+
+def config2(model="AT1", omega=1.0, seed=0, n=2048):
+    h = 1.0 / n
+    p = tension(n, 4 * h, model, omega)
+    y0, a = notch_config2(n, seed)
+    notch = notch_mask_2d(n, n, y0, a)
+    loads = [0.1 * k for k in range(1, 21)]
+    return p, notch, loads, (y0, a)
+
+
+def small_tension(n, model="AT1", omega=1.0, seed=0, ell=None):
+    h = 1.0 / n
+    p = tension(n, ell if ell is not None else 4 * h, model, omega)
+    y0, a = notch_config2(n, seed)
+    return p, notch_mask_2d(n, n, y0, a), (y0, a)
+
+
+def random_fields(N, ndof, seed, notch=None):
+    """Random displacement and damage fields for operator checks."""
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal(ndof)
+    alpha = rng.uniform(0.0, 1.0, N)
+    if notch is not None:
+        alpha[np.asarray(notch, bool)] = 1.0
+    return u, alpha
+
+
+def oracle_kwargs(p):
+    """The subset of parameters the oracle's problem builders take."""
+    return dict(E=p["E"], nu=p["nu"], Gc=p["Gc"], ell=p["ell"], k_ell=p["k_ell"],
+                model=p["model"], plane_stress=bool(p.get("plane_stress", 0)))

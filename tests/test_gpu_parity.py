@@ -1,0 +1,265 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle, element by element.
+
+Operators (matrix-free on the GPU, assembled sparse in the oracle) agree to
+1e-12 relative; converged load steps agree to 1e-6 relative L2 in u and
+alpha (the stated tolerances).  Sizes span several 64x4 node tiles with
+ragged tails (e.g. 97 x 81 nodes).
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import am, fem, mesh, problems
+from paper_1511_08463_amd import fracture, workloads
+
+pytestmark = pytest.mark.gpu
+
+OPS_TOL = 1e-12
+STEP_TOL = 1e-6
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    d = np.linalg.norm(a - b)
+    s = np.linalg.norm(b)
+    return d / s if s > 0 else d
+
+
+def _solver(p, notch=None, **kw):
+    _torch()
+    params = fracture.make_params(**dict(p, **kw))
+    return fracture.Fracture(params, notch, device="cuda:0")
+
+
+def _problem(p):
+    return problems.tension_2d(p["nx"], p["ny"], p.get("lx", 1.0), p.get("ly", 1.0),
+                               **workloads.oracle_kwargs(p))
+
+
+SHAPES = [(8, 8), (96, 80), (64, 128)]
+
+
+@pytest.mark.parametrize("nx,ny", SHAPES)
+@pytest.mark.parametrize("model", ["AT1", "AT2"])
+def test_elasticity_apply_matches_assembled(nx, ny, model):
+    p = workloads.tension(nx, 0.05, model, nx=nx, ny=ny)
+    print(f"[apply] {nx}x{ny} {model}", flush=True)
+    s = _solver(p)
+    P = _problem(p)
+    u, alpha = workloads.random_fields(P.model.N, 2 * P.model.N, seed=nx + ny)
+    s.set_state(u=u, alpha=alpha)
+    y = s.apply(fracture.FRACTURE_OP_ELASTICITY, u)
+    want = P.model.K(alpha) @ u
+    err = np.max(np.abs(y - want)) / np.max(np.abs(want))
+    assert err < OPS_TOL, err
+    # k_ell contrast: a fully damaged field leaves only k_ell stiffness
+    s.set_state(alpha=np.ones(P.model.N))
+    y = s.apply(fracture.FRACTURE_OP_ELASTICITY, u)
+    want = P.model.K(np.ones(P.model.N)) @ u
+    assert np.max(np.abs(y - want)) / np.max(np.abs(want)) < OPS_TOL
+    s.close()
+
+
+def _interp(nxc, nyc):
+    """P1 interpolation from the (nxc, nyc) grid to its red refinement."""
+    nxf, nyf = 2 * nxc, 2 * nyc
+    rows, cols, vals = [], [], []
+    Wc = nxc + 1
+    for jf in range(nyf + 1):
+        for i_f in range(nxf + 1):
+            f = i_f + jf * (nxf + 1)
+            a = (i_f // 2 + Wc * (jf // 2), (i_f + 1) // 2 + Wc * ((jf + 1) // 2))
+            for c in a:
+                rows.append(f)
+                cols.append(c)
+                vals.append(0.5)
+    Ps = sp.csr_matrix((vals, (rows, cols)), shape=((nxf + 1) * (nyf + 1), (nxc + 1) * (nyc + 1)))
+    return sp.block_diag([Ps, Ps]).tocsr()
+
+
+@pytest.mark.parametrize("nx,ny", [(16, 16), (96, 80)])
+def test_coarse_levels_are_galerkin_products(nx, ny):
+    """Coarse operators from averaged coefficients equal P^T K P (restricted to
+    free DOFs), with P the nested P1 interpolation."""
+    p = workloads.tension(nx, 0.05, nx=nx, ny=ny)
+    print(f"[galerkin] {nx}x{ny}", flush=True)
+    notch = workloads.notch_mask_2d(nx, ny, 0.5, 0.3)
+    s = _solver(p, notch)
+    P = _problem(p)
+    rng = np.random.default_rng(7)
+    alpha = rng.uniform(0, 1, P.model.N)
+    alpha[notch.astype(bool)] = 1.0
+    s.set_state(alpha=alpha)
+    fracture.fracture_update_coefficients(s.h)
+    K = P.model.K(alpha)
+    shapes = s.levels()
+    Pc = sp.identity(K.shape[0], format="csr")
+    for l in range(1, len(shapes)):
+        nxc, nyc, _ = shapes[l]
+        Pc = (Pc @ _interp(nxc, nyc)).tocsr()
+        Kl = (Pc.T @ K @ Pc).tocsr()
+        Nl = (nxc + 1) * (nyc + 1)
+        fixed = np.zeros(2 * Nl, bool)
+        ii, jj = np.meshgrid(np.arange(nxc + 1), np.arange(nyc + 1), indexing="xy")
+        fixed[Nl + np.flatnonzero((jj.ravel() == 0) | (jj.ravel() == nyc))] = True
+        fixed[0] = True
+        x = rng.standard_normal(2 * Nl)
+        x[fixed] = 0.0
+        want = Kl @ x
+        want[fixed] = 0.0
+        y = s.apply(fracture.FRACTURE_OP_LEVEL, x, level=l)
+        err = np.max(np.abs(y - want)) / np.max(np.abs(want))
+        assert err < OPS_TOL, (l, err)
+    s.close()
+
+
+def test_preconditioner_is_symmetric_positive():
+    p = workloads.tension(96, 0.05, nx=96, ny=80)
+    notch = workloads.notch_mask_2d(96, 80, 0.5, 0.3)
+    s = _solver(p, notch)
+    P = _problem(p)
+    rng = np.random.default_rng(3)
+    alpha = np.clip(rng.uniform(-0.5, 1.0, P.model.N), 0, 1)
+    alpha[notch.astype(bool)] = 1.0
+    s.set_state(alpha=alpha)
+    fracture.fracture_update_coefficients(s.h)
+    free = P.free
+    x = rng.standard_normal(2 * P.model.N) * free
+    y = rng.standard_normal(2 * P.model.N) * free
+    Mx = s.apply(fracture.FRACTURE_OP_PRECOND, x)
+    My = s.apply(fracture.FRACTURE_OP_PRECOND, y)
+    assert np.all(Mx[~free] == 0)
+    assert abs(x @ My - y @ Mx) <= 1e-10 * abs(x @ Mx)
+    assert x @ Mx > 0 and y @ My > 0
+    s.close()
+
+
+@pytest.mark.parametrize("model", ["AT1", "AT2"])
+def test_damage_hessian_and_gradient_match(model):
+    nx, ny = 96, 80
+    p = workloads.tension(nx, 0.05, model, nx=nx, ny=ny)
+    s = _solver(p)
+    P = _problem(p)
+    u, alpha = workloads.random_fields(P.model.N, 2 * P.model.N, seed=11)
+    u *= 0.05
+    s.set_state(u=u, alpha=alpha, alpha_prev=np.zeros(P.model.N))
+    x = np.random.default_rng(2).standard_normal(P.model.N)
+    y = s.apply(fracture.FRACTURE_OP_DAMAGE_HESS, x)
+    want = P.model.damage_hessian(u) @ x
+    assert np.max(np.abs(y - want)) / np.max(np.abs(want)) < OPS_TOL
+    Eu, Ea = s.gradient()
+    want_u = P.model.grad_u(u, alpha)
+    want_a = P.model.grad_alpha(u, alpha)
+    assert np.max(np.abs(Eu - want_u)) / np.max(np.abs(want_u)) < OPS_TOL
+    assert np.max(np.abs(Ea - want_a)) / np.max(np.abs(want_a)) < 1e-11
+    el, su = s.energy()
+    wel, wsu = P.model.energies(u, alpha)
+    assert abs(el - wel) / abs(wel) < OPS_TOL and abs(su - wsu) / abs(wsu) < OPS_TOL
+    s.close()
+
+
+def _run_both(p, notch, loads, omega=1.0, relax="project", am_tol=1e-10, **kw):
+    relax_code = {"project": 0, "ratio": 1, "bisect": 2}[relax]
+    s = _solver(p, notch, omega=omega, relax_mode=relax_code, am_tol=am_tol, pcg_rtol=1e-13,
+                vi_cg_rtol=1e-13, **kw)
+    P = _problem(p)
+    st = am.initial_state(P, notch.astype(bool))
+    out = []
+    for t in loads:
+        s.set_load(t)
+        stats = s.solve_step()
+        o = am.solve_load_step(P, st, t, omega=omega, relax=relax, am_tol=am_tol)
+        u, a, ap = s.state()
+        el, su = s.energy()
+        oel, osu = P.model.energies(st.u, st.alpha)
+        out.append(dict(t=t, eu=_rel(u, st.u), ea=_rel(a, st.alpha), sweeps=stats["sweeps"],
+                        osweeps=o["sweeps"], el=abs(el - oel) / max(abs(oel), 1e-300),
+                        su=abs(su - osu) / abs(osu), a=a, ap=ap, lo=st.alpha_prev))
+        print(f"  t={t:.4f} sweeps gpu/oracle={stats['sweeps']}/{o['sweeps']} pcg={stats['pcg_iters']} "
+              f"vi={stats['vi_iters']} rel_u={out[-1]['eu']:.2e} rel_a={out[-1]['ea']:.2e}", flush=True)
+    s.close()
+    return out
+
+
+def test_config1_load_path_parity():
+    """The 64x64 AT1 notched square, all 10 load steps (AM to ||dalpha|| < 1e-10)."""
+    p, notch, loads = workloads.config1()
+    print("[config1]", flush=True)
+    res = _run_both(p, notch, loads)
+    for r in res:
+        assert r["eu"] < STEP_TOL and r["ea"] < STEP_TOL
+        assert r["su"] < STEP_TOL and r["el"] < STEP_TOL
+        assert np.all(r["a"] >= r["ap"] - 0.0) and np.all(r["a"] <= 1.0)
+
+
+@pytest.mark.parametrize("model,omega,relax", [("AT1", 1.0, "project"), ("AT2", 1.0, "project"),
+                                              ("AT1", 1.5, "project"), ("AT1", 1.5, "ratio"),
+                                              ("AT1", 1.5, "bisect")])
+def test_growing_crack_parity(model, omega, relax):
+    """A 48x48 notched square loaded until the crack grows (several sweeps)."""
+    n = 48
+    p, notch, _ = workloads.small_tension(n, model, ell=0.08)
+    print(f"[grow] {model} omega={omega} {relax}", flush=True)
+    loads = [0.3, 0.8, 1.1]
+    res = _run_both(p, notch, loads, omega=omega, relax=relax)
+    for r in res:
+        assert r["eu"] < STEP_TOL and r["ea"] < STEP_TOL, r
+
+
+def test_ragged_mesh_parity():
+    p = workloads.tension(96, 0.06, "AT1", nx=96, ny=80)
+    notch = workloads.notch_mask_2d(96, 80, 0.5, 0.25)
+    print("[ragged]", flush=True)
+    res = _run_both(p, notch, [0.2, 0.6])
+    for r in res:
+        assert r["eu"] < STEP_TOL and r["ea"] < STEP_TOL
+
+
+def test_undamaged_below_elastic_limit_is_exactly_zero():
+    """No notch, homogeneous bar below the AT1 elastic limit: alpha stays 0 bitwise."""
+    p = workloads.tension(32, 0.1, "AT1")
+    s = _solver(p, None)
+    t_c = np.sqrt(3.0 / (8 * 0.1)) * np.sqrt(1 - 0.09)
+    s.set_load(0.99 * t_c)
+    s.solve_step()
+    _, a, ap = s.state()
+    assert np.all(a == 0.0) and np.all(ap == 0.0)
+    s.set_load(1.05 * t_c)
+    s.solve_step()
+    _, a, _ = s.state()
+    W2 = (1.05 * t_c) ** 2 / (1 - 0.09)
+    assert np.allclose(a, 1 - 3.0 / (8 * 0.1 * W2), rtol=1e-9)
+    s.close()
+
+
+def test_iteration_limit_rolls_back_state():
+    p, notch, _ = workloads.small_tension(32, "AT1", ell=0.1)
+    s = _solver(p, notch, max_pcg=1, pcg_rtol=1e-14)
+    s.set_load(0.5)
+    u0, a0, ap0 = s.state()
+    st = s.solve_step(raise_on_error=False)
+    assert st["code"] == fracture.FRACTURE_ENOTCONV
+    u1, a1, ap1 = s.state()
+    assert np.array_equal(u0, u1) and np.array_equal(a0, a1) and np.array_equal(ap0, ap1)
+    s.close()
+
+
+def test_bitwise_reproducible():
+    p, notch, _ = workloads.small_tension(64, "AT1", ell=0.06)
+    outs = []
+    for _ in range(2):
+        s = _solver(p, notch)
+        for t in (0.4, 0.9):
+            s.set_load(t)
+            s.solve_step()
+        outs.append(s.state())
+        s.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
