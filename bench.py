@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Benchmark: quasi-static load steps of the 2048 x 2048 AT1 notched square.
+
+A "step" is one load step: set the next load, run the over-relaxed
+alternate minimisation (elastic PCG with multigrid, damage box-QP active set,
+relaxations) to its stop test, commit alpha_prev.  The workload is the
+2048^2 plane-strain unit square with a seeded edge notch (height and length
+drawn from U[0.1, 0.4]), ell = 4h, k_ell = 1e-6, loads t = 0.1 k.
+W warm-up load steps run untimed, then K load steps are timed
+(HIP-synchronised on both sides); value = K / seconds.
+
+Also reported: PCG DOF-iterations per second, the roofline of the dominant
+kernel (algorithmic bytes per launch over its mean duration, measured with
+HIP events on the solver's stream) and the CPU oracle timed on a bounded
+sample (rank 0 only).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "load steps/s + PCG DOF/s (FP64 vs mixed) at 2048² AT1; p50/p99 step latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_sample=256, n_full=2048, model="AT1"):
+    """The oracle (assembled sparse FE, exact LU solves, exact box-QP active
+    set) on the same recipe at n_sample^2, load step 1; its time per load step
+    is scaled by the node ratio to the n_full^2 workload."""
+    import numpy as np
+    from oracle import am, problems
+    from paper_1511_08463_amd import workloads
+    p, notch, _ = workloads.small_tension(n_sample, model)
+    P = problems.tension_2d(n_sample, n_sample, **workloads.oracle_kwargs(p))
+    st = am.initial_state(P, notch.astype(bool))
+    t0 = time.perf_counter()
+    o = am.solve_load_step(P, st, 0.1, omega=1.0, am_tol=1e-5)
+    dt = time.perf_counter() - t0
+    ratio = ((n_full + 1) / (n_sample + 1)) ** 2
+    threads = os.environ.get("OMP_NUM_THREADS", "unset")
+    return {
+        "value": 1.0 / (dt * ratio),
+        "unit": "load steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle load step 1 (t=0.1, {o['sweeps']} AM sweeps to ||dalpha||inf<1e-5) of the "
+                   f"same recipe at {n_sample}x{n_sample}: {dt:.2f} s, scaled x{ratio:.1f} by node count "
+                   f"to {n_full}x{n_full} (linear-cost assumption; sparse LU grows faster). "
+                   f"SciPy SuperLU and sparse matvec are single-threaded; host cpu_count="
+                   f"{os.cpu_count()}, affinity={len(os.sched_getaffinity(0))}, OMP_NUM_THREADS={threads}"),
+        "seconds": dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4, help="timed load steps")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed load steps first")
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--model", default="AT1")
+    ap.add_argument("--omega", type=float, default=1.0)
+    ap.add_argument("--am-tol", type=float, default=1e-5)
+    ap.add_argument("--pcg-rtol", type=float, default=1e-8)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the multi-GPU decomposition is a design, not built)"}))
+        sys.exit(2)
+    if args.warmup + args.steps > 20:
+        sys.exit("warmup + steps must be <= 20 (the load sequence has 20 steps)")
+
+    import numpy as np
+    import torch
+    from paper_1511_08463_amd import fracture, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    p, notch, loads, (y0, a) = workloads.config2(args.model, args.omega, seed=0, n=args.n)
+    params = fracture.make_params(**p, am_tol=args.am_tol, pcg_rtol=args.pcg_rtol,
+                                  vi_cg_rtol=1e-10, max_am=5000)
+    log(f"[bench] {args.n}^2 {args.model} omega={args.omega} notch y0={y0:.4f} a={a:.4f} "
+        f"warmup={args.warmup} steps={args.steps}")
+    solver = fracture.Fracture(params, notch, device=dev)
+    free_dofs = solver.ndof - (args.n + 1) * 2 - 1
+
+    def run(k):
+        solver.set_load(loads[k])
+        t0 = time.perf_counter()
+        st = solver.solve_step()
+        st["wall_s"] = time.perf_counter() - t0
+        log(f"[bench] step {k + 1} t={loads[k]:.2f} sweeps={st['sweeps']} pcg={st['pcg_iters']} "
+            f"vi={st['vi_iters']} vi_cg={st['vi_cg_iters']} dalpha={st['dalpha_inf']:.2e} "
+            f"ms={st['ms_total']:.1f} (pcg {st['ms_pcg']:.1f}, vi {st['ms_vi']:.1f})")
+        return st
+
+    for k in range(args.warmup):
+        run(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [run(k) for k in range(args.warmup, args.warmup + args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    pcg_iters = sum(s["pcg_iters"] for s in stats)
+    pcg_s = sum(s["ms_pcg"] for s in stats) / 1e3
+    sweeps = sum(s["sweeps"] for s in stats)
+
+    # roofline of the dominant kernel: the finest-level Chebyshev step
+    rl = {}
+    for name, kid in (("smooth", fracture.FRACTURE_KERNEL_SMOOTH), ("apply", fracture.FRACTURE_KERNEL_APPLY),
+                      ("vi_eval", fracture.FRACTURE_KERNEL_VI_EVAL), ("helm", fracture.FRACTURE_KERNEL_HELM)):
+        ms, nbytes = fracture.fracture_time_kernel(solver.h, kid, args.kernel_reps)
+        rl[name] = {"ms": ms, "bytes": nbytes, "gbs": nbytes / (ms * 1e-3) / 1e9}
+        log(f"[bench] kernel {name}: {ms * 1e3:.1f} us/launch, {nbytes / 1e6:.1f} MB -> "
+            f"{rl[name]['gbs']:.0f} GB/s")
+    dom = rl["smooth"]
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "load steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{args.n}x{args.n} plane-strain unit square, P1 right-diagonal triangles, "
+                         f"{args.model}, ell=4h, k_ell=1e-6, seeded edge notch (y0={y0:.4f}, a={a:.4f}), "
+                         f"tension load steps t=0.1k, k={args.warmup + 1}..{args.warmup + args.steps} timed; "
+                         f"ORAM omega={args.omega} to ||dalpha||inf<{args.am_tol:g}, PCG rtol {args.pcg_rtol:g}"),
+            "precision": "fp64",
+            "newton": False,
+        },
+        "pcg_dof_iter_per_s": free_dofs * pcg_iters / pcg_s if pcg_s > 0 else None,
+        "sweeps": sweeps,
+        "pcg_iters": pcg_iters,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_node2d<SMOOTH> (finest-level Chebyshev step)",
+            "achieved": dom["gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": dom["gbs"] / HBM_PEAK_GBS,
+            "traffic": None,
+            "per_kernel_gbs": {k: round(v["gbs"], 1) for k, v in rl.items()},
+            "per_kernel_us": {k: round(v["ms"] * 1e3, 2) for k, v in rl.items()},
+        },
+    }
+    solver.close()
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(256, args.n, args.model)
+        log(f"[bench] cpu baseline {out['cpu_baseline']['seconds']:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

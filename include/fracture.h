@@ -202,6 +202,29 @@ int fracture_gradient(fracture_t h, double* d_Eu, double* d_Ea);
 int fracture_levels(fracture_t h, int* nlevels);
 int fracture_level_shape(fracture_t h, int level, int* nx, int* ny, int* nz);
 
+/* ---- measurement hook ---------------------------------------------------
+ * Launch one of the hot kernels `reps` times back to back on the handle's
+ * stream on the handle's current buffers, bracketed by HIP events, and
+ * return the mean duration per launch (host *avg_ms) and the kernel's
+ * algorithmic (compulsory) bytes per launch (host *bytes): every distinct
+ * input read once plus every output written once, from the level's sizes.
+ *   APPLY    finest-level y = K(alpha) x with the x.y reduction (the PCG
+ *            product): x 16 + alpha 8 + y 16 = 40 B per node.
+ *   SMOOTH   finest-level Chebyshev step with iterate, rhs and update
+ *            vectors: x 16 + alpha 8 + b 16 + d 16 in, x' 16 + d' 16 out
+ *            = 88 B per node.
+ *   VI_EVAL  damage residual, FB function and active set: alpha 8 +
+ *            alpha_prev 8 + W2 16 in (2 per cell), F 8 + Phi 8 + mask 1 +
+ *            inverse diagonal 8 out = 57 B per node.
+ *   HELM     masked damage Hessian apply with the x.y reduction: x 8 +
+ *            W2 16 + mask 1 in, y 8 out = 33 B per node.
+ * The buffers are overwritten (call between load steps only). */
+#define FRACTURE_KERNEL_APPLY   0
+#define FRACTURE_KERNEL_SMOOTH  1
+#define FRACTURE_KERNEL_VI_EVAL 2
+#define FRACTURE_KERNEL_HELM    3
+int fracture_time_kernel(fracture_t h, int kernel, int reps, double* avg_ms, double* bytes);
+
 const char* fracture_strerror(int code);
 
 /* Release the handle (host state only; the caller frees the workspace). */

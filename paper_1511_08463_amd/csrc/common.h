@@ -1,10 +1,10 @@
 // Shared device helpers and plain-data structs of the fracture library.
 //
 // Reductions are deterministic: each block reduces in a fixed order
-// (wavefront shuffles, then LDS), writes one partial, and the last block to
-// finish (device-scope counter) sums the partials in a fixed order.  The
-// result therefore does not depend on block scheduling, so a run is
-// bitwise reproducible.
+// (wavefront shuffles, then LDS) and writes one partial; a one-block finishing
+// kernel sums the partials in a fixed order and applies the scalar
+// post-operation.  The result does not depend on block scheduling, so a run
+// is bitwise reproducible.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,10 +26,10 @@ enum { BC_TENSION_2D = 0, BC_THERMAL_3D = 1 };
 enum {
   S_RZ = 0, S_PQ, S_ALPHA, S_RR, S_BETA, S_RZNEW, S_MU,
   S_PHI2, S_PHIMAX, S_DAMAX, S_EL, S_SURF, S_EU2, S_TMP0, S_TMP1, S_TMP2,
-  S_RATIO, S_INFEAS, S_GG, S_MR0, S_MR1, S_MR2, S_MR3, S_MR4, S_MR5, S_MR6, S_MR7,
+  S_RATIO, S_INFEAS, S_GG, S_JLO, S_JHI, S_MR0, S_MR1, S_MR2, S_MR3, S_MR4, S_MR5, S_MR6, S_MR7,
   S_COUNT = 64
 };
-// Counters of the last-block reductions, one per concurrent reduction slot.
+// Partial-sum slots: one per reduction that may be pending at the same time.
 enum { C_SLOTS = 16 };
 
 // A structured level: (nx+1)(ny+1)[(nz+1)] nodes.
@@ -51,7 +51,6 @@ enum Post { P_STORE = 0, P_CG_ALPHA, P_CG_BETA, P_SQRT, P_NEG };
 
 struct Red {
   double* part;       // >= number of blocks of the launch
-  unsigned* cnt;      // one counter, zero between launches
   double* S;          // scalar array
   int slot;           // S[slot] receives the result
   int post;           // Post
@@ -92,13 +91,15 @@ __device__ __forceinline__ void post_scalar(double s, const Red& r) {
   }
 }
 
-// Block-wide deterministic sum (MAX = false) or max (MAX = true) of v, then
-// the cross-block finish.  Every thread of the block must call it.
+// Block-wide deterministic sum (MAX = false) or max (MAX = true) of v, stored
+// as the block's partial r.part[bid].  A finishing kernel (launch_finish)
+// then reduces the partials in a fixed order.  Every thread of the block must
+// call it.  No fences or atomics: the kernel boundary orders the two passes.
 template <int NT, bool MAX>
-__device__ __forceinline__ void reduce_finish(double v, const Red& r, int nblocks, int bid,
+__device__ __forceinline__ void block_reduce(double v, const Red& r, int nblocks, int bid,
                                               int tid) {
   __shared__ double sh[NT / WAVE];
-  __shared__ int last;
+  (void)nblocks;
   __syncthreads();
   v = MAX ? wave_max(v) : wave_sum(v);
   const int lane = tid & (WAVE - 1), w = tid / WAVE;
@@ -108,26 +109,6 @@ __device__ __forceinline__ void reduce_finish(double v, const Red& r, int nblock
     double s = sh[0];
     for (int k = 1; k < NT / WAVE; ++k) s = MAX ? fmax(s, sh[k]) : s + sh[k];
     r.part[bid] = s;
-    __threadfence();
-    unsigned t = atomicAdd(r.cnt, 1u);
-    last = (t == (unsigned)(nblocks - 1));
-  }
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    const volatile double* vp = r.part;
-    double acc = MAX ? -INFINITY : 0.0;
-    for (int k = tid; k < nblocks; k += NT) acc = MAX ? fmax(acc, vp[k]) : acc + vp[k];
-    acc = MAX ? wave_max(acc) : wave_sum(acc);
-    if (lane == 0) sh[w] = acc;
-    __syncthreads();
-    if (tid == 0) {
-      double s = sh[0];
-      for (int k = 1; k < NT / WAVE; ++k) s = MAX ? fmax(s, sh[k]) : s + sh[k];
-      post_scalar(s, r);
-      *r.cnt = 0u;
-      __threadfence();
-    }
   }
 }
 

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(NB) void k_node2d(Grid g, Mat m, const double* __re
     }
   }
   if (RED != R_NONE)
-    reduce_finish<NB, false>(acc, red, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
+    block_reduce<NB, false>(acc, red, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
                              threadIdx.x + NB_X * threadIdx.y);
 }
 
@@ -256,6 +256,7 @@ void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, cons
     else APPLY_CASE(false, R_FREE2);
   }
 #undef APPLY_CASE
+  if (red != R_NONE) launch_finish(st, r, (int)(gr.x * gr.y), false);
 }
 
 // r = b - K x on free rows, 0 on Dirichlet rows; optional ||r||^2 into S[slot].
@@ -271,6 +272,7 @@ void launch_resid2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, cons
     if (red) RES_CASE(false, R_DOT); else RES_CASE(false, R_NONE);
   }
 #undef RES_CASE
+  if (red) launch_finish(st, rr, (int)(gr.x * gr.y), false);
 }
 
 // One Jacobi-preconditioned Chebyshev step:
@@ -463,18 +465,20 @@ __device__ __forceinline__ void tri_nodes(int t, int di[3], int dj[3]) {
 
 // (H a)_v, g_v and H_vv at node (i,j) for the damage field a; when TRIAL the
 // field is clip(a + mu*d, lo, 1) evaluated on the fly.
-template <bool TRIAL>
+template <bool TRIAL, bool MASKIN = false>
 __device__ __forceinline__ void helm_node2d(const Grid& g, const Helm& hp,
                                             const double* __restrict__ w2,
                                             const double* __restrict__ a,
                                             const double* __restrict__ d,
                                             const double* __restrict__ lo, double mu, int i, int j,
-                                            double& Ha, double& gv, double& Hd) {
+                                            double& Ha, double& gv, double& Hd,
+                                            const uint8_t* __restrict__ mask = nullptr) {
   const int W = g.nx + 1;
   const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy, area = 0.5 * g.hx * g.hy;
   Ha = 0.0; gv = 0.0; Hd = 0.0;
   auto val = [&](int n) -> double {
     if (TRIAL) return fmin(fmax(a[n] + mu * d[n], lo[n]), 1.0);
+    if (MASKIN) return mask[n] ? 0.0 : a[n];
     return a[n];
   };
 #pragma unroll
@@ -513,10 +517,11 @@ __global__ __launch_bounds__(NB) void k_vi_eval2d(Grid g, Helm hp, const double*
                                                   double zeta, double* __restrict__ F,
                                                   double* __restrict__ phi,
                                                   uint8_t* __restrict__ mask,
-                                                  double* __restrict__ hdinv, Red r2, Red rm) {
+                                                  double* __restrict__ hdinv, Red r2, Red rm,
+                                                  Red rlo, Red rhi) {
   const int i = blockIdx.x * NB_X + threadIdx.x;
   const int j = blockIdx.y * NB_Y + threadIdx.y;
-  double p2 = 0.0, pm = 0.0;
+  double p2 = 0.0, pm = 0.0, jlo = -INFINITY, jhi = -INFINITY;
   if (i <= g.nx && j <= g.ny) {
     const int n = i + (g.nx + 1) * j;
     const double mu = TRIAL ? S[mu_slot] : 0.0;
@@ -534,26 +539,37 @@ __global__ __launch_bounds__(NB) void k_vi_eval2d(Grid g, Helm hp, const double*
       const bool act = (x - l <= zeta && Fv > 0.0) || (1.0 - x <= zeta && Fv < 0.0) || (l >= 1.0);
       mask[n] = act ? 1 : 0;
       hdinv[n] = act ? 0.0 : 1.0 / Hd;
+      if (!act) { jlo = -(double)j; jhi = (double)j; }
     }
   }
   const int nb = gridDim.x * gridDim.y, bid = blockIdx.x + gridDim.x * blockIdx.y;
   const int tid = threadIdx.x + NB_X * threadIdx.y;
-  reduce_finish<NB, false>(p2, r2, nb, bid, tid);
-  reduce_finish<NB, true>(pm, rm, nb, bid, tid);
+  block_reduce<NB, false>(p2, r2, nb, bid, tid);
+  block_reduce<NB, true>(pm, rm, nb, bid, tid);
+  if (!TRIAL) {
+    block_reduce<NB, true>(jlo, rlo, nb, bid, tid);
+    block_reduce<NB, true>(jhi, rhi, nb, bid, tid);
+  }
 }
 
 void launch_vi_eval2d(hipStream_t st, const Grid& g, double cL, double cM, double cm,
                       const double* w2, const double* a, const double* d, const double* lo,
                       const double* S, int mu_slot, double zeta, double* F, double* phi,
-                      uint8_t* mask, double* hdinv, Red r2, Red rm, bool trial) {
+                      uint8_t* mask, double* hdinv, Red r2, Red rm, Red rlo, Red rhi, bool trial) {
   Helm hp{cL, cM, cm};
   dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
   if (trial)
     hipLaunchKernelGGL((k_vi_eval2d<true>), gr, bl, 0, st, g, hp, w2, a, d, lo, S, mu_slot, zeta,
-                       F, phi, mask, hdinv, r2, rm);
+                       F, phi, mask, hdinv, r2, rm, rlo, rhi);
   else
     hipLaunchKernelGGL((k_vi_eval2d<false>), gr, bl, 0, st, g, hp, w2, a, d, lo, S, mu_slot, zeta,
-                       F, phi, mask, hdinv, r2, rm);
+                       F, phi, mask, hdinv, r2, rm, rlo, rhi);
+  launch_finish(st, r2, (int)(gr.x * gr.y), false);
+  launch_finish(st, rm, (int)(gr.x * gr.y), true);
+  if (!trial) {
+    launch_finish(st, rlo, (int)(gr.x * gr.y), true);
+    launch_finish(st, rhi, (int)(gr.x * gr.y), true);
+  }
 }
 
 // y = H x (MASKED: rows and columns of active nodes removed, i.e. x is taken
@@ -562,35 +578,43 @@ template <bool MASKED, bool DOT>
 __global__ __launch_bounds__(NB) void k_helm_apply2d(Grid g, Helm hp, const double* __restrict__ w2,
                                                      const double* __restrict__ x,
                                                      const uint8_t* __restrict__ mask,
-                                                     double* __restrict__ y, Red r) {
+                                                     double* __restrict__ y, int j0, int j1,
+                                                     Red r) {
   const int i = blockIdx.x * NB_X + threadIdx.x;
-  const int j = blockIdx.y * NB_Y + threadIdx.y;
+  const int j = j0 + blockIdx.y * NB_Y + threadIdx.y;
   double acc = 0.0;
-  if (i <= g.nx && j <= g.ny) {
+  if (i <= g.nx && j <= j1) {
     const int n = i + (g.nx + 1) * j;
     double Hx, gv, Hd;
-    // x is zero on active nodes already (the reduced CG keeps it so)
-    helm_node2d<false>(g, hp, w2, x, nullptr, nullptr, 0.0, i, j, Hx, gv, Hd);
+    // MASKED: x is read as zero on active nodes, so values outside the
+    // processed row range (all active) never enter
+    helm_node2d<false, MASKED>(g, hp, w2, x, nullptr, nullptr, 0.0, i, j, Hx, gv, Hd, mask);
     if (MASKED && mask[n]) Hx = 0.0;
     y[n] = Hx;
-    if (DOT) acc = x[n] * Hx;
+    if (DOT) acc = (MASKED && mask[n]) ? 0.0 : x[n] * Hx;
   }
   if (DOT)
-    reduce_finish<NB, false>(acc, r, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
+    block_reduce<NB, false>(acc, r, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
                              threadIdx.x + NB_X * threadIdx.y);
 }
 
 void launch_helm_apply2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
-                         const double* x, const uint8_t* mask, double* y, bool dot, Red r) {
+                         const double* x, const uint8_t* mask, double* y, bool dot, Red r,
+                         int j0, int j1) {
   Helm hp{cL, cM, 0.0};
-  dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
+  if (j0 < 0) j0 = 0;
+  if (j1 < 0 || j1 > g.ny) j1 = g.ny;
+  if (j1 < j0) return;
+  dim3 gr((g.nx + 1 + NB_X - 1) / NB_X, (j1 - j0 + 1 + NB_Y - 1) / NB_Y), bl(NB_X, NB_Y);
+#define HELM_CASE(M, D) \
+  hipLaunchKernelGGL((k_helm_apply2d<M, D>), gr, bl, 0, st, g, hp, w2, x, mask, y, j0, j1, r)
   if (mask) {
-    if (dot) hipLaunchKernelGGL((k_helm_apply2d<true, true>), gr, bl, 0, st, g, hp, w2, x, mask, y, r);
-    else hipLaunchKernelGGL((k_helm_apply2d<true, false>), gr, bl, 0, st, g, hp, w2, x, mask, y, r);
+    if (dot) HELM_CASE(true, true); else HELM_CASE(true, false);
   } else {
-    if (dot) hipLaunchKernelGGL((k_helm_apply2d<false, true>), gr, bl, 0, st, g, hp, w2, x, mask, y, r);
-    else hipLaunchKernelGGL((k_helm_apply2d<false, false>), gr, bl, 0, st, g, hp, w2, x, mask, y, r);
+    if (dot) HELM_CASE(false, true); else HELM_CASE(false, false);
   }
+#undef HELM_CASE
+  if (dot) launch_finish(st, r, (int)(gr.x * gr.y), false);
 }
 
 // ---------------------------------------------------------------------------
@@ -630,8 +654,8 @@ __global__ __launch_bounds__(VB) void k_energy2d(Grid g, Mat m, double kell, dou
       su += gc_cw * (wint / ell + ell * area * (grx * grx + gry * gry));
     }
   }
-  reduce_finish<VB, false>(el, rel, gridDim.x, blockIdx.x, threadIdx.x);
-  reduce_finish<VB, false>(su, rsu, gridDim.x, blockIdx.x, threadIdx.x);
+  block_reduce<VB, false>(el, rel, gridDim.x, blockIdx.x, threadIdx.x);
+  block_reduce<VB, false>(su, rsu, gridDim.x, blockIdx.x, threadIdx.x);
 }
 
 void launch_energy2d(hipStream_t st, const Grid& g, const Mat& m, double kell, double gc_cw,
@@ -640,6 +664,8 @@ void launch_energy2d(hipStream_t st, const Grid& g, const Mat& m, double kell, d
   int nb = (ncell + VB - 1) / VB;
   if (nb > VGRID) nb = VGRID;
   hipLaunchKernelGGL(k_energy2d, dim3(nb), dim3(VB), 0, st, g, m, kell, gc_cw, ell, at2, u, a, rel, rsu);
+  launch_finish(st, rel, nb, false);
+  launch_finish(st, rsu, nb, false);
 }
 
 }  // namespace frac

@@ -25,9 +25,12 @@ void launch_w2_2d(hipStream_t st, const Grid& g, const Mat& m, const double* u, 
 void launch_vi_eval2d(hipStream_t st, const Grid& g, double cL, double cM, double cm,
                       const double* w2, const double* a, const double* d, const double* lo,
                       const double* S, int mu_slot, double zeta, double* F, double* phi,
-                      uint8_t* mask, double* hdinv, Red r2, Red rm, bool trial);
+                      uint8_t* mask, double* hdinv, Red r2, Red rm, Red rlo, Red rhi,
+                      bool trial);
+// rows j0..j1 only (j1 < 0: all rows)
 void launch_helm_apply2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
-                         const double* x, const uint8_t* mask, double* y, bool dot, Red r);
+                         const double* x, const uint8_t* mask, double* y, bool dot, Red r,
+                         int j0 = 0, int j1 = -1);
 void launch_energy2d(hipStream_t st, const Grid& g, const Mat& m, double kell, double gc_cw,
                      double ell, int at2, const double* u, const double* a, Red rel, Red rsu);
 
@@ -38,6 +41,7 @@ void launch_dense_solve(hipStream_t st, int n, const double* Ainv, const double*
 
 // ---- vector kernels (vec.hip) -----------------------------------------------
 int vec_blocks(int64_t n);
+void launch_finish(hipStream_t st, const Red& r, int nblocks, bool is_max);
 void launch_cg_update(hipStream_t st, int64_t n, double* x, double* r, const double* p,
                       const double* q, const double* S, Red rr);
 void launch_xpby(hipStream_t st, int64_t n, const double* z, double* p, const double* S);

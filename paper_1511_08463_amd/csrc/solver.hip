@@ -78,7 +78,6 @@ struct fracture {
   uint8_t* mask = nullptr;
   // reductions
   double* S = nullptr;
-  unsigned* cnt = nullptr;
   double* part = nullptr;
   int part_n = 0;
   // coarsest level
@@ -196,7 +195,6 @@ size_t layout(const fracture_params* p, fracture* h, void* ws) {
   t->part_n = pn;
   t->part = c.take<double>(pn * C_SLOTS);
   t->S = c.take<double>(S_COUNT);
-  t->cnt = c.take<unsigned>(C_SLOTS);
   t->nlev = L;
   t->dense_n = dn;
   t->N = N;
@@ -246,7 +244,7 @@ double chebyshev_bound2d(const Grid& g, const Mat& m) {
 }
 
 Red red(fracture* h, int cslot, int sslot, int post = P_STORE) {
-  return Red{h->part + (size_t)cslot * h->part_n, h->cnt + cslot, h->S, sslot, post};
+  return Red{h->part + (size_t)cslot * h->part_n, h->S, sslot, post};
 }
 
 int read_scalars(fracture* h) {
@@ -377,7 +375,7 @@ int line_search(fracture* h, double psi0, double slope, bool* accepted) {
     launch_set_scalar(h->st, h->S, S_MU, mu);
     launch_vi_eval2d(h->st, g, h->cL, h->cM, h->cm, h->w2, h->atil, h->vd, h->alpha_prev, h->S,
                      S_MU, 1e-12, nullptr, nullptr, nullptr, nullptr, red(h, 5, S_TMP0),
-                     red(h, 6, S_TMP1), true);
+                     red(h, 6, S_TMP1), red(h, 12, S_JLO), red(h, 13, S_JHI), true);
     int rc = read_scalars(h);
     if (rc) return rc;
     const double psi = 0.5 * h->hS[S_TMP0];
@@ -400,7 +398,7 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
   for (int it = 0;; ++it) {
     launch_vi_eval2d(st, g, h->cL, h->cM, h->cm, h->w2, h->atil, nullptr, h->alpha_prev, h->S,
                      S_MU, 1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2),
-                     red(h, 6, S_PHIMAX), false);
+                     red(h, 6, S_PHIMAX), red(h, 12, S_JLO), red(h, 13, S_JHI), false);
     int rc = read_scalars(h);
     if (rc) return rc;
     const double phimax = h->hS[S_PHIMAX], phi2 = h->hS[S_PHI2];
@@ -408,31 +406,43 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
     if (phimax <= h->p.vi_tol) return FRACTURE_OK;
     if (it >= h->p.max_vi) return FRACTURE_ENOTCONV;
     ++*vi_iters;
-    // reduced Newton step: H_NN d_N = -F_N (Jacobi CG), d_A = 0
+    // reduced Newton step: H_NN d_N = -F_N (Jacobi CG), d_A = 0.  The CG runs
+    // on the row range that holds every inactive node (its vectors are zero
+    // outside), which for crack bands is a thin strip of the grid.
+    const double jlo = -h->hS[S_JLO], jhi = h->hS[S_JHI];
     launch_neg_masked(st, N, h->F, h->mask, h->vr, h->vd);
-    launch_norm2(st, N, h->vr, red(h, 7, S_TMP2));
-    launch_jacobi_dot(st, N, h->vr, h->hdinv, h->vz, red(h, 1, S_RZ));
-    HIPCHK(hipMemcpyAsync(h->vp, h->vz, N * sizeof(double), hipMemcpyDeviceToDevice, st));
-    rc = read_scalars(h);
-    if (rc) return rc;
-    const double r0 = std::sqrt(h->hS[S_TMP2]);
+    // no inactive node: d = 0, and the line search falls back to steepest descent
+    const bool any_inactive = std::isfinite(jlo) && std::isfinite(jhi) && jhi >= jlo;
+    const int j0 = any_inactive ? (int)jlo : 0, j1 = any_inactive ? (int)jhi : -1;
+    const int64_t W = g.nx + 1, off = (int64_t)j0 * W;
+    const int64_t cnt = any_inactive ? (int64_t)(j1 - j0 + 1) * W : 0;
+    double *vr = h->vr + off, *vz = h->vz + off, *vp = h->vp + off, *vq = h->vq + off,
+           *vd = h->vd + off;
+    const double* hd = h->hdinv + off;
+    if (any_inactive) {
+      launch_norm2(st, cnt, vr, red(h, 7, S_TMP2));
+      launch_jacobi_dot(st, cnt, vr, hd, vz, red(h, 1, S_RZ));
+      HIPCHK(hipMemcpyAsync(vp, vz, cnt * sizeof(double), hipMemcpyDeviceToDevice, st));
+      rc = read_scalars(h);
+      if (rc) return rc;
+    }
+    const double r0 = any_inactive ? std::sqrt(h->hS[S_TMP2]) : 0.0;
     const double tol = h->p.vi_cg_rtol * r0;
     if (r0 > 0) {
-      bool conv = false;
       for (int k = 1; k <= h->p.max_vi_cg; ++k) {
         launch_helm_apply2d(st, g, h->cL, h->cM, h->w2, h->vp, h->mask, h->vq, true,
-                            red(h, 2, S_PQ, P_CG_ALPHA));
-        launch_cg_update(st, N, h->vd, h->vr, h->vp, h->vq, h->S, red(h, 3, S_RR));
+                            red(h, 2, S_PQ, P_CG_ALPHA), j0, j1);
+        launch_cg_update(st, cnt, vd, vr, vp, vq, h->S, red(h, 3, S_RR));
         rc = read_scalars(h);
         if (rc) return rc;
         ++*cg_iters;
         const double rr = h->hS[S_RR];
         if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
-        if (std::sqrt(rr) <= tol) { conv = true; break; }
-        launch_jacobi_dot(st, N, h->vr, h->hdinv, h->vz, red(h, 4, S_RZNEW, P_CG_BETA));
-        launch_xpby(st, N, h->vz, h->vp, h->S);
+        if (std::sqrt(rr) <= tol) break;
+        launch_jacobi_dot(st, cnt, vr, hd, vz, red(h, 4, S_RZNEW, P_CG_BETA));
+        launch_xpby(st, cnt, vz, vp, h->S);
       }
-      (void)conv;  // an inexact step is still a descent direction; the line search decides
+      // an inexact step is still tried: the line search decides
     }
     bool ok = false;
     const double psi0 = 0.5 * phi2;
@@ -464,7 +474,7 @@ int residual_norm(fracture* h, double* out) {
   launch_w2_2d(h->st, g, h->mat, h->u, h->w2);
   launch_vi_eval2d(h->st, g, h->cL, h->cM, h->cm, h->w2, h->alpha, nullptr, h->alpha_prev, h->S,
                    S_MU, 1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2),
-                   red(h, 6, S_PHIMAX), false);
+                   red(h, 6, S_PHIMAX), red(h, 12, S_JLO), red(h, 13, S_JHI), false);
   int rc = read_scalars(h);
   if (rc) return rc;
   *out = std::sqrt(h->hS[S_EU2] + h->hS[S_PHI2]);
@@ -695,7 +705,6 @@ int fracture_create(const fracture_params* p, const uint8_t* notch_mask, void* d
   }
   hipStream_t st = h->st;
   bool ok = true;
-  ok &= hipMemsetAsync(h->cnt, 0, C_SLOTS * sizeof(unsigned), st) == hipSuccess;
   ok &= hipMemsetAsync(h->S, 0, S_COUNT * sizeof(double), st) == hipSuccess;
   ok &= hipMemsetAsync(h->u, 0, h->n2 * sizeof(double), st) == hipSuccess;
   ok &= hipMemsetAsync(h->alpha, 0, h->N * sizeof(double), st) == hipSuccess;
@@ -820,7 +829,7 @@ int fracture_gradient(fracture_t h, double* d_Eu, double* d_Ea) {
     launch_w2_2d(h->st, g, h->mat, h->u, h->w2);
     launch_vi_eval2d(h->st, g, h->cL, h->cM, h->cm, h->w2, h->alpha, nullptr, h->alpha_prev, h->S,
                      S_MU, 1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2),
-                     red(h, 6, S_PHIMAX), false);
+                     red(h, 6, S_PHIMAX), red(h, 12, S_JLO), red(h, 13, S_JHI), false);
     HIPCHK(hipMemcpyAsync(d_Ea, h->F, h->N * sizeof(double), hipMemcpyDeviceToDevice, h->st));
   }
   return hip_ok(hipStreamSynchronize(h->st));
@@ -837,6 +846,60 @@ int fracture_level_shape(fracture_t h, int level, int* nx, int* ny, int* nz) {
   if (nx) *nx = h->lv[level].g.nx;
   if (ny) *ny = h->lv[level].g.ny;
   if (nz) *nz = h->lv[level].g.nz;
+  return FRACTURE_OK;
+}
+
+int fracture_time_kernel(fracture_t h, int kernel, int reps, double* avg_ms, double* bytes) {
+  if (!h || reps < 1 || !avg_ms) return FRACTURE_EINVAL;
+  const Level& L0 = h->lv[0];
+  const Grid& g = L0.g;
+  hipStream_t st = h->st;
+  const double N = (double)h->N;
+  const int64_t n2 = h->n2;
+  // deterministic inputs: the current state
+  HIPCHK(hipMemcpyAsync(L0.xa, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(L0.b, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemsetAsync(L0.d, 0, n2 * sizeof(double), st));
+  launch_w2_2d(st, g, h->mat, h->u, h->w2);
+  launch_vi_eval2d(st, g, h->cL, h->cM, h->cm, h->w2, h->alpha, nullptr, h->alpha_prev, h->S, S_MU,
+                   1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2), red(h, 6, S_PHIMAX), red(h, 12, S_JLO),
+                   red(h, 13, S_JHI), false);
+  HIPCHK(hipMemsetAsync(h->vp, 0, h->N * sizeof(double), st));
+  double b = 0;
+  auto one = [&]() {
+    switch (kernel) {
+      case FRACTURE_KERNEL_APPLY:
+        launch_apply2d(st, g, h->mat, true, h->alpha, h->p.k_ell, L0.xa, L0.xb, nullptr, 1, 1,
+                       red(h, 2, S_PQ, P_STORE));
+        break;
+      case FRACTURE_KERNEL_SMOOTH:
+        launch_smooth2d(st, g, h->mat, true, h->alpha, h->p.k_ell, L0.xa, L0.xb, L0.b, L0.d, L0.d,
+                        h->cheb_cd[1], h->cheb_cr[1]);
+        break;
+      case FRACTURE_KERNEL_VI_EVAL:
+        launch_vi_eval2d(st, g, h->cL, h->cM, h->cm, h->w2, h->alpha, nullptr, h->alpha_prev, h->S,
+                         S_MU, 1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2),
+                         red(h, 6, S_PHIMAX), red(h, 12, S_JLO), red(h, 13, S_JHI), false);
+        break;
+      default:
+        launch_helm_apply2d(st, g, h->cL, h->cM, h->w2, h->vp, h->mask, h->vq, true,
+                            red(h, 2, S_PQ, P_STORE));
+    }
+  };
+  switch (kernel) {
+    case FRACTURE_KERNEL_APPLY: b = 40.0 * N; break;
+    case FRACTURE_KERNEL_SMOOTH: b = 88.0 * N; break;
+    case FRACTURE_KERNEL_VI_EVAL: b = 57.0 * N; break;
+    case FRACTURE_KERNEL_HELM: b = 33.0 * N; break;
+    default: return FRACTURE_EINVAL;
+  }
+  one();  // warm
+  HIPCHK(hipEventRecord(h->ev[5], st));
+  for (int k = 0; k < reps; ++k) one();
+  HIPCHK(hipEventRecord(h->ev[6], st));
+  HIPCHK(hipEventSynchronize(h->ev[6]));
+  *avg_ms = elapsed(h->ev[5], h->ev[6]) / reps;
+  if (bytes) *bytes = b;
   return FRACTURE_OK;
 }
 

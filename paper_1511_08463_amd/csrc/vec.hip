@@ -17,6 +17,32 @@ static int vgrid(int64_t n) {
 
 int vec_blocks(int64_t n) { return vgrid(n); }
 
+// Second pass of every reduction: one block sums (or maxes) the partials in a
+// fixed order and applies the scalar post-operation.
+constexpr int FB = 1024;
+template <bool MAX>
+__global__ __launch_bounds__(FB) void k_finish(Red r, int nblocks) {
+  __shared__ double sh[FB / WAVE];
+  double acc = MAX ? -INFINITY : 0.0;
+  for (int k = threadIdx.x; k < nblocks; k += FB) acc = MAX ? fmax(acc, r.part[k]) : acc + r.part[k];
+  acc = MAX ? wave_max(acc) : wave_sum(acc);
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  if (lane == 0) sh[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = sh[0];
+    for (int k = 1; k < FB / WAVE; ++k) s = MAX ? fmax(s, sh[k]) : s + sh[k];
+    post_scalar(s, r);
+  }
+}
+
+void launch_finish(hipStream_t st, const Red& r, int nblocks, bool is_max) {
+  if (is_max)
+    hipLaunchKernelGGL((k_finish<true>), dim3(1), dim3(FB), 0, st, r, nblocks);
+  else
+    hipLaunchKernelGGL((k_finish<false>), dim3(1), dim3(FB), 0, st, r, nblocks);
+}
+
 #define GRID_STRIDE(k, n) for (int64_t k = (int64_t)blockIdx.x * VB + threadIdx.x; k < (n); k += (int64_t)gridDim.x * VB)
 
 // x += a p; r -= a q; S[slot] = r.r   (a = S[S_ALPHA])
@@ -33,12 +59,13 @@ __global__ __launch_bounds__(VB) void k_cg_update(int64_t n, double* __restrict_
     r[k] = rv;
     acc += rv * rv;
   }
-  reduce_finish<VB, false>(acc, rr, gridDim.x, blockIdx.x, threadIdx.x);
+  block_reduce<VB, false>(acc, rr, gridDim.x, blockIdx.x, threadIdx.x);
 }
 
 void launch_cg_update(hipStream_t st, int64_t n, double* x, double* r, const double* p,
                       const double* q, const double* S, Red rr) {
   hipLaunchKernelGGL(k_cg_update, dim3(vgrid(n)), dim3(VB), 0, st, n, x, r, p, q, S, rr);
+  launch_finish(st, rr, vgrid(n), false);
 }
 
 // p = z + beta p   (beta = S[S_BETA])
@@ -57,11 +84,12 @@ __global__ __launch_bounds__(VB) void k_dot(int64_t n, const double* __restrict_
                                             const double* __restrict__ b, Red r) {
   double acc = 0.0;
   GRID_STRIDE(k, n) acc += a[k] * b[k];
-  reduce_finish<VB, false>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
+  block_reduce<VB, false>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
 }
 
 void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, Red r) {
   hipLaunchKernelGGL(k_dot, dim3(vgrid(n)), dim3(VB), 0, st, n, a, b, r);
+  launch_finish(st, r, vgrid(n), false);
 }
 
 // z = dinv .* r; S = r.z (post)
@@ -74,12 +102,13 @@ __global__ __launch_bounds__(VB) void k_jacobi_dot(int64_t n, const double* __re
     z[k] = zv;
     acc += r[k] * zv;
   }
-  reduce_finish<VB, false>(acc, red, gridDim.x, blockIdx.x, threadIdx.x);
+  block_reduce<VB, false>(acc, red, gridDim.x, blockIdx.x, threadIdx.x);
 }
 
 void launch_jacobi_dot(hipStream_t st, int64_t n, const double* r, const double* dinv, double* z,
                        Red red) {
   hipLaunchKernelGGL(k_jacobi_dot, dim3(vgrid(n)), dim3(VB), 0, st, n, r, dinv, z, red);
+  launch_finish(st, red, vgrid(n), false);
 }
 
 // y = a x + b y (host scalars)
@@ -100,14 +129,16 @@ __global__ __launch_bounds__(VB) void k_norm(int64_t n, const double* __restrict
     const double v = x[k];
     acc = MAX ? fmax(acc, nan_to_inf(fabs(v))) : acc + v * v;
   }
-  reduce_finish<VB, MAX>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
+  block_reduce<VB, MAX>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
 }
 
 void launch_norm2(hipStream_t st, int64_t n, const double* x, Red r) {
   hipLaunchKernelGGL((k_norm<false>), dim3(vgrid(n)), dim3(VB), 0, st, n, x, r);
+  launch_finish(st, r, vgrid(n), false);
 }
 void launch_normmax(hipStream_t st, int64_t n, const double* x, Red r) {
   hipLaunchKernelGGL((k_norm<true>), dim3(vgrid(n)), dim3(VB), 0, st, n, x, r);
+  launch_finish(st, r, vgrid(n), true);
 }
 
 // Reduced damage CG set-up: r = -F on inactive nodes (0 on active), x = 0.
@@ -151,13 +182,14 @@ __global__ __launch_bounds__(VB) void k_relax_alpha(int64_t n, double* __restric
     a[k] = nv;
     acc = fmax(acc, nan_to_inf(fabs(nv - old)));
   }
-  reduce_finish<VB, true>(acc, rd, gridDim.x, blockIdx.x, threadIdx.x);
+  block_reduce<VB, true>(acc, rd, gridDim.x, blockIdx.x, threadIdx.x);
 }
 
 void launch_relax_alpha(hipStream_t st, int64_t n, double* a, const double* at, const double* lo,
                         double omega, const double* S, int wslot, Red rd) {
   hipLaunchKernelGGL(k_relax_alpha, dim3(vgrid(n)), dim3(VB), 0, st, n, a, at, lo, omega, S, wslot,
                      rd);
+  launch_finish(st, rd, vgrid(n), true);
 }
 
 // Exact ratio test: S[slot] = -(largest feasible common factor), reduced as a
@@ -173,12 +205,13 @@ __global__ __launch_bounds__(VB) void k_ratio(int64_t n, const double* __restric
     else if (d < 0.0) lim = (lo[k] - a[k]) / d;
     acc = fmax(acc, -lim);
   }
-  reduce_finish<VB, true>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
+  block_reduce<VB, true>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
 }
 
 void launch_ratio(hipStream_t st, int64_t n, const double* a, const double* at, const double* lo,
                   double omega, Red r) {
   hipLaunchKernelGGL(k_ratio, dim3(vgrid(n)), dim3(VB), 0, st, n, a, at, lo, omega, r);
+  launch_finish(st, r, vgrid(n), true);
 }
 
 // S[slot] = max violation of the bounds by alpha + w (at - alpha) (0 when feasible).
@@ -190,12 +223,13 @@ __global__ __launch_bounds__(VB) void k_violation(int64_t n, const double* __res
     const double v = a[k] + w * (at[k] - a[k]);
     acc = fmax(acc, fmax(v - 1.0, lo[k] - v));
   }
-  reduce_finish<VB, true>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
+  block_reduce<VB, true>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
 }
 
 void launch_violation(hipStream_t st, int64_t n, const double* a, const double* at,
                       const double* lo, double w, Red r) {
   hipLaunchKernelGGL(k_violation, dim3(vgrid(n)), dim3(VB), 0, st, n, a, at, lo, w, r);
+  launch_finish(st, r, vgrid(n), true);
 }
 
 // alpha <- clip(alpha + mu d, lo, 1), mu = S[S_MU]   (projected step, Algorithm 4)
@@ -251,11 +285,12 @@ __global__ __launch_bounds__(VB) void k_neg_sum(int64_t n, const double* __restr
     d[k] = v;
     acc += v * v;
   }
-  reduce_finish<VB, false>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
+  block_reduce<VB, false>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
 }
 
 void launch_neg_sum(hipStream_t st, int64_t n, const double* g, const double* hw, double* d, Red r) {
   hipLaunchKernelGGL(k_neg_sum, dim3(vgrid(n)), dim3(VB), 0, st, n, g, hw, d, r);
+  launch_finish(st, r, vgrid(n), false);
 }
 
 // Scalar store on the device (S[slot] = v) without a host-to-device copy.

@@ -41,6 +41,11 @@ FRACTURE_OP_COUPLING = 3
 FRACTURE_OP_COUPLING_T = 4
 FRACTURE_OP_PRECOND = 5
 
+FRACTURE_KERNEL_APPLY = 0
+FRACTURE_KERNEL_SMOOTH = 1
+FRACTURE_KERNEL_VI_EVAL = 2
+FRACTURE_KERNEL_HELM = 3
+
 
 class fracture_params(ctypes.Structure):
     _fields_ = [
@@ -80,7 +85,7 @@ EXPORTS = [
     "fracture_set_load", "fracture_solve_step", "fracture_solve_steps", "fracture_energy",
     "fracture_get_state", "fracture_set_state", "fracture_apply", "fracture_update_coefficients",
     "fracture_gradient", "fracture_levels", "fracture_level_shape", "fracture_strerror",
-    "fracture_destroy",
+    "fracture_time_kernel", "fracture_destroy",
 ]
 
 _lib = None
@@ -114,6 +119,7 @@ def load_library(path=LIB_PATH):
         "fracture_levels": (ctypes.c_int, [vp, P(ctypes.c_int)]),
         "fracture_level_shape": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int)]),
         "fracture_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "fracture_time_kernel": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, dp, dp]),
         "fracture_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -251,6 +257,13 @@ def fracture_level_shape(h, level):
     _check(load_library().fracture_level_shape(h, level, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
            "fracture_level_shape")
     return a.value, b.value, c.value
+
+
+def fracture_time_kernel(h, kernel, reps):
+    ms, b = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().fracture_time_kernel(h, kernel, reps, ctypes.byref(ms), ctypes.byref(b)),
+           "fracture_time_kernel")
+    return ms.value, b.value
 
 
 def fracture_destroy(h):
