@@ -669,3 +669,239 @@ void launch_energy2d(hipStream_t st, const Grid& g, const Mat& m, double kell, d
 }
 
 }  // namespace frac
+
+namespace frac {
+
+// ---------------------------------------------------------------------------
+// coupled Jacobian (Newton step of Algorithm 3 / 4 on the full problem)
+// ---------------------------------------------------------------------------
+//
+// E_ualpha of eq. (offdiag) with a'(alpha) = -2 (1 - alpha), integrated
+// exactly with P1 alpha:  B[v, j] = sum_e -2 |T| (B_e^T D eps_e(u))_v (M_ref b_e)_j,
+// b = 1 - alpha, M_ref = (1 + delta_ab)/12.
+//
+// k_jac_u2d:  y_u = A x_u + B x_a   (A = K(alpha), Dirichlet rows zero)
+// k_jac_a2d:  y_a = B^T x_u + C x_a (C = H, rows and columns of active nodes removed)
+// Either operand may be absent (nullptr) to apply one block only.
+
+// (M_ref b)-weighted pairing w_e^T M_ref b_e of a triangle's three nodes.
+__device__ __forceinline__ double mref_pair(double w0, double w1, double w2, double b0, double b1,
+                                            double b2) {
+  return (w0 * b0 + w1 * b1 + w2 * b2 + (w0 + w1 + w2) * (b0 + b1 + b2)) * (1.0 / 12.0);
+}
+
+template <bool HAS_XU, bool HAS_XA, bool DOT>
+__global__ __launch_bounds__(NB) void k_jac_u2d(Grid g, Mat m, double kell,
+                                                const double* __restrict__ alpha,
+                                                const double* __restrict__ u,
+                                                const double* __restrict__ xu,
+                                                const double* __restrict__ xa,
+                                                const uint8_t* __restrict__ mask,
+                                                double* __restrict__ yu, Red r) {
+  const int i = blockIdx.x * NB_X + threadIdx.x;
+  const int j = blockIdx.y * NB_Y + threadIdx.y;
+  double acc = 0.0;
+  if (i <= g.nx && j <= g.ny) {
+    const int N = g.N, n = i + (g.nx + 1) * j;
+    double fx = 0, fy = 0, dx, dy;
+    if (HAS_XU) {
+      double c[6];
+      coef6<true>(g, alpha, kell, i, j, c);
+      node_force2d<true, false>(g, m, c, xu, xu + N, i, j, fx, fy, dx, dy);
+    }
+    if (HAS_XA) {
+      // coupling coefficients c_e = -2 w_e^T M_ref b_e with w = x_a masked to the inactive set
+      const int W = g.nx + 1;
+      const bool L = i > 0, R = i < g.nx, D = j > 0, U = j < g.ny;
+      auto w_at = [&](bool ok, int k) -> double { return (ok && !mask[k]) ? xa[k] : 0.0; };
+      auto b_at = [&](bool ok, int k) -> double { return ok ? 1.0 - alpha[k] : 0.0; };
+      const double wC = w_at(true, n), wE = w_at(R, n + 1), wNE = w_at(R && U, n + 1 + W),
+                   wN = w_at(U, n + W), wW = w_at(L, n - 1), wSW = w_at(L && D, n - 1 - W),
+                   wS = w_at(D, n - W);
+      const double bC = b_at(true, n), bE = b_at(R, n + 1), bNE = b_at(R && U, n + 1 + W),
+                   bN = b_at(U, n + W), bW = b_at(L, n - 1), bSW = b_at(L && D, n - 1 - W),
+                   bS = b_at(D, n - W);
+      double c[6];
+      c[0] = -2.0 * mref_pair(wC, wE, wNE, bC, bE, bNE);
+      c[1] = -2.0 * mref_pair(wC, wNE, wN, bC, bNE, bN);
+      c[2] = -2.0 * mref_pair(wW, wC, wN, bW, bC, bN);
+      c[3] = -2.0 * mref_pair(wSW, wS, wC, bSW, bS, bC);
+      c[4] = -2.0 * mref_pair(wSW, wC, wW, bSW, bC, bW);
+      c[5] = -2.0 * mref_pair(wS, wE, wC, bS, bE, bC);
+      double gx, gy;
+      node_force2d<true, false>(g, m, c, u, u + N, i, j, gx, gy, dx, dy);
+      fx += gx;
+      fy += gy;
+    }
+    if (fixed_x2(g, i, j)) fx = 0.0;
+    if (fixed_y2(g, i, j)) fy = 0.0;
+    yu[n] = fx;
+    yu[n + N] = fy;
+    if (DOT) acc = xu[n] * fx + xu[n + N] * fy;
+  }
+  if (DOT)
+    block_reduce<NB, false>(acc, r, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
+                            threadIdx.x + NB_X * threadIdx.y);
+}
+
+// Strain (exx, eyy, gamma) of a P1 field on triangle type t with local nodes 0..2.
+__device__ __forceinline__ void tri_strain(int t, double ihx, double ihy, const double vx[3],
+                                           const double vy[3], double& exx, double& eyy,
+                                           double& gam) {
+  double gx[3], gy[3];
+  tri_grads(t, ihx, ihy, gx, gy);
+  exx = gx[0] * vx[0] + gx[1] * vx[1] + gx[2] * vx[2];
+  eyy = gy[0] * vy[0] + gy[1] * vy[1] + gy[2] * vy[2];
+  gam = gy[0] * vx[0] + gy[1] * vx[1] + gy[2] * vx[2] + gx[0] * vy[0] + gx[1] * vy[1] + gx[2] * vy[2];
+}
+
+template <bool HAS_XU, bool HAS_XA, bool DOT>
+__global__ __launch_bounds__(NB) void k_jac_a2d(Grid g, Mat m, Helm hp,
+                                                const double* __restrict__ alpha,
+                                                const double* __restrict__ u,
+                                                const double* __restrict__ w2,
+                                                const double* __restrict__ xu,
+                                                const double* __restrict__ xa,
+                                                const uint8_t* __restrict__ mask,
+                                                double* __restrict__ ya, Red r) {
+  const int i = blockIdx.x * NB_X + threadIdx.x;
+  const int j = blockIdx.y * NB_Y + threadIdx.y;
+  double acc = 0.0;
+  if (i <= g.nx && j <= g.ny) {
+    const int N = g.N, W = g.nx + 1, n = i + W * j;
+    double y = 0.0;
+    if (!mask[n]) {
+      if (HAS_XA) {
+        double Hx, gv, Hd;
+        helm_node2d<false, true>(g, hp, w2, xa, nullptr, nullptr, 0.0, i, j, Hx, gv, Hd, mask);
+        y += Hx;
+      }
+      if (HAS_XU) {
+        const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy, area = 0.5 * g.hx * g.hy;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const int ci = i + c_tri_di[k], cj = j + c_tri_dj[k];
+          if (ci < 0 || cj < 0 || ci >= g.nx || cj >= g.ny) continue;
+          const int t = c_tri_t[k], v = c_tri_v[k];
+          int di[3], dj[3];
+          tri_nodes(t, di, dj);
+          double ux[3], uy[3], vx[3], vy[3], bb[3];
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            const int nn = ci + di[q] + W * (cj + dj[q]);
+            ux[q] = u[nn]; uy[q] = u[nn + N];
+            vx[q] = xu[nn]; vy[q] = xu[nn + N];
+            bb[q] = 1.0 - alpha[nn];
+          }
+          double e0, e1, e2, f0, f1, f2;
+          tri_strain(t, ihx, ihy, ux, uy, e0, e1, e2);
+          tri_strain(t, ihx, ihy, vx, vy, f0, f1, f2);
+          // sigma(u) : eps(v) with sigma = D eps (engineering shear)
+          const double s = (m.l2m * e0 + m.lam * e1) * f0 + (m.lam * e0 + m.l2m * e1) * f1 + m.mu * e2 * f2;
+          const double mb = (bb[v] + bb[0] + bb[1] + bb[2]) * (1.0 / 12.0);
+          y += -2.0 * area * s * mb;
+        }
+      }
+    }
+    ya[n] = y;
+    if (DOT) acc = (HAS_XA && !mask[n]) ? xa[n] * y : 0.0;
+  }
+  if (DOT)
+    block_reduce<NB, false>(acc, r, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
+                            threadIdx.x + NB_X * threadIdx.y);
+}
+
+// y_u = A x_u + B x_a (either part optional); y_a = B^T x_u + C x_a.
+// dot: S[slot_u] = x_u . y_u and S[slot_a] = x_a . y_a (inactive part).
+void launch_jac2d(hipStream_t st, const Grid& g, const Mat& m, double kell, double cL, double cM,
+                  const double* alpha, const double* u, const double* w2, const uint8_t* mask,
+                  const double* xu, const double* xa, double* yu, double* ya, bool dot, Red ru,
+                  Red ra) {
+  dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
+  Helm hp{cL, cM, 0.0};
+  if (yu) {
+#define JU(A, B, D) \
+  hipLaunchKernelGGL((k_jac_u2d<A, B, D>), gr, bl, 0, st, g, m, kell, alpha, u, xu, xa, mask, yu, ru)
+    if (xu && xa) { if (dot) JU(true, true, true); else JU(true, true, false); }
+    else if (xu) { if (dot) JU(true, false, true); else JU(true, false, false); }
+    else JU(false, true, false);
+#undef JU
+    if (dot && xu) launch_finish(st, ru, (int)(gr.x * gr.y), false);
+  }
+  if (ya) {
+#define JA(A, B, D) \
+  hipLaunchKernelGGL((k_jac_a2d<A, B, D>), gr, bl, 0, st, g, m, hp, alpha, u, w2, xu, xa, mask, ya, ra)
+    if (xu && xa) { if (dot) JA(true, true, true); else JA(true, true, false); }
+    else if (xa) { if (dot) JA(false, true, true); else JA(false, true, false); }
+    else JA(true, false, false);
+#undef JA
+    if (dot && xa) launch_finish(st, ra, (int)(gr.x * gr.y), false);
+  }
+}
+
+// Jacobi-preconditioned Chebyshev step on C = H_NN (the damage block of the
+// Newton Jacobian): d_new = cd d_in + cr D^{-1} (b - C x_in); x_out = x_in + d_new.
+__global__ __launch_bounds__(NB) void k_cheb_helm2d(Grid g, Helm hp, const double* __restrict__ w2,
+                                                    const uint8_t* __restrict__ mask,
+                                                    const double* __restrict__ x_in,
+                                                    double* __restrict__ x_out,
+                                                    const double* __restrict__ b,
+                                                    const double* __restrict__ d_in,
+                                                    double* __restrict__ d_out, double cd,
+                                                    double cr) {
+  const int i = blockIdx.x * NB_X + threadIdx.x;
+  const int j = blockIdx.y * NB_Y + threadIdx.y;
+  if (i > g.nx || j > g.ny) return;
+  const int n = i + (g.nx + 1) * j;
+  if (mask[n]) {
+    x_out[n] = 0.0;
+    if (d_out) d_out[n] = 0.0;
+    return;
+  }
+  double Hx = 0.0, gv, Hd;
+  if (x_in) helm_node2d<false, true>(g, hp, w2, x_in, nullptr, nullptr, 0.0, i, j, Hx, gv, Hd, mask);
+  else helm_node2d<false, true>(g, hp, w2, b, nullptr, nullptr, 0.0, i, j, Hx, gv, Hd, mask);
+  if (!x_in) Hx = 0.0;
+  double dn = cr * (b[n] - Hx) / Hd;
+  if (d_in) dn += cd * d_in[n];
+  x_out[n] = (x_in ? x_in[n] : 0.0) + dn;
+  if (d_out) d_out[n] = dn;
+}
+
+void launch_cheb_helm2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                        const uint8_t* mask, const double* x_in, double* x_out, const double* b,
+                        const double* d_in, double* d_out, double cd, double cr) {
+  Helm hp{cL, cM, 0.0};
+  dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
+  hipLaunchKernelGGL(k_cheb_helm2d, gr, bl, 0, st, g, hp, w2, mask, x_in, x_out, b, d_in, d_out, cd, cr);
+}
+
+// Trial state of the coupled line search: u_t = u + mu d_u on free DOFs,
+// alpha_t = clip(alpha + mu d_a, lo, 1); mu = S[S_MU].
+__global__ __launch_bounds__(VB) void k_trial_state(int64_t n2, int64_t N, const double* __restrict__ u,
+                                                    const double* __restrict__ a,
+                                                    const double* __restrict__ du,
+                                                    const double* __restrict__ da,
+                                                    const double* __restrict__ lo,
+                                                    const double* __restrict__ S,
+                                                    double* __restrict__ ut,
+                                                    double* __restrict__ at) {
+  const double mu = S[S_MU];
+  for (int64_t k = (int64_t)blockIdx.x * VB + threadIdx.x; k < n2 + N; k += (int64_t)gridDim.x * VB) {
+    if (k < n2) ut[k] = u[k] + mu * du[k];
+    else {
+      const int64_t q = k - n2;
+      at[q] = fmin(fmax(a[q] + mu * da[q], lo[q]), 1.0);
+    }
+  }
+}
+
+void launch_trial_state(hipStream_t st, int64_t n2, int64_t N, const double* u, const double* a,
+                        const double* du, const double* da, const double* lo, const double* S,
+                        double* ut, double* at) {
+  int64_t nb = (n2 + N + VB - 1) / VB;
+  if (nb > VGRID) nb = VGRID;
+  hipLaunchKernelGGL(k_trial_state, dim3((int)nb), dim3(VB), 0, st, n2, N, u, a, du, da, lo, S, ut, at);
+}
+
+}  // namespace frac

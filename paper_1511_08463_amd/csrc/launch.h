@@ -34,6 +34,17 @@ void launch_helm_apply2d(hipStream_t st, const Grid& g, double cL, double cM, co
 void launch_energy2d(hipStream_t st, const Grid& g, const Mat& m, double kell, double gc_cw,
                      double ell, int at2, const double* u, const double* a, Red rel, Red rsu);
 
+void launch_jac2d(hipStream_t st, const Grid& g, const Mat& m, double kell, double cL, double cM,
+                  const double* alpha, const double* u, const double* w2, const uint8_t* mask,
+                  const double* xu, const double* xa, double* yu, double* ya, bool dot, Red ru,
+                  Red ra);
+void launch_cheb_helm2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                        const uint8_t* mask, const double* x_in, double* x_out, const double* b,
+                        const double* d_in, double* d_out, double cd, double cr);
+void launch_trial_state(hipStream_t st, int64_t n2, int64_t N, const double* u, const double* a,
+                        const double* du, const double* da, const double* lo, const double* S,
+                        double* ut, double* at);
+
 // ---- coarse dense solve (dense.hip) ----------------------------------------
 void launch_dense_setup2d(hipStream_t st, const Grid& g, const Mat& m, const double* abar,
                           double* A, double* Ainv);

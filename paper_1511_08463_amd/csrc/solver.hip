@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
 
 #include "../../include/fracture.h"
 #include "common.h"
@@ -80,6 +81,12 @@ struct fracture {
   double* S = nullptr;
   double* part = nullptr;
   int part_n = 0;
+  // Newton (ORAM-N): 3N block vectors [u_x | u_y | alpha] and temporaries
+  double *nv_prev = nullptr, *nv = nullptr, *naz = nullptr, *nz = nullptr, *nw_prev = nullptr,
+         *nw = nullptr, *nx = nullptr;
+  double *npu1 = nullptr, *npu2 = nullptr, *npa1 = nullptr, *npa2 = nullptr, *nca = nullptr,
+         *ncb = nullptr, *ncd = nullptr, *nut = nullptr, *nat = nullptr, *nFu = nullptr;
+  double chebC_cd[8] = {}, chebC_cr[8] = {};
   // coarsest level
   double *dA = nullptr, *dAinv = nullptr;
   int dense_n = 0;
@@ -118,7 +125,7 @@ int validate(const fracture_params* p) {
   if (p->relax_mode < 0 || p->relax_mode > 2) return FRACTURE_EINVAL;
   if (p->load_kind != FRACTURE_LOAD_TENSION_2D) return FRACTURE_EINVAL;
   if (p->precision != FRACTURE_FP64) return FRACTURE_EINVAL;
-  if (p->newton) return FRACTURE_EINVAL;
+  if (p->newton && !(p->minres_rtol > 0 && p->max_minres >= 1 && p->max_newton >= 1)) return FRACTURE_EINVAL;
   if (p->max_am < 1 || p->max_pcg < 1 || p->max_vi < 1 || p->max_vi_cg < 1) return FRACTURE_EINVAL;
   if (p->cheb_degree < 1 || p->cheb_degree > 8) return FRACTURE_EINVAL;
   if ((int64_t)(p->nx + 1) * (p->ny + 1) > (int64_t)1 << 30) return FRACTURE_EINVAL;
@@ -186,6 +193,26 @@ size_t layout(const fracture_params* p, fracture* h, void* ws) {
     v.xb = c.take<double>(m2);
     v.d = c.take<double>(m2);
     v.r = c.take<double>(m2);
+  }
+  if (p->newton) {
+    const int64_t n3 = 3 * N;
+    t->nv_prev = c.take<double>(n3);
+    t->nv = c.take<double>(n3);
+    t->naz = c.take<double>(n3);
+    t->nz = c.take<double>(n3);
+    t->nw_prev = c.take<double>(n3);
+    t->nw = c.take<double>(n3);
+    t->nx = c.take<double>(n3);
+    t->npu1 = c.take<double>(n2);
+    t->npu2 = c.take<double>(n2);
+    t->npa1 = c.take<double>(N);
+    t->npa2 = c.take<double>(N);
+    t->nca = c.take<double>(N);
+    t->ncb = c.take<double>(N);
+    t->ncd = c.take<double>(N);
+    t->nut = c.take<double>(n2);
+    t->nat = c.take<double>(N);
+    t->nFu = c.take<double>(n2);
   }
   const int dn = 2 * gl[L - 1].N;
   t->dA = c.take<double>((size_t)dn * dn);
@@ -514,6 +541,205 @@ int relax_alpha(fracture* h) {
   return FRACTURE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Newton composition (Algorithm 3): reduced-space active-set Newton on the
+// coupled optimality system, Jacobian solves by preconditioned MINRES
+// ---------------------------------------------------------------------------
+
+constexpr int CHEB_C = 4;            // Chebyshev steps approximating C^{-1}
+constexpr double CHEB_C_LMAX = 2.0;  // lambda_max(D^{-1} C) <= 2 (element ratios of M and L)
+constexpr double CHEB_C_LMIN = 0.04;
+
+// Phi at (u, a): F_u = K(a) u (Dirichlet rows zero) into Fu; W2(u); F_a, Phi_a,
+// the active set and the inverse diagonal via the VI evaluation.
+// Returns ||Phi||^2 = sum over free rows of F_u^2 + sum Phi_a^2.
+int coupled_residual(fracture* h, const double* u, const double* a, double* Fu, double* phi2) {
+  const Grid& g = h->lv[0].g;
+  launch_apply2d(h->st, g, h->mat, true, a, h->p.k_ell, u, Fu, nullptr, 1, 2, red(h, 0, S_EU2));
+  launch_w2_2d(h->st, g, h->mat, u, h->w2);
+  launch_vi_eval2d(h->st, g, h->cL, h->cM, h->cm, h->w2, a, nullptr, h->alpha_prev, h->S, S_MU,
+                   1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2), red(h, 6, S_PHIMAX),
+                   red(h, 12, S_JLO), red(h, 13, S_JHI), false);
+  int rc = read_scalars(h);
+  if (rc) return rc;
+  *phi2 = h->hS[S_EU2] + h->hS[S_PHI2];
+  return std::isfinite(*phi2) ? FRACTURE_OK : FRACTURE_ENONFINITE;
+}
+
+// y = A^{-1} x approximated by two multigrid V-cycles (a fixed symmetric
+// positive definite operator, as MINRES needs).
+void apply_Ainv(fracture* h, const double* x, double* y) {
+  const Grid& g = h->lv[0].g;
+  const int64_t n2 = h->n2;
+  double* z = vcycle(h, 0, x);
+  (void)hipMemcpyAsync(y, z, n2 * sizeof(double), hipMemcpyDeviceToDevice, h->st);
+  Red none{};
+  launch_resid2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, y, h->npu2, x, false, none);
+  z = vcycle(h, 0, h->npu2);
+  launch_axpby(h->st, n2, 1.0, z, 1.0, y);
+}
+
+// y = C^{-1} x approximated by CHEB_C Jacobi-Chebyshev steps on H_NN from 0.
+void apply_Cinv(fracture* h, const double* x, double* y) {
+  const Grid& g = h->lv[0].g;
+  const double* cur = nullptr;
+  double* bufs[2] = {h->nca, h->ncb};
+  for (int s = 0; s < CHEB_C; ++s) {
+    double* out = (s == CHEB_C - 1) ? y : bufs[s % 2];
+    const double* din = s == 0 ? nullptr : (s == 1 ? cur : h->ncd);
+    double* dout = (s < CHEB_C - 1) ? h->ncd : nullptr;
+    launch_cheb_helm2d(h->st, g, h->cL, h->cM, h->w2, h->mask, cur, out, x, din, dout,
+                       h->chebC_cd[s], h->chebC_cr[s]);
+    cur = out;
+  }
+}
+
+// Block preconditioner with S ~ C (eq. (preconditioner)), applied in the
+// symmetric multiplicative order: y1 = A^{-1} x1; y2 = C^{-1}(x2 - B^T y1);
+// z1 = A^{-1}(x1 - B y2); result [z1; y2].
+void apply_P(fracture* h, const double* x, double* y) {
+  const Grid& g = h->lv[0].g;
+  const int64_t n2 = h->n2, N = h->N;
+  Red none{};
+  apply_Ainv(h, x, h->npu1);                                               // y1
+  launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask,
+               h->npu1, nullptr, nullptr, h->npa1, false, none, none);     // B^T y1
+  launch_axpby(h->st, N, 1.0, x + n2, -1.0, h->npa1);                      // x2 - B^T y1
+  apply_Cinv(h, h->npa1, y + n2);                                          // y2
+  launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask,
+               nullptr, y + n2, h->npu1, nullptr, false, none, none);      // B y2
+  launch_axpby(h->st, n2, 1.0, x, -1.0, h->npu1);                          // x1 - B y2
+  apply_Ainv(h, h->npu1, y);                                               // z1
+}
+
+// y = J x on the inactive coupled system; S[S_TMP0] + S[S_TMP1] = x.y.
+void apply_J(fracture* h, const double* x, double* y) {
+  const Grid& g = h->lv[0].g;
+  const int64_t n2 = h->n2;
+  launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask, x,
+               x + n2, y, y + n2, true, red(h, 7, S_TMP0), red(h, 8, S_TMP1));
+}
+
+double dot3(fracture* h, const double* a, const double* b) {
+  launch_dot(h->st, 3 * h->N, a, b, red(h, 9, S_TMP2));
+  if (read_scalars(h)) return NAN;
+  return h->hS[S_TMP2];
+}
+
+// MINRES (preconditioned; the three-term Lanczos recurrence with Givens
+// rotations) for J d = rhs, rhs in nv.  Solution in nx.
+int minres(fracture* h, int* iters) {
+  hipStream_t st = h->st;
+  const int64_t n3 = 3 * h->N;
+  HIPCHK(hipMemsetAsync(h->nx, 0, n3 * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(h->nv_prev, 0, n3 * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(h->nw_prev, 0, n3 * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(h->nw, 0, n3 * sizeof(double), st));
+  double *v_prev = h->nv_prev, *v = h->nv, *az = h->naz, *z = h->nz, *w_prev = h->nw_prev,
+         *w = h->nw;
+  apply_P(h, v, z);
+  double g = dot3(h, z, v);
+  if (!std::isfinite(g)) return FRACTURE_ENONFINITE;
+  if (g <= 0.0) { *iters = 0; return FRACTURE_OK; }
+  g = std::sqrt(g);
+  const double g1 = g;
+  double g_prev = 1.0, eta = g, s_prev = 0.0, s = 0.0, c_prev = 1.0, c = 1.0;
+  for (int j = 1; j <= h->p.max_minres; ++j) {
+    launch_axpby(st, n3, 1.0 / g, z, 0.0, z);
+    apply_J(h, z, az);
+    int rc = read_scalars(h);
+    if (rc) return rc;
+    const double d = h->hS[S_TMP0] + h->hS[S_TMP1];
+    launch_axpby(st, n3, -d / g, v, 1.0, az);
+    launch_axpby(st, n3, -g / g_prev, v_prev, 1.0, az);          // az = v_{j+1}
+    double* vn = az;
+    apply_P(h, vn, v_prev);                                      // v_prev buffer <- z_{j+1}
+    double* zn = v_prev;
+    const double gn2 = dot3(h, zn, vn);
+    if (!std::isfinite(gn2) || !std::isfinite(d)) return FRACTURE_ENONFINITE;
+    const double gn = std::sqrt(gn2 > 0 ? gn2 : 0.0);
+    const double a0 = c * d - c_prev * s * g;
+    const double a1 = std::sqrt(a0 * a0 + gn * gn);
+    const double a2 = s * d + c_prev * c * g;
+    const double a3 = s_prev * g;
+    const double cn = a0 / a1, sn = gn / a1;
+    // w_{j+1} = (z_j - a3 w_{j-1} - a2 w_j) / a1, written into w_prev
+    launch_axpby(st, n3, 1.0 / a1, z, -a3 / a1, w_prev);
+    launch_axpby(st, n3, -a2 / a1, w, 1.0, w_prev);
+    launch_axpby(st, n3, cn * eta, w_prev, 1.0, h->nx);
+    eta = -sn * eta;
+    // rotate buffers
+    double* old_v = v;
+    v_prev = old_v;            // v_{j}
+    v = vn;                    // v_{j+1}
+    az = z;                    // free buffer
+    z = zn;                    // z_{j+1}
+    std::swap(w_prev, w);      // w <- w_{j+1}, w_prev <- w_j
+    g_prev = g; g = gn;
+    c_prev = c; c = cn;
+    s_prev = s; s = sn;
+    *iters = j;
+    if (std::fabs(eta) <= h->p.minres_rtol * g1 || gn == 0.0) return FRACTURE_OK;
+  }
+  return FRACTURE_OK;  // an inexact Newton direction is still tried by the line search
+}
+
+// One Newton phase (Algorithm 3, inner loop): iterate until ||Phi|| <=
+// final_tol (converged), the line search fails or max_newton is reached
+// (failed).  *nphi receives the final ||Phi||_2.
+int newton_phase(fracture* h, fracture_stats* st, double* nphi, bool* converged) {
+  hipStream_t s = h->st;
+  const int64_t n2 = h->n2, N = h->N;
+  *converged = false;
+  double phi2 = 0;
+  int rc = coupled_residual(h, h->u, h->alpha, h->nFu, &phi2);
+  if (rc) return rc;
+  for (int it = 0; it < h->p.max_newton; ++it) {
+    *nphi = std::sqrt(phi2);
+    if (*nphi <= h->p.final_tol) { *converged = true; return FRACTURE_OK; }
+    update_coefficients(h);
+    // rhs = -[F_u; F_a on the inactive set]
+    launch_axpby(s, n2, -1.0, h->nFu, 0.0, h->nv);
+    launch_neg_masked(s, N, h->F, h->mask, h->nv + n2, h->nca);
+    int its = 0;
+    rc = minres(h, &its);
+    st->minres_iters += its;
+    if (rc) return rc;
+    ++st->newton_iters;
+    // projected Armijo search on psi = 1/2 ||Phi||^2 (Newton direction: slope -2 psi)
+    const double psi0 = 0.5 * phi2;
+    double mu = 1.0;
+    bool ok = false;
+    for (int k = 0; k <= MAX_HALVINGS; ++k) {
+      launch_set_scalar(s, h->S, S_MU, mu);
+      launch_trial_state(s, n2, N, h->u, h->alpha, h->nx, h->nx + n2, h->alpha_prev, h->S, h->nut,
+                         h->nat);
+      double p2t = 0;
+      rc = coupled_residual(h, h->nut, h->nat, h->npu2, &p2t);
+      if (rc == FRACTURE_ENONFINITE) { mu *= 0.5; continue; }
+      if (rc) return rc;
+      if (0.5 * p2t <= psi0 * (1.0 - 2.0 * ARMIJO_SIGMA * mu)) {
+        HIPCHK(hipMemcpyAsync(h->u, h->nut, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(h->alpha, h->nat, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(h->nFu, h->npu2, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        phi2 = p2t;
+        ok = true;
+        break;
+      }
+      mu *= 0.5;
+    }
+    if (!ok) {
+      // restore the active set / residual of the accepted point for the caller
+      rc = coupled_residual(h, h->u, h->alpha, h->nFu, &phi2);
+      *nphi = std::sqrt(phi2);
+      return rc;
+    }
+  }
+  *nphi = std::sqrt(phi2);
+  if (*nphi <= h->p.final_tol) *converged = true;
+  return FRACTURE_OK;
+}
+
 float elapsed(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
@@ -529,7 +755,8 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
   HIPCHK(hipMemcpyAsync(h->u_entry, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(h->alpha_entry, h->alpha, N * sizeof(double), hipMemcpyDeviceToDevice, st));
   int rc = FRACTURE_OK;
-  double ms_pcg = 0, ms_vi = 0;
+  double ms_pcg = 0, ms_vi = 0, ms_newton = 0;
+  double threshold = h->p.switch_tol;
   for (int sweep = 1; sweep <= h->p.max_am; ++sweep) {
     update_coefficients(h);
     if (sweep == 1) {
@@ -563,7 +790,7 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
     ms_vi += elapsed(h->ev[2], h->ev[3]);
     loc.dalpha_inf = h->hS[S_DAMAX];
     if (!std::isfinite(loc.dalpha_inf)) { rc = FRACTURE_ENONFINITE; break; }
-    if (h->p.am_stop == FRACTURE_STOP_DALPHA) {
+    if (!h->p.newton && h->p.am_stop == FRACTURE_STOP_DALPHA) {
       if (loc.dalpha_inf < h->p.am_tol) { loc.converged = 1; break; }
     } else {
       double nphi = 0;
@@ -572,6 +799,19 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
       loc.phi_l2 = nphi;
       if (!std::isfinite(nphi)) { rc = FRACTURE_ENONFINITE; break; }
       if (nphi <= h->p.final_tol) { loc.converged = 1; break; }
+      if (h->p.newton && nphi < threshold) {
+        HIPCHK(hipEventRecord(h->ev[1], st));
+        bool conv = false;
+        rc = newton_phase(h, &loc, &nphi, &conv);
+        HIPCHK(hipEventRecord(h->ev[2], st));
+        HIPCHK(hipEventSynchronize(h->ev[2]));
+        ms_newton += elapsed(h->ev[1], h->ev[2]);
+        if (rc) break;
+        loc.phi_l2 = nphi;
+        if (conv) { loc.converged = 1; break; }
+        ++loc.newton_failures;
+        threshold = h->p.switch_rel * nphi;   // back to ORAM until Phi falls by switch_rel
+      }
     }
   }
   if (rc == FRACTURE_OK && !loc.converged) rc = FRACTURE_ENOTCONV;
@@ -587,6 +827,7 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
   loc.ms_total = elapsed(h->ev[0], h->ev[4]);
   loc.ms_pcg = ms_pcg;
   loc.ms_vi = ms_vi;
+  loc.ms_newton = ms_newton;
   if (s) *s = loc;
   return rc;
 }
@@ -691,6 +932,19 @@ int fracture_create(const fracture_params* p, const uint8_t* notch_mask, void* d
     h->cheb_cd[s] = rn * rho;
     h->cheb_cr[s] = 2.0 * rn / delta;
     rho = rn;
+  }
+  {
+    const double th = 0.5 * (CHEB_C_LMAX + CHEB_C_LMIN), de = 0.5 * (CHEB_C_LMAX - CHEB_C_LMIN);
+    const double sg = th / de;
+    double rh = 1.0 / sg;
+    h->chebC_cd[0] = 0.0;
+    h->chebC_cr[0] = 1.0 / th;
+    for (int k = 1; k < CHEB_C; ++k) {
+      const double rn = 1.0 / (2.0 * sg - rh);
+      h->chebC_cd[k] = rn * rh;
+      h->chebC_cr[k] = 2.0 * rn / de;
+      rh = rn;
+    }
   }
   if (hipHostMalloc((void**)&h->hS, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete h;
@@ -808,6 +1062,18 @@ int fracture_apply(fracture_t h, int op, int level, const double* d_x, double* d
       launch_w2_2d(h->st, g, h->mat, h->u, h->w2);
       launch_helm_apply2d(h->st, g, h->cL, h->cM, h->w2, d_x, nullptr, d_y, false, none);
       break;
+    case FRACTURE_OP_COUPLING:
+    case FRACTURE_OP_COUPLING_T: {
+      // the full coupling block (no active set): mask cleared
+      launch_w2_2d(h->st, g, h->mat, h->u, h->w2);
+      HIPCHK(hipMemsetAsync(h->mask, 0, h->N, h->st));
+      if (op == FRACTURE_OP_COUPLING)
+        launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask,
+                     nullptr, d_x, d_y, nullptr, false, none, none);
+      else
+        launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask,
+                     d_x, nullptr, nullptr, d_y, false, none, none);
+    } break;
     case FRACTURE_OP_PRECOND: {
       if (!h->coef_valid) update_coefficients(h);
       double* z = vcycle(h, 0, d_x);

@@ -263,3 +263,58 @@ def test_bitwise_reproducible():
         s.close()
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
+
+
+# ----------------------------------------------------------------------------- Newton composition
+
+def test_coupling_blocks_match_assembled():
+    """E_ualpha (eq. (offdiag)) and its transpose, matrix-free vs assembled."""
+    nx, ny = 96, 80
+    p = workloads.tension(nx, 0.05, "AT1", nx=nx, ny=ny)
+    s = _solver(p, None, newton=1)
+    P = _problem(p)
+    u, alpha = workloads.random_fields(P.model.N, 2 * P.model.N, seed=5)
+    u *= 0.1
+    s.set_state(u=u, alpha=alpha, alpha_prev=np.zeros(P.model.N))
+    B = P.model.coupling(u, alpha)
+    rng = np.random.default_rng(4)
+    w = rng.standard_normal(P.model.N)
+    y = s.apply(fracture.FRACTURE_OP_COUPLING, w, out_len=2 * P.model.N)
+    want = B @ w
+    want[P.fixed] = 0.0
+    assert np.max(np.abs(y - want)) / np.max(np.abs(want)) < OPS_TOL
+    v = rng.standard_normal(2 * P.model.N) * P.free
+    y = s.apply(fracture.FRACTURE_OP_COUPLING_T, v, out_len=P.model.N)
+    want = B.T @ v
+    assert np.max(np.abs(y - want)) / np.max(np.abs(want)) < OPS_TOL
+    s.close()
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.4])
+def test_oram_newton_parity(omega):
+    """ORAM-N (Algorithm 3) to ||Phi||_2 <= 1e-9 against the oracle's ORAM-N
+    (exact LU Newton steps) on a growing crack: same converged state."""
+    n = 48
+    p, notch, _ = workloads.small_tension(n, "AT1", ell=0.08)
+    print(f"[oram-n] omega={omega}", flush=True)
+    loads = [0.3, 0.9]
+    s = _solver(p, notch, omega=omega, newton=1, switch_tol=1e-3, final_tol=1e-9,
+                pcg_rtol=1e-12, vi_cg_rtol=1e-12, minres_rtol=1e-8, max_newton=20)
+    P = _problem(p)
+    st = am.initial_state(P, notch.astype(bool))
+    total_newton = 0
+    for t in loads:
+        s.set_load(t)
+        stats = s.solve_step()
+        o = am.solve_load_step(P, st, t, omega=omega, newton_on=True, switch_tol=1e-3,
+                               final_tol=1e-9, max_am=5000)
+        u, a, _ = s.state()
+        eu, ea = _rel(u, st.u), _rel(a, st.alpha)
+        total_newton += stats["newton_iters"]
+        print(f"  t={t} sweeps={stats['sweeps']} newton={stats['newton_iters']} minres={stats['minres_iters']} "
+              f"fails={stats['newton_failures']} phi={stats['phi_l2']:.2e} oracle sweeps={o['sweeps']} "
+              f"newton={o['newton_its']} rel_u={eu:.2e} rel_a={ea:.2e}", flush=True)
+        assert stats["converged"] and stats["phi_l2"] <= 1e-9
+        assert eu < STEP_TOL and ea < STEP_TOL
+    assert total_newton > 0
+    s.close()

@@ -213,3 +213,26 @@ def test_oram_n_reaches_am_fixed_point_and_recovers_from_failure():
         assert np.allclose(st.u, ref.u, atol=1e-7)
         nphi = np.linalg.norm(am.residual(P, st))
         assert nphi <= 1e-11
+
+
+def test_block_preconditioner_identity():
+    """The fieldsplit preconditioner with S ~ C (Sec. 3.3) read with the lower
+    factor [[I, 0], [-B^T, I]]: its action y1 = A^-1 x1, y2 = C^-1 (x2 - B^T y1),
+    z1 = A^-1 (x1 - B y2) equals the inverse of [[A, B], [B^T, C + B^T A^-1 B]]
+    and the expanded block form printed in the paper."""
+    rng = np.random.default_rng(0)
+    n1, n2 = 7, 5
+    X = rng.standard_normal((n1, n1)); A = X @ X.T + n1 * np.eye(n1)
+    Y = rng.standard_normal((n2, n2)); C = Y @ Y.T + n2 * np.eye(n2)
+    B = rng.standard_normal((n1, n2))
+    Ai, Ci = np.linalg.inv(A), np.linalg.inv(C)
+    x = rng.standard_normal(n1 + n2)
+    y1 = Ai @ x[:n1]
+    y2 = Ci @ (x[n1:] - B.T @ y1)
+    z1 = Ai @ (x[:n1] - B @ y2)
+    P = np.block([[A, B], [B.T, C + B.T @ Ai @ B]])
+    assert np.allclose(np.concatenate([z1, y2]), np.linalg.solve(P, x))
+    expanded = np.block([[Ai + Ai @ B @ Ci @ B.T @ Ai, -Ai @ B @ Ci], [-Ci @ B.T @ Ai, Ci]])
+    assert np.allclose(expanded @ x, np.linalg.solve(P, x))
+    # and it is symmetric positive definite
+    assert np.allclose(expanded, expanded.T) and np.linalg.eigvalsh(expanded).min() > 0
