@@ -71,6 +71,11 @@ def main():
     ap.add_argument("--omega", type=float, default=1.0)
     ap.add_argument("--am-tol", type=float, default=1e-5)
     ap.add_argument("--pcg-rtol", type=float, default=1e-8)
+    ap.add_argument("--newton", type=int, default=1, help="ORAM-N (1) or ORAM alone (0)")
+    ap.add_argument("--switch-tol", type=float, default=1e-3)
+    ap.add_argument("--final-tol", type=float, default=1e-7)
+    ap.add_argument("--minres-rtol", type=float, default=1e-6)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -90,10 +95,23 @@ def main():
     dev = torch.device("cuda:0")
     p, notch, loads, (y0, a) = workloads.config2(args.model, args.omega, seed=0, n=args.n)
     params = fracture.make_params(**p, am_tol=args.am_tol, pcg_rtol=args.pcg_rtol,
-                                  vi_cg_rtol=1e-10, max_am=5000)
-    log(f"[bench] {args.n}^2 {args.model} omega={args.omega} notch y0={y0:.4f} a={a:.4f} "
+                                  vi_cg_rtol=1e-10, max_am=5000, newton=args.newton,
+                                  switch_tol=args.switch_tol, final_tol=args.final_tol,
+                                  minres_rtol=args.minres_rtol,
+                                  precision=fracture.FRACTURE_MIXED if args.precision == "mixed"
+                                  else fracture.FRACTURE_FP64)
+    log(f"[bench] {args.precision} {args.n}^2 {args.model} omega={args.omega} notch y0={y0:.4f} a={a:.4f} "
         f"warmup={args.warmup} steps={args.steps}")
     solver = fracture.Fracture(params, notch, device=dev)
+    last = [time.perf_counter()]
+
+    def monitor(sweep, da, phi):
+        now = time.perf_counter()
+        if now - last[0] > 5.0:
+            last[0] = now
+            log(f"[bench]   ... sweep/newton {sweep} dalpha={da:.2e} phi={phi:.2e}")
+
+    solver.set_monitor(monitor)
     free_dofs = solver.ndof - (args.n + 1) * 2 - 1
 
     def run(k):
@@ -102,8 +120,10 @@ def main():
         st = solver.solve_step()
         st["wall_s"] = time.perf_counter() - t0
         log(f"[bench] step {k + 1} t={loads[k]:.2f} sweeps={st['sweeps']} pcg={st['pcg_iters']} "
-            f"vi={st['vi_iters']} vi_cg={st['vi_cg_iters']} dalpha={st['dalpha_inf']:.2e} "
-            f"ms={st['ms_total']:.1f} (pcg {st['ms_pcg']:.1f}, vi {st['ms_vi']:.1f})")
+            f"vi={st['vi_iters']} vi_cg={st['vi_cg_iters']} newton={st['newton_iters']} "
+            f"minres={st['minres_iters']} fails={st['newton_failures']} dalpha={st['dalpha_inf']:.2e} "
+            f"phi={st['phi_l2']:.2e} ms={st['ms_total']:.1f} (pcg {st['ms_pcg']:.1f}, vi {st['ms_vi']:.1f}, "
+            f"newton {st['ms_newton']:.1f})")
         return st
 
     for k in range(args.warmup):
@@ -138,15 +158,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32 inside f64 refinement",
         "data": "synthetic",
         "config": {
             "workload": (f"{args.n}x{args.n} plane-strain unit square, P1 right-diagonal triangles, "
                          f"{args.model}, ell=4h, k_ell=1e-6, seeded edge notch (y0={y0:.4f}, a={a:.4f}), "
                          f"tension load steps t=0.1k, k={args.warmup + 1}..{args.warmup + args.steps} timed; "
-                         f"ORAM omega={args.omega} to ||dalpha||inf<{args.am_tol:g}, PCG rtol {args.pcg_rtol:g}"),
-            "precision": "fp64",
-            "newton": False,
+                         + (f"ORAM omega={args.omega} switching to reduced-space Newton at ||Phi||2<{args.switch_tol:g}, "
+                            f"stop ||Phi||2<{args.final_tol:g}" if args.newton else
+                            f"ORAM omega={args.omega} to ||dalpha||inf<{args.am_tol:g}")
+                         + f", PCG rtol {args.pcg_rtol:g}"),
+            "precision": args.precision,
+            "newton": bool(args.newton),
         },
         "pcg_dof_iter_per_s": free_dofs * pcg_iters / pcg_s if pcg_s > 0 else None,
         "sweeps": sweeps,

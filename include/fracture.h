@@ -157,6 +157,12 @@ int fracture_solve_step(fracture_t h, fracture_stats* out);
    calls; out (host) has n entries or is NULL; codes (host) has n entries. */
 int fracture_solve_steps(fracture_t* hs, int n, fracture_stats* out, int* codes);
 
+/* Progress monitor: when set, fn(user, sweep, dalpha_inf, phi_l2) is called
+   on the host after every ORAM sweep and Newton iteration of solve_step
+   (phi_l2 is -1 when not computed).  fn = NULL removes it. */
+typedef void (*fracture_monitor_fn)(void* user, int sweep, double dalpha_inf, double phi_l2);
+int fracture_set_monitor(fracture_t h, fracture_monitor_fn fn, void* user);
+
 /* Elastic and surface parts of eq. (regenergy) at the current state
    (host outputs). */
 int fracture_energy(fracture_t h, double* elastic, double* surface);

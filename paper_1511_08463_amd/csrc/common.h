@@ -12,6 +12,11 @@
 
 namespace frac {
 
+// Non-deduced type alias: lets nullptr stand for an optional T* argument of a
+// function template whose T is fixed by the other arguments.
+template <class T> struct NonDeduced { using type = T; };
+template <class T> using ND = typename NonDeduced<T>::type;
+
 constexpr int WAVE = 64;
 constexpr int NB_X = 64;          // 2D node kernels: 64 x 4 threads per block
 constexpr int NB_Y = 4;
@@ -47,7 +52,7 @@ struct Mat {
 };
 
 // What the finishing block does with a reduced sum s (see post_scalar).
-enum Post { P_STORE = 0, P_CG_ALPHA, P_CG_BETA, P_SQRT, P_NEG };
+enum Post { P_STORE = 0, P_CG_ALPHA, P_CG_BETA, P_SQRT, P_NEG, P_FCG_BETA, P_FCG_ALPHA };
 
 struct Red {
   double* part;       // >= number of blocks of the launch
@@ -86,6 +91,16 @@ __device__ __forceinline__ void post_scalar(double s, const Red& r) {
     case P_NEG:
       r.S[r.slot] = -s;
       break;
+    case P_FCG_BETA: {  // beta = -(z.q_prev) / (p_prev.q_prev)
+      const double pq = r.S[S_PQ];
+      r.S[S_BETA] = (pq != 0.0) ? -s / pq : 0.0;
+      r.S[r.slot] = s;
+    } break;
+    case P_FCG_ALPHA: {  // alpha = (p.r) / (p.q)
+      const double pq = r.S[S_PQ];
+      r.S[S_ALPHA] = (pq != 0.0) ? s / pq : 0.0;
+      r.S[r.slot] = s;
+    } break;
     default:
       r.S[r.slot] = s;
   }

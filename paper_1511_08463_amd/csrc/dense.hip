@@ -108,23 +108,27 @@ void launch_dense_setup2d(hipStream_t st, const Grid& g, const Mat& m, const dou
   hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(DB), 2 * n * sizeof(double), st, n, A, Ainv);
 }
 
-// x = Ainv b (dense, one block; row-per-thread with b in LDS).
+// x = Ainv b (dense, one block; row-per-thread with b in LDS; float64
+// accumulation for either value type of b and x).
+template <class T>
 __global__ __launch_bounds__(DB) void k_dense_solve(int n, const double* __restrict__ Ainv,
-                                                    const double* __restrict__ b,
-                                                    double* __restrict__ x) {
+                                                    const T* __restrict__ b, T* __restrict__ x) {
   extern __shared__ double sb[];
-  for (int i = threadIdx.x; i < n; i += DB) sb[i] = b[i];
+  for (int i = threadIdx.x; i < n; i += DB) sb[i] = (double)b[i];
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += DB) {
     double s = 0.0;
     const double* row = Ainv + (size_t)i * n;
     for (int j = 0; j < n; ++j) s += row[j] * sb[j];
-    x[i] = s;
+    x[i] = T(s);
   }
 }
 
-void launch_dense_solve(hipStream_t st, int n, const double* Ainv, const double* b, double* x) {
-  hipLaunchKernelGGL(k_dense_solve, dim3(1), dim3(DB), n * sizeof(double), st, n, Ainv, b, x);
+template <class T>
+void launch_dense_solve(hipStream_t st, int n, const double* Ainv, const T* b, T* x) {
+  hipLaunchKernelGGL((k_dense_solve<T>), dim3(1), dim3(DB), n * sizeof(double), st, n, Ainv, b, x);
 }
+template void launch_dense_solve<float>(hipStream_t, int, const double*, const float*, float*);
+template void launch_dense_solve<double>(hipStream_t, int, const double*, const double*, double*);
 
 }  // namespace frac

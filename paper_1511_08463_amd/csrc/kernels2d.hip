@@ -33,27 +33,29 @@ __device__ __forceinline__ bool fixed_y2(const Grid& g, int i, int j) {
 // the node operator
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double abar3(double a0, double a1, double a2, double k) {
-  const double b0 = 1.0 - a0, b1 = 1.0 - a1, b2 = 1.0 - a2, s = b0 + b1 + b2;
-  return k + (b0 * b0 + b1 * b1 + b2 * b2 + s * s) * (1.0 / 12.0);
+template <class T>
+__device__ __forceinline__ T abar3(T a0, T a1, T a2, T k) {
+  const T b0 = T(1) - a0, b1 = T(1) - a1, b2 = T(1) - a2, s = b0 + b1 + b2;
+  return k + (b0 * b0 + b1 * b1 + b2 * b2 + s * s) * (T(1) / T(12));
 }
 
 // Coefficients of the six triangles around node (i, j), in the order
 // (a) cell(i,j) T0, (b) cell(i,j) T1, (c) cell(i-1,j) T0,
 // (d) cell(i-1,j-1) T0, (e) cell(i-1,j-1) T1, (f) cell(i,j-1) T1.
-template <bool FA>
-__device__ __forceinline__ void coef6(const Grid& g, const double* __restrict__ coef, double kell,
-                                      int i, int j, double c[6]) {
+// FA: from nodal alpha (finest level); otherwise from the element array.
+template <bool FA, class T>
+__device__ __forceinline__ void coef6(const Grid& g, const T* __restrict__ coef, T kell, int i,
+                                      int j, T c[6]) {
   const int W = g.nx + 1, n = i + W * j;
   const bool L = i > 0, R = i < g.nx, D = j > 0, U = j < g.ny;
   if (FA) {
-    const double aC = coef[n];
-    const double aE = R ? coef[n + 1] : 0.0;
-    const double aNE = (R && U) ? coef[n + 1 + W] : 0.0;
-    const double aN = U ? coef[n + W] : 0.0;
-    const double aW = L ? coef[n - 1] : 0.0;
-    const double aSW = (L && D) ? coef[n - 1 - W] : 0.0;
-    const double aS = D ? coef[n - W] : 0.0;
+    const T aC = coef[n];
+    const T aE = R ? coef[n + 1] : T(0);
+    const T aNE = (R && U) ? coef[n + 1 + W] : T(0);
+    const T aN = U ? coef[n + W] : T(0);
+    const T aW = L ? coef[n - 1] : T(0);
+    const T aSW = (L && D) ? coef[n - 1 - W] : T(0);
+    const T aS = D ? coef[n - W] : T(0);
     c[0] = abar3(aC, aE, aNE, kell);
     c[1] = abar3(aC, aNE, aN, kell);
     c[2] = abar3(aW, aC, aN, kell);
@@ -62,28 +64,27 @@ __device__ __forceinline__ void coef6(const Grid& g, const double* __restrict__ 
     c[5] = abar3(aS, aE, aC, kell);
   } else {
     const int nx = g.nx;
-    c[0] = (R && U) ? coef[2 * (i + nx * j)] : 0.0;
-    c[1] = (R && U) ? coef[2 * (i + nx * j) + 1] : 0.0;
-    c[2] = (L && U) ? coef[2 * (i - 1 + nx * j)] : 0.0;
-    c[3] = (L && D) ? coef[2 * (i - 1 + nx * (j - 1))] : 0.0;
-    c[4] = (L && D) ? coef[2 * (i - 1 + nx * (j - 1)) + 1] : 0.0;
-    c[5] = (R && D) ? coef[2 * (i + nx * (j - 1)) + 1] : 0.0;
+    c[0] = (R && U) ? coef[2 * (i + nx * j)] : T(0);
+    c[1] = (R && U) ? coef[2 * (i + nx * j) + 1] : T(0);
+    c[2] = (L && U) ? coef[2 * (i - 1 + nx * j)] : T(0);
+    c[3] = (L && D) ? coef[2 * (i - 1 + nx * (j - 1))] : T(0);
+    c[4] = (L && D) ? coef[2 * (i - 1 + nx * (j - 1)) + 1] : T(0);
+    c[5] = (R && D) ? coef[2 * (i + nx * (j - 1)) + 1] : T(0);
   }
 }
 
 // Force (fx, fy) = (K x) at node (i, j) and, when DIAG, the diagonal entries
 // (dx, dy) of K for the node's two DOFs.
-template <bool HASX, bool DIAG>
-__device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const double c[6],
-                                             const double* __restrict__ ux,
-                                             const double* __restrict__ uy, int i, int j,
-                                             double& fx, double& fy, double& dx, double& dy) {
+template <bool HASX, bool DIAG, class T>
+__device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const T c[6],
+                                             const T* __restrict__ ux, const T* __restrict__ uy,
+                                             int i, int j, T& fx, T& fy, T& dx, T& dy) {
   const int W = g.nx + 1, n = i + W * j;
   const bool L = i > 0, R = i < g.nx, D = j > 0, U = j < g.ny;
-  const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy, area = 0.5 * g.hx * g.hy;
-  const double l2m = m.l2m, lam = m.lam, mu = m.mu;
-  double cx = 0, cy = 0, ex = 0, ey = 0, nex = 0, ney = 0, nnx = 0, nny = 0;
-  double wx = 0, wy = 0, swx = 0, swy = 0, sx = 0, sy = 0;
+  const T ihx = T(1.0 / g.hx), ihy = T(1.0 / g.hy), area = T(0.5 * g.hx * g.hy);
+  const T l2m = T(m.l2m), lam = T(m.lam), mu = T(m.mu);
+  T cx = 0, cy = 0, ex = 0, ey = 0, nex = 0, ney = 0, nnx = 0, nny = 0;
+  T wx = 0, wy = 0, swx = 0, swy = 0, sx = 0, sy = 0;
   if (HASX) {
     cx = ux[n];
     cy = uy[n];
@@ -94,15 +95,15 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
     if (L && D) { swx = ux[n - 1 - W]; swy = uy[n - 1 - W]; }
     if (D) { sx = ux[n - W]; sy = uy[n - W]; }
   }
-  fx = fy = dx = dy = 0.0;
-  const double hxx = ihx * ihx, hyy = ihy * ihy;
+  fx = fy = dx = dy = T(0);
+  const T hxx = ihx * ihx, hyy = ihy * ihy;
   // (a) cell(i,j) T0: node is vertex 0, gradient (-1/hx, 0)
   if (R && U) {
-    const double w = c[0] * area;
+    const T w = c[0] * area;
     if (HASX) {
-      const double exx = (ex - cx) * ihx, eyy = (ney - ey) * ihy;
-      const double gam = (ey - cy) * ihx + (nex - ex) * ihy;
-      const double sxx = l2m * exx + lam * eyy, sxy = mu * gam;
+      const T exx = (ex - cx) * ihx, eyy = (ney - ey) * ihy;
+      const T gam = (ey - cy) * ihx + (nex - ex) * ihy;
+      const T sxx = l2m * exx + lam * eyy, sxy = mu * gam;
       fx += w * (-sxx * ihx);
       fy += w * (-sxy * ihx);
     }
@@ -110,11 +111,11 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
   }
   // (b) cell(i,j) T1: vertex 0, gradient (0, -1/hy)
   if (R && U) {
-    const double w = c[1] * area;
+    const T w = c[1] * area;
     if (HASX) {
-      const double exx = (nex - nnx) * ihx, eyy = (nny - cy) * ihy;
-      const double gam = (ney - nny) * ihx + (nnx - cx) * ihy;
-      const double syy = lam * exx + l2m * eyy, sxy = mu * gam;
+      const T exx = (nex - nnx) * ihx, eyy = (nny - cy) * ihy;
+      const T gam = (ney - nny) * ihx + (nnx - cx) * ihy;
+      const T syy = lam * exx + l2m * eyy, sxy = mu * gam;
       fx += w * (-sxy * ihy);
       fy += w * (-syy * ihy);
     }
@@ -122,11 +123,11 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
   }
   // (c) cell(i-1,j) T0: vertex 1, gradient (1/hx, -1/hy)
   if (L && U) {
-    const double w = c[2] * area;
+    const T w = c[2] * area;
     if (HASX) {
-      const double exx = (cx - wx) * ihx, eyy = (nny - cy) * ihy;
-      const double gam = (cy - wy) * ihx + (nnx - cx) * ihy;
-      const double sxx = l2m * exx + lam * eyy, syy = lam * exx + l2m * eyy, sxy = mu * gam;
+      const T exx = (cx - wx) * ihx, eyy = (nny - cy) * ihy;
+      const T gam = (cy - wy) * ihx + (nnx - cx) * ihy;
+      const T sxx = l2m * exx + lam * eyy, syy = lam * exx + l2m * eyy, sxy = mu * gam;
       fx += w * (sxx * ihx - sxy * ihy);
       fy += w * (sxy * ihx - syy * ihy);
     }
@@ -134,11 +135,11 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
   }
   // (d) cell(i-1,j-1) T0: vertex 2, gradient (0, 1/hy)
   if (L && D) {
-    const double w = c[3] * area;
+    const T w = c[3] * area;
     if (HASX) {
-      const double exx = (sx - swx) * ihx, eyy = (cy - sy) * ihy;
-      const double gam = (sy - swy) * ihx + (cx - sx) * ihy;
-      const double syy = lam * exx + l2m * eyy, sxy = mu * gam;
+      const T exx = (sx - swx) * ihx, eyy = (cy - sy) * ihy;
+      const T gam = (sy - swy) * ihx + (cx - sx) * ihy;
+      const T syy = lam * exx + l2m * eyy, sxy = mu * gam;
       fx += w * (sxy * ihy);
       fy += w * (syy * ihy);
     }
@@ -146,11 +147,11 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
   }
   // (e) cell(i-1,j-1) T1: vertex 1, gradient (1/hx, 0)
   if (L && D) {
-    const double w = c[4] * area;
+    const T w = c[4] * area;
     if (HASX) {
-      const double exx = (cx - wx) * ihx, eyy = (wy - swy) * ihy;
-      const double gam = (cy - wy) * ihx + (wx - swx) * ihy;
-      const double sxx = l2m * exx + lam * eyy, sxy = mu * gam;
+      const T exx = (cx - wx) * ihx, eyy = (wy - swy) * ihy;
+      const T gam = (cy - wy) * ihx + (wx - swx) * ihy;
+      const T sxx = l2m * exx + lam * eyy, sxy = mu * gam;
       fx += w * (sxx * ihx);
       fy += w * (sxy * ihx);
     }
@@ -158,11 +159,11 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
   }
   // (f) cell(i,j-1) T1: vertex 2, gradient (-1/hx, 1/hy)
   if (R && D) {
-    const double w = c[5] * area;
+    const T w = c[5] * area;
     if (HASX) {
-      const double exx = (ex - cx) * ihx, eyy = (cy - sy) * ihy;
-      const double gam = (ey - cy) * ihx + (cx - sx) * ihy;
-      const double sxx = l2m * exx + lam * eyy, syy = lam * exx + l2m * eyy, sxy = mu * gam;
+      const T exx = (ex - cx) * ihx, eyy = (cy - sy) * ihy;
+      const T gam = (ey - cy) * ihx + (cx - sx) * ihy;
+      const T sxx = l2m * exx + lam * eyy, syy = lam * exx + l2m * eyy, sxy = mu * gam;
       fx += w * (-sxx * ihx + sxy * ihy);
       fy += w * (-sxy * ihx + syy * ihy);
     }
@@ -177,47 +178,45 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
 enum { M_APPLY = 0, M_RESID = 1, M_SMOOTH = 2 };
 enum { R_NONE = 0, R_DOT = 1, R_FREE2 = 2 };
 
-template <int MODE, bool FA, bool HASX, int RED>
-__global__ __launch_bounds__(NB) void k_node2d(Grid g, Mat m, const double* __restrict__ coef,
-                                               double kell, const double* __restrict__ x,
-                                               double* __restrict__ y,
-                                               const double* __restrict__ b,
-                                               const double* __restrict__ din,
-                                               double* __restrict__ dout, double cd, double cr,
-                                               int mask, Red red) {
+template <int MODE, bool FA, bool HASX, int RED, class T>
+__global__ __launch_bounds__(NB) void k_node2d(Grid g, Mat m, const T* __restrict__ coef, T kell,
+                                               const T* __restrict__ x, T* __restrict__ y,
+                                               const T* __restrict__ b, const T* __restrict__ din,
+                                               T* __restrict__ dout, T cd, T cr, int mask, Red red) {
   const int i = blockIdx.x * NB_X + threadIdx.x;
   const int j = blockIdx.y * NB_Y + threadIdx.y;
   double acc = 0.0;
   if (i <= g.nx && j <= g.ny) {
     const int N = g.N, n = i + (g.nx + 1) * j;
-    double c[6];
+    T c[6];
     coef6<FA>(g, coef, kell, i, j, c);
-    double fx, fy, dx, dy;
+    T fx, fy, dx, dy;
     node_force2d<HASX, MODE == M_SMOOTH>(g, m, c, x, x + N, i, j, fx, fy, dx, dy);
     const bool fxd = fixed_x2(g, i, j), fyd = fixed_y2(g, i, j);
     if (MODE == M_APPLY) {
-      const double yx = (mask && fxd) ? 0.0 : fx;
-      const double yy = (mask && fyd) ? 0.0 : fy;
+      const T yx = (mask && fxd) ? T(0) : fx;
+      const T yy = (mask && fyd) ? T(0) : fy;
       y[n] = yx;
       y[n + N] = yy;
-      if (RED == R_DOT) acc = x[n] * yx + x[n + N] * yy;
+      if (RED == R_DOT) acc = (double)x[n] * yx + (double)x[n + N] * yy;
       if (RED == R_FREE2) {
-        const double rx = fx - (b ? b[n] : 0.0), ry = fy - (b ? b[n + N] : 0.0);
+        const double rx = (double)fx - (b ? (double)b[n] : 0.0);
+        const double ry = (double)fy - (b ? (double)b[n + N] : 0.0);
         acc = (fxd ? 0.0 : rx * rx) + (fyd ? 0.0 : ry * ry);
       }
     } else if (MODE == M_RESID) {
-      const double rx = fxd ? 0.0 : (b ? b[n] : 0.0) - fx;
-      const double ry = fyd ? 0.0 : (b ? b[n + N] : 0.0) - fy;
+      const T rx = fxd ? T(0) : (b ? b[n] : T(0)) - fx;
+      const T ry = fyd ? T(0) : (b ? b[n + N] : T(0)) - fy;
       y[n] = rx;
       y[n + N] = ry;
-      if (RED == R_DOT) acc = rx * rx + ry * ry;
+      if (RED == R_DOT) acc = (double)rx * rx + (double)ry * ry;
     } else {
-      const double rx = (b ? b[n] : 0.0) - fx, ry = (b ? b[n + N] : 0.0) - fy;
-      double ddx = cr * rx / dx, ddy = cr * ry / dy;
+      const T rx = (b ? b[n] : T(0)) - fx, ry = (b ? b[n + N] : T(0)) - fy;
+      T ddx = cr * rx / dx, ddy = cr * ry / dy;
       if (din) { ddx += cd * din[n]; ddy += cd * din[n + N]; }
-      double xo = (HASX ? x[n] : 0.0) + ddx, yo = (HASX ? x[n + N] : 0.0) + ddy;
-      if (fxd) { xo = 0.0; ddx = 0.0; }
-      if (fyd) { yo = 0.0; ddy = 0.0; }
+      T xo = (HASX ? x[n] : T(0)) + ddx, yo = (HASX ? x[n + N] : T(0)) + ddy;
+      if (fxd) { xo = T(0); ddx = T(0); }
+      if (fyd) { yo = T(0); ddy = T(0); }
       y[n] = xo;
       y[n + N] = yo;
       if (dout) { dout[n] = ddx; dout[n + N] = ddy; }
@@ -225,7 +224,7 @@ __global__ __launch_bounds__(NB) void k_node2d(Grid g, Mat m, const double* __re
   }
   if (RED != R_NONE)
     block_reduce<NB, false>(acc, red, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
-                             threadIdx.x + NB_X * threadIdx.y);
+                            threadIdx.x + NB_X * threadIdx.y);
 }
 
 static dim3 node_grid2(const Grid& g) {
@@ -239,13 +238,14 @@ int node_blocks2(const Grid& g) {
 
 // y = K x (mask: zero Dirichlet rows).  red (optional): R_DOT -> S[slot] = x.y,
 // R_FREE2 -> S[slot] = sum over free rows of (K x - b)^2.
-void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const double* coef,
-                    double kell, const double* x, double* y, const double* b, int mask, int red,
-                    Red r) {
+template <class T>
+void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
+                    double kell, const T* x, T* y, const ND<T>* b, int mask, int red, Red r) {
   dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
+  const T k = T(kell);
 #define APPLY_CASE(FA, RD) \
-  hipLaunchKernelGGL((k_node2d<M_APPLY, FA, true, RD>), gr, bl, 0, st, g, m, coef, kell, x, y, b, \
-                     nullptr, nullptr, 0.0, 0.0, mask, r)
+  hipLaunchKernelGGL((k_node2d<M_APPLY, FA, true, RD, T>), gr, bl, 0, st, g, m, coef, k, x, y, b, \
+                     (const T*)nullptr, (T*)nullptr, T(0), T(0), mask, r)
   if (fine) {
     if (red == R_NONE) APPLY_CASE(true, R_NONE);
     else if (red == R_DOT) APPLY_CASE(true, R_DOT);
@@ -260,12 +260,14 @@ void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, cons
 }
 
 // r = b - K x on free rows, 0 on Dirichlet rows; optional ||r||^2 into S[slot].
-void launch_resid2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const double* coef,
-                    double kell, const double* x, double* r, const double* b, bool red, Red rr) {
+template <class T>
+void launch_resid2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
+                    double kell, const T* x, T* r, const ND<T>* b, bool red, Red rr) {
   dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
+  const T k = T(kell);
 #define RES_CASE(FA, RD) \
-  hipLaunchKernelGGL((k_node2d<M_RESID, FA, true, RD>), gr, bl, 0, st, g, m, coef, kell, x, r, b, \
-                     nullptr, nullptr, 0.0, 0.0, 1, rr)
+  hipLaunchKernelGGL((k_node2d<M_RESID, FA, true, RD, T>), gr, bl, 0, st, g, m, coef, k, x, r, b, \
+                     (const T*)nullptr, (T*)nullptr, T(0), T(0), 1, rr)
   if (fine) {
     if (red) RES_CASE(true, R_DOT); else RES_CASE(true, R_NONE);
   } else {
@@ -278,14 +280,16 @@ void launch_resid2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, cons
 // One Jacobi-preconditioned Chebyshev step:
 //   d_new = cd * d_in + cr * D^{-1} (b - K x_in);  x_out = x_in + d_new
 // x_in == nullptr means x_in = 0; d_in may be nullptr (0); d_out optional.
-void launch_smooth2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const double* coef,
-                     double kell, const double* x_in, double* x_out, const double* b,
-                     const double* d_in, double* d_out, double cd, double cr) {
+template <class T>
+void launch_smooth2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
+                     double kell, const ND<T>* x_in, T* x_out, const T* b, const ND<T>* d_in, ND<T>* d_out,
+                     double cd, double cr) {
   dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
   Red none{};
+  const T k = T(kell);
 #define SM_CASE(FA, HX) \
-  hipLaunchKernelGGL((k_node2d<M_SMOOTH, FA, HX, R_NONE>), gr, bl, 0, st, g, m, coef, kell, x_in, \
-                     x_out, b, d_in, d_out, cd, cr, 1, none)
+  hipLaunchKernelGGL((k_node2d<M_SMOOTH, FA, HX, R_NONE, T>), gr, bl, 0, st, g, m, coef, k, x_in, \
+                     x_out, b, d_in, d_out, T(cd), T(cr), 1, none)
   if (fine) {
     if (x_in) SM_CASE(true, true); else SM_CASE(true, false);
   } else {
@@ -301,10 +305,12 @@ void launch_smooth2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, con
 // Coarse element coefficients: the mean of the four fine children.
 //   coarse T0 of cell (I,J) = fine {(2I,2J) T0, (2I+1,2J) T0, (2I+1,2J) T1, (2I+1,2J+1) T0}
 //   coarse T1 of cell (I,J) = fine {(2I,2J) T1, (2I,2J+1) T1, (2I,2J+1) T0, (2I+1,2J+1) T1}
-template <bool FA>
-__global__ __launch_bounds__(VB) void k_coarsen2d(Grid gf, const double* __restrict__ fine,
-                                                  double kell, Grid gc,
-                                                  double* __restrict__ coarse) {
+// Always formed in float64 from the float64 fine data, then stored as T.
+template <bool FA, class T>
+__global__ __launch_bounds__(VB) void k_coarsen2d(Grid gf, const double* __restrict__ fine_a,
+                                                  const T* __restrict__ fine_c, double kell,
+                                                  Grid gc, double* __restrict__ coarse64,
+                                                  T* __restrict__ coarse) {
   const int cell = blockIdx.x * VB + threadIdx.x;
   if (cell >= gc.nx * gc.ny) return;
   const int I = cell % gc.nx, J = cell / gc.nx;
@@ -312,80 +318,101 @@ __global__ __launch_bounds__(VB) void k_coarsen2d(Grid gf, const double* __restr
   auto fc = [&](int ci, int cj, int t) -> double {
     if (FA) {
       const int W = gf.nx + 1, n = ci + W * cj;
-      const double a00 = fine[n], a10 = fine[n + 1], a11 = fine[n + 1 + W], a01 = fine[n + W];
+      const double a00 = fine_a[n], a10 = fine_a[n + 1], a11 = fine_a[n + 1 + W], a01 = fine_a[n + W];
       return t == 0 ? abar3(a00, a10, a11, kell) : abar3(a00, a11, a01, kell);
     } else {
-      return fine[2 * (ci + gf.nx * cj) + t];
+      return fine_a[2 * (ci + gf.nx * cj) + t];
     }
   };
-  coarse[2 * cell] = 0.25 * (fc(fi, fj, 0) + fc(fi + 1, fj, 0) + fc(fi + 1, fj, 1) + fc(fi + 1, fj + 1, 0));
-  coarse[2 * cell + 1] = 0.25 * (fc(fi, fj, 1) + fc(fi, fj + 1, 1) + fc(fi, fj + 1, 0) + fc(fi + 1, fj + 1, 1));
+  const double c0 = 0.25 * (fc(fi, fj, 0) + fc(fi + 1, fj, 0) + fc(fi + 1, fj, 1) + fc(fi + 1, fj + 1, 0));
+  const double c1 = 0.25 * (fc(fi, fj, 1) + fc(fi, fj + 1, 1) + fc(fi, fj + 1, 0) + fc(fi + 1, fj + 1, 1));
+  if (coarse64) { coarse64[2 * cell] = c0; coarse64[2 * cell + 1] = c1; }
+  if (coarse) { coarse[2 * cell] = T(c0); coarse[2 * cell + 1] = T(c1); }
 }
 
+// Coarse coefficients from the finer level (alpha when fine_is_alpha); the
+// float64 array coarse64 is always written, coarse32 (float copy) when given.
 void launch_coarsen2d(hipStream_t st, const Grid& gf, bool fine_is_alpha, const double* fine,
-                      double kell, const Grid& gc, double* coarse) {
+                      double kell, const Grid& gc, double* coarse64, float* coarse32) {
   const int n = gc.nx * gc.ny;
   dim3 gr((n + VB - 1) / VB), bl(VB);
   if (fine_is_alpha)
-    hipLaunchKernelGGL((k_coarsen2d<true>), gr, bl, 0, st, gf, fine, kell, gc, coarse);
+    hipLaunchKernelGGL((k_coarsen2d<true, float>), gr, bl, 0, st, gf, fine, (const float*)nullptr,
+                       kell, gc, coarse64, coarse32);
   else
-    hipLaunchKernelGGL((k_coarsen2d<false>), gr, bl, 0, st, gf, fine, kell, gc, coarse);
+    hipLaunchKernelGGL((k_coarsen2d<false, float>), gr, bl, 0, st, gf, fine, (const float*)nullptr,
+                       kell, gc, coarse64, coarse32);
 }
 
 // b_c = P^T r_f.  P interpolates linearly: fine node (2I,2J) takes coarse
 // (I,J); a fine node at the midpoint of a coarse edge takes the mean of its
 // two ends (edges along x, along y and along the cell diagonal).
-__global__ __launch_bounds__(NB) void k_restrict2d(Grid gf, Grid gc, const double* __restrict__ rf,
-                                                   double* __restrict__ bc) {
+template <class T>
+__global__ __launch_bounds__(NB) void k_restrict2d(Grid gf, Grid gc, const T* __restrict__ rf,
+                                                   T* __restrict__ bc) {
   const int I = blockIdx.x * NB_X + threadIdx.x;
   const int J = blockIdx.y * NB_Y + threadIdx.y;
   if (I > gc.nx || J > gc.ny) return;
   const int Wf = gf.nx + 1, Nf = gf.N, fi = 2 * I, fj = 2 * J, f = fi + Wf * fj;
   const int nc = I + (gc.nx + 1) * J;
   for (int comp = 0; comp < 2; ++comp) {
-    const double* r = rf + comp * Nf;
-    double s = r[f];
-    double h = 0.0;
+    const T* r = rf + comp * Nf;
+    T s = r[f];
+    T h = 0;
     if (fi > 0) h += r[f - 1];
     if (fi < gf.nx) h += r[f + 1];
     if (fj > 0) h += r[f - Wf];
     if (fj < gf.ny) h += r[f + Wf];
     if (fi < gf.nx && fj < gf.ny) h += r[f + 1 + Wf];
     if (fi > 0 && fj > 0) h += r[f - 1 - Wf];
-    s += 0.5 * h;
+    s += T(0.5) * h;
     const bool fixed = comp == 0 ? fixed_x2(gc, I, J) : fixed_y2(gc, I, J);
-    bc[comp * gc.N + nc] = fixed ? 0.0 : s;
+    bc[comp * gc.N + nc] = fixed ? T(0) : s;
   }
 }
 
-void launch_restrict2d(hipStream_t st, const Grid& gf, const Grid& gc, const double* rf,
-                       double* bc) {
+template <class T>
+void launch_restrict2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* rf, T* bc) {
   dim3 gr(node_grid2(gc)), bl(NB_X, NB_Y);
-  hipLaunchKernelGGL(k_restrict2d, gr, bl, 0, st, gf, gc, rf, bc);
+  hipLaunchKernelGGL((k_restrict2d<T>), gr, bl, 0, st, gf, gc, rf, bc);
 }
 
 // x_f += P x_c.
-__global__ __launch_bounds__(NB) void k_prolong2d(Grid gf, Grid gc, const double* __restrict__ xc,
-                                                  double* __restrict__ xf) {
+template <class T>
+__global__ __launch_bounds__(NB) void k_prolong2d(Grid gf, Grid gc, const T* __restrict__ xc,
+                                                  T* __restrict__ xf) {
   const int i = blockIdx.x * NB_X + threadIdx.x;
   const int j = blockIdx.y * NB_Y + threadIdx.y;
   if (i > gf.nx || j > gf.ny) return;
   const int Wc = gc.nx + 1, n = i + (gf.nx + 1) * j;
   const int I0 = i >> 1, J0 = j >> 1, I1 = (i + 1) >> 1, J1 = (j + 1) >> 1;
   for (int comp = 0; comp < 2; ++comp) {
-    const double* c = xc + comp * gc.N;
+    const T* c = xc + comp * gc.N;
     // (i,j) even/even -> one node; otherwise the two ends of the edge
-    const double v = 0.5 * (c[I0 + Wc * J0] + c[I1 + Wc * J1]);
+    const T v = T(0.5) * (c[I0 + Wc * J0] + c[I1 + Wc * J1]);
     const bool fixed = comp == 0 ? fixed_x2(gf, i, j) : fixed_y2(gf, i, j);
     if (!fixed) xf[comp * gf.N + n] += v;
   }
 }
 
-void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const double* xc,
-                      double* xf) {
+template <class T>
+void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* xc, T* xf) {
   dim3 gr(node_grid2(gf)), bl(NB_X, NB_Y);
-  hipLaunchKernelGGL(k_prolong2d, gr, bl, 0, st, gf, gc, xc, xf);
+  hipLaunchKernelGGL((k_prolong2d<T>), gr, bl, 0, st, gf, gc, xc, xf);
 }
+
+#define INST(T)                                                                                  \
+  template void launch_apply2d<T>(hipStream_t, const Grid&, const Mat&, bool, const T*, double,   \
+                                  const T*, T*, const ND<T>*, int, int, Red);                         \
+  template void launch_resid2d<T>(hipStream_t, const Grid&, const Mat&, bool, const T*, double,   \
+                                  const T*, T*, const ND<T>*, bool, Red);                             \
+  template void launch_smooth2d<T>(hipStream_t, const Grid&, const Mat&, bool, const T*, double,  \
+                                   const ND<T>*, T*, const T*, const ND<T>*, ND<T>*, double, double);        \
+  template void launch_restrict2d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);        \
+  template void launch_prolong2d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);
+INST(float)
+INST(double)
+#undef INST
 
 // ---------------------------------------------------------------------------
 // Dirichlet lifting (tension): u_y = 0 at j = 0, u_y = t at j = ny, u_x(0,0) = 0

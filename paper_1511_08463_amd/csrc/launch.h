@@ -8,18 +8,22 @@ namespace frac {
 
 // ---- 2D operator kernels (kernels2d.hip) -----------------------------------
 int node_blocks2(const Grid& g);
-void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const double* coef,
-                    double kell, const double* x, double* y, const double* b, int mask, int red,
-                    Red r);
-void launch_resid2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const double* coef,
-                    double kell, const double* x, double* r, const double* b, bool red, Red rr);
-void launch_smooth2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const double* coef,
-                     double kell, const double* x_in, double* x_out, const double* b,
-                     const double* d_in, double* d_out, double cd, double cr);
+template <class T>
+void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
+                    double kell, const T* x, T* y, const ND<T>* b, int mask, int red, Red r);
+template <class T>
+void launch_resid2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
+                    double kell, const T* x, T* r, const ND<T>* b, bool red, Red rr);
+template <class T>
+void launch_smooth2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
+                     double kell, const ND<T>* x_in, T* x_out, const T* b, const ND<T>* d_in, ND<T>* d_out,
+                     double cd, double cr);
 void launch_coarsen2d(hipStream_t st, const Grid& gf, bool fine_is_alpha, const double* fine,
-                      double kell, const Grid& gc, double* coarse);
-void launch_restrict2d(hipStream_t st, const Grid& gf, const Grid& gc, const double* rf, double* bc);
-void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const double* xc, double* xf);
+                      double kell, const Grid& gc, double* coarse64, float* coarse32);
+template <class T>
+void launch_restrict2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* rf, T* bc);
+template <class T>
+void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* xc, T* xf);
 void launch_lift2d(hipStream_t st, const Grid& g, double* u, double t);
 void launch_w2_2d(hipStream_t st, const Grid& g, const Mat& m, const double* u, double* w2);
 void launch_vi_eval2d(hipStream_t st, const Grid& g, double cL, double cM, double cm,
@@ -48,7 +52,8 @@ void launch_trial_state(hipStream_t st, int64_t n2, int64_t N, const double* u, 
 // ---- coarse dense solve (dense.hip) ----------------------------------------
 void launch_dense_setup2d(hipStream_t st, const Grid& g, const Mat& m, const double* abar,
                           double* A, double* Ainv);
-void launch_dense_solve(hipStream_t st, int n, const double* Ainv, const double* b, double* x);
+template <class T>
+void launch_dense_solve(hipStream_t st, int n, const double* Ainv, const T* b, T* x);
 
 // ---- vector kernels (vec.hip) -----------------------------------------------
 int vec_blocks(int64_t n);
@@ -77,5 +82,12 @@ void launch_merit_parts(hipStream_t st, int64_t n, const double* x, const double
                         const double* lo, double* w, double* g);
 void launch_neg_sum(hipStream_t st, int64_t n, const double* g, const double* hw, double* d, Red r);
 void launch_set_scalar(hipStream_t st, double* S, int slot, double v);
+// float32 vectors (mixed-precision inner solver)
+void launch_cg_update_f(hipStream_t st, int64_t n, float* x, float* r, const float* p,
+                        const float* q, const double* S, Red rr);
+void launch_xpby_f(hipStream_t st, int64_t n, const float* z, float* p, const double* S);
+void launch_dot_f(hipStream_t st, int64_t n, const float* a, const float* b, Red r);
+void launch_to_float(hipStream_t st, int64_t n, const double* x, float* y, double scale);
+void launch_add_scaled_f(hipStream_t st, int64_t n, double* x, const float* e, double scale);
 
 }  // namespace frac

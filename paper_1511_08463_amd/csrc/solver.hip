@@ -39,6 +39,9 @@ struct Level {
   Grid g;
   double* abar = nullptr;  // element coefficients (levels >= 1)
   double *b = nullptr, *xa = nullptr, *xb = nullptr, *d = nullptr, *r = nullptr;
+  // float32 copies for the mixed-precision multigrid
+  float* abar32 = nullptr;
+  float *b32 = nullptr, *xa32 = nullptr, *xb32 = nullptr, *d32 = nullptr, *r32 = nullptr;
 };
 
 // Bump allocator over the caller's workspace (or a dry run that only counts).
@@ -87,6 +90,9 @@ struct fracture {
   double *npu1 = nullptr, *npu2 = nullptr, *npa1 = nullptr, *npa2 = nullptr, *nca = nullptr,
          *ncb = nullptr, *ncd = nullptr, *nut = nullptr, *nat = nullptr, *nFu = nullptr;
   double chebC_cd[8] = {}, chebC_cr[8] = {};
+  // mixed precision: float32 alpha and the inner flexible-CG vectors
+  bool mixed = false;
+  float *alpha32 = nullptr, *fe32 = nullptr, *fr32 = nullptr, *fp32 = nullptr, *fq32 = nullptr;
   // coarsest level
   double *dA = nullptr, *dAinv = nullptr;
   int dense_n = 0;
@@ -95,6 +101,8 @@ struct fracture {
   hipEvent_t ev[8] = {};
   double load = 0.0;
   double bnorm = 0.0;
+  fracture_monitor_fn monitor = nullptr;
+  void* monitor_user = nullptr;
   bool coef_valid = false;
 };
 
@@ -124,7 +132,7 @@ int validate(const fracture_params* p) {
   if (!(p->omega > 0 && p->omega < 2)) return FRACTURE_EINVAL;
   if (p->relax_mode < 0 || p->relax_mode > 2) return FRACTURE_EINVAL;
   if (p->load_kind != FRACTURE_LOAD_TENSION_2D) return FRACTURE_EINVAL;
-  if (p->precision != FRACTURE_FP64) return FRACTURE_EINVAL;
+  if (p->precision != FRACTURE_FP64 && p->precision != FRACTURE_MIXED) return FRACTURE_EINVAL;
   if (p->newton && !(p->minres_rtol > 0 && p->max_minres >= 1 && p->max_newton >= 1)) return FRACTURE_EINVAL;
   if (p->max_am < 1 || p->max_pcg < 1 || p->max_vi < 1 || p->max_vi_cg < 1) return FRACTURE_EINVAL;
   if (p->cheb_degree < 1 || p->cheb_degree > 8) return FRACTURE_EINVAL;
@@ -193,6 +201,22 @@ size_t layout(const fracture_params* p, fracture* h, void* ws) {
     v.xb = c.take<double>(m2);
     v.d = c.take<double>(m2);
     v.r = c.take<double>(m2);
+    if (p->precision == FRACTURE_MIXED) {
+      v.abar32 = l > 0 ? c.take<float>(2 * (int64_t)gl[l].nx * gl[l].ny) : nullptr;
+      v.b32 = c.take<float>(m2);
+      v.xa32 = c.take<float>(m2);
+      v.xb32 = c.take<float>(m2);
+      v.d32 = c.take<float>(m2);
+      v.r32 = c.take<float>(m2);
+    }
+  }
+  if (p->precision == FRACTURE_MIXED) {
+    t->mixed = true;
+    t->alpha32 = c.take<float>(N);
+    t->fe32 = c.take<float>(n2);
+    t->fr32 = c.take<float>(n2);
+    t->fp32 = c.take<float>(n2);
+    t->fq32 = c.take<float>(n2);
   }
   if (p->newton) {
     const int64_t n3 = 3 * N;
@@ -289,7 +313,8 @@ const double* level_coef(fracture* h, int l) { return l == 0 ? h->alpha : h->lv[
 void update_coefficients(fracture* h) {
   for (int l = 1; l < h->nlev; ++l)
     launch_coarsen2d(h->st, h->lv[l - 1].g, l == 1, level_coef(h, l - 1), h->p.k_ell, h->lv[l].g,
-                     h->lv[l].abar);
+                     h->lv[l].abar, h->mixed ? h->lv[l].abar32 : nullptr);
+  if (h->mixed) launch_to_float(h->st, h->N, h->alpha, h->alpha32, 1.0);
   const int Lc = h->nlev - 1;
   if (Lc >= 1) launch_dense_setup2d(h->st, h->lv[Lc].g, h->mat, h->lv[Lc].abar, h->dA, h->dAinv);
   h->coef_valid = true;
@@ -298,45 +323,72 @@ void update_coefficients(fracture* h) {
 // Coarsest level with nlev == 1 has no abar array; assemble from alpha then.
 // (validate() guarantees nlev >= 2 for the sizes this driver accepts.)
 
-// z = V-cycle(b) on level l; returns the buffer holding the result.
-double* vcycle(fracture* h, int l, const double* b) {
+// Buffers of a level in the value type of the cycle.
+template <class T>
+struct LevelBufs {
+  T *b, *xa, *xb, *d, *r;
+  const T* coef;
+};
+
+template <class T>
+LevelBufs<T> bufs(fracture* h, int l);
+
+template <>
+LevelBufs<double> bufs<double>(fracture* h, int l) {
   Level& v = h->lv[l];
+  return {v.b, v.xa, v.xb, v.d, v.r, l == 0 ? h->alpha : v.abar};
+}
+
+template <>
+LevelBufs<float> bufs<float>(fracture* h, int l) {
+  Level& v = h->lv[l];
+  return {v.b32, v.xa32, v.xb32, v.d32, v.r32, l == 0 ? h->alpha32 : v.abar32};
+}
+
+// z = V-cycle(b) on level l; returns the buffer holding the result.  The
+// cycle is symmetric: pre- and post-smoothing apply the same Chebyshev
+// polynomial, so it is a fixed SPD preconditioner in exact arithmetic.
+template <class T>
+T* vcycle_t(fracture* h, int l, const T* b) {
+  LevelBufs<T> v = bufs<T>(h, l);
+  const Grid& g = h->lv[l].g;
   const int k = h->p.cheb_degree;
   const bool fine = l == 0;
-  const double* coef = level_coef(h, l);
   const double kell = h->p.k_ell;
   if (l == h->nlev - 1) {
-    launch_dense_solve(h->st, h->dense_n, h->dAinv, b, v.xa);
+    launch_dense_solve<T>(h->st, h->dense_n, h->dAinv, b, v.xa);
     return v.xa;
   }
   // pre-smoothing from zero
-  double* cur = nullptr;
+  T* cur = nullptr;
   for (int s = 0; s < k; ++s) {
-    double* out = (s % 2 == 0) ? v.xa : v.xb;
-    const double* din = s == 0 ? nullptr : (s == 1 ? cur : v.d);
-    double* dout = (s < k - 1) ? v.d : nullptr;
-    launch_smooth2d(h->st, v.g, h->mat, fine, coef, kell, cur, out, b, din, dout, h->cheb_cd[s],
-                    h->cheb_cr[s]);
+    T* out = (s % 2 == 0) ? v.xa : v.xb;
+    const T* din = s == 0 ? nullptr : (s == 1 ? cur : v.d);
+    T* dout = (s < k - 1) ? v.d : nullptr;
+    launch_smooth2d<T>(h->st, g, h->mat, fine, v.coef, kell, cur, out, b, din, dout,
+                       h->cheb_cd[s], h->cheb_cr[s]);
     cur = out;
   }
   // residual, restriction, coarse correction
   Red none{};
-  launch_resid2d(h->st, v.g, h->mat, fine, coef, kell, cur, v.r, b, false, none);
-  Level& c = h->lv[l + 1];
-  launch_restrict2d(h->st, v.g, c.g, v.r, c.b);
-  double* xc = vcycle(h, l + 1, c.b);
-  launch_prolong2d(h->st, v.g, c.g, xc, cur);
+  launch_resid2d<T>(h->st, g, h->mat, fine, v.coef, kell, cur, v.r, b, false, none);
+  LevelBufs<T> c = bufs<T>(h, l + 1);
+  launch_restrict2d<T>(h->st, g, h->lv[l + 1].g, v.r, c.b);
+  T* xc = vcycle_t<T>(h, l + 1, c.b);
+  launch_prolong2d<T>(h->st, g, h->lv[l + 1].g, xc, cur);
   // post-smoothing (same polynomial: the V-cycle is symmetric)
   for (int s = 0; s < k; ++s) {
-    double* out = (cur == v.xa) ? v.xb : v.xa;
-    const double* din = s == 0 ? nullptr : v.d;
-    double* dout = (s < k - 1) ? v.d : nullptr;
-    launch_smooth2d(h->st, v.g, h->mat, fine, coef, kell, cur, out, b, din, dout, h->cheb_cd[s],
-                    h->cheb_cr[s]);
+    T* out = (cur == v.xa) ? v.xb : v.xa;
+    const T* din = s == 0 ? nullptr : v.d;
+    T* dout = (s < k - 1) ? v.d : nullptr;
+    launch_smooth2d<T>(h->st, g, h->mat, fine, v.coef, kell, cur, out, b, din, dout,
+                       h->cheb_cd[s], h->cheb_cr[s]);
     cur = out;
   }
   return cur;
 }
+
+double* vcycle(fracture* h, int l, const double* b) { return vcycle_t<double>(h, l, b); }
 
 // ---------------------------------------------------------------------------
 // elastic subproblem: x <- argmin at fixed alpha, warm start from u
@@ -373,6 +425,57 @@ int pcg(fracture* h, double tol, int* iters) {
     launch_xpby(st, n2, z, h->pv, h->S);
   }
   return FRACTURE_ENOTCONV;
+}
+
+// Mixed precision: iterative refinement in float64 around a float32
+// flexible CG (FCG(1): p_k = z_k - (z_k.q_{k-1})/(p_{k-1}.q_{k-1}) p_{k-1},
+// alpha_k = p_k.r_k / p_k.q_k) whose operator, V-cycle and vectors are all
+// float32.  The float64 residual r = f - K x is recomputed before every
+// inner solve, which sees it normalised to unit length.
+constexpr double MIXED_INNER_RTOL = 1e-4;
+constexpr int MIXED_MAX_OUTER = 30;
+
+int pcg_mixed(fracture* h, double tol, int* iters) {
+  const Grid& g = h->lv[0].g;
+  const int64_t n2 = h->n2;
+  hipStream_t st = h->st;
+  *iters = 0;
+  HIPCHK(hipMemcpyAsync(h->x, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  for (int outer = 0;; ++outer) {
+    launch_resid2d<double>(st, g, h->mat, true, h->alpha, h->p.k_ell, h->x, h->r, nullptr, true,
+                           red(h, 0, S_RR));
+    int rc = read_scalars(h);
+    if (rc) return rc;
+    const double rr = h->hS[S_RR];
+    if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
+    const double rn = std::sqrt(rr);
+    if (rn <= tol) return FRACTURE_OK;
+    if (outer >= MIXED_MAX_OUTER || *iters >= h->p.max_pcg) return FRACTURE_ENOTCONV;
+    // inner solve of K e = r / |r| in float32
+    launch_to_float(st, n2, h->r, h->fr32, 1.0 / rn);
+    HIPCHK(hipMemsetAsync(h->fe32, 0, n2 * sizeof(float), st));
+    const double tin = std::fmax(MIXED_INNER_RTOL, 0.5 * tol / rn);
+    float* z = vcycle_t<float>(h, 0, h->fr32);
+    HIPCHK(hipMemcpyAsync(h->fp32, z, n2 * sizeof(float), hipMemcpyDeviceToDevice, st));
+    for (int it = 0;; ++it) {
+      if (it > 0) {
+        z = vcycle_t<float>(h, 0, h->fr32);
+        launch_dot_f(st, n2, z, h->fq32, red(h, 1, S_TMP0, P_FCG_BETA));
+        launch_xpby_f(st, n2, z, h->fp32, h->S);
+      }
+      launch_apply2d<float>(st, g, h->mat, true, h->alpha32, h->p.k_ell, h->fp32, h->fq32, nullptr,
+                            1, 1, red(h, 2, S_PQ));
+      launch_dot_f(st, n2, h->fp32, h->fr32, red(h, 4, S_TMP1, P_FCG_ALPHA));
+      launch_cg_update_f(st, n2, h->fe32, h->fr32, h->fp32, h->fq32, h->S, red(h, 3, S_RR));
+      rc = read_scalars(h);
+      if (rc) return rc;
+      ++*iters;
+      const double rin = h->hS[S_RR];
+      if (!std::isfinite(rin)) return FRACTURE_ENONFINITE;
+      if (std::sqrt(rin) <= tin || *iters >= h->p.max_pcg) break;
+    }
+    launch_add_scaled_f(st, n2, h->x, h->fe32, rn);
+  }
 }
 
 // ||f - K u_D|| on free rows: the load the elastic problem carries (its RHS
@@ -696,6 +799,7 @@ int newton_phase(fracture* h, fracture_stats* st, double* nphi, bool* converged)
   if (rc) return rc;
   for (int it = 0; it < h->p.max_newton; ++it) {
     *nphi = std::sqrt(phi2);
+    if (h->monitor) h->monitor(h->monitor_user, -(it + 1), -1.0, *nphi);
     if (*nphi <= h->p.final_tol) { *converged = true; return FRACTURE_OK; }
     update_coefficients(h);
     // rhs = -[F_u; F_a on the inactive set]
@@ -768,7 +872,7 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
     int it = 0;
     // tolerance: relative to the load vector; an absolute floor keeps zero loads finite
     const double tol = h->p.pcg_rtol * (h->bnorm > 0 ? h->bnorm : 1.0);
-    rc = pcg(h, tol, &it);
+    rc = h->mixed ? pcg_mixed(h, tol, &it) : pcg(h, tol, &it);
     loc.pcg_iters += it;
     if (rc) break;
     if (h->p.omega == 1.0)
@@ -790,6 +894,8 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
     ms_vi += elapsed(h->ev[2], h->ev[3]);
     loc.dalpha_inf = h->hS[S_DAMAX];
     if (!std::isfinite(loc.dalpha_inf)) { rc = FRACTURE_ENONFINITE; break; }
+    if (h->monitor && (h->p.newton || h->p.am_stop != FRACTURE_STOP_PHI))
+      h->monitor(h->monitor_user, sweep, loc.dalpha_inf, -1.0);
     if (!h->p.newton && h->p.am_stop == FRACTURE_STOP_DALPHA) {
       if (loc.dalpha_inf < h->p.am_tol) { loc.converged = 1; break; }
     } else {
@@ -798,6 +904,7 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
       if (rc) break;
       loc.phi_l2 = nphi;
       if (!std::isfinite(nphi)) { rc = FRACTURE_ENONFINITE; break; }
+      if (h->monitor) h->monitor(h->monitor_user, sweep, loc.dalpha_inf, nphi);
       if (nphi <= h->p.final_tol) { loc.converged = 1; break; }
       if (h->p.newton && nphi < threshold) {
         HIPCHK(hipEventRecord(h->ev[1], st));
@@ -1004,6 +1111,13 @@ int fracture_solve_steps(fracture_t* hs, int n, fracture_stats* out, int* codes)
     if (rc && !worst) worst = rc;
   }
   return worst;
+}
+
+int fracture_set_monitor(fracture_t h, fracture_monitor_fn fn, void* user) {
+  if (!h) return FRACTURE_EINVAL;
+  h->monitor = fn;
+  h->monitor_user = user;
+  return FRACTURE_OK;
 }
 
 int fracture_energy(fracture_t h, double* elastic, double* surface) {

@@ -302,4 +302,72 @@ void launch_set_scalar(hipStream_t st, double* S, int slot, double v) {
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(WAVE), 0, st, S, slot, v);
 }
 
+// ---- float32 vectors of the mixed-precision inner solver (float64 sums) ----
+
+// x += a p; r -= a q; S[slot] = r.r  (a = S[S_ALPHA])
+__global__ __launch_bounds__(VB) void k_cg_update_f(int64_t n, float* __restrict__ x,
+                                                    float* __restrict__ r,
+                                                    const float* __restrict__ p,
+                                                    const float* __restrict__ q,
+                                                    const double* __restrict__ S, Red rr) {
+  const float a = (float)S[S_ALPHA];
+  double acc = 0.0;
+  GRID_STRIDE(k, n) {
+    x[k] += a * p[k];
+    const float rv = r[k] - a * q[k];
+    r[k] = rv;
+    acc += (double)rv * rv;
+  }
+  block_reduce<VB, false>(acc, rr, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_cg_update_f(hipStream_t st, int64_t n, float* x, float* r, const float* p,
+                        const float* q, const double* S, Red rr) {
+  hipLaunchKernelGGL(k_cg_update_f, dim3(vgrid(n)), dim3(VB), 0, st, n, x, r, p, q, S, rr);
+  launch_finish(st, rr, vgrid(n), false);
+}
+
+// p = z + beta p (beta = S[S_BETA])
+__global__ __launch_bounds__(VB) void k_xpby_f(int64_t n, const float* __restrict__ z,
+                                               float* __restrict__ p, const double* __restrict__ S) {
+  const float b = (float)S[S_BETA];
+  GRID_STRIDE(k, n) p[k] = z[k] + b * p[k];
+}
+
+void launch_xpby_f(hipStream_t st, int64_t n, const float* z, float* p, const double* S) {
+  hipLaunchKernelGGL(k_xpby_f, dim3(vgrid(n)), dim3(VB), 0, st, n, z, p, S);
+}
+
+__global__ __launch_bounds__(VB) void k_dot_f(int64_t n, const float* __restrict__ a,
+                                              const float* __restrict__ b, Red r) {
+  double acc = 0.0;
+  GRID_STRIDE(k, n) acc += (double)a[k] * b[k];
+  block_reduce<VB, false>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_dot_f(hipStream_t st, int64_t n, const float* a, const float* b, Red r) {
+  hipLaunchKernelGGL(k_dot_f, dim3(vgrid(n)), dim3(VB), 0, st, n, a, b, r);
+  launch_finish(st, r, vgrid(n), false);
+}
+
+// y = float(x * scale)
+__global__ __launch_bounds__(VB) void k_to_float(int64_t n, const double* __restrict__ x,
+                                                 float* __restrict__ y, double scale) {
+  GRID_STRIDE(k, n) y[k] = (float)(x[k] * scale);
+}
+
+void launch_to_float(hipStream_t st, int64_t n, const double* x, float* y, double scale) {
+  hipLaunchKernelGGL(k_to_float, dim3(vgrid(n)), dim3(VB), 0, st, n, x, y, scale);
+}
+
+// x += scale * e  (float64 accumulation of a float32 correction)
+__global__ __launch_bounds__(VB) void k_add_scaled_f(int64_t n, double* __restrict__ x,
+                                                     const float* __restrict__ e, double scale) {
+  GRID_STRIDE(k, n) x[k] += scale * (double)e[k];
+}
+
+void launch_add_scaled_f(hipStream_t st, int64_t n, double* x, const float* e, double scale) {
+  hipLaunchKernelGGL(k_add_scaled_f, dim3(vgrid(n)), dim3(VB), 0, st, n, x, e, scale);
+}
+
 }  // namespace frac

@@ -85,8 +85,10 @@ EXPORTS = [
     "fracture_set_load", "fracture_solve_step", "fracture_solve_steps", "fracture_energy",
     "fracture_get_state", "fracture_set_state", "fracture_apply", "fracture_update_coefficients",
     "fracture_gradient", "fracture_levels", "fracture_level_shape", "fracture_strerror",
-    "fracture_time_kernel", "fracture_destroy",
+    "fracture_time_kernel", "fracture_set_monitor", "fracture_destroy",
 ]
+
+MONITOR_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double)
 
 _lib = None
 
@@ -120,6 +122,7 @@ def load_library(path=LIB_PATH):
         "fracture_level_shape": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int)]),
         "fracture_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "fracture_time_kernel": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, dp, dp]),
+        "fracture_set_monitor": (ctypes.c_int, [vp, MONITOR_FN, vp]),
         "fracture_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -266,6 +269,14 @@ def fracture_time_kernel(h, kernel, reps):
     return ms.value, b.value
 
 
+def fracture_set_monitor(h, fn):
+    """fn(sweep, dalpha_inf, phi_l2) or None; returns the ctypes callback,
+    which the caller must keep alive while it is installed."""
+    cb = MONITOR_FN(lambda user, sweep, da, phi: fn(sweep, da, phi)) if fn else MONITOR_FN()
+    _check(load_library().fracture_set_monitor(h, cb, None), "fracture_set_monitor")
+    return cb
+
+
 def fracture_destroy(h):
     load_library().fracture_destroy(h)
 
@@ -302,6 +313,9 @@ class Fracture:
             self.close()
         except Exception:
             pass
+
+    def set_monitor(self, fn):
+        self._monitor_cb = fracture_set_monitor(self.h, fn)
 
     def set_load(self, t):
         fracture_set_load(self.h, t)

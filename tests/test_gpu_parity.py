@@ -318,3 +318,35 @@ def test_oram_newton_parity(omega):
         assert eu < STEP_TOL and ea < STEP_TOL
     assert total_newton > 0
     s.close()
+
+
+# ----------------------------------------------------------------------------- mixed precision
+
+@pytest.mark.parametrize("model", ["AT1", "AT2"])
+def test_mixed_precision_matches_oracle(model):
+    """float32 operator + multigrid inside float64 iterative refinement:
+    converged load steps agree with the float64 oracle to 1e-6."""
+    n = 64
+    p, notch, _ = workloads.small_tension(n, model, ell=0.06)
+    print(f"[mixed] {model}", flush=True)
+    res = _run_both(p, notch, [0.3, 0.9, 1.2], precision=fracture.FRACTURE_MIXED)
+    for r in res:
+        assert r["eu"] < STEP_TOL and r["ea"] < STEP_TOL, r
+
+
+def test_mixed_precision_ragged_and_newton():
+    p = workloads.tension(96, 0.06, "AT1", nx=96, ny=80)
+    notch = workloads.notch_mask_2d(96, 80, 0.5, 0.25)
+    print("[mixed ragged newton]", flush=True)
+    s = _solver(p, notch, precision=fracture.FRACTURE_MIXED, newton=1, final_tol=1e-9,
+                pcg_rtol=1e-12, vi_cg_rtol=1e-12, minres_rtol=1e-8, max_newton=20)
+    P = _problem(p)
+    st = am.initial_state(P, notch.astype(bool))
+    for t in (0.3, 0.8):
+        s.set_load(t)
+        stats = s.solve_step()
+        am.solve_load_step(P, st, t, newton_on=True, final_tol=1e-9, max_am=5000)
+        u, a, _ = s.state()
+        assert stats["converged"]
+        assert _rel(u, st.u) < STEP_TOL and _rel(a, st.alpha) < STEP_TOL
+    s.close()
