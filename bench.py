@@ -61,6 +61,20 @@ def cpu_baseline(n_sample=256, n_full=2048, model="AT1"):
     }
 
 
+def serve(args):
+    """The served stream (config 5): first --instances requests of the seeded
+    Poisson stream, admitted under a device memory budget, run concurrently."""
+    from paper_1511_08463_amd import serving, workloads
+    reqs = [serving.Request(r["rid"], r["params"], r["notch"], r["loads"], r["arrival"])
+            for r in workloads.config5(n_instances=args.instances)]
+    budget = int(args.budget_gb * 1e9)
+    log(f"[serve] {len(reqs)} requests, budget {args.budget_gb} GB, {args.workers} workers")
+    svc = serving.Service(budget, max_slots=args.slots, workers=args.workers)
+    summary, _ = svc.run(reqs)
+    log(f"[serve] {summary}")
+    return summary
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +92,12 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="run only the served stream")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream sample")
+    ap.add_argument("--instances", type=int, default=48)
+    ap.add_argument("--budget-gb", type=float, default=4.0)
+    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--slots", type=int, default=16)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -93,6 +113,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.serve:
+        summary = serve(args)
+        print(json.dumps({"serving": summary}), flush=True)
+        return
     p, notch, loads, (y0, a) = workloads.config2(args.model, args.omega, seed=0, n=args.n)
     params = fracture.make_params(**p, am_tol=args.am_tol, pcg_rtol=args.pcg_rtol,
                                   vi_cg_rtol=1e-10, max_am=5000, newton=args.newton,
@@ -187,6 +211,15 @@ def main():
         },
     }
     solver.close()
+    if not args.no_serve:
+        sv = serve(args)
+        out["serving"] = {k: sv[k] for k in ("instances", "steps", "wall_s", "steps_per_s",
+                                             "instances_per_s", "p50_ms", "p99_ms",
+                                             "failed_steps", "peak_used_bytes")}
+        out["serving"]["workload"] = (f"first {args.instances} requests of the seeded config-5 stream "
+                                      f"(n in 64..1024, ell in [0.01,0.05], h=ell/4, 10-30 steps, "
+                                      f"Poisson 50/s), mixed precision, budget {args.budget_gb} GB, "
+                                      f"{args.workers} workers")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(256, args.n, args.model)

@@ -152,9 +152,12 @@ int fracture_set_load(fracture_t h, double load);
    (host, may be NULL) receives the statistics. */
 int fracture_solve_step(fracture_t h, fracture_stats* out);
 
-/* One load step for each of n handles, interleaved on their streams
-   (continuous batching).  Results equal n separate fracture_solve_step
-   calls; out (host) has n entries or is NULL; codes (host) has n entries. */
+/* One load step for each of n handles, run concurrently (one host thread per
+   handle, each on its handle's stream, so the device overlaps their work).
+   The handles must be distinct and should have distinct streams.  Results
+   equal n separate fracture_solve_step calls; out (host) has n entries or
+   is NULL; codes (host) has n entries or is NULL.  Returns the first
+   non-zero code, else FRACTURE_OK. */
 int fracture_solve_steps(fracture_t* hs, int n, fracture_stats* out, int* codes);
 
 /* Progress monitor: when set, fn(user, sweep, dalpha_inf, phi_l2) is called

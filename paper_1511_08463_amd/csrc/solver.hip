@@ -20,7 +20,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <utility>
+#include <vector>
 
 #include "../../include/fracture.h"
 #include "common.h"
@@ -1104,11 +1106,20 @@ int fracture_solve_step(fracture_t h, fracture_stats* out) {
 
 int fracture_solve_steps(fracture_t* hs, int n, fracture_stats* out, int* codes) {
   if (!hs || n < 0) return FRACTURE_EINVAL;
+  // one host thread per handle: each drives its own stream, so the load
+  // steps of different instances run on the device at the same time
+  std::vector<int> rcs(n, FRACTURE_EINVAL);
+  std::vector<std::thread> pool;
+  pool.reserve(n);
+  for (int k = 0; k < n; ++k) {
+    if (!hs[k]) continue;
+    pool.emplace_back([&, k]() { rcs[k] = solve_step_impl(hs[k], out ? out + k : nullptr); });
+  }
+  for (auto& t : pool) t.join();
   int worst = FRACTURE_OK;
   for (int k = 0; k < n; ++k) {
-    const int rc = hs[k] ? solve_step_impl(hs[k], out ? out + k : nullptr) : FRACTURE_EINVAL;
-    if (codes) codes[k] = rc;
-    if (rc && !worst) worst = rc;
+    if (codes) codes[k] = rcs[k];
+    if (rcs[k] && !worst) worst = rcs[k];
   }
   return worst;
 }

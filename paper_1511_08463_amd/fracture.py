@@ -162,6 +162,8 @@ def make_params(**kw):
     for k, v in kw.items():
         if k == "model" and isinstance(v, str):
             v = FRACTURE_AT1 if v == "AT1" else FRACTURE_AT2
+        if k == "precision" and isinstance(v, str):
+            v = FRACTURE_MIXED if v == "mixed" else FRACTURE_FP64
         if not hasattr(p, k):
             raise KeyError(k)
         setattr(p, k, v)

@@ -16,6 +16,14 @@ Recipes (the paper uses no dataset; these stand in for its test problems):
   length a drawn from U[0.1, 0.4] (seed 0) and snapped to nodes, 20 steps
   t = 0.1 k.
 * ``small_tension``: the config-2 recipe at a small n (parity sizes).
+* ``config5``: a served stream of independent tension problems: side
+  n ~ U{64, ..., 1024}, ell ~ U[0.01, 0.05], h = ell/4, domain side
+  L = n h, the config-2 notch recipe scaled by L, 10-30 load steps with
+  t_k = k t_max / steps, t_max = c sqrt(L) (the onset displacement of a
+  notched square scales like sqrt(L)); c = 1 by default, which reaches crack
+  onset at the last steps (c = 2 drives most instances through unstable
+  propagation across the whole specimen), Poisson arrivals at rate 50/s
+  (seed 1), AT1, omega = 1, mixed precision, no Newton.
 """
 
 import numpy as np
@@ -85,3 +93,25 @@ def oracle_kwargs(p):
     """The subset of parameters the oracle's problem builders take."""
     return dict(E=p["E"], nu=p["nu"], Gc=p["Gc"], ell=p["ell"], k_ell=p["k_ell"],
                 model=p["model"], plane_stress=bool(p.get("plane_stress", 0)))
+
+
+def config5(n_instances=256, seed=1, sizes=(64, 128, 256, 512, 1024), rate=50.0,
+            max_am=400, load_scale=1.0):
+    """Requests of the served stream: (rid, params, notch, loads, arrival)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for rid in range(n_instances):
+        n = int(rng.choice(sizes))
+        ell = float(rng.uniform(0.01, 0.05))
+        h = ell / 4.0
+        L = n * h
+        steps = int(rng.integers(10, 31))
+        y0 = round(rng.uniform(0.1, 0.4) * n) * h
+        a = round(rng.uniform(0.1, 0.4) * n) * h
+        t += float(rng.exponential(1.0 / rate))
+        p = tension(n, ell, "AT1", 1.0, lx=L, ly=L, precision=1, max_am=max_am)
+        notch = notch_mask_2d(n, n, y0, a, L, L)
+        loads = [k * (load_scale * np.sqrt(L)) / steps for k in range(1, steps + 1)]
+        out.append(dict(rid=rid, params=p, notch=notch, loads=loads, arrival=t))
+    return out
