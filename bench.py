@@ -75,6 +75,42 @@ def serve(args):
     return summary
 
 
+def thermal(args):
+    """Config 3: the 128x128x32 thermal-shock slab, FP64 or mixed, AM load steps."""
+    import torch
+    from paper_1511_08463_amd import fracture, workloads
+    p, loads = workloads.config3()
+    params = fracture.make_params(**p, am_tol=args.am_tol, pcg_rtol=args.pcg_rtol, max_am=2000,
+                                  precision=fracture.FRACTURE_MIXED if args.precision == "mixed"
+                                  else fracture.FRACTURE_FP64)
+    solver = fracture.Fracture(params, None, device="cuda:0")
+    log(f"[thermal] 128x128x32 Kuhn, {args.precision}, DT_c={workloads.thermal_dtc(p):.3f}")
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, t in enumerate(loads[: args.warmup + args.steps]):
+        solver.set_load(t)
+        st = solver.solve_step()
+        stats.append(st)
+        el, su = solver.energy()
+        log(f"[thermal] step {k + 1} DT={t:.3f} sweeps={st['sweeps']} pcg={st['pcg_iters']} "
+            f"vi={st['vi_iters']} ms={st['ms_total']:.1f} E_el={el:.4e} E_s={su:.4e}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rl = {}
+    for name, kid in (("smooth", fracture.FRACTURE_KERNEL_SMOOTH), ("apply", fracture.FRACTURE_KERNEL_APPLY)):
+        ms, nbytes = fracture.fracture_time_kernel(solver.h, kid, args.kernel_reps)
+        rl[name] = {"us": ms * 1e3, "gbs": nbytes / (ms * 1e-3) / 1e9}
+        log(f"[thermal] kernel {name}: {ms * 1e3:.1f} us, {rl[name]['gbs']:.0f} GB/s")
+    solver.close()
+    n = args.warmup + args.steps
+    return {"workload": "128x128x32 hexes x 6 Kuhn tetrahedra, AT1, ell=4h, thermal eigenstrain "
+                        f"-DT exp(-x/0.05) I, DT_k=(k/15) 2 DT_c, k=1..{n}, AM to ||dalpha||inf<{args.am_tol:g}",
+            "precision": args.precision, "load_steps": n, "seconds": dt, "load_steps_per_s": n / dt,
+            "sweeps": sum(s["sweeps"] for s in stats), "pcg_iters": sum(s["pcg_iters"] for s in stats),
+            "kernels": rl}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +129,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="run only the served stream")
+    ap.add_argument("--thermal", action="store_true", help="run only the 3D thermal slab (config 3)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream sample")
     ap.add_argument("--instances", type=int, default=48)
     ap.add_argument("--budget-gb", type=float, default=4.0)
@@ -116,6 +153,9 @@ def main():
     if args.serve:
         summary = serve(args)
         print(json.dumps({"serving": summary}), flush=True)
+        return
+    if args.thermal:
+        print(json.dumps({"thermal": thermal(args)}), flush=True)
         return
     p, notch, loads, (y0, a) = workloads.config2(args.model, args.omega, seed=0, n=args.n)
     params = fracture.make_params(**p, am_tol=args.am_tol, pcg_rtol=args.pcg_rtol,

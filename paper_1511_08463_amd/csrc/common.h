@@ -43,6 +43,10 @@ struct Grid {
   double hx, hy, hz;
   int N;
   int bc;
+  int dim;
+  // thermal eigenstrain eps0 = -eig_dT exp(-x_c / eig_depth) I per element
+  // (3D thermal load); zero for operator actions on error equations
+  double eig_dT, eig_depth;
 };
 
 // Isotropic A0 in the form the element kernels use: sigma_xx = l2m e_xx +

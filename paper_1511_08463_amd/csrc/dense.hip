@@ -101,10 +101,11 @@ __global__ __launch_bounds__(DB) void k_gauss_jordan(int n, double* __restrict__
   }
 }
 
-void launch_dense_setup2d(hipStream_t st, const Grid& g, const Mat& m, const double* abar,
-                          double* A, double* Ainv) {
-  const int n = 2 * g.N;
-  hipLaunchKernelGGL(k_dense_assemble2d, dim3(1), dim3(DB), 0, st, g, m, abar, A);
+void launch_dense_setup(hipStream_t st, const Grid& g, const Mat& m, const double* abar,
+                        double* A, double* Ainv) {
+  const int n = g.dim * g.N;
+  if (g.dim == 3) launch_dense_assemble3d(st, g, m, abar, A);
+  else hipLaunchKernelGGL(k_dense_assemble2d, dim3(1), dim3(DB), 0, st, g, m, abar, A);
   hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(DB), 2 * n * sizeof(double), st, n, A, Ainv);
 }
 

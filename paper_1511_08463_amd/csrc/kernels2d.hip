@@ -236,11 +236,14 @@ int node_blocks2(const Grid& g) {
   return (int)(gr.x * gr.y);
 }
 
+int node_blocks(const Grid& g) { return g.dim == 3 ? node_blocks3(g) : node_blocks2(g); }
+
 // y = K x (mask: zero Dirichlet rows).  red (optional): R_DOT -> S[slot] = x.y,
 // R_FREE2 -> S[slot] = sum over free rows of (K x - b)^2.
 template <class T>
 void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
                     double kell, const T* x, T* y, const ND<T>* b, int mask, int red, Red r) {
+  if (g.dim == 3) return launch_apply3d<T>(st, g, m, fine, coef, kell, x, y, b, mask, red, r);
   dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
   const T k = T(kell);
 #define APPLY_CASE(FA, RD) \
@@ -263,6 +266,7 @@ void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, cons
 template <class T>
 void launch_resid2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
                     double kell, const T* x, T* r, const ND<T>* b, bool red, Red rr) {
+  if (g.dim == 3) return launch_resid3d<T>(st, g, m, fine, coef, kell, x, r, b, red, rr);
   dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
   const T k = T(kell);
 #define RES_CASE(FA, RD) \
@@ -284,6 +288,8 @@ template <class T>
 void launch_smooth2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
                      double kell, const ND<T>* x_in, T* x_out, const T* b, const ND<T>* d_in, ND<T>* d_out,
                      double cd, double cr) {
+  if (g.dim == 3)
+    return launch_smooth3d<T>(st, g, m, fine, coef, kell, x_in, x_out, b, d_in, d_out, cd, cr);
   dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
   Red none{};
   const T k = T(kell);
@@ -334,6 +340,7 @@ __global__ __launch_bounds__(VB) void k_coarsen2d(Grid gf, const double* __restr
 // float64 array coarse64 is always written, coarse32 (float copy) when given.
 void launch_coarsen2d(hipStream_t st, const Grid& gf, bool fine_is_alpha, const double* fine,
                       double kell, const Grid& gc, double* coarse64, float* coarse32) {
+  if (gc.dim == 3) return launch_coarsen3d(st, gf, fine_is_alpha, fine, kell, gc, coarse64, coarse32);
   const int n = gc.nx * gc.ny;
   dim3 gr((n + VB - 1) / VB), bl(VB);
   if (fine_is_alpha)
@@ -373,6 +380,7 @@ __global__ __launch_bounds__(NB) void k_restrict2d(Grid gf, Grid gc, const T* __
 
 template <class T>
 void launch_restrict2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* rf, T* bc) {
+  if (gc.dim == 3) return launch_restrict3d<T>(st, gf, gc, rf, bc);
   dim3 gr(node_grid2(gc)), bl(NB_X, NB_Y);
   hipLaunchKernelGGL((k_restrict2d<T>), gr, bl, 0, st, gf, gc, rf, bc);
 }
@@ -397,6 +405,7 @@ __global__ __launch_bounds__(NB) void k_prolong2d(Grid gf, Grid gc, const T* __r
 
 template <class T>
 void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* xc, T* xf) {
+  if (gf.dim == 3) return launch_prolong3d<T>(st, gf, gc, xc, xf);
   dim3 gr(node_grid2(gf)), bl(NB_X, NB_Y);
   hipLaunchKernelGGL((k_prolong2d<T>), gr, bl, 0, st, gf, gc, xc, xf);
 }
@@ -428,6 +437,7 @@ __global__ __launch_bounds__(VB) void k_lift2d(Grid g, double* __restrict__ u, d
 }
 
 void launch_lift2d(hipStream_t st, const Grid& g, double* u, double t) {
+  if (g.dim == 3) return launch_lift3d(st, g, u);
   hipLaunchKernelGGL(k_lift2d, dim3((g.nx + 1 + VB - 1) / VB), dim3(VB), 0, st, g, u, t);
 }
 
@@ -458,6 +468,7 @@ __global__ __launch_bounds__(VB) void k_w2_2d(Grid g, Mat m, const double* __res
 }
 
 void launch_w2_2d(hipStream_t st, const Grid& g, const Mat& m, const double* u, double* w2) {
+  if (g.dim == 3) return launch_w2_3d(st, g, m, u, w2);
   const int n = g.nx * g.ny;
   hipLaunchKernelGGL(k_w2_2d, dim3((n + VB - 1) / VB), dim3(VB), 0, st, g, m, u, w2);
 }
@@ -583,6 +594,9 @@ void launch_vi_eval2d(hipStream_t st, const Grid& g, double cL, double cM, doubl
                       const double* w2, const double* a, const double* d, const double* lo,
                       const double* S, int mu_slot, double zeta, double* F, double* phi,
                       uint8_t* mask, double* hdinv, Red r2, Red rm, Red rlo, Red rhi, bool trial) {
+  if (g.dim == 3)
+    return launch_vi_eval3d(st, g, cL, cM, cm, w2, a, d, lo, S, mu_slot, zeta, F, phi, mask, hdinv,
+                            r2, rm, rlo, rhi, trial);
   Helm hp{cL, cM, cm};
   dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
   if (trial)
@@ -628,6 +642,7 @@ __global__ __launch_bounds__(NB) void k_helm_apply2d(Grid g, Helm hp, const doub
 void launch_helm_apply2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
                          const double* x, const uint8_t* mask, double* y, bool dot, Red r,
                          int j0, int j1) {
+  if (g.dim == 3) return launch_helm_apply3d(st, g, cL, cM, w2, x, mask, y, dot, r, j0, j1);
   Helm hp{cL, cM, 0.0};
   if (j0 < 0) j0 = 0;
   if (j1 < 0 || j1 > g.ny) j1 = g.ny;

@@ -1,0 +1,741 @@
+// 3D kernels: P1 Kuhn tetrahedra on a structured grid of hexahedra.
+//
+// Hexahedron (ci, cj, ck) holds six tetrahedra, one per permutation
+// (a, b, c) of the axes (order 012, 021, 102, 120, 201, 210): vertices
+// o0 = 0, o1 = e_a, o2 = e_a + e_b, o3 = (1,1,1).  Barycentric gradients are
+// g0 = -e_a/h_a, g1 = e_a/h_a - e_b/h_b, g2 = e_b/h_b - e_c/h_c, g3 = e_c/h_c,
+// so the displacement gradient along axis a is a difference along the path
+// o0 -> o1, along b along o1 -> o2 and along c along o2 -> o3.  Volume
+// hx hy hz / 6.  Element e = 6 (ci + nx (cj + ny ck)) + p.
+//
+// A node lies in 24 tetrahedra; the node kernels sum their forces, enumerated
+// at compile time (template parameters) so every stencil index is a
+// constant.  The eigenstrain of the thermal load enters as
+// eps_eff = eps(u) - s I with s = -DT exp(-x_c/depth) at the element centroid.
+#include "common.h"
+#include "launch.h"
+
+namespace frac {
+
+template <int P> struct Perm3;
+template <> struct Perm3<0> { static constexpr int a = 0, b = 1, c = 2; };
+template <> struct Perm3<1> { static constexpr int a = 0, b = 2, c = 1; };
+template <> struct Perm3<2> { static constexpr int a = 1, b = 0, c = 2; };
+template <> struct Perm3<3> { static constexpr int a = 1, b = 2, c = 0; };
+template <> struct Perm3<4> { static constexpr int a = 2, b = 0, c = 1; };
+template <> struct Perm3<5> { static constexpr int a = 2, b = 1, c = 0; };
+
+// offset of local vertex W of tetrahedron P along axis AX
+template <int P, int W, int AX>
+struct VOff {
+  static constexpr int v = W == 0 ? 0
+                           : W == 3 ? 1
+                           : W == 1 ? (AX == Perm3<P>::a ? 1 : 0)
+                                    : ((AX == Perm3<P>::a || AX == Perm3<P>::b) ? 1 : 0);
+};
+
+// slot of the 3x3x3 neighbourhood for a node offset (dx, dy, dz) in {-1,0,1}^3
+constexpr int nslot(int dx, int dy, int dz) { return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1); }
+
+template <int HX, int HY, int HZ, int P, int W>
+struct VSlot {
+  static constexpr int v = nslot(HX + VOff<P, W, 0>::v, HY + VOff<P, W, 1>::v, HZ + VOff<P, W, 2>::v);
+};
+
+__device__ __forceinline__ bool fixed3(const Grid& g, int comp, int i, int j, int k) {
+  if (g.bc != BC_THERMAL_3D) return false;
+  if (i != g.nx) return false;
+  if (comp == 0) return true;
+  if (comp == 1) return j == 0 && k == 0;
+  return k == 0 && (j == 0 || j == g.ny);
+}
+
+// Per-node neighbourhood: the 15 nodes the Kuhn stencil touches, loaded once.
+template <class T>
+struct Hood3 {
+  T u[27][3];
+  T a[27];
+};
+
+__device__ __forceinline__ bool in3(const Grid& g, int i, int j, int k) {
+  return i >= 0 && j >= 0 && k >= 0 && i <= g.nx && j <= g.ny && k <= g.nz;
+}
+
+// the 15 stencil offsets (0, +-e_a, +-(e_a+e_b), +-(1,1,1))
+#define FOR_STENCIL3(X)                                                                 \
+  X(0, 0, 0) X(1, 0, 0) X(-1, 0, 0) X(0, 1, 0) X(0, -1, 0) X(0, 0, 1) X(0, 0, -1)       \
+  X(1, 1, 0) X(-1, -1, 0) X(1, 0, 1) X(-1, 0, -1) X(0, 1, 1) X(0, -1, -1) X(1, 1, 1)    \
+  X(-1, -1, -1)
+
+// The 24 (hex offset, tetrahedron, local vertex) incidences of a node.
+#define FOR_TETS3(X)                                                                     \
+  X(-1, -1, -1, 0, 3) X(-1, -1, -1, 1, 3) X(-1, -1, -1, 2, 3) X(-1, -1, -1, 3, 3)       \
+  X(-1, -1, -1, 4, 3) X(-1, -1, -1, 5, 3) X(-1, -1, 0, 0, 2) X(-1, -1, 0, 2, 2)         \
+  X(-1, 0, -1, 1, 2) X(-1, 0, -1, 4, 2) X(-1, 0, 0, 0, 1) X(-1, 0, 0, 1, 1)             \
+  X(0, -1, -1, 3, 2) X(0, -1, -1, 5, 2) X(0, -1, 0, 2, 1) X(0, -1, 0, 3, 1)             \
+  X(0, 0, -1, 4, 1) X(0, 0, -1, 5, 1) X(0, 0, 0, 0, 0) X(0, 0, 0, 1, 0) X(0, 0, 0, 2, 0) \
+  X(0, 0, 0, 3, 0) X(0, 0, 0, 4, 0) X(0, 0, 0, 5, 0)
+
+template <class T>
+__device__ __forceinline__ T abar4(T a0, T a1, T a2, T a3, T k) {
+  const T b0 = T(1) - a0, b1 = T(1) - a1, b2 = T(1) - a2, b3 = T(1) - a3;
+  const T s = b0 + b1 + b2 + b3;
+  return k + (b0 * b0 + b1 * b1 + b2 * b2 + b3 * b3 + s * s) * (T(1) / T(20));
+}
+
+// Gradient of local vertex W of tetrahedron P (axis components).
+template <int P, int W, class T>
+__device__ __forceinline__ void grad3(const T ih[3], T g[3]) {
+  constexpr int A = Perm3<P>::a, B = Perm3<P>::b, C = Perm3<P>::c;
+  g[0] = g[1] = g[2] = T(0);
+  if (W == 0) g[A] = -ih[A];
+  if (W == 1) { g[A] = ih[A]; g[B] = -ih[B]; }
+  if (W == 2) { g[B] = ih[B]; g[C] = -ih[C]; }
+  if (W == 3) g[C] = ih[C];
+}
+
+// Voigt-free strain of a tetrahedron: displacement gradient G[comp][axis].
+template <int HX, int HY, int HZ, int P, class T>
+__device__ __forceinline__ void tet_grad(const T (&u)[27][3], const T ih[3], T G[3][3]) {
+  constexpr int A = Perm3<P>::a, B = Perm3<P>::b, C = Perm3<P>::c;
+  constexpr int s0 = VSlot<HX, HY, HZ, P, 0>::v, s1 = VSlot<HX, HY, HZ, P, 1>::v;
+  constexpr int s2 = VSlot<HX, HY, HZ, P, 2>::v, s3 = VSlot<HX, HY, HZ, P, 3>::v;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    G[c][A] = (u[s1][c] - u[s0][c]) * ih[A];
+    G[c][B] = (u[s2][c] - u[s1][c]) * ih[B];
+    G[c][C] = (u[s3][c] - u[s2][c]) * ih[C];
+  }
+}
+
+// x coordinate of the tetrahedron's centroid, in cells from the hex corner
+template <int P>
+__device__ __forceinline__ double tet_xc() {
+  return 0.25 * (VOff<P, 1, 0>::v + VOff<P, 2, 0>::v + 1.0);
+}
+
+template <int HX, int HY, int HZ, int P, int V, bool FA, bool HASX, bool DIAG, bool EIG, class T>
+__device__ __forceinline__ void tet_force(const Grid& g, const Mat& m, const Hood3<T>& hd,
+                                          const T* __restrict__ abar, T kell, int i, int j, int k,
+                                          const T ih[3], T vol, T f[3], T d[3]) {
+  const int ci = i + HX, cj = j + HY, ck = k + HZ;
+  if (ci < 0 || cj < 0 || ck < 0 || ci >= g.nx || cj >= g.ny || ck >= g.nz) return;
+  T c;
+  if (FA) {
+    c = abar4(hd.a[VSlot<HX, HY, HZ, P, 0>::v], hd.a[VSlot<HX, HY, HZ, P, 1>::v],
+              hd.a[VSlot<HX, HY, HZ, P, 2>::v], hd.a[VSlot<HX, HY, HZ, P, 3>::v], kell);
+  } else {
+    c = abar[6 * (ci + g.nx * (cj + g.ny * ck)) + P];
+  }
+  const T w = c * vol;
+  T gv[3];
+  grad3<P, V>(ih, gv);
+  const T lam = T(m.lam), mu = T(m.mu);
+  if (HASX) {
+    T G[3][3];
+    tet_grad<HX, HY, HZ, P>(hd.u, ih, G);
+    T e0 = G[0][0], e1 = G[1][1], e2 = G[2][2];
+    if (EIG) {
+      const double xc = (ci + tet_xc<P>()) * g.hx;
+      const T s = T(-g.eig_dT * exp(-xc / g.eig_depth));
+      e0 -= s; e1 -= s; e2 -= s;
+    }
+    const T tr = e0 + e1 + e2;
+    T S[3][3];
+    S[0][0] = lam * tr + T(2) * mu * e0;
+    S[1][1] = lam * tr + T(2) * mu * e1;
+    S[2][2] = lam * tr + T(2) * mu * e2;
+    S[0][1] = S[1][0] = mu * (G[0][1] + G[1][0]);
+    S[0][2] = S[2][0] = mu * (G[0][2] + G[2][0]);
+    S[1][2] = S[2][1] = mu * (G[1][2] + G[2][1]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) f[a] += w * (S[a][0] * gv[0] + S[a][1] * gv[1] + S[a][2] * gv[2]);
+  }
+  if (DIAG) {
+    const T gg = gv[0] * gv[0] + gv[1] * gv[1] + gv[2] * gv[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] += w * ((lam + mu) * gv[a] * gv[a] + mu * gg);
+  }
+}
+
+template <bool FA, bool HASX, bool DIAG, bool EIG, class T>
+__device__ __forceinline__ void node_force3d(const Grid& g, const Mat& m, const T* __restrict__ coef,
+                                             T kell, const T* __restrict__ x, int i, int j, int k,
+                                             T f[3], T d[3]) {
+  const int W = g.nx + 1, H = g.ny + 1, N = g.N;
+  const int n = i + W * (j + H * k);
+  Hood3<T> hd;
+#define LOAD3(DX, DY, DZ)                                                                   \
+  {                                                                                         \
+    constexpr int sl = nslot(DX, DY, DZ);                                                   \
+    const bool ok = in3(g, i + DX, j + DY, k + DZ);                                         \
+    const int nn = n + DX + W * (DY + H * DZ);                                              \
+    if (HASX) {                                                                             \
+      hd.u[sl][0] = ok ? x[nn] : T(0);                                                      \
+      hd.u[sl][1] = ok ? x[nn + N] : T(0);                                                  \
+      hd.u[sl][2] = ok ? x[nn + 2 * N] : T(0);                                              \
+    }                                                                                       \
+    if (FA) hd.a[sl] = ok ? coef[nn] : T(0);                                                \
+  }
+  FOR_STENCIL3(LOAD3)
+#undef LOAD3
+  const T ih[3] = {T(1.0 / g.hx), T(1.0 / g.hy), T(1.0 / g.hz)};
+  const T vol = T(g.hx * g.hy * g.hz / 6.0);
+  f[0] = f[1] = f[2] = d[0] = d[1] = d[2] = T(0);
+#define TET3(HX, HY, HZ, P, V) \
+  tet_force<HX, HY, HZ, P, V, FA, HASX, DIAG, EIG>(g, m, hd, coef, kell, i, j, k, ih, vol, f, d);
+  FOR_TETS3(TET3)
+#undef TET3
+}
+
+// ---------------------------------------------------------------------------
+// node kernels (apply / residual / Chebyshev step), value type T
+// ---------------------------------------------------------------------------
+
+enum { M3_APPLY = 0, M3_RESID = 1, M3_SMOOTH = 2 };
+enum { R3_NONE = 0, R3_DOT = 1, R3_FREE2 = 2 };
+
+template <int MODE, bool FA, bool HASX, int RED, bool EIG, class T>
+__global__ __launch_bounds__(NB) void k_node3d(Grid g, Mat m, const T* __restrict__ coef, T kell,
+                                               const T* __restrict__ x, T* __restrict__ y,
+                                               const T* __restrict__ b, const T* __restrict__ din,
+                                               T* __restrict__ dout, T cd, T cr, int mask, Red red) {
+  const int i = blockIdx.x * NB_X + threadIdx.x;
+  const int j = blockIdx.y * NB_Y + threadIdx.y;
+  const int k = blockIdx.z;
+  double acc = 0.0;
+  if (i <= g.nx && j <= g.ny) {
+    const int N = g.N, n = i + (g.nx + 1) * (j + (g.ny + 1) * k);
+    T f[3], d[3];
+    node_force3d<FA, HASX, MODE == M3_SMOOTH, EIG>(g, m, coef, kell, x, i, j, k, f, d);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const bool fx = fixed3(g, c, i, j, k);
+      const int q = n + c * N;
+      if (MODE == M3_APPLY) {
+        const T yv = (mask && fx) ? T(0) : f[c];
+        y[q] = yv;
+        if (RED == R3_DOT) acc += (double)x[q] * yv;
+        if (RED == R3_FREE2) {
+          const double r = (double)f[c] - (b ? (double)b[q] : 0.0);
+          acc += fx ? 0.0 : r * r;
+        }
+      } else if (MODE == M3_RESID) {
+        const T r = fx ? T(0) : (b ? b[q] : T(0)) - f[c];
+        y[q] = r;
+        if (RED == R3_DOT) acc += (double)r * r;
+      } else {
+        const T r = (b ? b[q] : T(0)) - f[c];
+        T dd = cr * r / d[c];
+        if (din) dd += cd * din[q];
+        T xo = (HASX ? x[q] : T(0)) + dd;
+        if (fx) { xo = T(0); dd = T(0); }
+        y[q] = xo;
+        if (dout) dout[q] = dd;
+      }
+    }
+  }
+  if (RED != R3_NONE)
+    block_reduce<NB, false>(acc, red, gridDim.x * gridDim.y * gridDim.z,
+                            blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                            threadIdx.x + NB_X * threadIdx.y);
+}
+
+static dim3 node_grid3(const Grid& g) {
+  return dim3((g.nx + 1 + NB_X - 1) / NB_X, (g.ny + 1 + NB_Y - 1) / NB_Y, g.nz + 1);
+}
+
+int node_blocks3(const Grid& g) {
+  dim3 gr = node_grid3(g);
+  return (int)(gr.x * gr.y * gr.z);
+}
+
+template <class T>
+void launch_apply3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
+                    double kell, const T* x, T* y, const ND<T>* b, int mask, int red, Red r) {
+  dim3 gr = node_grid3(g), bl(NB_X, NB_Y);
+  const T k = T(kell);
+  const bool eig = fine && g.eig_dT != 0.0;
+#define A3(FA, RD, EG) \
+  hipLaunchKernelGGL((k_node3d<M3_APPLY, FA, true, RD, EG, T>), gr, bl, 0, st, g, m, coef, k, x, y, b, \
+                     (const T*)nullptr, (T*)nullptr, T(0), T(0), mask, r)
+  if (fine && eig) {
+    if (red == R3_NONE) A3(true, R3_NONE, true);
+    else if (red == R3_DOT) A3(true, R3_DOT, true);
+    else A3(true, R3_FREE2, true);
+  } else if (fine) {
+    if (red == R3_NONE) A3(true, R3_NONE, false);
+    else if (red == R3_DOT) A3(true, R3_DOT, false);
+    else A3(true, R3_FREE2, false);
+  } else {
+    if (red == R3_NONE) A3(false, R3_NONE, false);
+    else if (red == R3_DOT) A3(false, R3_DOT, false);
+    else A3(false, R3_FREE2, false);
+  }
+#undef A3
+  if (red != R3_NONE) launch_finish(st, r, (int)(gr.x * gr.y * gr.z), false);
+}
+
+template <class T>
+void launch_resid3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
+                    double kell, const T* x, T* r, const ND<T>* b, bool red, Red rr) {
+  dim3 gr = node_grid3(g), bl(NB_X, NB_Y);
+  const T k = T(kell);
+  const bool eig = fine && g.eig_dT != 0.0;
+#define R3(FA, RD, EG) \
+  hipLaunchKernelGGL((k_node3d<M3_RESID, FA, true, RD, EG, T>), gr, bl, 0, st, g, m, coef, k, x, r, b, \
+                     (const T*)nullptr, (T*)nullptr, T(0), T(0), 1, rr)
+  if (fine) {
+    if (eig) { if (red) R3(true, R3_DOT, true); else R3(true, R3_NONE, true); }
+    else { if (red) R3(true, R3_DOT, false); else R3(true, R3_NONE, false); }
+  } else {
+    if (red) R3(false, R3_DOT, false); else R3(false, R3_NONE, false);
+  }
+#undef R3
+  if (red) launch_finish(st, rr, (int)(gr.x * gr.y * gr.z), false);
+}
+
+template <class T>
+void launch_smooth3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
+                     double kell, const ND<T>* x_in, T* x_out, const T* b, const ND<T>* d_in,
+                     ND<T>* d_out, double cd, double cr) {
+  dim3 gr = node_grid3(g), bl(NB_X, NB_Y);
+  Red none{};
+  const T k = T(kell);
+#define S3(FA, HX) \
+  hipLaunchKernelGGL((k_node3d<M3_SMOOTH, FA, HX, R3_NONE, false, T>), gr, bl, 0, st, g, m, coef, k, \
+                     x_in, x_out, b, d_in, d_out, T(cd), T(cr), 1, none)
+  if (fine) { if (x_in) S3(true, true); else S3(true, false); }
+  else { if (x_in) S3(false, true); else S3(false, false); }
+#undef S3
+}
+
+// ---------------------------------------------------------------------------
+// transfers
+// ---------------------------------------------------------------------------
+
+// The Kuhn triangulation of the half-size grid refines that of the coarse
+// grid: each coarse tetrahedron is the union of 8 fine ones.  Children of
+// coarse tetrahedron p: (fine hex offset x, y, z in {0,1}, fine permutation).
+__device__ __constant__ int c_kuhn_kids[6][8][4] = {
+  {{0,0,0,0}, {1,0,0,0}, {1,0,0,2}, {1,0,0,3}, {1,1,0,0}, {1,1,0,1}, {1,1,0,4}, {1,1,1,0}},
+  {{0,0,0,1}, {1,0,0,1}, {1,0,0,4}, {1,0,0,5}, {1,0,1,0}, {1,0,1,1}, {1,0,1,2}, {1,1,1,1}},
+  {{0,0,0,2}, {0,1,0,0}, {0,1,0,1}, {0,1,0,2}, {1,1,0,2}, {1,1,0,3}, {1,1,0,5}, {1,1,1,2}},
+  {{0,0,0,3}, {0,1,0,3}, {0,1,0,4}, {0,1,0,5}, {0,1,1,0}, {0,1,1,2}, {0,1,1,3}, {1,1,1,3}},
+  {{0,0,0,4}, {0,0,1,0}, {0,0,1,1}, {0,0,1,4}, {1,0,1,3}, {1,0,1,4}, {1,0,1,5}, {1,1,1,4}},
+  {{0,0,0,5}, {0,0,1,2}, {0,0,1,3}, {0,0,1,5}, {0,1,1,1}, {0,1,1,4}, {0,1,1,5}, {1,1,1,5}},
+};
+// vertex offsets of the 6 tetrahedra: [perm][vertex][axis]
+__device__ __constant__ int c_kuhn_off[6][4][3] = {
+  {{0,0,0},{1,0,0},{1,1,0},{1,1,1}}, {{0,0,0},{1,0,0},{1,0,1},{1,1,1}},
+  {{0,0,0},{0,1,0},{1,1,0},{1,1,1}}, {{0,0,0},{0,1,0},{0,1,1},{1,1,1}},
+  {{0,0,0},{0,0,1},{1,0,1},{1,1,1}}, {{0,0,0},{0,0,1},{0,1,1},{1,1,1}},
+};
+
+template <bool FA>
+__global__ __launch_bounds__(VB) void k_coarsen3d(Grid gf, const double* __restrict__ fine,
+                                                  double kell, Grid gc, double* __restrict__ c64,
+                                                  float* __restrict__ c32) {
+  const int e = blockIdx.x * VB + threadIdx.x;
+  const int ne = 6 * gc.nx * gc.ny * gc.nz;
+  if (e >= ne) return;
+  const int p = e % 6, hex = e / 6;
+  const int I = hex % gc.nx, J = (hex / gc.nx) % gc.ny, K = hex / (gc.nx * gc.ny);
+  const int W = gf.nx + 1, H = gf.ny + 1;
+  double s = 0.0;
+  for (int q = 0; q < 8; ++q) {
+    const int fi = 2 * I + c_kuhn_kids[p][q][0], fj = 2 * J + c_kuhn_kids[p][q][1];
+    const int fk = 2 * K + c_kuhn_kids[p][q][2], fp = c_kuhn_kids[p][q][3];
+    if (FA) {
+      double a[4];
+      for (int v = 0; v < 4; ++v)
+        a[v] = fine[(fi + c_kuhn_off[fp][v][0]) + W * ((fj + c_kuhn_off[fp][v][1]) + H * (fk + c_kuhn_off[fp][v][2]))];
+      s += abar4(a[0], a[1], a[2], a[3], kell);
+    } else {
+      s += fine[6 * (fi + gf.nx * (fj + gf.ny * fk)) + fp];
+    }
+  }
+  s *= 0.125;
+  c64[e] = s;
+  if (c32) c32[e] = (float)s;
+}
+
+void launch_coarsen3d(hipStream_t st, const Grid& gf, bool fine_is_alpha, const double* fine,
+                      double kell, const Grid& gc, double* c64, float* c32) {
+  const int ne = 6 * gc.nx * gc.ny * gc.nz;
+  dim3 gr((ne + VB - 1) / VB), bl(VB);
+  if (fine_is_alpha) hipLaunchKernelGGL((k_coarsen3d<true>), gr, bl, 0, st, gf, fine, kell, gc, c64, c32);
+  else hipLaunchKernelGGL((k_coarsen3d<false>), gr, bl, 0, st, gf, fine, kell, gc, c64, c32);
+}
+
+// positive edge directions of the Kuhn mesh (the interpolation stencil)
+__device__ __constant__ int c_kuhn_dir[7][3] = {{1,0,0},{0,1,0},{0,0,1},{1,1,0},{1,0,1},{0,1,1},{1,1,1}};
+
+template <class T>
+__global__ __launch_bounds__(NB) void k_restrict3d(Grid gf, Grid gc, const T* __restrict__ rf,
+                                                   T* __restrict__ bc) {
+  const int I = blockIdx.x * NB_X + threadIdx.x, J = blockIdx.y * NB_Y + threadIdx.y, K = blockIdx.z;
+  if (I > gc.nx || J > gc.ny) return;
+  const int Wf = gf.nx + 1, Hf = gf.ny + 1, fi = 2 * I, fj = 2 * J, fk = 2 * K;
+  const int f = fi + Wf * (fj + Hf * fk);
+  const int nc = I + (gc.nx + 1) * (J + (gc.ny + 1) * K);
+  for (int comp = 0; comp < 3; ++comp) {
+    const T* r = rf + comp * gf.N;
+    T s = r[f], h = 0;
+    for (int q = 0; q < 7; ++q) {
+      const int dx = c_kuhn_dir[q][0], dy = c_kuhn_dir[q][1], dz = c_kuhn_dir[q][2];
+      const int off = dx + Wf * (dy + Hf * dz);
+      if (in3(gf, fi + dx, fj + dy, fk + dz)) h += r[f + off];
+      if (in3(gf, fi - dx, fj - dy, fk - dz)) h += r[f - off];
+    }
+    s += T(0.5) * h;
+    bc[comp * gc.N + nc] = fixed3(gc, comp, I, J, K) ? T(0) : s;
+  }
+}
+
+template <class T>
+void launch_restrict3d(hipStream_t st, const Grid& gf, const Grid& gc, const T* rf, T* bc) {
+  hipLaunchKernelGGL((k_restrict3d<T>), node_grid3(gc), dim3(NB_X, NB_Y), 0, st, gf, gc, rf, bc);
+}
+
+template <class T>
+__global__ __launch_bounds__(NB) void k_prolong3d(Grid gf, Grid gc, const T* __restrict__ xc,
+                                                  T* __restrict__ xf) {
+  const int i = blockIdx.x * NB_X + threadIdx.x, j = blockIdx.y * NB_Y + threadIdx.y, k = blockIdx.z;
+  if (i > gf.nx || j > gf.ny) return;
+  const int Wc = gc.nx + 1, Hc = gc.ny + 1;
+  const int n = i + (gf.nx + 1) * (j + (gf.ny + 1) * k);
+  const int c0 = (i >> 1) + Wc * ((j >> 1) + Hc * (k >> 1));
+  const int c1 = ((i + 1) >> 1) + Wc * (((j + 1) >> 1) + Hc * ((k + 1) >> 1));
+  for (int comp = 0; comp < 3; ++comp) {
+    const T* c = xc + comp * gc.N;
+    if (!fixed3(gf, comp, i, j, k)) xf[comp * gf.N + n] += T(0.5) * (c[c0] + c[c1]);
+  }
+}
+
+template <class T>
+void launch_prolong3d(hipStream_t st, const Grid& gf, const Grid& gc, const T* xc, T* xf) {
+  hipLaunchKernelGGL((k_prolong3d<T>), node_grid3(gf), dim3(NB_X, NB_Y), 0, st, gf, gc, xc, xf);
+}
+
+// Dirichlet values of the thermal problem are all zero.
+__global__ __launch_bounds__(NB) void k_lift3d(Grid g, double* __restrict__ u) {
+  const int i = blockIdx.x * NB_X + threadIdx.x, j = blockIdx.y * NB_Y + threadIdx.y, k = blockIdx.z;
+  if (i > g.nx || j > g.ny) return;
+  const int n = i + (g.nx + 1) * (j + (g.ny + 1) * k);
+  for (int c = 0; c < 3; ++c)
+    if (fixed3(g, c, i, j, k)) u[c * g.N + n] = 0.0;
+}
+
+void launch_lift3d(hipStream_t st, const Grid& g, double* u) {
+  hipLaunchKernelGGL(k_lift3d, node_grid3(g), dim3(NB_X, NB_Y), 0, st, g, u);
+}
+
+// ---------------------------------------------------------------------------
+// damage side: W2 per tetrahedron, Helmholtz node operator, VI evaluation
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(VB) void k_w2_3d(Grid g, Mat m, const double* __restrict__ u,
+                                              double* __restrict__ w2) {
+  const int e = blockIdx.x * VB + threadIdx.x;
+  if (e >= 6 * g.nx * g.ny * g.nz) return;
+  const int p = e % 6, hex = e / 6;
+  const int ci = hex % g.nx, cj = (hex / g.nx) % g.ny, ck = hex / (g.nx * g.ny);
+  const int W = g.nx + 1, H = g.ny + 1, N = g.N;
+  const double ih[3] = {1.0 / g.hx, 1.0 / g.hy, 1.0 / g.hz};
+  int nd[4];
+  for (int v = 0; v < 4; ++v)
+    nd[v] = (ci + c_kuhn_off[p][v][0]) + W * ((cj + c_kuhn_off[p][v][1]) + H * (ck + c_kuhn_off[p][v][2]));
+  // axis visited by each path step o_v -> o_{v+1}
+  int ax[3];
+  for (int s = 0; s < 3; ++s)
+    for (int a = 0; a < 3; ++a)
+      if (c_kuhn_off[p][s + 1][a] != c_kuhn_off[p][s][a]) ax[s] = a;
+  double G[3][3];
+  for (int c = 0; c < 3; ++c)
+    for (int s = 0; s < 3; ++s) G[c][ax[s]] = (u[nd[s + 1] + c * N] - u[nd[s] + c * N]) * ih[ax[s]];
+  double e0 = G[0][0], e1 = G[1][1], e2 = G[2][2];
+  if (g.eig_dT != 0.0) {
+    const double xc = (ci + 0.25 * (c_kuhn_off[p][1][0] + c_kuhn_off[p][2][0] + 1)) * g.hx;
+    const double s = -g.eig_dT * exp(-xc / g.eig_depth);
+    e0 -= s; e1 -= s; e2 -= s;
+  }
+  const double g01 = G[0][1] + G[1][0], g02 = G[0][2] + G[2][0], g12 = G[1][2] + G[2][1];
+  const double tr = e0 + e1 + e2;
+  w2[e] = m.lam * tr * tr + 2.0 * m.mu * (e0 * e0 + e1 * e1 + e2 * e2) +
+          m.mu * (g01 * g01 + g02 * g02 + g12 * g12);
+}
+
+void launch_w2_3d(hipStream_t st, const Grid& g, const Mat& m, const double* u, double* w2) {
+  const int ne = 6 * g.nx * g.ny * g.nz;
+  hipLaunchKernelGGL(k_w2_3d, dim3((ne + VB - 1) / VB), dim3(VB), 0, st, g, m, u, w2);
+}
+
+struct Helm3 {
+  double cL, cM, cm;
+};
+
+// the 24 tetrahedra around a node as runtime data (damage kernels)
+__device__ __constant__ int c_tets3[24][5] = {
+  {-1,-1,-1,0,3},{-1,-1,-1,1,3},{-1,-1,-1,2,3},{-1,-1,-1,3,3},{-1,-1,-1,4,3},{-1,-1,-1,5,3},
+  {-1,-1,0,0,2},{-1,-1,0,2,2},{-1,0,-1,1,2},{-1,0,-1,4,2},{-1,0,0,0,1},{-1,0,0,1,1},
+  {0,-1,-1,3,2},{0,-1,-1,5,2},{0,-1,0,2,1},{0,-1,0,3,1},{0,0,-1,4,1},{0,0,-1,5,1},
+  {0,0,0,0,0},{0,0,0,1,0},{0,0,0,2,0},{0,0,0,3,0},{0,0,0,4,0},{0,0,0,5,0}};
+
+__device__ __forceinline__ void kuhn_grad(int p, int v, const double ih[3], double g[3]) {
+  g[0] = g[1] = g[2] = 0.0;
+  // gradient of vertex v: difference of the path steps entering and leaving it
+  if (v < 3) {
+    for (int a = 0; a < 3; ++a)
+      if (c_kuhn_off[p][v + 1][a] != c_kuhn_off[p][v][a]) g[a] -= ih[a];
+  }
+  if (v > 0) {
+    for (int a = 0; a < 3; ++a)
+      if (c_kuhn_off[p][v][a] != c_kuhn_off[p][v - 1][a]) g[a] += ih[a];
+  }
+}
+
+template <bool TRIAL, bool MASKIN>
+__device__ __forceinline__ void helm_node3d(const Grid& g, const Helm3& hp,
+                                            const double* __restrict__ w2,
+                                            const double* __restrict__ a,
+                                            const double* __restrict__ d,
+                                            const double* __restrict__ lo, double mu,
+                                            const uint8_t* __restrict__ mask, int i, int j, int k,
+                                            double& Ha, double& gv, double& Hd) {
+  const int W = g.nx + 1, H = g.ny + 1;
+  const double ih[3] = {1.0 / g.hx, 1.0 / g.hy, 1.0 / g.hz};
+  const double vol = g.hx * g.hy * g.hz / 6.0;
+  Ha = gv = Hd = 0.0;
+  auto val = [&](int n) -> double {
+    if (TRIAL) return fmin(fmax(a[n] + mu * d[n], lo[n]), 1.0);
+    if (MASKIN) return mask[n] ? 0.0 : a[n];
+    return a[n];
+  };
+  for (int t = 0; t < 24; ++t) {
+    const int ci = i + c_tets3[t][0], cj = j + c_tets3[t][1], ck = k + c_tets3[t][2];
+    if (ci < 0 || cj < 0 || ck < 0 || ci >= g.nx || cj >= g.ny || ck >= g.nz) continue;
+    const int p = c_tets3[t][3], v = c_tets3[t][4];
+    double av[4], grad[3] = {0, 0, 0}, gvv[3];
+    double sum = 0;
+    for (int q = 0; q < 4; ++q) {
+      const int nn = (ci + c_kuhn_off[p][q][0]) + W * ((cj + c_kuhn_off[p][q][1]) + H * (ck + c_kuhn_off[p][q][2]));
+      av[q] = val(nn);
+      sum += av[q];
+      double gq[3];
+      kuhn_grad(p, q, ih, gq);
+      for (int c = 0; c < 3; ++c) grad[c] += av[q] * gq[c];
+    }
+    kuhn_grad(p, v, ih, gvv);
+    const double we = w2[6 * (ci + g.nx * (cj + g.ny * ck)) + p];
+    const double mass = vol / 20.0 * (av[v] + sum);
+    const double lap = vol * (gvv[0] * grad[0] + gvv[1] * grad[1] + gvv[2] * grad[2]);
+    Ha += (we + hp.cM) * mass + hp.cL * lap;
+    gv += (we - hp.cm) * vol / 4.0;
+    Hd += (we + hp.cM) * vol / 10.0 + hp.cL * vol * (gvv[0] * gvv[0] + gvv[1] * gvv[1] + gvv[2] * gvv[2]);
+  }
+}
+
+template <bool TRIAL>
+__global__ __launch_bounds__(NB) void k_vi_eval3d(Grid g, Helm3 hp, const double* __restrict__ w2,
+                                                  const double* __restrict__ a,
+                                                  const double* __restrict__ d,
+                                                  const double* __restrict__ lo,
+                                                  const double* __restrict__ S, int mu_slot,
+                                                  double zeta, double* __restrict__ F,
+                                                  double* __restrict__ phi,
+                                                  uint8_t* __restrict__ mask,
+                                                  double* __restrict__ hdinv, Red r2, Red rm,
+                                                  Red rlo, Red rhi) {
+  const int i = blockIdx.x * NB_X + threadIdx.x, j = blockIdx.y * NB_Y + threadIdx.y, k = blockIdx.z;
+  double p2 = 0.0, pm = 0.0, jlo = -INFINITY, jhi = -INFINITY;
+  if (i <= g.nx && j <= g.ny) {
+    const int n = i + (g.nx + 1) * (j + (g.ny + 1) * k);
+    const double mu = TRIAL ? S[mu_slot] : 0.0;
+    double Ha, gv, Hd;
+    helm_node3d<TRIAL, false>(g, hp, w2, a, d, lo, mu, nullptr, i, j, k, Ha, gv, Hd);
+    const double x = TRIAL ? fmin(fmax(a[n] + mu * d[n], lo[n]), 1.0) : a[n];
+    const double l = lo[n];
+    const double Fv = Ha - gv;
+    const double ph = mcp_fb(x, Fv, l, 1.0);
+    p2 = ph * ph;
+    pm = nan_to_inf(fabs(ph));
+    if (!TRIAL) {
+      F[n] = Fv;
+      phi[n] = ph;
+      const bool act = (x - l <= zeta && Fv > 0.0) || (1.0 - x <= zeta && Fv < 0.0) || (l >= 1.0);
+      mask[n] = act ? 1 : 0;
+      hdinv[n] = act ? 0.0 : 1.0 / Hd;
+      // row index (j, k) of an inactive node, for the reduced CG range
+      const double row = (double)(j + (g.ny + 1) * k);
+      if (!act) { jlo = -row; jhi = row; }
+    }
+  }
+  const int nb = gridDim.x * gridDim.y * gridDim.z;
+  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int tid = threadIdx.x + NB_X * threadIdx.y;
+  block_reduce<NB, false>(p2, r2, nb, bid, tid);
+  block_reduce<NB, true>(pm, rm, nb, bid, tid);
+  if (!TRIAL) {
+    block_reduce<NB, true>(jlo, rlo, nb, bid, tid);
+    block_reduce<NB, true>(jhi, rhi, nb, bid, tid);
+  }
+}
+
+void launch_vi_eval3d(hipStream_t st, const Grid& g, double cL, double cM, double cm,
+                      const double* w2, const double* a, const double* d, const double* lo,
+                      const double* S, int mu_slot, double zeta, double* F, double* phi,
+                      uint8_t* mask, double* hdinv, Red r2, Red rm, Red rlo, Red rhi, bool trial) {
+  Helm3 hp{cL, cM, cm};
+  dim3 gr = node_grid3(g), bl(NB_X, NB_Y);
+  if (trial)
+    hipLaunchKernelGGL((k_vi_eval3d<true>), gr, bl, 0, st, g, hp, w2, a, d, lo, S, mu_slot, zeta, F,
+                       phi, mask, hdinv, r2, rm, rlo, rhi);
+  else
+    hipLaunchKernelGGL((k_vi_eval3d<false>), gr, bl, 0, st, g, hp, w2, a, d, lo, S, mu_slot, zeta,
+                       F, phi, mask, hdinv, r2, rm, rlo, rhi);
+  const int nb = (int)(gr.x * gr.y * gr.z);
+  launch_finish(st, r2, nb, false);
+  launch_finish(st, rm, nb, true);
+  if (!trial) {
+    launch_finish(st, rlo, nb, true);
+    launch_finish(st, rhi, nb, true);
+  }
+}
+
+// y = H x on rows (j, k) whose row index lies in [r0, r1] (MASKED: reduced).
+template <bool MASKED, bool DOT>
+__global__ __launch_bounds__(NB) void k_helm_apply3d(Grid g, Helm3 hp, const double* __restrict__ w2,
+                                                     const double* __restrict__ x,
+                                                     const uint8_t* __restrict__ mask,
+                                                     double* __restrict__ y, int r0, int r1, Red r) {
+  const int i = blockIdx.x * NB_X + threadIdx.x, j = blockIdx.y * NB_Y + threadIdx.y, k = blockIdx.z;
+  double acc = 0.0;
+  const int row = j + (g.ny + 1) * k;
+  if (i <= g.nx && j <= g.ny && row >= r0 && row <= r1) {
+    const int n = i + (g.nx + 1) * row;
+    double Hx, gv, Hd;
+    helm_node3d<false, MASKED>(g, hp, w2, x, nullptr, nullptr, 0.0, mask, i, j, k, Hx, gv, Hd);
+    if (MASKED && mask[n]) Hx = 0.0;
+    y[n] = Hx;
+    if (DOT) acc = (MASKED && mask[n]) ? 0.0 : x[n] * Hx;
+  }
+  if (DOT)
+    block_reduce<NB, false>(acc, r, gridDim.x * gridDim.y * gridDim.z,
+                            blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                            threadIdx.x + NB_X * threadIdx.y);
+}
+
+void launch_helm_apply3d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                         const double* x, const uint8_t* mask, double* y, bool dot, Red r, int r0,
+                         int r1) {
+  Helm3 hp{cL, cM, 0.0};
+  const int rows = (g.ny + 1) * (g.nz + 1);
+  if (r0 < 0) r0 = 0;
+  if (r1 < 0 || r1 >= rows) r1 = rows - 1;
+  dim3 gr = node_grid3(g), bl(NB_X, NB_Y);
+#define H3(M, D) hipLaunchKernelGGL((k_helm_apply3d<M, D>), gr, bl, 0, st, g, hp, w2, x, mask, y, r0, r1, r)
+  if (mask) { if (dot) H3(true, true); else H3(true, false); }
+  else { if (dot) H3(false, true); else H3(false, false); }
+#undef H3
+  if (dot) launch_finish(st, r, (int)(gr.x * gr.y * gr.z), false);
+}
+
+__global__ __launch_bounds__(VB) void k_energy3d(Grid g, Mat m, double kell, double gc_cw, double ell,
+                                                 int at2, const double* __restrict__ w2,
+                                                 const double* __restrict__ a, Red rel, Red rsu) {
+  const int ne = 6 * g.nx * g.ny * g.nz;
+  const int W = g.nx + 1, H = g.ny + 1;
+  const double ih[3] = {1.0 / g.hx, 1.0 / g.hy, 1.0 / g.hz};
+  const double vol = g.hx * g.hy * g.hz / 6.0;
+  double el = 0.0, su = 0.0;
+  for (int e = blockIdx.x * VB + threadIdx.x; e < ne; e += gridDim.x * VB) {
+    const int p = e % 6, hex = e / 6;
+    const int ci = hex % g.nx, cj = (hex / g.nx) % g.ny, ck = hex / (g.nx * g.ny);
+    double av[4], grad[3] = {0, 0, 0}, s = 0, s2 = 0;
+    for (int q = 0; q < 4; ++q) {
+      av[q] = a[(ci + c_kuhn_off[p][q][0]) + W * ((cj + c_kuhn_off[p][q][1]) + H * (ck + c_kuhn_off[p][q][2]))];
+      s += av[q];
+      s2 += av[q] * av[q];
+      double gq[3];
+      kuhn_grad(p, q, ih, gq);
+      for (int c = 0; c < 3; ++c) grad[c] += av[q] * gq[c];
+    }
+    el += 0.5 * abar4(av[0], av[1], av[2], av[3], kell) * vol * w2[e];
+    const double wint = at2 ? vol / 20.0 * (s2 + s * s) : vol / 4.0 * s;
+    su += gc_cw * (wint / ell + ell * vol * (grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]));
+  }
+  block_reduce<VB, false>(el, rel, gridDim.x, blockIdx.x, threadIdx.x);
+  block_reduce<VB, false>(su, rsu, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_energy3d(hipStream_t st, const Grid& g, const Mat& m, double kell, double gc_cw,
+                     double ell, int at2, const double* w2, const double* a, Red rel, Red rsu) {
+  const int ne = 6 * g.nx * g.ny * g.nz;
+  int nb = (ne + VB - 1) / VB;
+  if (nb > VGRID) nb = VGRID;
+  hipLaunchKernelGGL(k_energy3d, dim3(nb), dim3(VB), 0, st, g, m, kell, gc_cw, ell, at2, w2, a, rel, rsu);
+  launch_finish(st, rel, nb, false);
+  launch_finish(st, rsu, nb, false);
+}
+
+// Dense assembly of the coarsest 3D level (one thread per node row).
+__global__ __launch_bounds__(1024) void k_dense_assemble3d(Grid g, Mat m, const double* __restrict__ abar,
+                                                           double* __restrict__ A) {
+  const int N = g.N, n3 = 3 * N, W = g.nx + 1, H = g.ny + 1;
+  for (int q = threadIdx.x; q < n3 * n3; q += 1024) A[q] = 0.0;
+  __syncthreads();
+  const double ih[3] = {1.0 / g.hx, 1.0 / g.hy, 1.0 / g.hz};
+  const double vol = g.hx * g.hy * g.hz / 6.0;
+  for (int n = threadIdx.x; n < N; n += 1024) {
+    const int i = n % W, j = (n / W) % H, k = n / (W * H);
+    for (int t = 0; t < 24; ++t) {
+      const int ci = i + c_tets3[t][0], cj = j + c_tets3[t][1], ck = k + c_tets3[t][2];
+      if (ci < 0 || cj < 0 || ck < 0 || ci >= g.nx || cj >= g.ny || ck >= g.nz) continue;
+      const int p = c_tets3[t][3], v = c_tets3[t][4];
+      const double w = abar[6 * (ci + g.nx * (cj + g.ny * ck)) + p] * vol;
+      double gv[3];
+      kuhn_grad(p, v, ih, gv);
+      for (int q = 0; q < 4; ++q) {
+        const int nb = (ci + c_kuhn_off[p][q][0]) + W * ((cj + c_kuhn_off[p][q][1]) + H * (ck + c_kuhn_off[p][q][2]));
+        double gw[3];
+        kuhn_grad(p, q, ih, gw);
+        const double gg = gv[0] * gw[0] + gv[1] * gw[1] + gv[2] * gw[2];
+        for (int c = 0; c < 3; ++c)
+          for (int d = 0; d < 3; ++d)
+            A[(size_t)(c * N + n) * n3 + d * N + nb] +=
+                w * (m.lam * gv[c] * gw[d] + m.mu * gv[d] * gw[c] + (c == d ? m.mu * gg : 0.0));
+      }
+    }
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < n3; r += 1024) {
+    const int comp = r / N, n = r % N;
+    if (fixed3(g, comp, n % W, (n / W) % H, n / (W * H))) {
+      for (int c = 0; c < n3; ++c) {
+        A[(size_t)r * n3 + c] = (c == r) ? 1.0 : 0.0;
+        A[(size_t)c * n3 + r] = (c == r) ? 1.0 : 0.0;
+      }
+    }
+  }
+}
+
+void launch_dense_assemble3d(hipStream_t st, const Grid& g, const Mat& m, const double* abar, double* A) {
+  hipLaunchKernelGGL(k_dense_assemble3d, dim3(1), dim3(1024), 0, st, g, m, abar, A);
+}
+
+#define INST3(T)                                                                                \
+  template void launch_apply3d<T>(hipStream_t, const Grid&, const Mat&, bool, const T*, double,  \
+                                  const T*, T*, const ND<T>*, int, int, Red);                    \
+  template void launch_resid3d<T>(hipStream_t, const Grid&, const Mat&, bool, const T*, double,  \
+                                  const T*, T*, const ND<T>*, bool, Red);                        \
+  template void launch_smooth3d<T>(hipStream_t, const Grid&, const Mat&, bool, const T*, double, \
+                                   const ND<T>*, T*, const T*, const ND<T>*, ND<T>*, double,     \
+                                   double);                                                      \
+  template void launch_restrict3d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);       \
+  template void launch_prolong3d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);
+INST3(float)
+INST3(double)
+#undef INST3
+
+}  // namespace frac

@@ -8,6 +8,7 @@ namespace frac {
 
 // ---- 2D operator kernels (kernels2d.hip) -----------------------------------
 int node_blocks2(const Grid& g);
+int node_blocks(const Grid& g);
 template <class T>
 void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
                     double kell, const T* x, T* y, const ND<T>* b, int mask, int red, Red r);
@@ -49,9 +50,42 @@ void launch_trial_state(hipStream_t st, int64_t n2, int64_t N, const double* u, 
                         const double* du, const double* da, const double* lo, const double* S,
                         double* ut, double* at);
 
+// ---- 3D operator kernels (kernels3d.hip); the 2D launchers forward to these
+// when g.dim == 3 ----------------------------------------------------------
+int node_blocks3(const Grid& g);
+template <class T>
+void launch_apply3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
+                    double kell, const T* x, T* y, const ND<T>* b, int mask, int red, Red r);
+template <class T>
+void launch_resid3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
+                    double kell, const T* x, T* r, const ND<T>* b, bool red, Red rr);
+template <class T>
+void launch_smooth3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
+                     double kell, const ND<T>* x_in, T* x_out, const T* b, const ND<T>* d_in,
+                     ND<T>* d_out, double cd, double cr);
+void launch_coarsen3d(hipStream_t st, const Grid& gf, bool fine_is_alpha, const double* fine,
+                      double kell, const Grid& gc, double* c64, float* c32);
+template <class T>
+void launch_restrict3d(hipStream_t st, const Grid& gf, const Grid& gc, const T* rf, T* bc);
+template <class T>
+void launch_prolong3d(hipStream_t st, const Grid& gf, const Grid& gc, const T* xc, T* xf);
+void launch_lift3d(hipStream_t st, const Grid& g, double* u);
+void launch_w2_3d(hipStream_t st, const Grid& g, const Mat& m, const double* u, double* w2);
+void launch_vi_eval3d(hipStream_t st, const Grid& g, double cL, double cM, double cm,
+                      const double* w2, const double* a, const double* d, const double* lo,
+                      const double* S, int mu_slot, double zeta, double* F, double* phi,
+                      uint8_t* mask, double* hdinv, Red r2, Red rm, Red rlo, Red rhi, bool trial);
+void launch_helm_apply3d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                         const double* x, const uint8_t* mask, double* y, bool dot, Red r, int r0,
+                         int r1);
+void launch_energy3d(hipStream_t st, const Grid& g, const Mat& m, double kell, double gc_cw,
+                     double ell, int at2, const double* w2, const double* a, Red rel, Red rsu);
+void launch_dense_assemble3d(hipStream_t st, const Grid& g, const Mat& m, const double* abar,
+                             double* A);
+
 // ---- coarse dense solve (dense.hip) ----------------------------------------
-void launch_dense_setup2d(hipStream_t st, const Grid& g, const Mat& m, const double* abar,
-                          double* A, double* Ainv);
+void launch_dense_setup(hipStream_t st, const Grid& g, const Mat& m, const double* abar,
+                        double* A, double* Ainv);
 template <class T>
 void launch_dense_solve(hipStream_t st, int n, const double* Ainv, const T* b, T* x);
 

@@ -124,40 +124,51 @@ int hip_ok(hipError_t e) { return e == hipSuccess ? FRACTURE_OK : FRACTURE_EDEVI
 
 int validate(const fracture_params* p) {
   if (!p) return FRACTURE_EINVAL;
-  if (p->dim != 2) return FRACTURE_EINVAL;
+  if (p->dim != 2 && p->dim != 3) return FRACTURE_EINVAL;
   if (p->nx < 2 || p->ny < 2) return FRACTURE_EINVAL;
   if (!(p->lx > 0) || !(p->ly > 0)) return FRACTURE_EINVAL;
+  if (p->dim == 3 && (p->nz < 1 || !(p->lz > 0) || !(p->thermal_depth > 0))) return FRACTURE_EINVAL;
   if (p->model != FRACTURE_AT1 && p->model != FRACTURE_AT2) return FRACTURE_EINVAL;
   if (!(p->E > 0) || !(p->nu > -1.0 && p->nu < 0.5) || !(p->Gc > 0) || !(p->ell > 0) ||
       !(p->k_ell >= 0))
     return FRACTURE_EINVAL;
   if (!(p->omega > 0 && p->omega < 2)) return FRACTURE_EINVAL;
   if (p->relax_mode < 0 || p->relax_mode > 2) return FRACTURE_EINVAL;
-  if (p->load_kind != FRACTURE_LOAD_TENSION_2D) return FRACTURE_EINVAL;
+  if (p->dim == 2 && p->load_kind != FRACTURE_LOAD_TENSION_2D) return FRACTURE_EINVAL;
+  if (p->dim == 3 && p->load_kind != FRACTURE_LOAD_THERMAL_3D) return FRACTURE_EINVAL;
+  if (p->dim == 3 && p->newton) return FRACTURE_EINVAL;   // coupled Newton blocks are 2D only
   if (p->precision != FRACTURE_FP64 && p->precision != FRACTURE_MIXED) return FRACTURE_EINVAL;
   if (p->newton && !(p->minres_rtol > 0 && p->max_minres >= 1 && p->max_newton >= 1)) return FRACTURE_EINVAL;
   if (p->max_am < 1 || p->max_pcg < 1 || p->max_vi < 1 || p->max_vi_cg < 1) return FRACTURE_EINVAL;
   if (p->cheb_degree < 1 || p->cheb_degree > 8) return FRACTURE_EINVAL;
-  if ((int64_t)(p->nx + 1) * (p->ny + 1) > (int64_t)1 << 30) return FRACTURE_EINVAL;
+  if ((int64_t)(p->nx + 1) * (p->ny + 1) * (p->dim == 3 ? p->nz + 1 : 1) > (int64_t)1 << 29)
+    return FRACTURE_EINVAL;
   return FRACTURE_OK;
 }
 
 // Level shapes: halve both axes while they stay even and the level has more
 // DOFs than coarse_max_dofs (at least once, so there is always a coarse level).
 int level_shapes(const fracture_params* p, Grid* out) {
-  int nx = p->nx, ny = p->ny, L = 0;
-  double hx = p->lx / nx, hy = p->ly / ny;
+  const int dim = p->dim;
+  int nx = p->nx, ny = p->ny, nz = dim == 3 ? p->nz : 0, L = 0;
+  double hx = p->lx / nx, hy = p->ly / ny, hz = dim == 3 ? p->lz / nz : 0.0;
   for (;;) {
     Grid g{};
-    g.nx = nx; g.ny = ny; g.nz = 0; g.hx = hx; g.hy = hy; g.hz = 0;
-    g.N = (nx + 1) * (ny + 1);
-    g.bc = BC_TENSION_2D;
+    g.nx = nx; g.ny = ny; g.nz = nz; g.hx = hx; g.hy = hy; g.hz = hz;
+    g.N = (nx + 1) * (ny + 1) * (dim == 3 ? nz + 1 : 1);
+    g.bc = dim == 3 ? BC_THERMAL_3D : BC_TENSION_2D;
+    g.dim = dim;
+    g.eig_dT = 0.0;
+    g.eig_depth = p->thermal_depth;
     out[L++] = g;
-    const bool can = (nx % 2 == 0) && (ny % 2 == 0) && nx >= 4 && ny >= 4 && L < MAXLEV;
-    if (!can || (L >= 2 && 2 * g.N <= p->coarse_max_dofs)) break;
+    bool can = (nx % 2 == 0) && (ny % 2 == 0) && L < MAXLEV;
+    if (dim == 2) can = can && nx >= 4 && ny >= 4;
+    else can = can && (nz % 2 == 0) && nx >= 2 && ny >= 2 && nz >= 2;
+    if (!can || (L >= 2 && dim * g.N <= p->coarse_max_dofs)) break;
     nx /= 2; ny /= 2; hx *= 2; hy *= 2;
+    if (dim == 3) { nz /= 2; hz *= 2; }
   }
-  if (2 * out[L - 1].N > DENSE_MAX) return -1;
+  if (dim * out[L - 1].N > DENSE_MAX) return -1;
   if (L < 2) return -1;   // at least one coarse level
   return L;
 }
@@ -167,8 +178,9 @@ size_t layout(const fracture_params* p, fracture* h, void* ws) {
   const int L = level_shapes(p, gl);
   if (L < 1) return 0;
   Carver c(ws);
-  const int64_t N = gl[0].N, n2 = 2 * N;
-  const int64_t ncell = (int64_t)p->nx * p->ny;
+  const int dim = p->dim;
+  const int64_t N = gl[0].N, n2 = dim * N;   // displacement DOFs
+  const int64_t nelem = (int64_t)p->nx * p->ny * (dim == 3 ? 6 * (int64_t)p->nz : 2);
   fracture tmp;
   fracture* t = h ? h : &tmp;
   t->u = c.take<double>(n2);
@@ -180,7 +192,7 @@ size_t layout(const fracture_params* p, fracture* h, void* ws) {
   t->r = c.take<double>(n2);
   t->pv = c.take<double>(n2);
   t->q = c.take<double>(n2);
-  t->w2 = c.take<double>(2 * ncell);
+  t->w2 = c.take<double>(nelem);
   t->F = c.take<double>(N);
   t->phi = c.take<double>(N);
   t->hdinv = c.take<double>(N);
@@ -196,15 +208,16 @@ size_t layout(const fracture_params* p, fracture* h, void* ws) {
   for (int l = 0; l < L; ++l) {
     Level& v = t->lv[l];
     v.g = gl[l];
-    const int64_t m2 = 2 * (int64_t)gl[l].N;
-    v.abar = l > 0 ? c.take<double>(2 * (int64_t)gl[l].nx * gl[l].ny) : nullptr;
+    const int64_t m2 = dim * (int64_t)gl[l].N;
+    const int64_t ne = (int64_t)gl[l].nx * gl[l].ny * (dim == 3 ? 6 * (int64_t)gl[l].nz : 2);
+    v.abar = l > 0 ? c.take<double>(ne) : nullptr;
     v.b = c.take<double>(m2);
     v.xa = c.take<double>(m2);
     v.xb = c.take<double>(m2);
     v.d = c.take<double>(m2);
     v.r = c.take<double>(m2);
     if (p->precision == FRACTURE_MIXED) {
-      v.abar32 = l > 0 ? c.take<float>(2 * (int64_t)gl[l].nx * gl[l].ny) : nullptr;
+      v.abar32 = l > 0 ? c.take<float>(ne) : nullptr;
       v.b32 = c.take<float>(m2);
       v.xa32 = c.take<float>(m2);
       v.xb32 = c.take<float>(m2);
@@ -240,10 +253,10 @@ size_t layout(const fracture_params* p, fracture* h, void* ws) {
     t->nat = c.take<double>(N);
     t->nFu = c.take<double>(n2);
   }
-  const int dn = 2 * gl[L - 1].N;
+  const int dn = dim * gl[L - 1].N;
   t->dA = c.take<double>((size_t)dn * dn);
   t->dAinv = c.take<double>((size_t)dn * dn);
-  int pn = node_blocks2(gl[0]);
+  int pn = node_blocks(gl[0]);
   if (vec_blocks(n2) > pn) pn = vec_blocks(n2);
   t->part_n = pn;
   t->part = c.take<double>(pn * C_SLOTS);
@@ -296,6 +309,48 @@ double chebyshev_bound2d(const Grid& g, const Mat& m) {
   return best;
 }
 
+// The same bound for the six Kuhn tetrahedra (12 x 12 element matrices).
+double chebyshev_bound3d(const Grid& g, const Mat& m) {
+  static const int off[6][4][3] = {
+    {{0,0,0},{1,0,0},{1,1,0},{1,1,1}}, {{0,0,0},{1,0,0},{1,0,1},{1,1,1}},
+    {{0,0,0},{0,1,0},{1,1,0},{1,1,1}}, {{0,0,0},{0,1,0},{0,1,1},{1,1,1}},
+    {{0,0,0},{0,0,1},{1,0,1},{1,1,1}}, {{0,0,0},{0,0,1},{0,1,1},{1,1,1}}};
+  const double ih[3] = {1.0 / g.hx, 1.0 / g.hy, 1.0 / g.hz};
+  double best = 0.0;
+  for (int p = 0; p < 6; ++p) {
+    double gr[4][3] = {};
+    for (int v = 0; v < 4; ++v) {
+      for (int a = 0; a < 3; ++a) {
+        if (v < 3 && off[p][v + 1][a] != off[p][v][a]) gr[v][a] -= ih[a];
+        if (v > 0 && off[p][v][a] != off[p][v - 1][a]) gr[v][a] += ih[a];
+      }
+    }
+    for (int v = 0; v < 4; ++v)
+      for (int c = 0; c < 3; ++c) {
+        double diag = 0, sum = 0;
+        for (int w = 0; w < 4; ++w) {
+          const double gg = gr[v][0] * gr[w][0] + gr[v][1] * gr[w][1] + gr[v][2] * gr[w][2];
+          for (int d = 0; d < 3; ++d) {
+            const double kv = m.lam * gr[v][c] * gr[w][d] + m.mu * gr[v][d] * gr[w][c] + (c == d ? m.mu * gg : 0.0);
+            if (w == v && d == c) diag = kv;
+            sum += std::fabs(kv);
+          }
+        }
+        if (sum / diag > best) best = sum / diag;
+      }
+  }
+  return best;
+}
+
+// The finest grid carrying the current load as thermal eigenstrain (3D); the
+// residual, W2 and energy of the actual problem use it, operator actions on
+// error equations use the plain grid.
+Grid load_grid(const fracture* h) {
+  Grid g = h->lv[0].g;
+  g.eig_dT = (g.dim == 3) ? h->load : 0.0;
+  return g;
+}
+
 Red red(fracture* h, int cslot, int sslot, int post = P_STORE) {
   return Red{h->part + (size_t)cslot * h->part_n, h->S, sslot, post};
 }
@@ -318,7 +373,7 @@ void update_coefficients(fracture* h) {
                      h->lv[l].abar, h->mixed ? h->lv[l].abar32 : nullptr);
   if (h->mixed) launch_to_float(h->st, h->N, h->alpha, h->alpha32, 1.0);
   const int Lc = h->nlev - 1;
-  if (Lc >= 1) launch_dense_setup2d(h->st, h->lv[Lc].g, h->mat, h->lv[Lc].abar, h->dA, h->dAinv);
+  if (Lc >= 1) launch_dense_setup(h->st, h->lv[Lc].g, h->mat, h->lv[Lc].abar, h->dA, h->dAinv);
   h->coef_valid = true;
 }
 
@@ -401,7 +456,8 @@ int pcg(fracture* h, double tol, int* iters) {
   const int64_t n2 = h->n2;
   hipStream_t st = h->st;
   HIPCHK(hipMemcpyAsync(h->x, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
-  launch_resid2d(st, g, h->mat, true, h->alpha, h->p.k_ell, h->x, h->r, nullptr, true,
+  const Grid gl = load_grid(h);
+  launch_resid2d(st, gl, h->mat, true, h->alpha, h->p.k_ell, h->x, h->r, nullptr, true,
                  red(h, 0, S_RR));
   int rc = read_scalars(h);
   if (rc) return rc;
@@ -444,7 +500,7 @@ int pcg_mixed(fracture* h, double tol, int* iters) {
   *iters = 0;
   HIPCHK(hipMemcpyAsync(h->x, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
   for (int outer = 0;; ++outer) {
-    launch_resid2d<double>(st, g, h->mat, true, h->alpha, h->p.k_ell, h->x, h->r, nullptr, true,
+    launch_resid2d<double>(st, load_grid(h), h->mat, true, h->alpha, h->p.k_ell, h->x, h->r, nullptr, true,
                            red(h, 0, S_RR));
     int rc = read_scalars(h);
     if (rc) return rc;
@@ -483,7 +539,7 @@ int pcg_mixed(fracture* h, double tol, int* iters) {
 // ||f - K u_D|| on free rows: the load the elastic problem carries (its RHS
 // with a zero initial guess).  The PCG tolerance is relative to it.
 int load_norm(fracture* h, double* out) {
-  const Grid& g = h->lv[0].g;
+  const Grid g = load_grid(h);
   HIPCHK(hipMemsetAsync(h->q, 0, h->n2 * sizeof(double), h->st));
   launch_lift2d(h->st, g, h->q, h->load);
   launch_resid2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, h->q, h->r, nullptr, true,
@@ -600,7 +656,7 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
 // ---------------------------------------------------------------------------
 
 int residual_norm(fracture* h, double* out) {
-  const Grid& g = h->lv[0].g;
+  const Grid g = load_grid(h);
   launch_apply2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, h->u, h->q, nullptr, 0, 2,
                  red(h, 0, S_EU2));
   launch_w2_2d(h->st, g, h->mat, h->u, h->w2);
@@ -883,7 +939,7 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
       launch_relax_u(st, n2, h->u, h->x, h->p.omega);
     HIPCHK(hipEventRecord(h->ev[2], st));
     // damage substep
-    launch_w2_2d(st, h->lv[0].g, h->mat, h->u, h->w2);
+    launch_w2_2d(st, load_grid(h), h->mat, h->u, h->w2);
     rc = damage_qp(h, &loc.vi_iters, &loc.vi_cg_iters);
     if (rc) break;
     rc = relax_alpha(h);
@@ -1029,7 +1085,7 @@ int fracture_create(const fracture_params* p, const uint8_t* notch_mask, void* d
   h->cM = p->model == FRACTURE_AT2 ? 2.0 * p->Gc / (h->cw * p->ell) : 0.0;
   h->cm = p->model == FRACTURE_AT1 ? p->Gc / (h->cw * p->ell) : 0.0;
   // Chebyshev polynomial on [0.06 lmax, lmax]
-  h->lam_max = chebyshev_bound2d(h->lv[0].g, h->mat);
+  h->lam_max = p->dim == 3 ? chebyshev_bound3d(h->lv[0].g, h->mat) : chebyshev_bound2d(h->lv[0].g, h->mat);
   h->lam_min = 0.06 * h->lam_max;
   const double theta = 0.5 * (h->lam_max + h->lam_min), delta = 0.5 * (h->lam_max - h->lam_min);
   const double sigma = theta / delta;
@@ -1133,8 +1189,14 @@ int fracture_set_monitor(fracture_t h, fracture_monitor_fn fn, void* user) {
 
 int fracture_energy(fracture_t h, double* elastic, double* surface) {
   if (!h) return FRACTURE_EINVAL;
-  launch_energy2d(h->st, h->lv[0].g, h->mat, h->p.k_ell, h->gc_cw, h->p.ell,
-                  h->p.model == FRACTURE_AT2, h->u, h->alpha, red(h, 10, S_EL), red(h, 11, S_SURF));
+  if (h->dim == 3) {
+    launch_w2_3d(h->st, load_grid(h), h->mat, h->u, h->w2);
+    launch_energy3d(h->st, h->lv[0].g, h->mat, h->p.k_ell, h->gc_cw, h->p.ell,
+                    h->p.model == FRACTURE_AT2, h->w2, h->alpha, red(h, 10, S_EL), red(h, 11, S_SURF));
+  } else {
+    launch_energy2d(h->st, h->lv[0].g, h->mat, h->p.k_ell, h->gc_cw, h->p.ell,
+                    h->p.model == FRACTURE_AT2, h->u, h->alpha, red(h, 10, S_EL), red(h, 11, S_SURF));
+  }
   int rc = read_scalars(h);
   if (rc) return rc;
   if (elastic) *elastic = h->hS[S_EL];
@@ -1184,11 +1246,12 @@ int fracture_apply(fracture_t h, int op, int level, const double* d_x, double* d
                      d_x, d_y, nullptr, 1, 0, none);
     } break;
     case FRACTURE_OP_DAMAGE_HESS:
-      launch_w2_2d(h->st, g, h->mat, h->u, h->w2);
+      launch_w2_2d(h->st, load_grid(h), h->mat, h->u, h->w2);
       launch_helm_apply2d(h->st, g, h->cL, h->cM, h->w2, d_x, nullptr, d_y, false, none);
       break;
     case FRACTURE_OP_COUPLING:
     case FRACTURE_OP_COUPLING_T: {
+      if (h->dim != 2) return FRACTURE_EINVAL;
       // the full coupling block (no active set): mask cleared
       launch_w2_2d(h->st, g, h->mat, h->u, h->w2);
       HIPCHK(hipMemsetAsync(h->mask, 0, h->N, h->st));
@@ -1212,7 +1275,7 @@ int fracture_apply(fracture_t h, int op, int level, const double* d_x, double* d
 
 int fracture_gradient(fracture_t h, double* d_Eu, double* d_Ea) {
   if (!h) return FRACTURE_EINVAL;
-  const Grid& g = h->lv[0].g;
+  const Grid g = load_grid(h);
   Red none{};
   if (d_Eu)
     launch_apply2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, h->u, d_Eu, nullptr, 0, 0, none);
@@ -1277,11 +1340,13 @@ int fracture_time_kernel(fracture_t h, int kernel, int reps, double* avg_ms, dou
                             red(h, 2, S_PQ, P_STORE));
     }
   };
+  const double dv = 8.0 * h->dim;                 // one displacement vector, per node
+  const double w2b = 8.0 * (h->dim == 3 ? 6 : 2);  // W2 per node (elements per node)
   switch (kernel) {
-    case FRACTURE_KERNEL_APPLY: b = 40.0 * N; break;
-    case FRACTURE_KERNEL_SMOOTH: b = 88.0 * N; break;
-    case FRACTURE_KERNEL_VI_EVAL: b = 57.0 * N; break;
-    case FRACTURE_KERNEL_HELM: b = 33.0 * N; break;
+    case FRACTURE_KERNEL_APPLY: b = (2 * dv + 8.0) * N; break;
+    case FRACTURE_KERNEL_SMOOTH: b = (5 * dv + 8.0) * N; break;
+    case FRACTURE_KERNEL_VI_EVAL: b = (8.0 + 8.0 + w2b + 8.0 + 8.0 + 1.0 + 8.0) * N; break;
+    case FRACTURE_KERNEL_HELM: b = (8.0 + w2b + 1.0 + 8.0) * N; break;
     default: return FRACTURE_EINVAL;
   }
   one();  // warm

@@ -16,6 +16,12 @@ Recipes (the paper uses no dataset; these stand in for its test problems):
   length a drawn from U[0.1, 0.4] (seed 0) and snapped to nodes, 20 steps
   t = 0.1 k.
 * ``small_tension``: the config-2 recipe at a small n (parity sizes).
+* ``config3``: the 3D thermal-shock slab [0,1] x [0,1] x [0,0.25],
+  128 x 128 x 32 hexahedra split into 6 Kuhn tetrahedra, AT1, ell = 4h,
+  eigenstrain -DT exp(-x/0.05) I, u_x = 0 on x = 1 plus the pins that
+  remove the remaining rigid motions, DT_k = (k/15) 2 DT_c for k = 1..15 with
+  DT_c = sqrt(3 Gc (1 - nu) / (16 E ell)) (the surface layer's onset under
+  biaxial in-plane constraint, beta = 1).
 * ``config5``: a served stream of independent tension problems: side
   n ~ U{64, ..., 1024}, ell ~ U[0.01, 0.05], h = ell/4, domain side
   L = n h, the config-2 notch recipe scaled by L, 10-30 load steps with
@@ -115,3 +121,29 @@ def config5(n_instances=256, seed=1, sizes=(64, 128, 256, 512, 1024), rate=50.0,
         loads = [k * (load_scale * np.sqrt(L)) / steps for k in range(1, steps + 1)]
         out.append(dict(rid=rid, params=p, notch=notch, loads=loads, arrival=t))
     return out
+
+
+def thermal(nx, ny, nz, lx=1.0, ly=1.0, lz=0.25, ell=None, model="AT1", depth=0.05, **extra):
+    if ell is None:
+        ell = 4.0 * lx / nx
+    p = dict(dim=3, nx=nx, ny=ny, nz=nz, lx=lx, ly=ly, lz=lz, model=model, E=1.0, nu=0.3,
+             Gc=1.0, ell=ell, k_ell=1e-6, load_kind=1, thermal_depth=depth)
+    p.update(extra)
+    return p
+
+
+def thermal_dtc(p):
+    """Onset temperature drop of the biaxially constrained surface layer (AT1)."""
+    return float(np.sqrt(3.0 * p["Gc"] * (1.0 - p["nu"]) / (16.0 * p["E"] * p["ell"])))
+
+
+def config3(n=128, nz=32, steps=15):
+    p = thermal(n, n, nz, 1.0, 1.0, 0.25)
+    dtc = thermal_dtc(p)
+    loads = [(k / steps) * 2.0 * dtc for k in range(1, steps + 1)]
+    return p, loads
+
+
+def oracle_kwargs3(p):
+    return dict(E=p["E"], nu=p["nu"], Gc=p["Gc"], ell=p["ell"], k_ell=p["k_ell"],
+                model=p["model"], depth=p["thermal_depth"])

@@ -350,3 +350,130 @@ def test_mixed_precision_ragged_and_newton():
         assert stats["converged"]
         assert _rel(u, st.u) < STEP_TOL and _rel(a, st.alpha) < STEP_TOL
     s.close()
+
+
+# ----------------------------------------------------------------------------- 3D Kuhn tetrahedra
+
+def _problem3(p):
+    return problems.thermal_3d(p["nx"], p["ny"], p["nz"], p["lx"], p["ly"], p["lz"],
+                               **workloads.oracle_kwargs3(p))
+
+
+SHAPES3 = [(4, 4, 2), (12, 10, 6), (70, 4, 2)]
+
+
+@pytest.mark.parametrize("nx,ny,nz", SHAPES3)
+def test_elasticity_apply_3d_matches_assembled(nx, ny, nz):
+    p = workloads.thermal(nx, ny, nz, 1.0, 0.8, 0.5)
+    print(f"[apply3d] {nx}x{ny}x{nz}", flush=True)
+    s = _solver(p)
+    P = _problem3(p)
+    u, alpha = workloads.random_fields(P.model.N, 3 * P.model.N, seed=nx + ny + nz)
+    s.set_state(u=u, alpha=alpha)
+    y = s.apply(fracture.FRACTURE_OP_ELASTICITY, u)
+    want = P.model.K(alpha) @ u
+    assert np.max(np.abs(y - want)) / np.max(np.abs(want)) < OPS_TOL
+    s.close()
+
+
+def _interp3(nxc, nyc, nzc):
+    nxf, nyf, nzf = 2 * nxc, 2 * nyc, 2 * nzc
+    Wc, Hc = nxc + 1, nyc + 1
+    rows, cols, vals = [], [], []
+    for kf in range(nzf + 1):
+        for jf in range(nyf + 1):
+            for i_f in range(nxf + 1):
+                f = i_f + (nxf + 1) * (jf + (nyf + 1) * kf)
+                for (a, b, c) in ((i_f // 2, jf // 2, kf // 2), ((i_f + 1) // 2, (jf + 1) // 2, (kf + 1) // 2)):
+                    rows.append(f)
+                    cols.append(a + Wc * (b + Hc * c))
+                    vals.append(0.5)
+    Ps = sp.csr_matrix((vals, (rows, cols)), shape=((nxf + 1) * (nyf + 1) * (nzf + 1), Wc * Hc * (nzc + 1)))
+    return sp.block_diag([Ps, Ps, Ps]).tocsr()
+
+
+def test_coarse_levels_3d_are_galerkin_products():
+    p = workloads.thermal(16, 8, 4, 1.0, 0.5, 0.25)
+    s = _solver(p)
+    P = _problem3(p)
+    rng = np.random.default_rng(2)
+    alpha = rng.uniform(0, 1, P.model.N)
+    s.set_state(alpha=alpha)
+    fracture.fracture_update_coefficients(s.h)
+    K = P.model.K(alpha)
+    shapes = s.levels()
+    assert len(shapes) >= 3
+    Pc = sp.identity(K.shape[0], format="csr")
+    for l in range(1, len(shapes)):
+        nxc, nyc, nzc = shapes[l]
+        Pc = (Pc @ _interp3(nxc, nyc, nzc)).tocsr()
+        Kl = (Pc.T @ K @ Pc).tocsr()
+        Nl = (nxc + 1) * (nyc + 1) * (nzc + 1)
+        ii = np.arange(Nl) % (nxc + 1)
+        jj = (np.arange(Nl) // (nxc + 1)) % (nyc + 1)
+        kk = np.arange(Nl) // ((nxc + 1) * (nyc + 1))
+        fixed = np.zeros(3 * Nl, bool)
+        fixed[np.flatnonzero(ii == nxc)] = True
+        fixed[Nl + np.flatnonzero((ii == nxc) & (jj == 0) & (kk == 0))] = True
+        fixed[2 * Nl + np.flatnonzero((ii == nxc) & (kk == 0) & ((jj == 0) | (jj == nyc)))] = True
+        x = rng.standard_normal(3 * Nl)
+        x[fixed] = 0.0
+        want = Kl @ x
+        want[fixed] = 0.0
+        y = s.apply(fracture.FRACTURE_OP_LEVEL, x, level=l)
+        assert np.max(np.abs(y - want)) / np.max(np.abs(want)) < OPS_TOL, l
+    s.close()
+
+
+def test_gradients_3d_with_eigenstrain_match():
+    p = workloads.thermal(12, 10, 6, 1.0, 0.8, 0.5)
+    s = _solver(p)
+    P = _problem3(p)
+    u, alpha = workloads.random_fields(P.model.N, 3 * P.model.N, seed=9)
+    u *= 0.02
+    dT = 1.7
+    s.set_load(dT)
+    u[P.fixed] = 0.0
+    s.set_state(u=u, alpha=alpha, alpha_prev=np.zeros(P.model.N))
+    Eu, Ea = s.gradient()
+    eps0 = P.eps0(dT)
+    want_u = P.model.grad_u(u, alpha, eps0)
+    want_a = P.model.grad_alpha(u, alpha, eps0)
+    assert np.max(np.abs(Eu - want_u)) / np.max(np.abs(want_u)) < OPS_TOL
+    assert np.max(np.abs(Ea - want_a)) / np.max(np.abs(want_a)) < 1e-11
+    x = np.random.default_rng(1).standard_normal(P.model.N)
+    y = s.apply(fracture.FRACTURE_OP_DAMAGE_HESS, x)
+    want = P.model.damage_hessian(u, eps0) @ x
+    assert np.max(np.abs(y - want)) / np.max(np.abs(want)) < OPS_TOL
+    el, su = s.energy()
+    wel, wsu = P.model.energies(u, alpha, eps0)
+    assert abs(el - wel) / abs(wel) < OPS_TOL and abs(su - wsu) / abs(wsu) < OPS_TOL
+    s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_thermal_3d_load_path_parity(precision):
+    """A 32x8x4 slab under a growing thermal shock: AM load steps against the
+    oracle.  Here the heated layer (depth 0.05) is thinner than ell = 0.125, so
+    damage starts near 8 DT_c rather than at the thick-layer estimate DT_c."""
+    p = workloads.thermal(32, 8, 4, 1.0, 0.25, 0.125)
+    dtc = workloads.thermal_dtc(p)
+    loads = [2.0 * dtc, 8.5 * dtc, 10.0 * dtc]
+    print(f"[thermal3d] precision={precision} dtc={dtc:.3f}", flush=True)
+    s = _solver(p, None, precision=precision, am_tol=1e-10, pcg_rtol=1e-13, vi_cg_rtol=1e-13)
+    P = _problem3(p)
+    st = am.initial_state(P)
+    grew = False
+    for t in loads:
+        s.set_load(t)
+        stats = s.solve_step()
+        am.solve_load_step(P, st, t, am_tol=1e-10)
+        u, a, _ = s.state()
+        eu, ea = _rel(u, st.u), _rel(a, st.alpha)
+        print(f"  dT={t:.3f} sweeps={stats['sweeps']} pcg={stats['pcg_iters']} max_alpha={a.max():.3f} "
+              f"rel_u={eu:.2e} rel_a={ea:.2e}", flush=True)
+        assert eu < STEP_TOL
+        assert (ea < STEP_TOL) or (np.linalg.norm(st.alpha) == 0 and np.max(np.abs(a)) < 1e-12)
+        grew = grew or a.max() > 0.05
+    assert grew
+    s.close()

@@ -84,3 +84,20 @@ def test_every_gpu_test_shape_is_accepted():
     for nx, ny in [(8, 8), (16, 16), (32, 32), (48, 48), (64, 64), (96, 80), (64, 128), (2048, 2048)]:
         q = fracture.make_params(**workloads.tension(nx, 0.05, nx=nx, ny=ny))
         assert fracture.fracture_workspace_bytes(q) > 0, (nx, ny)
+
+
+def test_3d_shapes_and_validation():
+    from paper_1511_08463_amd import workloads as w
+    p, loads = w.config3()
+    q = fracture.make_params(**p)
+    assert fracture.fracture_workspace_bytes(q) > 0
+    n, d = fracture.fracture_sizes(q)
+    assert n == 129 * 129 * 33 and d == 3 * n
+    assert abs(w.thermal_dtc(p) - 2.049) < 1e-3 and len(loads) == 15
+    for shape in [(4, 4, 2), (12, 10, 6), (70, 4, 2), (32, 8, 4), (16, 8, 4)]:
+        q = fracture.make_params(**w.thermal(*shape))
+        assert fracture.fracture_workspace_bytes(q) > 0, shape
+    bad = fracture.make_params(**dict(w.thermal(16, 8, 4), newton=1))
+    assert fracture.fracture_workspace_bytes(bad) == 0
+    bad = fracture.make_params(**dict(w.thermal(16, 8, 4), load_kind=0))
+    assert fracture.fracture_workspace_bytes(bad) == 0
