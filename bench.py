@@ -79,7 +79,7 @@ def thermal(args):
     """Config 3: the 128x128x32 thermal-shock slab, FP64 or mixed, AM load steps."""
     import torch
     from paper_1511_08463_amd import fracture, workloads
-    p, loads = workloads.config3()
+    p, loads = workloads.config3(dt_max_factor=args.dt_factor)
     params = fracture.make_params(**p, am_tol=args.am_tol, pcg_rtol=args.pcg_rtol, max_am=2000,
                                   precision=fracture.FRACTURE_MIXED if args.precision == "mixed"
                                   else fracture.FRACTURE_FP64)
@@ -105,7 +105,7 @@ def thermal(args):
     solver.close()
     n = args.warmup + args.steps
     return {"workload": "128x128x32 hexes x 6 Kuhn tetrahedra, AT1, ell=4h, thermal eigenstrain "
-                        f"-DT exp(-x/0.05) I, DT_k=(k/15) 2 DT_c, k=1..{n}, AM to ||dalpha||inf<{args.am_tol:g}",
+                        f"-DT exp(-x/0.05) I, DT_k=(k/15) {args.dt_factor:g} DT_c, k=1..{n}, AM to ||dalpha||inf<{args.am_tol:g}",
             "precision": args.precision, "load_steps": n, "seconds": dt, "load_steps_per_s": n / dt,
             "sweeps": sum(s["sweeps"] for s in stats), "pcg_iters": sum(s["pcg_iters"] for s in stats),
             "kernels": rl}
@@ -130,6 +130,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="run only the served stream")
     ap.add_argument("--thermal", action="store_true", help="run only the 3D thermal slab (config 3)")
+    ap.add_argument("--dt-factor", type=float, default=16.0, help="thermal ramp end in units of DT_c")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream sample")
     ap.add_argument("--instances", type=int, default=48)
     ap.add_argument("--budget-gb", type=float, default=4.0)

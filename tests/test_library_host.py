@@ -94,6 +94,7 @@ def test_3d_shapes_and_validation():
     n, d = fracture.fracture_sizes(q)
     assert n == 129 * 129 * 33 and d == 3 * n
     assert abs(w.thermal_dtc(p) - 2.049) < 1e-3 and len(loads) == 15
+    assert abs(loads[-1] - 16 * w.thermal_dtc(p)) < 1e-12
     for shape in [(4, 4, 2), (12, 10, 6), (70, 4, 2), (32, 8, 4), (16, 8, 4)]:
         q = fracture.make_params(**w.thermal(*shape))
         assert fracture.fracture_workspace_bytes(q) > 0, shape
