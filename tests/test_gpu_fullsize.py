@@ -1,0 +1,129 @@
+"""Parity at the benchmark's full size (2048 x 2048, config 2) in the launch
+configuration bench.py times.  The oracle cannot assemble the whole problem
+in a test, so it computes sampled outputs one by one: each node's row of an
+operator involves only the elements around it, and the oracle assembles
+exactly those (a patch of at most 2 x 2 cells) with the same spacing and the
+same field values.  After converged load steps the first-order conditions
+(eq. (kkt)) are checked at sampled nodes the same way, together with the
+bounds at every node."""
+
+import numpy as np
+import pytest
+
+from oracle import fem, mesh, vi
+from paper_1511_08463_amd import fracture, workloads
+
+pytestmark = pytest.mark.gpu
+
+N_SIDE = 2048
+
+
+def _patch(i, j, n, h):
+    """Cells around node (i, j), clipped to the domain: (X, T, global ids, local id)."""
+    i0, i1 = max(i - 1, 0), min(i + 1, n)
+    j0, j1 = max(j - 1, 0), min(j + 1, n)
+    X, T = mesh.structured_mesh_2d(i1 - i0, j1 - j0, (i1 - i0) * h, (j1 - j0) * h)
+    X = X + np.array([i0 * h, j0 * h])
+    ii, jj = np.meshgrid(np.arange(i0, i1 + 1), np.arange(j0, j1 + 1), indexing="xy")
+    gid = (ii + (n + 1) * jj).ravel()
+    loc = (i - i0) + (i1 - i0 + 1) * (j - j0)
+    return X, T, gid, loc
+
+
+def _samples(n, rng, k=160):
+    pts = {(0, 0), (n, 0), (0, n), (n, n), (0, n // 2), (n, n // 2), (n // 2, 0), (n // 2, n)}
+    while len(pts) < k:
+        pts.add((int(rng.integers(0, n + 1)), int(rng.integers(0, n + 1))))
+    return sorted(pts)
+
+
+def _model(p, X, T):
+    return fem.Model(X, T, E=p["E"], nu=p["nu"], Gc=p["Gc"], ell=p["ell"], k_ell=p["k_ell"],
+                     model=p["model"])
+
+
+def test_full_size_operator_rows():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    p, notch, _, _ = workloads.config2()
+    n, h = N_SIDE, 1.0 / N_SIDE
+    params = fracture.make_params(**p, newton=1)
+    s = fracture.Fracture(params, notch, device="cuda:0")
+    N = s.N
+    rng = np.random.default_rng(12)
+    u = rng.standard_normal(2 * N) * 1e-3
+    alpha = rng.uniform(0, 1, N)
+    s.set_state(u=u, alpha=alpha, alpha_prev=np.zeros(N))
+    y = s.apply(fracture.FRACTURE_OP_ELASTICITY, u)
+    x = rng.standard_normal(N)
+    hx = s.apply(fracture.FRACTURE_OP_DAMAGE_HESS, x)
+    Eu, Ea = s.gradient()
+    worst = 0.0
+    for (i, j) in _samples(n, rng):
+        X, T, gid, loc = _patch(i, j, n, h)
+        M = _model(p, X, T)
+        up = np.concatenate([u[gid], u[N + gid]])
+        ap = alpha[gid]
+        m = len(gid)
+        row = M.K(ap) @ up
+        g = i + (n + 1) * j
+        want = np.array([row[loc], row[m + loc]])
+        got = np.array([y[g], y[N + g]])
+        scale = np.max(np.abs(M.K(ap).toarray()[[loc, m + loc]])) * np.max(np.abs(up))
+        worst = max(worst, np.max(np.abs(got - want)) / scale)
+        hrow = M.damage_hessian(up) @ x[gid]
+        assert abs(hx[g] - hrow[loc]) <= 1e-12 * max(1e-300, np.max(np.abs(M.damage_hessian(up).toarray()[loc])) * np.max(np.abs(x[gid])))
+        ga = M.grad_alpha(up, ap)
+        assert abs(Ea[g] - ga[loc]) <= 1e-11 * max(abs(ga[loc]), np.max(np.abs(M.damage_linear(up))), 1e-300)
+    assert worst < 1e-12, worst
+    s.close()
+
+
+def test_full_size_load_step_kkt():
+    """The first two bench load steps (ORAM-N): the bounds hold at every node
+    and, at sampled nodes, every component of the residual Phi (the free rows
+    of E_u and the box Fischer--Burmeister residual of the damage VI, as in
+    Algorithm 3) is within the reported ||Phi||_2."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    p, notch, loads, _ = workloads.config2()
+    n, h = N_SIDE, 1.0 / N_SIDE
+    params = fracture.make_params(**p, newton=1, pcg_rtol=1e-8, max_am=5000)
+    s = fracture.Fracture(params, notch, device="cuda:0")
+    for t in loads[:2]:
+        s.set_load(t)
+        st = s.solve_step()
+        print(f"[fullsize] t={t}: {st}", flush=True)
+        assert st["converged"]
+    u, a, ap = s.state()
+    N = s.N
+    assert np.all(a >= ap) and np.all(a <= 1.0) and np.all(a[notch.astype(bool)] == 1.0)
+    assert np.count_nonzero(a > 0.5) > np.count_nonzero(notch)   # damage is active
+    bound = st["phi_l2"] * (1 + 1e-6) + 1e-13
+    rng = np.random.default_rng(5)
+    rows, cols = notch.reshape(n + 1, n + 1).nonzero()
+    tip_i, tip_j = int(cols.max()), int(rows[0])
+    pts = _samples(n, rng, 120) + [(tip_i + di, tip_j + dj)
+                                   for di in range(-3, 12, 2) for dj in range(-10, 11, 2)]
+    for (i, j) in pts:
+        if not (0 <= i <= n and 0 <= j <= n):
+            continue
+        X, T, gid, loc = _patch(i, j, n, h)
+        M = _model(p, X, T)
+        up = np.concatenate([u[gid], u[N + gid]])
+        m = len(gid)
+        Eu = M.K(a[gid]) @ up
+        g = i + (n + 1) * j
+        # free rows: u_x everywhere except the pinned corner (0, 0);
+        # u_y except on the bottom and top edges
+        if not (i == 0 and j == 0):
+            assert abs(Eu[loc]) <= bound, (i, j, Eu[loc], bound)
+        if 0 < j < n:
+            assert abs(Eu[m + loc]) <= bound, (i, j, Eu[m + loc], bound)
+        Fa = M.grad_alpha(up, a[gid])[loc]
+        phi = vi.mcp_residual(np.array([a[g]]), np.array([Fa]), np.array([ap[g]]),
+                              np.array([1.0]))[0]
+        assert abs(phi) <= bound, (i, j, phi, a[g], Fa, bound)
+    s.close()
