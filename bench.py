@@ -126,6 +126,9 @@ def main():
     ap.add_argument("--final-tol", type=float, default=1e-7)
     ap.add_argument("--minres-rtol", type=float, default=1e-6)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--newton-vcycles", type=int, default=1,
+                    help="V-cycles per action of A^-1 in the Newton block preconditioner")
+    ap.add_argument("--no-graphs", action="store_true", help="launch eagerly (no HIP graph replay)")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="run only the served stream")
@@ -163,6 +166,8 @@ def main():
                                   vi_cg_rtol=1e-10, max_am=5000, newton=args.newton,
                                   switch_tol=args.switch_tol, final_tol=args.final_tol,
                                   minres_rtol=args.minres_rtol,
+                                  newton_vcycles=args.newton_vcycles,
+                                  use_graphs=0 if args.no_graphs else 1,
                                   precision=fracture.FRACTURE_MIXED if args.precision == "mixed"
                                   else fracture.FRACTURE_FP64)
     log(f"[bench] {args.precision} {args.n}^2 {args.model} omega={args.omega} notch y0={y0:.4f} a={a:.4f} "

@@ -99,6 +99,16 @@ typedef struct {
   int max_am, max_pcg, max_vi, max_vi_cg, max_newton, max_minres;
   int cheb_degree;          /* Chebyshev smoothing steps per V-cycle side      */
   int coarse_max_dofs;      /* coarsen until the level has at most this many   */
+  int newton_vcycles;       /* multigrid V-cycles per action of A^{-1} inside
+                               the Newton block preconditioner, 1 or 2.  The
+                               paper's setup (Sec. 3.3) uses two; the default
+                               is one, which costs fewer V-cycles per Newton
+                               solve on the structured meshes here.            */
+  int use_graphs;           /* 1: record the fixed launch sequences (V-cycle,
+                               block preconditioner) once per operand set and
+                               replay them as HIP graphs; 0: launch eagerly.
+                               Both run the same kernels in the same order,
+                               so results are bitwise identical.               */
 } fracture_params;
 
 /* Fill *p with the documented defaults for a 2D tension problem on an

@@ -36,6 +36,18 @@ constexpr int MAXLEV = 16;
 constexpr int DENSE_MAX = 1024;   // largest coarsest-level system inverted densely
 constexpr double ARMIJO_SIGMA = 1e-4;
 constexpr int MAX_HALVINGS = 20;
+constexpr int MAX_GRAPHS = 16;    // recorded launch sequences kept per instance
+
+// Launch sequences recorded once and replayed as HIP graphs.
+enum GraphOp { G_VCYCLE64 = 1, G_VCYCLE32 = 2, G_PRECOND = 3 };
+
+struct Captured {
+  int op;
+  const void* a;
+  const void* b;
+  void* out;               // result buffer of the sequence
+  hipGraphExec_t exec;
+};
 
 struct Level {
   Grid g;
@@ -106,6 +118,11 @@ struct fracture {
   fracture_monitor_fn monitor = nullptr;
   void* monitor_user = nullptr;
   bool coef_valid = false;
+  // recorded launch sequences: captured on a private stream, replayed on st
+  std::vector<Captured> graphs;
+  hipStream_t cap = nullptr;
+  bool capturing = false;
+  bool graph_error = false;
 };
 
 namespace {
@@ -141,6 +158,8 @@ int validate(const fracture_params* p) {
   if (p->newton && !(p->minres_rtol > 0 && p->max_minres >= 1 && p->max_newton >= 1)) return FRACTURE_EINVAL;
   if (p->max_am < 1 || p->max_pcg < 1 || p->max_vi < 1 || p->max_vi_cg < 1) return FRACTURE_EINVAL;
   if (p->cheb_degree < 1 || p->cheb_degree > 8) return FRACTURE_EINVAL;
+  if (p->newton_vcycles < 1 || p->newton_vcycles > 2) return FRACTURE_EINVAL;
+  if (p->use_graphs != 0 && p->use_graphs != 1) return FRACTURE_EINVAL;
   if ((int64_t)(p->nx + 1) * (p->ny + 1) * (p->dim == 3 ? p->nz + 1 : 1) > (int64_t)1 << 29)
     return FRACTURE_EINVAL;
   return FRACTURE_OK;
@@ -356,6 +375,7 @@ Red red(fracture* h, int cslot, int sslot, int post = P_STORE) {
 }
 
 int read_scalars(fracture* h) {
+  if (h->graph_error) return FRACTURE_EDEVICE;
   HIPCHK(hipMemcpyAsync(h->hS, h->S, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
   return FRACTURE_OK;
@@ -402,11 +422,12 @@ LevelBufs<float> bufs<float>(fracture* h, int l) {
   return {v.b32, v.xa32, v.xb32, v.d32, v.r32, l == 0 ? h->alpha32 : v.abar32};
 }
 
-// z = V-cycle(b) on level l; returns the buffer holding the result.  The
-// cycle is symmetric: pre- and post-smoothing apply the same Chebyshev
-// polynomial, so it is a fixed SPD preconditioner in exact arithmetic.
+// z = V-cycle(b) on level l; returns the buffer holding the result (final_out
+// when given: the last post-smoothing step writes there).  The cycle is
+// symmetric: pre- and post-smoothing apply the same Chebyshev polynomial, so
+// it is a fixed SPD preconditioner in exact arithmetic.
 template <class T>
-T* vcycle_t(fracture* h, int l, const T* b) {
+T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr) {
   LevelBufs<T> v = bufs<T>(h, l);
   const Grid& g = h->lv[l].g;
   const int k = h->p.cheb_degree;
@@ -436,6 +457,7 @@ T* vcycle_t(fracture* h, int l, const T* b) {
   // post-smoothing (same polynomial: the V-cycle is symmetric)
   for (int s = 0; s < k; ++s) {
     T* out = (cur == v.xa) ? v.xb : v.xa;
+    if (s == k - 1 && final_out) out = final_out;
     const T* din = s == 0 ? nullptr : v.d;
     T* dout = (s < k - 1) ? v.d : nullptr;
     launch_smooth2d<T>(h->st, g, h->mat, fine, v.coef, kell, cur, out, b, din, dout,
@@ -446,6 +468,62 @@ T* vcycle_t(fracture* h, int l, const T* b) {
 }
 
 double* vcycle(fracture* h, int l, const double* b) { return vcycle_t<double>(h, l, b); }
+
+// Runs body(), which launches on h->st and returns its result buffer.  With
+// use_graphs the first call for an operand set (op, a, b) records the
+// launches on the private stream h->cap as a HIP graph, later calls replay
+// it on h->st.  A recorded sequence holds kernel launches only: no memset or
+// copy node and no host synchronisation.  If recording fails the instance
+// stops using graphs and launches eagerly (the same kernels in the same
+// order).
+template <class F>
+void* graphed(fracture* h, int op, const void* a, const void* b, F&& body) {
+  if (!h->p.use_graphs || h->capturing) return body();
+  for (const Captured& c : h->graphs)
+    if (c.op == op && c.a == a && c.b == b) {
+      if (hipGraphLaunch(c.exec, h->st) != hipSuccess) h->graph_error = true;
+      return c.out;
+    }
+  if ((int)h->graphs.size() >= MAX_GRAPHS) return body();
+  if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) {
+    h->cap = nullptr;
+    h->p.use_graphs = 0;
+    return body();
+  }
+  if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    h->p.use_graphs = 0;
+    return body();
+  }
+  hipStream_t user = h->st;
+  h->st = h->cap;
+  h->capturing = true;
+  void* out = body();
+  h->st = user;
+  h->capturing = false;
+  hipGraph_t gr = nullptr;
+  hipGraphExec_t ex = nullptr;
+  bool ok = hipStreamEndCapture(h->cap, &gr) == hipSuccess && gr;
+  ok = ok && hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) == hipSuccess;
+  if (gr) (void)hipGraphDestroy(gr);
+  if (!ok) {
+    (void)hipGetLastError();
+    h->p.use_graphs = 0;
+    return body();
+  }
+  h->graphs.push_back({op, a, b, out, ex});
+  if (hipGraphLaunch(ex, h->st) != hipSuccess) h->graph_error = true;
+  return out;
+}
+
+// V-cycle on the finest level (recorded per right-hand side buffer).
+double* vcycle0(fracture* h, const double* b, double* final_out = nullptr) {
+  return (double*)graphed(h, G_VCYCLE64, b, final_out,
+                          [&] { return (void*)vcycle_t<double>(h, 0, b, final_out); });
+}
+
+float* vcycle0f(fracture* h, const float* b) {
+  return (float*)graphed(h, G_VCYCLE32, b, nullptr, [&] { return (void*)vcycle_t<float>(h, 0, b); });
+}
 
 // ---------------------------------------------------------------------------
 // elastic subproblem: x <- argmin at fixed alpha, warm start from u
@@ -465,7 +543,7 @@ int pcg(fracture* h, double tol, int* iters) {
   if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
   *iters = 0;
   if (std::sqrt(rr) <= tol) return FRACTURE_OK;
-  double* z = vcycle(h, 0, h->r);
+  double* z = vcycle0(h, h->r);
   launch_dot(st, n2, h->r, z, red(h, 1, S_RZ));
   HIPCHK(hipMemcpyAsync(h->pv, z, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
   for (int it = 1; it <= h->p.max_pcg; ++it) {
@@ -478,7 +556,7 @@ int pcg(fracture* h, double tol, int* iters) {
     *iters = it;
     if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
     if (std::sqrt(rr) <= tol) return FRACTURE_OK;
-    z = vcycle(h, 0, h->r);
+    z = vcycle0(h, h->r);
     launch_dot(st, n2, h->r, z, red(h, 4, S_RZNEW, P_CG_BETA));
     launch_xpby(st, n2, z, h->pv, h->S);
   }
@@ -513,11 +591,11 @@ int pcg_mixed(fracture* h, double tol, int* iters) {
     launch_to_float(st, n2, h->r, h->fr32, 1.0 / rn);
     HIPCHK(hipMemsetAsync(h->fe32, 0, n2 * sizeof(float), st));
     const double tin = std::fmax(MIXED_INNER_RTOL, 0.5 * tol / rn);
-    float* z = vcycle_t<float>(h, 0, h->fr32);
+    float* z = vcycle0f(h, h->fr32);
     HIPCHK(hipMemcpyAsync(h->fp32, z, n2 * sizeof(float), hipMemcpyDeviceToDevice, st));
     for (int it = 0;; ++it) {
       if (it > 0) {
-        z = vcycle_t<float>(h, 0, h->fr32);
+        z = vcycle0f(h, h->fr32);
         launch_dot_f(st, n2, z, h->fq32, red(h, 1, S_TMP0, P_FCG_BETA));
         launch_xpby_f(st, n2, z, h->fp32, h->S);
       }
@@ -727,17 +805,29 @@ int coupled_residual(fracture* h, const double* u, const double* a, double* Fu, 
   return std::isfinite(*phi2) ? FRACTURE_OK : FRACTURE_ENONFINITE;
 }
 
-// y = A^{-1} x approximated by two multigrid V-cycles (a fixed symmetric
-// positive definite operator, as MINRES needs).
+// y = A^{-1} x approximated by newton_vcycles multigrid V-cycles from zero
+// (the paper's preconditioner uses two): y = V x, then y += V (x - A y).
+// Either way a fixed symmetric positive definite operator, as MINRES needs.
+// In mixed precision the cycles run in float32 on the float32 copy of their
+// right-hand side (MINRES vectors are normalised, so no scaling is needed);
+// the residual between the cycles and y stay float64.
 void apply_Ainv(fracture* h, const double* x, double* y) {
   const Grid& g = h->lv[0].g;
   const int64_t n2 = h->n2;
-  double* z = vcycle(h, 0, x);
-  (void)hipMemcpyAsync(y, z, n2 * sizeof(double), hipMemcpyDeviceToDevice, h->st);
   Red none{};
+  if (h->mixed) {
+    launch_to_float(h->st, n2, x, h->fr32, 1.0);
+    launch_from_float(h->st, n2, vcycle0f(h, h->fr32), y, 1.0);
+    if (h->p.newton_vcycles == 1) return;
+    launch_resid2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, y, h->npu2, x, false, none);
+    launch_to_float(h->st, n2, h->npu2, h->fr32, 1.0);
+    launch_add_scaled_f(h->st, n2, y, vcycle0f(h, h->fr32), 1.0);
+    return;
+  }
+  vcycle0(h, x, y);
+  if (h->p.newton_vcycles == 1) return;
   launch_resid2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, y, h->npu2, x, false, none);
-  z = vcycle(h, 0, h->npu2);
-  launch_axpby(h->st, n2, 1.0, z, 1.0, y);
+  launch_axpby(h->st, n2, 1.0, vcycle0(h, h->npu2), 1.0, y);
 }
 
 // y = C^{-1} x approximated by CHEB_C Jacobi-Chebyshev steps on H_NN from 0.
@@ -758,7 +848,7 @@ void apply_Cinv(fracture* h, const double* x, double* y) {
 // Block preconditioner with S ~ C (eq. (preconditioner)), applied in the
 // symmetric multiplicative order: y1 = A^{-1} x1; y2 = C^{-1}(x2 - B^T y1);
 // z1 = A^{-1}(x1 - B y2); result [z1; y2].
-void apply_P(fracture* h, const double* x, double* y) {
+void apply_P_body(fracture* h, const double* x, double* y) {
   const Grid& g = h->lv[0].g;
   const int64_t n2 = h->n2, N = h->N;
   Red none{};
@@ -771,6 +861,13 @@ void apply_P(fracture* h, const double* x, double* y) {
                nullptr, y + n2, h->npu1, nullptr, false, none, none);      // B y2
   launch_axpby(h->st, n2, 1.0, x, -1.0, h->npu1);                          // x1 - B y2
   apply_Ainv(h, h->npu1, y);                                               // z1
+}
+
+void apply_P(fracture* h, const double* x, double* y) {
+  graphed(h, G_PRECOND, x, y, [&] {
+    apply_P_body(h, x, y);
+    return (void*)y;
+  });
 }
 
 // y = J x on the inactive coupled system; S[S_TMP0] + S[S_TMP1] = x.y.
@@ -806,13 +903,13 @@ int minres(fracture* h, int* iters) {
   const double g1 = g;
   double g_prev = 1.0, eta = g, s_prev = 0.0, s = 0.0, c_prev = 1.0, c = 1.0;
   for (int j = 1; j <= h->p.max_minres; ++j) {
-    launch_axpby(st, n3, 1.0 / g, z, 0.0, z);
-    apply_J(h, z, az);
+    // z holds z_j unnormalised (the normalised vector is z / g)
+    apply_J(h, z, az);                                           // az = J z, S = z.J z
     int rc = read_scalars(h);
     if (rc) return rc;
-    const double d = h->hS[S_TMP0] + h->hS[S_TMP1];
-    launch_axpby(st, n3, -d / g, v, 1.0, az);
-    launch_axpby(st, n3, -g / g_prev, v_prev, 1.0, az);          // az = v_{j+1}
+    const double d = (h->hS[S_TMP0] + h->hS[S_TMP1]) / (g * g);
+    // v_{j+1} = J z/g - (d/g) v_j - (g/g_prev) v_{j-1}, in az
+    launch_lincomb3(st, n3, 1.0 / g, az, -d / g, v, -g / g_prev, v_prev);
     double* vn = az;
     apply_P(h, vn, v_prev);                                      // v_prev buffer <- z_{j+1}
     double* zn = v_prev;
@@ -824,10 +921,9 @@ int minres(fracture* h, int* iters) {
     const double a2 = s * d + c_prev * c * g;
     const double a3 = s_prev * g;
     const double cn = a0 / a1, sn = gn / a1;
-    // w_{j+1} = (z_j - a3 w_{j-1} - a2 w_j) / a1, written into w_prev
-    launch_axpby(st, n3, 1.0 / a1, z, -a3 / a1, w_prev);
-    launch_axpby(st, n3, -a2 / a1, w, 1.0, w_prev);
-    launch_axpby(st, n3, cn * eta, w_prev, 1.0, h->nx);
+    // w_{j+1} = (z/g - a3 w_{j-1} - a2 w_j) / a1 into w_prev; x += cn eta w_{j+1}
+    launch_minres_update(st, n3, 1.0 / (a1 * g), z, -a3 / a1, w_prev, -a2 / a1, w, cn * eta,
+                         h->nx);
     eta = -sn * eta;
     // rotate buffers
     double* old_v = v;
@@ -1045,6 +1141,8 @@ void fracture_default_params(fracture_params* p, int nx, int ny) {
   p->max_minres = 500;
   p->cheb_degree = 2;
   p->coarse_max_dofs = 200;
+  p->newton_vcycles = 1;
+  p->use_graphs = 1;
 }
 
 size_t fracture_workspace_bytes(const fracture_params* p) {
@@ -1374,6 +1472,9 @@ const char* fracture_strerror(int code) {
 void fracture_destroy(fracture_t h) {
   if (!h) return;
   if (h->st) (void)hipStreamSynchronize(h->st);
+  for (Captured& c : h->graphs) (void)hipGraphExecDestroy(c.exec);
+  h->graphs.clear();
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   for (int k = 0; k < 8; ++k)
     if (h->ev[k]) (void)hipEventDestroy(h->ev[k]);
   if (h->hS) (void)hipHostFree(h->hS);

@@ -114,11 +114,46 @@ void launch_jacobi_dot(hipStream_t st, int64_t n, const double* r, const double*
 // y = a x + b y (host scalars)
 __global__ __launch_bounds__(VB) void k_axpby(int64_t n, double a, const double* __restrict__ x,
                                               double b, double* __restrict__ y) {
-  GRID_STRIDE(k, n) y[k] = a * x[k] + b * y[k];
+  // b == 0 overwrites y without reading it (y may hold anything, NaN included)
+  if (b == 0.0) {
+    GRID_STRIDE(k, n) y[k] = a * x[k];
+  } else {
+    GRID_STRIDE(k, n) y[k] = a * x[k] + b * y[k];
+  }
 }
 
 void launch_axpby(hipStream_t st, int64_t n, double a, const double* x, double b, double* y) {
   hipLaunchKernelGGL(k_axpby, dim3(vgrid(n)), dim3(VB), 0, st, n, a, x, b, y);
+}
+
+// z = a z + b x + c y
+__global__ __launch_bounds__(VB) void k_lincomb3(int64_t n, double a, double* __restrict__ z,
+                                                 double b, const double* __restrict__ x, double c,
+                                                 const double* __restrict__ y) {
+  GRID_STRIDE(k, n) z[k] = a * z[k] + b * x[k] + c * y[k];
+}
+
+void launch_lincomb3(hipStream_t st, int64_t n, double a, double* z, double b, const double* x,
+                     double c, const double* y) {
+  hipLaunchKernelGGL(k_lincomb3, dim3(vgrid(n)), dim3(VB), 0, st, n, a, z, b, x, c, y);
+}
+
+// MINRES direction and iterate: w2 = a z + b w2 + c w1; x += e w2
+__global__ __launch_bounds__(VB) void k_minres_update(int64_t n, double a,
+                                                      const double* __restrict__ z, double b,
+                                                      double* __restrict__ w2, double c,
+                                                      const double* __restrict__ w1, double e,
+                                                      double* __restrict__ x) {
+  GRID_STRIDE(k, n) {
+    const double wn = a * z[k] + b * w2[k] + c * w1[k];
+    w2[k] = wn;
+    x[k] += e * wn;
+  }
+}
+
+void launch_minres_update(hipStream_t st, int64_t n, double a, const double* z, double b,
+                          double* w2, double c, const double* w1, double e, double* x) {
+  hipLaunchKernelGGL(k_minres_update, dim3(vgrid(n)), dim3(VB), 0, st, n, a, z, b, w2, c, w1, e, x);
 }
 
 // S[slot] = ||x||^2 or max|x| (NaN -> inf)
@@ -368,6 +403,16 @@ __global__ __launch_bounds__(VB) void k_add_scaled_f(int64_t n, double* __restri
 
 void launch_add_scaled_f(hipStream_t st, int64_t n, double* x, const float* e, double scale) {
   hipLaunchKernelGGL(k_add_scaled_f, dim3(vgrid(n)), dim3(VB), 0, st, n, x, e, scale);
+}
+
+// x = scale * e
+__global__ __launch_bounds__(VB) void k_from_float(int64_t n, const float* __restrict__ e,
+                                                   double* __restrict__ x, double scale) {
+  GRID_STRIDE(k, n) x[k] = scale * (double)e[k];
+}
+
+void launch_from_float(hipStream_t st, int64_t n, const float* e, double* x, double scale) {
+  hipLaunchKernelGGL(k_from_float, dim3(vgrid(n)), dim3(VB), 0, st, n, e, x, scale);
 }
 
 }  // namespace frac

@@ -265,6 +265,33 @@ def test_bitwise_reproducible():
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("precision", [fracture.FRACTURE_FP64, fracture.FRACTURE_MIXED])
+def test_graph_replay_equals_eager(precision):
+    """Recorded launch sequences (V-cycles, block preconditioner) replayed as
+    HIP graphs, many times with eager work and host reads in between, give
+    bitwise the same load path as eager launches."""
+    p = workloads.tension(96, 0.06, "AT1", nx=96, ny=80)
+    notch = workloads.notch_mask_2d(96, 80, 0.5, 0.25)
+    print(f"[graphs] precision={precision}", flush=True)
+    runs = []
+    for graphs in (0, 1):
+        s = _solver(p, notch, precision=precision, newton=1, final_tol=1e-9, minres_rtol=1e-8,
+                    max_newton=20, use_graphs=graphs)
+        stats = []
+        for t in (0.3, 0.8, 1.0):
+            s.set_load(t)
+            stats.append(s.solve_step())
+        runs.append((s.state(), stats))
+        s.close()
+    (st0, stats0), (st1, stats1) = runs
+    assert sum(x["minres_iters"] for x in stats1) > 0 and sum(x["pcg_iters"] for x in stats1) > 0
+    for a, b in zip(st0, st1):
+        assert np.array_equal(a, b)
+    for a, b in zip(stats0, stats1):
+        for k in ("sweeps", "pcg_iters", "vi_iters", "newton_iters", "minres_iters"):
+            assert a[k] == b[k], (k, a[k], b[k])
+
+
 # ----------------------------------------------------------------------------- Newton composition
 
 def test_coupling_blocks_match_assembled():
@@ -290,16 +317,18 @@ def test_coupling_blocks_match_assembled():
     s.close()
 
 
-@pytest.mark.parametrize("omega", [1.0, 1.4])
-def test_oram_newton_parity(omega):
+@pytest.mark.parametrize("omega,vcycles", [(1.0, 2), (1.4, 2), (1.0, 1)])
+def test_oram_newton_parity(omega, vcycles):
     """ORAM-N (Algorithm 3) to ||Phi||_2 <= 1e-9 against the oracle's ORAM-N
-    (exact LU Newton steps) on a growing crack: same converged state."""
+    (exact LU Newton steps) on a growing crack: same converged state, with
+    one or two V-cycles per action of A^{-1} in the block preconditioner."""
     n = 48
     p, notch, _ = workloads.small_tension(n, "AT1", ell=0.08)
-    print(f"[oram-n] omega={omega}", flush=True)
+    print(f"[oram-n] omega={omega} vcycles={vcycles}", flush=True)
     loads = [0.3, 0.9]
     s = _solver(p, notch, omega=omega, newton=1, switch_tol=1e-3, final_tol=1e-9,
-                pcg_rtol=1e-12, vi_cg_rtol=1e-12, minres_rtol=1e-8, max_newton=20)
+                pcg_rtol=1e-12, vi_cg_rtol=1e-12, minres_rtol=1e-8, max_newton=20,
+                newton_vcycles=vcycles)
     P = _problem(p)
     st = am.initial_state(P, notch.astype(bool))
     total_newton = 0
