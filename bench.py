@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--newton-vcycles", type=int, default=1,
                     help="V-cycles per action of A^-1 in the Newton block preconditioner")
     ap.add_argument("--no-graphs", action="store_true", help="launch eagerly (no HIP graph replay)")
+    ap.add_argument("--newton-forcing", type=float, default=0.1,
+                    help="adaptive Newton forcing factor (0: fixed --minres-rtol)")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="run only the served stream")
@@ -167,6 +169,7 @@ def main():
                                   switch_tol=args.switch_tol, final_tol=args.final_tol,
                                   minres_rtol=args.minres_rtol,
                                   newton_vcycles=args.newton_vcycles,
+                                  newton_forcing=args.newton_forcing,
                                   use_graphs=0 if args.no_graphs else 1,
                                   precision=fracture.FRACTURE_MIXED if args.precision == "mixed"
                                   else fracture.FRACTURE_FP64)

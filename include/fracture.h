@@ -104,6 +104,13 @@ typedef struct {
                                paper's setup (Sec. 3.3) uses two; the default
                                is one, which costs fewer V-cycles per Newton
                                solve on the structured meshes here.            */
+  double newton_forcing;    /* > 0: each Newton system is solved to the
+                               relative tolerance max(minres_rtol,
+                               min(0.1, newton_forcing * final_tol / ||Phi||)),
+                               just enough for the step to reach final_tol
+                               (the adaptive forcing the paper recommends for
+                               practical use, Sec. 5.3); 0: always
+                               minres_rtol, as in the paper's experiments     */
   int use_graphs;           /* 1: record the fixed launch sequences (V-cycle,
                                block preconditioner) once per operand set and
                                replay them as HIP graphs; 0: launch eagerly.

@@ -26,6 +26,48 @@ namespace frac {
 enum { M_APPLY = 0, M_RESID = 1, M_SMOOTH = 2 };
 enum { R_NONE = 0, R_DOT = 1, R_FREE2 = 2 };
 
+// Output of a node kernel at node (i, j) from the node's force (fx, fy) = K x,
+// diagonal (dx, dy) and iterate (xc, yc); acc collects the optional reduction.
+template <int MODE, int RED, class T>
+__device__ __forceinline__ void node_out2d(const Grid& g, int i, int j, T fx, T fy, T dx, T dy,
+                                           T xc, T yc, T* __restrict__ y,
+                                           const T* __restrict__ b, const T* __restrict__ din,
+                                           T* __restrict__ dout, T cd, T cr, int mask,
+                                           double& acc) {
+  const int N = g.N, n = i + (g.nx + 1) * j;
+  const bool fxd = fixed_x2(g, i, j), fyd = fixed_y2(g, i, j);
+  if (MODE == M_APPLY) {
+    const T yx = (mask && fxd) ? T(0) : fx;
+    const T yy = (mask && fyd) ? T(0) : fy;
+    y[n] = yx;
+    y[n + N] = yy;
+    if (RED == R_DOT) acc += (double)xc * yx + (double)yc * yy;
+    if (RED == R_FREE2) {
+      const double rx = (double)fx - (b ? (double)b[n] : 0.0);
+      const double ry = (double)fy - (b ? (double)b[n + N] : 0.0);
+      acc += (fxd ? 0.0 : rx * rx) + (fyd ? 0.0 : ry * ry);
+    }
+  } else if (MODE == M_RESID) {
+    const T rx = fxd ? T(0) : (b ? b[n] : T(0)) - fx;
+    const T ry = fyd ? T(0) : (b ? b[n + N] : T(0)) - fy;
+    y[n] = rx;
+    y[n + N] = ry;
+    if (RED == R_DOT) acc += (double)rx * rx + (double)ry * ry;
+  } else {
+    const T rx = (b ? b[n] : T(0)) - fx, ry = (b ? b[n + N] : T(0)) - fy;
+    T ddx = cr * rx / dx, ddy = cr * ry / dy;
+    if (din) { ddx += cd * din[n]; ddy += cd * din[n + N]; }
+    T xo = xc + ddx, yo = yc + ddy;
+    if (fxd) { xo = T(0); ddx = T(0); }
+    if (fyd) { yo = T(0); ddy = T(0); }
+    y[n] = xo;
+    y[n + N] = yo;
+    if (dout) { dout[n] = ddx; dout[n + N] = ddy; }
+  }
+}
+
+// One thread per node (64 x NB_Y threads per tile): the short dependency
+// chain suits the small, latency-bound multigrid levels.
 template <int MODE, bool FA, bool HASX, int RED, class T>
 __global__ __launch_bounds__(NB) void k_node2d(Grid g, Mat m, const T* __restrict__ coef, T kell,
                                                const T* __restrict__ x, T* __restrict__ y,
@@ -40,40 +82,41 @@ __global__ __launch_bounds__(NB) void k_node2d(Grid g, Mat m, const T* __restric
     coef6<FA>(g, coef, kell, i, j, c);
     T fx, fy, dx, dy;
     node_force2d<HASX, MODE == M_SMOOTH>(g, m, c, x, x + N, i, j, fx, fy, dx, dy);
-    const bool fxd = fixed_x2(g, i, j), fyd = fixed_y2(g, i, j);
-    if (MODE == M_APPLY) {
-      const T yx = (mask && fxd) ? T(0) : fx;
-      const T yy = (mask && fyd) ? T(0) : fy;
-      y[n] = yx;
-      y[n + N] = yy;
-      if (RED == R_DOT) acc = (double)x[n] * yx + (double)x[n + N] * yy;
-      if (RED == R_FREE2) {
-        const double rx = (double)fx - (b ? (double)b[n] : 0.0);
-        const double ry = (double)fy - (b ? (double)b[n + N] : 0.0);
-        acc = (fxd ? 0.0 : rx * rx) + (fyd ? 0.0 : ry * ry);
-      }
-    } else if (MODE == M_RESID) {
-      const T rx = fxd ? T(0) : (b ? b[n] : T(0)) - fx;
-      const T ry = fyd ? T(0) : (b ? b[n + N] : T(0)) - fy;
-      y[n] = rx;
-      y[n + N] = ry;
-      if (RED == R_DOT) acc = (double)rx * rx + (double)ry * ry;
-    } else {
-      const T rx = (b ? b[n] : T(0)) - fx, ry = (b ? b[n + N] : T(0)) - fy;
-      T ddx = cr * rx / dx, ddy = cr * ry / dy;
-      if (din) { ddx += cd * din[n]; ddy += cd * din[n + N]; }
-      T xo = (HASX ? x[n] : T(0)) + ddx, yo = (HASX ? x[n + N] : T(0)) + ddy;
-      if (fxd) { xo = T(0); ddx = T(0); }
-      if (fyd) { yo = T(0); ddy = T(0); }
-      y[n] = xo;
-      y[n + N] = yo;
-      if (dout) { dout[n] = ddx; dout[n + N] = ddy; }
-    }
+    const T xc = HASX ? x[n] : T(0), yc = HASX ? x[n + N] : T(0);
+    node_out2d<MODE, RED>(g, i, j, fx, fy, dx, dy, xc, yc, y, b, din, dout, cd, cr, mask, acc);
   }
   if (RED != R_NONE)
     block_reduce<NB, false>(acc, red, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
                             threadIdx.x + NB_X * threadIdx.y);
 }
+
+// One wavefront per 64 x NB_Y tile, thread i walking the tile's column
+// (column2d): each element stress is formed once per thread and each row is
+// loaded once, which pays on the large levels.  Same tiles and block count as
+// k_node2d.
+template <int MODE, bool FA, bool HASX, int RED, class T>
+__global__ __launch_bounds__(NB_X) void k_col2d(Grid g, Mat m, const T* __restrict__ coef, T kell,
+                                                const T* __restrict__ x, T* __restrict__ y,
+                                                const T* __restrict__ b, const T* __restrict__ din,
+                                                T* __restrict__ dout, T cd, T cr, int mask, Red red) {
+  const int i = blockIdx.x * NB_X + threadIdx.x;
+  const int j0 = blockIdx.y * NB_Y;
+  double acc = 0.0;
+  if (i <= g.nx) {
+    column2d<FA, HASX, MODE == M_SMOOTH>(
+        g, m, coef, kell, x, i, j0, [&](int j, T fx, T fy, T dx, T dy, T xc, T yc) {
+          node_out2d<MODE, RED>(g, i, j, fx, fy, dx, dy, xc, yc, y, b, din, dout, cd, cr, mask, acc);
+        });
+  }
+  if (RED != R_NONE)
+    block_reduce<NB_X, false>(acc, red, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
+                              threadIdx.x);
+}
+
+// Levels with at least this many nodes use the column-blocked kernels.
+constexpr int64_t COL_MIN_NODES = (int64_t)1 << 21;
+
+static bool use_col2d(const Grid& g) { return (int64_t)(g.nx + 1) * (g.ny + 1) >= COL_MIN_NODES; }
 
 static dim3 node_grid2(const Grid& g) {
   return dim3((g.nx + 1 + NB_X - 1) / NB_X, (g.ny + 1 + NB_Y - 1) / NB_Y);
@@ -92,11 +135,18 @@ template <class T>
 void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
                     double kell, const T* x, T* y, const ND<T>* b, int mask, int red, Red r) {
   if (g.dim == 3) return launch_apply3d<T>(st, g, m, fine, coef, kell, x, y, b, mask, red, r);
-  dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
+  dim3 gr = node_grid2(g);
+  const bool col = use_col2d(g);
   const T k = T(kell);
-#define APPLY_CASE(FA, RD) \
-  hipLaunchKernelGGL((k_node2d<M_APPLY, FA, true, RD, T>), gr, bl, 0, st, g, m, coef, k, x, y, b, \
-                     (const T*)nullptr, (T*)nullptr, T(0), T(0), mask, r)
+#define APPLY_CASE(FA, RD)                                                                      \
+  do {                                                                                          \
+  if (col)                                                                                      \
+    hipLaunchKernelGGL((k_col2d<M_APPLY, FA, true, RD, T>), gr, dim3(NB_X), 0, st, g, m, coef, k, \
+                       x, y, b, (const T*)nullptr, (T*)nullptr, T(0), T(0), mask, r);          \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_node2d<M_APPLY, FA, true, RD, T>), gr, dim3(NB_X, NB_Y), 0, st, g, m, \
+                       coef, k, x, y, b, (const T*)nullptr, (T*)nullptr, T(0), T(0), mask, r); \
+  } while (0)
   if (fine) {
     if (red == R_NONE) APPLY_CASE(true, R_NONE);
     else if (red == R_DOT) APPLY_CASE(true, R_DOT);
@@ -115,11 +165,18 @@ template <class T>
 void launch_resid2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
                     double kell, const T* x, T* r, const ND<T>* b, bool red, Red rr) {
   if (g.dim == 3) return launch_resid3d<T>(st, g, m, fine, coef, kell, x, r, b, red, rr);
-  dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
+  dim3 gr = node_grid2(g);
+  const bool col = use_col2d(g);
   const T k = T(kell);
-#define RES_CASE(FA, RD) \
-  hipLaunchKernelGGL((k_node2d<M_RESID, FA, true, RD, T>), gr, bl, 0, st, g, m, coef, k, x, r, b, \
-                     (const T*)nullptr, (T*)nullptr, T(0), T(0), 1, rr)
+#define RES_CASE(FA, RD)                                                                        \
+  do {                                                                                          \
+  if (col)                                                                                      \
+    hipLaunchKernelGGL((k_col2d<M_RESID, FA, true, RD, T>), gr, dim3(NB_X), 0, st, g, m, coef, k, \
+                       x, r, b, (const T*)nullptr, (T*)nullptr, T(0), T(0), 1, rr);            \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_node2d<M_RESID, FA, true, RD, T>), gr, dim3(NB_X, NB_Y), 0, st, g, m, \
+                       coef, k, x, r, b, (const T*)nullptr, (T*)nullptr, T(0), T(0), 1, rr); \
+  } while (0)
   if (fine) {
     if (red) RES_CASE(true, R_DOT); else RES_CASE(true, R_NONE);
   } else {
@@ -138,12 +195,19 @@ void launch_smooth2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, con
                      double cd, double cr) {
   if (g.dim == 3)
     return launch_smooth3d<T>(st, g, m, fine, coef, kell, x_in, x_out, b, d_in, d_out, cd, cr);
-  dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
+  dim3 gr = node_grid2(g);
+  const bool col = use_col2d(g);
   Red none{};
   const T k = T(kell);
-#define SM_CASE(FA, HX) \
-  hipLaunchKernelGGL((k_node2d<M_SMOOTH, FA, HX, R_NONE, T>), gr, bl, 0, st, g, m, coef, k, x_in, \
-                     x_out, b, d_in, d_out, T(cd), T(cr), 1, none)
+#define SM_CASE(FA, HX)                                                                          \
+  do {                                                                                          \
+  if (col)                                                                                       \
+    hipLaunchKernelGGL((k_col2d<M_SMOOTH, FA, HX, R_NONE, T>), gr, dim3(NB_X), 0, st, g, m, coef, \
+                       k, x_in, x_out, b, d_in, d_out, T(cd), T(cr), 1, none);                  \
+  else                                                                                           \
+    hipLaunchKernelGGL((k_node2d<M_SMOOTH, FA, HX, R_NONE, T>), gr, dim3(NB_X, NB_Y), 0, st, g, m, \
+                       coef, k, x_in, x_out, b, d_in, d_out, T(cd), T(cr), 1, none); \
+  } while (0)
   if (fine) {
     if (x_in) SM_CASE(true, true); else SM_CASE(true, false);
   } else {

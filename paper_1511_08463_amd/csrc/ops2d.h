@@ -1,5 +1,6 @@
-// Per-node device code of the 2D operator (right-diagonal P1 triangles),
-// shared by the stencil kernels and the fused coarse-level kernel.
+// Device code of the 2D operator (right-diagonal P1 triangles) shared by the
+// stencil kernels: per-node forms (coupled Jacobian rows) and the
+// column-blocked form (elasticity apply, residual, Chebyshev smoothing).
 #pragma once
 
 #include "common.h"
@@ -160,45 +161,129 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
 }
 
 // ---------------------------------------------------------------------------
-// per-node multigrid updates (one node (i, j) of level g)
+// column-blocked operator: one thread walks NB_Y consecutive nodes of a grid
+// column, so that every element stress is formed once per thread and each
+// grid row is loaded once (a sliding window of two rows in registers).
 // ---------------------------------------------------------------------------
 
-// One Jacobi-Chebyshev step at a node: d = cd d_in + cr D^{-1}(b - K x_in),
-// x_out = x_in + d (x_in == nullptr: zero iterate).  FA: coefficients from
-// nodal alpha.
-template <bool FA, class T>
-__device__ __forceinline__ void smooth_node2d(const Grid& g, const Mat& m, const T* __restrict__ coef,
-                                              T kell, const T* __restrict__ x_in,
-                                              T* __restrict__ x_out, const T* __restrict__ b,
-                                              const T* __restrict__ d_in, T* __restrict__ d_out,
-                                              T cd, T cr, int i, int j) {
-  const int N = g.N, n = i + (g.nx + 1) * j;
-  T c[6];
-  coef6<FA>(g, coef, kell, i, j, c);
-  T fx = 0, fy = 0, dx, dy;
-  if (x_in) node_force2d<true, true>(g, m, c, x_in, x_in + N, i, j, fx, fy, dx, dy);
-  else node_force2d<false, true>(g, m, c, x_in, x_in, i, j, fx, fy, dx, dy);
-  T ddx = cr * (b[n] - fx) / dx, ddy = cr * (b[n + N] - fy) / dy;
-  if (d_in) { ddx += cd * d_in[n]; ddy += cd * d_in[n + N]; }
-  T xo = (x_in ? x_in[n] : T(0)) + ddx, yo = (x_in ? x_in[n + N] : T(0)) + ddy;
-  if (fixed_x2(g, i, j)) { xo = T(0); ddx = T(0); }
-  if (fixed_y2(g, i, j)) { yo = T(0); ddy = T(0); }
-  x_out[n] = xo;
-  x_out[n + N] = yo;
-  if (d_out) { d_out[n] = ddx; d_out[n + N] = ddy; }
+// Nodal values of grid row r at columns i-1, i, i+1 (zero outside the grid):
+// displacement components and, on the finest level, alpha.
+template <class T>
+struct Row3 {
+  T ux[3], uy[3], a[3];
+};
+
+template <bool FA, bool HASX, class T>
+__device__ __forceinline__ void load_row3(const Grid& g, const T* __restrict__ x,
+                                          const T* __restrict__ coef, int i, int r, Row3<T>& R) {
+  const int W = g.nx + 1, N = g.N;
+  const bool ok = r >= 0 && r <= g.ny;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int ii = i - 1 + k;
+    const bool in = ok && ii >= 0 && ii <= g.nx;
+    const int n = ii + W * r;
+    R.ux[k] = (HASX && in) ? x[n] : T(0);
+    R.uy[k] = (HASX && in) ? x[n + N] : T(0);
+    R.a[k] = (FA && in) ? coef[n] : T(0);
+  }
 }
 
-template <bool FA, class T>
-__device__ __forceinline__ void resid_node2d(const Grid& g, const Mat& m, const T* __restrict__ coef,
-                                             T kell, const T* __restrict__ x, T* __restrict__ r,
-                                             const T* __restrict__ b, int i, int j) {
-  const int N = g.N, n = i + (g.nx + 1) * j;
-  T c[6];
-  coef6<FA>(g, coef, kell, i, j, c);
-  T fx, fy, dx, dy;
-  node_force2d<true, false>(g, m, c, x, x + N, i, j, fx, fy, dx, dy);
-  r[n] = fixed_x2(g, i, j) ? T(0) : b[n] - fx;
-  r[n + N] = fixed_y2(g, i, j) ? T(0) : b[n + N] - fy;
+// Forces (K x) and, when DIAG, diagonal entries of K at nodes (i, j) for
+// j = j0 .. min(j0 + NB_Y - 1, ny); fin(j, fx, fy, dx, dy, x_x, x_y) receives
+// each node's values (x_x, x_y: x at the node, zero without HASX).
+// The cells of row cj left and right of the column, L = (i-1, cj) and
+// C = (i, cj), hold the four triangles the column's nodes share:
+//   L.T0 = [(i-1,cj), (i,cj), (i,cj+1)]      -> node (i,cj) as vertex 1, (i,cj+1) as vertex 2
+//   L.T1 = [(i-1,cj), (i,cj+1), (i-1,cj+1)]  -> node (i,cj+1) as vertex 1
+//   C.T0 = [(i,cj), (i+1,cj), (i+1,cj+1)]    -> node (i,cj) as vertex 0
+//   C.T1 = [(i,cj), (i+1,cj+1), (i,cj+1)]    -> node (i,cj) as vertex 0, (i,cj+1) as vertex 2
+// (the six triangles around a node are the three above it in cell row j and
+// the three below it in cell row j-1).  Precondition: 0 <= i <= nx,
+// 0 <= j0 <= ny.
+template <bool FA, bool HASX, bool DIAG, class T, class Fin>
+__device__ __forceinline__ void column2d(const Grid& g, const Mat& m, const T* __restrict__ coef,
+                                         T kell, const T* __restrict__ x, int i, int j0,
+                                         Fin&& fin) {
+  const T ihx = T(1.0 / g.hx), ihy = T(1.0 / g.hy), area = T(0.5 * g.hx * g.hy);
+  const T l2m = T(m.l2m), lam = T(m.lam), mu = T(m.mu);
+  const T hxx = ihx * ihx, hyy = ihy * ihy;
+  const bool hasL = i >= 1, hasC = i < g.nx;
+  const int nx = g.nx;
+  Row3<T> lo, hi;
+  load_row3<FA, HASX>(g, x, coef, i, j0 - 1, lo);
+  T fcx = 0, fcy = 0, dcx = 0, dcy = 0;   // node (i, cj)
+  T fnx = 0, fny = 0, dnx = 0, dny = 0;   // node (i, cj + 1)
+#pragma unroll
+  for (int s = 0; s <= NB_Y; ++s) {
+    const int cj = j0 - 1 + s;
+    if (cj > g.ny) break;
+    load_row3<FA, HASX>(g, x, coef, i, cj + 1, hi);
+    if (cj >= 0 && cj < g.ny) {
+      if (hasL) {
+        const T wl0 = area * (FA ? abar3(lo.a[0], lo.a[1], hi.a[1], kell) : coef[2 * (i - 1 + nx * cj)]);
+        const T wl1 = area * (FA ? abar3(lo.a[0], hi.a[1], hi.a[0], kell) : coef[2 * (i - 1 + nx * cj) + 1]);
+        T sxx = 0, syy = 0, sxy = 0, txx = 0, txy = 0;
+        if (HASX) {
+          // L.T0 strain: grads (-1/hx, 0), (1/hx, -1/hy), (0, 1/hy)
+          const T exx = (lo.ux[1] - lo.ux[0]) * ihx, eyy = (hi.uy[1] - lo.uy[1]) * ihy;
+          const T gam = (hi.ux[1] - lo.ux[1]) * ihy + (lo.uy[1] - lo.uy[0]) * ihx;
+          sxx = l2m * exx + lam * eyy; syy = lam * exx + l2m * eyy; sxy = mu * gam;
+          // L.T1 strain: grads (0, -1/hy), (1/hx, 0), (-1/hx, 1/hy)
+          const T fxx = (hi.ux[1] - hi.ux[0]) * ihx, fyy = (hi.uy[0] - lo.uy[0]) * ihy;
+          const T fam = (hi.ux[0] - lo.ux[0]) * ihy + (hi.uy[1] - hi.uy[0]) * ihx;
+          txx = l2m * fxx + lam * fyy; txy = mu * fam;
+        }
+        // L.T0 -> (i,cj) vertex 1 (1/hx, -1/hy); (i,cj+1) vertex 2 (0, 1/hy)
+        fcx += wl0 * (sxx * ihx - sxy * ihy);
+        fcy += wl0 * (sxy * ihx - syy * ihy);
+        fnx += wl0 * (sxy * ihy);
+        fny += wl0 * (syy * ihy);
+        // L.T1 -> (i,cj+1) vertex 1 (1/hx, 0)
+        fnx += wl1 * (txx * ihx);
+        fny += wl1 * (txy * ihx);
+        if (DIAG) {
+          dcx += wl0 * (l2m * hxx + mu * hyy);
+          dcy += wl0 * (l2m * hyy + mu * hxx);
+          dnx += wl0 * mu * hyy + wl1 * l2m * hxx;
+          dny += wl0 * l2m * hyy + wl1 * mu * hxx;
+        }
+      }
+      if (hasC) {
+        const T wc0 = area * (FA ? abar3(lo.a[1], lo.a[2], hi.a[2], kell) : coef[2 * (i + nx * cj)]);
+        const T wc1 = area * (FA ? abar3(lo.a[1], hi.a[2], hi.a[1], kell) : coef[2 * (i + nx * cj) + 1]);
+        T sxx = 0, sxy = 0, txx = 0, tyy = 0, txy = 0;
+        if (HASX) {
+          // C.T0 strain
+          const T exx = (lo.ux[2] - lo.ux[1]) * ihx, eyy = (hi.uy[2] - lo.uy[2]) * ihy;
+          const T gam = (hi.ux[2] - lo.ux[2]) * ihy + (lo.uy[2] - lo.uy[1]) * ihx;
+          sxx = l2m * exx + lam * eyy; sxy = mu * gam;
+          // C.T1 strain
+          const T fxx = (hi.ux[2] - hi.ux[1]) * ihx, fyy = (hi.uy[1] - lo.uy[1]) * ihy;
+          const T fam = (hi.ux[1] - lo.ux[1]) * ihy + (hi.uy[2] - hi.uy[1]) * ihx;
+          txx = l2m * fxx + lam * fyy; tyy = lam * fxx + l2m * fyy; txy = mu * fam;
+        }
+        // C.T0 -> (i,cj) vertex 0 (-1/hx, 0)
+        fcx -= wc0 * (sxx * ihx);
+        fcy -= wc0 * (sxy * ihx);
+        // C.T1 -> (i,cj) vertex 0 (0, -1/hy); (i,cj+1) vertex 2 (-1/hx, 1/hy)
+        fcx -= wc1 * (txy * ihy);
+        fcy -= wc1 * (tyy * ihy);
+        fnx += wc1 * (txy * ihy - txx * ihx);
+        fny += wc1 * (tyy * ihy - txy * ihx);
+        if (DIAG) {
+          dcx += wc0 * l2m * hxx + wc1 * mu * hyy;
+          dcy += wc0 * mu * hxx + wc1 * l2m * hyy;
+          dnx += wc1 * (l2m * hxx + mu * hyy);
+          dny += wc1 * (l2m * hyy + mu * hxx);
+        }
+      }
+    }
+    if (s >= 1) fin(cj, fcx, fcy, dcx, dcy, lo.ux[1], lo.uy[1]);
+    fcx = fnx; fcy = fny; dcx = dnx; dcy = dny;
+    fnx = fny = dnx = dny = T(0);
+    lo = hi;
+  }
 }
 
 // b_c(I,J) = (P^T r_f)(I,J): the coincident fine node plus half of the six

@@ -36,7 +36,8 @@ constexpr int MAXLEV = 16;
 constexpr int DENSE_MAX = 1024;   // largest coarsest-level system inverted densely
 constexpr double ARMIJO_SIGMA = 1e-4;
 constexpr int MAX_HALVINGS = 20;
-constexpr int MAX_GRAPHS = 16;    // recorded launch sequences kept per instance
+constexpr int MAX_GRAPHS = 16;
+constexpr double NEWTON_ETA_MAX = 0.1;   // loosest Newton forcing term    // recorded launch sequences kept per instance
 
 // Launch sequences recorded once and replayed as HIP graphs.
 enum GraphOp { G_VCYCLE64 = 1, G_VCYCLE32 = 2, G_PRECOND = 3 };
@@ -160,6 +161,7 @@ int validate(const fracture_params* p) {
   if (p->cheb_degree < 1 || p->cheb_degree > 8) return FRACTURE_EINVAL;
   if (p->newton_vcycles < 1 || p->newton_vcycles > 2) return FRACTURE_EINVAL;
   if (p->use_graphs != 0 && p->use_graphs != 1) return FRACTURE_EINVAL;
+  if (!(p->newton_forcing >= 0)) return FRACTURE_EINVAL;
   if ((int64_t)(p->nx + 1) * (p->ny + 1) * (p->dim == 3 ? p->nz + 1 : 1) > (int64_t)1 << 29)
     return FRACTURE_EINVAL;
   return FRACTURE_OK;
@@ -886,7 +888,7 @@ double dot3(fracture* h, const double* a, const double* b) {
 
 // MINRES (preconditioned; the three-term Lanczos recurrence with Givens
 // rotations) for J d = rhs, rhs in nv.  Solution in nx.
-int minres(fracture* h, int* iters) {
+int minres(fracture* h, double rtol, int* iters) {
   hipStream_t st = h->st;
   const int64_t n3 = 3 * h->N;
   HIPCHK(hipMemsetAsync(h->nx, 0, n3 * sizeof(double), st));
@@ -936,7 +938,7 @@ int minres(fracture* h, int* iters) {
     c_prev = c; c = cn;
     s_prev = s; s = sn;
     *iters = j;
-    if (std::fabs(eta) <= h->p.minres_rtol * g1 || gn == 0.0) return FRACTURE_OK;
+    if (std::fabs(eta) <= rtol * g1 || gn == 0.0) return FRACTURE_OK;
   }
   return FRACTURE_OK;  // an inexact Newton direction is still tried by the line search
 }
@@ -959,8 +961,13 @@ int newton_phase(fracture* h, fracture_stats* st, double* nphi, bool* converged)
     // rhs = -[F_u; F_a on the inactive set]
     launch_axpby(s, n2, -1.0, h->nFu, 0.0, h->nv);
     launch_neg_masked(s, N, h->F, h->mask, h->nv + n2, h->nca);
+    // forcing term: enough accuracy for this step to reach final_tol
+    double eta = h->p.minres_rtol;
+    if (h->p.newton_forcing > 0)
+      eta = std::fmax(h->p.minres_rtol,
+                      std::fmin(NEWTON_ETA_MAX, h->p.newton_forcing * h->p.final_tol / *nphi));
     int its = 0;
-    rc = minres(h, &its);
+    rc = minres(h, eta, &its);
     st->minres_iters += its;
     if (rc) return rc;
     ++st->newton_iters;
@@ -1142,6 +1149,7 @@ void fracture_default_params(fracture_params* p, int nx, int ny) {
   p->cheb_degree = 2;
   p->coarse_max_dofs = 200;
   p->newton_vcycles = 1;
+  p->newton_forcing = 0.1;
   p->use_graphs = 1;
 }
 
