@@ -111,6 +111,50 @@ def thermal(args):
             "kernels": rl}
 
 
+KERNELS = ("smooth", "apply", "vi_eval", "helm", "copy")
+
+
+def time_kernels(solver, reps):
+    """Mean duration of each hot kernel over back-to-back launches, timed with
+    HIP events on the solver's stream, and its algorithmic bytes."""
+    from paper_1511_08463_amd import fracture
+    ids = {"smooth": fracture.FRACTURE_KERNEL_SMOOTH, "apply": fracture.FRACTURE_KERNEL_APPLY,
+           "vi_eval": fracture.FRACTURE_KERNEL_VI_EVAL, "helm": fracture.FRACTURE_KERNEL_HELM,
+           "copy": fracture.FRACTURE_KERNEL_COPY}
+    rl = {}
+    for name in KERNELS:
+        ms, nbytes = fracture.fracture_time_kernel(solver.h, ids[name], reps)
+        rl[name] = {"us": ms * 1e3, "bytes": nbytes, "gbs": nbytes / (ms * 1e-3) / 1e9}
+        log(f"[bench] kernel {name}: {ms * 1e3:.1f} us/launch, {nbytes / 1e6:.1f} MB -> "
+            f"{rl[name]['gbs']:.0f} GB/s")
+    return rl
+
+
+# HBM bytes per launch of the finest-level Chebyshev step (2048^2, 88 B/node
+# variant timed above), from rocprofv3 FETCH_SIZE and WRITE_SIZE of
+# `bench.py --kernels-only`, scaled by the factor that maps the same counters
+# on the plain copy kernel to its known bytes.  Valid only for the kernel
+# sources they were taken on (sha256 over the files below).
+TRAFFIC = None
+TRAFFIC_SOURCES = ("paper_1511_08463_amd/csrc/common.h", "paper_1511_08463_amd/csrc/ops2d.h",
+                   "paper_1511_08463_amd/csrc/kernels2d.hip")
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    if TRAFFIC is None or TRAFFIC["source_sha256"] != kernel_source_sha():
+        return None
+    return TRAFFIC["bytes"]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +173,7 @@ def main():
     ap.add_argument("--newton-vcycles", type=int, default=1,
                     help="V-cycles per action of A^-1 in the Newton block preconditioner")
     ap.add_argument("--no-graphs", action="store_true", help="launch eagerly (no HIP graph replay)")
+    ap.add_argument("--cheb-degree", type=int, default=2, help="Chebyshev steps per V-cycle side")
     ap.add_argument("--newton-forcing", type=float, default=0.1,
                     help="adaptive Newton forcing factor (0: fixed --minres-rtol)")
     ap.add_argument("--kernel-reps", type=int, default=50)
@@ -137,6 +182,9 @@ def main():
     ap.add_argument("--thermal", action="store_true", help="run only the 3D thermal slab (config 3)")
     ap.add_argument("--dt-factor", type=float, default=16.0, help="thermal ramp end in units of DT_c")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream sample")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="time the hot kernels only (no solve), e.g. under hardware counters")
     ap.add_argument("--instances", type=int, default=48)
     ap.add_argument("--budget-gb", type=float, default=4.0)
     ap.add_argument("--workers", type=int, default=4)
@@ -164,70 +212,93 @@ def main():
         print(json.dumps({"thermal": thermal(args)}), flush=True)
         return
     p, notch, loads, (y0, a) = workloads.config2(args.model, args.omega, seed=0, n=args.n)
-    params = fracture.make_params(**p, am_tol=args.am_tol, pcg_rtol=args.pcg_rtol,
-                                  vi_cg_rtol=1e-10, max_am=5000, newton=args.newton,
-                                  switch_tol=args.switch_tol, final_tol=args.final_tol,
-                                  minres_rtol=args.minres_rtol,
-                                  newton_vcycles=args.newton_vcycles,
-                                  newton_forcing=args.newton_forcing,
-                                  use_graphs=0 if args.no_graphs else 1,
-                                  precision=fracture.FRACTURE_MIXED if args.precision == "mixed"
-                                  else fracture.FRACTURE_FP64)
-    log(f"[bench] {args.precision} {args.n}^2 {args.model} omega={args.omega} notch y0={y0:.4f} a={a:.4f} "
-        f"warmup={args.warmup} steps={args.steps}")
-    solver = fracture.Fracture(params, notch, device=dev)
-    last = [time.perf_counter()]
 
-    def monitor(sweep, da, phi):
-        now = time.perf_counter()
-        if now - last[0] > 5.0:
-            last[0] = now
-            log(f"[bench]   ... sweep/newton {sweep} dalpha={da:.2e} phi={phi:.2e}")
+    def make_solver(precision):
+        params = fracture.make_params(**p, am_tol=args.am_tol, pcg_rtol=args.pcg_rtol,
+                                      vi_cg_rtol=1e-10, max_am=5000, newton=args.newton,
+                                      switch_tol=args.switch_tol, final_tol=args.final_tol,
+                                      minres_rtol=args.minres_rtol,
+                                      newton_vcycles=args.newton_vcycles,
+                                      newton_forcing=args.newton_forcing,
+                                      cheb_degree=args.cheb_degree,
+                                      use_graphs=0 if args.no_graphs else 1,
+                                      precision=fracture.FRACTURE_MIXED if precision == "mixed"
+                                      else fracture.FRACTURE_FP64)
+        return fracture.Fracture(params, notch, device=dev)
 
-    solver.set_monitor(monitor)
-    free_dofs = solver.ndof - (args.n + 1) * 2 - 1
+    if args.kernels_only:
+        # the hot kernels alone (no solve), for hardware-counter runs
+        solver = make_solver(args.precision)
+        solver.set_load(loads[0])
+        rl = time_kernels(solver, args.kernel_reps)
+        solver.close()
+        print(json.dumps({"kernels": rl}), flush=True)
+        return
 
-    def run(k):
-        solver.set_load(loads[k])
+    free_dofs = 2 * (args.n + 1) ** 2 - (args.n + 1) * 2 - 1
+
+    def leg(precision):
+        """W untimed + K timed load steps of one solver instance."""
+        log(f"[bench] {precision} {args.n}^2 {args.model} omega={args.omega} notch y0={y0:.4f} "
+            f"a={a:.4f} warmup={args.warmup} steps={args.steps}")
+        solver = make_solver(precision)
+        last = [time.perf_counter()]
+
+        def monitor(sweep, da, phi):
+            now = time.perf_counter()
+            if now - last[0] > 5.0:
+                last[0] = now
+                log(f"[bench]   ... sweep/newton {sweep} dalpha={da:.2e} phi={phi:.2e}")
+
+        solver.set_monitor(monitor)
+
+        def run(k):
+            solver.set_load(loads[k])
+            st = solver.solve_step()
+            log(f"[bench] {precision} step {k + 1} t={loads[k]:.2f} sweeps={st['sweeps']} "
+                f"pcg={st['pcg_iters']} vi={st['vi_iters']} vi_cg={st['vi_cg_iters']} "
+                f"newton={st['newton_iters']} minres={st['minres_iters']} "
+                f"fails={st['newton_failures']} dalpha={st['dalpha_inf']:.2e} phi={st['phi_l2']:.2e} "
+                f"ms={st['ms_total']:.1f} (pcg {st['ms_pcg']:.1f}, vi {st['ms_vi']:.1f}, "
+                f"newton {st['ms_newton']:.1f})")
+            return st
+
+        for k in range(args.warmup):
+            run(k)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = solver.solve_step()
-        st["wall_s"] = time.perf_counter() - t0
-        log(f"[bench] step {k + 1} t={loads[k]:.2f} sweeps={st['sweeps']} pcg={st['pcg_iters']} "
-            f"vi={st['vi_iters']} vi_cg={st['vi_cg_iters']} newton={st['newton_iters']} "
-            f"minres={st['minres_iters']} fails={st['newton_failures']} dalpha={st['dalpha_inf']:.2e} "
-            f"phi={st['phi_l2']:.2e} ms={st['ms_total']:.1f} (pcg {st['ms_pcg']:.1f}, vi {st['ms_vi']:.1f}, "
-            f"newton {st['ms_newton']:.1f})")
-        return st
+        stats = [run(k) for k in range(args.warmup, args.warmup + args.steps)]
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        pcg_iters = sum(s["pcg_iters"] for s in stats)
+        pcg_s = sum(s["ms_pcg"] for s in stats) / 1e3
+        res = {
+            "value": args.steps / elapsed,
+            "ms_per_step": 1e3 * elapsed / args.steps,
+            "pcg_dof_iter_per_s": free_dofs * pcg_iters / pcg_s if pcg_s > 0 else None,
+            "sweeps": sum(s["sweeps"] for s in stats),
+            "pcg_iters": pcg_iters,
+            "newton_iters": sum(s["newton_iters"] for s in stats),
+            "minres_iters": sum(s["minres_iters"] for s in stats),
+            "step_ms": [round(s["ms_total"], 2) for s in stats],
+        }
+        state = solver.state()
+        energy = solver.energy()
+        return solver, res, state, energy
 
-    for k in range(args.warmup):
-        run(k)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = [run(k) for k in range(args.warmup, args.warmup + args.steps)]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    pcg_iters = sum(s["pcg_iters"] for s in stats)
-    pcg_s = sum(s["ms_pcg"] for s in stats) / 1e3
-    sweeps = sum(s["sweeps"] for s in stats)
-
-    # roofline of the dominant kernel: the finest-level Chebyshev step
-    rl = {}
-    for name, kid in (("smooth", fracture.FRACTURE_KERNEL_SMOOTH), ("apply", fracture.FRACTURE_KERNEL_APPLY),
-                      ("vi_eval", fracture.FRACTURE_KERNEL_VI_EVAL), ("helm", fracture.FRACTURE_KERNEL_HELM)):
-        ms, nbytes = fracture.fracture_time_kernel(solver.h, kid, args.kernel_reps)
-        rl[name] = {"ms": ms, "bytes": nbytes, "gbs": nbytes / (ms * 1e-3) / 1e9}
-        log(f"[bench] kernel {name}: {ms * 1e3:.1f} us/launch, {nbytes / 1e6:.1f} MB -> "
-            f"{rl[name]['gbs']:.0f} GB/s")
+    solver, res, state64, energy64 = leg(args.precision)
+    rl = time_kernels(solver, args.kernel_reps)
+    solver.close()
     dom = rl["smooth"]
+    traffic = recorded_traffic()
     out = {
         "metric": METRIC,
-        "value": args.steps / elapsed,
+        "value": res["value"],
         "unit": "load steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -238,28 +309,48 @@ def main():
                          f"{args.model}, ell=4h, k_ell=1e-6, seeded edge notch (y0={y0:.4f}, a={a:.4f}), "
                          f"tension load steps t=0.1k, k={args.warmup + 1}..{args.warmup + args.steps} timed; "
                          + (f"ORAM omega={args.omega} switching to reduced-space Newton at ||Phi||2<{args.switch_tol:g}, "
-                            f"stop ||Phi||2<{args.final_tol:g}" if args.newton else
+                            f"stop ||Phi||2<{args.final_tol:g}, MINRES forcing "
+                            + (f"adaptive ({args.newton_forcing:g} final_tol/||Phi||, floor {args.minres_rtol:g})"
+                               if args.newton_forcing > 0 else f"{args.minres_rtol:g}")
+                            + f", {args.newton_vcycles} V-cycle(s) per A^-1"
+                            if args.newton else
                             f"ORAM omega={args.omega} to ||dalpha||inf<{args.am_tol:g}")
                          + f", PCG rtol {args.pcg_rtol:g}"),
             "precision": args.precision,
             "newton": bool(args.newton),
         },
-        "pcg_dof_iter_per_s": free_dofs * pcg_iters / pcg_s if pcg_s > 0 else None,
-        "sweeps": sweeps,
-        "pcg_iters": pcg_iters,
+        "pcg_dof_iter_per_s": res["pcg_dof_iter_per_s"],
+        "sweeps": res["sweeps"],
+        "pcg_iters": res["pcg_iters"],
+        "newton_iters": res["newton_iters"],
+        "minres_iters": res["minres_iters"],
+        "step_ms": res["step_ms"],
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_node2d<SMOOTH> (finest-level Chebyshev step)",
+            "kernel": "k_col2d<SMOOTH> (finest-level Chebyshev step, 88 B/node)",
             "achieved": dom["gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": dom["gbs"] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "per_kernel_gbs": {k: round(v["gbs"], 1) for k, v in rl.items()},
-            "per_kernel_us": {k: round(v["ms"] * 1e3, 2) for k, v in rl.items()},
+            "per_kernel_us": {k: round(v["us"], 2) for k, v in rl.items()},
         },
     }
-    solver.close()
+    if not args.no_mixed and args.precision == "fp64":
+        # the same load steps with the float32 operator and multigrid inside
+        # float64 refinement, against the float64 run just made
+        s32, r32, state32, energy32 = leg("mixed")
+        s32.close()
+        rel = lambda a_, b_: float(np.linalg.norm(a_ - b_) / max(np.linalg.norm(b_), 1e-300))
+        out["mixed"] = {
+            "value": r32["value"], "unit": "load steps/s", "ms_per_step": r32["ms_per_step"],
+            "pcg_dof_iter_per_s": r32["pcg_dof_iter_per_s"], "pcg_iters": r32["pcg_iters"],
+            "minres_iters": r32["minres_iters"], "speedup_vs_fp64": r32["value"] / res["value"],
+            "rel_l2_u_vs_fp64": rel(state32[0], state64[0]),
+            "rel_l2_alpha_vs_fp64": rel(state32[1], state64[1]),
+            "rel_energy_vs_fp64": abs(sum(energy32) - sum(energy64)) / abs(sum(energy64)),
+        }
     if not args.no_serve:
         sv = serve(args)
         out["serving"] = {k: sv[k] for k in ("instances", "steps", "wall_s", "steps_per_s",

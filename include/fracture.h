@@ -234,8 +234,8 @@ int fracture_level_shape(fracture_t h, int level, int* nx, int* ny, int* nz);
  * return the mean duration per launch (host *avg_ms) and the kernel's
  * algorithmic (compulsory) bytes per launch (host *bytes): every distinct
  * input read once plus every output written once, from the level's sizes.
- *   APPLY    finest-level y = K(alpha) x with the x.y reduction (the PCG
- *            product): x 16 + alpha 8 + y 16 = 40 B per node.
+ *   APPLY    finest-level y = K(alpha) x: x 16 + alpha 8 + y 16 = 40 B
+ *            per node.
  *   SMOOTH   finest-level Chebyshev step with iterate, rhs and update
  *            vectors: x 16 + alpha 8 + b 16 + d 16 in, x' 16 + d' 16 out
  *            = 88 B per node.
@@ -244,11 +244,16 @@ int fracture_level_shape(fracture_t h, int level, int* nx, int* ny, int* nz);
  *            inverse diagonal 8 out = 57 B per node.
  *   HELM     masked damage Hessian apply with the x.y reduction: x 8 +
  *            W2 16 + mask 1 in, y 8 out = 33 B per node.
+ *   COPY     y = x for one displacement vector: 16 in + 16 out = 32 B per
+ *            node.
  * The buffers are overwritten (call between load steps only). */
 #define FRACTURE_KERNEL_APPLY   0
 #define FRACTURE_KERNEL_SMOOTH  1
 #define FRACTURE_KERNEL_VI_EVAL 2
 #define FRACTURE_KERNEL_HELM    3
+#define FRACTURE_KERNEL_COPY    4   /* plain copy of one displacement vector:
+                                       the streaming reference (and the
+                                       calibration kernel for HBM counters) */
 int fracture_time_kernel(fracture_t h, int kernel, int reps, double* avg_ms, double* bytes);
 
 const char* fracture_strerror(int code);

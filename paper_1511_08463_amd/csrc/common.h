@@ -131,6 +131,18 @@ __device__ __forceinline__ void block_reduce(double v, const Red& r, int nblocks
   }
 }
 
+// XCD-aware tile order.  The dispatcher deals consecutive workgroups to the
+// eight XCDs in turn, and each XCD has its own L2; remapping the dispatch
+// index p so that XCD x receives one contiguous range of tiles keeps a
+// tile's neighbours (which share its halo rows) in the same L2.
+constexpr int NUM_XCD = 8;
+
+__device__ __forceinline__ int xcd_tile(int p, int total) {
+  const int x = p % NUM_XCD, slot = p / NUM_XCD;
+  const int per = total / NUM_XCD, rem = total % NUM_XCD;
+  return x * per + (x < rem ? x : rem) + slot;
+}
+
 // Map NaN to +inf so that max-reductions report non-finite values.
 __device__ __forceinline__ double nan_to_inf(double x) { return (x != x) ? INFINITY : x; }
 

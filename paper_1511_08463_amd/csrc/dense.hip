@@ -1,6 +1,7 @@
 // Coarsest multigrid level: assemble the (small) Galerkin operator densely,
-// invert it once per coefficient update by Gauss-Jordan elimination in a
-// single workgroup, and apply the symmetrised inverse as a dense
+// invert it once per coefficient update in a single workgroup (symmetric
+// sweeps in registers for the usual small sizes, Gauss-Jordan in global
+// memory otherwise), and apply the symmetric inverse as a dense
 // matrix-vector product.  Dirichlet rows and columns are replaced by the
 // identity, so the inverse leaves them at zero when the right-hand side is.
 #include "common.h"
@@ -69,8 +70,8 @@ __global__ __launch_bounds__(DB) void k_dense_assemble2d(Grid g, Mat m, const do
   }
 }
 
-// In-place Gauss-Jordan inverse of an SPD matrix (no pivoting), then
-// symmetrisation into Ainv.
+// In-place Gauss-Jordan inverse of an SPD matrix (no pivoting) in global
+// memory, then symmetrisation into Ainv (any n up to DENSE_MAX).
 __global__ __launch_bounds__(DB) void k_gauss_jordan(int n, double* __restrict__ A,
                                                      double* __restrict__ Ainv) {
   extern __shared__ double sm[];
@@ -101,16 +102,82 @@ __global__ __launch_bounds__(DB) void k_gauss_jordan(int n, double* __restrict__
   }
 }
 
+// Small coarsest levels (n <= GJ_NMAX): the symmetric sweep operator on the
+// lower triangle, held in registers.  Sweeping pivot k with d = A_kk maps
+//   A_ij -> A_ij - A_ik A_jk / d  (i, j != k),  A_ik -> A_ik / d,  A_kk -> -1/d,
+// which keeps the matrix symmetric; after all n pivots it holds -A^{-1}.
+// Thread t owns the lower-triangle entries e = t + q DB (row-major packed);
+// at step k the owners of column k publish it through LDS and every thread
+// updates its own entries: two workgroup barriers per step and no global
+// memory traffic.
+constexpr int GJ_Q = 14;
+constexpr int GJ_NMAX = 168;   // n (n + 1) / 2 <= DB * GJ_Q
+
+__global__ __launch_bounds__(DB) void k_sweep_inverse(int n, const double* __restrict__ A,
+                                                      double* __restrict__ Ainv) {
+  extern __shared__ double colk[];
+  const int ne = n * (n + 1) / 2, t = threadIdx.x;
+  double a[GJ_Q];
+  int ij[GJ_Q];   // (row << 16) | column with row >= column, or -1 past the end
+#pragma unroll
+  for (int q = 0; q < GJ_Q; ++q) {
+    const int e = t + q * DB;
+    int r = -1, c = 0;
+    if (e < ne) {
+      r = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+      while (r * (r + 1) / 2 > e) --r;
+      while ((r + 1) * (r + 2) / 2 <= e) ++r;
+      c = e - r * (r + 1) / 2;
+    }
+    ij[q] = r < 0 ? -1 : (r << 16) | c;
+    a[q] = r < 0 ? 0.0 : A[(size_t)r * n + c];
+  }
+  for (int k = 0; k < n; ++k) {
+    // column k of the symmetric matrix: entries (i, k) for i >= k, (k, j) for j < k
+#pragma unroll
+    for (int q = 0; q < GJ_Q; ++q) {
+      if (ij[q] < 0) continue;
+      const int i = ij[q] >> 16, j = ij[q] & 0xffff;
+      if (j == k) colk[i] = a[q];
+      else if (i == k) colk[j] = a[q];
+    }
+    __syncthreads();
+    const double d = colk[k], inv = 1.0 / d;
+#pragma unroll
+    for (int q = 0; q < GJ_Q; ++q) {
+      if (ij[q] < 0) continue;
+      const int i = ij[q] >> 16, j = ij[q] & 0xffff;
+      if (i == k && j == k) a[q] = -inv;
+      else if (i == k) a[q] = colk[j] * inv;
+      else if (j == k) a[q] = colk[i] * inv;
+      else a[q] -= colk[i] * colk[j] * inv;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < GJ_Q; ++q) {
+    if (ij[q] < 0) continue;
+    const int i = ij[q] >> 16, j = ij[q] & 0xffff;
+    Ainv[(size_t)i * n + j] = -a[q];
+    Ainv[(size_t)j * n + i] = -a[q];
+  }
+}
+
 void launch_dense_setup(hipStream_t st, const Grid& g, const Mat& m, const double* abar,
                         double* A, double* Ainv) {
   const int n = g.dim * g.N;
   if (g.dim == 3) launch_dense_assemble3d(st, g, m, abar, A);
   else hipLaunchKernelGGL(k_dense_assemble2d, dim3(1), dim3(DB), 0, st, g, m, abar, A);
-  hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(DB), 2 * n * sizeof(double), st, n, A, Ainv);
+  if (n <= GJ_NMAX)
+    hipLaunchKernelGGL(k_sweep_inverse, dim3(1), dim3(DB), n * sizeof(double), st, n, A, Ainv);
+  else
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(DB), 2 * n * sizeof(double), st, n, A, Ainv);
 }
 
-// x = Ainv b (dense, one block; row-per-thread with b in LDS; float64
-// accumulation for either value type of b and x).
+// x = Ainv b (dense, one block; thread i forms entry i with b in LDS; float64
+// accumulation for either value type of b and x).  Ainv is symmetric, so
+// thread i walks column i: at each step the threads read consecutive
+// addresses.
 template <class T>
 __global__ __launch_bounds__(DB) void k_dense_solve(int n, const double* __restrict__ Ainv,
                                                     const T* __restrict__ b, T* __restrict__ x) {
@@ -119,8 +186,7 @@ __global__ __launch_bounds__(DB) void k_dense_solve(int n, const double* __restr
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += DB) {
     double s = 0.0;
-    const double* row = Ainv + (size_t)i * n;
-    for (int j = 0; j < n; ++j) s += row[j] * sb[j];
+    for (int j = 0; j < n; ++j) s += Ainv[(size_t)j * n + i] * sb[j];
     x[i] = T(s);
   }
 }

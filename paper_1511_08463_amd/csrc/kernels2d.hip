@@ -93,14 +93,16 @@ __global__ __launch_bounds__(NB) void k_node2d(Grid g, Mat m, const T* __restric
 // One wavefront per 64 x NB_Y tile, thread i walking the tile's column
 // (column2d): each element stress is formed once per thread and each row is
 // loaded once, which pays on the large levels.  Same tiles and block count as
-// k_node2d.
+// k_node2d; tiles are taken in XCD-aware order (xcd_tile).
 template <int MODE, bool FA, bool HASX, int RED, class T>
 __global__ __launch_bounds__(NB_X) void k_col2d(Grid g, Mat m, const T* __restrict__ coef, T kell,
                                                 const T* __restrict__ x, T* __restrict__ y,
                                                 const T* __restrict__ b, const T* __restrict__ din,
                                                 T* __restrict__ dout, T cd, T cr, int mask, Red red) {
-  const int i = blockIdx.x * NB_X + threadIdx.x;
-  const int j0 = blockIdx.y * NB_Y;
+  const int nbx = gridDim.x, total = gridDim.x * gridDim.y;
+  const int t = xcd_tile(blockIdx.x + nbx * blockIdx.y, total);
+  const int i = (t % nbx) * NB_X + threadIdx.x;
+  const int j0 = (t / nbx) * NB_Y;
   double acc = 0.0;
   if (i <= g.nx) {
     column2d<FA, HASX, MODE == M_SMOOTH>(
@@ -108,9 +110,7 @@ __global__ __launch_bounds__(NB_X) void k_col2d(Grid g, Mat m, const T* __restri
           node_out2d<MODE, RED>(g, i, j, fx, fy, dx, dy, xc, yc, y, b, din, dout, cd, cr, mask, acc);
         });
   }
-  if (RED != R_NONE)
-    block_reduce<NB_X, false>(acc, red, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
-                              threadIdx.x);
+  if (RED != R_NONE) block_reduce<NB_X, false>(acc, red, total, t, threadIdx.x);
 }
 
 // Levels with at least this many nodes use the column-blocked kernels.

@@ -123,6 +123,7 @@ void launch_xpby_f(hipStream_t st, int64_t n, const float* z, float* p, const do
 void launch_dot_f(hipStream_t st, int64_t n, const float* a, const float* b, Red r);
 void launch_to_float(hipStream_t st, int64_t n, const double* x, float* y, double scale);
 void launch_add_scaled_f(hipStream_t st, int64_t n, double* x, const float* e, double scale);
+void launch_copy(hipStream_t st, int64_t n, const double* x, double* y);
 void launch_lincomb3(hipStream_t st, int64_t n, double a, double* z, double b, const double* x,
                      double c, const double* y);
 void launch_minres_update(hipStream_t st, int64_t n, double a, const double* z, double b,

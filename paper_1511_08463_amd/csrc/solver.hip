@@ -1429,8 +1429,11 @@ int fracture_time_kernel(fracture_t h, int kernel, int reps, double* avg_ms, dou
   auto one = [&]() {
     switch (kernel) {
       case FRACTURE_KERNEL_APPLY:
-        launch_apply2d(st, g, h->mat, true, h->alpha, h->p.k_ell, L0.xa, L0.xb, nullptr, 1, 1,
+        launch_apply2d(st, g, h->mat, true, h->alpha, h->p.k_ell, L0.xa, L0.xb, nullptr, 1, 0,
                        red(h, 2, S_PQ, P_STORE));
+        break;
+      case FRACTURE_KERNEL_COPY:
+        launch_copy(st, n2, L0.xa, L0.xb);
         break;
       case FRACTURE_KERNEL_SMOOTH:
         launch_smooth2d(st, g, h->mat, true, h->alpha, h->p.k_ell, L0.xa, L0.xb, L0.b, L0.d, L0.d,
@@ -1441,9 +1444,12 @@ int fracture_time_kernel(fracture_t h, int kernel, int reps, double* avg_ms, dou
                          S_MU, 1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2),
                          red(h, 6, S_PHIMAX), red(h, 12, S_JLO), red(h, 13, S_JHI), false);
         break;
-      default:
+      case FRACTURE_KERNEL_HELM:
         launch_helm_apply2d(st, g, h->cL, h->cM, h->w2, h->vp, h->mask, h->vq, true,
                             red(h, 2, S_PQ, P_STORE));
+        break;
+      default:
+        break;
     }
   };
   const double dv = 8.0 * h->dim;                 // one displacement vector, per node
@@ -1453,6 +1459,7 @@ int fracture_time_kernel(fracture_t h, int kernel, int reps, double* avg_ms, dou
     case FRACTURE_KERNEL_SMOOTH: b = (5 * dv + 8.0) * N; break;
     case FRACTURE_KERNEL_VI_EVAL: b = (8.0 + 8.0 + w2b + 8.0 + 8.0 + 1.0 + 8.0) * N; break;
     case FRACTURE_KERNEL_HELM: b = (8.0 + w2b + 1.0 + 8.0) * N; break;
+    case FRACTURE_KERNEL_COPY: b = 2.0 * dv * N; break;
     default: return FRACTURE_EINVAL;
   }
   one();  // warm

@@ -126,6 +126,16 @@ void launch_axpby(hipStream_t st, int64_t n, double a, const double* x, double b
   hipLaunchKernelGGL(k_axpby, dim3(vgrid(n)), dim3(VB), 0, st, n, a, x, b, y);
 }
 
+// y = x (a plain streaming copy)
+__global__ __launch_bounds__(VB) void k_copy(int64_t n, const double* __restrict__ x,
+                                             double* __restrict__ y) {
+  GRID_STRIDE(k, n) y[k] = x[k];
+}
+
+void launch_copy(hipStream_t st, int64_t n, const double* x, double* y) {
+  hipLaunchKernelGGL(k_copy, dim3(vgrid(n)), dim3(VB), 0, st, n, x, y);
+}
+
 // z = a z + b x + c y
 __global__ __launch_bounds__(VB) void k_lincomb3(int64_t n, double a, double* __restrict__ z,
                                                  double b, const double* __restrict__ x, double c,

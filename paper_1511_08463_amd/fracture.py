@@ -45,6 +45,7 @@ FRACTURE_KERNEL_APPLY = 0
 FRACTURE_KERNEL_SMOOTH = 1
 FRACTURE_KERNEL_VI_EVAL = 2
 FRACTURE_KERNEL_HELM = 3
+FRACTURE_KERNEL_COPY = 4
 
 
 class fracture_params(ctypes.Structure):
