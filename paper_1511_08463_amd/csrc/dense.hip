@@ -174,20 +174,23 @@ void launch_dense_setup(hipStream_t st, const Grid& g, const Mat& m, const doubl
     hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(DB), 2 * n * sizeof(double), st, n, A, Ainv);
 }
 
-// x = Ainv b (dense, one block; thread i forms entry i with b in LDS; float64
-// accumulation for either value type of b and x).  Ainv is symmetric, so
-// thread i walks column i: at each step the threads read consecutive
-// addresses.
+// x = Ainv b (dense, one block, b in LDS; float64 accumulation for either
+// value type of b and x): wave w forms rows w, w + 16, ...; its lanes read a
+// row with consecutive addresses and the partial sums meet in a wave
+// reduction.
 template <class T>
 __global__ __launch_bounds__(DB) void k_dense_solve(int n, const double* __restrict__ Ainv,
                                                     const T* __restrict__ b, T* __restrict__ x) {
   extern __shared__ double sb[];
   for (int i = threadIdx.x; i < n; i += DB) sb[i] = (double)b[i];
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += DB) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  for (int i = w; i < n; i += DB / WAVE) {
+    const double* row = Ainv + (size_t)i * n;
     double s = 0.0;
-    for (int j = 0; j < n; ++j) s += Ainv[(size_t)j * n + i] * sb[j];
-    x[i] = T(s);
+    for (int j = lane; j < n; j += WAVE) s += row[j] * sb[j];
+    s = wave_sum(s);
+    if (lane == 0) x[i] = T(s);
   }
 }
 

@@ -101,6 +101,10 @@ def load_library(path=LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch ships its own HIP runtime under the same soname; load it first so
+    # that this library binds to it and device pointers from torch tensors
+    # belong to the runtime the library calls.
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
     lib = ctypes.CDLL(path)
