@@ -34,6 +34,8 @@ enum {
   S_RATIO, S_INFEAS, S_GG, S_JLO, S_JHI, S_MR0, S_MR1, S_MR2, S_MR3, S_MR4, S_MR5, S_MR6, S_MR7,
   S_COUNT = 64
 };
+// kernels read the inactive row band as the pair (S[S_JLO], S[S_JHI])
+static_assert(S_JHI == S_JLO + 1, "band slots must be adjacent");
 // Partial-sum slots: one per reduction that may be pending at the same time.
 enum { C_SLOTS = 16 };
 

@@ -628,10 +628,19 @@ __global__ __launch_bounds__(NB) void k_jac_u2d(Grid g, Mat m, double kell,
                                                 const double* __restrict__ xu,
                                                 const double* __restrict__ xa,
                                                 const uint8_t* __restrict__ mask,
-                                                double* __restrict__ yu, Red r) {
+                                                double* __restrict__ yu, Red r,
+                                                const double* __restrict__ band) {
   const int i = blockIdx.x * NB_X + threadIdx.x;
   const int j = blockIdx.y * NB_Y + threadIdx.y;
   double acc = 0.0;
+  // B x_a vanishes at nodes with no inactive node within one row: with band
+  // = (-j_lo, j_hi) of the inactive rows, only rows j_lo - 1 .. j_hi + 1 carry
+  // it (band == nullptr: every row)
+  bool couple = HAS_XA;
+  if (HAS_XA && band) {
+    const double jlo = -band[0], jhi = band[1];
+    couple = jlo <= jhi && (double)j >= jlo - 1.0 && (double)j <= jhi + 1.0;
+  }
   if (i <= g.nx && j <= g.ny) {
     const int N = g.N, n = i + (g.nx + 1) * j;
     double fx = 0, fy = 0, dx, dy;
@@ -640,7 +649,7 @@ __global__ __launch_bounds__(NB) void k_jac_u2d(Grid g, Mat m, double kell,
       coef6<true>(g, alpha, kell, i, j, c);
       node_force2d<true, false>(g, m, c, xu, xu + N, i, j, fx, fy, dx, dy);
     }
-    if (HAS_XA) {
+    if (couple) {
       // coupling coefficients c_e = -2 w_e^T M_ref b_e with w = x_a masked to the inactive set
       const int W = g.nx + 1;
       const bool L = i > 0, R = i < g.nx, D = j > 0, U = j < g.ny;
@@ -747,12 +756,13 @@ __global__ __launch_bounds__(NB) void k_jac_a2d(Grid g, Mat m, Helm hp,
 void launch_jac2d(hipStream_t st, const Grid& g, const Mat& m, double kell, double cL, double cM,
                   const double* alpha, const double* u, const double* w2, const uint8_t* mask,
                   const double* xu, const double* xa, double* yu, double* ya, bool dot, Red ru,
-                  Red ra) {
+                  Red ra, const double* band) {
   dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
   Helm hp{cL, cM, 0.0};
   if (yu) {
 #define JU(A, B, D) \
-  hipLaunchKernelGGL((k_jac_u2d<A, B, D>), gr, bl, 0, st, g, m, kell, alpha, u, xu, xa, mask, yu, ru)
+  hipLaunchKernelGGL((k_jac_u2d<A, B, D>), gr, bl, 0, st, g, m, kell, alpha, u, xu, xa, mask, yu, ru, \
+                     band)
     if (xu && xa) { if (dot) JU(true, true, true); else JU(true, true, false); }
     else if (xu) { if (dot) JU(true, false, true); else JU(true, false, false); }
     else JU(false, true, false);

@@ -856,11 +856,11 @@ void apply_P_body(fracture* h, const double* x, double* y) {
   Red none{};
   apply_Ainv(h, x, h->npu1);                                               // y1
   launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask,
-               h->npu1, nullptr, nullptr, h->npa1, false, none, none);     // B^T y1
+               h->npu1, nullptr, nullptr, h->npa1, false, none, none, h->S + S_JLO);  // B^T y1
   launch_axpby(h->st, N, 1.0, x + n2, -1.0, h->npa1);                      // x2 - B^T y1
   apply_Cinv(h, h->npa1, y + n2);                                          // y2
   launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask,
-               nullptr, y + n2, h->npu1, nullptr, false, none, none);      // B y2
+               nullptr, y + n2, h->npu1, nullptr, false, none, none, h->S + S_JLO);   // B y2
   launch_axpby(h->st, n2, 1.0, x, -1.0, h->npu1);                          // x1 - B y2
   apply_Ainv(h, h->npu1, y);                                               // z1
 }
@@ -877,7 +877,7 @@ void apply_J(fracture* h, const double* x, double* y) {
   const Grid& g = h->lv[0].g;
   const int64_t n2 = h->n2;
   launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask, x,
-               x + n2, y, y + n2, true, red(h, 7, S_TMP0), red(h, 8, S_TMP1));
+               x + n2, y, y + n2, true, red(h, 7, S_TMP0), red(h, 8, S_TMP1), h->S + S_JLO);
 }
 
 double dot3(fracture* h, const double* a, const double* b) {
@@ -1363,10 +1363,10 @@ int fracture_apply(fracture_t h, int op, int level, const double* d_x, double* d
       HIPCHK(hipMemsetAsync(h->mask, 0, h->N, h->st));
       if (op == FRACTURE_OP_COUPLING)
         launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask,
-                     nullptr, d_x, d_y, nullptr, false, none, none);
+                     nullptr, d_x, d_y, nullptr, false, none, none, nullptr);
       else
         launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask,
-                     d_x, nullptr, nullptr, d_y, false, none, none);
+                     d_x, nullptr, nullptr, d_y, false, none, none, nullptr);
     } break;
     case FRACTURE_OP_PRECOND: {
       if (!h->coef_valid) update_coefficients(h);
