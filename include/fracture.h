@@ -116,6 +116,10 @@ typedef struct {
                                replay them as HIP graphs; 0: launch eagerly.
                                Both run the same kernels in the same order,
                                so results are bitwise identical.               */
+  int vcycle_tail;          /* 1: run the smallest 2D multigrid levels and the
+                               coarsest solve of each V-cycle in one
+                               workgroup with its data in LDS; 0: one kernel
+                               per step.  Same per-node arithmetic.           */
 } fracture_params;
 
 /* Fill *p with the documented defaults for a 2D tension problem on an

@@ -23,58 +23,18 @@ namespace frac {
 // node kernels: apply / residual / Chebyshev step
 // ---------------------------------------------------------------------------
 
-enum { M_APPLY = 0, M_RESID = 1, M_SMOOTH = 2 };
-enum { R_NONE = 0, R_DOT = 1, R_FREE2 = 2 };
-
-// Output of a node kernel at node (i, j) from the node's force (fx, fy) = K x,
-// diagonal (dx, dy) and iterate (xc, yc); acc collects the optional reduction.
-template <int MODE, int RED, class T>
-__device__ __forceinline__ void node_out2d(const Grid& g, int i, int j, T fx, T fy, T dx, T dy,
-                                           T xc, T yc, T* __restrict__ y,
-                                           const T* __restrict__ b, const T* __restrict__ din,
-                                           T* __restrict__ dout, T cd, T cr, int mask,
-                                           double& acc) {
-  const int N = g.N, n = i + (g.nx + 1) * j;
-  const bool fxd = fixed_x2(g, i, j), fyd = fixed_y2(g, i, j);
-  if (MODE == M_APPLY) {
-    const T yx = (mask && fxd) ? T(0) : fx;
-    const T yy = (mask && fyd) ? T(0) : fy;
-    y[n] = yx;
-    y[n + N] = yy;
-    if (RED == R_DOT) acc += (double)xc * yx + (double)yc * yy;
-    if (RED == R_FREE2) {
-      const double rx = (double)fx - (b ? (double)b[n] : 0.0);
-      const double ry = (double)fy - (b ? (double)b[n + N] : 0.0);
-      acc += (fxd ? 0.0 : rx * rx) + (fyd ? 0.0 : ry * ry);
-    }
-  } else if (MODE == M_RESID) {
-    const T rx = fxd ? T(0) : (b ? b[n] : T(0)) - fx;
-    const T ry = fyd ? T(0) : (b ? b[n + N] : T(0)) - fy;
-    y[n] = rx;
-    y[n + N] = ry;
-    if (RED == R_DOT) acc += (double)rx * rx + (double)ry * ry;
-  } else {
-    const T rx = (b ? b[n] : T(0)) - fx, ry = (b ? b[n + N] : T(0)) - fy;
-    T ddx = cr * rx / dx, ddy = cr * ry / dy;
-    if (din) { ddx += cd * din[n]; ddy += cd * din[n + N]; }
-    T xo = xc + ddx, yo = yc + ddy;
-    if (fxd) { xo = T(0); ddx = T(0); }
-    if (fyd) { yo = T(0); ddy = T(0); }
-    y[n] = xo;
-    y[n + N] = yo;
-    if (dout) { dout[n] = ddx; dout[n + N] = ddy; }
-  }
-}
-
-// One thread per node (64 x NB_Y threads per tile): the short dependency
-// chain suits the small, latency-bound multigrid levels.
+// One thread per node (64 x NB_Y threads per tile, tiles in XCD-aware
+// order): the short dependency chain suits the small, latency-bound
+// multigrid levels.
 template <int MODE, bool FA, bool HASX, int RED, class T>
 __global__ __launch_bounds__(NB) void k_node2d(Grid g, Mat m, const T* __restrict__ coef, T kell,
                                                const T* __restrict__ x, T* __restrict__ y,
                                                const T* __restrict__ b, const T* __restrict__ din,
                                                T* __restrict__ dout, T cd, T cr, int mask, Red red) {
-  const int i = blockIdx.x * NB_X + threadIdx.x;
-  const int j = blockIdx.y * NB_Y + threadIdx.y;
+  const int nbx = gridDim.x, total = gridDim.x * gridDim.y;
+  const int tt = xcd_tile(blockIdx.x + nbx * blockIdx.y, total);
+  const int i = (tt % nbx) * NB_X + threadIdx.x;
+  const int j = (tt / nbx) * NB_Y + threadIdx.y;
   double acc = 0.0;
   if (i <= g.nx && j <= g.ny) {
     const int N = g.N, n = i + (g.nx + 1) * j;
@@ -85,9 +45,7 @@ __global__ __launch_bounds__(NB) void k_node2d(Grid g, Mat m, const T* __restric
     const T xc = HASX ? x[n] : T(0), yc = HASX ? x[n + N] : T(0);
     node_out2d<MODE, RED>(g, i, j, fx, fy, dx, dy, xc, yc, y, b, din, dout, cd, cr, mask, acc);
   }
-  if (RED != R_NONE)
-    block_reduce<NB, false>(acc, red, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
-                            threadIdx.x + NB_X * threadIdx.y);
+  if (RED != R_NONE) block_reduce<NB, false>(acc, red, total, tt, threadIdx.x + NB_X * threadIdx.y);
 }
 
 // One wavefront per 64 x NB_Y tile, thread i walking the tile's column

@@ -89,6 +89,30 @@ void launch_dense_setup(hipStream_t st, const Grid& g, const Mat& m, const doubl
 template <class T>
 void launch_dense_solve(hipStream_t st, int n, const double* Ainv, const T* b, T* x);
 
+// ---- bottom of the 2D V-cycle in one workgroup (tail2d.hip) -----------------
+constexpr int TAIL_MAX_LEVELS = 3;
+constexpr int TAIL_LDS_BYTES = 160 * 1024;
+
+template <class T>
+struct TailArgs {
+  int nl;                          // smoothed levels in the tail, 1 .. TAIL_MAX_LEVELS
+  Grid g[TAIL_MAX_LEVELS + 1];     // those levels (finest first), then the coarsest level
+  const T* coef[TAIL_MAX_LEVELS];  // their element coefficients
+  Mat m;
+  double kell;
+  int k;                           // Chebyshev steps per V-cycle side
+  double cd[8], cr[8];
+  const double* Ainv;              // inverse of the coarsest operator, dense_n^2
+  int dense_n;
+  const T* b;                      // right-hand side on the first tail level
+  T* x;                            // V-cycle result on the first tail level
+};
+
+// LDS bytes of a tail over levels g[0 .. nl-1] and a coarsest system of n DOFs.
+size_t tail_lds_bytes(const Grid* g, int nl, int n, size_t elem);
+template <class T>
+void launch_vtail2d(hipStream_t st, const TailArgs<T>& a);
+
 // ---- vector kernels (vec.hip) -----------------------------------------------
 int vec_blocks(int64_t n);
 void launch_finish(hipStream_t st, const Red& r, int nblocks, bool is_max);

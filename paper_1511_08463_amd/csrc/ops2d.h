@@ -161,6 +161,53 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
 }
 
 // ---------------------------------------------------------------------------
+// node outputs of the apply / residual / Chebyshev-step kernels
+// ---------------------------------------------------------------------------
+
+enum { M_APPLY = 0, M_RESID = 1, M_SMOOTH = 2 };
+enum { R_NONE = 0, R_DOT = 1, R_FREE2 = 2 };
+
+// Output of a node kernel at node (i, j) from the node's force (fx, fy) = K x,
+// diagonal (dx, dy) and iterate (xc, yc); acc collects the optional reduction.
+template <int MODE, int RED, class T>
+__device__ __forceinline__ void node_out2d(const Grid& g, int i, int j, T fx, T fy, T dx, T dy,
+                                           T xc, T yc, T* __restrict__ y,
+                                           const T* __restrict__ b, const T* __restrict__ din,
+                                           T* __restrict__ dout, T cd, T cr, int mask,
+                                           double& acc) {
+  const int N = g.N, n = i + (g.nx + 1) * j;
+  const bool fxd = fixed_x2(g, i, j), fyd = fixed_y2(g, i, j);
+  if (MODE == M_APPLY) {
+    const T yx = (mask && fxd) ? T(0) : fx;
+    const T yy = (mask && fyd) ? T(0) : fy;
+    y[n] = yx;
+    y[n + N] = yy;
+    if (RED == R_DOT) acc += (double)xc * yx + (double)yc * yy;
+    if (RED == R_FREE2) {
+      const double rx = (double)fx - (b ? (double)b[n] : 0.0);
+      const double ry = (double)fy - (b ? (double)b[n + N] : 0.0);
+      acc += (fxd ? 0.0 : rx * rx) + (fyd ? 0.0 : ry * ry);
+    }
+  } else if (MODE == M_RESID) {
+    const T rx = fxd ? T(0) : (b ? b[n] : T(0)) - fx;
+    const T ry = fyd ? T(0) : (b ? b[n + N] : T(0)) - fy;
+    y[n] = rx;
+    y[n + N] = ry;
+    if (RED == R_DOT) acc += (double)rx * rx + (double)ry * ry;
+  } else {
+    const T rx = (b ? b[n] : T(0)) - fx, ry = (b ? b[n + N] : T(0)) - fy;
+    T ddx = cr * rx / dx, ddy = cr * ry / dy;
+    if (din) { ddx += cd * din[n]; ddy += cd * din[n + N]; }
+    T xo = xc + ddx, yo = yc + ddy;
+    if (fxd) { xo = T(0); ddx = T(0); }
+    if (fyd) { yo = T(0); ddy = T(0); }
+    y[n] = xo;
+    y[n + N] = yo;
+    if (dout) { dout[n] = ddx; dout[n + N] = ddy; }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // column-blocked operator: one thread walks NB_Y consecutive nodes of a grid
 // column, so that every element stress is formed once per thread and each
 // grid row is loaded once (a sliding window of two rows in registers).

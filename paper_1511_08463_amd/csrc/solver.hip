@@ -111,6 +111,8 @@ struct fracture {
   // coarsest level
   double *dA = nullptr, *dAinv = nullptr;
   int dense_n = 0;
+  // first level of the single-workgroup V-cycle tail per value type (-1: none)
+  int tail64 = -1, tail32 = -1;
   // host side
   double* hS = nullptr;  // pinned copy of the scalar array
   hipEvent_t ev[8] = {};
@@ -162,6 +164,7 @@ int validate(const fracture_params* p) {
   if (p->newton_vcycles < 1 || p->newton_vcycles > 2) return FRACTURE_EINVAL;
   if (p->use_graphs != 0 && p->use_graphs != 1) return FRACTURE_EINVAL;
   if (!(p->newton_forcing >= 0)) return FRACTURE_EINVAL;
+  if (p->vcycle_tail != 0 && p->vcycle_tail != 1) return FRACTURE_EINVAL;
   if ((int64_t)(p->nx + 1) * (p->ny + 1) * (p->dim == 3 ? p->nz + 1 : 1) > (int64_t)1 << 29)
     return FRACTURE_EINVAL;
   return FRACTURE_OK;
@@ -192,6 +195,17 @@ int level_shapes(const fracture_params* p, Grid* out) {
   if (dim * out[L - 1].N > DENSE_MAX) return -1;
   if (L < 2) return -1;   // at least one coarse level
   return L;
+}
+
+// First level of the V-cycle tail that runs in one workgroup (2D only): the
+// most levels, at most TAIL_MAX_LEVELS and never the finest, whose vectors,
+// coefficients and coarsest system fit in LDS; -1 if none fits.
+int tail_start(const Grid* gl, int L, int dim, int dn, size_t elem) {
+  if (dim != 2) return -1;
+  int best = -1;
+  for (int lt = L - 2; lt >= 1 && L - 1 - lt <= TAIL_MAX_LEVELS; --lt)
+    if (tail_lds_bytes(gl + lt, L - 1 - lt, dn, elem) <= (size_t)TAIL_LDS_BYTES) best = lt;
+  return best;
 }
 
 size_t layout(const fracture_params* p, fracture* h, void* ws) {
@@ -286,6 +300,8 @@ size_t layout(const fracture_params* p, fracture* h, void* ws) {
   t->dense_n = dn;
   t->N = N;
   t->n2 = n2;
+  t->tail64 = tail_start(gl, L, dim, dn, sizeof(double));
+  t->tail32 = tail_start(gl, L, dim, dn, sizeof(float));
   return c.off + 256;
 }
 
@@ -437,6 +453,23 @@ T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr) {
   const double kell = h->p.k_ell;
   if (l == h->nlev - 1) {
     launch_dense_solve<T>(h->st, h->dense_n, h->dAinv, b, v.xa);
+    return v.xa;
+  }
+  const int tail = sizeof(T) == sizeof(double) ? h->tail64 : h->tail32;
+  if (h->p.vcycle_tail && l == tail) {
+    TailArgs<T> ta{};
+    ta.nl = h->nlev - 1 - l;
+    for (int q = 0; q <= ta.nl; ++q) ta.g[q] = h->lv[l + q].g;
+    for (int q = 0; q < ta.nl; ++q) ta.coef[q] = bufs<T>(h, l + q).coef;
+    ta.m = h->mat;
+    ta.kell = kell;
+    ta.k = k;
+    for (int s = 0; s < k; ++s) { ta.cd[s] = h->cheb_cd[s]; ta.cr[s] = h->cheb_cr[s]; }
+    ta.Ainv = h->dAinv;
+    ta.dense_n = h->dense_n;
+    ta.b = b;
+    ta.x = v.xa;
+    launch_vtail2d<T>(h->st, ta);
     return v.xa;
   }
   // pre-smoothing from zero
@@ -1151,6 +1184,7 @@ void fracture_default_params(fracture_params* p, int nx, int ny) {
   p->newton_vcycles = 1;
   p->newton_forcing = 0.1;
   p->use_graphs = 1;
+  p->vcycle_tail = 1;
 }
 
 size_t fracture_workspace_bytes(const fracture_params* p) {

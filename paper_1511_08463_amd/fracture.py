@@ -65,7 +65,7 @@ class fracture_params(ctypes.Structure):
         ("max_vi_cg", ctypes.c_int), ("max_newton", ctypes.c_int), ("max_minres", ctypes.c_int),
         ("cheb_degree", ctypes.c_int), ("coarse_max_dofs", ctypes.c_int),
         ("newton_vcycles", ctypes.c_int), ("newton_forcing", ctypes.c_double),
-        ("use_graphs", ctypes.c_int),
+        ("use_graphs", ctypes.c_int), ("vcycle_tail", ctypes.c_int),
     ]
 
 

@@ -292,6 +292,36 @@ def test_graph_replay_equals_eager(precision):
             assert a[k] == b[k], (k, a[k], b[k])
 
 
+@pytest.mark.parametrize("nx,ny", [(256, 256), (96, 80)])
+def test_vcycle_tail_matches_per_level_kernels(nx, ny):
+    """The V-cycle whose smallest levels and coarsest solve run in one
+    workgroup (data in LDS) equals the kernel-per-step V-cycle, in float64
+    (the preconditioner action) and along a mixed-precision load path."""
+    p = workloads.tension(nx, 0.06, "AT1", nx=nx, ny=ny)
+    notch = workloads.notch_mask_2d(nx, ny, 0.5, 0.25)
+    print(f"[tail] {nx}x{ny}", flush=True)
+    x = np.random.default_rng(3).standard_normal(2 * (nx + 1) * (ny + 1))
+    alpha = np.random.default_rng(4).uniform(0, 1, (nx + 1) * (ny + 1))
+    outs = []
+    for tail in (0, 1):
+        s = _solver(p, notch, vcycle_tail=tail)
+        s.set_state(alpha=alpha)
+        outs.append(s.apply(fracture.FRACTURE_OP_PRECOND, x))
+        s.close()
+    assert np.max(np.abs(outs[0] - outs[1])) <= 1e-12 * np.max(np.abs(outs[0]))
+    states = []
+    for tail in (0, 1):
+        s = _solver(p, notch, vcycle_tail=tail, precision=fracture.FRACTURE_MIXED, newton=1,
+                    final_tol=1e-9, minres_rtol=1e-8, max_newton=20)
+        for t in (0.3, 0.8):
+            s.set_load(t)
+            s.solve_step()
+        states.append(s.state())
+        s.close()
+    for a, b in zip(*states):
+        assert _rel(a, b) < 1e-7
+
+
 # ----------------------------------------------------------------------------- Newton composition
 
 def test_coupling_blocks_match_assembled():
