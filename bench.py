@@ -135,7 +135,11 @@ def time_kernels(solver, reps):
 # `bench.py --kernels-only`, scaled by the factor that maps the same counters
 # on the plain copy kernel to its known bytes.  Valid only for the kernel
 # sources they were taken on (sha256 over the files below).
-TRAFFIC = None
+TRAFFIC = {
+    # profiles/hbm_traffic_2048_at1.md: FETCH 139692.0 KiB x 1.9997 + WRITE 133353.0 KiB x 1.0000
+    "bytes": 422602886,
+    "source_sha256": "70ad7165402f26c61c2cd2bb25a0b277100f413cb2c116ee51a3952444c6f774",
+}
 TRAFFIC_SOURCES = ("paper_1511_08463_amd/csrc/common.h", "paper_1511_08463_amd/csrc/ops2d.h",
                    "paper_1511_08463_amd/csrc/kernels2d.hip")
 
