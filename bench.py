@@ -187,6 +187,7 @@ def main():
     ap.add_argument("--dt-factor", type=float, default=16.0, help="thermal ramp end in units of DT_c")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream sample")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-omega", action="store_true", help="skip the omega = 1.4, 1.8 legs")
     ap.add_argument("--kernels-only", action="store_true",
                     help="time the hot kernels only (no solve), e.g. under hardware counters")
     ap.add_argument("--instances", type=int, default=48)
@@ -217,8 +218,9 @@ def main():
         return
     p, notch, loads, (y0, a) = workloads.config2(args.model, args.omega, seed=0, n=args.n)
 
-    def make_solver(precision):
-        params = fracture.make_params(**p, am_tol=args.am_tol, pcg_rtol=args.pcg_rtol,
+    def make_solver(precision, omega=None):
+        pp = dict(p, omega=args.omega if omega is None else omega)
+        params = fracture.make_params(**pp, am_tol=args.am_tol, pcg_rtol=args.pcg_rtol,
                                       vi_cg_rtol=1e-10, max_am=5000, newton=args.newton,
                                       switch_tol=args.switch_tol, final_tol=args.final_tol,
                                       minres_rtol=args.minres_rtol,
@@ -241,11 +243,12 @@ def main():
 
     free_dofs = 2 * (args.n + 1) ** 2 - (args.n + 1) * 2 - 1
 
-    def leg(precision):
+    def leg(precision, omega=None):
         """W untimed + K timed load steps of one solver instance."""
-        log(f"[bench] {precision} {args.n}^2 {args.model} omega={args.omega} notch y0={y0:.4f} "
+        om = args.omega if omega is None else omega
+        log(f"[bench] {precision} {args.n}^2 {args.model} omega={om} notch y0={y0:.4f} "
             f"a={a:.4f} warmup={args.warmup} steps={args.steps}")
-        solver = make_solver(precision)
+        solver = make_solver(precision, om)
         last = [time.perf_counter()]
 
         def monitor(sweep, da, phi):
@@ -337,10 +340,22 @@ def main():
             "unit": "GB/s",
             "frac": dom["gbs"] / HBM_PEAK_GBS,
             "traffic": traffic,
+            "traffic_gbs": traffic / (dom["us"] * 1e-6) / 1e9 if traffic else None,
             "per_kernel_gbs": {k: round(v["gbs"], 1) for k, v in rl.items()},
             "per_kernel_us": {k: round(v["us"], 2) for k, v in rl.items()},
         },
     }
+    if not args.no_omega and args.precision == "fp64":
+        # the other over-relaxation factors of the workload, same load steps
+        out["omega_sweep"] = {}
+        for om in (1.4, 1.8):
+            if om == args.omega:
+                continue
+            s_om, r_om, _, _ = leg(args.precision, omega=om)
+            s_om.close()
+            out["omega_sweep"][f"{om:g}"] = {k: r_om[k] for k in ("value", "ms_per_step", "sweeps",
+                                                                  "pcg_iters", "newton_iters",
+                                                                  "minres_iters")}
     if not args.no_mixed and args.precision == "fp64":
         # the same load steps with the float32 operator and multigrid inside
         # float64 refinement, against the float64 run just made
