@@ -120,6 +120,13 @@ typedef struct {
                                coarsest solve of each V-cycle in one
                                workgroup with its data in LDS; 0: one kernel
                                per step.  Same per-node arithmetic.           */
+  int newton_precond;       /* Newton MINRES preconditioner: 0 the paper's
+                               symmetric multiplicative block form with
+                               S ~ C (eq. (preconditioner): two actions of
+                               A^{-1} and one of C^{-1}); 1 (default) the
+                               block-diagonal form diag(A^{-1}, C^{-1}), one
+                               of each, also SPD.  Both solve the same Newton
+                               system to the same tolerance.                  */
 } fracture_params;
 
 /* Fill *p with the documented defaults for a 2D tension problem on an

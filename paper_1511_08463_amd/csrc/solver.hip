@@ -165,6 +165,7 @@ int validate(const fracture_params* p) {
   if (p->use_graphs != 0 && p->use_graphs != 1) return FRACTURE_EINVAL;
   if (!(p->newton_forcing >= 0)) return FRACTURE_EINVAL;
   if (p->vcycle_tail != 0 && p->vcycle_tail != 1) return FRACTURE_EINVAL;
+  if (p->newton_precond != 0 && p->newton_precond != 1) return FRACTURE_EINVAL;
   if ((int64_t)(p->nx + 1) * (p->ny + 1) * (p->dim == 3 ? p->nz + 1 : 1) > (int64_t)1 << 29)
     return FRACTURE_EINVAL;
   return FRACTURE_OK;
@@ -887,6 +888,12 @@ void apply_P_body(fracture* h, const double* x, double* y) {
   const Grid& g = h->lv[0].g;
   const int64_t n2 = h->n2, N = h->N;
   Red none{};
+  if (h->p.newton_precond == 1) {
+    // block-diagonal variant: [A^{-1} x1; C^{-1} x2]
+    apply_Ainv(h, x, y);
+    apply_Cinv(h, x + n2, y + n2);
+    return;
+  }
   apply_Ainv(h, x, h->npu1);                                               // y1
   launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask,
                h->npu1, nullptr, nullptr, h->npa1, false, none, none, h->S + S_JLO);  // B^T y1
@@ -1185,6 +1192,7 @@ void fracture_default_params(fracture_params* p, int nx, int ny) {
   p->newton_forcing = 0.1;
   p->use_graphs = 1;
   p->vcycle_tail = 1;
+  p->newton_precond = 1;
 }
 
 size_t fracture_workspace_bytes(const fracture_params* p) {
