@@ -1,18 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark: quasi-static load steps of the 2048 x 2048 AT1 notched square.
 
-A "step" is one load step: set the next load, run the over-relaxed
-alternate minimisation (elastic PCG with multigrid, damage box-QP active set,
-relaxations) to its stop test, commit alpha_prev.  The workload is the
-2048^2 plane-strain unit square with a seeded edge notch (height and length
-drawn from U[0.1, 0.4]), ell = 4h, k_ell = 1e-6, loads t = 0.1 k.
-W warm-up load steps run untimed, then K load steps are timed
-(HIP-synchronised on both sides); value = K / seconds.
+A "step" is one load step: set the next load, run ORAM (over-relaxed
+alternate minimisation: elastic PCG with multigrid, damage box-QP active set,
+relaxation) and its composition with reduced-space Newton (Algorithm 3) to
+the stop test, commit alpha_prev.  The workload is the 2048^2 plane-strain
+unit square with a seeded edge notch (height and length drawn from
+U[0.1, 0.4]), ell = 4h, k_ell = 1e-6, loads t = 0.1 k.  W warm-up load steps
+run untimed (default 1: the notch forms its damage profile), then K load
+steps are timed (HIP-synchronised on both sides); value = K / seconds.  The
+default K = 13 covers the elastic loading, crack initiation (t = 1.0) and
+stable growth up to t = 1.4; the unstable propagation at t = 1.5 is not
+timed (ORAM advances that crack about one element per sweep).
 
-Also reported: PCG DOF-iterations per second, the roofline of the dominant
+Also reported: PCG DOF-iterations per second, the same steps in mixed
+precision and at omega = 1.4, 1.8 (shorter), the roofline of the dominant
 kernel (algorithmic bytes per launch over its mean duration, measured with
-HIP events on the solver's stream) and the CPU oracle timed on a bounded
-sample (rank 0 only).
+HIP events on the solver's stream) with its measured HBM traffic, the served
+stream (p50/p99 step latency) and the CPU oracle timed on a bounded sample.
 """
 
 import argparse
@@ -162,7 +167,7 @@ def recorded_traffic():
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4, help="timed load steps")
+    ap.add_argument("--steps", type=int, default=13, help="timed load steps")
     ap.add_argument("--warmup", type=int, default=1, help="untimed load steps first")
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--model", default="AT1")
@@ -191,19 +196,21 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream sample")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-omega", action="store_true", help="skip the omega = 1.4, 1.8 legs")
+    ap.add_argument("--omega-steps", type=int, default=4,
+                    help="timed load steps of the omega = 1.4, 1.8 legs (after the same warm-up)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="time the hot kernels only (no solve), e.g. under hardware counters")
     ap.add_argument("--instances", type=int, default=48)
     ap.add_argument("--budget-gb", type=float, default=4.0)
-    ap.add_argument("--workers", type=int, default=4)
-    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--slots", type=int, default=32)
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(the multi-GPU decomposition is a design, not built)"}))
         sys.exit(2)
-    if args.warmup + args.steps > 20:
+    if args.warmup + max(args.steps, args.omega_steps) > 20:
         sys.exit("warmup + steps must be <= 20 (the load sequence has 20 steps)")
 
     import numpy as np
@@ -247,11 +254,12 @@ def main():
 
     free_dofs = 2 * (args.n + 1) ** 2 - (args.n + 1) * 2 - 1
 
-    def leg(precision, omega=None):
+    def leg(precision, omega=None, steps=None):
         """W untimed + K timed load steps of one solver instance."""
         om = args.omega if omega is None else omega
+        nsteps = args.steps if steps is None else steps
         log(f"[bench] {precision} {args.n}^2 {args.model} omega={om} notch y0={y0:.4f} "
-            f"a={a:.4f} warmup={args.warmup} steps={args.steps}")
+            f"a={a:.4f} warmup={args.warmup} steps={nsteps}")
         solver = make_solver(precision, om)
         last = [time.perf_counter()]
 
@@ -279,14 +287,14 @@ def main():
             run(k)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        stats = [run(k) for k in range(args.warmup, args.warmup + args.steps)]
+        stats = [run(k) for k in range(args.warmup, args.warmup + nsteps)]
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         pcg_iters = sum(s["pcg_iters"] for s in stats)
         pcg_s = sum(s["ms_pcg"] for s in stats) / 1e3
         res = {
-            "value": args.steps / elapsed,
-            "ms_per_step": 1e3 * elapsed / args.steps,
+            "value": nsteps / elapsed,
+            "ms_per_step": 1e3 * elapsed / nsteps,
             "pcg_dof_iter_per_s": free_dofs * pcg_iters / pcg_s if pcg_s > 0 else None,
             "sweeps": sum(s["sweeps"] for s in stats),
             "pcg_iters": pcg_iters,
@@ -356,11 +364,13 @@ def main():
         for om in (1.4, 1.8):
             if om == args.omega:
                 continue
-            s_om, r_om, _, _ = leg(args.precision, omega=om)
+            s_om, r_om, _, _ = leg(args.precision, omega=om, steps=args.omega_steps)
             s_om.close()
             out["omega_sweep"][f"{om:g}"] = {k: r_om[k] for k in ("value", "ms_per_step", "sweeps",
                                                                   "pcg_iters", "newton_iters",
                                                                   "minres_iters")}
+            out["omega_sweep"][f"{om:g}"]["load_steps"] = (
+                f"{args.warmup + 1}..{args.warmup + args.omega_steps}")
     if not args.no_mixed and args.precision == "fp64":
         # the same load steps with the float32 operator and multigrid inside
         # float64 refinement, against the float64 run just made

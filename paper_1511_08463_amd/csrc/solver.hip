@@ -114,8 +114,8 @@ struct fracture {
   // first level of the single-workgroup V-cycle tail per value type (-1: none)
   int tail64 = -1, tail32 = -1;
   // host side
-  double* hS = nullptr;  // pinned copy of the scalar array
-  hipEvent_t ev[8] = {};
+  double* hS = nullptr;  // pinned copy of the scalar array (+ 2 lagged-read slots)
+  hipEvent_t ev[10] = {};  // 0..7 timing, 8..9 lagged scalar reads
   double load = 0.0;
   double bnorm = 0.0;
   fracture_monitor_fn monitor = nullptr;
@@ -397,6 +397,24 @@ int read_scalars(fracture* h) {
   if (h->graph_error) return FRACTURE_EDEVICE;
   HIPCHK(hipMemcpyAsync(h->hS, h->S, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
+  return FRACTURE_OK;
+}
+
+// Lagged read of one device scalar: the value of S[slot] after iteration k
+// is copied to pinned slot k % 2 behind an event, and the host waits for
+// iteration k - 1's value while iteration k is already queued, so the device
+// does not idle on the host's convergence test (at the price of one extra
+// iteration once the test passes).
+void lag_post(fracture* h, int slot, int k) {
+  (void)hipMemcpyAsync(h->hS + S_COUNT + (k & 1), h->S + slot, sizeof(double),
+                       hipMemcpyDeviceToHost, h->st);
+  (void)hipEventRecord(h->ev[8 + (k & 1)], h->st);
+}
+
+int lag_get(fracture* h, int k, double* v) {
+  if (h->graph_error) return FRACTURE_EDEVICE;
+  HIPCHK(hipEventSynchronize(h->ev[8 + (k & 1)]));
+  *v = h->hS[S_COUNT + (k & 1)];
   return FRACTURE_OK;
 }
 
@@ -731,16 +749,21 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
     const double r0 = any_inactive ? std::sqrt(h->hS[S_TMP2]) : 0.0;
     const double tol = h->p.vi_cg_rtol * r0;
     if (r0 > 0) {
+      // CG scalars live on the device; the host tests ||r|| one iteration
+      // late (lag_post / lag_get)
       for (int k = 1; k <= h->p.max_vi_cg; ++k) {
         launch_helm_apply2d(st, g, h->cL, h->cM, h->w2, h->vp, h->mask, h->vq, true,
                             red(h, 2, S_PQ, P_CG_ALPHA), j0, j1);
         launch_cg_update(st, cnt, vd, vr, vp, vq, h->S, red(h, 3, S_RR));
-        rc = read_scalars(h);
-        if (rc) return rc;
         ++*cg_iters;
-        const double rr = h->hS[S_RR];
-        if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
-        if (std::sqrt(rr) <= tol) break;
+        lag_post(h, S_RR, k);
+        if (k > 1) {
+          double rr = 0;
+          rc = lag_get(h, k - 1, &rr);
+          if (rc) return rc;
+          if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
+          if (std::sqrt(rr) <= tol) break;
+        }
         launch_jacobi_dot(st, cnt, vr, hd, vz, red(h, 4, S_RZNEW, P_CG_BETA));
         launch_xpby(st, cnt, vz, vp, h->S);
       }
@@ -1259,14 +1282,17 @@ int fracture_create(const fracture_params* p, const uint8_t* notch_mask, void* d
       rh = rn;
     }
   }
-  if (hipHostMalloc((void**)&h->hS, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&h->hS, (S_COUNT + 2) * sizeof(double), hipHostMallocDefault) !=
+      hipSuccess) {
     delete h;
     return FRACTURE_EDEVICE;
   }
-  for (int k = 0; k < 8; ++k) {
-    if (hipEventCreate(&h->ev[k]) != hipSuccess) {
-      (void)hipHostFree(h->hS);
-      delete h;
+  for (int k = 0; k < 10; ++k) {
+    const hipError_t e = k < 8 ? hipEventCreate(&h->ev[k])
+                               : hipEventCreateWithFlags(&h->ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      h->ev[k] = nullptr;
+      fracture_destroy(h);
       return FRACTURE_EDEVICE;
     }
   }
@@ -1532,7 +1558,7 @@ void fracture_destroy(fracture_t h) {
   for (Captured& c : h->graphs) (void)hipGraphExecDestroy(c.exec);
   h->graphs.clear();
   if (h->cap) (void)hipStreamDestroy(h->cap);
-  for (int k = 0; k < 8; ++k)
+  for (int k = 0; k < 10; ++k)
     if (h->ev[k]) (void)hipEventDestroy(h->ev[k]);
   if (h->hS) (void)hipHostFree(h->hS);
   delete h;
