@@ -31,9 +31,16 @@ enum { BC_TENSION_2D = 0, BC_THERMAL_3D = 1 };
 enum {
   S_RZ = 0, S_PQ, S_ALPHA, S_RR, S_BETA, S_RZNEW, S_MU,
   S_PHI2, S_PHIMAX, S_DAMAX, S_EL, S_SURF, S_EU2, S_TMP0, S_TMP1, S_TMP2,
-  S_RATIO, S_INFEAS, S_GG, S_JLO, S_JHI, S_MR0, S_MR1, S_MR2, S_MR3, S_MR4, S_MR5, S_MR6, S_MR7,
+  S_RATIO, S_INFEAS, S_GG, S_JLO, S_JHI,
+  // MINRES recurrence (Lanczos scalars, Givens rotations, vector coefficients)
+  S_MN_G, S_MN_GP, S_MN_G1, S_MN_C, S_MN_CP, S_MN_S, S_MN_SP, S_MN_ETA, S_MN_D,
+  S_MN_L0, S_MN_L1, S_MN_L2, S_MN_U0, S_MN_U1, S_MN_U2, S_MN_U3,
+  S_MN_ABSETA, S_MN_GN, S_MN_BAD,
   S_COUNT = 64
 };
+static_assert(S_MN_BAD < S_COUNT, "scalar slots");
+// the host reads |eta|, gamma_{j+1} and the non-finite flag of MINRES as one block
+static_assert(S_MN_GN == S_MN_ABSETA + 1 && S_MN_BAD == S_MN_ABSETA + 2, "MINRES status slots");
 // kernels read the inactive row band as the pair (S[S_JLO], S[S_JHI])
 static_assert(S_JHI == S_JLO + 1, "band slots must be adjacent");
 // Partial-sum slots: one per reduction that may be pending at the same time.

@@ -148,10 +148,13 @@ void launch_dot_f(hipStream_t st, int64_t n, const float* a, const float* b, Red
 void launch_to_float(hipStream_t st, int64_t n, const double* x, float* y, double scale);
 void launch_add_scaled_f(hipStream_t st, int64_t n, double* x, const float* e, double scale);
 void launch_copy(hipStream_t st, int64_t n, const double* x, double* y);
-void launch_lincomb3(hipStream_t st, int64_t n, double a, double* z, double b, const double* x,
-                     double c, const double* y);
-void launch_minres_update(hipStream_t st, int64_t n, double a, const double* z, double b,
-                          double* w2, double c, const double* w1, double e, double* x);
+void launch_minres_init(hipStream_t st, double* S);
+void launch_minres_a(hipStream_t st, double* S);
+void launch_minres_b(hipStream_t st, double* S);
+void launch_lincomb3_s(hipStream_t st, int64_t n, const double* S, double* z, const double* x,
+                       const double* y);
+void launch_minres_update_s(hipStream_t st, int64_t n, const double* S, const double* z,
+                            double* w2, const double* w1, double* x);
 void launch_from_float(hipStream_t st, int64_t n, const float* e, double* x, double scale);
 
 }  // namespace frac

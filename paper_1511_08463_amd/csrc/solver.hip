@@ -114,7 +114,7 @@ struct fracture {
   // first level of the single-workgroup V-cycle tail per value type (-1: none)
   int tail64 = -1, tail32 = -1;
   // host side
-  double* hS = nullptr;  // pinned copy of the scalar array (+ 2 lagged-read slots)
+  double* hS = nullptr;  // pinned copy of the scalar array (+ two lagged-read slots)
   hipEvent_t ev[10] = {};  // 0..7 timing, 8..9 lagged scalar reads
   double load = 0.0;
   double bnorm = 0.0;
@@ -400,21 +400,22 @@ int read_scalars(fracture* h) {
   return FRACTURE_OK;
 }
 
-// Lagged read of one device scalar: the value of S[slot] after iteration k
-// is copied to pinned slot k % 2 behind an event, and the host waits for
-// iteration k - 1's value while iteration k is already queued, so the device
-// does not idle on the host's convergence test (at the price of one extra
-// iteration once the test passes).
-void lag_post(fracture* h, int slot, int k) {
-  (void)hipMemcpyAsync(h->hS + S_COUNT + (k & 1), h->S + slot, sizeof(double),
+// Lagged read of device scalars: the block S[slot .. slot + count) after
+// iteration k is copied to pinned slot k % 2 behind an event, and the host
+// waits for iteration k - 1's (or k's) values while later work is already
+// queued, so the device does not idle on the host's convergence test.
+constexpr int LAG_W = 4;   // doubles per pinned slot
+
+void lag_post(fracture* h, int slot, int count, int k) {
+  (void)hipMemcpyAsync(h->hS + S_COUNT + LAG_W * (k & 1), h->S + slot, count * sizeof(double),
                        hipMemcpyDeviceToHost, h->st);
   (void)hipEventRecord(h->ev[8 + (k & 1)], h->st);
 }
 
-int lag_get(fracture* h, int k, double* v) {
+int lag_get(fracture* h, int k, int count, double* v) {
   if (h->graph_error) return FRACTURE_EDEVICE;
   HIPCHK(hipEventSynchronize(h->ev[8 + (k & 1)]));
-  *v = h->hS[S_COUNT + (k & 1)];
+  for (int q = 0; q < count; ++q) v[q] = h->hS[S_COUNT + LAG_W * (k & 1) + q];
   return FRACTURE_OK;
 }
 
@@ -756,10 +757,10 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
                             red(h, 2, S_PQ, P_CG_ALPHA), j0, j1);
         launch_cg_update(st, cnt, vd, vr, vp, vq, h->S, red(h, 3, S_RR));
         ++*cg_iters;
-        lag_post(h, S_RR, k);
+        lag_post(h, S_RR, 1, k);
         if (k > 1) {
           double rr = 0;
-          rc = lag_get(h, k - 1, &rr);
+          rc = lag_get(h, k - 1, 1, &rr);
           if (rc) return rc;
           if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
           if (std::sqrt(rr) <= tol) break;
@@ -943,14 +944,12 @@ void apply_J(fracture* h, const double* x, double* y) {
                x + n2, y, y + n2, true, red(h, 7, S_TMP0), red(h, 8, S_TMP1), h->S + S_JLO);
 }
 
-double dot3(fracture* h, const double* a, const double* b) {
-  launch_dot(h->st, 3 * h->N, a, b, red(h, 9, S_TMP2));
-  if (read_scalars(h)) return NAN;
-  return h->hS[S_TMP2];
-}
-
 // MINRES (preconditioned; the three-term Lanczos recurrence with Givens
-// rotations) for J d = rhs, rhs in nv.  Solution in nx.
+// rotations) for J d = rhs, rhs in nv.  Solution in nx.  The recurrence
+// scalars live on the device (k_minres_a / k_minres_b), so the host only
+// enqueues; it reads |eta| one step late through a pinned copy, and while it
+// waits the device already applies J for the next iteration (discarded when
+// the test passes).
 int minres(fracture* h, double rtol, int* iters) {
   hipStream_t st = h->st;
   const int64_t n3 = 3 * h->N;
@@ -960,48 +959,39 @@ int minres(fracture* h, double rtol, int* iters) {
   HIPCHK(hipMemsetAsync(h->nw, 0, n3 * sizeof(double), st));
   double *v_prev = h->nv_prev, *v = h->nv, *az = h->naz, *z = h->nz, *w_prev = h->nw_prev,
          *w = h->nw;
+  *iters = 0;
   apply_P(h, v, z);
-  double g = dot3(h, z, v);
-  if (!std::isfinite(g)) return FRACTURE_ENONFINITE;
-  if (g <= 0.0) { *iters = 0; return FRACTURE_OK; }
-  g = std::sqrt(g);
-  const double g1 = g;
-  double g_prev = 1.0, eta = g, s_prev = 0.0, s = 0.0, c_prev = 1.0, c = 1.0;
+  launch_dot(st, n3, z, v, red(h, 9, S_TMP2));
+  launch_minres_init(st, h->S);
+  int rc = read_scalars(h);
+  if (rc) return rc;
+  if (h->hS[S_MN_BAD] != 0.0) return FRACTURE_ENONFINITE;
+  const double g1 = h->hS[S_MN_G1];
+  if (!(g1 > 0.0)) return FRACTURE_OK;
+  apply_J(h, z, az);                                             // az = J z, S = z.J z
   for (int j = 1; j <= h->p.max_minres; ++j) {
-    // z holds z_j unnormalised (the normalised vector is z / g)
-    apply_J(h, z, az);                                           // az = J z, S = z.J z
-    int rc = read_scalars(h);
-    if (rc) return rc;
-    const double d = (h->hS[S_TMP0] + h->hS[S_TMP1]) / (g * g);
-    // v_{j+1} = J z/g - (d/g) v_j - (g/g_prev) v_{j-1}, in az
-    launch_lincomb3(st, n3, 1.0 / g, az, -d / g, v, -g / g_prev, v_prev);
+    launch_minres_a(st, h->S);
+    launch_lincomb3_s(st, n3, h->S, az, v, v_prev);              // az = v_{j+1}
     double* vn = az;
     apply_P(h, vn, v_prev);                                      // v_prev buffer <- z_{j+1}
     double* zn = v_prev;
-    const double gn2 = dot3(h, zn, vn);
-    if (!std::isfinite(gn2) || !std::isfinite(d)) return FRACTURE_ENONFINITE;
-    const double gn = std::sqrt(gn2 > 0 ? gn2 : 0.0);
-    const double a0 = c * d - c_prev * s * g;
-    const double a1 = std::sqrt(a0 * a0 + gn * gn);
-    const double a2 = s * d + c_prev * c * g;
-    const double a3 = s_prev * g;
-    const double cn = a0 / a1, sn = gn / a1;
-    // w_{j+1} = (z/g - a3 w_{j-1} - a2 w_j) / a1 into w_prev; x += cn eta w_{j+1}
-    launch_minres_update(st, n3, 1.0 / (a1 * g), z, -a3 / a1, w_prev, -a2 / a1, w, cn * eta,
-                         h->nx);
-    eta = -sn * eta;
+    launch_dot(st, n3, zn, vn, red(h, 9, S_TMP2));
+    launch_minres_b(st, h->S);
+    launch_minres_update_s(st, n3, h->S, z, w_prev, w, h->nx);   // w_prev <- w_{j+1}; x update
+    lag_post(h, S_MN_ABSETA, 3, j);
     // rotate buffers
-    double* old_v = v;
-    v_prev = old_v;            // v_{j}
+    v_prev = v;                // v_{j}
     v = vn;                    // v_{j+1}
     az = z;                    // free buffer
     z = zn;                    // z_{j+1}
     std::swap(w_prev, w);      // w <- w_{j+1}, w_prev <- w_j
-    g_prev = g; g = gn;
-    c_prev = c; c = cn;
-    s_prev = s; s = sn;
     *iters = j;
-    if (std::fabs(eta) <= rtol * g1 || gn == 0.0) return FRACTURE_OK;
+    if (j < h->p.max_minres) apply_J(h, z, az);                  // next iteration's J z
+    double stat[3];
+    rc = lag_get(h, j, 3, stat);
+    if (rc) return rc;
+    if (stat[2] != 0.0) return FRACTURE_ENONFINITE;
+    if (stat[0] <= rtol * g1 || stat[1] == 0.0) return FRACTURE_OK;
   }
   return FRACTURE_OK;  // an inexact Newton direction is still tried by the line search
 }
@@ -1282,7 +1272,7 @@ int fracture_create(const fracture_params* p, const uint8_t* notch_mask, void* d
       rh = rn;
     }
   }
-  if (hipHostMalloc((void**)&h->hS, (S_COUNT + 2) * sizeof(double), hipHostMallocDefault) !=
+  if (hipHostMalloc((void**)&h->hS, (S_COUNT + 2 * LAG_W) * sizeof(double), hipHostMallocDefault) !=
       hipSuccess) {
     delete h;
     return FRACTURE_EDEVICE;

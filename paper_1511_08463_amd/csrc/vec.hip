@@ -136,24 +136,105 @@ void launch_copy(hipStream_t st, int64_t n, const double* x, double* y) {
   hipLaunchKernelGGL(k_copy, dim3(vgrid(n)), dim3(VB), 0, st, n, x, y);
 }
 
-// z = a z + b x + c y
-__global__ __launch_bounds__(VB) void k_lincomb3(int64_t n, double a, double* __restrict__ z,
-                                                 double b, const double* __restrict__ x, double c,
-                                                 const double* __restrict__ y) {
+// ---------------------------------------------------------------------------
+// MINRES on the device: the scalar recurrence (preconditioned Lanczos with
+// Givens rotations, as in the host form it replaces) runs in one-thread
+// kernels between the vector kernels, which read their coefficients from S.
+// ---------------------------------------------------------------------------
+
+// gamma_1 = sqrt(z_1 . v_1) from S_TMP2; rotations and eta initialised.
+__global__ void k_minres_init(double* S) {
+  if (threadIdx.x != 0) return;
+  const double gg = S[S_TMP2];
+  const double g = gg > 0.0 ? sqrt(gg) : 0.0;
+  S[S_MN_G] = g;
+  S[S_MN_G1] = g;
+  S[S_MN_GP] = 1.0;
+  S[S_MN_ETA] = g;
+  S[S_MN_ABSETA] = g;
+  S[S_MN_GN] = g;
+  S[S_MN_C] = 1.0;
+  S[S_MN_CP] = 1.0;
+  S[S_MN_S] = 0.0;
+  S[S_MN_SP] = 0.0;
+  S[S_MN_BAD] = isfinite(gg) ? 0.0 : 1.0;
+}
+
+// after J z_j (z_j unnormalised; S_TMP0 + S_TMP1 = z_j . J z_j):
+// delta = z.Jz / gamma^2 and the coefficients of
+// v_{j+1} = J z_j / gamma - (delta / gamma) v_j - (gamma / gamma_prev) v_{j-1}
+__global__ void k_minres_a(double* S) {
+  if (threadIdx.x != 0) return;
+  const double g = S[S_MN_G], gp = S[S_MN_GP];
+  const double d = (S[S_TMP0] + S[S_TMP1]) / (g * g);
+  S[S_MN_D] = d;
+  S[S_MN_L0] = 1.0 / g;
+  S[S_MN_L1] = -d / g;
+  S[S_MN_L2] = -g / gp;
+  if (!isfinite(d)) S[S_MN_BAD] = 1.0;
+}
+
+// after z_{j+1} = P v_{j+1} and S_TMP2 = z_{j+1} . v_{j+1}: the next Givens
+// rotation, the coefficients of w_{j+1} = (z_j / gamma - a3 w_{j-1} - a2 w_j) / a1
+// and of x += c_{j+1} eta w_{j+1}, then eta and the scalars shift by one.
+__global__ void k_minres_b(double* S) {
+  if (threadIdx.x != 0) return;
+  const double g = S[S_MN_G], d = S[S_MN_D], c = S[S_MN_C], cp = S[S_MN_CP];
+  const double s = S[S_MN_S], sp = S[S_MN_SP], eta = S[S_MN_ETA], gn2 = S[S_TMP2];
+  const double gn = sqrt(gn2 > 0.0 ? gn2 : 0.0);
+  const double a0 = c * d - cp * s * g;
+  const double a1 = sqrt(a0 * a0 + gn * gn);
+  const double a2 = s * d + cp * c * g;
+  const double a3 = sp * g;
+  const double cn = a0 / a1, sn = gn / a1;
+  S[S_MN_U0] = 1.0 / (a1 * g);
+  S[S_MN_U1] = -a3 / a1;
+  S[S_MN_U2] = -a2 / a1;
+  S[S_MN_U3] = cn * eta;
+  const double etan = -sn * eta;
+  S[S_MN_ETA] = etan;
+  S[S_MN_ABSETA] = fabs(etan);
+  S[S_MN_GN] = gn;
+  S[S_MN_GP] = g;
+  S[S_MN_G] = gn;
+  S[S_MN_CP] = c;
+  S[S_MN_C] = cn;
+  S[S_MN_SP] = s;
+  S[S_MN_S] = sn;
+  if (!isfinite(gn2)) S[S_MN_BAD] = 1.0;
+}
+
+void launch_minres_init(hipStream_t st, double* S) {
+  hipLaunchKernelGGL(k_minres_init, dim3(1), dim3(WAVE), 0, st, S);
+}
+void launch_minres_a(hipStream_t st, double* S) {
+  hipLaunchKernelGGL(k_minres_a, dim3(1), dim3(WAVE), 0, st, S);
+}
+void launch_minres_b(hipStream_t st, double* S) {
+  hipLaunchKernelGGL(k_minres_b, dim3(1), dim3(WAVE), 0, st, S);
+}
+
+// z = L0 z + L1 x + L2 y with the coefficients in S
+__global__ __launch_bounds__(VB) void k_lincomb3_s(int64_t n, const double* __restrict__ S,
+                                                   double* __restrict__ z,
+                                                   const double* __restrict__ x,
+                                                   const double* __restrict__ y) {
+  const double a = S[S_MN_L0], b = S[S_MN_L1], c = S[S_MN_L2];
   GRID_STRIDE(k, n) z[k] = a * z[k] + b * x[k] + c * y[k];
 }
 
-void launch_lincomb3(hipStream_t st, int64_t n, double a, double* z, double b, const double* x,
-                     double c, const double* y) {
-  hipLaunchKernelGGL(k_lincomb3, dim3(vgrid(n)), dim3(VB), 0, st, n, a, z, b, x, c, y);
+void launch_lincomb3_s(hipStream_t st, int64_t n, const double* S, double* z, const double* x,
+                       const double* y) {
+  hipLaunchKernelGGL(k_lincomb3_s, dim3(vgrid(n)), dim3(VB), 0, st, n, S, z, x, y);
 }
 
-// MINRES direction and iterate: w2 = a z + b w2 + c w1; x += e w2
-__global__ __launch_bounds__(VB) void k_minres_update(int64_t n, double a,
-                                                      const double* __restrict__ z, double b,
-                                                      double* __restrict__ w2, double c,
-                                                      const double* __restrict__ w1, double e,
-                                                      double* __restrict__ x) {
+// w2 = U0 z + U1 w2 + U2 w1; x += U3 w2 with the coefficients in S
+__global__ __launch_bounds__(VB) void k_minres_update_s(int64_t n, const double* __restrict__ S,
+                                                        const double* __restrict__ z,
+                                                        double* __restrict__ w2,
+                                                        const double* __restrict__ w1,
+                                                        double* __restrict__ x) {
+  const double a = S[S_MN_U0], b = S[S_MN_U1], c = S[S_MN_U2], e = S[S_MN_U3];
   GRID_STRIDE(k, n) {
     const double wn = a * z[k] + b * w2[k] + c * w1[k];
     w2[k] = wn;
@@ -161,9 +242,9 @@ __global__ __launch_bounds__(VB) void k_minres_update(int64_t n, double a,
   }
 }
 
-void launch_minres_update(hipStream_t st, int64_t n, double a, const double* z, double b,
-                          double* w2, double c, const double* w1, double e, double* x) {
-  hipLaunchKernelGGL(k_minres_update, dim3(vgrid(n)), dim3(VB), 0, st, n, a, z, b, w2, c, w1, e, x);
+void launch_minres_update_s(hipStream_t st, int64_t n, const double* S, const double* z,
+                            double* w2, const double* w1, double* x) {
+  hipLaunchKernelGGL(k_minres_update_s, dim3(vgrid(n)), dim3(VB), 0, st, n, S, z, w2, w1, x);
 }
 
 // S[slot] = ||x||^2 or max|x| (NaN -> inf)
