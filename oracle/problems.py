@@ -8,6 +8,12 @@ eigenstrain and the damage bounds:
   u_y = 0 on the bottom edge, u_y = t on the top edge, lateral edges free.
   The x-translation left free by these conditions is removed by u_x = 0 at
   the node (0, 0).
+* Surfing (Sec. 4.1): the slab [0, lx] x [0, ly] (the paper's
+  [0, L] x [-H/2, H/2] shifted by H/2) with u = u_bar(x - Lc - v t, y - ly/2)
+  on the whole boundary, u_bar the asymptotic Mode-I crack-tip displacement
+  of eq. (surfingloading) with kappa = (3 - nu)/(1 + nu) as printed.  On the
+  crack line behind the tip (y = ly/2, x < Lc + v t) the two crack faces
+  carry opposite u_y; a boundary node there takes their mean, u = 0.
 * 3D thermal shock with an exponential temperature profile through x
   (a variant of Sec. 4.3, eqs. (energytshock), (tempfielderfc)): eps0 =
   -DT exp(-x / depth) I evaluated at each tetrahedron's centroid (beta = 1),
@@ -59,6 +65,49 @@ def tension_2d(nx, ny, lx=1.0, ly=1.0, E=1.0, nu=0.3, Gc=1.0, ell=0.05, k_ell=1e
         return v
 
     return Problem(M, fixed, dirichlet)
+
+
+def mode_i_displacement(X, Y, KI, E, nu):
+    """u_bar of eq. (surfingloading): K_I / (2 mu) sqrt(r / 2pi)
+    (kappa - cos theta) (cos(theta/2), sin(theta/2)), (r, theta) the polar
+    coordinates of (X, Y) about the crack tip, theta in (-pi, pi]; zero on
+    the crack line behind the tip (the mean of the two faces)."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    mu = E / (2.0 * (1.0 + nu))
+    kappa = (3.0 - nu) / (1.0 + nu)
+    r = np.hypot(X, Y)
+    theta = np.arctan2(Y, X)
+    f = KI / (2.0 * mu) * np.sqrt(r / (2.0 * np.pi)) * (kappa - np.cos(theta))
+    ux = f * np.cos(0.5 * theta)
+    uy = f * np.sin(0.5 * theta)
+    on_faces = (Y == 0.0) & (X < 0.0)
+    ux = np.where(on_faces, 0.0, ux)
+    uy = np.where(on_faces, 0.0, uy)
+    return ux, uy
+
+
+def surfing_2d(nx, ny, lx=2.0, ly=1.0, KI=1.0, v=1.0, Lc=0.05, E=1.0, nu=0.3, Gc=1.0,
+               ell=0.05, k_ell=1e-6, model="AT1", plane_stress=True):
+    X, T = mesh.structured_mesh_2d(nx, ny, lx, ly)
+    M = fem.Model(X, T, E=E, nu=nu, Gc=Gc, ell=ell, k_ell=k_ell, model=model,
+                  plane_stress=plane_stress)
+    N = M.N
+    x, y = X[:, 0], X[:, 1]
+    edge = (np.isclose(x, 0.0) | np.isclose(x, lx) | np.isclose(y, 0.0) | np.isclose(y, ly))
+    fixed = np.concatenate([edge, edge])
+
+    def dirichlet(t):
+        ux, uy = mode_i_displacement(x - Lc - v * t, y - 0.5 * ly, KI, E, nu)
+        return np.concatenate([np.where(edge, ux, 0.0), np.where(edge, uy, 0.0)])
+
+    return Problem(M, fixed, dirichlet)
+
+
+def surfing_notch(nx, ny, lx=2.0, ly=1.0, Lc=0.05):
+    """The preexisting crack: nodes of the mid line y = ly/2 with x <= Lc."""
+    X, _ = mesh.structured_mesh_2d(nx, ny, lx, ly)
+    return np.isclose(X[:, 1], 0.5 * ly) & (X[:, 0] <= Lc + 1e-12)
 
 
 def thermal_3d(nx, ny, nz, lx=1.0, ly=1.0, lz=0.25, E=1.0, nu=0.3, Gc=1.0, ell=None,
