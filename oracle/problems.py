@@ -96,9 +96,12 @@ def surfing_2d(nx, ny, lx=2.0, ly=1.0, KI=1.0, v=1.0, Lc=0.05, E=1.0, nu=0.3, Gc
     x, y = X[:, 0], X[:, 1]
     edge = (np.isclose(x, 0.0) | np.isclose(x, lx) | np.isclose(y, 0.0) | np.isclose(y, ly))
     fixed = np.concatenate([edge, edge])
+    # height above the mid line from the integer row index (exactly 0 on it)
+    jrow = np.rint(y / (ly / ny))
+    ymid = (2.0 * jrow - ny) * (0.5 * ly / ny)
 
     def dirichlet(t):
-        ux, uy = mode_i_displacement(x - Lc - v * t, y - 0.5 * ly, KI, E, nu)
+        ux, uy = mode_i_displacement(x - Lc - v * t, ymid, KI, E, nu)
         return np.concatenate([np.where(edge, ux, 0.0), np.where(edge, uy, 0.0)])
 
     return Problem(M, fixed, dirichlet)
