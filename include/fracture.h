@@ -60,6 +60,14 @@ extern "C" {
                                        element centroid (Sec. 4.3 variant);
                                        u_x = 0 on x = lx; u_y = u_z = 0 at
                                        (lx,0,0); u_z = 0 at (lx,ly,0)        */
+#define FRACTURE_LOAD_SURFING_2D 2  /* surfing (Sec. 4.1): the whole boundary
+                                       carries the asymptotic Mode-I crack
+                                       displacement of eq. (surfingloading)
+                                       about the tip (surf_lc + surf_v t,
+                                       ly/2), kappa = (3-nu)/(1+nu) as
+                                       printed; load = t.  On the crack line
+                                       behind the tip the boundary node takes
+                                       the mean of the two faces (zero).     */
 
 #define FRACTURE_RELAX_PROJECT 0  /* alpha <- clip(alpha + omega*dalpha)       */
 #define FRACTURE_RELAX_RATIO   1  /* largest common feasible omega_bar <= omega */
@@ -82,6 +90,9 @@ typedef struct {
   double E, nu, Gc, ell, k_ell;
   int load_kind;            /* FRACTURE_LOAD_*                                 */
   double thermal_depth;     /* decay length of the thermal eigenstrain         */
+  double surf_ki;           /* surfing: stress intensity factor K_I            */
+  double surf_v;            /* surfing: crack-tip speed v                      */
+  double surf_lc;           /* surfing: initial tip abscissa L_c               */
   int precision;            /* FRACTURE_FP64 | FRACTURE_MIXED                  */
   double omega;             /* over-relaxation, in (0, 2) (Algorithm 2)        */
   int relax_mode;           /* FRACTURE_RELAX_*                                */

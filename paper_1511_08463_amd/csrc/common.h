@@ -25,7 +25,17 @@ constexpr int VB = 256;           // 1D vector kernels
 constexpr int VGRID = 2048;       // fixed grid of 1D reductions (8 blocks per CU)
 
 // Boundary-condition families (mirrors FRACTURE_LOAD_* of the C ABI).
-enum { BC_TENSION_2D = 0, BC_THERMAL_3D = 1 };
+enum { BC_TENSION_2D = 0, BC_THERMAL_3D = 1, BC_SURFING_2D = 2 };
+
+// Parameters of the 2D Dirichlet lifting: for the surfing load, the boundary
+// carries K_I/(2 mu) sqrt(r/2pi) (kappa - cos theta) (cos(theta/2), sin(theta/2))
+// about the tip (lc + v t, ly/2).
+struct Load2D {
+  int kind;          // BC_TENSION_2D or BC_SURFING_2D
+  double ki2mu;      // K_I / (2 mu)
+  double kappa;      // (3 - nu) / (1 + nu)
+  double lc, v;      // initial tip abscissa and speed
+};
 
 // Indices of device-resident scalars (an array of doubles in the workspace).
 enum {

@@ -283,8 +283,35 @@ __global__ __launch_bounds__(VB) void k_lift2d(Grid g, double* __restrict__ u, d
   if (i == 0) u[0] = 0.0;
 }
 
-void launch_lift2d(hipStream_t st, const Grid& g, double* u, double t) {
+// Surfing (Sec. 4.1, eq. (surfingloading)): every boundary node takes the
+// asymptotic Mode-I displacement about the tip (lc + v t, ly/2); on the crack
+// line behind the tip the two faces' values average to zero.  The height
+// above the mid line is formed from the integer row index, exactly zero on it.
+__global__ __launch_bounds__(VB) void k_lift_surf2d(Grid g, Load2D ld, double* __restrict__ u,
+                                                    double t) {
+  const int n = blockIdx.x * VB + threadIdx.x;
+  if (n >= g.N) return;
+  const int W = g.nx + 1, i = n % W, j = n / W;
+  if (!(i == 0 || i == g.nx || j == 0 || j == g.ny)) return;
+  const double X = i * g.hx - ld.lc - ld.v * t;
+  const double Y = (2.0 * j - g.ny) * (0.5 * g.hy);
+  double ux = 0.0, uy = 0.0;
+  if (!(Y == 0.0 && X < 0.0)) {
+    const double r = hypot(X, Y), th = atan2(Y, X);
+    const double f = ld.ki2mu * sqrt(r / (2.0 * M_PI)) * (ld.kappa - cos(th));
+    ux = f * cos(0.5 * th);
+    uy = f * sin(0.5 * th);
+  }
+  u[n] = ux;
+  u[g.N + n] = uy;
+}
+
+void launch_lift2d(hipStream_t st, const Grid& g, double* u, double t, const Load2D& ld) {
   if (g.dim == 3) return launch_lift3d(st, g, u);
+  if (ld.kind == BC_SURFING_2D) {
+    hipLaunchKernelGGL(k_lift_surf2d, dim3((g.N + VB - 1) / VB), dim3(VB), 0, st, g, ld, u, t);
+    return;
+  }
   hipLaunchKernelGGL(k_lift2d, dim3((g.nx + 1 + VB - 1) / VB), dim3(VB), 0, st, g, u, t);
 }
 

@@ -25,7 +25,7 @@ template <class T>
 void launch_restrict2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* rf, T* bc);
 template <class T>
 void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* xc, T* xf);
-void launch_lift2d(hipStream_t st, const Grid& g, double* u, double t);
+void launch_lift2d(hipStream_t st, const Grid& g, double* u, double t, const Load2D& ld);
 void launch_w2_2d(hipStream_t st, const Grid& g, const Mat& m, const double* u, double* w2);
 void launch_vi_eval2d(hipStream_t st, const Grid& g, double cL, double cM, double cm,
                       const double* w2, const double* a, const double* d, const double* lo,

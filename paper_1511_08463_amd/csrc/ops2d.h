@@ -11,10 +11,17 @@ namespace frac {
 // boundary conditions
 // ---------------------------------------------------------------------------
 
+// tension: u_x at node (0,0), u_y on the bottom and top edges;
+// surfing: both components on the whole boundary
+__device__ __forceinline__ bool on_edge2(const Grid& g, int i, int j) {
+  return i == 0 || i == g.nx || j == 0 || j == g.ny;
+}
 __device__ __forceinline__ bool fixed_x2(const Grid& g, int i, int j) {
+  if (g.bc == BC_SURFING_2D) return on_edge2(g, i, j);
   return (g.bc == BC_TENSION_2D) && i == 0 && j == 0;
 }
 __device__ __forceinline__ bool fixed_y2(const Grid& g, int i, int j) {
+  if (g.bc == BC_SURFING_2D) return on_edge2(g, i, j);
   return (g.bc == BC_TENSION_2D) && (j == 0 || j == g.ny);
 }
 

@@ -118,6 +118,7 @@ struct fracture {
   hipEvent_t ev[10] = {};  // 0..7 timing, 8..9 lagged scalar reads
   double load = 0.0;
   double bnorm = 0.0;
+  Load2D load2d{};
   fracture_monitor_fn monitor = nullptr;
   void* monitor_user = nullptr;
   bool coef_valid = false;
@@ -154,7 +155,12 @@ int validate(const fracture_params* p) {
     return FRACTURE_EINVAL;
   if (!(p->omega > 0 && p->omega < 2)) return FRACTURE_EINVAL;
   if (p->relax_mode < 0 || p->relax_mode > 2) return FRACTURE_EINVAL;
-  if (p->dim == 2 && p->load_kind != FRACTURE_LOAD_TENSION_2D) return FRACTURE_EINVAL;
+  if (p->dim == 2 && p->load_kind != FRACTURE_LOAD_TENSION_2D &&
+      p->load_kind != FRACTURE_LOAD_SURFING_2D)
+    return FRACTURE_EINVAL;
+  if (p->load_kind == FRACTURE_LOAD_SURFING_2D &&
+      (!std::isfinite(p->surf_ki) || !std::isfinite(p->surf_v) || !std::isfinite(p->surf_lc)))
+    return FRACTURE_EINVAL;
   if (p->dim == 3 && p->load_kind != FRACTURE_LOAD_THERMAL_3D) return FRACTURE_EINVAL;
   if (p->dim == 3 && p->newton) return FRACTURE_EINVAL;   // coupled Newton blocks are 2D only
   if (p->precision != FRACTURE_FP64 && p->precision != FRACTURE_MIXED) return FRACTURE_EINVAL;
@@ -181,7 +187,8 @@ int level_shapes(const fracture_params* p, Grid* out) {
     Grid g{};
     g.nx = nx; g.ny = ny; g.nz = nz; g.hx = hx; g.hy = hy; g.hz = hz;
     g.N = (nx + 1) * (ny + 1) * (dim == 3 ? nz + 1 : 1);
-    g.bc = dim == 3 ? BC_THERMAL_3D : BC_TENSION_2D;
+    g.bc = dim == 3 ? BC_THERMAL_3D
+                    : (p->load_kind == FRACTURE_LOAD_SURFING_2D ? BC_SURFING_2D : BC_TENSION_2D);
     g.dim = dim;
     g.eig_dT = 0.0;
     g.eig_depth = p->thermal_depth;
@@ -674,7 +681,7 @@ int pcg_mixed(fracture* h, double tol, int* iters) {
 int load_norm(fracture* h, double* out) {
   const Grid g = load_grid(h);
   HIPCHK(hipMemsetAsync(h->q, 0, h->n2 * sizeof(double), h->st));
-  launch_lift2d(h->st, g, h->q, h->load);
+  launch_lift2d(h->st, g, h->q, h->load, h->load2d);
   launch_resid2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, h->q, h->r, nullptr, true,
                  red(h, 0, S_RR));
   int rc = read_scalars(h);
@@ -1180,6 +1187,9 @@ void fracture_default_params(fracture_params* p, int nx, int ny) {
   p->k_ell = 1e-6;
   p->load_kind = FRACTURE_LOAD_TENSION_2D;
   p->thermal_depth = 0.05;
+  p->surf_ki = 1.0;
+  p->surf_v = 1.0;
+  p->surf_lc = 0.05;
   p->precision = FRACTURE_FP64;
   p->omega = 1.0;
   p->relax_mode = FRACTURE_RELAX_PROJECT;
@@ -1240,6 +1250,11 @@ int fracture_create(const fracture_params* p, const uint8_t* notch_mask, void* d
   h->st = (hipStream_t)hip_stream;
   layout(p, h, d_workspace);
   h->mat = make_mat(p);
+  h->load2d.kind = p->load_kind == FRACTURE_LOAD_SURFING_2D ? BC_SURFING_2D : BC_TENSION_2D;
+  h->load2d.ki2mu = p->surf_ki / (2.0 * h->mat.mu);
+  h->load2d.kappa = (3.0 - p->nu) / (1.0 + p->nu);
+  h->load2d.lc = p->surf_lc;
+  h->load2d.v = p->surf_v;
   h->cw = p->model == FRACTURE_AT1 ? 8.0 / 3.0 : 2.0;
   h->gc_cw = p->Gc / h->cw;
   h->cL = 2.0 * p->Gc * p->ell / h->cw;
@@ -1315,7 +1330,7 @@ int fracture_create(const fracture_params* p, const uint8_t* notch_mask, void* d
 int fracture_set_load(fracture_t h, double load) {
   if (!h || !std::isfinite(load)) return FRACTURE_EINVAL;
   h->load = load;
-  launch_lift2d(h->st, h->lv[0].g, h->u, load);
+  launch_lift2d(h->st, h->lv[0].g, h->u, load, h->load2d);
   return hip_ok(hipGetLastError());
 }
 

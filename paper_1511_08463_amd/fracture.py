@@ -26,6 +26,7 @@ FRACTURE_AT1 = 1
 FRACTURE_AT2 = 2
 FRACTURE_LOAD_TENSION_2D = 0
 FRACTURE_LOAD_THERMAL_3D = 1
+FRACTURE_LOAD_SURFING_2D = 2
 FRACTURE_RELAX_PROJECT = 0
 FRACTURE_RELAX_RATIO = 1
 FRACTURE_RELAX_BISECT = 2
@@ -56,6 +57,7 @@ class fracture_params(ctypes.Structure):
         ("E", ctypes.c_double), ("nu", ctypes.c_double), ("Gc", ctypes.c_double),
         ("ell", ctypes.c_double), ("k_ell", ctypes.c_double),
         ("load_kind", ctypes.c_int), ("thermal_depth", ctypes.c_double),
+        ("surf_ki", ctypes.c_double), ("surf_v", ctypes.c_double), ("surf_lc", ctypes.c_double),
         ("precision", ctypes.c_int), ("omega", ctypes.c_double), ("relax_mode", ctypes.c_int),
         ("newton", ctypes.c_int), ("am_stop", ctypes.c_int), ("am_tol", ctypes.c_double),
         ("switch_tol", ctypes.c_double), ("switch_rel", ctypes.c_double),

@@ -25,6 +25,12 @@ Recipes (the paper uses no dataset; these stand in for its test problems):
   W2 decays over 0.025 < ell, so onset comes later than DT_c (near 3 DT_c);
   the ramp runs to 16 DT_c, the largest intensity ratio of the paper's
   thermal-shock study, to cover nucleation and growth.
+* ``surfing(ell)``: the surfing test of Sec. 4.1: the slab [0, 2] x [0, 1]
+  (the paper's [0, L] x [-H/2, H/2] shifted by H/2), uniform cells of side
+  h = ell/4 (the paper refines a band to h = ell/5; a uniform mesh here),
+  plane stress, E = Gc = 1, nu = 0.3, K_I = sqrt(Gc E), v = 1, L_c = 0.05,
+  AT1, the preexisting crack as alpha = 1 on the mid-line nodes with
+  x <= L_c, loads t = 0.1 k.
 * ``config5``: a served stream of independent tension problems: side
   n ~ U{64, ..., 1024}, ell ~ U[0.01, 0.05], h = ell/4, domain side
   L = n h, the config-2 notch recipe scaled by L, 10-30 load steps with
@@ -124,6 +130,27 @@ def config5(n_instances=256, seed=1, sizes=(64, 128, 256, 512, 1024), rate=50.0,
         loads = [k * (load_scale * np.sqrt(L)) / steps for k in range(1, steps + 1)]
         out.append(dict(rid=rid, params=p, notch=notch, loads=loads, arrival=t))
     return out
+
+
+def surfing(ell=0.05, h_factor=4, model="AT1", steps=9, dt=0.1, **extra):
+    """Parameters, preexisting-crack mask and loads of the surfing slab."""
+    ny = int(round(1.0 / (ell / h_factor)))
+    ny += ny % 2                                  # a node row on the mid line
+    nx = 2 * ny
+    p = dict(dim=2, nx=nx, ny=ny, lx=2.0, ly=1.0, model=model, E=1.0, nu=0.3, Gc=1.0, ell=ell,
+             k_ell=1e-6, plane_stress=1, load_kind=2, surf_ki=1.0, surf_v=1.0, surf_lc=0.05)
+    p.update(extra)
+    x = np.arange(nx + 1) * (2.0 / nx)
+    mask = np.zeros((ny + 1, nx + 1), dtype=np.uint8)
+    mask[ny // 2, x <= p["surf_lc"] + 1e-12] = 1
+    loads = [round(dt * k, 12) for k in range(steps)]
+    return p, mask.ravel(), loads
+
+
+def oracle_kwargs_surfing(p):
+    return dict(lx=p["lx"], ly=p["ly"], KI=p["surf_ki"], v=p["surf_v"], Lc=p["surf_lc"], E=p["E"],
+                nu=p["nu"], Gc=p["Gc"], ell=p["ell"], k_ell=p["k_ell"], model=p["model"],
+                plane_stress=bool(p["plane_stress"]))
 
 
 def thermal(nx, ny, nz, lx=1.0, ly=1.0, lz=0.25, ell=None, model="AT1", depth=0.05, **extra):

@@ -1,0 +1,86 @@
+"""GPU parity of the surfing load (Sec. 4.1): the Mode-I boundary field, the
+load path against the oracle, and Griffith's dissipation rate on a finer mesh
+than the oracle handles quickly."""
+
+import numpy as np
+import pytest
+
+from oracle import am, problems
+from paper_1511_08463_amd import fracture, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(p, notch, **kw):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return fracture.Fracture(fracture.make_params(**dict(p, **kw)), notch, device="cuda:0")
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_surfing_boundary_values():
+    p, notch, _ = workloads.surfing(0.1)
+    print("[surf] boundary field", flush=True)
+    P = problems.surfing_2d(p["nx"], p["ny"], **workloads.oracle_kwargs_surfing(p))
+    s = _solver(p, notch)
+    for t in (0.0, 0.37, 1.2):
+        s.set_load(t)
+        u, _, _ = s.state()
+        want = P.dirichlet_values(t)
+        f = P.fixed
+        assert np.max(np.abs(u[f] - want[f])) <= 1e-13 * np.max(np.abs(want[f]))
+    s.close()
+
+
+def test_surfing_load_path_parity():
+    """ell = 0.1, h = ell/4 (81 x 41 nodes), ORAM-N to ||Phi||_2 <= 1e-9 on both
+    sides through crack initiation and propagation, t = 0 .. 0.4."""
+    p, notch, loads = workloads.surfing(0.1, steps=5)
+    print("[surf] parity", flush=True)
+    P = problems.surfing_2d(p["nx"], p["ny"], **workloads.oracle_kwargs_surfing(p))
+    st = am.initial_state(P, notch.astype(bool))
+    s = _solver(p, notch, newton=1, final_tol=1e-9, pcg_rtol=1e-12, vi_cg_rtol=1e-12,
+                minres_rtol=1e-8, max_newton=20, max_am=3000)
+    for t in loads:
+        s.set_load(t)
+        stats = s.solve_step()
+        am.solve_load_step(P, st, t, newton_on=True, final_tol=1e-9, max_am=3000)
+        u, a, _ = s.state()
+        eu, ea = _rel(u, st.u), _rel(a, st.alpha)
+        el, su = s.energy()
+        oel, osu = P.model.energies(st.u, st.alpha)
+        print(f"  t={t} sweeps={stats['sweeps']} newton={stats['newton_iters']} rel_u={eu:.2e} "
+              f"rel_a={ea:.2e} Es={su:.5f}/{osu:.5f}", flush=True)
+        assert stats["converged"]
+        assert eu < 1e-6 and ea < 1e-6
+        assert abs(su - osu) <= 1e-6 * abs(osu)
+    s.close()
+
+
+def test_surfing_dissipation_rate():
+    """ell = 0.05, h = ell/4 (161 x 81 nodes): after the initial transient the
+    crack tip moves by v dt per step and the surface energy grows at Gc v,
+    within the +15% overestimate of the regularised energy at h = ell/4."""
+    p, notch, loads = workloads.surfing(0.05, steps=9)
+    print("[surf] dissipation", flush=True)
+    s = _solver(p, notch, newton=1, max_am=3000)
+    nx, ny = p["nx"], p["ny"]
+    x = np.arange(nx + 1) * (2.0 / nx)
+    surf, tips = [], []
+    for t in loads:
+        s.set_load(t)
+        assert s.solve_step()["converged"]
+        surf.append(s.energy()[1])
+        a = s.state()[1].reshape(ny + 1, nx + 1)[ny // 2]
+        tips.append(x[a > 0.5].max())
+    ts, surf, tips = np.array(loads), np.array(surf), np.array(tips)
+    late = ts >= 0.3 - 1e-12
+    rate = np.polyfit(ts[late], surf[late], 1)[0]
+    print(f"  rate {rate:.4f}, tips {tips}", flush=True)
+    assert 1.0 <= rate <= 1.15, rate
+    assert np.all(np.abs(np.diff(tips[late]) - 0.1) <= 2.0 / nx + 1e-12)
+    s.close()
