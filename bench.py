@@ -164,6 +164,55 @@ def recorded_traffic():
     return TRAFFIC["bytes"]
 
 
+def surfing(args):
+    """The surfing slab (Sec. 4.1) at ell = --surf-ell, h = ell/4, ORAM-N:
+    load steps/s over t = 0.1 .. 0.8 and the dissipation rate against
+    Griffith's Gc v."""
+    import numpy as np
+    import torch
+    from paper_1511_08463_amd import fracture, workloads
+    p, notch, loads = workloads.surfing(args.surf_ell, steps=9)
+    params = fracture.make_params(**p, newton=args.newton, max_am=args.max_am,
+                                  pcg_rtol=args.pcg_rtol, omega=args.omega,
+                                  precision=fracture.FRACTURE_MIXED if args.precision == "mixed"
+                                  else fracture.FRACTURE_FP64)
+    solver = fracture.Fracture(params, notch, device="cuda:0")
+    nx, ny = p["nx"], p["ny"]
+    x = np.arange(nx + 1) * (2.0 / nx)
+    log(f"[surfing] {nx}x{ny} cells, ell={args.surf_ell}, {args.precision}, omega={args.omega}, "
+        f"newton={args.newton}")
+    surf, tips, stats = [], [], []
+    torch.cuda.synchronize()
+    t_start = None
+    for k, t in enumerate(loads):
+        if k == 1:
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+        solver.set_load(t)
+        st = solver.solve_step()
+        stats.append(st)
+        surf.append(solver.energy()[1])
+        a = solver.state()[1].reshape(ny + 1, nx + 1)[ny // 2]
+        tips.append(float(x[a > 0.5].max()))
+        log(f"[surfing] t={t:.1f} sweeps={st['sweeps']} pcg={st['pcg_iters']} newton={st['newton_iters']} "
+            f"minres={st['minres_iters']} ms={st['ms_total']:.1f} Es={surf[-1]:.5f} tip={tips[-1]:.4f}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t_start
+    solver.close()
+    ts = np.array(loads)
+    late = ts >= 0.3 - 1e-12
+    rate = float(np.polyfit(ts[late], np.array(surf)[late], 1)[0])
+    return {"workload": (f"surfing slab [0,2]x[0,1] (Sec. 4.1), {nx}x{ny} cells (h = ell/4), AT1, "
+                         f"ell={args.surf_ell}, plane stress, K_I = sqrt(Gc E), v = 1, L_c = 0.05; "
+                         f"{'ORAM-N' if args.newton else 'ORAM'} omega={args.omega}, "
+                         f"t = 0.1..0.8 timed after t = 0"),
+            "precision": args.precision, "omega": args.omega, "load_steps": len(loads) - 1, "seconds": dt,
+            "load_steps_per_s": (len(loads) - 1) / dt,
+            "sweeps": sum(s["sweeps"] for s in stats[1:]),
+            "newton_iters": sum(s["newton_iters"] for s in stats[1:]),
+            "dissipation_rate": rate, "griffith_rate": 1.0, "tips": tips}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +242,9 @@ def main():
     ap.add_argument("--serve", action="store_true", help="run only the served stream")
     ap.add_argument("--thermal", action="store_true", help="run only the 3D thermal slab (config 3)")
     ap.add_argument("--dt-factor", type=float, default=16.0, help="thermal ramp end in units of DT_c")
+    ap.add_argument("--surfing", action="store_true", help="run only the surfing slab (Sec. 4.1)")
+    ap.add_argument("--surf-ell", type=float, default=1.0 / 128)
+    ap.add_argument("--no-surfing", action="store_true", help="skip the surfing sample")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream sample")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-omega", action="store_true", help="skip the omega = 1.4, 1.8 legs")
@@ -225,6 +277,9 @@ def main():
         return
     if args.thermal:
         print(json.dumps({"thermal": thermal(args)}), flush=True)
+        return
+    if args.surfing:
+        print(json.dumps({"surfing": surfing(args)}), flush=True)
         return
     p, notch, loads, (y0, a) = workloads.config2(args.model, args.omega, seed=0, n=args.n)
 
@@ -394,6 +449,11 @@ def main():
                                       f"(n in 64..1024, ell in [0.01,0.05], h=ell/4, 10-30 steps, "
                                       f"Poisson 50/s), mixed precision, budget {args.budget_gb} GB, "
                                       f"{args.workers} workers")
+    if not args.no_surfing:
+        # the second workload: the surfing slab at ell = 1/64, ORAM-N, omega = 1.8
+        sargs = argparse.Namespace(**vars(args))
+        sargs.surf_ell, sargs.omega, sargs.precision, sargs.newton = 1.0 / 64, 1.8, "fp64", 1
+        out["surfing"] = surfing(sargs)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(256, args.n, args.model)
