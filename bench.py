@@ -174,6 +174,7 @@ def surfing(args):
     p, notch, loads = workloads.surfing(args.surf_ell, steps=9)
     params = fracture.make_params(**p, newton=args.newton, max_am=args.max_am,
                                   pcg_rtol=args.pcg_rtol, omega=args.omega,
+                                  omega_auto=1 if args.omega_auto else 0, am_tol=args.am_tol,
                                   precision=fracture.FRACTURE_MIXED if args.precision == "mixed"
                                   else fracture.FRACTURE_FP64)
     solver = fracture.Fracture(params, notch, device="cuda:0")
@@ -204,7 +205,8 @@ def surfing(args):
     rate = float(np.polyfit(ts[late], np.array(surf)[late], 1)[0])
     return {"workload": (f"surfing slab [0,2]x[0,1] (Sec. 4.1), {nx}x{ny} cells (h = ell/4), AT1, "
                          f"ell={args.surf_ell}, plane stress, K_I = sqrt(Gc E), v = 1, L_c = 0.05; "
-                         f"{'ORAM-N' if args.newton else 'ORAM'} omega={args.omega}, "
+                         f"{'ORAM-N' if args.newton else 'ORAM'} omega="
+                         f"{('auto <= %g' % args.omega) if args.omega_auto else args.omega}, "
                          f"t = 0.1..0.8 timed after t = 0"),
             "precision": args.precision, "omega": args.omega, "load_steps": len(loads) - 1, "seconds": dt,
             "load_steps_per_s": (len(loads) - 1) / dt,
@@ -221,6 +223,8 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--model", default="AT1")
     ap.add_argument("--omega", type=float, default=1.0)
+    ap.add_argument("--omega-auto", action="store_true",
+                    help="per-step omega from the measured AM convergence factor (cap: --omega)")
     ap.add_argument("--am-tol", type=float, default=1e-5)
     ap.add_argument("--max-am", type=int, default=5000, help="sweep limit per load step")
     ap.add_argument("--pcg-rtol", type=float, default=1e-8)
@@ -293,6 +297,7 @@ def main():
                                       newton_forcing=args.newton_forcing,
                                       cheb_degree=args.cheb_degree,
                                       newton_precond=args.newton_precond,
+                                      omega_auto=1 if args.omega_auto else 0,
                                       use_graphs=0 if args.no_graphs else 1,
                                       precision=fracture.FRACTURE_MIXED if precision == "mixed"
                                       else fracture.FRACTURE_FP64)
@@ -450,9 +455,11 @@ def main():
                                       f"Poisson 50/s), mixed precision, budget {args.budget_gb} GB, "
                                       f"{args.workers} workers")
     if not args.no_surfing:
-        # the second workload: the surfing slab at ell = 1/64, ORAM-N, omega = 1.8
+        # the second workload: the surfing slab at ell = 1/64, ORAM-N with the
+        # automatic over-relaxation factor (cap 1.9)
         sargs = argparse.Namespace(**vars(args))
-        sargs.surf_ell, sargs.omega, sargs.precision, sargs.newton = 1.0 / 64, 1.8, "fp64", 1
+        sargs.surf_ell, sargs.omega, sargs.precision, sargs.newton = 1.0 / 64, 1.9, "fp64", 1
+        sargs.omega_auto = True
         out["surfing"] = surfing(sargs)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")

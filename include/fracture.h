@@ -138,6 +138,14 @@ typedef struct {
                                block-diagonal form diag(A^{-1}, C^{-1}), one
                                of each, also SPD.  Both solve the same Newton
                                system to the same tolerance.                  */
+  int omega_auto;           /* 1: choose the over-relaxation factor per load
+                               step: omega = 1 until the convergence factor
+                               rho of plain alternate minimisation is
+                               measured over 4 sweep ratios, then Young's SOR
+                               optimum 2 / (1 + sqrt(1 - rho)), capped at
+                               omega (the paper's hypothesis on the optimal
+                               omega, Sec. 2.2; it leaves an automatic choice
+                               to future work); 0: omega throughout           */
 } fracture_params;
 
 /* Fill *p with the documented defaults for a 2D tension problem on an

@@ -37,7 +37,8 @@ constexpr int DENSE_MAX = 1024;   // largest coarsest-level system inverted dens
 constexpr double ARMIJO_SIGMA = 1e-4;
 constexpr int MAX_HALVINGS = 20;
 constexpr int MAX_GRAPHS = 16;
-constexpr double NEWTON_ETA_MAX = 0.1;   // loosest Newton forcing term    // recorded launch sequences kept per instance
+constexpr double NEWTON_ETA_MAX = 0.1;   // loosest Newton forcing term
+constexpr int OMEGA_PROBE = 4;           // omega_auto: sweep ratios that estimate rho    // recorded launch sequences kept per instance
 
 // Launch sequences recorded once and replayed as HIP graphs.
 enum GraphOp { G_VCYCLE64 = 1, G_VCYCLE32 = 2, G_PRECOND = 3 };
@@ -119,6 +120,7 @@ struct fracture {
   double load = 0.0;
   double bnorm = 0.0;
   Load2D load2d{};
+  double omega_cur = 1.0;   // over-relaxation factor of the current sweep
   fracture_monitor_fn monitor = nullptr;
   void* monitor_user = nullptr;
   bool coef_valid = false;
@@ -172,6 +174,7 @@ int validate(const fracture_params* p) {
   if (!(p->newton_forcing >= 0)) return FRACTURE_EINVAL;
   if (p->vcycle_tail != 0 && p->vcycle_tail != 1) return FRACTURE_EINVAL;
   if (p->newton_precond != 0 && p->newton_precond != 1) return FRACTURE_EINVAL;
+  if (p->omega_auto != 0 && p->omega_auto != 1) return FRACTURE_EINVAL;
   if ((int64_t)(p->nx + 1) * (p->ny + 1) * (p->dim == 3 ? p->nz + 1 : 1) > (int64_t)1 << 29)
     return FRACTURE_EINVAL;
   return FRACTURE_OK;
@@ -821,7 +824,7 @@ int residual_norm(fracture* h, double* out) {
 int relax_alpha(fracture* h) {
   hipStream_t st = h->st;
   const int64_t N = h->N;
-  const double w = h->p.omega;
+  const double w = h->omega_cur;
   if (h->p.relax_mode == FRACTURE_RELAX_PROJECT || w <= 1.0) {
     launch_relax_alpha(st, N, h->alpha, h->atil, h->alpha_prev, w, h->S, -1, red(h, 8, S_DAMAX));
     return FRACTURE_OK;
@@ -1082,6 +1085,11 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
   int rc = FRACTURE_OK;
   double ms_pcg = 0, ms_vi = 0, ms_newton = 0;
   double threshold = h->p.switch_tol;
+  // omega: fixed, or (omega_auto) 1 until the convergence factor rho of the
+  // plain alternate minimisation is measured, then Young's optimum
+  // 2 / (1 + sqrt(1 - rho)) of SOR theory, capped at p.omega
+  h->omega_cur = h->p.omega_auto ? 1.0 : h->p.omega;
+  double da_hist[OMEGA_PROBE + 1] = {};
   for (int sweep = 1; sweep <= h->p.max_am; ++sweep) {
     update_coefficients(h);
     if (sweep == 1) {
@@ -1096,10 +1104,10 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
     rc = h->mixed ? pcg_mixed(h, tol, &it) : pcg(h, tol, &it);
     loc.pcg_iters += it;
     if (rc) break;
-    if (h->p.omega == 1.0)
+    if (h->omega_cur == 1.0)
       HIPCHK(hipMemcpyAsync(h->u, h->x, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
     else
-      launch_relax_u(st, n2, h->u, h->x, h->p.omega);
+      launch_relax_u(st, n2, h->u, h->x, h->omega_cur);
     HIPCHK(hipEventRecord(h->ev[2], st));
     // damage substep
     launch_w2_2d(st, load_grid(h), h->mat, h->u, h->w2);
@@ -1115,6 +1123,16 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
     ms_vi += elapsed(h->ev[2], h->ev[3]);
     loc.dalpha_inf = h->hS[S_DAMAX];
     if (!std::isfinite(loc.dalpha_inf)) { rc = FRACTURE_ENONFINITE; break; }
+    if (h->p.omega_auto && h->omega_cur == 1.0) {
+      // ||dalpha||_inf of the last OMEGA_PROBE + 1 sweeps at omega = 1
+      const int q = (sweep - 1) % (OMEGA_PROBE + 1);
+      da_hist[q] = loc.dalpha_inf;
+      if (sweep % (OMEGA_PROBE + 1) == 0 && da_hist[0] > 0.0) {
+        const double rho = std::pow(da_hist[OMEGA_PROBE] / da_hist[0], 1.0 / OMEGA_PROBE);
+        if (rho > 0.0 && rho < 1.0)
+          h->omega_cur = std::fmin(h->p.omega, 2.0 / (1.0 + std::sqrt(1.0 - rho)));
+      }
+    }
     if (h->monitor && (h->p.newton || h->p.am_stop != FRACTURE_STOP_PHI))
       h->monitor(h->monitor_user, sweep, loc.dalpha_inf, -1.0);
     if (!h->p.newton && h->p.am_stop == FRACTURE_STOP_DALPHA) {
@@ -1216,6 +1234,7 @@ void fracture_default_params(fracture_params* p, int nx, int ny) {
   p->use_graphs = 1;
   p->vcycle_tail = 1;
   p->newton_precond = 1;
+  p->omega_auto = 0;
 }
 
 size_t fracture_workspace_bytes(const fracture_params* p) {
