@@ -175,6 +175,7 @@ def surfing(args):
     params = fracture.make_params(**p, newton=args.newton, max_am=args.max_am,
                                   pcg_rtol=args.pcg_rtol, omega=args.omega,
                                   omega_auto=1 if args.omega_auto else 0, am_tol=args.am_tol,
+                                  newton_forcing_mode=args.forcing_mode,
                                   precision=fracture.FRACTURE_MIXED if args.precision == "mixed"
                                   else fracture.FRACTURE_FP64)
     solver = fracture.Fracture(params, notch, device="cuda:0")
@@ -241,6 +242,8 @@ def main():
                     help="0: symmetric block preconditioner (paper), 1: block diagonal")
     ap.add_argument("--newton-forcing", type=float, default=0.1,
                     help="adaptive Newton forcing factor (0: fixed --minres-rtol)")
+    ap.add_argument("--forcing-mode", type=int, default=1,
+                    help="1: Eisenstat-Walker forcing terms; 0: the final-tolerance target")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="run only the served stream")
@@ -295,6 +298,7 @@ def main():
                                       minres_rtol=args.minres_rtol,
                                       newton_vcycles=args.newton_vcycles,
                                       newton_forcing=args.newton_forcing,
+                                      newton_forcing_mode=args.forcing_mode,
                                       cheb_degree=args.cheb_degree,
                                       newton_precond=args.newton_precond,
                                       omega_auto=1 if args.omega_auto else 0,
@@ -390,7 +394,8 @@ def main():
                          f"tension load steps t=0.1k, k={args.warmup + 1}..{args.warmup + args.steps} timed; "
                          + (f"ORAM omega={args.omega} switching to reduced-space Newton at ||Phi||2<{args.switch_tol:g}, "
                             f"stop ||Phi||2<{args.final_tol:g}, MINRES forcing "
-                            + (f"adaptive ({args.newton_forcing:g} final_tol/||Phi||, floor {args.minres_rtol:g})"
+                            + ((("Eisenstat-Walker, " if args.forcing_mode == 1 else "")
+                                + f"target {args.newton_forcing:g} final_tol/||Phi||, floor {args.minres_rtol:g}")
                                if args.newton_forcing > 0 else f"{args.minres_rtol:g}")
                             + f", {args.newton_vcycles} V-cycle(s) per A^-1"
                             if args.newton else
@@ -460,6 +465,7 @@ def main():
         sargs = argparse.Namespace(**vars(args))
         sargs.surf_ell, sargs.omega, sargs.precision, sargs.newton = 1.0 / 64, 1.9, "fp64", 1
         sargs.omega_auto = True
+        sargs.forcing_mode = 0
         out["surfing"] = surfing(sargs)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")

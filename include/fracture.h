@@ -115,13 +115,13 @@ typedef struct {
                                paper's setup (Sec. 3.3) uses two; the default
                                is one, which costs fewer V-cycles per Newton
                                solve on the structured meshes here.            */
-  double newton_forcing;    /* > 0: each Newton system is solved to the
-                               relative tolerance max(minres_rtol,
-                               min(0.1, newton_forcing * final_tol / ||Phi||)),
-                               just enough for the step to reach final_tol
-                               (the adaptive forcing the paper recommends for
-                               practical use, Sec. 5.3); 0: always
-                               minres_rtol, as in the paper's experiments     */
+  double newton_forcing;    /* > 0: adaptive forcing terms (the paper
+                               recommends adaptive tolerances for practical
+                               use, Sec. 5.3), never tighter than the
+                               target newton_forcing * final_tol / ||Phi||
+                               that lets the step reach final_tol and never
+                               below minres_rtol; 0: always minres_rtol, as
+                               in the paper's experiments                     */
   int use_graphs;           /* 1: record the fixed launch sequences (V-cycle,
                                block preconditioner) once per operand set and
                                replay them as HIP graphs; 0: launch eagerly.
@@ -138,6 +138,11 @@ typedef struct {
                                block-diagonal form diag(A^{-1}, C^{-1}), one
                                of each, also SPD.  Both solve the same Newton
                                system to the same tolerance.                  */
+  int newton_forcing_mode;  /* with newton_forcing > 0: 0 the target itself
+                               (capped at 0.1); 1 (default) Eisenstat-Walker
+                               choice 2, eta_k = 0.9 (||Phi_k||/||Phi_k-1||)^2
+                               with eta_0 = 0.01 and their safeguard, capped
+                               at 0.5                                         */
   int omega_auto;           /* 1: choose the over-relaxation factor per load
                                step: omega = 1 until the convergence factor
                                rho of plain alternate minimisation is

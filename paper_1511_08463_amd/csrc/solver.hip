@@ -37,7 +37,9 @@ constexpr int DENSE_MAX = 1024;   // largest coarsest-level system inverted dens
 constexpr double ARMIJO_SIGMA = 1e-4;
 constexpr int MAX_HALVINGS = 20;
 constexpr int MAX_GRAPHS = 16;
-constexpr double NEWTON_ETA_MAX = 0.1;   // loosest Newton forcing term
+constexpr double NEWTON_ETA_MAX = 0.1;   // loosest forcing term of the target rule
+constexpr double EW_ETA0 = 0.01;         // Eisenstat-Walker: first forcing term of a phase
+constexpr double EW_ETA_MAX = 0.5;       // Eisenstat-Walker: loosest forcing term
 constexpr int OMEGA_PROBE = 4;           // omega_auto: sweep ratios that estimate rho    // recorded launch sequences kept per instance
 
 // Launch sequences recorded once and replayed as HIP graphs.
@@ -175,6 +177,7 @@ int validate(const fracture_params* p) {
   if (p->vcycle_tail != 0 && p->vcycle_tail != 1) return FRACTURE_EINVAL;
   if (p->newton_precond != 0 && p->newton_precond != 1) return FRACTURE_EINVAL;
   if (p->omega_auto != 0 && p->omega_auto != 1) return FRACTURE_EINVAL;
+  if (p->newton_forcing_mode != 0 && p->newton_forcing_mode != 1) return FRACTURE_EINVAL;
   if ((int64_t)(p->nx + 1) * (p->ny + 1) * (p->dim == 3 ? p->nz + 1 : 1) > (int64_t)1 << 29)
     return FRACTURE_EINVAL;
   return FRACTURE_OK;
@@ -1016,6 +1019,7 @@ int newton_phase(fracture* h, fracture_stats* st, double* nphi, bool* converged)
   double phi2 = 0;
   int rc = coupled_residual(h, h->u, h->alpha, h->nFu, &phi2);
   if (rc) return rc;
+  double nphi_prev = 1.0, eta_prev = EW_ETA0;
   for (int it = 0; it < h->p.max_newton; ++it) {
     *nphi = std::sqrt(phi2);
     if (h->monitor) h->monitor(h->monitor_user, -(it + 1), -1.0, *nphi);
@@ -1024,11 +1028,27 @@ int newton_phase(fracture* h, fracture_stats* st, double* nphi, bool* converged)
     // rhs = -[F_u; F_a on the inactive set]
     launch_axpby(s, n2, -1.0, h->nFu, 0.0, h->nv);
     launch_neg_masked(s, N, h->F, h->mask, h->nv + n2, h->nca);
-    // forcing term: enough accuracy for this step to reach final_tol
+    // forcing term.  target: enough accuracy for this step to reach
+    // final_tol.  Eisenstat-Walker (choice 2, gamma = 0.9, exponent 2, with
+    // their safeguard): eta_k = 0.9 (||Phi_k|| / ||Phi_k-1||)^2, eta_0 =
+    // EW_ETA0, never tighter than the target
     double eta = h->p.minres_rtol;
-    if (h->p.newton_forcing > 0)
-      eta = std::fmax(h->p.minres_rtol,
-                      std::fmin(NEWTON_ETA_MAX, h->p.newton_forcing * h->p.final_tol / *nphi));
+    if (h->p.newton_forcing > 0) {
+      const double target = h->p.newton_forcing * h->p.final_tol / *nphi;
+      if (h->p.newton_forcing_mode == 1) {
+        double ew = EW_ETA0;
+        if (it > 0) {
+          ew = 0.9 * (*nphi / nphi_prev) * (*nphi / nphi_prev);
+          const double sg = 0.9 * eta_prev * eta_prev;
+          if (sg > 0.1) ew = std::fmax(ew, sg);
+        }
+        eta = std::fmax(h->p.minres_rtol, std::fmin(EW_ETA_MAX, std::fmax(ew, target)));
+      } else {
+        eta = std::fmax(h->p.minres_rtol, std::fmin(NEWTON_ETA_MAX, target));
+      }
+    }
+    nphi_prev = *nphi;
+    eta_prev = eta;
     int its = 0;
     rc = minres(h, eta, &its);
     st->minres_iters += its;
@@ -1235,6 +1255,7 @@ void fracture_default_params(fracture_params* p, int nx, int ny) {
   p->vcycle_tail = 1;
   p->newton_precond = 1;
   p->omega_auto = 0;
+  p->newton_forcing_mode = 1;
 }
 
 size_t fracture_workspace_bytes(const fracture_params* p) {

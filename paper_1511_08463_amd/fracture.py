@@ -68,7 +68,8 @@ class fracture_params(ctypes.Structure):
         ("cheb_degree", ctypes.c_int), ("coarse_max_dofs", ctypes.c_int),
         ("newton_vcycles", ctypes.c_int), ("newton_forcing", ctypes.c_double),
         ("use_graphs", ctypes.c_int), ("vcycle_tail", ctypes.c_int),
-        ("newton_precond", ctypes.c_int), ("omega_auto", ctypes.c_int),
+        ("newton_precond", ctypes.c_int), ("newton_forcing_mode", ctypes.c_int),
+        ("omega_auto", ctypes.c_int),
     ]
 
 

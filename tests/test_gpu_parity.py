@@ -347,21 +347,24 @@ def test_coupling_blocks_match_assembled():
     s.close()
 
 
-@pytest.mark.parametrize("omega,vcycles,forcing,precond",
-                         [(1.0, 2, 0.0, 0), (1.4, 1, 0.1, 1), (1.0, 1, 0.1, 1), (1.0, 1, 0.1, 0)])
-def test_oram_newton_parity(omega, vcycles, forcing, precond):
+@pytest.mark.parametrize("omega,vcycles,forcing,precond,mode",
+                         [(1.0, 2, 0.0, 0, 0), (1.4, 1, 0.1, 1, 1), (1.0, 1, 0.1, 1, 1),
+                          (1.0, 1, 0.1, 0, 0)])
+def test_oram_newton_parity(omega, vcycles, forcing, precond, mode):
     """ORAM-N (Algorithm 3) to ||Phi||_2 <= 1e-9 against the oracle's ORAM-N
     (exact LU Newton steps) on a growing crack: same converged state, with
     one or two V-cycles per action of A^{-1}, a fixed or adaptive Newton
-    forcing term, and the paper's symmetric block preconditioner or the
-    block-diagonal one."""
+    forcing term (final-tolerance target or Eisenstat-Walker), and the
+    paper's symmetric block preconditioner or the block-diagonal one."""
     n = 48
     p, notch, _ = workloads.small_tension(n, "AT1", ell=0.08)
-    print(f"[oram-n] omega={omega} vcycles={vcycles} forcing={forcing} precond={precond}", flush=True)
+    print(f"[oram-n] omega={omega} vcycles={vcycles} forcing={forcing} precond={precond} "
+          f"mode={mode}", flush=True)
     loads = [0.3, 0.9]
     s = _solver(p, notch, omega=omega, newton=1, switch_tol=1e-3, final_tol=1e-9,
                 pcg_rtol=1e-12, vi_cg_rtol=1e-12, minres_rtol=1e-8, max_newton=20,
-                newton_vcycles=vcycles, newton_forcing=forcing, newton_precond=precond)
+                newton_vcycles=vcycles, newton_forcing=forcing, newton_precond=precond,
+                newton_forcing_mode=mode)
     P = _problem(p)
     st = am.initial_state(P, notch.astype(bool))
     total_newton = 0
