@@ -176,6 +176,7 @@ def surfing(args):
                                   pcg_rtol=args.pcg_rtol, omega=args.omega,
                                   omega_auto=1 if args.omega_auto else 0, am_tol=args.am_tol,
                                   newton_forcing_mode=args.forcing_mode,
+                                  pcg_reduction=args.pcg_reduction,
                                   precision=fracture.FRACTURE_MIXED if args.precision == "mixed"
                                   else fracture.FRACTURE_FP64)
     solver = fracture.Fracture(params, notch, device="cuda:0")
@@ -242,6 +243,8 @@ def main():
                     help="0: symmetric block preconditioner (paper), 1: block diagonal")
     ap.add_argument("--newton-forcing", type=float, default=0.1,
                     help="adaptive Newton forcing factor (0: fixed --minres-rtol)")
+    ap.add_argument("--pcg-reduction", type=float, default=0.01,
+                    help="ORAM-N: elastic solves of ORAM sweeps stop at this reduction of the warm-start residual")
     ap.add_argument("--forcing-mode", type=int, default=1,
                     help="1: Eisenstat-Walker forcing terms; 0: the final-tolerance target")
     ap.add_argument("--kernel-reps", type=int, default=50)
@@ -299,6 +302,7 @@ def main():
                                       newton_vcycles=args.newton_vcycles,
                                       newton_forcing=args.newton_forcing,
                                       newton_forcing_mode=args.forcing_mode,
+                                      pcg_reduction=args.pcg_reduction,
                                       cheb_degree=args.cheb_degree,
                                       newton_precond=args.newton_precond,
                                       omega_auto=1 if args.omega_auto else 0,
@@ -400,7 +404,9 @@ def main():
                             + f", {args.newton_vcycles} V-cycle(s) per A^-1"
                             if args.newton else
                             f"ORAM omega={args.omega} to ||dalpha||inf<{args.am_tol:g}")
-                         + f", PCG rtol {args.pcg_rtol:g}"),
+                         + f", PCG rtol {args.pcg_rtol:g}"
+                         + (f" (ORAM sweeps: or {args.pcg_reduction:g} x warm-start residual)"
+                            if args.newton and args.pcg_reduction > 0 else "")),
             "precision": args.precision,
             "newton": bool(args.newton),
         },

@@ -143,6 +143,12 @@ typedef struct {
                                choice 2, eta_k = 0.9 (||Phi_k||/||Phi_k-1||)^2
                                with eta_0 = 0.01 and their safeguard, capped
                                at 0.5                                         */
+  double pcg_reduction;     /* ORAM-N only (newton = 1): the elastic solve of
+                               an ORAM sweep may stop once its residual has
+                               fallen by this factor from the warm start (or
+                               at pcg_rtol, whichever is looser); the Newton
+                               phase enforces the final accuracy.  0: always
+                               pcg_rtol.  Default 0.01.                       */
   int omega_auto;           /* 1: choose the over-relaxation factor per load
                                step: omega = 1 until the convergence factor
                                rho of plain alternate minimisation is

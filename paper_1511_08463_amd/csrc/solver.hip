@@ -178,6 +178,7 @@ int validate(const fracture_params* p) {
   if (p->newton_precond != 0 && p->newton_precond != 1) return FRACTURE_EINVAL;
   if (p->omega_auto != 0 && p->omega_auto != 1) return FRACTURE_EINVAL;
   if (p->newton_forcing_mode != 0 && p->newton_forcing_mode != 1) return FRACTURE_EINVAL;
+  if (!(p->pcg_reduction >= 0 && p->pcg_reduction < 1)) return FRACTURE_EINVAL;
   if ((int64_t)(p->nx + 1) * (p->ny + 1) * (p->dim == 3 ? p->nz + 1 : 1) > (int64_t)1 << 29)
     return FRACTURE_EINVAL;
   return FRACTURE_OK;
@@ -597,6 +598,15 @@ float* vcycle0f(fracture* h, const float* b) {
 // elastic subproblem: x <- argmin at fixed alpha, warm start from u
 // ---------------------------------------------------------------------------
 
+// Stopping tolerance of one elastic solve inside ORAM: the absolute
+// pcg_rtol * ||f||, or, under ORAM-N (whose Newton phase enforces the final
+// accuracy of u and alpha), the looser of that and pcg_reduction times the
+// residual at the warm start.
+double sweep_tol(const fracture* h, double tol, double r0) {
+  if (h->p.newton && h->p.pcg_reduction > 0) return std::fmax(tol, h->p.pcg_reduction * r0);
+  return tol;
+}
+
 int pcg(fracture* h, double tol, int* iters) {
   const Grid& g = h->lv[0].g;
   const int64_t n2 = h->n2;
@@ -610,6 +620,7 @@ int pcg(fracture* h, double tol, int* iters) {
   double rr = h->hS[S_RR];
   if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
   *iters = 0;
+  tol = sweep_tol(h, tol, std::sqrt(rr));
   if (std::sqrt(rr) <= tol) return FRACTURE_OK;
   double* z = vcycle0(h, h->r);
   launch_dot(st, n2, h->r, z, red(h, 1, S_RZ));
@@ -653,6 +664,7 @@ int pcg_mixed(fracture* h, double tol, int* iters) {
     const double rr = h->hS[S_RR];
     if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
     const double rn = std::sqrt(rr);
+    if (outer == 0) tol = sweep_tol(h, tol, rn);
     if (rn <= tol) return FRACTURE_OK;
     if (outer >= MIXED_MAX_OUTER || *iters >= h->p.max_pcg) return FRACTURE_ENOTCONV;
     // inner solve of K e = r / |r| in float32
@@ -1256,6 +1268,7 @@ void fracture_default_params(fracture_params* p, int nx, int ny) {
   p->newton_precond = 1;
   p->omega_auto = 0;
   p->newton_forcing_mode = 1;
+  p->pcg_reduction = 0.01;
 }
 
 size_t fracture_workspace_bytes(const fracture_params* p) {
