@@ -243,6 +243,8 @@ def main():
                     help="0: symmetric block preconditioner (paper), 1: block diagonal")
     ap.add_argument("--newton-forcing", type=float, default=0.1,
                     help="adaptive Newton forcing factor (0: fixed --minres-rtol)")
+    ap.add_argument("--vi-cg-rtol", type=float, default=1e-4,
+                    help="relative tolerance of the damage CG inside the active-set method")
     ap.add_argument("--pcg-reduction", type=float, default=0.01,
                     help="ORAM-N: elastic solves of ORAM sweeps stop at this reduction of the warm-start residual")
     ap.add_argument("--forcing-mode", type=int, default=1,
@@ -296,7 +298,7 @@ def main():
     def make_solver(precision, omega=None):
         pp = dict(p, omega=args.omega if omega is None else omega)
         params = fracture.make_params(**pp, am_tol=args.am_tol, pcg_rtol=args.pcg_rtol,
-                                      vi_cg_rtol=1e-10, max_am=args.max_am, newton=args.newton,
+                                      vi_cg_rtol=args.vi_cg_rtol, max_am=args.max_am, newton=args.newton,
                                       switch_tol=args.switch_tol, final_tol=args.final_tol,
                                       minres_rtol=args.minres_rtol,
                                       newton_vcycles=args.newton_vcycles,

@@ -105,7 +105,9 @@ typedef struct {
   double final_tol;         /* ||Phi||_2 stop (ORAM-N, or am_stop == PHI)      */
   double pcg_rtol;          /* elastic PCG: ||r|| <= pcg_rtol * ||b_load||     */
   double vi_tol;            /* damage VI: ||Phi_alpha||_inf <= vi_tol          */
-  double vi_cg_rtol;        /* reduced damage CG relative tolerance            */
+  double vi_cg_rtol;        /* reduced damage CG relative tolerance (default
+                               1e-4: the active-set iteration around it still
+                               drives the box residual to vi_tol)             */
   double minres_rtol;       /* Newton MINRES relative tolerance                */
   int max_am, max_pcg, max_vi, max_vi_cg, max_newton, max_minres;
   int cheb_degree;          /* Chebyshev smoothing steps per V-cycle side      */

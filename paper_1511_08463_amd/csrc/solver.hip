@@ -1251,7 +1251,7 @@ void fracture_default_params(fracture_params* p, int nx, int ny) {
   p->final_tol = 1e-7;
   p->pcg_rtol = 1e-10;
   p->vi_tol = 1e-13;
-  p->vi_cg_rtol = 1e-10;
+  p->vi_cg_rtol = 1e-4;
   p->minres_rtol = 1e-6;
   p->max_am = 2000;
   p->max_pcg = 1000;
