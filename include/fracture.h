@@ -151,6 +151,10 @@ typedef struct {
                                at pcg_rtol, whichever is looser); the Newton
                                phase enforces the final accuracy.  0: always
                                pcg_rtol.  Default 0.01.                       */
+  double newton_stall;      /* a Newton step that leaves more than this
+                               fraction of ||Phi|| is an insufficient
+                               reduction and ends the Newton phase (back to
+                               ORAM, Sec. 2.3); 1 disables.  Default 0.9.     */
   int omega_auto;           /* 1: choose the over-relaxation factor per load
                                step: omega = 1 until the convergence factor
                                rho of plain alternate minimisation is

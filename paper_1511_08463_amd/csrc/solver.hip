@@ -179,6 +179,7 @@ int validate(const fracture_params* p) {
   if (p->omega_auto != 0 && p->omega_auto != 1) return FRACTURE_EINVAL;
   if (p->newton_forcing_mode != 0 && p->newton_forcing_mode != 1) return FRACTURE_EINVAL;
   if (!(p->pcg_reduction >= 0 && p->pcg_reduction < 1)) return FRACTURE_EINVAL;
+  if (!(p->newton_stall > 0 && p->newton_stall <= 1)) return FRACTURE_EINVAL;
   if ((int64_t)(p->nx + 1) * (p->ny + 1) * (p->dim == 3 ? p->nz + 1 : 1) > (int64_t)1 << 29)
     return FRACTURE_EINVAL;
   return FRACTURE_OK;
@@ -1094,6 +1095,14 @@ int newton_phase(fracture* h, fracture_stats* st, double* nphi, bool* converged)
       *nphi = std::sqrt(phi2);
       return rc;
     }
+    // insufficient reduction: an accepted step that removes less than a
+    // fraction 1 - newton_stall of ||Phi|| ends the phase (the iterate is
+    // outside the region of fast Newton convergence); ORAM takes over
+    if (h->p.newton_stall < 1.0 && std::sqrt(phi2) > h->p.newton_stall * *nphi &&
+        std::sqrt(phi2) > h->p.final_tol) {
+      *nphi = std::sqrt(phi2);
+      return FRACTURE_OK;
+    }
   }
   *nphi = std::sqrt(phi2);
   if (*nphi <= h->p.final_tol) *converged = true;
@@ -1269,6 +1278,7 @@ void fracture_default_params(fracture_params* p, int nx, int ny) {
   p->omega_auto = 0;
   p->newton_forcing_mode = 1;
   p->pcg_reduction = 0.01;
+  p->newton_stall = 0.9;
 }
 
 size_t fracture_workspace_bytes(const fracture_params* p) {

@@ -69,7 +69,8 @@ class fracture_params(ctypes.Structure):
         ("newton_vcycles", ctypes.c_int), ("newton_forcing", ctypes.c_double),
         ("use_graphs", ctypes.c_int), ("vcycle_tail", ctypes.c_int),
         ("newton_precond", ctypes.c_int), ("newton_forcing_mode", ctypes.c_int),
-        ("pcg_reduction", ctypes.c_double), ("omega_auto", ctypes.c_int),
+        ("pcg_reduction", ctypes.c_double), ("newton_stall", ctypes.c_double),
+        ("omega_auto", ctypes.c_int),
     ]
 
 
