@@ -262,6 +262,9 @@ def main():
     ap.add_argument("--no-omega", action="store_true", help="skip the omega = 1.4, 1.8 legs")
     ap.add_argument("--omega-steps", type=int, default=4,
                     help="timed load steps of the omega = 1.4, 1.8 legs (after the same warm-up)")
+    ap.add_argument("--snap-step", type=int, default=9,
+                    help="load step whose state the mixed leg is also compared at (9: t = 0.9, "
+                         "before initiation); 0 for none")
     ap.add_argument("--kernels-only", action="store_true",
                     help="time the hot kernels only (no solve), e.g. under hardware counters")
     ap.add_argument("--instances", type=int, default=48)
@@ -357,9 +360,17 @@ def main():
             run(k)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        stats = [run(k) for k in range(args.warmup, args.warmup + nsteps)]
+        stats, snap, paused = [], None, 0.0
+        for k in range(args.warmup, args.warmup + nsteps):
+            stats.append(run(k))
+            if k + 1 == args.snap_step:
+                # the state before crack initiation, copied out untimed
+                torch.cuda.synchronize()
+                tp = time.perf_counter()
+                snap = solver.state()
+                paused += time.perf_counter() - tp
         torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
+        elapsed = time.perf_counter() - t0 - paused
         pcg_iters = sum(s["pcg_iters"] for s in stats)
         pcg_s = sum(s["ms_pcg"] for s in stats) / 1e3
         res = {
@@ -374,9 +385,9 @@ def main():
         }
         state = solver.state()
         energy = solver.energy()
-        return solver, res, state, energy
+        return solver, res, (state, snap), energy
 
-    solver, res, state64, energy64 = leg(args.precision)
+    solver, res, (state64, snap64), energy64 = leg(args.precision)
     rl = time_kernels(solver, args.kernel_reps)
     solver.close()
     dom = rl["smooth"]
@@ -447,7 +458,7 @@ def main():
     if not args.no_mixed and args.precision == "fp64":
         # the same load steps with the float32 operator and multigrid inside
         # float64 refinement, against the float64 run just made
-        s32, r32, state32, energy32 = leg("mixed")
+        s32, r32, (state32, snap32), energy32 = leg("mixed")
         s32.close()
         rel = lambda a_, b_: float(np.linalg.norm(a_ - b_) / max(np.linalg.norm(b_), 1e-300))
         out["mixed"] = {
@@ -458,6 +469,13 @@ def main():
             "rel_l2_alpha_vs_fp64": rel(state32[1], state64[1]),
             "rel_energy_vs_fp64": abs(sum(energy32) - sum(energy64)) / abs(sum(energy64)),
         }
+        if snap32 is not None and snap64 is not None:
+            # before initiation the two runs track one solution branch; at
+            # initiation each may select a different one (the crack path is a
+            # bifurcation), so the distance after it is not a rounding measure
+            out["mixed"][f"rel_l2_u_vs_fp64_t{loads[args.snap_step - 1]:.1f}"] = rel(snap32[0], snap64[0])
+            out["mixed"][f"rel_l2_alpha_vs_fp64_t{loads[args.snap_step - 1]:.1f}"] = rel(snap32[1],
+                                                                                      snap64[1])
     if not args.no_serve:
         sv = serve(args)
         out["serving"] = {k: sv[k] for k in ("instances", "steps", "wall_s", "steps_per_s",

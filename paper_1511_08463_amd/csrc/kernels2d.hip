@@ -48,10 +48,19 @@ __global__ __launch_bounds__(NB) void k_node2d(Grid g, Mat m, const T* __restric
   if (RED != R_NONE) block_reduce<NB, false>(acc, red, total, tt, threadIdx.x + NB_X * threadIdx.y);
 }
 
-// One wavefront per 64 x NB_Y tile, thread i walking the tile's column
+// Rows one thread of k_col2d walks: a column tile re-reads one grid row
+// above and below it (x and alpha), so taller tiles read less, while
+// shorter ones give more waves to hide latency with.  The Chebyshev step
+// (seven streams) gains from 16 rows; apply and residual do best at 8.
+constexpr int COL_NY = 8;
+constexpr int COL_NY_SMOOTH = 16;
+template <int MODE>
+constexpr int col_rows() { return MODE == M_SMOOTH ? COL_NY_SMOOTH : COL_NY; }
+
+// One wavefront per 64 x col_rows<MODE>() tile, thread i walking the tile's column
 // (column2d): each element stress is formed once per thread and each row is
-// loaded once, which pays on the large levels.  Same tiles and block count as
-// k_node2d; tiles are taken in XCD-aware order (xcd_tile).
+// loaded once, which pays on the large levels.  Tiles are taken in
+// XCD-aware order (xcd_tile); there are no more of them than k_node2d's.
 template <int MODE, bool FA, bool HASX, int RED, class T>
 __global__ __launch_bounds__(NB_X) void k_col2d(Grid g, Mat m, const T* __restrict__ coef, T kell,
                                                 const T* __restrict__ x, T* __restrict__ y,
@@ -60,10 +69,10 @@ __global__ __launch_bounds__(NB_X) void k_col2d(Grid g, Mat m, const T* __restri
   const int nbx = gridDim.x, total = gridDim.x * gridDim.y;
   const int t = xcd_tile(blockIdx.x + nbx * blockIdx.y, total);
   const int i = (t % nbx) * NB_X + threadIdx.x;
-  const int j0 = (t / nbx) * NB_Y;
+  const int j0 = (t / nbx) * col_rows<MODE>();
   double acc = 0.0;
   if (i <= g.nx) {
-    column2d<FA, HASX, MODE == M_SMOOTH>(
+    column2d<col_rows<MODE>(), FA, HASX, MODE == M_SMOOTH>(
         g, m, coef, kell, x, i, j0, [&](int j, T fx, T fy, T dx, T dy, T xc, T yc) {
           node_out2d<MODE, RED>(g, i, j, fx, fy, dx, dy, xc, yc, y, b, din, dout, cd, cr, mask, acc);
         });
@@ -80,6 +89,15 @@ static dim3 node_grid2(const Grid& g) {
   return dim3((g.nx + 1 + NB_X - 1) / NB_X, (g.ny + 1 + NB_Y - 1) / NB_Y);
 }
 
+// Grid of the operator kernels: column tiles of `rows` rows on large
+// levels, else node tiles.
+static dim3 op_grid2(const Grid& g, bool col, int rows) {
+  if (!col) return node_grid2(g);
+  static_assert(COL_NY % NB_Y == 0 && COL_NY_SMOOTH % NB_Y == 0,
+                "column tiles cover whole node tiles");
+  return dim3((g.nx + 1 + NB_X - 1) / NB_X, (g.ny + 1 + rows - 1) / rows);
+}
+
 int node_blocks2(const Grid& g) {
   dim3 gr = node_grid2(g);
   return (int)(gr.x * gr.y);
@@ -93,8 +111,8 @@ template <class T>
 void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
                     double kell, const T* x, T* y, const ND<T>* b, int mask, int red, Red r) {
   if (g.dim == 3) return launch_apply3d<T>(st, g, m, fine, coef, kell, x, y, b, mask, red, r);
-  dim3 gr = node_grid2(g);
   const bool col = use_col2d(g);
+  const dim3 gr = op_grid2(g, col, col_rows<M_APPLY>());
   const T k = T(kell);
 #define APPLY_CASE(FA, RD)                                                                      \
   do {                                                                                          \
@@ -123,8 +141,8 @@ template <class T>
 void launch_resid2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
                     double kell, const T* x, T* r, const ND<T>* b, bool red, Red rr) {
   if (g.dim == 3) return launch_resid3d<T>(st, g, m, fine, coef, kell, x, r, b, red, rr);
-  dim3 gr = node_grid2(g);
   const bool col = use_col2d(g);
+  const dim3 gr = op_grid2(g, col, col_rows<M_RESID>());
   const T k = T(kell);
 #define RES_CASE(FA, RD)                                                                        \
   do {                                                                                          \
@@ -153,8 +171,8 @@ void launch_smooth2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, con
                      double cd, double cr) {
   if (g.dim == 3)
     return launch_smooth3d<T>(st, g, m, fine, coef, kell, x_in, x_out, b, d_in, d_out, cd, cr);
-  dim3 gr = node_grid2(g);
   const bool col = use_col2d(g);
+  const dim3 gr = op_grid2(g, col, col_rows<M_SMOOTH>());
   Red none{};
   const T k = T(kell);
 #define SM_CASE(FA, HX)                                                                          \

@@ -244,7 +244,7 @@ __device__ __forceinline__ void load_row3(const Grid& g, const T* __restrict__ x
 }
 
 // Forces (K x) and, when DIAG, diagonal entries of K at nodes (i, j) for
-// j = j0 .. min(j0 + NB_Y - 1, ny); fin(j, fx, fy, dx, dy, x_x, x_y) receives
+// j = j0 .. min(j0 + ROWS - 1, ny); fin(j, fx, fy, dx, dy, x_x, x_y) receives
 // each node's values (x_x, x_y: x at the node, zero without HASX).
 // The cells of row cj left and right of the column, L = (i-1, cj) and
 // C = (i, cj), hold the four triangles the column's nodes share:
@@ -255,7 +255,7 @@ __device__ __forceinline__ void load_row3(const Grid& g, const T* __restrict__ x
 // (the six triangles around a node are the three above it in cell row j and
 // the three below it in cell row j-1).  Precondition: 0 <= i <= nx,
 // 0 <= j0 <= ny.
-template <bool FA, bool HASX, bool DIAG, class T, class Fin>
+template <int ROWS, bool FA, bool HASX, bool DIAG, class T, class Fin>
 __device__ __forceinline__ void column2d(const Grid& g, const Mat& m, const T* __restrict__ coef,
                                          T kell, const T* __restrict__ x, int i, int j0,
                                          Fin&& fin) {
@@ -269,7 +269,7 @@ __device__ __forceinline__ void column2d(const Grid& g, const Mat& m, const T* _
   T fcx = 0, fcy = 0, dcx = 0, dcy = 0;   // node (i, cj)
   T fnx = 0, fny = 0, dnx = 0, dny = 0;   // node (i, cj + 1)
 #pragma unroll
-  for (int s = 0; s <= NB_Y; ++s) {
+  for (int s = 0; s <= ROWS; ++s) {
     const int cj = j0 - 1 + s;
     if (cj > g.ny) break;
     load_row3<FA, HASX>(g, x, coef, i, cj + 1, hi);

@@ -18,12 +18,15 @@ pytestmark = pytest.mark.gpu
 N_SIDE = 2048
 
 
-def _patch(i, j, n, h):
-    """Cells around node (i, j), clipped to the domain: (X, T, global ids, local id)."""
+def _patch(i, j, n, h, ny=None, hy=None):
+    """Cells around node (i, j) of an n x ny grid (cells h x hy), clipped to
+    the domain: (X, T, global ids, local id)."""
+    ny = n if ny is None else ny
+    hy = h if hy is None else hy
     i0, i1 = max(i - 1, 0), min(i + 1, n)
-    j0, j1 = max(j - 1, 0), min(j + 1, n)
-    X, T = mesh.structured_mesh_2d(i1 - i0, j1 - j0, (i1 - i0) * h, (j1 - j0) * h)
-    X = X + np.array([i0 * h, j0 * h])
+    j0, j1 = max(j - 1, 0), min(j + 1, ny)
+    X, T = mesh.structured_mesh_2d(i1 - i0, j1 - j0, (i1 - i0) * h, (j1 - j0) * hy)
+    X = X + np.array([i0 * h, j0 * hy])
     ii, jj = np.meshgrid(np.arange(i0, i1 + 1), np.arange(j0, j1 + 1), indexing="xy")
     gid = (ii + (n + 1) * jj).ravel()
     loc = (i - i0) + (i1 - i0 + 1) * (j - j0)
@@ -77,6 +80,49 @@ def test_full_size_operator_rows():
         ga = M.grad_alpha(up, ap)
         assert abs(Ea[g] - ga[loc]) <= 1e-11 * max(abs(ga[loc]), np.max(np.abs(M.damage_linear(up))), 1e-300)
     assert worst < 1e-12, worst
+    s.close()
+
+
+def test_ragged_large_grid_operator_rows():
+    """A grid large enough for the column-tiled operator kernels, with a
+    one-node ragged tail in both directions (1537 columns: 24 whole 64-wide
+    tiles and one node; 1409 rows: one row past any tile height the kernels
+    use; both axes still halve down to a dense coarsest level) and unequal
+    cell sides: operator rows at tile seams, the last rows and columns, and
+    random nodes match the oracle's patch assembly."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    nx, ny = 1536, 1408
+    p = workloads.tension(nx, 0.01, "AT2", nx=nx, ny=ny)
+    hx, hy = 1.0 / nx, 1.0 / ny
+    s = fracture.Fracture(fracture.make_params(**p), None, device="cuda:0")
+    N = s.N
+    rng = np.random.default_rng(21)
+    u = rng.standard_normal(2 * N)
+    alpha = rng.uniform(0, 1, N)
+    s.set_state(u=u, alpha=alpha, alpha_prev=np.zeros(N))
+    y = s.apply(fracture.FRACTURE_OP_ELASTICITY, u)
+    js = sorted({0, 1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 32, 33, ny - 2, ny - 1, ny,
+                 ny - ny % 16, ny - ny % 8, ny - ny % 4, ny - ny % 16 - 1, ny - ny % 8 - 1}
+                | {int(v) for v in rng.integers(0, ny + 1, 12)})
+    ii = sorted({0, 1, 62, 63, 64, 65, 127, 128, nx - 1, nx, nx - nx % 64, nx - nx % 64 - 1}
+                | {int(v) for v in rng.integers(0, nx + 1, 6)})
+    worst = 0.0
+    for j in js:
+        for i in ii:
+            X, T, gid, loc = _patch(i, j, nx, hx, ny, hy)
+            M = _model(p, X, T)
+            up = np.concatenate([u[gid], u[N + gid]])
+            K = M.K(alpha[gid])
+            row = K @ up
+            m = len(gid)
+            g = i + (nx + 1) * j
+            scale = np.max(np.abs(K.toarray()[[loc, m + loc]])) * np.max(np.abs(up))
+            err = max(abs(y[g] - row[loc]), abs(y[N + g] - row[m + loc])) / scale
+            worst = max(worst, err)
+            assert err < 1e-12, (i, j, err)
+    print(f"[ragged-large] {len(js)}x{len(ii)} nodes, worst {worst:.2e}", flush=True)
     s.close()
 
 
