@@ -14,6 +14,14 @@ eigenstrain and the damage bounds:
   of eq. (surfingloading) with kappa = (3 - nu)/(1 + nu) as printed.  On the
   crack line behind the tip (y = ly/2, x < Lc + v t) the two crack faces
   carry opposite u_y; a boundary node there takes their mean, u = 0.
+* 2D thermal shock (Sec. 4.3, eqs. (energytshock), (tempfielderfc)): the
+  slab [0, lx] x [0, ly] (the paper's [-L/2, L/2] x [0, H] shifted by L/2),
+  cooled on its bottom face y = 0; eps0 = beta T I with T = -DT
+  erfc(y / (ell tau)) evaluated at each triangle's centroid, the loading
+  parameter being the dimensionless time tau (eps0 = 0 at tau = 0).  The
+  displacement conditions of the paper's sketch are not in its text; the
+  reading here: u_x = 0 on the lateral edges x = 0, lx and u_y = 0 on the
+  top edge y = ly, the cooled face traction free.
 * 3D thermal shock with an exponential temperature profile through x
   (a variant of Sec. 4.3, eqs. (energytshock), (tempfielderfc)): eps0 =
   -DT exp(-x / depth) I evaluated at each tetrahedron's centroid (beta = 1),
@@ -111,6 +119,45 @@ def surfing_notch(nx, ny, lx=2.0, ly=1.0, Lc=0.05):
     """The preexisting crack: nodes of the mid line y = ly/2 with x <= Lc."""
     X, _ = mesh.structured_mesh_2d(nx, ny, lx, ly)
     return np.isclose(X[:, 1], 0.5 * ly) & (X[:, 0] <= Lc + 1e-12)
+
+
+def thermal_shock_2d(nx, ny, lx=40.0, ly=10.0, dT=1.0, beta=1.0, E=1.0, nu=0.3, Gc=1.0,
+                     ell=1.0, k_ell=1e-6, model="AT1", plane_stress=False):
+    """The 2D thermal shock; the load passed to dirichlet/eps0 is tau."""
+    from scipy.special import erfc
+    X, T = mesh.structured_mesh_2d(nx, ny, lx, ly)
+    M = fem.Model(X, T, E=E, nu=nu, Gc=Gc, ell=ell, k_ell=k_ell, model=model,
+                  plane_stress=plane_stress)
+    N = M.N
+    fixed = np.zeros(2 * N, dtype=bool)
+    fixed[np.flatnonzero(np.isclose(X[:, 0], 0.0) | np.isclose(X[:, 0], lx))] = True
+    fixed[N + np.flatnonzero(np.isclose(X[:, 1], ly))] = True
+    yc = X[T].mean(axis=1)[:, 1]
+
+    def dirichlet(tau):
+        return np.zeros(2 * N)
+
+    def eps0(tau):
+        if tau <= 0.0:
+            return fem.isotropic_eigenstrain(np.zeros(len(T)), 2)
+        return fem.isotropic_eigenstrain(-beta * dT * erfc(yc / (ell * tau)), 2)
+
+    return Problem(M, fixed, dirichlet, eps0)
+
+
+def thermal_shock_dTc(E=1.0, nu=0.3, Gc=1.0, ell=1.0, beta=1.0, model="AT1",
+                      plane_stress=False):
+    """Shock intensity below which the 2D slab stays undamaged (the purely
+    elastic regime of Sec. 4.3), in the reading that the cooled surface layer
+    is held at zero lateral strain and free of normal stress: there the
+    effective strain energy density A0 eps_eff : eps_eff is E' (beta T)^2 with
+    E' = E / (1 - nu^2) (plane strain) or E (plane stress), and AT1 damage
+    starts where it reaches G_c / (c_w ell) (c_w = 8/3).  AT2 has no elastic
+    phase (damage for any load), so None."""
+    if model != "AT1":
+        return None
+    Ep = E if plane_stress else E / (1.0 - nu * nu)
+    return np.sqrt(3.0 * Gc / (8.0 * ell * Ep)) / beta
 
 
 def thermal_3d(nx, ny, nz, lx=1.0, ly=1.0, lz=0.25, E=1.0, nu=0.3, Gc=1.0, ell=None,
