@@ -217,6 +217,58 @@ def surfing(args):
             "dissipation_rate": rate, "griffith_rate": 1.0, "tips": tips}
 
 
+def tshock(args, ratios=(2.0, 4.0, 8.0, 16.0), omegas=(0.8, 1.0, 1.2, 1.4, 1.6, 1.8)):
+    """The 2D thermal shock (Sec. 4.3) on the paper's 40 x 10 slab, ell = 1,
+    --tshock-n x --tshock-n/4 cells: plain ORAM sweeps over the evolution
+    tau = 0.1 .. --tshock-tau in steps of 0.1, for each shock intensity
+    DT/DT_c and over-relaxation factor (the experiment of Table 3)."""
+    import torch
+    from paper_1511_08463_amd import fracture, workloads
+    nx = args.tshock_n
+    ny = nx // 4
+    nsteps = int(round(args.tshock_tau / 0.1))
+    taus = [round(0.1 * k, 10) for k in range(1, nsteps + 1)]
+    rows = {}
+    for ratio in ratios:
+        row = {}
+        for om in omegas:
+            p = workloads.tshock(nx, ny, 40.0, 10.0, ratio=ratio, omega=om)
+            params = fracture.make_params(**p, newton=0, am_tol=args.am_tol,
+                                          max_am=args.tshock_max_am, pcg_rtol=args.pcg_rtol)
+            solver = fracture.Fracture(params, None, device="cuda:0")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sweeps, ok = 0, True
+            for tau in taus:
+                solver.set_load(tau)
+                try:
+                    st = solver.solve_step()
+                except fracture.FractureError as e:
+                    # sweep limit of a step: reported, and the evolution stops there
+                    log(f"[tshock] DT/DT_c={ratio:g} omega={om:g} tau={tau:g}: {e}")
+                    ok = False
+                    break
+                sweeps += st["sweeps"]
+                ok = ok and st["converged"]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            amax = float(solver.state()[1].max())
+            solver.close()
+            log(f"[tshock] DT/DT_c={ratio:g} omega={om:g}: {sweeps} sweeps, {dt:.2f} s, "
+                f"converged={ok}, max alpha {amax:.3f}")
+            row[f"{om:g}"] = {"sweeps": sweeps, "seconds": round(dt, 3), "converged": ok}
+        base = row["1"]["sweeps"] if "1" in row and row["1"]["converged"] else None
+        best = min((v["sweeps"] for v in row.values() if v["converged"]), default=None)
+        row["reduction_vs_omega1"] = round(1.0 - best / base, 4) if base and best else None
+        rows[f"{ratio:g}"] = row
+    return {"workload": (f"2D thermal shock (Sec. 4.3): slab 40 x 10, ell = 1, {nx}x{ny} cells "
+                         f"(h = ell/{nx / 40:g}), AT1, plane strain, nu = 0.3, erfc eigenstrain, "
+                         f"u_x = 0 laterally, u_y = 0 on top; plain ORAM to ||dalpha||inf < "
+                         f"{args.am_tol:g}, tau = 0.1..{args.tshock_tau:g} in steps of 0.1; "
+                         f"sweeps summed over the evolution"),
+            "sweeps": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,6 +309,11 @@ def main():
     ap.add_argument("--surfing", action="store_true", help="run only the surfing slab (Sec. 4.1)")
     ap.add_argument("--surf-ell", type=float, default=1.0 / 128)
     ap.add_argument("--no-surfing", action="store_true", help="skip the surfing sample")
+    ap.add_argument("--tshock", action="store_true",
+                    help="run only the 2D thermal shock omega sweep (Sec. 4.3, Table 3)")
+    ap.add_argument("--tshock-n", type=int, default=256, help="thermal shock cells along the slab")
+    ap.add_argument("--tshock-tau", type=float, default=2.0, help="last tau of the thermal shock")
+    ap.add_argument("--tshock-max-am", type=int, default=20000, help="sweep limit per thermal shock step")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream sample")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-omega", action="store_true", help="skip the omega = 1.4, 1.8 legs")
@@ -295,6 +352,9 @@ def main():
         return
     if args.surfing:
         print(json.dumps({"surfing": surfing(args)}), flush=True)
+        return
+    if args.tshock:
+        print(json.dumps({"tshock": tshock(args)}), flush=True)
         return
     p, notch, loads, (y0, a) = workloads.config2(args.model, args.omega, seed=0, n=args.n)
 

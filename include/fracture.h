@@ -68,6 +68,16 @@ extern "C" {
                                        printed; load = t.  On the crack line
                                        behind the tip the boundary node takes
                                        the mean of the two faces (zero).     */
+#define FRACTURE_LOAD_THERMAL_SHOCK_2D 3
+                                    /* thermal shock (Sec. 4.3, eqs.
+                                       (energytshock), (tempfielderfc)): the
+                                       slab is cooled on y = 0; eps0 =
+                                       -thermal_dT * erfc(y_c / (ell t)) I at
+                                       each triangle centroid y_c, load = t
+                                       the dimensionless time tau (eps0 = 0
+                                       for t <= 0); u_x = 0 on x = 0 and
+                                       x = lx, u_y = 0 on y = ly, the cooled
+                                       face traction free                    */
 
 #define FRACTURE_RELAX_PROJECT 0  /* alpha <- clip(alpha + omega*dalpha)       */
 #define FRACTURE_RELAX_RATIO   1  /* largest common feasible omega_bar <= omega */
@@ -163,6 +173,9 @@ typedef struct {
                                omega (the paper's hypothesis on the optimal
                                omega, Sec. 2.2; it leaves an automatic choice
                                to future work); 0: omega throughout           */
+  double thermal_dT;        /* FRACTURE_LOAD_THERMAL_SHOCK_2D: shock intensity
+                               beta * DT of the imposed temperature; finite,
+                               any sign (negative heats)                      */
 } fracture_params;
 
 /* Fill *p with the documented defaults for a 2D tension problem on an

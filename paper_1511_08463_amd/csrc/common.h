@@ -25,13 +25,13 @@ constexpr int VB = 256;           // 1D vector kernels
 constexpr int VGRID = 2048;       // fixed grid of 1D reductions (8 blocks per CU)
 
 // Boundary-condition families (mirrors FRACTURE_LOAD_* of the C ABI).
-enum { BC_TENSION_2D = 0, BC_THERMAL_3D = 1, BC_SURFING_2D = 2 };
+enum { BC_TENSION_2D = 0, BC_THERMAL_3D = 1, BC_SURFING_2D = 2, BC_TSHOCK_2D = 3 };
 
 // Parameters of the 2D Dirichlet lifting: for the surfing load, the boundary
 // carries K_I/(2 mu) sqrt(r/2pi) (kappa - cos theta) (cos(theta/2), sin(theta/2))
 // about the tip (lc + v t, ly/2).
 struct Load2D {
-  int kind;          // BC_TENSION_2D or BC_SURFING_2D
+  int kind;          // BC_TENSION_2D, BC_SURFING_2D or BC_TSHOCK_2D
   double ki2mu;      // K_I / (2 mu)
   double kappa;      // (3 - nu) / (1 + nu)
   double lc, v;      // initial tip abscissa and speed
@@ -63,8 +63,10 @@ struct Grid {
   int N;
   int bc;
   int dim;
-  // thermal eigenstrain eps0 = -eig_dT exp(-x_c / eig_depth) I per element
-  // (3D thermal load); zero for operator actions on error equations
+  // thermal eigenstrain per element: eps0 = -eig_dT exp(-x_c / eig_depth) I
+  // (3D thermal load) or -eig_dT erfc(y_c / eig_depth) I (2D thermal shock,
+  // bc == BC_TSHOCK_2D); eig_dT is zero for operator actions on error
+  // equations
   double eig_dT, eig_depth;
 };
 

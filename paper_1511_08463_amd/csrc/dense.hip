@@ -13,6 +13,7 @@ constexpr int DB = 1024;
 
 __device__ __forceinline__ bool fixed_dof2(const Grid& g, int comp, int i, int j) {
   if (g.bc == BC_SURFING_2D) return i == 0 || i == g.nx || j == 0 || j == g.ny;
+  if (g.bc == BC_TSHOCK_2D) return comp == 0 ? (i == 0 || i == g.nx) : (j == g.ny);
   if (g.bc != BC_TENSION_2D) return false;
   return comp == 0 ? (i == 0 && j == 0) : (j == 0 || j == g.ny);
 }

@@ -26,7 +26,7 @@ namespace frac {
 // One thread per node (64 x NB_Y threads per tile, tiles in XCD-aware
 // order): the short dependency chain suits the small, latency-bound
 // multigrid levels.
-template <int MODE, bool FA, bool HASX, int RED, class T>
+template <int MODE, bool FA, bool HASX, int RED, class T, bool EIG = false>
 __global__ __launch_bounds__(NB) void k_node2d(Grid g, Mat m, const T* __restrict__ coef, T kell,
                                                const T* __restrict__ x, T* __restrict__ y,
                                                const T* __restrict__ b, const T* __restrict__ din,
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(NB) void k_node2d(Grid g, Mat m, const T* __restric
     T c[6];
     coef6<FA>(g, coef, kell, i, j, c);
     T fx, fy, dx, dy;
-    node_force2d<HASX, MODE == M_SMOOTH>(g, m, c, x, x + N, i, j, fx, fy, dx, dy);
+    node_force2d<HASX, MODE == M_SMOOTH, EIG>(g, m, c, x, x + N, i, j, fx, fy, dx, dy);
     const T xc = HASX ? x[n] : T(0), yc = HASX ? x[n + N] : T(0);
     node_out2d<MODE, RED>(g, i, j, fx, fy, dx, dy, xc, yc, y, b, din, dout, cd, cr, mask, acc);
   }
@@ -61,7 +61,7 @@ constexpr int col_rows() { return MODE == M_SMOOTH ? COL_NY_SMOOTH : COL_NY; }
 // (column2d): each element stress is formed once per thread and each row is
 // loaded once, which pays on the large levels.  Tiles are taken in
 // XCD-aware order (xcd_tile); there are no more of them than k_node2d's.
-template <int MODE, bool FA, bool HASX, int RED, class T>
+template <int MODE, bool FA, bool HASX, int RED, class T, bool EIG = false>
 __global__ __launch_bounds__(NB_X) void k_col2d(Grid g, Mat m, const T* __restrict__ coef, T kell,
                                                 const T* __restrict__ x, T* __restrict__ y,
                                                 const T* __restrict__ b, const T* __restrict__ din,
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(NB_X) void k_col2d(Grid g, Mat m, const T* __restri
   const int j0 = (t / nbx) * col_rows<MODE>();
   double acc = 0.0;
   if (i <= g.nx) {
-    column2d<col_rows<MODE>(), FA, HASX, MODE == M_SMOOTH>(
+    column2d<col_rows<MODE>(), FA, HASX, MODE == M_SMOOTH, EIG>(
         g, m, coef, kell, x, i, j0, [&](int j, T fx, T fy, T dx, T dy, T xc, T yc) {
           node_out2d<MODE, RED>(g, i, j, fx, fy, dx, dy, xc, yc, y, b, din, dout, cd, cr, mask, acc);
         });
@@ -114,16 +114,24 @@ void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, cons
   const bool col = use_col2d(g);
   const dim3 gr = op_grid2(g, col, col_rows<M_APPLY>());
   const T k = T(kell);
-#define APPLY_CASE(FA, RD)                                                                      \
+  // the thermal-shock eigenstrain enters the operator of the actual problem
+  // (finest level, load grid): y = K x - f
+  const bool eig = fine && g.eig_dT != 0.0;
+#define APPLY_CASE_E(FA, RD, EG)                                                                \
   do {                                                                                          \
   if (col)                                                                                      \
-    hipLaunchKernelGGL((k_col2d<M_APPLY, FA, true, RD, T>), gr, dim3(NB_X), 0, st, g, m, coef, k, \
-                       x, y, b, (const T*)nullptr, (T*)nullptr, T(0), T(0), mask, r);          \
+    hipLaunchKernelGGL((k_col2d<M_APPLY, FA, true, RD, T, EG>), gr, dim3(NB_X), 0, st, g, m, coef, \
+                       k, x, y, b, (const T*)nullptr, (T*)nullptr, T(0), T(0), mask, r);       \
   else                                                                                          \
-    hipLaunchKernelGGL((k_node2d<M_APPLY, FA, true, RD, T>), gr, dim3(NB_X, NB_Y), 0, st, g, m, \
-                       coef, k, x, y, b, (const T*)nullptr, (T*)nullptr, T(0), T(0), mask, r); \
+    hipLaunchKernelGGL((k_node2d<M_APPLY, FA, true, RD, T, EG>), gr, dim3(NB_X, NB_Y), 0, st, g, \
+                       m, coef, k, x, y, b, (const T*)nullptr, (T*)nullptr, T(0), T(0), mask, r); \
   } while (0)
-  if (fine) {
+#define APPLY_CASE(FA, RD) APPLY_CASE_E(FA, RD, false)
+  if (fine && eig) {
+    if (red == R_NONE) APPLY_CASE_E(true, R_NONE, true);
+    else if (red == R_DOT) APPLY_CASE_E(true, R_DOT, true);
+    else APPLY_CASE_E(true, R_FREE2, true);
+  } else if (fine) {
     if (red == R_NONE) APPLY_CASE(true, R_NONE);
     else if (red == R_DOT) APPLY_CASE(true, R_DOT);
     else APPLY_CASE(true, R_FREE2);
@@ -133,6 +141,7 @@ void launch_apply2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, cons
     else APPLY_CASE(false, R_FREE2);
   }
 #undef APPLY_CASE
+#undef APPLY_CASE_E
   if (red != R_NONE) launch_finish(st, r, (int)(gr.x * gr.y), false);
 }
 
@@ -144,21 +153,26 @@ void launch_resid2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, cons
   const bool col = use_col2d(g);
   const dim3 gr = op_grid2(g, col, col_rows<M_RESID>());
   const T k = T(kell);
-#define RES_CASE(FA, RD)                                                                        \
+  const bool eig = fine && g.eig_dT != 0.0;   // r = b - (K x - f) with the eigenstrain load
+#define RES_CASE_E(FA, RD, EG)                                                                  \
   do {                                                                                          \
   if (col)                                                                                      \
-    hipLaunchKernelGGL((k_col2d<M_RESID, FA, true, RD, T>), gr, dim3(NB_X), 0, st, g, m, coef, k, \
-                       x, r, b, (const T*)nullptr, (T*)nullptr, T(0), T(0), 1, rr);            \
+    hipLaunchKernelGGL((k_col2d<M_RESID, FA, true, RD, T, EG>), gr, dim3(NB_X), 0, st, g, m, coef, \
+                       k, x, r, b, (const T*)nullptr, (T*)nullptr, T(0), T(0), 1, rr);         \
   else                                                                                          \
-    hipLaunchKernelGGL((k_node2d<M_RESID, FA, true, RD, T>), gr, dim3(NB_X, NB_Y), 0, st, g, m, \
-                       coef, k, x, r, b, (const T*)nullptr, (T*)nullptr, T(0), T(0), 1, rr); \
+    hipLaunchKernelGGL((k_node2d<M_RESID, FA, true, RD, T, EG>), gr, dim3(NB_X, NB_Y), 0, st, g, \
+                       m, coef, k, x, r, b, (const T*)nullptr, (T*)nullptr, T(0), T(0), 1, rr); \
   } while (0)
-  if (fine) {
+#define RES_CASE(FA, RD) RES_CASE_E(FA, RD, false)
+  if (fine && eig) {
+    if (red) RES_CASE_E(true, R_DOT, true); else RES_CASE_E(true, R_NONE, true);
+  } else if (fine) {
     if (red) RES_CASE(true, R_DOT); else RES_CASE(true, R_NONE);
   } else {
     if (red) RES_CASE(false, R_DOT); else RES_CASE(false, R_NONE);
   }
 #undef RES_CASE
+#undef RES_CASE_E
   if (red) launch_finish(st, rr, (int)(gr.x * gr.y), false);
 }
 
@@ -324,8 +338,21 @@ __global__ __launch_bounds__(VB) void k_lift_surf2d(Grid g, Load2D ld, double* _
   u[g.N + n] = uy;
 }
 
+// Thermal shock: the lateral u_x and the top u_y are held at zero.
+__global__ __launch_bounds__(VB) void k_lift_tshock2d(Grid g, double* __restrict__ u) {
+  const int n = blockIdx.x * VB + threadIdx.x;
+  if (n >= g.N) return;
+  const int W = g.nx + 1, i = n % W, j = n / W;
+  if (fixed_x2(g, i, j)) u[n] = 0.0;
+  if (fixed_y2(g, i, j)) u[g.N + n] = 0.0;
+}
+
 void launch_lift2d(hipStream_t st, const Grid& g, double* u, double t, const Load2D& ld) {
   if (g.dim == 3) return launch_lift3d(st, g, u);
+  if (ld.kind == BC_TSHOCK_2D) {
+    hipLaunchKernelGGL(k_lift_tshock2d, dim3((g.N + VB - 1) / VB), dim3(VB), 0, st, g, u);
+    return;
+  }
   if (ld.kind == BC_SURFING_2D) {
     hipLaunchKernelGGL(k_lift_surf2d, dim3((g.N + VB - 1) / VB), dim3(VB), 0, st, g, ld, u, t);
     return;
@@ -337,7 +364,9 @@ void launch_lift2d(hipStream_t st, const Grid& g, double* u, double t, const Loa
 // damage subproblem: W2 per element, Helmholtz operator, VI residual
 // ---------------------------------------------------------------------------
 
-// W2_e = A0 eps_e : eps_e for both triangles of every cell.
+// W2_e = A0 eps_e : eps_e for both triangles of every cell, eps_e the
+// effective strain eps(u) - eps0 when the grid carries the thermal-shock
+// eigenstrain.
 __global__ __launch_bounds__(VB) void k_w2_2d(Grid g, Mat m, const double* __restrict__ u,
                                               double* __restrict__ w2) {
   const int cell = blockIdx.x * VB + threadIdx.x;
@@ -347,13 +376,15 @@ __global__ __launch_bounds__(VB) void k_w2_2d(Grid g, Mat m, const double* __res
   const double* ux = u;
   const double* uy = u + g.N;
   const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy;
+  double s0 = 0.0, s1 = 0.0;
+  if (g.eig_dT != 0.0) eig_row2d(g, cj, s0, s1);
   {
-    const double exx = (ux[n10] - ux[n00]) * ihx, eyy = (uy[n11] - uy[n10]) * ihy;
+    const double exx = (ux[n10] - ux[n00]) * ihx - s0, eyy = (uy[n11] - uy[n10]) * ihy - s0;
     const double gam = (uy[n10] - uy[n00]) * ihx + (ux[n11] - ux[n10]) * ihy;
     w2[2 * cell] = m.l2m * (exx * exx + eyy * eyy) + 2.0 * m.lam * exx * eyy + m.mu * gam * gam;
   }
   {
-    const double exx = (ux[n11] - ux[n01]) * ihx, eyy = (uy[n01] - uy[n00]) * ihy;
+    const double exx = (ux[n11] - ux[n01]) * ihx - s1, eyy = (uy[n01] - uy[n00]) * ihy - s1;
     const double gam = (uy[n11] - uy[n01]) * ihx + (ux[n01] - ux[n00]) * ihy;
     w2[2 * cell + 1] = m.l2m * (exx * exx + eyy * eyy) + 2.0 * m.lam * exx * eyy + m.mu * gam * gam;
   }
@@ -566,6 +597,8 @@ __global__ __launch_bounds__(VB) void k_energy2d(Grid g, Mat m, double kell, dou
     const int n00 = ci + W * cj, n10 = n00 + 1, n11 = n00 + 1 + W, n01 = n00 + W;
     const double* ux = u;
     const double* uy = u + g.N;
+    double es[2] = {0.0, 0.0};   // thermal-shock eigenstrain of the cell's T0, T1
+    if (g.eig_dT != 0.0) eig_row2d(g, cj, es[0], es[1]);
     for (int t = 0; t < 2; ++t) {
       const int nA = n00, nB = t == 0 ? n10 : n11, nC = t == 0 ? n11 : n01;
       double exx, eyy, gam;
@@ -576,6 +609,8 @@ __global__ __launch_bounds__(VB) void k_energy2d(Grid g, Mat m, double kell, dou
         exx = (ux[n11] - ux[n01]) * ihx; eyy = (uy[n01] - uy[n00]) * ihy;
         gam = (uy[n11] - uy[n01]) * ihx + (ux[n01] - ux[n00]) * ihy;
       }
+      exx -= es[t];
+      eyy -= es[t];
       const double w2 = m.l2m * (exx * exx + eyy * eyy) + 2.0 * m.lam * exx * eyy + m.mu * gam * gam;
       const double a0 = a[nA], a1 = a[nB], a2 = a[nC];
       el += 0.5 * abar3(a0, a1, a2, kell) * area * w2;
@@ -624,7 +659,7 @@ __device__ __forceinline__ double mref_pair(double w0, double w1, double w2, dou
   return (w0 * b0 + w1 * b1 + w2 * b2 + (w0 + w1 + w2) * (b0 + b1 + b2)) * (1.0 / 12.0);
 }
 
-template <bool HAS_XU, bool HAS_XA, bool DOT>
+template <bool HAS_XU, bool HAS_XA, bool DOT, bool EIG>
 __global__ __launch_bounds__(NB) void k_jac_u2d(Grid g, Mat m, double kell,
                                                 const double* __restrict__ alpha,
                                                 const double* __restrict__ u,
@@ -672,7 +707,8 @@ __global__ __launch_bounds__(NB) void k_jac_u2d(Grid g, Mat m, double kell,
       c[4] = -2.0 * mref_pair(wSW, wC, wW, bSW, bC, bW);
       c[5] = -2.0 * mref_pair(wS, wE, wC, bS, bE, bC);
       double gx, gy;
-      node_force2d<true, false>(g, m, c, u, u + N, i, j, gx, gy, dx, dy);
+      // the stress of the effective strain of u (eigenstrain when EIG)
+      node_force2d<true, false, EIG>(g, m, c, u, u + N, i, j, gx, gy, dx, dy);
       fx += gx;
       fy += gy;
     }
@@ -698,7 +734,7 @@ __device__ __forceinline__ void tri_strain(int t, double ihx, double ihy, const 
   gam = gy[0] * vx[0] + gy[1] * vx[1] + gy[2] * vx[2] + gx[0] * vy[0] + gx[1] * vy[1] + gx[2] * vy[2];
 }
 
-template <bool HAS_XU, bool HAS_XA, bool DOT>
+template <bool HAS_XU, bool HAS_XA, bool DOT, bool EIG>
 __global__ __launch_bounds__(NB) void k_jac_a2d(Grid g, Mat m, Helm hp,
                                                 const double* __restrict__ alpha,
                                                 const double* __restrict__ u,
@@ -739,6 +775,13 @@ __global__ __launch_bounds__(NB) void k_jac_a2d(Grid g, Mat m, Helm hp,
           double e0, e1, e2, f0, f1, f2;
           tri_strain(t, ihx, ihy, ux, uy, e0, e1, e2);
           tri_strain(t, ihx, ihy, vx, vy, f0, f1, f2);
+          if (EIG) {   // effective strain of u
+            double s0, s1;
+            eig_row2d(g, cj, s0, s1);
+            const double se = t == 0 ? s0 : s1;
+            e0 -= se;
+            e1 -= se;
+          }
           // sigma(u) : eps(v) with sigma = D eps (engineering shear)
           const double s = (m.l2m * e0 + m.lam * e1) * f0 + (m.lam * e0 + m.l2m * e1) * f1 + m.mu * e2 * f2;
           const double mb = (bb[v] + bb[0] + bb[1] + bb[2]) * (1.0 / 12.0);
@@ -762,10 +805,19 @@ void launch_jac2d(hipStream_t st, const Grid& g, const Mat& m, double kell, doub
                   Red ra, const double* band) {
   dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
   Helm hp{cL, cM, 0.0};
+  // the coupling blocks carry the stress of u's effective strain: the
+  // thermal-shock eigenstrain when the (load) grid has one
+  const bool eig = g.eig_dT != 0.0;
   if (yu) {
-#define JU(A, B, D) \
-  hipLaunchKernelGGL((k_jac_u2d<A, B, D>), gr, bl, 0, st, g, m, kell, alpha, u, xu, xa, mask, yu, ru, \
-                     band)
+#define JU(A, B, D)                                                                                \
+  do {                                                                                             \
+    if (eig && B)                                                                                  \
+      hipLaunchKernelGGL((k_jac_u2d<A, B, D, true>), gr, bl, 0, st, g, m, kell, alpha, u, xu, xa,  \
+                         mask, yu, ru, band);                                                      \
+    else                                                                                           \
+      hipLaunchKernelGGL((k_jac_u2d<A, B, D, false>), gr, bl, 0, st, g, m, kell, alpha, u, xu, xa, \
+                         mask, yu, ru, band);                                                      \
+  } while (0)
     if (xu && xa) { if (dot) JU(true, true, true); else JU(true, true, false); }
     else if (xu) { if (dot) JU(true, false, true); else JU(true, false, false); }
     else JU(false, true, false);
@@ -773,8 +825,15 @@ void launch_jac2d(hipStream_t st, const Grid& g, const Mat& m, double kell, doub
     if (dot && xu) launch_finish(st, ru, (int)(gr.x * gr.y), false);
   }
   if (ya) {
-#define JA(A, B, D) \
-  hipLaunchKernelGGL((k_jac_a2d<A, B, D>), gr, bl, 0, st, g, m, hp, alpha, u, w2, xu, xa, mask, ya, ra)
+#define JA(A, B, D)                                                                                \
+  do {                                                                                             \
+    if (eig && A)                                                                                  \
+      hipLaunchKernelGGL((k_jac_a2d<A, B, D, true>), gr, bl, 0, st, g, m, hp, alpha, u, w2, xu, xa, \
+                         mask, ya, ra);                                                            \
+    else                                                                                           \
+      hipLaunchKernelGGL((k_jac_a2d<A, B, D, false>), gr, bl, 0, st, g, m, hp, alpha, u, w2, xu,   \
+                         xa, mask, ya, ra);                                                        \
+  } while (0)
     if (xu && xa) { if (dot) JA(true, true, true); else JA(true, true, false); }
     else if (xa) { if (dot) JA(false, true, true); else JA(false, true, false); }
     else JA(true, false, false);

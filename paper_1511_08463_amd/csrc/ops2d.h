@@ -12,17 +12,30 @@ namespace frac {
 // ---------------------------------------------------------------------------
 
 // tension: u_x at node (0,0), u_y on the bottom and top edges;
-// surfing: both components on the whole boundary
+// surfing: both components on the whole boundary;
+// thermal shock: u_x on the lateral edges, u_y on the top edge
 __device__ __forceinline__ bool on_edge2(const Grid& g, int i, int j) {
   return i == 0 || i == g.nx || j == 0 || j == g.ny;
 }
 __device__ __forceinline__ bool fixed_x2(const Grid& g, int i, int j) {
   if (g.bc == BC_SURFING_2D) return on_edge2(g, i, j);
+  if (g.bc == BC_TSHOCK_2D) return i == 0 || i == g.nx;
   return (g.bc == BC_TENSION_2D) && i == 0 && j == 0;
 }
 __device__ __forceinline__ bool fixed_y2(const Grid& g, int i, int j) {
   if (g.bc == BC_SURFING_2D) return on_edge2(g, i, j);
+  if (g.bc == BC_TSHOCK_2D) return j == g.ny;
   return (g.bc == BC_TENSION_2D) && (j == 0 || j == g.ny);
+}
+
+// Thermal-shock eigenstrain eps0 = s I of the triangles of cell row cj
+// (eq. (tempfielderfc) at the centroid): T0 (s0) has its centroid at
+// (cj + 1/3) hy, T1 (s1) at (cj + 2/3) hy.  Zero outside the grid rows.
+__device__ __forceinline__ void eig_row2d(const Grid& g, int cj, double& s0, double& s1) {
+  if (cj < 0 || cj >= g.ny) { s0 = s1 = 0.0; return; }
+  const double r = g.hy / g.eig_depth;
+  s0 = -g.eig_dT * erfc((cj + 1.0 / 3.0) * r);
+  s1 = -g.eig_dT * erfc((cj + 2.0 / 3.0) * r);
 }
 
 // ---------------------------------------------------------------------------
@@ -71,7 +84,11 @@ __device__ __forceinline__ void coef6(const Grid& g, const T* __restrict__ coef,
 
 // Force (fx, fy) = (K x) at node (i, j) and, when DIAG, the diagonal entries
 // (dx, dy) of K for the node's two DOFs.
-template <bool HASX, bool DIAG, class T>
+//
+// EIG (thermal shock, finest level): the forces of the effective strain
+// eps(x) - eps0, i.e. K x - f with f the eigenstrain load of eq.
+// (energytshock).
+template <bool HASX, bool DIAG, bool EIG = false, class T>
 __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const T c[6],
                                              const T* __restrict__ ux, const T* __restrict__ uy,
                                              int i, int j, T& fx, T& fy, T& dx, T& dy) {
@@ -93,11 +110,19 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
   }
   fx = fy = dx = dy = T(0);
   const T hxx = ihx * ihx, hyy = ihy * ihy;
+  // eigenstrain of the cell rows above (j) and below (j - 1) the node
+  T su0 = 0, su1 = 0, sd0 = 0, sd1 = 0;
+  if (EIG) {
+    double a0, a1, b0, b1;
+    eig_row2d(g, j, a0, a1);
+    eig_row2d(g, j - 1, b0, b1);
+    su0 = T(a0); su1 = T(a1); sd0 = T(b0); sd1 = T(b1);
+  }
   // (a) cell(i,j) T0: node is vertex 0, gradient (-1/hx, 0)
   if (R && U) {
     const T w = c[0] * area;
     if (HASX) {
-      const T exx = (ex - cx) * ihx, eyy = (ney - ey) * ihy;
+      const T exx = (ex - cx) * ihx - su0, eyy = (ney - ey) * ihy - su0;
       const T gam = (ey - cy) * ihx + (nex - ex) * ihy;
       const T sxx = l2m * exx + lam * eyy, sxy = mu * gam;
       fx += w * (-sxx * ihx);
@@ -109,7 +134,7 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
   if (R && U) {
     const T w = c[1] * area;
     if (HASX) {
-      const T exx = (nex - nnx) * ihx, eyy = (nny - cy) * ihy;
+      const T exx = (nex - nnx) * ihx - su1, eyy = (nny - cy) * ihy - su1;
       const T gam = (ney - nny) * ihx + (nnx - cx) * ihy;
       const T syy = lam * exx + l2m * eyy, sxy = mu * gam;
       fx += w * (-sxy * ihy);
@@ -121,7 +146,7 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
   if (L && U) {
     const T w = c[2] * area;
     if (HASX) {
-      const T exx = (cx - wx) * ihx, eyy = (nny - cy) * ihy;
+      const T exx = (cx - wx) * ihx - su0, eyy = (nny - cy) * ihy - su0;
       const T gam = (cy - wy) * ihx + (nnx - cx) * ihy;
       const T sxx = l2m * exx + lam * eyy, syy = lam * exx + l2m * eyy, sxy = mu * gam;
       fx += w * (sxx * ihx - sxy * ihy);
@@ -133,7 +158,7 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
   if (L && D) {
     const T w = c[3] * area;
     if (HASX) {
-      const T exx = (sx - swx) * ihx, eyy = (cy - sy) * ihy;
+      const T exx = (sx - swx) * ihx - sd0, eyy = (cy - sy) * ihy - sd0;
       const T gam = (sy - swy) * ihx + (cx - sx) * ihy;
       const T syy = lam * exx + l2m * eyy, sxy = mu * gam;
       fx += w * (sxy * ihy);
@@ -145,7 +170,7 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
   if (L && D) {
     const T w = c[4] * area;
     if (HASX) {
-      const T exx = (cx - wx) * ihx, eyy = (wy - swy) * ihy;
+      const T exx = (cx - wx) * ihx - sd1, eyy = (wy - swy) * ihy - sd1;
       const T gam = (cy - wy) * ihx + (wx - swx) * ihy;
       const T sxx = l2m * exx + lam * eyy, sxy = mu * gam;
       fx += w * (sxx * ihx);
@@ -157,7 +182,7 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
   if (R && D) {
     const T w = c[5] * area;
     if (HASX) {
-      const T exx = (ex - cx) * ihx, eyy = (cy - sy) * ihy;
+      const T exx = (ex - cx) * ihx - sd1, eyy = (cy - sy) * ihy - sd1;
       const T gam = (ey - cy) * ihx + (cx - sx) * ihy;
       const T sxx = l2m * exx + lam * eyy, syy = lam * exx + l2m * eyy, sxy = mu * gam;
       fx += w * (-sxx * ihx + sxy * ihy);
@@ -243,7 +268,8 @@ __device__ __forceinline__ void load_row3(const Grid& g, const T* __restrict__ x
   }
 }
 
-// Forces (K x) and, when DIAG, diagonal entries of K at nodes (i, j) for
+// Forces (K x, or K x - f with the thermal-shock eigenstrain load when EIG)
+// and, when DIAG, diagonal entries of K at nodes (i, j) for
 // j = j0 .. min(j0 + ROWS - 1, ny); fin(j, fx, fy, dx, dy, x_x, x_y) receives
 // each node's values (x_x, x_y: x at the node, zero without HASX).
 // The cells of row cj left and right of the column, L = (i-1, cj) and
@@ -255,7 +281,7 @@ __device__ __forceinline__ void load_row3(const Grid& g, const T* __restrict__ x
 // (the six triangles around a node are the three above it in cell row j and
 // the three below it in cell row j-1).  Precondition: 0 <= i <= nx,
 // 0 <= j0 <= ny.
-template <int ROWS, bool FA, bool HASX, bool DIAG, class T, class Fin>
+template <int ROWS, bool FA, bool HASX, bool DIAG, bool EIG, class T, class Fin>
 __device__ __forceinline__ void column2d(const Grid& g, const Mat& m, const T* __restrict__ coef,
                                          T kell, const T* __restrict__ x, int i, int j0,
                                          Fin&& fin) {
@@ -273,6 +299,12 @@ __device__ __forceinline__ void column2d(const Grid& g, const Mat& m, const T* _
     const int cj = j0 - 1 + s;
     if (cj > g.ny) break;
     load_row3<FA, HASX>(g, x, coef, i, cj + 1, hi);
+    T s0 = 0, s1 = 0;   // eigenstrain of the row's T0 / T1 triangles (EIG)
+    if (EIG) {
+      double e0, e1;
+      eig_row2d(g, cj, e0, e1);
+      s0 = T(e0); s1 = T(e1);
+    }
     if (cj >= 0 && cj < g.ny) {
       if (hasL) {
         const T wl0 = area * (FA ? abar3(lo.a[0], lo.a[1], hi.a[1], kell) : coef[2 * (i - 1 + nx * cj)]);
@@ -280,11 +312,11 @@ __device__ __forceinline__ void column2d(const Grid& g, const Mat& m, const T* _
         T sxx = 0, syy = 0, sxy = 0, txx = 0, txy = 0;
         if (HASX) {
           // L.T0 strain: grads (-1/hx, 0), (1/hx, -1/hy), (0, 1/hy)
-          const T exx = (lo.ux[1] - lo.ux[0]) * ihx, eyy = (hi.uy[1] - lo.uy[1]) * ihy;
+          const T exx = (lo.ux[1] - lo.ux[0]) * ihx - s0, eyy = (hi.uy[1] - lo.uy[1]) * ihy - s0;
           const T gam = (hi.ux[1] - lo.ux[1]) * ihy + (lo.uy[1] - lo.uy[0]) * ihx;
           sxx = l2m * exx + lam * eyy; syy = lam * exx + l2m * eyy; sxy = mu * gam;
           // L.T1 strain: grads (0, -1/hy), (1/hx, 0), (-1/hx, 1/hy)
-          const T fxx = (hi.ux[1] - hi.ux[0]) * ihx, fyy = (hi.uy[0] - lo.uy[0]) * ihy;
+          const T fxx = (hi.ux[1] - hi.ux[0]) * ihx - s1, fyy = (hi.uy[0] - lo.uy[0]) * ihy - s1;
           const T fam = (hi.ux[0] - lo.ux[0]) * ihy + (hi.uy[1] - hi.uy[0]) * ihx;
           txx = l2m * fxx + lam * fyy; txy = mu * fam;
         }
@@ -309,11 +341,11 @@ __device__ __forceinline__ void column2d(const Grid& g, const Mat& m, const T* _
         T sxx = 0, sxy = 0, txx = 0, tyy = 0, txy = 0;
         if (HASX) {
           // C.T0 strain
-          const T exx = (lo.ux[2] - lo.ux[1]) * ihx, eyy = (hi.uy[2] - lo.uy[2]) * ihy;
+          const T exx = (lo.ux[2] - lo.ux[1]) * ihx - s0, eyy = (hi.uy[2] - lo.uy[2]) * ihy - s0;
           const T gam = (hi.ux[2] - lo.ux[2]) * ihy + (lo.uy[2] - lo.uy[1]) * ihx;
           sxx = l2m * exx + lam * eyy; sxy = mu * gam;
           // C.T1 strain
-          const T fxx = (hi.ux[2] - hi.ux[1]) * ihx, fyy = (hi.uy[1] - lo.uy[1]) * ihy;
+          const T fxx = (hi.ux[2] - hi.ux[1]) * ihx - s1, fyy = (hi.uy[1] - lo.uy[1]) * ihy - s1;
           const T fam = (hi.ux[1] - lo.ux[1]) * ihy + (hi.uy[2] - hi.uy[1]) * ihx;
           txx = l2m * fxx + lam * fyy; tyy = lam * fxx + l2m * fyy; txy = mu * fam;
         }

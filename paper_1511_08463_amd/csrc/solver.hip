@@ -160,7 +160,9 @@ int validate(const fracture_params* p) {
   if (!(p->omega > 0 && p->omega < 2)) return FRACTURE_EINVAL;
   if (p->relax_mode < 0 || p->relax_mode > 2) return FRACTURE_EINVAL;
   if (p->dim == 2 && p->load_kind != FRACTURE_LOAD_TENSION_2D &&
-      p->load_kind != FRACTURE_LOAD_SURFING_2D)
+      p->load_kind != FRACTURE_LOAD_SURFING_2D && p->load_kind != FRACTURE_LOAD_THERMAL_SHOCK_2D)
+    return FRACTURE_EINVAL;
+  if (p->load_kind == FRACTURE_LOAD_THERMAL_SHOCK_2D && !std::isfinite(p->thermal_dT))
     return FRACTURE_EINVAL;
   if (p->load_kind == FRACTURE_LOAD_SURFING_2D &&
       (!std::isfinite(p->surf_ki) || !std::isfinite(p->surf_v) || !std::isfinite(p->surf_lc)))
@@ -185,6 +187,13 @@ int validate(const fracture_params* p) {
   return FRACTURE_OK;
 }
 
+// Boundary-condition family of a 2D load kind.
+int bc_kind2d(int load_kind) {
+  if (load_kind == FRACTURE_LOAD_SURFING_2D) return BC_SURFING_2D;
+  if (load_kind == FRACTURE_LOAD_THERMAL_SHOCK_2D) return BC_TSHOCK_2D;
+  return BC_TENSION_2D;
+}
+
 // Level shapes: halve both axes while they stay even and the level has more
 // DOFs than coarse_max_dofs (at least once, so there is always a coarse level).
 int level_shapes(const fracture_params* p, Grid* out) {
@@ -195,8 +204,7 @@ int level_shapes(const fracture_params* p, Grid* out) {
     Grid g{};
     g.nx = nx; g.ny = ny; g.nz = nz; g.hx = hx; g.hy = hy; g.hz = hz;
     g.N = (nx + 1) * (ny + 1) * (dim == 3 ? nz + 1 : 1);
-    g.bc = dim == 3 ? BC_THERMAL_3D
-                    : (p->load_kind == FRACTURE_LOAD_SURFING_2D ? BC_SURFING_2D : BC_TENSION_2D);
+    g.bc = dim == 3 ? BC_THERMAL_3D : bc_kind2d(p->load_kind);
     g.dim = dim;
     g.eig_dT = 0.0;
     g.eig_depth = p->thermal_depth;
@@ -395,12 +403,20 @@ double chebyshev_bound3d(const Grid& g, const Mat& m) {
   return best;
 }
 
-// The finest grid carrying the current load as thermal eigenstrain (3D); the
-// residual, W2 and energy of the actual problem use it, operator actions on
-// error equations use the plain grid.
+// The finest grid carrying the current load as thermal eigenstrain (3D: the
+// load is DT; 2D thermal shock: the load is the time tau, the erfc length
+// ell tau); the residual, W2, energy and coupling blocks of the actual
+// problem use it, operator actions on error equations use the plain grid.
 Grid load_grid(const fracture* h) {
   Grid g = h->lv[0].g;
-  g.eig_dT = (g.dim == 3) ? h->load : 0.0;
+  if (g.dim == 3) {
+    g.eig_dT = h->load;
+  } else if (g.bc == BC_TSHOCK_2D && h->load > 0.0) {
+    g.eig_dT = h->p.thermal_dT;
+    g.eig_depth = h->p.ell * h->load;
+  } else {
+    g.eig_dT = 0.0;
+  }
   return g;
 }
 
@@ -879,7 +895,7 @@ constexpr double CHEB_C_LMIN = 0.04;
 // the active set and the inverse diagonal via the VI evaluation.
 // Returns ||Phi||^2 = sum over free rows of F_u^2 + sum Phi_a^2.
 int coupled_residual(fracture* h, const double* u, const double* a, double* Fu, double* phi2) {
-  const Grid& g = h->lv[0].g;
+  const Grid g = load_grid(h);
   launch_apply2d(h->st, g, h->mat, true, a, h->p.k_ell, u, Fu, nullptr, 1, 2, red(h, 0, S_EU2));
   launch_w2_2d(h->st, g, h->mat, u, h->w2);
   launch_vi_eval2d(h->st, g, h->cL, h->cM, h->cm, h->w2, a, nullptr, h->alpha_prev, h->S, S_MU,
@@ -935,7 +951,7 @@ void apply_Cinv(fracture* h, const double* x, double* y) {
 // symmetric multiplicative order: y1 = A^{-1} x1; y2 = C^{-1}(x2 - B^T y1);
 // z1 = A^{-1}(x1 - B y2); result [z1; y2].
 void apply_P_body(fracture* h, const double* x, double* y) {
-  const Grid& g = h->lv[0].g;
+  const Grid g = load_grid(h);   // B and B^T carry the stress of u's effective strain
   const int64_t n2 = h->n2, N = h->N;
   Red none{};
   if (h->p.newton_precond == 1) {
@@ -964,7 +980,7 @@ void apply_P(fracture* h, const double* x, double* y) {
 
 // y = J x on the inactive coupled system; S[S_TMP0] + S[S_TMP1] = x.y.
 void apply_J(fracture* h, const double* x, double* y) {
-  const Grid& g = h->lv[0].g;
+  const Grid g = load_grid(h);   // B and B^T carry the stress of u's effective strain
   const int64_t n2 = h->n2;
   launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask, x,
                x + n2, y, y + n2, true, red(h, 7, S_TMP0), red(h, 8, S_TMP1), h->S + S_JLO);
@@ -1313,7 +1329,7 @@ int fracture_create(const fracture_params* p, const uint8_t* notch_mask, void* d
   h->st = (hipStream_t)hip_stream;
   layout(p, h, d_workspace);
   h->mat = make_mat(p);
-  h->load2d.kind = p->load_kind == FRACTURE_LOAD_SURFING_2D ? BC_SURFING_2D : BC_TENSION_2D;
+  h->load2d.kind = bc_kind2d(p->load_kind);
   h->load2d.ki2mu = p->surf_ki / (2.0 * h->mat.mu);
   h->load2d.kappa = (3.0 - p->nu) / (1.0 + p->nu);
   h->load2d.lc = p->surf_lc;
@@ -1436,7 +1452,7 @@ int fracture_energy(fracture_t h, double* elastic, double* surface) {
     launch_energy3d(h->st, h->lv[0].g, h->mat, h->p.k_ell, h->gc_cw, h->p.ell,
                     h->p.model == FRACTURE_AT2, h->w2, h->alpha, red(h, 10, S_EL), red(h, 11, S_SURF));
   } else {
-    launch_energy2d(h->st, h->lv[0].g, h->mat, h->p.k_ell, h->gc_cw, h->p.ell,
+    launch_energy2d(h->st, load_grid(h), h->mat, h->p.k_ell, h->gc_cw, h->p.ell,
                     h->p.model == FRACTURE_AT2, h->u, h->alpha, red(h, 10, S_EL), red(h, 11, S_SURF));
   }
   int rc = read_scalars(h);
@@ -1495,13 +1511,14 @@ int fracture_apply(fracture_t h, int op, int level, const double* d_x, double* d
     case FRACTURE_OP_COUPLING_T: {
       if (h->dim != 2) return FRACTURE_EINVAL;
       // the full coupling block (no active set): mask cleared
-      launch_w2_2d(h->st, g, h->mat, h->u, h->w2);
+      const Grid gl = load_grid(h);
+      launch_w2_2d(h->st, gl, h->mat, h->u, h->w2);
       HIPCHK(hipMemsetAsync(h->mask, 0, h->N, h->st));
       if (op == FRACTURE_OP_COUPLING)
-        launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask,
+        launch_jac2d(h->st, gl, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask,
                      nullptr, d_x, d_y, nullptr, false, none, none, nullptr);
       else
-        launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask,
+        launch_jac2d(h->st, gl, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask,
                      d_x, nullptr, nullptr, d_y, false, none, none, nullptr);
     } break;
     case FRACTURE_OP_PRECOND: {

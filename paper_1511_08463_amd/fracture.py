@@ -27,6 +27,7 @@ FRACTURE_AT2 = 2
 FRACTURE_LOAD_TENSION_2D = 0
 FRACTURE_LOAD_THERMAL_3D = 1
 FRACTURE_LOAD_SURFING_2D = 2
+FRACTURE_LOAD_THERMAL_SHOCK_2D = 3
 FRACTURE_RELAX_PROJECT = 0
 FRACTURE_RELAX_RATIO = 1
 FRACTURE_RELAX_BISECT = 2
@@ -71,6 +72,7 @@ class fracture_params(ctypes.Structure):
         ("newton_precond", ctypes.c_int), ("newton_forcing_mode", ctypes.c_int),
         ("pcg_reduction", ctypes.c_double), ("newton_stall", ctypes.c_double),
         ("omega_auto", ctypes.c_int),
+        ("thermal_dT", ctypes.c_double),
     ]
 
 

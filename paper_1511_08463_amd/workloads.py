@@ -177,3 +177,29 @@ def config3(n=128, nz=32, steps=15, dt_max_factor=16.0):
 def oracle_kwargs3(p):
     return dict(E=p["E"], nu=p["nu"], Gc=p["Gc"], ell=p["ell"], k_ell=p["k_ell"],
                 model=p["model"], depth=p["thermal_depth"])
+
+
+def tshock_dtc(E=1.0, nu=0.3, Gc=1.0, ell=1.0, plane_stress=0):
+    """Critical shock of the 2D slab (AT1, beta = 1): the cooled surface layer
+    at zero lateral strain and zero normal stress stores E' (beta T)^2,
+    E' = E/(1 - nu^2) in plane strain or E in plane stress, and damage
+    starts where that reaches Gc/(c_w ell) with c_w = 8/3 (Sec. 4.3)."""
+    Ep = E if plane_stress else E / (1.0 - nu * nu)
+    return float(np.sqrt(3.0 * Gc / (8.0 * ell * Ep)))
+
+
+def tshock(nx, ny, lx=40.0, ly=10.0, ratio=2.0, ell=1.0, model="AT1", **extra):
+    """The 2D thermal shock of Sec. 4.3 on [0, lx] x [0, ly] (the paper's
+    slab is 40 x 10 with ell = 1): shock intensity ratio * DT_c; the load
+    of each step is the dimensionless time tau."""
+    p = dict(dim=2, nx=nx, ny=ny, lx=lx, ly=ly, model=model, E=1.0, nu=0.3, Gc=1.0, ell=ell,
+             k_ell=1e-6, plane_stress=0, load_kind=3)
+    p.update(extra)
+    p["thermal_dT"] = ratio * tshock_dtc(p["E"], p["nu"], p["Gc"], p["ell"], p["plane_stress"])
+    return p
+
+
+def oracle_kwargs_tshock(p):
+    return dict(lx=p["lx"], ly=p["ly"], dT=p["thermal_dT"], E=p["E"], nu=p["nu"], Gc=p["Gc"],
+                ell=p["ell"], k_ell=p["k_ell"], model=p["model"],
+                plane_stress=bool(p["plane_stress"]))
