@@ -311,6 +311,7 @@ def main():
     ap.add_argument("--no-surfing", action="store_true", help="skip the surfing sample")
     ap.add_argument("--tshock", action="store_true",
                     help="run only the 2D thermal shock omega sweep (Sec. 4.3, Table 3)")
+    ap.add_argument("--no-tshock", action="store_true", help="skip the thermal shock sample")
     ap.add_argument("--tshock-n", type=int, default=256, help="thermal shock cells along the slab")
     ap.add_argument("--tshock-tau", type=float, default=2.0, help="last tau of the thermal shock")
     ap.add_argument("--tshock-max-am", type=int, default=20000, help="sweep limit per thermal shock step")
@@ -553,6 +554,10 @@ def main():
         sargs.omega_auto = True
         sargs.forcing_mode = 0
         out["surfing"] = surfing(sargs)
+    if not args.no_tshock:
+        # the third workload: the 2D thermal shock at DT = 4 DT_c, plain ORAM at
+        # omega = 1 and at the paper's best over-relaxation 1.6
+        out["tshock"] = tshock(args, ratios=(4.0,), omegas=(1.0, 1.6))
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(256, args.n, args.model)
