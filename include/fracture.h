@@ -120,6 +120,10 @@ typedef struct {
                                drives the box residual to vi_tol)             */
   double minres_rtol;       /* Newton MINRES relative tolerance                */
   int max_am, max_pcg, max_vi, max_vi_cg, max_newton, max_minres;
+                            /* iteration limits (defaults 2000 sweeps, 1000
+                               PCG, 200 active-set and 2000 CG iterations per
+                               damage solve, 10 Newton, 500 MINRES); reaching
+                               one is FRACTURE_ENOTCONV                       */
   int cheb_degree;          /* Chebyshev smoothing steps per V-cycle side      */
   int coarse_max_dofs;      /* coarsen until the level has at most this many   */
   int newton_vcycles;       /* multigrid V-cycles per action of A^{-1} inside

@@ -425,8 +425,10 @@ __device__ __forceinline__ void tri_nodes(int t, int di[3], int dj[3]) {
 }
 
 // (H a)_v, g_v and H_vv at node (i,j) for the damage field a; when TRIAL the
-// field is clip(a + mu*d, lo, 1) evaluated on the fly.
-template <bool TRIAL, bool MASKIN = false>
+// field is clip(a + mu*d, lo, 1) evaluated on the fly; MASKIN reads it as
+// zero on active nodes, and with XPBY as a + mu*d (a CG direction update)
+// there.
+template <bool TRIAL, bool MASKIN = false, bool XPBY = false>
 __device__ __forceinline__ void helm_node2d(const Grid& g, const Helm& hp,
                                             const double* __restrict__ w2,
                                             const double* __restrict__ a,
@@ -439,6 +441,7 @@ __device__ __forceinline__ void helm_node2d(const Grid& g, const Helm& hp,
   Ha = 0.0; gv = 0.0; Hd = 0.0;
   auto val = [&](int n) -> double {
     if (TRIAL) return fmin(fmax(a[n] + mu * d[n], lo[n]), 1.0);
+    if (MASKIN && XPBY) return mask[n] ? 0.0 : a[n] + mu * d[n];
     if (MASKIN) return mask[n] ? 0.0 : a[n];
     return a[n];
   };
@@ -580,6 +583,58 @@ void launch_helm_apply2d(hipStream_t st, const Grid& g, double cL, double cM, co
   }
 #undef HELM_CASE
   if (dot) launch_finish(st, r, (int)(gr.x * gr.y), false);
+}
+
+// One direction step of the Jacobi-preconditioned CG on H_NN over rows
+// j0..j1: p_new = z + beta p_old (beta = S[S_BETA]; FIRST: p_new = z), formed
+// on the fly wherever the stencil reads it, q = H_NN p_new, and the partial
+// sums of p_new.q.  p_old and p_new are distinct buffers.
+template <bool FIRST>
+__global__ __launch_bounds__(NB) void k_helm_cg2d(Grid g, Helm hp, const double* __restrict__ w2,
+                                                  const double* __restrict__ z,
+                                                  const double* __restrict__ p_old,
+                                                  const uint8_t* __restrict__ mask,
+                                                  double* __restrict__ p_new,
+                                                  double* __restrict__ q, int j0, int j1,
+                                                  const double* __restrict__ S, Red r) {
+  const int i = blockIdx.x * NB_X + threadIdx.x;
+  const int j = j0 + blockIdx.y * NB_Y + threadIdx.y;
+  const double beta = FIRST ? 0.0 : S[S_BETA];
+  double acc = 0.0;
+  if (i <= g.nx && j <= j1) {
+    const int n = i + (g.nx + 1) * j;
+    double Hx, gv, Hd;
+    // active nodes read as zero, so rows outside j0..j1 (all active) never enter
+    if (FIRST)
+      helm_node2d<false, true>(g, hp, w2, z, nullptr, nullptr, 0.0, i, j, Hx, gv, Hd, mask);
+    else
+      helm_node2d<false, true, true>(g, hp, w2, z, p_old, nullptr, beta, i, j, Hx, gv, Hd, mask);
+    const bool act = mask[n] != 0;
+    const double pn = act ? 0.0 : (FIRST ? z[n] : z[n] + beta * p_old[n]);
+    if (act) Hx = 0.0;
+    p_new[n] = pn;
+    q[n] = Hx;
+    acc = pn * Hx;
+  }
+  block_reduce<NB, false>(acc, r, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
+                          threadIdx.x + NB_X * threadIdx.y);
+}
+
+void launch_helm_cg2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                      const double* z, const double* p_old, const uint8_t* mask, double* p_new,
+                      double* q, int j0, int j1, const double* S, bool first, Red r) {
+  Helm hp{cL, cM, 0.0};
+  if (j0 < 0) j0 = 0;
+  if (j1 < 0 || j1 > g.ny) j1 = g.ny;
+  if (j1 < j0) return;
+  dim3 gr((g.nx + 1 + NB_X - 1) / NB_X, (j1 - j0 + 1 + NB_Y - 1) / NB_Y), bl(NB_X, NB_Y);
+  if (first)
+    hipLaunchKernelGGL((k_helm_cg2d<true>), gr, bl, 0, st, g, hp, w2, z, p_old, mask, p_new, q, j0,
+                       j1, S, r);
+  else
+    hipLaunchKernelGGL((k_helm_cg2d<false>), gr, bl, 0, st, g, hp, w2, z, p_old, mask, p_new, q, j0,
+                       j1, S, r);
+  launch_finish(st, r, (int)(gr.x * gr.y), false);
 }
 
 // ---------------------------------------------------------------------------

@@ -119,6 +119,12 @@ void launch_finish(hipStream_t st, const Red& r, int nblocks, bool is_max);
 void launch_cg_update(hipStream_t st, int64_t n, double* x, double* r, const double* p,
                       const double* q, const double* S, Red rr);
 void launch_xpby(hipStream_t st, int64_t n, const double* z, double* p, const double* S);
+void launch_cg_update_jac(hipStream_t st, int64_t n, double* x, double* r, const double* p,
+                          const double* q, const double* dinv, double* z, const double* S, Red rr,
+                          Red rz);
+void launch_helm_cg2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                      const double* z, const double* p_old, const uint8_t* mask, double* p_new,
+                      double* q, int j0, int j1, const double* S, bool first, Red r);
 void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, Red r);
 void launch_jacobi_dot(hipStream_t st, int64_t n, const double* r, const double* dinv, double* z,
                        Red red);

@@ -782,16 +782,39 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
     double *vr = h->vr + off, *vz = h->vz + off, *vp = h->vp + off, *vq = h->vq + off,
            *vd = h->vd + off;
     const double* hd = h->hdinv + off;
+    // 2D: the direction update rides in the Hessian apply (p ping-pongs
+    // between vp and vt1) and the preconditioner in the CG update, so an
+    // iteration is two kernels and two finishing launches
+    const bool fused = h->dim == 2;
     if (any_inactive) {
       launch_norm2(st, cnt, vr, red(h, 7, S_TMP2));
       launch_jacobi_dot(st, cnt, vr, hd, vz, red(h, 1, S_RZ));
-      HIPCHK(hipMemcpyAsync(vp, vz, cnt * sizeof(double), hipMemcpyDeviceToDevice, st));
+      if (!fused)
+        HIPCHK(hipMemcpyAsync(vp, vz, cnt * sizeof(double), hipMemcpyDeviceToDevice, st));
       rc = read_scalars(h);
       if (rc) return rc;
     }
     const double r0 = any_inactive ? std::sqrt(h->hS[S_TMP2]) : 0.0;
     const double tol = h->p.vi_cg_rtol * r0;
-    if (r0 > 0) {
+    if (r0 > 0 && fused) {
+      double* pb[2] = {h->vp, h->vt1};
+      for (int k = 1; k <= h->p.max_vi_cg; ++k) {
+        double* pn = pb[k & 1];
+        launch_helm_cg2d(st, g, h->cL, h->cM, h->w2, h->vz, pb[(k + 1) & 1], h->mask, pn, h->vq,
+                         j0, j1, h->S, k == 1, red(h, 2, S_PQ, P_CG_ALPHA));
+        launch_cg_update_jac(st, cnt, vd, vr, pn + off, vq, hd, vz, h->S, red(h, 3, S_RR),
+                             red(h, 4, S_RZNEW, P_CG_BETA));
+        ++*cg_iters;
+        lag_post(h, S_RR, 1, k);
+        if (k > 1) {
+          double rr = 0;
+          rc = lag_get(h, k - 1, 1, &rr);
+          if (rc) return rc;
+          if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
+          if (std::sqrt(rr) <= tol) break;
+        }
+      }
+    } else if (r0 > 0) {
       // CG scalars live on the device; the host tests ||r|| one iteration
       // late (lag_post / lag_get)
       for (int k = 1; k <= h->p.max_vi_cg; ++k) {
@@ -1280,7 +1303,7 @@ void fracture_default_params(fracture_params* p, int nx, int ny) {
   p->minres_rtol = 1e-6;
   p->max_am = 2000;
   p->max_pcg = 1000;
-  p->max_vi = 50;
+  p->max_vi = 200;
   p->max_vi_cg = 2000;
   p->max_newton = 10;
   p->max_minres = 500;

@@ -36,6 +36,23 @@ __global__ __launch_bounds__(FB) void k_finish(Red r, int nblocks) {
   }
 }
 
+// Two independent sums finished at once, one block each.
+__global__ __launch_bounds__(FB) void k_finish2(Red r0, Red r1, int nblocks) {
+  __shared__ double sh[FB / WAVE];
+  const Red& r = blockIdx.x == 0 ? r0 : r1;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nblocks; k += FB) acc += r.part[k];
+  acc = wave_sum(acc);
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  if (lane == 0) sh[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = sh[0];
+    for (int k = 1; k < FB / WAVE; ++k) s += sh[k];
+    post_scalar(s, r);
+  }
+}
+
 void launch_finish(hipStream_t st, const Red& r, int nblocks, bool is_max) {
   if (is_max)
     hipLaunchKernelGGL((k_finish<true>), dim3(1), dim3(FB), 0, st, r, nblocks);
@@ -66,6 +83,40 @@ void launch_cg_update(hipStream_t st, int64_t n, double* x, double* r, const dou
                       const double* q, const double* S, Red rr) {
   hipLaunchKernelGGL(k_cg_update, dim3(vgrid(n)), dim3(VB), 0, st, n, x, r, p, q, S, rr);
   launch_finish(st, rr, vgrid(n), false);
+}
+
+// x += a p; r -= a q; z = dinv .* r; S[rr.slot] = r.r, S[rz.slot] = r.z
+// (a = S[S_ALPHA]; both sums finished by one launch).  The two reductions
+// must not touch each other's scalars: rz's post-operation reads S_RZ only.
+__global__ __launch_bounds__(VB) void k_cg_update_jac(int64_t n, double* __restrict__ x,
+                                                      double* __restrict__ r,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ q,
+                                                      const double* __restrict__ dinv,
+                                                      double* __restrict__ z,
+                                                      const double* __restrict__ S, Red rr,
+                                                      Red rz) {
+  const double a = S[S_ALPHA];
+  double arr = 0.0, arz = 0.0;
+  GRID_STRIDE(k, n) {
+    x[k] += a * p[k];
+    const double rv = r[k] - a * q[k];
+    r[k] = rv;
+    const double zv = dinv[k] * rv;
+    z[k] = zv;
+    arr += rv * rv;
+    arz += rv * zv;
+  }
+  block_reduce<VB, false>(arr, rr, gridDim.x, blockIdx.x, threadIdx.x);
+  block_reduce<VB, false>(arz, rz, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_cg_update_jac(hipStream_t st, int64_t n, double* x, double* r, const double* p,
+                          const double* q, const double* dinv, double* z, const double* S, Red rr,
+                          Red rz) {
+  hipLaunchKernelGGL(k_cg_update_jac, dim3(vgrid(n)), dim3(VB), 0, st, n, x, r, p, q, dinv, z, S,
+                     rr, rz);
+  hipLaunchKernelGGL(k_finish2, dim3(2), dim3(FB), 0, st, rr, rz, vgrid(n));
 }
 
 // p = z + beta p   (beta = S[S_BETA])

@@ -70,7 +70,8 @@ def test_tshock_operators_match_oracle(model, ps):
     s.close()
 
 
-@pytest.mark.parametrize("newton,omega,precision", [(1, 1.0, 0), (0, 1.4, 0), (1, 1.0, 1)])
+@pytest.mark.parametrize("newton,omega,precision",
+                         [(1, 1.0, 0), (0, 1.4, 0), (0, 0.8, 0), (1, 1.0, 1)])
 def test_tshock_load_path_parity(newton, omega, precision):
     """64 x 16 cells on 16 x 4 (h = ell/4), DT = 2 DT_c, tau = 0.2 .. 2.0:
     the damage band, its bifurcation (tau ~ 1.6) and the cracks through the
