@@ -99,7 +99,8 @@ def thermal(args):
         stats.append(st)
         el, su = solver.energy()
         log(f"[thermal] step {k + 1} DT={t:.3f} sweeps={st['sweeps']} pcg={st['pcg_iters']} "
-            f"vi={st['vi_iters']} ms={st['ms_total']:.1f} E_el={el:.4e} E_s={su:.4e}")
+            f"vi={st['vi_iters']} vi_cg={st['vi_cg_iters']} ms={st['ms_total']:.1f} "
+            f"(pcg {st['ms_pcg']:.1f}, vi {st['ms_vi']:.1f}) E_el={el:.4e} E_s={su:.4e}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rl = {}

@@ -623,6 +623,8 @@ __global__ __launch_bounds__(NB) void k_helm_cg2d(Grid g, Helm hp, const double*
 void launch_helm_cg2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
                       const double* z, const double* p_old, const uint8_t* mask, double* p_new,
                       double* q, int j0, int j1, const double* S, bool first, Red r) {
+  if (g.dim == 3)
+    return launch_helm_cg3d(st, g, cL, cM, w2, z, p_old, mask, p_new, q, j0, j1, S, first, r);
   Helm hp{cL, cM, 0.0};
   if (j0 < 0) j0 = 0;
   if (j1 < 0 || j1 > g.ny) j1 = g.ny;

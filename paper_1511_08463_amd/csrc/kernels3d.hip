@@ -302,7 +302,39 @@ __device__ __forceinline__ void kuhn_grad(int p, int v, const double ih[3], doub
   }
 }
 
-template <bool TRIAL, bool MASKIN>
+// One tetrahedron's part of (H a)_v, g_v and H_vv for node v = (i, j, k): hex
+// offset (HX, HY, HZ), tetrahedron P, the node as local vertex V (all known
+// at compile time); av holds the field on the node's 15-point stencil.
+template <int HX, int HY, int HZ, int P, int V>
+__device__ __forceinline__ void tet_helm(const Grid& g, const Helm3& hp,
+                                         const double* __restrict__ w2, const double (&av)[27],
+                                         int i, int j, int k, const double ih[3], double vol,
+                                         double& Ha, double& gv, double& Hd) {
+  const int ci = i + HX, cj = j + HY, ck = k + HZ;
+  if (ci < 0 || cj < 0 || ck < 0 || ci >= g.nx || cj >= g.ny || ck >= g.nz) return;
+  constexpr int A = Perm3<P>::a, B = Perm3<P>::b, C = Perm3<P>::c;
+  const double a0 = av[VSlot<HX, HY, HZ, P, 0>::v], a1 = av[VSlot<HX, HY, HZ, P, 1>::v];
+  const double a2 = av[VSlot<HX, HY, HZ, P, 2>::v], a3 = av[VSlot<HX, HY, HZ, P, 3>::v];
+  // gradient of the P1 field: differences along the path o0 -> o1 -> o2 -> o3
+  double grad[3];
+  grad[A] = (a1 - a0) * ih[A];
+  grad[B] = (a2 - a1) * ih[B];
+  grad[C] = (a3 - a2) * ih[C];
+  double gvv[3];
+  grad3<P, V>(ih, gvv);
+  const double we = w2[6 * (ci + g.nx * (cj + g.ny * ck)) + P];
+  const double aV = V == 0 ? a0 : (V == 1 ? a1 : (V == 2 ? a2 : a3));
+  const double mass = vol / 20.0 * (aV + a0 + a1 + a2 + a3);   // (M_e a)_v
+  const double lap = vol * (gvv[0] * grad[0] + gvv[1] * grad[1] + gvv[2] * grad[2]);
+  Ha += (we + hp.cM) * mass + hp.cL * lap;
+  gv += (we - hp.cm) * vol / 4.0;
+  Hd += (we + hp.cM) * vol / 10.0 + hp.cL * vol * (gvv[0] * gvv[0] + gvv[1] * gvv[1] + gvv[2] * gvv[2]);
+}
+
+// (H a)_v, g_v and H_vv at node (i,j,k) over its 24 tetrahedra, enumerated
+// at compile time; when TRIAL the field is clip(a + mu*d, lo, 1), with MASKIN
+// it is read as zero on active nodes, and with XPBY as a + mu*d there.
+template <bool TRIAL, bool MASKIN, bool XPBY = false>
 __device__ __forceinline__ void helm_node3d(const Grid& g, const Helm3& hp,
                                             const double* __restrict__ w2,
                                             const double* __restrict__ a,
@@ -311,36 +343,27 @@ __device__ __forceinline__ void helm_node3d(const Grid& g, const Helm3& hp,
                                             const uint8_t* __restrict__ mask, int i, int j, int k,
                                             double& Ha, double& gv, double& Hd) {
   const int W = g.nx + 1, H = g.ny + 1;
+  const int n = i + W * (j + H * k);
   const double ih[3] = {1.0 / g.hx, 1.0 / g.hy, 1.0 / g.hz};
   const double vol = g.hx * g.hy * g.hz / 6.0;
   Ha = gv = Hd = 0.0;
-  auto val = [&](int n) -> double {
-    if (TRIAL) return fmin(fmax(a[n] + mu * d[n], lo[n]), 1.0);
-    if (MASKIN) return mask[n] ? 0.0 : a[n];
-    return a[n];
+  auto val = [&](int q) -> double {
+    if (TRIAL) return fmin(fmax(a[q] + mu * d[q], lo[q]), 1.0);
+    if (MASKIN && XPBY) return mask[q] ? 0.0 : a[q] + mu * d[q];
+    if (MASKIN) return mask[q] ? 0.0 : a[q];
+    return a[q];
   };
-  for (int t = 0; t < 24; ++t) {
-    const int ci = i + c_tets3[t][0], cj = j + c_tets3[t][1], ck = k + c_tets3[t][2];
-    if (ci < 0 || cj < 0 || ck < 0 || ci >= g.nx || cj >= g.ny || ck >= g.nz) continue;
-    const int p = c_tets3[t][3], v = c_tets3[t][4];
-    double av[4], grad[3] = {0, 0, 0}, gvv[3];
-    double sum = 0;
-    for (int q = 0; q < 4; ++q) {
-      const int nn = (ci + c_kuhn_off[p][q][0]) + W * ((cj + c_kuhn_off[p][q][1]) + H * (ck + c_kuhn_off[p][q][2]));
-      av[q] = val(nn);
-      sum += av[q];
-      double gq[3];
-      kuhn_grad(p, q, ih, gq);
-      for (int c = 0; c < 3; ++c) grad[c] += av[q] * gq[c];
-    }
-    kuhn_grad(p, v, ih, gvv);
-    const double we = w2[6 * (ci + g.nx * (cj + g.ny * ck)) + p];
-    const double mass = vol / 20.0 * (av[v] + sum);
-    const double lap = vol * (gvv[0] * grad[0] + gvv[1] * grad[1] + gvv[2] * grad[2]);
-    Ha += (we + hp.cM) * mass + hp.cL * lap;
-    gv += (we - hp.cm) * vol / 4.0;
-    Hd += (we + hp.cM) * vol / 10.0 + hp.cL * vol * (gvv[0] * gvv[0] + gvv[1] * gvv[1] + gvv[2] * gvv[2]);
+  double av[27];
+#define LOADH3(DX, DY, DZ)                                                     \
+  {                                                                            \
+    constexpr int sl = nslot(DX, DY, DZ);                                      \
+    av[sl] = in3(g, i + DX, j + DY, k + DZ) ? val(n + DX + W * (DY + H * DZ)) : 0.0; \
   }
+  FOR_STENCIL3(LOADH3)
+#undef LOADH3
+#define HELM3(HX, HY, HZ, P, V) tet_helm<HX, HY, HZ, P, V>(g, hp, w2, av, i, j, k, ih, vol, Ha, gv, Hd);
+  FOR_TETS3(HELM3)
+#undef HELM3
 }
 
 template <bool TRIAL>
@@ -446,6 +469,57 @@ void launch_helm_apply3d(hipStream_t st, const Grid& g, double cL, double cM, co
   else { if (dot) H3(false, true); else H3(false, false); }
 #undef H3
   if (dot) launch_finish(st, r, (int)(gr.x * gr.y * gr.z), false);
+}
+
+// The 3D form of k_helm_cg2d: p_new = z + beta p_old formed on the fly
+// (FIRST: p_new = z), q = H_NN p_new and the partial sums of p_new.q, on
+// rows (j, k) whose row index lies in [r0, r1].
+template <bool FIRST>
+__global__ __launch_bounds__(NB) void k_helm_cg3d(Grid g, Helm3 hp, const double* __restrict__ w2,
+                                                  const double* __restrict__ z,
+                                                  const double* __restrict__ p_old,
+                                                  const uint8_t* __restrict__ mask,
+                                                  double* __restrict__ p_new,
+                                                  double* __restrict__ q, int r0, int r1,
+                                                  const double* __restrict__ S, Red r) {
+  const int i = blockIdx.x * NB_X + threadIdx.x, j = blockIdx.y * NB_Y + threadIdx.y, k = blockIdx.z;
+  const double beta = FIRST ? 0.0 : S[S_BETA];
+  double acc = 0.0;
+  const int row = j + (g.ny + 1) * k;
+  if (i <= g.nx && j <= g.ny && row >= r0 && row <= r1) {
+    const int n = i + (g.nx + 1) * row;
+    double Hx, gv, Hd;
+    if (FIRST)
+      helm_node3d<false, true>(g, hp, w2, z, nullptr, nullptr, 0.0, mask, i, j, k, Hx, gv, Hd);
+    else
+      helm_node3d<false, true, true>(g, hp, w2, z, p_old, nullptr, beta, mask, i, j, k, Hx, gv, Hd);
+    const bool act = mask[n] != 0;
+    const double pn = act ? 0.0 : (FIRST ? z[n] : z[n] + beta * p_old[n]);
+    if (act) Hx = 0.0;
+    p_new[n] = pn;
+    q[n] = Hx;
+    acc = pn * Hx;
+  }
+  block_reduce<NB, false>(acc, r, gridDim.x * gridDim.y * gridDim.z,
+                          blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                          threadIdx.x + NB_X * threadIdx.y);
+}
+
+void launch_helm_cg3d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                      const double* z, const double* p_old, const uint8_t* mask, double* p_new,
+                      double* q, int r0, int r1, const double* S, bool first, Red r) {
+  Helm3 hp{cL, cM, 0.0};
+  const int rows = (g.ny + 1) * (g.nz + 1);
+  if (r0 < 0) r0 = 0;
+  if (r1 < 0 || r1 >= rows) r1 = rows - 1;
+  dim3 gr = node_grid3(g), bl(NB_X, NB_Y);
+  if (first)
+    hipLaunchKernelGGL((k_helm_cg3d<true>), gr, bl, 0, st, g, hp, w2, z, p_old, mask, p_new, q, r0,
+                       r1, S, r);
+  else
+    hipLaunchKernelGGL((k_helm_cg3d<false>), gr, bl, 0, st, g, hp, w2, z, p_old, mask, p_new, q, r0,
+                       r1, S, r);
+  launch_finish(st, r, (int)(gr.x * gr.y * gr.z), false);
 }
 
 __global__ __launch_bounds__(VB) void k_energy3d(Grid g, Mat m, double kell, double gc_cw, double ell,

@@ -122,6 +122,9 @@ void launch_xpby(hipStream_t st, int64_t n, const double* z, double* p, const do
 void launch_cg_update_jac(hipStream_t st, int64_t n, double* x, double* r, const double* p,
                           const double* q, const double* dinv, double* z, const double* S, Red rr,
                           Red rz);
+void launch_helm_cg3d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                      const double* z, const double* p_old, const uint8_t* mask, double* p_new,
+                      double* q, int r0, int r1, const double* S, bool first, Red r);
 void launch_helm_cg2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
                       const double* z, const double* p_old, const uint8_t* mask, double* p_new,
                       double* q, int j0, int j1, const double* S, bool first, Red r);

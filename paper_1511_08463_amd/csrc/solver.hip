@@ -779,24 +779,21 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
     const int j0 = any_inactive ? (int)jlo : 0, j1 = any_inactive ? (int)jhi : -1;
     const int64_t W = g.nx + 1, off = (int64_t)j0 * W;
     const int64_t cnt = any_inactive ? (int64_t)(j1 - j0 + 1) * W : 0;
-    double *vr = h->vr + off, *vz = h->vz + off, *vp = h->vp + off, *vq = h->vq + off,
-           *vd = h->vd + off;
+    double *vr = h->vr + off, *vz = h->vz + off, *vq = h->vq + off, *vd = h->vd + off;
     const double* hd = h->hdinv + off;
-    // 2D: the direction update rides in the Hessian apply (p ping-pongs
-    // between vp and vt1) and the preconditioner in the CG update, so an
-    // iteration is two kernels and two finishing launches
-    const bool fused = h->dim == 2;
+    // the direction update rides in the Hessian apply (p ping-pongs between
+    // vp and vt1) and the preconditioner in the CG update, so an iteration
+    // is two kernels and two finishing launches; the CG scalars live on the
+    // device and the host tests ||r|| one iteration late (lag_post / lag_get)
     if (any_inactive) {
       launch_norm2(st, cnt, vr, red(h, 7, S_TMP2));
       launch_jacobi_dot(st, cnt, vr, hd, vz, red(h, 1, S_RZ));
-      if (!fused)
-        HIPCHK(hipMemcpyAsync(vp, vz, cnt * sizeof(double), hipMemcpyDeviceToDevice, st));
       rc = read_scalars(h);
       if (rc) return rc;
     }
     const double r0 = any_inactive ? std::sqrt(h->hS[S_TMP2]) : 0.0;
     const double tol = h->p.vi_cg_rtol * r0;
-    if (r0 > 0 && fused) {
+    if (r0 > 0) {
       double* pb[2] = {h->vp, h->vt1};
       for (int k = 1; k <= h->p.max_vi_cg; ++k) {
         double* pn = pb[k & 1];
@@ -813,25 +810,6 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
           if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
           if (std::sqrt(rr) <= tol) break;
         }
-      }
-    } else if (r0 > 0) {
-      // CG scalars live on the device; the host tests ||r|| one iteration
-      // late (lag_post / lag_get)
-      for (int k = 1; k <= h->p.max_vi_cg; ++k) {
-        launch_helm_apply2d(st, g, h->cL, h->cM, h->w2, h->vp, h->mask, h->vq, true,
-                            red(h, 2, S_PQ, P_CG_ALPHA), j0, j1);
-        launch_cg_update(st, cnt, vd, vr, vp, vq, h->S, red(h, 3, S_RR));
-        ++*cg_iters;
-        lag_post(h, S_RR, 1, k);
-        if (k > 1) {
-          double rr = 0;
-          rc = lag_get(h, k - 1, 1, &rr);
-          if (rc) return rc;
-          if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
-          if (std::sqrt(rr) <= tol) break;
-        }
-        launch_jacobi_dot(st, cnt, vr, hd, vz, red(h, 4, S_RZNEW, P_CG_BETA));
-        launch_xpby(st, cnt, vz, vp, h->S);
       }
       // an inexact step is still tried: the line search decides
     }
