@@ -131,6 +131,14 @@ __device__ __forceinline__ void post_scalar(double s, const Red& r) {
   }
 }
 
+// Independent reductions of one launch, finished together (launch_finish_multi):
+// their post-operations must not read each other's results.
+struct FinishSet {
+  Red r[4];
+  int maxmask;   // bit q set: r[q] is a max
+  int count;     // 1..4
+};
+
 // Block-wide deterministic sum (MAX = false) or max (MAX = true) of v, stored
 // as the block's partial r.part[bid].  A finishing kernel (launch_finish)
 // then reduces the partials in a fixed order.  Every thread of the block must

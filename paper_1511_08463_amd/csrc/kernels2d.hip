@@ -531,12 +531,9 @@ void launch_vi_eval2d(hipStream_t st, const Grid& g, double cL, double cM, doubl
   else
     hipLaunchKernelGGL((k_vi_eval2d<false>), gr, bl, 0, st, g, hp, w2, a, d, lo, S, mu_slot, zeta,
                        F, phi, mask, hdinv, r2, rm, rlo, rhi);
-  launch_finish(st, r2, (int)(gr.x * gr.y), false);
-  launch_finish(st, rm, (int)(gr.x * gr.y), true);
-  if (!trial) {
-    launch_finish(st, rlo, (int)(gr.x * gr.y), true);
-    launch_finish(st, rhi, (int)(gr.x * gr.y), true);
-  }
+  // the four (trial: two) reductions are finished by one launch
+  const FinishSet fs{{r2, rm, rlo, rhi}, 0b1110, trial ? 2 : 4};
+  launch_finish_multi(st, fs, (int)(gr.x * gr.y));
 }
 
 // y = H x (MASKED: rows and columns of active nodes removed, i.e. x is taken
@@ -690,8 +687,8 @@ void launch_energy2d(hipStream_t st, const Grid& g, const Mat& m, double kell, d
   int nb = (ncell + VB - 1) / VB;
   if (nb > VGRID) nb = VGRID;
   hipLaunchKernelGGL(k_energy2d, dim3(nb), dim3(VB), 0, st, g, m, kell, gc_cw, ell, at2, u, a, rel, rsu);
-  launch_finish(st, rel, nb, false);
-  launch_finish(st, rsu, nb, false);
+  const FinishSet fs{{rel, rsu, Red{}, Red{}}, 0, 2};
+  launch_finish_multi(st, fs, nb);
 }
 
 }  // namespace frac

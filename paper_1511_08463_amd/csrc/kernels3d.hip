@@ -424,13 +424,8 @@ void launch_vi_eval3d(hipStream_t st, const Grid& g, double cL, double cM, doubl
   else
     hipLaunchKernelGGL((k_vi_eval3d<false>), gr, bl, 0, st, g, hp, w2, a, d, lo, S, mu_slot, zeta,
                        F, phi, mask, hdinv, r2, rm, rlo, rhi);
-  const int nb = (int)(gr.x * gr.y * gr.z);
-  launch_finish(st, r2, nb, false);
-  launch_finish(st, rm, nb, true);
-  if (!trial) {
-    launch_finish(st, rlo, nb, true);
-    launch_finish(st, rhi, nb, true);
-  }
+  const FinishSet fs{{r2, rm, rlo, rhi}, 0b1110, trial ? 2 : 4};
+  launch_finish_multi(st, fs, (int)(gr.x * gr.y * gr.z));
 }
 
 // y = H x on rows (j, k) whose row index lies in [r0, r1] (MASKED: reduced).
@@ -556,8 +551,8 @@ void launch_energy3d(hipStream_t st, const Grid& g, const Mat& m, double kell, d
   int nb = (ne + VB - 1) / VB;
   if (nb > VGRID) nb = VGRID;
   hipLaunchKernelGGL(k_energy3d, dim3(nb), dim3(VB), 0, st, g, m, kell, gc_cw, ell, at2, w2, a, rel, rsu);
-  launch_finish(st, rel, nb, false);
-  launch_finish(st, rsu, nb, false);
+  const FinishSet fs{{rel, rsu, Red{}, Red{}}, 0, 2};
+  launch_finish_multi(st, fs, nb);
 }
 
 // Dense assembly of the coarsest 3D level (one thread per node row).

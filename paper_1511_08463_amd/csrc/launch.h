@@ -116,6 +116,7 @@ void launch_vtail2d(hipStream_t st, const TailArgs<T>& a);
 // ---- vector kernels (vec.hip) -----------------------------------------------
 int vec_blocks(int64_t n);
 void launch_finish(hipStream_t st, const Red& r, int nblocks, bool is_max);
+void launch_finish_multi(hipStream_t st, const FinishSet& fs, int nblocks);
 void launch_cg_update(hipStream_t st, int64_t n, double* x, double* r, const double* p,
                       const double* q, const double* S, Red rr);
 void launch_xpby(hipStream_t st, int64_t n, const double* z, double* p, const double* S);

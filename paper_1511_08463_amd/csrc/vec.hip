@@ -53,6 +53,29 @@ __global__ __launch_bounds__(FB) void k_finish2(Red r0, Red r1, int nblocks) {
   }
 }
 
+// Up to four independent reductions of one launch finished at once, one
+// block each (bit q of maxmask: reduction q is a max).
+__global__ __launch_bounds__(FB) void k_finish_multi(FinishSet fs, int nblocks) {
+  __shared__ double sh[FB / WAVE];
+  const Red& r = fs.r[blockIdx.x];
+  const bool mx = (fs.maxmask >> blockIdx.x) & 1;
+  double acc = mx ? -INFINITY : 0.0;
+  for (int k = threadIdx.x; k < nblocks; k += FB) acc = mx ? fmax(acc, r.part[k]) : acc + r.part[k];
+  acc = mx ? wave_max(acc) : wave_sum(acc);
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  if (lane == 0) sh[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = sh[0];
+    for (int k = 1; k < FB / WAVE; ++k) s = mx ? fmax(s, sh[k]) : s + sh[k];
+    post_scalar(s, r);
+  }
+}
+
+void launch_finish_multi(hipStream_t st, const FinishSet& fs, int nblocks) {
+  hipLaunchKernelGGL(k_finish_multi, dim3(fs.count), dim3(FB), 0, st, fs, nblocks);
+}
+
 void launch_finish(hipStream_t st, const Red& r, int nblocks, bool is_max) {
   if (is_max)
     hipLaunchKernelGGL((k_finish<true>), dim3(1), dim3(FB), 0, st, r, nblocks);
