@@ -424,10 +424,52 @@ __device__ __forceinline__ void tri_nodes(int t, int di[3], int dj[3]) {
   else { di[1] = 1; dj[1] = 1; di[2] = 0; dj[2] = 1; }
 }
 
+// Triangle K (0..5) around a node, in the order of c_tri_*: cell offset
+// (di, dj), type t, the node's local vertex v, and the node offset of local
+// vertex Q from the node — all compile-time constants.
+template <int K>
+struct Tri2 {
+  static constexpr int di = (K == 2 || K == 3 || K == 4) ? -1 : 0;
+  static constexpr int dj = K >= 3 ? -1 : 0;
+  static constexpr int t = (K == 1 || K == 4 || K == 5) ? 1 : 0;
+  static constexpr int v = K <= 1 ? 0 : ((K == 2 || K == 4) ? 1 : 2);
+  template <int Q>
+  static constexpr int slot() {   // (dx + 1) + 3 (dy + 1) in the node's 3x3 neighbourhood
+    return (di + (Q == 0 ? 0 : (t == 0 ? 1 : (Q == 1 ? 1 : 0))) + 1) +
+           3 * (dj + (Q == 0 ? 0 : (t == 0 ? (Q == 1 ? 0 : 1) : 1)) + 1);
+  }
+};
+
+// Triangle K's part of (H a)_v, g_v and H_vv; av holds the field on the
+// node's 3x3 neighbourhood.
+template <int K>
+__device__ __forceinline__ void tri_helm2(const Grid& g, const Helm& hp,
+                                          const double* __restrict__ w2, const double (&av)[9],
+                                          int i, int j, double ihx, double ihy, double area,
+                                          double& Ha, double& gv, double& Hd) {
+  using TK = Tri2<K>;
+  const int ci = i + TK::di, cj = j + TK::dj;
+  if (ci < 0 || cj < 0 || ci >= g.nx || cj >= g.ny) return;
+  double gx[3], gy[3];
+  tri_grads(TK::t, ihx, ihy, gx, gy);
+  const double a0 = av[TK::template slot<0>()], a1 = av[TK::template slot<1>()];
+  const double a2 = av[TK::template slot<2>()];
+  const double we = w2[2 * (ci + g.nx * cj) + TK::t];
+  const double sum = a0 + a1 + a2;
+  const double aV = TK::v == 0 ? a0 : (TK::v == 1 ? a1 : a2);
+  const double mass = area / 12.0 * (aV + sum);                 // (M_e a)_v
+  const double grx = a0 * gx[0] + a1 * gx[1] + a2 * gx[2];
+  const double gry = a0 * gy[0] + a1 * gy[1] + a2 * gy[2];
+  const double lap = area * (gx[TK::v] * grx + gy[TK::v] * gry);  // (L_e a)_v
+  Ha += (we + hp.cM) * mass + hp.cL * lap;
+  gv += (we - hp.cm) * area / 3.0;
+  Hd += (we + hp.cM) * area / 6.0 + hp.cL * area * (gx[TK::v] * gx[TK::v] + gy[TK::v] * gy[TK::v]);
+}
+
 // (H a)_v, g_v and H_vv at node (i,j) for the damage field a; when TRIAL the
 // field is clip(a + mu*d, lo, 1) evaluated on the fly; MASKIN reads it as
 // zero on active nodes, and with XPBY as a + mu*d (a CG direction update)
-// there.
+// there.  The field is read once on the node's seven-point neighbourhood.
 template <bool TRIAL, bool MASKIN = false, bool XPBY = false>
 __device__ __forceinline__ void helm_node2d(const Grid& g, const Helm& hp,
                                             const double* __restrict__ w2,
@@ -436,37 +478,28 @@ __device__ __forceinline__ void helm_node2d(const Grid& g, const Helm& hp,
                                             const double* __restrict__ lo, double mu, int i, int j,
                                             double& Ha, double& gv, double& Hd,
                                             const uint8_t* __restrict__ mask = nullptr) {
-  const int W = g.nx + 1;
+  const int W = g.nx + 1, n = i + W * j;
   const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy, area = 0.5 * g.hx * g.hy;
   Ha = 0.0; gv = 0.0; Hd = 0.0;
-  auto val = [&](int n) -> double {
-    if (TRIAL) return fmin(fmax(a[n] + mu * d[n], lo[n]), 1.0);
-    if (MASKIN && XPBY) return mask[n] ? 0.0 : a[n] + mu * d[n];
-    if (MASKIN) return mask[n] ? 0.0 : a[n];
-    return a[n];
+  auto val = [&](int q) -> double {
+    if (TRIAL) return fmin(fmax(a[q] + mu * d[q], lo[q]), 1.0);
+    if (MASKIN && XPBY) return mask[q] ? 0.0 : a[q] + mu * d[q];
+    if (MASKIN) return mask[q] ? 0.0 : a[q];
+    return a[q];
   };
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const int ci = i + c_tri_di[k], cj = j + c_tri_dj[k];
-    if (ci < 0 || cj < 0 || ci >= g.nx || cj >= g.ny) continue;
-    const int t = c_tri_t[k], v = c_tri_v[k];
-    double gx[3], gy[3];
-    int di[3], dj[3];
-    tri_grads(t, ihx, ihy, gx, gy);
-    tri_nodes(t, di, dj);
-    double av[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) av[q] = val(ci + di[q] + W * (cj + dj[q]));
-    const double we = w2[2 * (ci + g.nx * cj) + t];
-    const double sum = av[0] + av[1] + av[2];
-    const double mass = area / 12.0 * (av[v] + sum);          // (M_e a)_v
-    const double grx = av[0] * gx[0] + av[1] * gx[1] + av[2] * gx[2];
-    const double gry = av[0] * gy[0] + av[1] * gy[1] + av[2] * gy[2];
-    const double lap = area * (gx[v] * grx + gy[v] * gry);     // (L_e a)_v
-    Ha += (we + hp.cM) * mass + hp.cL * lap;
-    gv += (we - hp.cm) * area / 3.0;
-    Hd += (we + hp.cM) * area / 6.0 + hp.cL * area * (gx[v] * gx[v] + gy[v] * gy[v]);
-  }
+  double av[9];
+#define LDH2(DX, DY)                                                                          \
+  av[(DX + 1) + 3 * (DY + 1)] =                                                               \
+      (i + DX >= 0 && i + DX <= g.nx && j + DY >= 0 && j + DY <= g.ny) ? val(n + DX + W * DY) \
+                                                                        : 0.0;
+  LDH2(0, 0) LDH2(1, 0) LDH2(1, 1) LDH2(0, 1) LDH2(-1, 0) LDH2(-1, -1) LDH2(0, -1)
+#undef LDH2
+  tri_helm2<0>(g, hp, w2, av, i, j, ihx, ihy, area, Ha, gv, Hd);
+  tri_helm2<1>(g, hp, w2, av, i, j, ihx, ihy, area, Ha, gv, Hd);
+  tri_helm2<2>(g, hp, w2, av, i, j, ihx, ihy, area, Ha, gv, Hd);
+  tri_helm2<3>(g, hp, w2, av, i, j, ihx, ihy, area, Ha, gv, Hd);
+  tri_helm2<4>(g, hp, w2, av, i, j, ihx, ihy, area, Ha, gv, Hd);
+  tri_helm2<5>(g, hp, w2, av, i, j, ihx, ihy, area, Ha, gv, Hd);
 }
 
 // F = H a - g, Phi (box FB with bounds [lo, 1]), active mask (eq. (reducedis)
