@@ -131,6 +131,17 @@ __device__ __forceinline__ void post_scalar(double s, const Red& r) {
   }
 }
 
+// Entries [0, n0) and [b0, b0 + n - n0) of a vector, walked as one index
+// range 0..n-1: the displacement block and the damage rows that can be
+// nonzero (the inactive band) of the coupled Newton vectors.
+struct Seg {
+  int64_t n0, b0, n;
+};
+
+__device__ __forceinline__ int64_t seg_index(const Seg& s, int64_t q) {
+  return q < s.n0 ? q : s.b0 + (q - s.n0);
+}
+
 // Independent reductions of one launch, finished together (launch_finish_multi):
 // their post-operations must not read each other's results.
 struct FinishSet {

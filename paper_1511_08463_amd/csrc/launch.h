@@ -161,10 +161,11 @@ void launch_copy(hipStream_t st, int64_t n, const double* x, double* y);
 void launch_minres_init(hipStream_t st, double* S);
 void launch_minres_a(hipStream_t st, double* S);
 void launch_minres_b(hipStream_t st, double* S);
-void launch_lincomb3_s(hipStream_t st, int64_t n, const double* S, double* z, const double* x,
+void launch_lincomb3_s(hipStream_t st, const Seg& sg, const double* S, double* z, const double* x,
                        const double* y);
-void launch_minres_update_s(hipStream_t st, int64_t n, const double* S, const double* z,
+void launch_minres_update_s(hipStream_t st, const Seg& sg, const double* S, const double* z,
                             double* w2, const double* w1, double* x);
+void launch_dot_seg(hipStream_t st, const Seg& sg, const double* a, const double* b, Red r);
 void launch_from_float(hipStream_t st, int64_t n, const float* e, double* x, double scale);
 
 }  // namespace frac

@@ -1002,9 +1002,19 @@ int minres(fracture* h, double rtol, int* iters) {
   HIPCHK(hipMemsetAsync(h->nw, 0, n3 * sizeof(double), st));
   double *v_prev = h->nv_prev, *v = h->nv, *az = h->naz, *z = h->nz, *w_prev = h->nw_prev,
          *w = h->nw;
+  // The damage block of every Krylov vector vanishes off the inactive set
+  // (the right-hand side, J and P all zero it there), so the vector updates
+  // and dot products walk the displacement block and the rows of the
+  // inactive band only (S_JLO, S_JHI from the VI evaluation of this
+  // iterate's residual).
+  const int64_t n2 = h->n2, W = h->lv[0].g.nx + 1;
+  const double jlo = -h->hS[S_JLO], jhi = h->hS[S_JHI];
+  Seg sg{n2, n2, n2};
+  if (std::isfinite(jlo) && std::isfinite(jhi) && jhi >= jlo)
+    sg = Seg{n2, n2 + (int64_t)jlo * W, n2 + ((int64_t)jhi - (int64_t)jlo + 1) * W};
   *iters = 0;
   apply_P(h, v, z);
-  launch_dot(st, n3, z, v, red(h, 9, S_TMP2));
+  launch_dot_seg(st, sg, z, v, red(h, 9, S_TMP2));
   launch_minres_init(st, h->S);
   int rc = read_scalars(h);
   if (rc) return rc;
@@ -1014,13 +1024,13 @@ int minres(fracture* h, double rtol, int* iters) {
   apply_J(h, z, az);                                             // az = J z, S = z.J z
   for (int j = 1; j <= h->p.max_minres; ++j) {
     launch_minres_a(st, h->S);
-    launch_lincomb3_s(st, n3, h->S, az, v, v_prev);              // az = v_{j+1}
+    launch_lincomb3_s(st, sg, h->S, az, v, v_prev);              // az = v_{j+1}
     double* vn = az;
     apply_P(h, vn, v_prev);                                      // v_prev buffer <- z_{j+1}
     double* zn = v_prev;
-    launch_dot(st, n3, zn, vn, red(h, 9, S_TMP2));
+    launch_dot_seg(st, sg, zn, vn, red(h, 9, S_TMP2));
     launch_minres_b(st, h->S);
-    launch_minres_update_s(st, n3, h->S, z, w_prev, w, h->nx);   // w_prev <- w_{j+1}; x update
+    launch_minres_update_s(st, sg, h->S, z, w_prev, w, h->nx);   // w_prev <- w_{j+1}; x update
     lag_post(h, S_MN_ABSETA, 3, j);
     // rotate buffers
     v_prev = v;                // v_{j}

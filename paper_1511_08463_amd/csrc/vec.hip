@@ -288,37 +288,58 @@ void launch_minres_b(hipStream_t st, double* S) {
   hipLaunchKernelGGL(k_minres_b, dim3(1), dim3(WAVE), 0, st, S);
 }
 
-// z = L0 z + L1 x + L2 y with the coefficients in S
-__global__ __launch_bounds__(VB) void k_lincomb3_s(int64_t n, const double* __restrict__ S,
+// z = L0 z + L1 x + L2 y with the coefficients in S, on the entries of sg
+__global__ __launch_bounds__(VB) void k_lincomb3_s(Seg sg, const double* __restrict__ S,
                                                    double* __restrict__ z,
                                                    const double* __restrict__ x,
                                                    const double* __restrict__ y) {
   const double a = S[S_MN_L0], b = S[S_MN_L1], c = S[S_MN_L2];
-  GRID_STRIDE(k, n) z[k] = a * z[k] + b * x[k] + c * y[k];
+  GRID_STRIDE(q, sg.n) {
+    const int64_t k = seg_index(sg, q);
+    z[k] = a * z[k] + b * x[k] + c * y[k];
+  }
 }
 
-void launch_lincomb3_s(hipStream_t st, int64_t n, const double* S, double* z, const double* x,
+void launch_lincomb3_s(hipStream_t st, const Seg& sg, const double* S, double* z, const double* x,
                        const double* y) {
-  hipLaunchKernelGGL(k_lincomb3_s, dim3(vgrid(n)), dim3(VB), 0, st, n, S, z, x, y);
+  hipLaunchKernelGGL(k_lincomb3_s, dim3(vgrid(sg.n)), dim3(VB), 0, st, sg, S, z, x, y);
 }
 
-// w2 = U0 z + U1 w2 + U2 w1; x += U3 w2 with the coefficients in S
-__global__ __launch_bounds__(VB) void k_minres_update_s(int64_t n, const double* __restrict__ S,
+// w2 = U0 z + U1 w2 + U2 w1; x += U3 w2 with the coefficients in S, on the
+// entries of sg
+__global__ __launch_bounds__(VB) void k_minres_update_s(Seg sg, const double* __restrict__ S,
                                                         const double* __restrict__ z,
                                                         double* __restrict__ w2,
                                                         const double* __restrict__ w1,
                                                         double* __restrict__ x) {
   const double a = S[S_MN_U0], b = S[S_MN_U1], c = S[S_MN_U2], e = S[S_MN_U3];
-  GRID_STRIDE(k, n) {
+  GRID_STRIDE(q, sg.n) {
+    const int64_t k = seg_index(sg, q);
     const double wn = a * z[k] + b * w2[k] + c * w1[k];
     w2[k] = wn;
     x[k] += e * wn;
   }
 }
 
-void launch_minres_update_s(hipStream_t st, int64_t n, const double* S, const double* z,
+void launch_minres_update_s(hipStream_t st, const Seg& sg, const double* S, const double* z,
                             double* w2, const double* w1, double* x) {
-  hipLaunchKernelGGL(k_minres_update_s, dim3(vgrid(n)), dim3(VB), 0, st, n, S, z, w2, w1, x);
+  hipLaunchKernelGGL(k_minres_update_s, dim3(vgrid(sg.n)), dim3(VB), 0, st, sg, S, z, w2, w1, x);
+}
+
+// S = a.b over the entries of sg (with the Red post-operation)
+__global__ __launch_bounds__(VB) void k_dot_seg(Seg sg, const double* __restrict__ a,
+                                                const double* __restrict__ b, Red r) {
+  double acc = 0.0;
+  GRID_STRIDE(q, sg.n) {
+    const int64_t k = seg_index(sg, q);
+    acc += a[k] * b[k];
+  }
+  block_reduce<VB, false>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_dot_seg(hipStream_t st, const Seg& sg, const double* a, const double* b, Red r) {
+  hipLaunchKernelGGL(k_dot_seg, dim3(vgrid(sg.n)), dim3(VB), 0, st, sg, a, b, r);
+  launch_finish(st, r, vgrid(sg.n), false);
 }
 
 // S[slot] = ||x||^2 or max|x| (NaN -> inf)
