@@ -77,7 +77,7 @@ struct Mat {
 };
 
 // What the finishing block does with a reduced sum s (see post_scalar).
-enum Post { P_STORE = 0, P_CG_ALPHA, P_CG_BETA, P_SQRT, P_NEG, P_FCG_BETA, P_FCG_ALPHA };
+enum Post { P_STORE = 0, P_CG_ALPHA, P_CG_BETA, P_SQRT, P_NEG, P_FCG_BETA, P_FCG_ALPHA, P_ADD };
 
 struct Red {
   double* part;       // >= number of blocks of the launch
@@ -126,6 +126,9 @@ __device__ __forceinline__ void post_scalar(double s, const Red& r) {
       r.S[S_ALPHA] = (pq != 0.0) ? s / pq : 0.0;
       r.S[r.slot] = s;
     } break;
+    case P_ADD:   // a second part of a sum stored earlier in the same slot
+      r.S[r.slot] += s;
+      break;
     default:
       r.S[r.slot] = s;
   }

@@ -746,6 +746,37 @@ __device__ __forceinline__ double mref_pair(double w0, double w1, double w2, dou
   return (w0 * b0 + w1 * b1 + w2 * b2 + (w0 + w1 + w2) * (b0 + b1 + b2)) * (1.0 / 12.0);
 }
 
+// (B x_a) at node (i, j): the coupling coefficients c_e = -2 w_e^T M_ref b_e
+// of the six triangles around the node, w = x_a masked to the inactive set,
+// applied to the stress of u (its effective strain when EIG).
+template <bool EIG>
+__device__ __forceinline__ void coupling_force2d(const Grid& g, const Mat& m,
+                                                 const double* __restrict__ alpha,
+                                                 const double* __restrict__ u,
+                                                 const double* __restrict__ xa,
+                                                 const uint8_t* __restrict__ mask, int i, int j,
+                                                 double& gx, double& gy) {
+  const int W = g.nx + 1, N = g.N, n = i + W * j;
+  const bool L = i > 0, R = i < g.nx, D = j > 0, U = j < g.ny;
+  auto w_at = [&](bool ok, int k) -> double { return (ok && !mask[k]) ? xa[k] : 0.0; };
+  auto b_at = [&](bool ok, int k) -> double { return ok ? 1.0 - alpha[k] : 0.0; };
+  const double wC = w_at(true, n), wE = w_at(R, n + 1), wNE = w_at(R && U, n + 1 + W),
+               wN = w_at(U, n + W), wW = w_at(L, n - 1), wSW = w_at(L && D, n - 1 - W),
+               wS = w_at(D, n - W);
+  const double bC = b_at(true, n), bE = b_at(R, n + 1), bNE = b_at(R && U, n + 1 + W),
+               bN = b_at(U, n + W), bW = b_at(L, n - 1), bSW = b_at(L && D, n - 1 - W),
+               bS = b_at(D, n - W);
+  double c[6];
+  c[0] = -2.0 * mref_pair(wC, wE, wNE, bC, bE, bNE);
+  c[1] = -2.0 * mref_pair(wC, wNE, wN, bC, bNE, bN);
+  c[2] = -2.0 * mref_pair(wW, wC, wN, bW, bC, bN);
+  c[3] = -2.0 * mref_pair(wSW, wS, wC, bSW, bS, bC);
+  c[4] = -2.0 * mref_pair(wSW, wC, wW, bSW, bC, bW);
+  c[5] = -2.0 * mref_pair(wS, wE, wC, bS, bE, bC);
+  double dx, dy;
+  node_force2d<true, false, EIG>(g, m, c, u, u + N, i, j, gx, gy, dx, dy);
+}
+
 template <bool HAS_XU, bool HAS_XA, bool DOT, bool EIG>
 __global__ __launch_bounds__(NB) void k_jac_u2d(Grid g, Mat m, double kell,
                                                 const double* __restrict__ alpha,
@@ -775,27 +806,8 @@ __global__ __launch_bounds__(NB) void k_jac_u2d(Grid g, Mat m, double kell,
       node_force2d<true, false>(g, m, c, xu, xu + N, i, j, fx, fy, dx, dy);
     }
     if (couple) {
-      // coupling coefficients c_e = -2 w_e^T M_ref b_e with w = x_a masked to the inactive set
-      const int W = g.nx + 1;
-      const bool L = i > 0, R = i < g.nx, D = j > 0, U = j < g.ny;
-      auto w_at = [&](bool ok, int k) -> double { return (ok && !mask[k]) ? xa[k] : 0.0; };
-      auto b_at = [&](bool ok, int k) -> double { return ok ? 1.0 - alpha[k] : 0.0; };
-      const double wC = w_at(true, n), wE = w_at(R, n + 1), wNE = w_at(R && U, n + 1 + W),
-                   wN = w_at(U, n + W), wW = w_at(L, n - 1), wSW = w_at(L && D, n - 1 - W),
-                   wS = w_at(D, n - W);
-      const double bC = b_at(true, n), bE = b_at(R, n + 1), bNE = b_at(R && U, n + 1 + W),
-                   bN = b_at(U, n + W), bW = b_at(L, n - 1), bSW = b_at(L && D, n - 1 - W),
-                   bS = b_at(D, n - W);
-      double c[6];
-      c[0] = -2.0 * mref_pair(wC, wE, wNE, bC, bE, bNE);
-      c[1] = -2.0 * mref_pair(wC, wNE, wN, bC, bNE, bN);
-      c[2] = -2.0 * mref_pair(wW, wC, wN, bW, bC, bN);
-      c[3] = -2.0 * mref_pair(wSW, wS, wC, bSW, bS, bC);
-      c[4] = -2.0 * mref_pair(wSW, wC, wW, bSW, bC, bW);
-      c[5] = -2.0 * mref_pair(wS, wE, wC, bS, bE, bC);
       double gx, gy;
-      // the stress of the effective strain of u (eigenstrain when EIG)
-      node_force2d<true, false, EIG>(g, m, c, u, u + N, i, j, gx, gy, dx, dy);
+      coupling_force2d<EIG>(g, m, alpha, u, xa, mask, i, j, gx, gy);
       fx += gx;
       fy += gy;
     }
@@ -927,6 +939,48 @@ void launch_jac2d(hipStream_t st, const Grid& g, const Mat& m, double kell, doub
 #undef JA
     if (dot && xa) launch_finish(st, ra, (int)(gr.x * gr.y), false);
   }
+}
+
+// y_u += B x_a on rows r0..r1 (the rows next to the inactive set, the only
+// ones B x_a reaches), Dirichlet rows left alone; partial sums of x_u . B x_a.
+template <bool EIG>
+__global__ __launch_bounds__(NB) void k_couple_u2d(Grid g, Mat m, const double* __restrict__ alpha,
+                                                   const double* __restrict__ u,
+                                                   const double* __restrict__ xu,
+                                                   const double* __restrict__ xa,
+                                                   const uint8_t* __restrict__ mask,
+                                                   double* __restrict__ yu, int r0, int r1, Red r) {
+  const int i = blockIdx.x * NB_X + threadIdx.x;
+  const int j = r0 + blockIdx.y * NB_Y + threadIdx.y;
+  double acc = 0.0;
+  if (i <= g.nx && j <= r1) {
+    const int N = g.N, n = i + (g.nx + 1) * j;
+    double gx, gy;
+    coupling_force2d<EIG>(g, m, alpha, u, xa, mask, i, j, gx, gy);
+    if (fixed_x2(g, i, j)) gx = 0.0;
+    if (fixed_y2(g, i, j)) gy = 0.0;
+    yu[n] += gx;
+    yu[n + N] += gy;
+    acc = xu[n] * gx + xu[n + N] * gy;
+  }
+  block_reduce<NB, false>(acc, r, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
+                          threadIdx.x + NB_X * threadIdx.y);
+}
+
+void launch_couple_u2d(hipStream_t st, const Grid& g, const Mat& m, const double* alpha,
+                       const double* u, const double* xu, const double* xa, const uint8_t* mask,
+                       double* yu, int r0, int r1, Red r) {
+  if (r0 < 0) r0 = 0;
+  if (r1 > g.ny) r1 = g.ny;
+  if (r1 < r0) return;
+  dim3 gr((g.nx + 1 + NB_X - 1) / NB_X, (r1 - r0 + 1 + NB_Y - 1) / NB_Y), bl(NB_X, NB_Y);
+  if (g.eig_dT != 0.0)
+    hipLaunchKernelGGL((k_couple_u2d<true>), gr, bl, 0, st, g, m, alpha, u, xu, xa, mask, yu, r0,
+                       r1, r);
+  else
+    hipLaunchKernelGGL((k_couple_u2d<false>), gr, bl, 0, st, g, m, alpha, u, xu, xa, mask, yu, r0,
+                       r1, r);
+  launch_finish(st, r, (int)(gr.x * gr.y), false);
 }
 
 // Jacobi-preconditioned Chebyshev step on C = H_NN (the damage block of the

@@ -980,11 +980,20 @@ void apply_P(fracture* h, const double* x, double* y) {
 }
 
 // y = J x on the inactive coupled system; S[S_TMP0] + S[S_TMP1] = x.y.
+// The displacement rows: A x_u by the column-tiled operator, then B x_a on
+// the rows next to the inactive band (S_JLO, S_JHI as last read by the host,
+// from the VI evaluation of this iterate), each adding its part of x_u.y_u.
 void apply_J(fracture* h, const double* x, double* y) {
   const Grid g = load_grid(h);   // B and B^T carry the stress of u's effective strain
   const int64_t n2 = h->n2;
+  launch_apply2d(h->st, h->lv[0].g, h->mat, true, h->alpha, h->p.k_ell, x, y, nullptr, 1,
+                 1 /* dot */, red(h, 7, S_TMP0));
+  const double jlo = -h->hS[S_JLO], jhi = h->hS[S_JHI];
+  if (std::isfinite(jlo) && std::isfinite(jhi) && jhi >= jlo)
+    launch_couple_u2d(h->st, g, h->mat, h->alpha, h->u, x, x + n2, h->mask, y, (int)jlo - 1,
+                      (int)jhi + 1, red(h, 14, S_TMP0, P_ADD));
   launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask, x,
-               x + n2, y, y + n2, true, red(h, 7, S_TMP0), red(h, 8, S_TMP1), h->S + S_JLO);
+               x + n2, nullptr, y + n2, true, red(h, 7, S_TMP0), red(h, 8, S_TMP1), h->S + S_JLO);
 }
 
 // MINRES (preconditioned; the three-term Lanczos recurrence with Givens
