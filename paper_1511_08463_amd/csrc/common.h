@@ -46,9 +46,10 @@ enum {
   S_MN_G, S_MN_GP, S_MN_G1, S_MN_C, S_MN_CP, S_MN_S, S_MN_SP, S_MN_ETA, S_MN_D,
   S_MN_L0, S_MN_L1, S_MN_L2, S_MN_U0, S_MN_U1, S_MN_U2, S_MN_U3,
   S_MN_ABSETA, S_MN_GN, S_MN_BAD,
+  S_COARSE_REFRESH,   // 1: the coarsest dense system is re-assembled and re-inverted
   S_COUNT = 64
 };
-static_assert(S_MN_BAD < S_COUNT, "scalar slots");
+static_assert(S_COARSE_REFRESH < S_COUNT, "scalar slots");
 // the host reads |eta|, gamma_{j+1} and the non-finite flag of MINRES as one block
 static_assert(S_MN_GN == S_MN_ABSETA + 1 && S_MN_BAD == S_MN_ABSETA + 2, "MINRES status slots");
 // kernels read the inactive row band as the pair (S[S_JLO], S[S_JHI])

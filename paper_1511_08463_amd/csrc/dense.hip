@@ -21,7 +21,9 @@ __device__ __forceinline__ bool fixed_dof2(const Grid& g, int comp, int i, int j
 // Dense 2D assembly: each thread owns one node and writes its two rows, summing
 // the 6x6 element matrices abar |T| B^T D B of the triangles around it.
 __global__ __launch_bounds__(DB) void k_dense_assemble2d(Grid g, Mat m, const double* __restrict__ abar,
-                                                         double* __restrict__ A) {
+                                                         double* __restrict__ A,
+                                                         const double* __restrict__ S) {
+  if (S[S_COARSE_REFRESH] == 0.0) return;   // uniform: the whole block keeps the old system
   const int N = g.N, n2 = 2 * N, W = g.nx + 1;
   for (int k = threadIdx.x; k < n2 * n2; k += DB) A[k] = 0.0;
   __syncthreads();
@@ -75,7 +77,9 @@ __global__ __launch_bounds__(DB) void k_dense_assemble2d(Grid g, Mat m, const do
 // In-place Gauss-Jordan inverse of an SPD matrix (no pivoting) in global
 // memory, then symmetrisation into Ainv (any n up to DENSE_MAX).
 __global__ __launch_bounds__(DB) void k_gauss_jordan(int n, double* __restrict__ A,
-                                                     double* __restrict__ Ainv) {
+                                                     double* __restrict__ Ainv,
+                                                     const double* __restrict__ S) {
+  if (S[S_COARSE_REFRESH] == 0.0) return;
   extern __shared__ double sm[];
   double* colk = sm;
   double* rowk = sm + n;
@@ -116,7 +120,9 @@ constexpr int GJ_Q = 14;
 constexpr int GJ_NMAX = 168;   // n (n + 1) / 2 <= DB * GJ_Q
 
 __global__ __launch_bounds__(DB) void k_sweep_inverse(int n, const double* __restrict__ A,
-                                                      double* __restrict__ Ainv) {
+                                                      double* __restrict__ Ainv,
+                                                      const double* __restrict__ S) {
+  if (S[S_COARSE_REFRESH] == 0.0) return;
   extern __shared__ double colk[];
   const int ne = n * (n + 1) / 2, t = threadIdx.x;
   double a[GJ_Q];
@@ -165,15 +171,49 @@ __global__ __launch_bounds__(DB) void k_sweep_inverse(int n, const double* __res
   }
 }
 
+// Whether the coarsest coefficients abar (ne elements) have drifted from ref,
+// those the current inverse was formed from, by more than a relative tol
+// anywhere (ref not finite or not positive counts as drifted).  On drift
+// S[S_COARSE_REFRESH] = 1 and ref <- abar, else 0.  A coarse correction from
+// a slightly older but still symmetric positive definite coarse operator
+// keeps the V-cycle a fixed SPD preconditioner; only its quality changes.
+__global__ __launch_bounds__(DB) void k_coarse_drift(int ne, const double* __restrict__ abar,
+                                                     double* __restrict__ ref,
+                                                     double* __restrict__ S, double tol) {
+  __shared__ double sh[DB / WAVE];
+  __shared__ int refresh;
+  double m = 0.0;
+  for (int e = threadIdx.x; e < ne; e += DB) {
+    const double r = ref[e];
+    const double rel = (r > 0.0 && isfinite(r)) ? fabs(abar[e] - r) / r : INFINITY;
+    m = fmax(m, isnan(rel) ? INFINITY : rel);
+  }
+  m = wave_max(m);
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  if (lane == 0) sh[w] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = sh[0];
+    for (int k = 1; k < DB / WAVE; ++k) a = fmax(a, sh[k]);
+    refresh = !(a <= tol);
+    S[S_COARSE_REFRESH] = refresh ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (refresh)
+    for (int e = threadIdx.x; e < ne; e += DB) ref[e] = abar[e];
+}
+
 void launch_dense_setup(hipStream_t st, const Grid& g, const Mat& m, const double* abar,
-                        double* A, double* Ainv) {
+                        double* A, double* Ainv, double* ref, double* S, double tol) {
   const int n = g.dim * g.N;
-  if (g.dim == 3) launch_dense_assemble3d(st, g, m, abar, A);
-  else hipLaunchKernelGGL(k_dense_assemble2d, dim3(1), dim3(DB), 0, st, g, m, abar, A);
+  const int ne = g.dim == 3 ? 6 * g.nx * g.ny * g.nz : 2 * g.nx * g.ny;
+  hipLaunchKernelGGL(k_coarse_drift, dim3(1), dim3(DB), 0, st, ne, abar, ref, S, tol);
+  if (g.dim == 3) launch_dense_assemble3d(st, g, m, abar, A, S);
+  else hipLaunchKernelGGL(k_dense_assemble2d, dim3(1), dim3(DB), 0, st, g, m, abar, A, S);
   if (n <= GJ_NMAX)
-    hipLaunchKernelGGL(k_sweep_inverse, dim3(1), dim3(DB), n * sizeof(double), st, n, A, Ainv);
+    hipLaunchKernelGGL(k_sweep_inverse, dim3(1), dim3(DB), n * sizeof(double), st, n, A, Ainv, S);
   else
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(DB), 2 * n * sizeof(double), st, n, A, Ainv);
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(DB), 2 * n * sizeof(double), st, n, A, Ainv, S);
 }
 
 // x = Ainv b (dense, one block, b in LDS; float64 accumulation for either

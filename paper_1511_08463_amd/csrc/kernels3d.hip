@@ -557,7 +557,9 @@ void launch_energy3d(hipStream_t st, const Grid& g, const Mat& m, double kell, d
 
 // Dense assembly of the coarsest 3D level (one thread per node row).
 __global__ __launch_bounds__(1024) void k_dense_assemble3d(Grid g, Mat m, const double* __restrict__ abar,
-                                                           double* __restrict__ A) {
+                                                           double* __restrict__ A,
+                                                           const double* __restrict__ S) {
+  if (S[S_COARSE_REFRESH] == 0.0) return;   // uniform: the whole block keeps the old system
   const int N = g.N, n3 = 3 * N, W = g.nx + 1, H = g.ny + 1;
   for (int q = threadIdx.x; q < n3 * n3; q += 1024) A[q] = 0.0;
   __syncthreads();
@@ -596,8 +598,9 @@ __global__ __launch_bounds__(1024) void k_dense_assemble3d(Grid g, Mat m, const 
   }
 }
 
-void launch_dense_assemble3d(hipStream_t st, const Grid& g, const Mat& m, const double* abar, double* A) {
-  hipLaunchKernelGGL(k_dense_assemble3d, dim3(1), dim3(1024), 0, st, g, m, abar, A);
+void launch_dense_assemble3d(hipStream_t st, const Grid& g, const Mat& m, const double* abar, double* A,
+                             const double* S) {
+  hipLaunchKernelGGL(k_dense_assemble3d, dim3(1), dim3(1024), 0, st, g, m, abar, A, S);
 }
 
 #define INST3(T)                                                                                \

@@ -84,11 +84,11 @@ void launch_helm_apply3d(hipStream_t st, const Grid& g, double cL, double cM, co
 void launch_energy3d(hipStream_t st, const Grid& g, const Mat& m, double kell, double gc_cw,
                      double ell, int at2, const double* w2, const double* a, Red rel, Red rsu);
 void launch_dense_assemble3d(hipStream_t st, const Grid& g, const Mat& m, const double* abar,
-                             double* A);
+                             double* A, const double* S);
 
 // ---- coarse dense solve (dense.hip) ----------------------------------------
 void launch_dense_setup(hipStream_t st, const Grid& g, const Mat& m, const double* abar,
-                        double* A, double* Ainv);
+                        double* A, double* Ainv, double* ref, double* S, double tol);
 template <class T>
 void launch_dense_solve(hipStream_t st, int n, const double* Ainv, const T* b, T* x);
 

@@ -34,6 +34,9 @@ namespace {
 
 constexpr int MAXLEV = 16;
 constexpr int DENSE_MAX = 1024;   // largest coarsest-level system inverted densely
+// The coarsest system is re-assembled and re-inverted once its coefficients
+// drift by more than this relative amount from those of the current inverse.
+constexpr double COARSE_DRIFT = 0.02;
 constexpr double ARMIJO_SIGMA = 1e-4;
 constexpr int MAX_HALVINGS = 20;
 constexpr int MAX_GRAPHS = 16;
@@ -113,6 +116,7 @@ struct fracture {
   float *alpha32 = nullptr, *fe32 = nullptr, *fr32 = nullptr, *fp32 = nullptr, *fq32 = nullptr;
   // coarsest level
   double *dA = nullptr, *dAinv = nullptr;
+  double* dref = nullptr;   // coarsest coefficients the dense inverse was formed from
   int dense_n = 0;
   // first level of the single-workgroup V-cycle tail per value type (-1: none)
   int tail64 = -1, tail32 = -1;
@@ -315,6 +319,8 @@ size_t layout(const fracture_params* p, fracture* h, void* ws) {
   const int dn = dim * gl[L - 1].N;
   t->dA = c.take<double>((size_t)dn * dn);
   t->dAinv = c.take<double>((size_t)dn * dn);
+  t->dref = c.take<double>((int64_t)gl[L - 1].nx * gl[L - 1].ny *
+                           (dim == 3 ? 6 * (int64_t)gl[L - 1].nz : 2));
   int pn = node_blocks(gl[0]);
   if (vec_blocks(n2) > pn) pn = vec_blocks(n2);
   t->part_n = pn;
@@ -462,7 +468,9 @@ void update_coefficients(fracture* h) {
                      h->lv[l].abar, h->mixed ? h->lv[l].abar32 : nullptr);
   if (h->mixed) launch_to_float(h->st, h->N, h->alpha, h->alpha32, 1.0);
   const int Lc = h->nlev - 1;
-  if (Lc >= 1) launch_dense_setup(h->st, h->lv[Lc].g, h->mat, h->lv[Lc].abar, h->dA, h->dAinv);
+  if (Lc >= 1)
+    launch_dense_setup(h->st, h->lv[Lc].g, h->mat, h->lv[Lc].abar, h->dA, h->dAinv, h->dref, h->S,
+                       COARSE_DRIFT);
   h->coef_valid = true;
 }
 
@@ -1403,6 +1411,12 @@ int fracture_create(const fracture_params* p, const uint8_t* notch_mask, void* d
   hipStream_t st = h->st;
   bool ok = true;
   ok &= hipMemsetAsync(h->S, 0, S_COUNT * sizeof(double), st) == hipSuccess;
+  // NaN reference coefficients: the first coefficient update inverts
+  {
+    const Grid& gc = h->lv[h->nlev - 1].g;
+    const size_t ne = (size_t)gc.nx * gc.ny * (gc.dim == 3 ? 6 * (size_t)gc.nz : 2);
+    ok &= hipMemsetAsync(h->dref, 0xFF, ne * sizeof(double), st) == hipSuccess;
+  }
   ok &= hipMemsetAsync(h->u, 0, h->n2 * sizeof(double), st) == hipSuccess;
   ok &= hipMemsetAsync(h->alpha, 0, h->N * sizeof(double), st) == hipSuccess;
   if (notch_mask) {
