@@ -85,6 +85,7 @@ struct Red {
   double* S;          // scalar array
   int slot;           // S[slot] receives the result
   int post;           // Post
+  double* host = nullptr;   // optional: pinned host memory that also receives S[slot]
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -133,6 +134,7 @@ __device__ __forceinline__ void post_scalar(double s, const Red& r) {
     default:
       r.S[r.slot] = s;
   }
+  if (r.host) r.host[0] = r.S[r.slot];   // the host reads it behind an event, no copy
 }
 
 // Entries [0, n0) and [b0, b0 + n - n0) of a vector, walked as one index

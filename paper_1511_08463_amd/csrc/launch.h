@@ -163,7 +163,7 @@ void launch_add_scaled_f(hipStream_t st, int64_t n, double* x, const float* e, d
 void launch_copy(hipStream_t st, int64_t n, const double* x, double* y);
 void launch_minres_init(hipStream_t st, double* S);
 void launch_minres_a(hipStream_t st, double* S);
-void launch_minres_b(hipStream_t st, double* S);
+void launch_minres_b(hipStream_t st, double* S, double* host);
 void launch_lincomb3_s(hipStream_t st, const Seg& sg, const double* S, double* z, const double* x,
                        const double* y);
 void launch_minres_update_s(hipStream_t st, const Seg& sg, const double* S, const double* z,

@@ -437,17 +437,18 @@ int read_scalars(fracture* h) {
   return FRACTURE_OK;
 }
 
-// Lagged read of device scalars: the block S[slot .. slot + count) after
-// iteration k is copied to pinned slot k % 2 behind an event, and the host
-// waits for iteration k - 1's (or k's) values while later work is already
-// queued, so the device does not idle on the host's convergence test.
+// Lagged read of device scalars: the values of iteration k land in pinned
+// slot k % 2 behind an event, and the host waits for iteration k - 1's (or
+// k's) values while later work is already queued, so the device does not
+// idle on the host's convergence test.
 constexpr int LAG_W = 4;   // doubles per pinned slot
 
-void lag_post(fracture* h, int slot, int count, int k) {
-  (void)hipMemcpyAsync(h->hS + S_COUNT + LAG_W * (k & 1), h->S + slot, count * sizeof(double),
-                       hipMemcpyDeviceToHost, h->st);
-  (void)hipEventRecord(h->ev[8 + (k & 1)], h->st);
-}
+// Pinned host slot of iteration k's lagged scalars.  The kernel that
+// produces them writes them there itself (Red::host, k_minres_b), so no copy
+// is queued; lag_mark records the event the host waits on.
+double* lag_slot(fracture* h, int k) { return h->hS + S_COUNT + LAG_W * (k & 1); }
+
+void lag_mark(fracture* h, int k) { (void)hipEventRecord(h->ev[8 + (k & 1)], h->st); }
 
 int lag_get(fracture* h, int k, int count, double* v) {
   if (h->graph_error) return FRACTURE_EDEVICE;
@@ -792,7 +793,7 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
     // the direction update rides in the Hessian apply (p ping-pongs between
     // vp and vt1) and the preconditioner in the CG update, so an iteration
     // is two kernels and two finishing launches; the CG scalars live on the
-    // device and the host tests ||r|| one iteration late (lag_post / lag_get)
+    // device and the host tests ||r|| one iteration late (lag_mark / lag_get)
     if (any_inactive) {
       launch_norm2(st, cnt, vr, red(h, 7, S_TMP2));
       launch_jacobi_dot(st, cnt, vr, hd, vz, red(h, 1, S_RZ));
@@ -807,10 +808,12 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
         double* pn = pb[k & 1];
         launch_helm_cg2d(st, g, h->cL, h->cM, h->w2, h->vz, pb[(k + 1) & 1], h->mask, pn, h->vq,
                          j0, j1, h->S, k == 1, red(h, 2, S_PQ, P_CG_ALPHA));
-        launch_cg_update_jac(st, cnt, vd, vr, pn + off, vq, hd, vz, h->S, red(h, 3, S_RR),
+        Red rr = red(h, 3, S_RR);
+        rr.host = lag_slot(h, k);
+        launch_cg_update_jac(st, cnt, vd, vr, pn + off, vq, hd, vz, h->S, rr,
                              red(h, 4, S_RZNEW, P_CG_BETA));
         ++*cg_iters;
-        lag_post(h, S_RR, 1, k);
+        lag_mark(h, k);
         if (k > 1) {
           double rr = 0;
           rc = lag_get(h, k - 1, 1, &rr);
@@ -1046,9 +1049,9 @@ int minres(fracture* h, double rtol, int* iters) {
     apply_P(h, vn, v_prev);                                      // v_prev buffer <- z_{j+1}
     double* zn = v_prev;
     launch_dot_seg(st, sg, zn, vn, red(h, 9, S_TMP2));
-    launch_minres_b(st, h->S);
+    launch_minres_b(st, h->S, lag_slot(h, j));
     launch_minres_update_s(st, sg, h->S, z, w_prev, w, h->nx);   // w_prev <- w_{j+1}; x update
-    lag_post(h, S_MN_ABSETA, 3, j);
+    lag_mark(h, j);
     // rotate buffers
     v_prev = v;                // v_{j}
     v = vn;                    // v_{j+1}

@@ -251,7 +251,7 @@ __global__ void k_minres_a(double* S) {
 // after z_{j+1} = P v_{j+1} and S_TMP2 = z_{j+1} . v_{j+1}: the next Givens
 // rotation, the coefficients of w_{j+1} = (z_j / gamma - a3 w_{j-1} - a2 w_j) / a1
 // and of x += c_{j+1} eta w_{j+1}, then eta and the scalars shift by one.
-__global__ void k_minres_b(double* S) {
+__global__ void k_minres_b(double* S, double* host) {
   if (threadIdx.x != 0) return;
   const double g = S[S_MN_G], d = S[S_MN_D], c = S[S_MN_C], cp = S[S_MN_CP];
   const double s = S[S_MN_S], sp = S[S_MN_SP], eta = S[S_MN_ETA], gn2 = S[S_TMP2];
@@ -276,6 +276,11 @@ __global__ void k_minres_b(double* S) {
   S[S_MN_SP] = s;
   S[S_MN_S] = sn;
   if (!isfinite(gn2)) S[S_MN_BAD] = 1.0;
+  if (host) {   // |eta|, gamma_{j+1}, the non-finite flag for the host's lagged test
+    host[0] = S[S_MN_ABSETA];
+    host[1] = S[S_MN_GN];
+    host[2] = S[S_MN_BAD];
+  }
 }
 
 void launch_minres_init(hipStream_t st, double* S) {
@@ -284,8 +289,8 @@ void launch_minres_init(hipStream_t st, double* S) {
 void launch_minres_a(hipStream_t st, double* S) {
   hipLaunchKernelGGL(k_minres_a, dim3(1), dim3(WAVE), 0, st, S);
 }
-void launch_minres_b(hipStream_t st, double* S) {
-  hipLaunchKernelGGL(k_minres_b, dim3(1), dim3(WAVE), 0, st, S);
+void launch_minres_b(hipStream_t st, double* S, double* host) {
+  hipLaunchKernelGGL(k_minres_b, dim3(1), dim3(WAVE), 0, st, S, host);
 }
 
 // z = L0 z + L1 x + L2 y with the coefficients in S, on the entries of sg
