@@ -272,6 +272,39 @@ void launch_restrict2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* 
   hipLaunchKernelGGL((k_restrict2d<T>), gr, bl, 0, st, gf, gc, rf, bc);
 }
 
+// b_c = P^T r_f and, from x = 0, the first Jacobi-Chebyshev step on the
+// coarse level, x_c = cr D^{-1} b_c (d_c = x_c when dout): from zero the step
+// reads no neighbour of x, so restriction and step are one pass over the
+// coarse nodes.  Same arithmetic as k_restrict2d followed by k_node2d<SMOOTH>
+// without x.
+template <class T>
+__global__ __launch_bounds__(NB) void k_restrict_smooth2d(Grid gf, Grid gc, Mat m,
+                                                          const T* __restrict__ coef, T kell,
+                                                          const T* __restrict__ rf,
+                                                          T* __restrict__ bc, T* __restrict__ xout,
+                                                          T* __restrict__ dout, T cr) {
+  const int I = blockIdx.x * NB_X + threadIdx.x;
+  const int J = blockIdx.y * NB_Y + threadIdx.y;
+  if (I > gc.nx || J > gc.ny) return;
+  restrict_node2d(gf, gc, rf, bc, I, J);
+  T c[6];
+  coef6<false>(gc, coef, kell, I, J, c);
+  T fx, fy, dx, dy;
+  node_force2d<false, true>(gc, m, c, (const T*)nullptr, (const T*)nullptr, I, J, fx, fy, dx, dy);
+  double acc = 0.0;
+  node_out2d<M_SMOOTH, R_NONE>(gc, I, J, fx, fy, dx, dy, T(0), T(0), xout, bc, (const T*)nullptr,
+                               dout, T(0), cr, 1, acc);
+}
+
+template <class T>
+void launch_restrict_smooth2d(hipStream_t st, const Grid& gf, const Grid& gc, const Mat& m,
+                              const T* coef, double kell, const T* rf, T* bc, T* xout, T* dout,
+                              double cr) {
+  dim3 gr(node_grid2(gc)), bl(NB_X, NB_Y);
+  hipLaunchKernelGGL((k_restrict_smooth2d<T>), gr, bl, 0, st, gf, gc, m, coef, T(kell), rf, bc,
+                     xout, dout, T(cr));
+}
+
 // x_f += P x_c.
 template <class T>
 __global__ __launch_bounds__(NB) void k_prolong2d(Grid gf, Grid gc, const T* __restrict__ xc,
@@ -297,6 +330,8 @@ void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* x
   template void launch_smooth2d<T>(hipStream_t, const Grid&, const Mat&, bool, const T*, double,  \
                                    const ND<T>*, T*, const T*, const ND<T>*, ND<T>*, double, double);        \
   template void launch_restrict2d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);        \
+  template void launch_restrict_smooth2d<T>(hipStream_t, const Grid&, const Grid&, const Mat&,     \
+                                            const T*, double, const T*, T*, T*, T*, double);       \
   template void launch_prolong2d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);
 INST(float)
 INST(double)

@@ -24,6 +24,10 @@ void launch_coarsen2d(hipStream_t st, const Grid& gf, bool fine_is_alpha, const 
 template <class T>
 void launch_restrict2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* rf, T* bc);
 template <class T>
+void launch_restrict_smooth2d(hipStream_t st, const Grid& gf, const Grid& gc, const Mat& m,
+                              const T* coef, double kell, const T* rf, T* bc, T* xout, T* dout,
+                              double cr);
+template <class T>
 void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* xc, T* xf);
 void launch_lift2d(hipStream_t st, const Grid& g, double* u, double t, const Load2D& ld);
 void launch_w2_2d(hipStream_t st, const Grid& g, const Mat& m, const double* u, double* w2);

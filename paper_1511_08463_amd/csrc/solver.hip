@@ -505,7 +505,7 @@ LevelBufs<float> bufs<float>(fracture* h, int l) {
 // symmetric: pre- and post-smoothing apply the same Chebyshev polynomial, so
 // it is a fixed SPD preconditioner in exact arithmetic.
 template <class T>
-T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr) {
+T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr, bool first_done = false) {
   LevelBufs<T> v = bufs<T>(h, l);
   const Grid& g = h->lv[l].g;
   const int k = h->p.cheb_degree;
@@ -532,10 +532,15 @@ T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr) {
     launch_vtail2d<T>(h->st, ta);
     return v.xa;
   }
-  // pre-smoothing from zero
+  // pre-smoothing from zero (first_done: the first step came with the
+  // restriction, into xa and d)
   T* cur = nullptr;
   for (int s = 0; s < k; ++s) {
     T* out = (s % 2 == 0) ? v.xa : v.xb;
+    if (s == 0 && first_done) {
+      cur = out;
+      continue;
+    }
     const T* din = s == 0 ? nullptr : (s == 1 ? cur : v.d);
     T* dout = (s < k - 1) ? v.d : nullptr;
     launch_smooth2d<T>(h->st, g, h->mat, fine, v.coef, kell, cur, out, b, din, dout,
@@ -546,8 +551,15 @@ T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr) {
   Red none{};
   launch_resid2d<T>(h->st, g, h->mat, fine, v.coef, kell, cur, v.r, b, false, none);
   LevelBufs<T> c = bufs<T>(h, l + 1);
-  launch_restrict2d<T>(h->st, g, h->lv[l + 1].g, v.r, c.b);
-  T* xc = vcycle_t<T>(h, l + 1, c.b);
+  // a next level smoothed by per-level kernels takes its first step from
+  // zero together with the restriction
+  const bool fuse = g.dim == 2 && l + 1 < h->nlev - 1 && !(h->p.vcycle_tail && l + 1 == tail);
+  if (fuse)
+    launch_restrict_smooth2d<T>(h->st, g, h->lv[l + 1].g, h->mat, c.coef, kell, v.r, c.b, c.xa,
+                                k > 1 ? c.d : nullptr, h->cheb_cr[0]);
+  else
+    launch_restrict2d<T>(h->st, g, h->lv[l + 1].g, v.r, c.b);
+  T* xc = vcycle_t<T>(h, l + 1, c.b, nullptr, fuse);
   launch_prolong2d<T>(h->st, g, h->lv[l + 1].g, xc, cur);
   // post-smoothing (same polynomial: the V-cycle is symmetric)
   for (int s = 0; s < k; ++s) {
