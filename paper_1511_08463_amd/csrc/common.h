@@ -47,15 +47,16 @@ enum {
   S_MN_L0, S_MN_L1, S_MN_L2, S_MN_U0, S_MN_U1, S_MN_U2, S_MN_U3,
   S_MN_ABSETA, S_MN_GN, S_MN_BAD,
   S_COARSE_REFRESH,   // 1: the coarsest dense system is re-assembled and re-inverted
+  S_ILO, S_IHI,       // 3D: -(smallest) and largest column i of an inactive damage node
   S_COUNT = 64
 };
-static_assert(S_COARSE_REFRESH < S_COUNT, "scalar slots");
+static_assert(S_IHI < S_COUNT, "scalar slots");
 // the host reads |eta|, gamma_{j+1} and the non-finite flag of MINRES as one block
 static_assert(S_MN_GN == S_MN_ABSETA + 1 && S_MN_BAD == S_MN_ABSETA + 2, "MINRES status slots");
 // kernels read the inactive row band as the pair (S[S_JLO], S[S_JHI])
 static_assert(S_JHI == S_JLO + 1, "band slots must be adjacent");
 // Partial-sum slots: one per reduction that may be pending at the same time.
-enum { C_SLOTS = 16 };
+enum { C_SLOTS = 18 };
 
 // A structured level: (nx+1)(ny+1)[(nz+1)] nodes.
 struct Grid {
@@ -146,6 +147,19 @@ struct Seg {
 
 __device__ __forceinline__ int64_t seg_index(const Seg& s, int64_t q) {
   return q < s.n0 ? q : s.b0 + (q - s.n0);
+}
+
+// The nodes of a box in a row-major grid: rows of stride W starting at base,
+// w consecutive entries taken per row (w == W: one contiguous range), n
+// entries in all, walked as one index range 0..n-1.
+struct Box {
+  int64_t base, W, w, n;
+};
+
+__device__ __forceinline__ int64_t box_index(const Box& b, int64_t q) {
+  if (b.w == b.W) return b.base + q;
+  const int64_t r = q / b.w;
+  return b.base + r * b.W + (q - r * b.w);
 }
 
 // Independent reductions of one launch, finished together (launch_finish_multi):

@@ -661,12 +661,13 @@ __global__ __launch_bounds__(NB) void k_helm_cg2d(Grid g, Helm hp, const double*
                                                   const uint8_t* __restrict__ mask,
                                                   double* __restrict__ p_new,
                                                   double* __restrict__ q, int j0, int j1,
-                                                  const double* __restrict__ S, Red r) {
-  const int i = blockIdx.x * NB_X + threadIdx.x;
+                                                  int i0, int i1, const double* __restrict__ S,
+                                                  Red r) {
+  const int i = i0 + blockIdx.x * NB_X + threadIdx.x;
   const int j = j0 + blockIdx.y * NB_Y + threadIdx.y;
   const double beta = FIRST ? 0.0 : S[S_BETA];
   double acc = 0.0;
-  if (i <= g.nx && j <= j1) {
+  if (i <= i1 && j <= j1) {
     const int n = i + (g.nx + 1) * j;
     double Hx, gv, Hd;
     // active nodes read as zero, so rows outside j0..j1 (all active) never enter
@@ -685,22 +686,27 @@ __global__ __launch_bounds__(NB) void k_helm_cg2d(Grid g, Helm hp, const double*
                           threadIdx.x + NB_X * threadIdx.y);
 }
 
+// Rows j0..j1 (3D: row indices j + (ny + 1) k) and columns i0..i1.
 void launch_helm_cg2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
                       const double* z, const double* p_old, const uint8_t* mask, double* p_new,
-                      double* q, int j0, int j1, const double* S, bool first, Red r) {
+                      double* q, int j0, int j1, int i0, int i1, const double* S, bool first,
+                      Red r) {
   if (g.dim == 3)
-    return launch_helm_cg3d(st, g, cL, cM, w2, z, p_old, mask, p_new, q, j0, j1, S, first, r);
+    return launch_helm_cg3d(st, g, cL, cM, w2, z, p_old, mask, p_new, q, j0, j1, i0, i1, S, first,
+                            r);
   Helm hp{cL, cM, 0.0};
   if (j0 < 0) j0 = 0;
   if (j1 < 0 || j1 > g.ny) j1 = g.ny;
-  if (j1 < j0) return;
-  dim3 gr((g.nx + 1 + NB_X - 1) / NB_X, (j1 - j0 + 1 + NB_Y - 1) / NB_Y), bl(NB_X, NB_Y);
+  if (i0 < 0) i0 = 0;
+  if (i1 < 0 || i1 > g.nx) i1 = g.nx;
+  if (j1 < j0 || i1 < i0) return;
+  dim3 gr((i1 - i0 + 1 + NB_X - 1) / NB_X, (j1 - j0 + 1 + NB_Y - 1) / NB_Y), bl(NB_X, NB_Y);
   if (first)
     hipLaunchKernelGGL((k_helm_cg2d<true>), gr, bl, 0, st, g, hp, w2, z, p_old, mask, p_new, q, j0,
-                       j1, S, r);
+                       j1, i0, i1, S, r);
   else
     hipLaunchKernelGGL((k_helm_cg2d<false>), gr, bl, 0, st, g, hp, w2, z, p_old, mask, p_new, q, j0,
-                       j1, S, r);
+                       j1, i0, i1, S, r);
   launch_finish(st, r, (int)(gr.x * gr.y), false);
 }
 

@@ -476,12 +476,14 @@ __global__ __launch_bounds__(NB) void k_helm_cg3d(Grid g, Helm3 hp, const double
                                                   const uint8_t* __restrict__ mask,
                                                   double* __restrict__ p_new,
                                                   double* __restrict__ q, int r0, int r1,
-                                                  const double* __restrict__ S, Red r) {
-  const int i = blockIdx.x * NB_X + threadIdx.x, j = blockIdx.y * NB_Y + threadIdx.y, k = blockIdx.z;
+                                                  int i0, int i1, const double* __restrict__ S,
+                                                  Red r) {
+  const int i = i0 + blockIdx.x * NB_X + threadIdx.x, j = blockIdx.y * NB_Y + threadIdx.y;
+  const int k = blockIdx.z;
   const double beta = FIRST ? 0.0 : S[S_BETA];
   double acc = 0.0;
   const int row = j + (g.ny + 1) * k;
-  if (i <= g.nx && j <= g.ny && row >= r0 && row <= r1) {
+  if (i <= i1 && j <= g.ny && row >= r0 && row <= r1) {
     const int n = i + (g.nx + 1) * row;
     double Hx, gv, Hd;
     if (FIRST)
@@ -502,19 +504,49 @@ __global__ __launch_bounds__(NB) void k_helm_cg3d(Grid g, Helm3 hp, const double
 
 void launch_helm_cg3d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
                       const double* z, const double* p_old, const uint8_t* mask, double* p_new,
-                      double* q, int r0, int r1, const double* S, bool first, Red r) {
+                      double* q, int r0, int r1, int i0, int i1, const double* S, bool first,
+                      Red r) {
   Helm3 hp{cL, cM, 0.0};
   const int rows = (g.ny + 1) * (g.nz + 1);
   if (r0 < 0) r0 = 0;
   if (r1 < 0 || r1 >= rows) r1 = rows - 1;
+  if (i0 < 0) i0 = 0;
+  if (i1 < 0 || i1 > g.nx) i1 = g.nx;
+  if (i1 < i0) return;
   dim3 gr = node_grid3(g), bl(NB_X, NB_Y);
+  gr.x = (i1 - i0 + 1 + NB_X - 1) / NB_X;
   if (first)
     hipLaunchKernelGGL((k_helm_cg3d<true>), gr, bl, 0, st, g, hp, w2, z, p_old, mask, p_new, q, r0,
-                       r1, S, r);
+                       r1, i0, i1, S, r);
   else
     hipLaunchKernelGGL((k_helm_cg3d<false>), gr, bl, 0, st, g, hp, w2, z, p_old, mask, p_new, q, r0,
-                       r1, S, r);
+                       r1, i0, i1, S, r);
   launch_finish(st, r, (int)(gr.x * gr.y * gr.z), false);
+}
+
+// -(smallest) and largest column index i of an inactive node (no inactive
+// node: -inf), which bound the damage CG's box in x.
+__global__ __launch_bounds__(VB) void k_irange3d(Grid g, const uint8_t* __restrict__ mask, Red rlo,
+                                                 Red rhi) {
+  const int W = g.nx + 1;
+  double lo = -INFINITY, hi = -INFINITY;
+  for (int n = blockIdx.x * VB + threadIdx.x; n < g.N; n += gridDim.x * VB) {
+    if (!mask[n]) {
+      const double i = (double)(n % W);
+      lo = fmax(lo, -i);
+      hi = fmax(hi, i);
+    }
+  }
+  block_reduce<VB, true>(lo, rlo, gridDim.x, blockIdx.x, threadIdx.x);
+  block_reduce<VB, true>(hi, rhi, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_irange3d(hipStream_t st, const Grid& g, const uint8_t* mask, Red rlo, Red rhi) {
+  int nb = (g.N + VB - 1) / VB;
+  if (nb > VGRID) nb = VGRID;
+  hipLaunchKernelGGL(k_irange3d, dim3(nb), dim3(VB), 0, st, g, mask, rlo, rhi);
+  const FinishSet fs{{rlo, rhi, Red{}, Red{}}, 0b11, 2};
+  launch_finish_multi(st, fs, nb);
 }
 
 __global__ __launch_bounds__(VB) void k_energy3d(Grid g, Mat m, double kell, double gc_cw, double ell,

@@ -47,6 +47,7 @@ void launch_jac2d(hipStream_t st, const Grid& g, const Mat& m, double kell, doub
                   const double* alpha, const double* u, const double* w2, const uint8_t* mask,
                   const double* xu, const double* xa, double* yu, double* ya, bool dot, Red ru,
                   Red ra, const double* band);
+void launch_irange3d(hipStream_t st, const Grid& g, const uint8_t* mask, Red rlo, Red rhi);
 void launch_couple_u2d(hipStream_t st, const Grid& g, const Mat& m, const double* alpha,
                        const double* u, const double* xu, const double* xa, const uint8_t* mask,
                        double* yu, int r0, int r1, Red r);
@@ -127,18 +128,19 @@ void launch_finish_multi(hipStream_t st, const FinishSet& fs, int nblocks);
 void launch_cg_update(hipStream_t st, int64_t n, double* x, double* r, const double* p,
                       const double* q, const double* S, Red rr);
 void launch_xpby(hipStream_t st, int64_t n, const double* z, double* p, const double* S);
-void launch_cg_update_jac(hipStream_t st, int64_t n, double* x, double* r, const double* p,
+void launch_cg_update_jac(hipStream_t st, const Box& bx, double* x, double* r, const double* p,
                           const double* q, const double* dinv, double* z, const double* S, Red rr,
                           Red rz);
 void launch_helm_cg3d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
                       const double* z, const double* p_old, const uint8_t* mask, double* p_new,
-                      double* q, int r0, int r1, const double* S, bool first, Red r);
+                      double* q, int r0, int r1, int i0, int i1, const double* S, bool first, Red r);
 void launch_helm_cg2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
                       const double* z, const double* p_old, const uint8_t* mask, double* p_new,
-                      double* q, int j0, int j1, const double* S, bool first, Red r);
+                      double* q, int r0, int r1, int i0, int i1, const double* S, bool first, Red r);
 void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, Red r);
-void launch_jacobi_dot(hipStream_t st, int64_t n, const double* r, const double* dinv, double* z,
+void launch_jacobi_dot(hipStream_t st, const Box& bx, const double* r, const double* dinv, double* z,
                        Red red);
+void launch_norm2_box(hipStream_t st, const Box& bx, const double* x, Red r);
 void launch_axpby(hipStream_t st, int64_t n, double a, const double* x, double b, double* y);
 void launch_norm2(hipStream_t st, int64_t n, const double* x, Red r);
 void launch_normmax(hipStream_t st, int64_t n, const double* x, Red r);

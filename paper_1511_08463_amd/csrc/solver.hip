@@ -783,6 +783,7 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
     launch_vi_eval2d(st, g, h->cL, h->cM, h->cm, h->w2, h->atil, nullptr, h->alpha_prev, h->S,
                      S_MU, 1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2),
                      red(h, 6, S_PHIMAX), red(h, 12, S_JLO), red(h, 13, S_JHI), false);
+    if (h->dim == 3) launch_irange3d(st, g, h->mask, red(h, 15, S_ILO), red(h, 16, S_IHI));
     int rc = read_scalars(h);
     if (rc) return rc;
     const double phimax = h->hS[S_PHIMAX], phi2 = h->hS[S_PHI2];
@@ -793,22 +794,28 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
     // reduced Newton step: H_NN d_N = -F_N (Jacobi CG), d_A = 0.  The CG runs
     // on the row range that holds every inactive node (its vectors are zero
     // outside), which for crack bands is a thin strip of the grid.
+    // In 3D the box is also cut to the columns that hold inactive nodes (a
+    // damaged surface layer is thin in x but spans every row).
     const double jlo = -h->hS[S_JLO], jhi = h->hS[S_JHI];
     launch_neg_masked(st, N, h->F, h->mask, h->vr, h->vd);
     // no inactive node: d = 0, and the line search falls back to steepest descent
     const bool any_inactive = std::isfinite(jlo) && std::isfinite(jhi) && jhi >= jlo;
     const int j0 = any_inactive ? (int)jlo : 0, j1 = any_inactive ? (int)jhi : -1;
-    const int64_t W = g.nx + 1, off = (int64_t)j0 * W;
-    const int64_t cnt = any_inactive ? (int64_t)(j1 - j0 + 1) * W : 0;
-    double *vr = h->vr + off, *vz = h->vz + off, *vq = h->vq + off, *vd = h->vd + off;
-    const double* hd = h->hdinv + off;
+    int i0 = 0, i1 = g.nx;
+    if (h->dim == 3 && any_inactive) {
+      i0 = (int)(-h->hS[S_ILO]);
+      i1 = (int)h->hS[S_IHI];
+    }
+    const int64_t W = g.nx + 1;
+    const Box bx{(int64_t)j0 * W + i0, W, (int64_t)(i1 - i0 + 1),
+                 any_inactive ? (int64_t)(j1 - j0 + 1) * (i1 - i0 + 1) : 0};
     // the direction update rides in the Hessian apply (p ping-pongs between
     // vp and vt1) and the preconditioner in the CG update, so an iteration
     // is two kernels and two finishing launches; the CG scalars live on the
     // device and the host tests ||r|| one iteration late (lag_mark / lag_get)
     if (any_inactive) {
-      launch_norm2(st, cnt, vr, red(h, 7, S_TMP2));
-      launch_jacobi_dot(st, cnt, vr, hd, vz, red(h, 1, S_RZ));
+      launch_norm2_box(st, bx, h->vr, red(h, 7, S_TMP2));
+      launch_jacobi_dot(st, bx, h->vr, h->hdinv, h->vz, red(h, 1, S_RZ));
       rc = read_scalars(h);
       if (rc) return rc;
     }
@@ -819,10 +826,10 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
       for (int k = 1; k <= h->p.max_vi_cg; ++k) {
         double* pn = pb[k & 1];
         launch_helm_cg2d(st, g, h->cL, h->cM, h->w2, h->vz, pb[(k + 1) & 1], h->mask, pn, h->vq,
-                         j0, j1, h->S, k == 1, red(h, 2, S_PQ, P_CG_ALPHA));
+                         j0, j1, i0, i1, h->S, k == 1, red(h, 2, S_PQ, P_CG_ALPHA));
         Red rr = red(h, 3, S_RR);
         rr.host = lag_slot(h, k);
-        launch_cg_update_jac(st, cnt, vd, vr, pn + off, vq, hd, vz, h->S, rr,
+        launch_cg_update_jac(st, bx, h->vd, h->vr, pn, h->vq, h->hdinv, h->vz, h->S, rr,
                              red(h, 4, S_RZNEW, P_CG_BETA));
         ++*cg_iters;
         lag_mark(h, k);

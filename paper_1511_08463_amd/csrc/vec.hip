@@ -108,10 +108,10 @@ void launch_cg_update(hipStream_t st, int64_t n, double* x, double* r, const dou
   launch_finish(st, rr, vgrid(n), false);
 }
 
-// x += a p; r -= a q; z = dinv .* r; S[rr.slot] = r.r, S[rz.slot] = r.z
-// (a = S[S_ALPHA]; both sums finished by one launch).  The two reductions
+// x += a p; r -= a q; z = dinv .* r; S[rr.slot] = r.r, S[rz.slot] = r.z over
+// the entries of a box (a = S[S_ALPHA]; both sums finished by one launch).  The two reductions
 // must not touch each other's scalars: rz's post-operation reads S_RZ only.
-__global__ __launch_bounds__(VB) void k_cg_update_jac(int64_t n, double* __restrict__ x,
+__global__ __launch_bounds__(VB) void k_cg_update_jac(Box bx, double* __restrict__ x,
                                                       double* __restrict__ r,
                                                       const double* __restrict__ p,
                                                       const double* __restrict__ q,
@@ -121,7 +121,8 @@ __global__ __launch_bounds__(VB) void k_cg_update_jac(int64_t n, double* __restr
                                                       Red rz) {
   const double a = S[S_ALPHA];
   double arr = 0.0, arz = 0.0;
-  GRID_STRIDE(k, n) {
+  GRID_STRIDE(qq, bx.n) {
+    const int64_t k = box_index(bx, qq);
     x[k] += a * p[k];
     const double rv = r[k] - a * q[k];
     r[k] = rv;
@@ -134,12 +135,12 @@ __global__ __launch_bounds__(VB) void k_cg_update_jac(int64_t n, double* __restr
   block_reduce<VB, false>(arz, rz, gridDim.x, blockIdx.x, threadIdx.x);
 }
 
-void launch_cg_update_jac(hipStream_t st, int64_t n, double* x, double* r, const double* p,
+void launch_cg_update_jac(hipStream_t st, const Box& bx, double* x, double* r, const double* p,
                           const double* q, const double* dinv, double* z, const double* S, Red rr,
                           Red rz) {
-  hipLaunchKernelGGL(k_cg_update_jac, dim3(vgrid(n)), dim3(VB), 0, st, n, x, r, p, q, dinv, z, S,
-                     rr, rz);
-  hipLaunchKernelGGL(k_finish2, dim3(2), dim3(FB), 0, st, rr, rz, vgrid(n));
+  hipLaunchKernelGGL(k_cg_update_jac, dim3(vgrid(bx.n)), dim3(VB), 0, st, bx, x, r, p, q, dinv, z,
+                     S, rr, rz);
+  hipLaunchKernelGGL(k_finish2, dim3(2), dim3(FB), 0, st, rr, rz, vgrid(bx.n));
 }
 
 // p = z + beta p   (beta = S[S_BETA])
@@ -166,12 +167,13 @@ void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, Red
   launch_finish(st, r, vgrid(n), false);
 }
 
-// z = dinv .* r; S = r.z (post)
-__global__ __launch_bounds__(VB) void k_jacobi_dot(int64_t n, const double* __restrict__ r,
+// z = dinv .* r; S = r.z (post), over the entries of a box
+__global__ __launch_bounds__(VB) void k_jacobi_dot(Box bx, const double* __restrict__ r,
                                                    const double* __restrict__ dinv,
                                                    double* __restrict__ z, Red red) {
   double acc = 0.0;
-  GRID_STRIDE(k, n) {
+  GRID_STRIDE(q, bx.n) {
+    const int64_t k = box_index(bx, q);
     const double zv = dinv[k] * r[k];
     z[k] = zv;
     acc += r[k] * zv;
@@ -179,10 +181,25 @@ __global__ __launch_bounds__(VB) void k_jacobi_dot(int64_t n, const double* __re
   block_reduce<VB, false>(acc, red, gridDim.x, blockIdx.x, threadIdx.x);
 }
 
-void launch_jacobi_dot(hipStream_t st, int64_t n, const double* r, const double* dinv, double* z,
+void launch_jacobi_dot(hipStream_t st, const Box& bx, const double* r, const double* dinv, double* z,
                        Red red) {
-  hipLaunchKernelGGL(k_jacobi_dot, dim3(vgrid(n)), dim3(VB), 0, st, n, r, dinv, z, red);
-  launch_finish(st, red, vgrid(n), false);
+  hipLaunchKernelGGL(k_jacobi_dot, dim3(vgrid(bx.n)), dim3(VB), 0, st, bx, r, dinv, z, red);
+  launch_finish(st, red, vgrid(bx.n), false);
+}
+
+// S = ||x||^2 over the entries of a box
+__global__ __launch_bounds__(VB) void k_norm2_box(Box bx, const double* __restrict__ x, Red r) {
+  double acc = 0.0;
+  GRID_STRIDE(q, bx.n) {
+    const double v = x[box_index(bx, q)];
+    acc += v * v;
+  }
+  block_reduce<VB, false>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
+}
+
+void launch_norm2_box(hipStream_t st, const Box& bx, const double* x, Red r) {
+  hipLaunchKernelGGL(k_norm2_box, dim3(vgrid(bx.n)), dim3(VB), 0, st, bx, x, r);
+  launch_finish(st, r, vgrid(bx.n), false);
 }
 
 // y = a x + b y (host scalars)

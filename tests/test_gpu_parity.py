@@ -141,6 +141,51 @@ def test_preconditioner_is_symmetric_positive():
     s.close()
 
 
+def test_coarsest_inverse_refreshed_on_drift():
+    """The coarsest dense inverse is rebuilt only when a coarsest coefficient
+    moves by more than 2%: a small damage change keeps the previous inverse
+    (the preconditioner then differs slightly from a fresh solver's but stays
+    symmetric and positive), a large one rebuilds it (the preconditioner then
+    equals a fresh solver's)."""
+    p = workloads.tension(96, 0.05, nx=96, ny=80)
+    P = _problem(p)
+    N = P.model.N
+    rng = np.random.default_rng(8)
+    free = P.free
+    x = rng.standard_normal(2 * N) * free
+    z = rng.standard_normal(2 * N) * free
+    a0 = np.clip(rng.uniform(-0.5, 0.6, N), 0, 1)
+
+    def precond(alpha, s=None):
+        fresh = s is None
+        s = s or _solver(p)
+        s.set_state(alpha=alpha)
+        fracture.fracture_update_coefficients(s.h)
+        Mx, Mz = s.apply(fracture.FRACTURE_OP_PRECOND, x), s.apply(fracture.FRACTURE_OP_PRECOND, z)
+        if fresh:
+            s.close()
+        return Mx, Mz
+
+    s = _solver(p)
+    precond(a0, s)
+    # small change: 1e-3 on every node moves each coarsest coefficient far less than 2%
+    a1 = np.clip(a0 + 1e-3, 0, 1)
+    Mx, Mz = precond(a1, s)
+    Fx, _ = precond(a1)
+    d = np.linalg.norm(Mx - Fx) / np.linalg.norm(Fx)
+    assert 0 < d < 1e-2, d                      # the previous coarse inverse was kept
+    assert abs(x @ Mz - z @ Mx) <= 1e-10 * abs(x @ Mx)
+    assert x @ Mx > 0 and z @ Mz > 0
+    # large change: a damaged band across the specimen rebuilds it
+    a2 = a1.copy()
+    y = P.model.X[:, 1]
+    a2[np.abs(y - 0.5) < 0.1] = 1.0
+    Mx, _ = precond(a2, s)
+    Fx, _ = precond(a2)
+    assert np.linalg.norm(Mx - Fx) <= 1e-12 * np.linalg.norm(Fx)
+    s.close()
+
+
 @pytest.mark.parametrize("model", ["AT1", "AT2"])
 def test_damage_hessian_and_gradient_match(model):
     nx, ny = 96, 80
