@@ -320,6 +320,23 @@ int fracture_level_shape(fracture_t h, int level, int* nx, int* ny, int* nz);
                                        calibration kernel for HBM counters) */
 int fracture_time_kernel(fracture_t h, int kernel, int reps, double* avg_ms, double* bytes);
 
+/* Live timing of a kernel inside the solves (measurement hook).  After
+   fracture_kernel_timing(h, FRACTURE_KERNEL_SMOOTH, capacity) every fifth
+   float64 finest-level Chebyshev step of the multigrid V-cycles (a sample
+   that cycles through the four steps of a V-cycle), whatever solve launches
+   them, is bracketed by HIP events on the instance's stream, up to
+   `capacity` steps, and each adds its algorithmic bytes (coefficients 8 B,
+   b, x_in, a distinct d_in, x_out, d_out at 8 B per DOF, per node); the
+   durations include the dispatch around each kernel.  While it is active the V-cycles are launched
+   eagerly (a recorded graph replay cannot hold the events).  The events are
+   created here, up to 32768 steps; capacity 0 ends the timing.  Only
+   FRACTURE_KERNEL_SMOOTH is accepted (else FRACTURE_EINVAL).
+   fracture_kernel_timing_read waits for the recorded steps, returns their
+   count, summed duration (ms) and summed algorithmic bytes, and clears the
+   record (the capacity stays). */
+int fracture_kernel_timing(fracture_t h, int kernel, int capacity);
+int fracture_kernel_timing_read(fracture_t h, int* count, double* total_ms, double* total_bytes);
+
 const char* fracture_strerror(int code);
 
 /* Release the handle (host state only; the caller frees the workspace). */

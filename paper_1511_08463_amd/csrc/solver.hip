@@ -37,6 +37,10 @@ constexpr int DENSE_MAX = 1024;   // largest coarsest-level system inverted dens
 // The coarsest system is re-assembled and re-inverted once its coefficients
 // drift by more than this relative amount from those of the current inverse.
 constexpr double COARSE_DRIFT = 0.02;
+constexpr int KT_MAX = 1 << 15;   // most finest-level steps timed at once
+// every KT_STRIDE-th finest-level step is timed: a stride prime to the four
+// steps of a V-cycle samples each kind alike, with a fifth of the events
+constexpr int KT_STRIDE = 5;
 constexpr double ARMIJO_SIGMA = 1e-4;
 constexpr int MAX_HALVINGS = 20;
 constexpr int MAX_GRAPHS = 16;
@@ -123,6 +127,10 @@ struct fracture {
   // host side
   double* hS = nullptr;  // pinned copy of the scalar array (+ two lagged-read slots)
   hipEvent_t ev[10] = {};  // 0..7 timing, 8..9 lagged scalar reads
+  // live timing of the finest-level Chebyshev steps (fracture_kernel_timing)
+  hipEvent_t* kt_ev = nullptr;
+  int kt_cap = 0, kt_used = 0, kt_seen = 0;
+  double kt_bytes = 0.0;
   double load = 0.0;
   double bnorm = 0.0;
   Load2D load2d{};
@@ -500,6 +508,26 @@ LevelBufs<float> bufs<float>(fracture* h, int l) {
   return {v.b32, v.xa32, v.xb32, v.d32, v.r32, l == 0 ? h->alpha32 : v.abar32};
 }
 
+// One Jacobi-Chebyshev step of the V-cycle; while fracture_kernel_timing is
+// active every KT_STRIDE-th float64 step on the finest level is bracketed by
+// events, with its algorithmic bytes (coefficients 8, b, x_in, a distinct
+// d_in, x_out, d_out per node).
+template <class T>
+void smooth_step(fracture* h, const Grid& g, bool fine, const T* coef, double kell, const T* x_in,
+                 T* x_out, const T* b, const T* din, T* dout, double cd, double cr) {
+  const bool timed = fine && sizeof(T) == sizeof(double) && h->kt_cap > 0 &&
+                     (h->kt_seen++ % KT_STRIDE == 0) && h->kt_used < h->kt_cap;
+  if (timed) (void)hipEventRecord(h->kt_ev[2 * h->kt_used], h->st);
+  launch_smooth2d<T>(h->st, g, h->mat, fine, coef, kell, x_in, x_out, b, din, dout, cd, cr);
+  if (timed) {
+    (void)hipEventRecord(h->kt_ev[2 * h->kt_used + 1], h->st);
+    const double dv = 8.0 * g.dim;
+    h->kt_bytes += (double)g.N * (8.0 + dv + (x_in ? dv : 0.0) + (din && din != x_in ? dv : 0.0) +
+                                  dv + (dout ? dv : 0.0));
+    ++h->kt_used;
+  }
+}
+
 // z = V-cycle(b) on level l; returns the buffer holding the result (final_out
 // when given: the last post-smoothing step writes there).  The cycle is
 // symmetric: pre- and post-smoothing apply the same Chebyshev polynomial, so
@@ -543,8 +571,7 @@ T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr, bool first_d
     }
     const T* din = s == 0 ? nullptr : (s == 1 ? cur : v.d);
     T* dout = (s < k - 1) ? v.d : nullptr;
-    launch_smooth2d<T>(h->st, g, h->mat, fine, v.coef, kell, cur, out, b, din, dout,
-                       h->cheb_cd[s], h->cheb_cr[s]);
+    smooth_step<T>(h, g, fine, v.coef, kell, cur, out, b, din, dout, h->cheb_cd[s], h->cheb_cr[s]);
     cur = out;
   }
   // residual, restriction, coarse correction
@@ -567,8 +594,7 @@ T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr, bool first_d
     if (s == k - 1 && final_out) out = final_out;
     const T* din = s == 0 ? nullptr : v.d;
     T* dout = (s < k - 1) ? v.d : nullptr;
-    launch_smooth2d<T>(h->st, g, h->mat, fine, v.coef, kell, cur, out, b, din, dout,
-                       h->cheb_cd[s], h->cheb_cr[s]);
+    smooth_step<T>(h, g, fine, v.coef, kell, cur, out, b, din, dout, h->cheb_cd[s], h->cheb_cr[s]);
     cur = out;
   }
   return cur;
@@ -585,7 +611,8 @@ double* vcycle(fracture* h, int l, const double* b) { return vcycle_t<double>(h,
 // order).
 template <class F>
 void* graphed(fracture* h, int op, const void* a, const void* b, F&& body) {
-  if (!h->p.use_graphs || h->capturing) return body();
+  // eager while the finest-level steps are timed (no events inside a replay)
+  if (!h->p.use_graphs || h->capturing || h->kt_cap > 0) return body();
   for (const Captured& c : h->graphs)
     if (c.op == op && c.a == a && c.b == b) {
       if (hipGraphLaunch(c.exec, h->st) != hipSuccess) h->graph_error = true;
@@ -1693,9 +1720,55 @@ const char* fracture_strerror(int code) {
   }
 }
 
+static void kt_release(fracture* h) {
+  if (h->kt_ev)
+    for (int q = 0; q < 2 * h->kt_cap; ++q)
+      if (h->kt_ev[q]) (void)hipEventDestroy(h->kt_ev[q]);
+  delete[] h->kt_ev;
+  h->kt_ev = nullptr;
+  h->kt_cap = h->kt_used = h->kt_seen = 0;
+  h->kt_bytes = 0.0;
+}
+
+int fracture_kernel_timing(fracture_t h, int kernel, int capacity) {
+  if (!h || capacity < 0 || capacity > KT_MAX) return FRACTURE_EINVAL;
+  if (capacity > 0 && kernel != FRACTURE_KERNEL_SMOOTH) return FRACTURE_EINVAL;
+  if (h->st) HIPCHK(hipStreamSynchronize(h->st));
+  kt_release(h);
+  if (capacity == 0) return FRACTURE_OK;
+  h->kt_ev = new (std::nothrow) hipEvent_t[2 * capacity]();
+  if (!h->kt_ev) return FRACTURE_ENOMEM;
+  h->kt_cap = capacity;
+  for (int q = 0; q < 2 * capacity; ++q)
+    if (hipEventCreate(&h->kt_ev[q]) != hipSuccess) {
+      h->kt_ev[q] = nullptr;
+      kt_release(h);
+      return FRACTURE_EDEVICE;
+    }
+  return FRACTURE_OK;
+}
+
+int fracture_kernel_timing_read(fracture_t h, int* count, double* total_ms, double* total_bytes) {
+  if (!h || !count || !total_ms || !total_bytes) return FRACTURE_EINVAL;
+  double ms = 0.0;
+  if (h->kt_used > 0) HIPCHK(hipEventSynchronize(h->kt_ev[2 * h->kt_used - 1]));
+  for (int q = 0; q < h->kt_used; ++q) {
+    float e = 0.0f;
+    HIPCHK(hipEventElapsedTime(&e, h->kt_ev[2 * q], h->kt_ev[2 * q + 1]));
+    ms += e;
+  }
+  *count = h->kt_used;
+  *total_ms = ms;
+  *total_bytes = h->kt_bytes;
+  h->kt_used = 0;
+  h->kt_bytes = 0.0;
+  return FRACTURE_OK;
+}
+
 void fracture_destroy(fracture_t h) {
   if (!h) return;
   if (h->st) (void)hipStreamSynchronize(h->st);
+  kt_release(h);
   for (Captured& c : h->graphs) (void)hipGraphExecDestroy(c.exec);
   h->graphs.clear();
   if (h->cap) (void)hipStreamDestroy(h->cap);

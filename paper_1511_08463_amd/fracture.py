@@ -95,7 +95,8 @@ EXPORTS = [
     "fracture_set_load", "fracture_solve_step", "fracture_solve_steps", "fracture_energy",
     "fracture_get_state", "fracture_set_state", "fracture_apply", "fracture_update_coefficients",
     "fracture_gradient", "fracture_levels", "fracture_level_shape", "fracture_strerror",
-    "fracture_time_kernel", "fracture_set_monitor", "fracture_destroy",
+    "fracture_time_kernel", "fracture_kernel_timing", "fracture_kernel_timing_read",
+    "fracture_set_monitor", "fracture_destroy",
 ]
 
 MONITOR_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double)
@@ -136,6 +137,8 @@ def load_library(path=LIB_PATH):
         "fracture_level_shape": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int)]),
         "fracture_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "fracture_time_kernel": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, dp, dp]),
+        "fracture_kernel_timing": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
+        "fracture_kernel_timing_read": (ctypes.c_int, [vp, P(ctypes.c_int), dp, dp]),
         "fracture_set_monitor": (ctypes.c_int, [vp, MONITOR_FN, vp]),
         "fracture_destroy": (None, [vp]),
     }
@@ -283,6 +286,19 @@ def fracture_time_kernel(h, kernel, reps):
     _check(load_library().fracture_time_kernel(h, kernel, reps, ctypes.byref(ms), ctypes.byref(b)),
            "fracture_time_kernel")
     return ms.value, b.value
+
+
+def fracture_kernel_timing(h, kernel, capacity):
+    _check(load_library().fracture_kernel_timing(h, kernel, capacity), "fracture_kernel_timing")
+
+
+def fracture_kernel_timing_read(h):
+    """(count, total_ms, total_bytes) of the timed launches since the last read."""
+    n, ms, b = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+    _check(load_library().fracture_kernel_timing_read(h, ctypes.byref(n), ctypes.byref(ms),
+                                                      ctypes.byref(b)),
+           "fracture_kernel_timing_read")
+    return n.value, ms.value, b.value
 
 
 def fracture_set_monitor(h, fn):
