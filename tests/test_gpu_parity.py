@@ -141,6 +141,39 @@ def test_preconditioner_is_symmetric_positive():
     s.close()
 
 
+def test_live_kernel_timing_leaves_results_unchanged():
+    """fracture_kernel_timing brackets every fifth finest-level Chebyshev step
+    with events and sums its algorithmic bytes (56 or 72 B per node here);
+    the load step is bitwise the one without timing."""
+    p = workloads.tension(96, 0.06, "AT1", nx=96, ny=80)
+    notch = workloads.notch_mask_2d(96, 80, 0.5, 0.3)
+    states = []
+    for timed in (False, True):
+        s = _solver(p, notch, newton=1)
+        if timed:
+            fracture.fracture_kernel_timing(s.h, fracture.FRACTURE_KERNEL_SMOOTH, 4096)
+        for t in (0.5, 1.0):
+            s.set_load(t)
+            s.solve_step()
+        if timed:
+            n, ms, b = fracture.fracture_kernel_timing_read(s.h)
+            N = 97 * 81
+            assert n > 10 and ms > 0
+            assert 56 * N * n - 1 <= b <= 72 * N * n + 1
+            assert fracture.fracture_kernel_timing_read(s.h)[0] == 0     # cleared
+            fracture.fracture_kernel_timing(s.h, fracture.FRACTURE_KERNEL_SMOOTH, 0)
+        states.append(s.state())
+        s.close()
+    for a, b in zip(*states):
+        assert np.array_equal(a, b)
+    with pytest.raises(fracture.FractureError):
+        s2 = _solver(p, notch)
+        try:
+            fracture.fracture_kernel_timing(s2.h, fracture.FRACTURE_KERNEL_APPLY, 16)
+        finally:
+            s2.close()
+
+
 def test_coarsest_inverse_refreshed_on_drift():
     """The coarsest dense inverse is rebuilt only when a coarsest coefficient
     moves by more than 2%: a small damage change keeps the previous inverse
