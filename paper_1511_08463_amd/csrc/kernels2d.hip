@@ -305,6 +305,45 @@ void launch_restrict_smooth2d(hipStream_t st, const Grid& gf, const Grid& gc, co
                      xout, dout, T(cr));
 }
 
+// The prolongation x += P x_c of a coarse level (node kernels, element
+// coefficients) folded into the first post-smoothing step, which starts from
+// it: x_out = x + P x_c + cr D^{-1} (b - K (x + P x_c)), d_out = that step.
+// Same arithmetic as k_prolong2d followed by k_node2d<SMOOTH> with x and no
+// d_in; x + P x_c itself is not stored.
+template <class T>
+__global__ __launch_bounds__(NB) void k_prol_smooth2d(Grid g, Grid gc, Mat m,
+                                                      const T* __restrict__ coef, T kell,
+                                                      const T* __restrict__ x,
+                                                      const T* __restrict__ xc,
+                                                      T* __restrict__ y, const T* __restrict__ b,
+                                                      T* __restrict__ dout, T cr) {
+  const int nbx = gridDim.x, total = gridDim.x * gridDim.y;
+  const int tt = xcd_tile(blockIdx.x + nbx * blockIdx.y, total);
+  const int i = (tt % nbx) * NB_X + threadIdx.x;
+  const int j = (tt / nbx) * NB_Y + threadIdx.y;
+  if (i > g.nx || j > g.ny) return;
+  const int N = g.N, n = i + (g.nx + 1) * j;
+  T c[6];
+  coef6<false>(g, coef, kell, i, j, c);
+  T fx, fy, dx, dy;
+  node_force2d<true, true, false, true>(g, m, c, x, x + N, i, j, fx, fy, dx, dy, &gc, xc);
+  T px, py;
+  prol_value(g, gc, xc, i, j, px, py);
+  double acc = 0.0;
+  node_out2d<M_SMOOTH, R_NONE>(g, i, j, fx, fy, dx, dy, x[n] + px, x[n + N] + py, y, b,
+                               (const T*)nullptr, dout, T(0), cr, 1, acc);
+}
+
+bool node_level2d(const Grid& g) { return g.dim == 2 && !use_col2d(g); }
+
+template <class T>
+void launch_prol_smooth2d(hipStream_t st, const Grid& g, const Grid& gc, const Mat& m,
+                          const T* coef, double kell, const T* x, const T* xc, T* y, const T* b,
+                          T* dout, double cr) {
+  hipLaunchKernelGGL((k_prol_smooth2d<T>), node_grid2(g), dim3(NB_X, NB_Y), 0, st, g, gc, m, coef,
+                     T(kell), x, xc, y, b, dout, T(cr));
+}
+
 // x_f += P x_c.
 template <class T>
 __global__ __launch_bounds__(NB) void k_prolong2d(Grid gf, Grid gc, const T* __restrict__ xc,
@@ -332,6 +371,9 @@ void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* x
   template void launch_restrict2d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);        \
   template void launch_restrict_smooth2d<T>(hipStream_t, const Grid&, const Grid&, const Mat&,     \
                                             const T*, double, const T*, T*, T*, T*, double);       \
+  template void launch_prol_smooth2d<T>(hipStream_t, const Grid&, const Grid&, const Mat&,         \
+                                        const T*, double, const T*, const T*, T*, const T*, T*,   \
+                                        double);                                                  \
   template void launch_prolong2d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);
 INST(float)
 INST(double)

@@ -88,10 +88,23 @@ __device__ __forceinline__ void coef6(const Grid& g, const T* __restrict__ coef,
 // EIG (thermal shock, finest level): the forces of the effective strain
 // eps(x) - eps0, i.e. K x - f with f the eigenstrain load of eq.
 // (energytshock).
-template <bool HASX, bool DIAG, bool EIG = false, class T>
+// PROL: x is taken as x + P x_c, the coarse correction of level gc
+// interpolated on the fly (prol_value), as after the V-cycle's prolongation.
+template <class T>
+__device__ __forceinline__ void prol_value(const Grid& gf, const Grid& gc, const T* __restrict__ xc,
+                                           int i, int j, T& px, T& py) {
+  const int Wc = gc.nx + 1;
+  const int a = (i >> 1) + Wc * (j >> 1), b = ((i + 1) >> 1) + Wc * ((j + 1) >> 1);
+  px = fixed_x2(gf, i, j) ? T(0) : T(0.5) * (xc[a] + xc[b]);
+  py = fixed_y2(gf, i, j) ? T(0) : T(0.5) * (xc[gc.N + a] + xc[gc.N + b]);
+}
+
+template <bool HASX, bool DIAG, bool EIG = false, bool PROL = false, class T>
 __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const T c[6],
                                              const T* __restrict__ ux, const T* __restrict__ uy,
-                                             int i, int j, T& fx, T& fy, T& dx, T& dy) {
+                                             int i, int j, T& fx, T& fy, T& dx, T& dy,
+                                             const Grid* gc = nullptr,
+                                             const T* __restrict__ xc = nullptr) {
   const int W = g.nx + 1, n = i + W * j;
   const bool L = i > 0, R = i < g.nx, D = j > 0, U = j < g.ny;
   const T ihx = T(1.0 / g.hx), ihy = T(1.0 / g.hy), area = T(0.5 * g.hx * g.hy);
@@ -107,6 +120,16 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
     if (L) { wx = ux[n - 1]; wy = uy[n - 1]; }
     if (L && D) { swx = ux[n - 1 - W]; swy = uy[n - 1 - W]; }
     if (D) { sx = ux[n - W]; sy = uy[n - W]; }
+  }
+  if (PROL) {
+    T px, py;
+    prol_value(g, *gc, xc, i, j, px, py); cx += px; cy += py;
+    if (R) { prol_value(g, *gc, xc, i + 1, j, px, py); ex += px; ey += py; }
+    if (R && U) { prol_value(g, *gc, xc, i + 1, j + 1, px, py); nex += px; ney += py; }
+    if (U) { prol_value(g, *gc, xc, i, j + 1, px, py); nnx += px; nny += py; }
+    if (L) { prol_value(g, *gc, xc, i - 1, j, px, py); wx += px; wy += py; }
+    if (L && D) { prol_value(g, *gc, xc, i - 1, j - 1, px, py); swx += px; swy += py; }
+    if (D) { prol_value(g, *gc, xc, i, j - 1, px, py); sx += px; sy += py; }
   }
   fx = fy = dx = dy = T(0);
   const T hxx = ihx * ihx, hyy = ihy * ihy;

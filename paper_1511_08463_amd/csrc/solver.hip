@@ -587,14 +587,22 @@ T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr, bool first_d
   else
     launch_restrict2d<T>(h->st, g, h->lv[l + 1].g, v.r, c.b);
   T* xc = vcycle_t<T>(h, l + 1, c.b, nullptr, fuse);
-  launch_prolong2d<T>(h->st, g, h->lv[l + 1].g, xc, cur);
+  // on a coarse level smoothed by the per-node kernels the prolongation rides
+  // in the first post-smoothing step
+  const bool prol_fused = !fine && node_level2d(g);
+  if (!prol_fused) launch_prolong2d<T>(h->st, g, h->lv[l + 1].g, xc, cur);
   // post-smoothing (same polynomial: the V-cycle is symmetric)
   for (int s = 0; s < k; ++s) {
     T* out = (cur == v.xa) ? v.xb : v.xa;
     if (s == k - 1 && final_out) out = final_out;
     const T* din = s == 0 ? nullptr : v.d;
     T* dout = (s < k - 1) ? v.d : nullptr;
-    smooth_step<T>(h, g, fine, v.coef, kell, cur, out, b, din, dout, h->cheb_cd[s], h->cheb_cr[s]);
+    if (s == 0 && prol_fused)
+      launch_prol_smooth2d<T>(h->st, g, h->lv[l + 1].g, h->mat, v.coef, kell, cur, xc, out, b, dout,
+                              h->cheb_cr[0]);
+    else
+      smooth_step<T>(h, g, fine, v.coef, kell, cur, out, b, din, dout, h->cheb_cd[s],
+                     h->cheb_cr[s]);
     cur = out;
   }
   return cur;
