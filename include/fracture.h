@@ -180,6 +180,20 @@ typedef struct {
   double thermal_dT;        /* FRACTURE_LOAD_THERMAL_SHOCK_2D: shock intensity
                                beta * DT of the imposed temperature; finite,
                                any sign (negative heats)                      */
+  int deflate;              /* 1: deflate the elastic CG of the sweeps by the
+                               rigid modes of each undamaged fragment (the
+                               per-piece near-null vectors Sec. 3.1 names as a
+                               possible improvement; deflated CG of Saad,
+                               Yeung, Erhel and Guyomarc'h, 2000), formed
+                               anew from alpha at every elastic solve.  2D and
+                               FRACTURE_FP64 only (else FRACTURE_EINVAL);
+                               the Newton phase is unchanged.  Default 0.    */
+  double deflate_theta;     /* a node is undamaged when alpha < this; in
+                               (0, 1]; default 0.5                            */
+  int deflate_min_nodes;    /* smallest fragment kept, in nodes (>= 1);
+                               default 64                                     */
+  int deflate_max_fragments;/* most fragments kept (1..8), the largest first;
+                               default 8                                      */
 } fracture_params;
 
 /* Fill *p with the documented defaults for a 2D tension problem on an
@@ -336,6 +350,23 @@ int fracture_time_kernel(fracture_t h, int kernel, int reps, double* avg_ms, dou
    record (the capacity stays). */
 int fracture_kernel_timing(fracture_t h, int kernel, int capacity);
 int fracture_kernel_timing_read(fracture_t h, int* count, double* total_ms, double* total_bytes);
+
+/* Crack-aware deflation (params.deflate = 1, else FRACTURE_EINVAL; 2D).
+   Fragments are the connected components of the nodes with alpha <
+   deflate_theta in the graph of the element edges; those of at least
+   deflate_min_nodes nodes are kept, at most deflate_max_fragments of them,
+   the largest first, ties by the smaller least node index.
+   fracture_fragments labels the current alpha: d_fid (device, N ints)
+   receives each node's fragment index, or -1 (damaged, or in a component
+   not kept); *nfrag (host) the number kept.
+   fracture_deflation_matrix forms E = W^T K(alpha) W (Sec. 3.1, eq.
+   (elasticity)) for the current alpha; column 3f + t of W is, on fragment
+   f, the x translation (t = 0), the y translation (t = 1) or the rotation
+   (-(y - ly/2), x - lx/2) * 2 / max(lx, ly) (t = 2), zero elsewhere and on
+   Dirichlet DOFs.  E (host, row-major m x m, room for 24 x 24 doubles)
+   receives it and *m = 3 nfrag.  Both wait for the instance's stream. */
+int fracture_fragments(fracture_t h, int* nfrag, int* d_fid);
+int fracture_deflation_matrix(fracture_t h, int* m, double* E);
 
 const char* fracture_strerror(int code);
 

@@ -59,6 +59,19 @@ static_assert(S_JHI == S_JLO + 1, "band slots must be adjacent");
 enum { C_SLOTS = 18 };
 
 // A structured level: (nx+1)(ny+1)[(nz+1)] nodes.
+// Crack-aware deflation of the elastic CG (2D): at most DFL_FMAX fragments,
+// three rigid modes each; the int metadata array holds the fragment count,
+// the candidate count, the kept roots and the candidate list.
+constexpr int DFL_FMAX = 8;
+constexpr int DFL_M = 3 * DFL_FMAX;
+constexpr int DFL_LIST = 256;
+enum { DFL_META_NFRAG = 0, DFL_META_NCAND = 1, DFL_META_ROOTS = 2, DFL_META_LIST = 16,
+       DFL_META_INTS = DFL_META_LIST + DFL_LIST };
+static_assert(DFL_META_ROOTS + DFL_FMAX <= DFL_META_LIST, "deflation metadata layout");
+// a mode whose Cholesky pivot falls below this fraction of E's largest
+// diagonal entry is dropped
+constexpr double DFL_PIVOT = 1e-12;
+
 struct Grid {
   int nx, ny, nz;
   double hx, hy, hz;

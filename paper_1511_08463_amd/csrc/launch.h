@@ -183,4 +183,16 @@ void launch_minres_update_s(hipStream_t st, const Seg& sg, const double* S, cons
 void launch_dot_seg(hipStream_t st, const Seg& sg, const double* a, const double* b, Red r);
 void launch_from_float(hipStream_t st, int64_t n, const float* e, double* x, double scale);
 
+
+// crack-aware deflation of the elastic CG (deflate.hip)
+int dfl_part_blocks(int64_t N);
+void launch_fragments2d(hipStream_t st, const Grid& g, const double* alpha, double theta,
+                        int min_nodes, int fmax, int* parent, int* label, int* fid, int* meta);
+void launch_dfl_mode(hipStream_t st, const Grid& g, const int* fid, int k, double* w);
+void launch_dfl_add(hipStream_t st, const Grid& g, const int* fid, const double* mu, double* x,
+                    double sign);
+void launch_dfl_wtv(hipStream_t st, const Grid& g, const int* fid, const double* v, double* part,
+                    int col, double* E, const double* Einv, double* mu);
+void launch_dfl_invert(hipStream_t st, const double* E, double* Einv, const int* meta);
+
 }  // namespace frac

@@ -100,6 +100,9 @@ struct fracture {
          *alpha_entry = nullptr;
   // elastic PCG
   double *x = nullptr, *r = nullptr, *pv = nullptr, *q = nullptr;
+  // crack-aware deflation of the elastic CG (params.deflate)
+  int *dfl_parent = nullptr, *dfl_label = nullptr, *dfl_fid = nullptr, *dfl_meta = nullptr;
+  double *dfl_part = nullptr, *dfl_E = nullptr, *dfl_Einv = nullptr, *dfl_mu = nullptr;
   // damage VI
   double *w2 = nullptr, *F = nullptr, *phi = nullptr, *hdinv = nullptr, *atil = nullptr;
   double *vd = nullptr, *vr = nullptr, *vz = nullptr, *vp = nullptr, *vq = nullptr,
@@ -194,6 +197,12 @@ int validate(const fracture_params* p) {
   if (p->newton_forcing_mode != 0 && p->newton_forcing_mode != 1) return FRACTURE_EINVAL;
   if (!(p->pcg_reduction >= 0 && p->pcg_reduction < 1)) return FRACTURE_EINVAL;
   if (!(p->newton_stall > 0 && p->newton_stall <= 1)) return FRACTURE_EINVAL;
+  if (p->deflate != 0 && p->deflate != 1) return FRACTURE_EINVAL;
+  if (p->deflate &&
+      (p->dim != 2 || p->precision != FRACTURE_FP64 || !(p->deflate_theta > 0 && p->deflate_theta <= 1) ||
+       p->deflate_min_nodes < 1 || p->deflate_max_fragments < 1 ||
+       p->deflate_max_fragments > DFL_FMAX))
+    return FRACTURE_EINVAL;
   if ((int64_t)(p->nx + 1) * (p->ny + 1) * (p->dim == 3 ? p->nz + 1 : 1) > (int64_t)1 << 29)
     return FRACTURE_EINVAL;
   return FRACTURE_OK;
@@ -333,6 +342,16 @@ size_t layout(const fracture_params* p, fracture* h, void* ws) {
   if (vec_blocks(n2) > pn) pn = vec_blocks(n2);
   t->part_n = pn;
   t->part = c.take<double>(pn * C_SLOTS);
+  if (p->deflate) {
+    t->dfl_parent = c.take<int>(N);
+    t->dfl_label = c.take<int>(N);
+    t->dfl_fid = c.take<int>(N);
+    t->dfl_meta = c.take<int>(DFL_META_INTS);
+    t->dfl_part = c.take<double>((size_t)dfl_part_blocks(N) * DFL_M);
+    t->dfl_E = c.take<double>(DFL_M * DFL_M);
+    t->dfl_Einv = c.take<double>(DFL_M * DFL_M);
+    t->dfl_mu = c.take<double>(DFL_M);
+  }
   t->S = c.take<double>(S_COUNT);
   t->nlev = L;
   t->dense_n = dn;
@@ -680,6 +699,49 @@ double sweep_tol(const fracture* h, double tol, double r0) {
   return tol;
 }
 
+// Crack-aware deflation: label the fragments of the current alpha and form
+// E = W^T K W (one operator action per mode, through pv and q) and its
+// inverse on the device.  *m receives the number of modes (0: no fragment).
+int dfl_setup(fracture* h, int* m) {
+  const Grid& g = h->lv[0].g;
+  hipStream_t st = h->st;
+  launch_fragments2d(st, g, h->alpha, h->p.deflate_theta, h->p.deflate_min_nodes,
+                     h->p.deflate_max_fragments, h->dfl_parent, h->dfl_label, h->dfl_fid,
+                     h->dfl_meta);
+  int nf = 0;
+  HIPCHK(hipMemcpyAsync(&nf, h->dfl_meta + DFL_META_NFRAG, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *m = 3 * nf;
+  Red none{};
+  for (int k = 0; k < *m; ++k) {
+    launch_dfl_mode(st, g, h->dfl_fid, k, h->pv);
+    launch_apply2d<double>(st, g, h->mat, true, h->alpha, h->p.k_ell, h->pv, h->q, nullptr, 1, 0,
+                           none);
+    launch_dfl_wtv(st, g, h->dfl_fid, h->q, h->dfl_part, k, h->dfl_E, nullptr, nullptr);
+  }
+  if (*m) launch_dfl_invert(st, h->dfl_E, h->dfl_Einv, h->dfl_meta);
+  return hip_ok(hipGetLastError());
+}
+
+// v -= W E^{-1} W^T K z (sign -1), the deflated CG direction correction, or
+// x += W E^{-1} W^T r (sign +1, with Kz = nullptr: r itself).
+void dfl_correct(fracture* h, const double* z, double* v, double sign) {
+  const Grid& g = h->lv[0].g;
+  const double* w = z;
+  if (sign < 0) {
+    Red none{};
+    launch_apply2d<double>(h->st, g, h->mat, true, h->alpha, h->p.k_ell, z, h->q, nullptr, 1, 0,
+                           none);
+    w = h->q;
+  }
+  launch_dfl_wtv(h->st, g, h->dfl_fid, w, h->dfl_part, -1, nullptr, h->dfl_Einv, h->dfl_mu);
+  launch_dfl_add(h->st, g, h->dfl_fid, h->dfl_mu, v, sign);
+}
+
+// Preconditioned CG on the elastic system, warm-started from u.  With
+// params.deflate, deflated CG (Saad, Yeung, Erhel and Guyomarc'h, 2000):
+// the start is corrected by W E^{-1} W^T r and every direction loses
+// W E^{-1} W^T K z, which keeps W^T r = 0 at every iterate.
 int pcg(fracture* h, double tol, int* iters) {
   const Grid& g = h->lv[0].g;
   const int64_t n2 = h->n2;
@@ -695,9 +757,25 @@ int pcg(fracture* h, double tol, int* iters) {
   *iters = 0;
   tol = sweep_tol(h, tol, std::sqrt(rr));
   if (std::sqrt(rr) <= tol) return FRACTURE_OK;
+  int m = 0;
+  if (h->p.deflate) {
+    rc = dfl_setup(h, &m);
+    if (rc) return rc;
+  }
+  if (m) {
+    dfl_correct(h, h->r, h->x, 1.0);
+    launch_resid2d(st, gl, h->mat, true, h->alpha, h->p.k_ell, h->x, h->r, nullptr, true,
+                   red(h, 0, S_RR));
+    rc = read_scalars(h);
+    if (rc) return rc;
+    rr = h->hS[S_RR];
+    if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
+    if (std::sqrt(rr) <= tol) return FRACTURE_OK;
+  }
   double* z = vcycle0(h, h->r);
   launch_dot(st, n2, h->r, z, red(h, 1, S_RZ));
   HIPCHK(hipMemcpyAsync(h->pv, z, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (m) dfl_correct(h, z, h->pv, -1.0);
   for (int it = 1; it <= h->p.max_pcg; ++it) {
     launch_apply2d(st, g, h->mat, true, h->alpha, h->p.k_ell, h->pv, h->q, nullptr, 1, 1,
                    red(h, 2, S_PQ, P_CG_ALPHA));
@@ -711,6 +789,7 @@ int pcg(fracture* h, double tol, int* iters) {
     z = vcycle0(h, h->r);
     launch_dot(st, n2, h->r, z, red(h, 4, S_RZNEW, P_CG_BETA));
     launch_xpby(st, n2, z, h->pv, h->S);
+    if (m) dfl_correct(h, z, h->pv, -1.0);
   }
   return FRACTURE_ENOTCONV;
 }
@@ -1380,6 +1459,10 @@ void fracture_default_params(fracture_params* p, int nx, int ny) {
   p->newton_forcing_mode = 1;
   p->pcg_reduction = 0.01;
   p->newton_stall = 0.9;
+  p->deflate = 0;
+  p->deflate_theta = 0.5;
+  p->deflate_min_nodes = 64;
+  p->deflate_max_fragments = DFL_FMAX;
 }
 
 size_t fracture_workspace_bytes(const fracture_params* p) {
@@ -1637,6 +1720,29 @@ int fracture_gradient(fracture_t h, double* d_Eu, double* d_Ea) {
     HIPCHK(hipMemcpyAsync(d_Ea, h->F, h->N * sizeof(double), hipMemcpyDeviceToDevice, h->st));
   }
   return hip_ok(hipStreamSynchronize(h->st));
+}
+
+int fracture_fragments(fracture_t h, int* nfrag, int* d_fid) {
+  if (!h || !nfrag || !d_fid || !h->p.deflate) return FRACTURE_EINVAL;
+  const Grid& g = h->lv[0].g;
+  launch_fragments2d(h->st, g, h->alpha, h->p.deflate_theta, h->p.deflate_min_nodes,
+                     h->p.deflate_max_fragments, h->dfl_parent, h->dfl_label, d_fid, h->dfl_meta);
+  HIPCHK(hipMemcpyAsync(nfrag, h->dfl_meta + DFL_META_NFRAG, sizeof(int), hipMemcpyDeviceToHost,
+                        h->st));
+  return hip_ok(hipStreamSynchronize(h->st));
+}
+
+int fracture_deflation_matrix(fracture_t h, int* m, double* E) {
+  if (!h || !m || !E || !h->p.deflate) return FRACTURE_EINVAL;
+  int rc = dfl_setup(h, m);
+  if (rc) return rc;
+  std::vector<double> full(DFL_M * DFL_M);
+  HIPCHK(hipMemcpyAsync(full.data(), h->dfl_E, full.size() * sizeof(double), hipMemcpyDeviceToHost,
+                        h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  for (int i = 0; i < *m; ++i)
+    for (int j = 0; j < *m; ++j) E[i * *m + j] = full[i * DFL_M + j];
+  return FRACTURE_OK;
 }
 
 int fracture_levels(fracture_t h, int* nlevels) {

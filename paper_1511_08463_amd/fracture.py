@@ -73,6 +73,8 @@ class fracture_params(ctypes.Structure):
         ("pcg_reduction", ctypes.c_double), ("newton_stall", ctypes.c_double),
         ("omega_auto", ctypes.c_int),
         ("thermal_dT", ctypes.c_double),
+        ("deflate", ctypes.c_int), ("deflate_theta", ctypes.c_double),
+        ("deflate_min_nodes", ctypes.c_int), ("deflate_max_fragments", ctypes.c_int),
     ]
 
 
@@ -96,7 +98,8 @@ EXPORTS = [
     "fracture_get_state", "fracture_set_state", "fracture_apply", "fracture_update_coefficients",
     "fracture_gradient", "fracture_levels", "fracture_level_shape", "fracture_strerror",
     "fracture_time_kernel", "fracture_kernel_timing", "fracture_kernel_timing_read",
-    "fracture_set_monitor", "fracture_destroy",
+    "fracture_set_monitor", "fracture_fragments", "fracture_deflation_matrix",
+    "fracture_destroy",
 ]
 
 MONITOR_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double)
@@ -140,6 +143,8 @@ def load_library(path=LIB_PATH):
         "fracture_kernel_timing": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
         "fracture_kernel_timing_read": (ctypes.c_int, [vp, P(ctypes.c_int), dp, dp]),
         "fracture_set_monitor": (ctypes.c_int, [vp, MONITOR_FN, vp]),
+        "fracture_fragments": (ctypes.c_int, [vp, P(ctypes.c_int), vp]),
+        "fracture_deflation_matrix": (ctypes.c_int, [vp, P(ctypes.c_int), dp]),
         "fracture_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -268,6 +273,23 @@ def fracture_gradient(h, Eu, Ea):
     _check(load_library().fracture_gradient(h, _ptr(Eu), _ptr(Ea)), "fracture_gradient")
 
 
+def fracture_fragments(h, fid):
+    """Fragments of the current alpha: their number; fid (device int32
+    tensor of N) receives each node's fragment index or -1."""
+    n = ctypes.c_int()
+    _check(load_library().fracture_fragments(h, ctypes.byref(n), _ptr(fid)), "fracture_fragments")
+    return n.value
+
+
+def fracture_deflation_matrix(h):
+    """E = W^T K W of the current fragments as an m x m float64 array."""
+    m = ctypes.c_int()
+    buf = (ctypes.c_double * (24 * 24))()
+    _check(load_library().fracture_deflation_matrix(h, ctypes.byref(m), buf),
+           "fracture_deflation_matrix")
+    return np.frombuffer(buf, dtype=np.float64)[: m.value * m.value].reshape(m.value, m.value).copy()
+
+
 def fracture_levels(h):
     n = ctypes.c_int()
     _check(load_library().fracture_levels(h, ctypes.byref(n)), "fracture_levels")
@@ -388,6 +410,16 @@ class Fracture:
         Ea = torch.empty(self.N, dtype=torch.float64, device=self.device)
         fracture_gradient(self.h, Eu, Ea)
         return Eu.cpu().numpy(), Ea.cpu().numpy()
+
+    def fragments(self):
+        """(nfrag, fid) of the current alpha (params.deflate = 1)."""
+        torch = self.torch
+        fid = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        n = fracture_fragments(self.h, fid)
+        return n, fid.cpu().numpy()
+
+    def deflation_matrix(self):
+        return fracture_deflation_matrix(self.h)
 
     def levels(self):
         return [fracture_level_shape(self.h, l) for l in range(fracture_levels(self.h))]
