@@ -302,6 +302,47 @@ def tshock(args, ratios=(2.0, 4.0, 8.0, 16.0), omegas=(0.8, 1.0, 1.2, 1.4, 1.6, 
             "sweeps": rows}
 
 
+def deflation(args):
+    """Crack-aware deflation of the elastic CG (Sec. 3.1) on a broken
+    specimen: the --n x --n tension square, AT1 damage profile (ell = 4h)
+    across the mid-line, alpha_prev = alpha, one plain ORAM load step at
+    t = 0.5 from u = 0, with and without deflation."""
+    import numpy as np
+    import torch
+    from paper_1511_08463_amd import fracture, workloads
+    n = args.n
+    p = workloads.tension(n, 4.0 / n, args.model)
+    y = np.repeat(np.arange(n + 1) / n, n + 1)
+    alpha = np.clip(1.0 - np.abs(y - 0.5) / (8.0 / n), 0.0, 1.0) ** 2
+    out, states = {}, {}
+    for dfl in (0, 1):
+        params = fracture.make_params(**p, newton=0, am_tol=args.am_tol, pcg_rtol=args.pcg_rtol,
+                                      vi_cg_rtol=args.vi_cg_rtol, max_am=args.max_am, deflate=dfl)
+        solver = fracture.Fracture(params, None, device="cuda:0")
+        solver.set_state(u=np.zeros(2 * alpha.size), alpha=alpha, alpha_prev=alpha)
+        solver.set_load(0.5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = solver.solve_step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        nf = solver.fragments()[0] if dfl else None
+        states[dfl] = solver.state()[0]
+        solver.close()
+        out["deflated" if dfl else "plain"] = {
+            "sweeps": st["sweeps"], "pcg_iters": st["pcg_iters"], "ms_pcg": round(st["ms_pcg"], 2),
+            "seconds": round(dt, 3), "fragments": nf, "converged": st["converged"]}
+        log(f"[deflation] deflate={dfl}: {st['sweeps']} sweeps, {st['pcg_iters']} PCG iterations, "
+            f"PCG {st['ms_pcg']:.1f} ms, step {dt:.2f} s, fragments {nf}")
+    d = np.linalg.norm(states[1] - states[0]) / np.linalg.norm(states[0])
+    out["rel_l2_u_deflated_vs_plain"] = float(d)
+    out["workload"] = (f"{n}x{n} tension square, {args.model}, ell = 4h, damage profile "
+                       f"(1 - |y - 1/2| / 2 ell)^2 across the mid-line (two fragments), "
+                       f"alpha_prev = alpha, one ORAM load step t = 0.5 from u = 0 to "
+                       f"||dalpha||inf < {args.am_tol:g}, PCG rtol {args.pcg_rtol:g}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,6 +390,11 @@ def main():
     ap.add_argument("--tshock-tau", type=float, default=2.0, help="last tau of the thermal shock")
     ap.add_argument("--tshock-max-am", type=int, default=20000, help="sweep limit per thermal shock step")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream sample")
+    ap.add_argument("--deflation", action="store_true",
+                    help="run only the deflated vs plain elastic CG comparison")
+    ap.add_argument("--no-deflation", action="store_true", help="skip the deflation sample")
+    ap.add_argument("--deflate", action="store_true",
+                    help="deflate the elastic CG of the headline legs by the fragments' rigid modes")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-omega", action="store_true", help="skip the omega = 1.4, 1.8 legs")
     ap.add_argument("--omega-steps", type=int, default=4,
@@ -390,6 +436,9 @@ def main():
     if args.tshock:
         print(json.dumps({"tshock": tshock(args)}), flush=True)
         return
+    if args.deflation:
+        print(json.dumps({"deflation": deflation(args)}), flush=True)
+        return
     p, notch, loads, (y0, a) = workloads.config2(args.model, args.omega, seed=0, n=args.n)
 
     def make_solver(precision, omega=None):
@@ -405,6 +454,7 @@ def main():
                                       cheb_degree=args.cheb_degree,
                                       newton_precond=args.newton_precond,
                                       omega_auto=1 if args.omega_auto else 0,
+                                      deflate=1 if args.deflate and precision != "mixed" else 0,
                                       use_graphs=0 if args.no_graphs else 1,
                                       precision=fracture.FRACTURE_MIXED if precision == "mixed"
                                       else fracture.FRACTURE_FP64)
@@ -531,6 +581,7 @@ def main():
                             if args.newton and args.pcg_reduction > 0 else "")),
             "precision": args.precision,
             "newton": bool(args.newton),
+            "deflate": bool(args.deflate),
         },
         "pcg_dof_iter_per_s": res["pcg_dof_iter_per_s"],
         "sweeps": res["sweeps"],
@@ -595,6 +646,8 @@ def main():
         # the third workload: the 2D thermal shock at DT = 4 DT_c, plain ORAM at
         # omega = 1 and at the paper's best over-relaxation 1.6
         out["tshock"] = tshock(args, ratios=(4.0,), omegas=(1.0, 1.6))
+    if not args.no_deflation:
+        out["deflation"] = deflation(args)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(256, args.n, args.model)

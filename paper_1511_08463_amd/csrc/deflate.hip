@@ -24,7 +24,7 @@
 // s = 2 / max(lx, ly), zero off the fragment and on Dirichlet DOFs.  Its
 // columns are never stored: every kernel evaluates them from fid and the
 // node's coordinates.  W^T v is a deterministic two-pass reduction (per-block
-// partials of all 3 max_fragments modes, summed in block order by one block).
+// partials of all DFL_M modes, summed in a fixed order by one block).
 // E = W^T K W is formed column by column from K applied to each mode, and
 // inverted by a Cholesky factorisation that drops a mode whose pivot falls
 // below a relative threshold (a mode dependent on the others).
@@ -208,25 +208,34 @@ __global__ __launch_bounds__(VB) void k_dfl_wtv(Grid g, const int* __restrict__ 
   }
 }
 
-// Sums the partials in block order: c = W^T v.  col >= 0 stores c as column
-// col of E; otherwise mu = E^{-1} c.
-__global__ __launch_bounds__(WAVE) void k_dfl_finish(const double* __restrict__ part, int nblocks,
+// Sums the partials: c = W^T v.  Thread t adds the entries t, t + FINT, ...
+// of the [nblocks][DFL_M] partials (FINT a multiple of DFL_M, so all of
+// them belong to mode t % DFL_M), then thread k < DFL_M adds its mode's FINT /
+// DFL_M thread sums in thread order: a fixed order, whatever the schedule.
+// col >= 0 stores c as column col of E; otherwise mu = E^{-1} c.
+constexpr int FINT = 40 * DFL_M;
+__global__ __launch_bounds__(FINT) void k_dfl_finish(const double* __restrict__ part, int nblocks,
                                                      int col, double* __restrict__ E,
                                                      const double* __restrict__ Einv,
                                                      double* __restrict__ mu) {
+  __shared__ double sh[FINT];
   __shared__ double c[DFL_M];
-  const int k = threadIdx.x;
-  if (k < DFL_M) {
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * DFL_M + k];
-    c[k] = s;
-    if (col >= 0) E[k * DFL_M + col] = s;
+  const int t = threadIdx.x, total = nblocks * DFL_M;
+  double s = 0.0;
+  for (int e = t; e < total; e += FINT) s += part[e];
+  sh[t] = s;
+  __syncthreads();
+  if (t < DFL_M) {
+    double a = 0.0;
+    for (int q = t; q < FINT; q += DFL_M) a += sh[q];
+    c[t] = a;
+    if (col >= 0) E[t * DFL_M + col] = a;
   }
   __syncthreads();
-  if (col < 0 && k < DFL_M) {
-    double s = 0.0;
-    for (int l = 0; l < DFL_M; ++l) s += Einv[k * DFL_M + l] * c[l];
-    mu[k] = s;
+  if (col < 0 && t < DFL_M) {
+    double a = 0.0;
+    for (int l = 0; l < DFL_M; ++l) a += Einv[t * DFL_M + l] * c[l];
+    mu[t] = a;
   }
 }
 
@@ -332,7 +341,7 @@ void launch_dfl_wtv(hipStream_t st, const Grid& g, const int* fid, const double*
                     int col, double* E, const double* Einv, double* mu) {
   const int nb = dfl_part_blocks(g.N);
   hipLaunchKernelGGL(k_dfl_wtv, dim3(nb), dim3(VB), 0, st, g, fid, v, part);
-  hipLaunchKernelGGL(k_dfl_finish, dim3(1), dim3(WAVE), 0, st, part, nb, col, E, Einv, mu);
+  hipLaunchKernelGGL(k_dfl_finish, dim3(1), dim3(FINT), 0, st, part, nb, col, E, Einv, mu);
 }
 
 void launch_dfl_invert(hipStream_t st, const double* E, double* Einv, const int* meta) {
