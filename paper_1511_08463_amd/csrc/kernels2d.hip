@@ -305,12 +305,13 @@ void launch_restrict_smooth2d(hipStream_t st, const Grid& gf, const Grid& gc, co
                      xout, dout, T(cr));
 }
 
-// The prolongation x += P x_c of a coarse level (node kernels, element
-// coefficients) folded into the first post-smoothing step, which starts from
-// it: x_out = x + P x_c + cr D^{-1} (b - K (x + P x_c)), d_out = that step.
-// Same arithmetic as k_prolong2d followed by k_node2d<SMOOTH> with x and no
-// d_in; x + P x_c itself is not stored.
-template <class T>
+// The prolongation x += P x_c folded into the first post-smoothing step,
+// which starts from it: x_out = x + P x_c + cr D^{-1} (b - K (x + P x_c)),
+// d_out = that step.  Same arithmetic as k_prolong2d followed by the
+// smoothing kernel of the level (k_node2d or k_col2d <SMOOTH>, with x and no
+// d_in); x + P x_c itself is not stored.  FA: coefficients from alpha (finest
+// level) or element averages.
+template <bool FA, class T>
 __global__ __launch_bounds__(NB) void k_prol_smooth2d(Grid g, Grid gc, Mat m,
                                                       const T* __restrict__ coef, T kell,
                                                       const T* __restrict__ x,
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(NB) void k_prol_smooth2d(Grid g, Grid gc, Mat m,
   if (i > g.nx || j > g.ny) return;
   const int N = g.N, n = i + (g.nx + 1) * j;
   T c[6];
-  coef6<false>(g, coef, kell, i, j, c);
+  coef6<FA>(g, coef, kell, i, j, c);
   T fx, fy, dx, dy;
   node_force2d<true, true, false, true>(g, m, c, x, x + N, i, j, fx, fy, dx, dy, &gc, xc);
   T px, py;
@@ -334,14 +335,65 @@ __global__ __launch_bounds__(NB) void k_prol_smooth2d(Grid g, Grid gc, Mat m,
                                (const T*)nullptr, dout, T(0), cr, 1, acc);
 }
 
-bool node_level2d(const Grid& g) { return g.dim == 2 && !use_col2d(g); }
+// Column-tiled form: the coarse nodes the tile's rows j0 - 1 .. j0 + ROWS
+// and columns i0 - 1 .. i0 + NB_X touch are staged in LDS first (coarse
+// columns (i0 - 1) >> 1 .. (i0 + NB_X) >> 1, rows (j0 - 1) >> 1 ..
+// (j0 + ROWS) >> 1 + 1, zero outside the coarse grid).
+template <bool FA, class T>
+__global__ __launch_bounds__(NB_X) void k_col_prol_smooth2d(Grid g, Grid gc, Mat m,
+                                                            const T* __restrict__ coef, T kell,
+                                                            const T* __restrict__ x,
+                                                            const T* __restrict__ xc,
+                                                            T* __restrict__ y,
+                                                            const T* __restrict__ b,
+                                                            T* __restrict__ dout, T cr) {
+  constexpr int ROWS = col_rows<M_SMOOTH>();
+  constexpr int PH = ROWS / 2 + 2;
+  static_assert(ROWS % 2 == 0 && NB_X % 2 == 0, "tiles start on even rows and columns");
+  __shared__ T sx[PH * PROL_PW], sy[PH * PROL_PW];
+  const int nbx = gridDim.x, total = gridDim.x * gridDim.y;
+  const int t = xcd_tile(blockIdx.x + nbx * blockIdx.y, total);
+  const int i0 = (t % nbx) * NB_X, i = i0 + threadIdx.x;
+  const int j0 = (t / nbx) * ROWS;
+  const int cc0 = (i0 >> 1) - 1, cr0 = (j0 >> 1) - 1, Wc = gc.nx + 1;
+  for (int q = threadIdx.x; q < PH * PROL_PW; q += NB_X) {
+    const int cy = cr0 + q / PROL_PW, cx = cc0 + q % PROL_PW;
+    const bool ok = cy >= 0 && cy <= gc.ny && cx >= 0 && cx <= gc.nx;
+    sx[q] = ok ? xc[cx + Wc * cy] : T(0);
+    sy[q] = ok ? xc[gc.N + cx + Wc * cy] : T(0);
+  }
+  __syncthreads();
+  if (i > g.nx) return;
+  double acc = 0.0;
+  column2d<ROWS, FA, true, true, false>(
+      g, m, coef, kell, x, i, j0,
+      [&](int j, T fx, T fy, T dx, T dy, T xn, T yn) {
+        node_out2d<M_SMOOTH, R_NONE>(g, i, j, fx, fy, dx, dy, xn, yn, y, b, (const T*)nullptr,
+                                     dout, T(0), cr, 1, acc);
+      },
+      AddProl<T>{sx, sy, cc0, cr0});
+}
 
 template <class T>
-void launch_prol_smooth2d(hipStream_t st, const Grid& g, const Grid& gc, const Mat& m,
+void launch_prol_smooth2d(hipStream_t st, const Grid& g, const Grid& gc, const Mat& m, bool fine,
                           const T* coef, double kell, const T* x, const T* xc, T* y, const T* b,
                           T* dout, double cr) {
-  hipLaunchKernelGGL((k_prol_smooth2d<T>), node_grid2(g), dim3(NB_X, NB_Y), 0, st, g, gc, m, coef,
-                     T(kell), x, xc, y, b, dout, T(cr));
+  const T k = T(kell), c = T(cr);
+  if (use_col2d(g)) {
+    const dim3 gr = op_grid2(g, true, col_rows<M_SMOOTH>());
+    if (fine)
+      hipLaunchKernelGGL((k_col_prol_smooth2d<true, T>), gr, dim3(NB_X), 0, st, g, gc, m, coef, k,
+                         x, xc, y, b, dout, c);
+    else
+      hipLaunchKernelGGL((k_col_prol_smooth2d<false, T>), gr, dim3(NB_X), 0, st, g, gc, m, coef, k,
+                         x, xc, y, b, dout, c);
+  } else if (fine) {
+    hipLaunchKernelGGL((k_prol_smooth2d<true, T>), node_grid2(g), dim3(NB_X, NB_Y), 0, st, g, gc, m,
+                       coef, k, x, xc, y, b, dout, c);
+  } else {
+    hipLaunchKernelGGL((k_prol_smooth2d<false, T>), node_grid2(g), dim3(NB_X, NB_Y), 0, st, g, gc,
+                       m, coef, k, x, xc, y, b, dout, c);
+  }
 }
 
 // x_f += P x_c.
@@ -371,7 +423,7 @@ void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* x
   template void launch_restrict2d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);        \
   template void launch_restrict_smooth2d<T>(hipStream_t, const Grid&, const Grid&, const Mat&,     \
                                             const T*, double, const T*, T*, T*, T*, double);       \
-  template void launch_prol_smooth2d<T>(hipStream_t, const Grid&, const Grid&, const Mat&,         \
+  template void launch_prol_smooth2d<T>(hipStream_t, const Grid&, const Grid&, const Mat&, bool,   \
                                         const T*, double, const T*, const T*, T*, const T*, T*,   \
                                         double);                                                  \
   template void launch_prolong2d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);

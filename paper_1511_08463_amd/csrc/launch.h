@@ -28,11 +28,10 @@ void launch_restrict_smooth2d(hipStream_t st, const Grid& gf, const Grid& gc, co
                               const T* coef, double kell, const T* rf, T* bc, T* xout, T* dout,
                               double cr);
 template <class T>
-void launch_prol_smooth2d(hipStream_t st, const Grid& g, const Grid& gc, const Mat& m,
+void launch_prol_smooth2d(hipStream_t st, const Grid& g, const Grid& gc, const Mat& m, bool fine,
                           const T* coef, double kell, const T* x, const T* xc, T* y, const T* b,
                           T* dout, double cr);
-// whether level g's operator kernels are the per-node (not column-tiled) ones
-bool node_level2d(const Grid& g);
+
 template <class T>
 void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* xc, T* xf);
 void launch_lift2d(hipStream_t st, const Grid& g, double* u, double t, const Load2D& ld);

@@ -275,9 +275,36 @@ struct Row3 {
   T ux[3], uy[3], a[3];
 };
 
-template <bool FA, bool HASX, class T>
+// What the row loads of column2d add to x: nothing (NoProl), or the coarse
+// correction P x_c of level gc interpolated on the fly (AddProl), as after
+// the V-cycle's prolongation.  AddProl reads x_c from a block of coarse
+// nodes staged in LDS: sx, sy hold the two components of coarse columns
+// cc0 .. cc0 + PROL_PW - 1 of rows cr0, cr0 + 1, ... (row pitch PROL_PW), the
+// coarse nodes that a column tile NB_X fine columns wide touches.
+constexpr int PROL_PW = NB_X / 2 + 2;
+struct NoProl {};
+template <class T>
+struct AddProl {
+  const T* sx;
+  const T* sy;
+  int cc0, cr0;
+};
+template <class T>
+__device__ __forceinline__ void add_prol(const Grid&, const NoProl&, int, int, T&, T&) {}
+// Same arithmetic as prol_value on the staged copy.
+template <class T>
+__device__ __forceinline__ void add_prol(const Grid& g, const AddProl<T>& pr, int i, int j, T& vx,
+                                         T& vy) {
+  const int a = ((j >> 1) - pr.cr0) * PROL_PW + ((i >> 1) - pr.cc0);
+  const int b = (((j + 1) >> 1) - pr.cr0) * PROL_PW + (((i + 1) >> 1) - pr.cc0);
+  vx += fixed_x2(g, i, j) ? T(0) : T(0.5) * (pr.sx[a] + pr.sx[b]);
+  vy += fixed_y2(g, i, j) ? T(0) : T(0.5) * (pr.sy[a] + pr.sy[b]);
+}
+
+template <bool FA, bool HASX, class T, class PR = NoProl>
 __device__ __forceinline__ void load_row3(const Grid& g, const T* __restrict__ x,
-                                          const T* __restrict__ coef, int i, int r, Row3<T>& R) {
+                                          const T* __restrict__ coef, int i, int r, Row3<T>& R,
+                                          const PR& pr = PR()) {
   const int W = g.nx + 1, N = g.N;
   const bool ok = r >= 0 && r <= g.ny;
 #pragma unroll
@@ -287,6 +314,7 @@ __device__ __forceinline__ void load_row3(const Grid& g, const T* __restrict__ x
     const int n = ii + W * r;
     R.ux[k] = (HASX && in) ? x[n] : T(0);
     R.uy[k] = (HASX && in) ? x[n + N] : T(0);
+    if (in) add_prol(g, pr, ii, r, R.ux[k], R.uy[k]);
     R.a[k] = (FA && in) ? coef[n] : T(0);
   }
 }
@@ -302,26 +330,28 @@ __device__ __forceinline__ void load_row3(const Grid& g, const T* __restrict__ x
 //   C.T0 = [(i,cj), (i+1,cj), (i+1,cj+1)]    -> node (i,cj) as vertex 0
 //   C.T1 = [(i,cj), (i+1,cj+1), (i,cj+1)]    -> node (i,cj) as vertex 0, (i,cj+1) as vertex 2
 // (the six triangles around a node are the three above it in cell row j and
-// the three below it in cell row j-1).  Precondition: 0 <= i <= nx,
+// the three below it in cell row j-1).  pr: what the row loads add to x
+// (NoProl, or AddProl: x + P x_c).  Precondition: 0 <= i <= nx,
 // 0 <= j0 <= ny.
-template <int ROWS, bool FA, bool HASX, bool DIAG, bool EIG, class T, class Fin>
+template <int ROWS, bool FA, bool HASX, bool DIAG, bool EIG, class T, class Fin,
+          class PR = NoProl>
 __device__ __forceinline__ void column2d(const Grid& g, const Mat& m, const T* __restrict__ coef,
                                          T kell, const T* __restrict__ x, int i, int j0,
-                                         Fin&& fin) {
+                                         Fin&& fin, const PR& pr = PR()) {
   const T ihx = T(1.0 / g.hx), ihy = T(1.0 / g.hy), area = T(0.5 * g.hx * g.hy);
   const T l2m = T(m.l2m), lam = T(m.lam), mu = T(m.mu);
   const T hxx = ihx * ihx, hyy = ihy * ihy;
   const bool hasL = i >= 1, hasC = i < g.nx;
   const int nx = g.nx;
   Row3<T> lo, hi;
-  load_row3<FA, HASX>(g, x, coef, i, j0 - 1, lo);
+  load_row3<FA, HASX>(g, x, coef, i, j0 - 1, lo, pr);
   T fcx = 0, fcy = 0, dcx = 0, dcy = 0;   // node (i, cj)
   T fnx = 0, fny = 0, dnx = 0, dny = 0;   // node (i, cj + 1)
 #pragma unroll
   for (int s = 0; s <= ROWS; ++s) {
     const int cj = j0 - 1 + s;
     if (cj > g.ny) break;
-    load_row3<FA, HASX>(g, x, coef, i, cj + 1, hi);
+    load_row3<FA, HASX>(g, x, coef, i, cj + 1, hi, pr);
     T s0 = 0, s1 = 0;   // eigenstrain of the row's T0 / T1 triangles (EIG)
     if (EIG) {
       double e0, e1;

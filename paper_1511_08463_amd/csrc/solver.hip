@@ -533,16 +533,21 @@ LevelBufs<float> bufs<float>(fracture* h, int l) {
 // d_in, x_out, d_out per node).
 template <class T>
 void smooth_step(fracture* h, const Grid& g, bool fine, const T* coef, double kell, const T* x_in,
-                 T* x_out, const T* b, const T* din, T* dout, double cd, double cr) {
+                 T* x_out, const T* b, const T* din, T* dout, double cd, double cr,
+                 const Grid* gc = nullptr, const T* xc = nullptr) {
   const bool timed = fine && sizeof(T) == sizeof(double) && h->kt_cap > 0 &&
                      (h->kt_seen++ % KT_STRIDE == 0) && h->kt_used < h->kt_cap;
   if (timed) (void)hipEventRecord(h->kt_ev[2 * h->kt_used], h->st);
-  launch_smooth2d<T>(h->st, g, h->mat, fine, coef, kell, x_in, x_out, b, din, dout, cd, cr);
+  if (xc)
+    launch_prol_smooth2d<T>(h->st, g, *gc, h->mat, fine, coef, kell, x_in, xc, x_out, b, dout, cr);
+  else
+    launch_smooth2d<T>(h->st, g, h->mat, fine, coef, kell, x_in, x_out, b, din, dout, cd, cr);
   if (timed) {
     (void)hipEventRecord(h->kt_ev[2 * h->kt_used + 1], h->st);
     const double dv = 8.0 * g.dim;
     h->kt_bytes += (double)g.N * (8.0 + dv + (x_in ? dv : 0.0) + (din && din != x_in ? dv : 0.0) +
-                                  dv + (dout ? dv : 0.0));
+                                  dv + (dout ? dv : 0.0)) +
+                   (xc ? dv * gc->N : 0.0);
     ++h->kt_used;
   }
 }
@@ -606,9 +611,8 @@ T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr, bool first_d
   else
     launch_restrict2d<T>(h->st, g, h->lv[l + 1].g, v.r, c.b);
   T* xc = vcycle_t<T>(h, l + 1, c.b, nullptr, fuse);
-  // on a coarse level smoothed by the per-node kernels the prolongation rides
-  // in the first post-smoothing step
-  const bool prol_fused = !fine && node_level2d(g);
+  // in 2D the prolongation rides in the first post-smoothing step
+  const bool prol_fused = g.dim == 2;
   if (!prol_fused) launch_prolong2d<T>(h->st, g, h->lv[l + 1].g, xc, cur);
   // post-smoothing (same polynomial: the V-cycle is symmetric)
   for (int s = 0; s < k; ++s) {
@@ -616,12 +620,9 @@ T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr, bool first_d
     if (s == k - 1 && final_out) out = final_out;
     const T* din = s == 0 ? nullptr : v.d;
     T* dout = (s < k - 1) ? v.d : nullptr;
-    if (s == 0 && prol_fused)
-      launch_prol_smooth2d<T>(h->st, g, h->lv[l + 1].g, h->mat, v.coef, kell, cur, xc, out, b, dout,
-                              h->cheb_cr[0]);
-    else
-      smooth_step<T>(h, g, fine, v.coef, kell, cur, out, b, din, dout, h->cheb_cd[s],
-                     h->cheb_cr[s]);
+    const bool pr = s == 0 && prol_fused;
+    smooth_step<T>(h, g, fine, v.coef, kell, cur, out, b, din, dout, h->cheb_cd[s], h->cheb_cr[s],
+                   pr ? &h->lv[l + 1].g : nullptr, pr ? xc : nullptr);
     cur = out;
   }
   return cur;
