@@ -122,7 +122,8 @@ LIVE_CAP = 4096   # finest-level Chebyshev steps timed (every fifth of the ~4900
 
 
 def roofline(live, dom, traffic, rl):
-    """The dominant kernel, the finest-level Chebyshev step k_col2d<SMOOTH>:
+    """The dominant kernel, the finest-level Chebyshev step k_col2d<SMOOTH>
+    (k_col_prol_smooth2d for the first post-smoothing step of a V-cycle):
     its launches inside the timed region (live HIP events; algorithmic bytes
     of each launch summed), with the back-to-back measurement of the 88 B/node
     form alongside."""
@@ -133,7 +134,9 @@ def roofline(live, dom, traffic, rl):
                        f"timed region (every fifth: {live['launches']} launches, "
                        f"{live['bytes'] / 1e6:.1f} MB "
                        f"algorithmic per launch on average: coefficients 8 B, b, x_in, a distinct "
-                       f"d_in, x_out, d_out 16 B each per node)"),
+                       f"d_in, x_out, d_out 16 B each per node, and 16 B per coarse node of the "
+                       f"coarse correction for the first post-smoothing step, which carries the "
+                       f"prolongation)"),
             "achieved": live["gbs"], "frac": live["gbs"] / HBM_PEAK_GBS,
             "avg_us": live["us"], "launches": live["launches"], "bytes_per_launch": live["bytes"],
             "traffic": traffic,
@@ -167,16 +170,17 @@ def time_kernels(solver, reps):
 
 # HBM bytes per launch of the finest-level Chebyshev step at 2048^2, averaged
 # over its launches inside the V-cycles of load steps 1-3 (the mix of the
-# timed region), from rocprofv3 FETCH_SIZE and WRITE_SIZE of the headline leg,
+# timed region: two steps with x given, one from zero, one that also applies
+# the prolongation), from rocprofv3 FETCH_SIZE and WRITE_SIZE of the headline leg,
 # each scaled by the factor that maps the same counter on the plain copy
 # kernel to its known bytes.  Valid only for the sources they were taken on
 # (sha256 over the files below: the kernels and the driver that sets each
 # launch's operands).
 TRAFFIC = {
     # profiles/hbm_traffic_2048_at1.md: mean over 344 launches of load steps 1-3,
-    # FETCH x 1.9994 + WRITE x 1.0000 (88 B/node form back to back: 384.9 MB)
-    "bytes": 288446519,
-    "source_sha256": "d1a9502dd57a44c822996eb21345046bfb9d6766418e0c584ffb84d331cb26db",
+    # FETCH x 1.9994 + WRITE x 1.0000 (88 B/node form back to back: 384.7 MB)
+    "bytes": 292248436,
+    "source_sha256": "594cdc3ed50aa771f5557958894b1accccbe3eacd134c0fe73dc14628867abff",
 }
 TRAFFIC_SOURCES = ("paper_1511_08463_amd/csrc/common.h", "paper_1511_08463_amd/csrc/ops2d.h",
                    "paper_1511_08463_amd/csrc/kernels2d.hip", "paper_1511_08463_amd/csrc/solver.hip")

@@ -340,7 +340,9 @@ int fracture_time_kernel(fracture_t h, int kernel, int reps, double* avg_ms, dou
    that cycles through the four steps of a V-cycle), whatever solve launches
    them, is bracketed by HIP events on the instance's stream, up to
    `capacity` steps, and each adds its algorithmic bytes (coefficients 8 B,
-   b, x_in, a distinct d_in, x_out, d_out at 8 B per DOF, per node); the
+   b, x_in, a distinct d_in, x_out, d_out at 8 B per DOF, per node; the
+   first post-smoothing step, which also applies the prolongation, adds the
+   coarse correction at 8 B per coarse DOF); the
    durations include the dispatch around each kernel.  While it is active the V-cycles are launched
    eagerly (a recorded graph replay cannot hold the events).  The events are
    created here, up to 32768 steps; capacity 0 ends the timing.  Only
