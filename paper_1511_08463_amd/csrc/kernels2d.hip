@@ -781,19 +781,20 @@ __global__ __launch_bounds__(NB) void k_helm_cg2d(Grid g, Helm hp, const double*
 }
 
 // Rows j0..j1 (3D: row indices j + (ny + 1) k) and columns i0..i1.
-void launch_helm_cg2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
-                      const double* z, const double* p_old, const uint8_t* mask, double* p_new,
-                      double* q, int j0, int j1, int i0, int i1, const double* S, bool first,
-                      Red r) {
-  if (g.dim == 3)
-    return launch_helm_cg3d(st, g, cL, cM, w2, z, p_old, mask, p_new, q, j0, j1, i0, i1, S, first,
-                            r);
+int launch_helm_cg2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                     const double* z, const double* p_old, const uint8_t* mask, double* p_new,
+                     double* q, int j0, int j1, int i0, int i1, const double* S, bool first,
+                     Red r, bool finish) {
+  if (g.dim == 3) {
+    launch_helm_cg3d(st, g, cL, cM, w2, z, p_old, mask, p_new, q, j0, j1, i0, i1, S, first, r);
+    return 0;
+  }
   Helm hp{cL, cM, 0.0};
   if (j0 < 0) j0 = 0;
   if (j1 < 0 || j1 > g.ny) j1 = g.ny;
   if (i0 < 0) i0 = 0;
   if (i1 < 0 || i1 > g.nx) i1 = g.nx;
-  if (j1 < j0 || i1 < i0) return;
+  if (j1 < j0 || i1 < i0) return 0;
   dim3 gr((i1 - i0 + 1 + NB_X - 1) / NB_X, (j1 - j0 + 1 + NB_Y - 1) / NB_Y), bl(NB_X, NB_Y);
   if (first)
     hipLaunchKernelGGL((k_helm_cg2d<true>), gr, bl, 0, st, g, hp, w2, z, p_old, mask, p_new, q, j0,
@@ -801,7 +802,9 @@ void launch_helm_cg2d(hipStream_t st, const Grid& g, double cL, double cM, const
   else
     hipLaunchKernelGGL((k_helm_cg2d<false>), gr, bl, 0, st, g, hp, w2, z, p_old, mask, p_new, q, j0,
                        j1, i0, i1, S, r);
+  if (!finish) return (int)(gr.x * gr.y);
   launch_finish(st, r, (int)(gr.x * gr.y), false);
+  return 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -133,15 +133,20 @@ void launch_finish_multi(hipStream_t st, const FinishSet& fs, int nblocks);
 void launch_cg_update(hipStream_t st, int64_t n, double* x, double* r, const double* p,
                       const double* q, const double* S, Red rr);
 void launch_xpby(hipStream_t st, int64_t n, const double* z, double* p, const double* S);
+// pq_part (optional): the unfinished partials of p.q (pq_nb of them), from
+// which each block forms alpha itself
 void launch_cg_update_jac(hipStream_t st, const Box& bx, double* x, double* r, const double* p,
                           const double* q, const double* dinv, double* z, const double* S, Red rr,
-                          Red rz);
+                          Red rz, const double* pq_part = nullptr, int pq_nb = 0);
 void launch_helm_cg3d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
                       const double* z, const double* p_old, const uint8_t* mask, double* p_new,
                       double* q, int r0, int r1, int i0, int i1, const double* S, bool first, Red r);
-void launch_helm_cg2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
-                      const double* z, const double* p_old, const uint8_t* mask, double* p_new,
-                      double* q, int r0, int r1, int i0, int i1, const double* S, bool first, Red r);
+// Returns 0 after finishing the p.q reduction into S (3D, or finish set), else
+// the number of partials left for the consumer (2D with finish = false).
+int launch_helm_cg2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                     const double* z, const double* p_old, const uint8_t* mask, double* p_new,
+                     double* q, int r0, int r1, int i0, int i1, const double* S, bool first, Red r,
+                     bool finish = true);
 void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, Red r);
 void launch_jacobi_dot(hipStream_t st, const Box& bx, const double* r, const double* dinv, double* z,
                        Red red);

@@ -925,9 +925,10 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
     const Box bx{(int64_t)j0 * W + i0, W, (int64_t)(i1 - i0 + 1),
                  any_inactive ? (int64_t)(j1 - j0 + 1) * (i1 - i0 + 1) : 0};
     // the direction update rides in the Hessian apply (p ping-pongs between
-    // vp and vt1) and the preconditioner in the CG update, so an iteration
-    // is two kernels and two finishing launches; the CG scalars live on the
-    // device and the host tests ||r|| one iteration late (lag_mark / lag_get)
+    // vp and vt1) and the preconditioner in the CG update, which in 2D also
+    // finishes p.q itself, so an iteration is two kernels and one finishing
+    // launch; the CG scalars live on the device and the host tests ||r|| one
+    // iteration late (lag_mark / lag_get)
     if (any_inactive) {
       launch_norm2_box(st, bx, h->vr, red(h, 7, S_TMP2));
       launch_jacobi_dot(st, bx, h->vr, h->hdinv, h->vz, red(h, 1, S_RZ));
@@ -940,12 +941,14 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
       double* pb[2] = {h->vp, h->vt1};
       for (int k = 1; k <= h->p.max_vi_cg; ++k) {
         double* pn = pb[k & 1];
-        launch_helm_cg2d(st, g, h->cL, h->cM, h->w2, h->vz, pb[(k + 1) & 1], h->mask, pn, h->vq,
-                         j0, j1, i0, i1, h->S, k == 1, red(h, 2, S_PQ, P_CG_ALPHA));
+        // in 2D the update forms alpha from the partials of p.q itself
+        const Red rpq = red(h, 2, S_PQ, P_CG_ALPHA);
+        const int npq = launch_helm_cg2d(st, g, h->cL, h->cM, h->w2, h->vz, pb[(k + 1) & 1], h->mask,
+                                         pn, h->vq, j0, j1, i0, i1, h->S, k == 1, rpq, false);
         Red rr = red(h, 3, S_RR);
         rr.host = lag_slot(h, k);
         launch_cg_update_jac(st, bx, h->vd, h->vr, pn, h->vq, h->hdinv, h->vz, h->S, rr,
-                             red(h, 4, S_RZNEW, P_CG_BETA));
+                             red(h, 4, S_RZNEW, P_CG_BETA), npq ? rpq.part : nullptr, npq);
         ++*cg_iters;
         lag_mark(h, k);
         if (k > 1) {

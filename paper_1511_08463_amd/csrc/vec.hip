@@ -108,18 +108,44 @@ void launch_cg_update(hipStream_t st, int64_t n, double* x, double* r, const dou
   launch_finish(st, rr, vgrid(n), false);
 }
 
+// The CG step length alpha = rz / pq from the per-block partials of pq, summed
+// in k_finish's order (FB threads striding the partials, then their wave sums
+// in wave order), so every block forms the same value and the result equals
+// the separate finishing launch bit for bit.
+__device__ __forceinline__ double cg_alpha_from_parts(const double* __restrict__ part, int nb,
+                                                      const double* __restrict__ S) {
+  static_assert(FB % VB == 0 && VB % WAVE == 0, "virtual finishing threads");
+  constexpr int M = FB / VB;
+  __shared__ double sh[FB / WAVE];
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    double acc = 0.0;
+    for (int k = threadIdx.x + m * VB; k < nb; k += FB) acc += part[k];
+    acc = wave_sum(acc);
+    if (lane == 0) sh[w + m * (VB / WAVE)] = acc;
+  }
+  __syncthreads();
+  double pq = sh[0];
+  for (int k = 1; k < FB / WAVE; ++k) pq += sh[k];
+  return (pq != 0.0) ? S[S_RZ] / pq : 0.0;
+}
+
 // x += a p; r -= a q; z = dinv .* r; S[rr.slot] = r.r, S[rz.slot] = r.z over
-// the entries of a box (a = S[S_ALPHA]; both sums finished by one launch).  The two reductions
-// must not touch each other's scalars: rz's post-operation reads S_RZ only.
+// the entries of a box (both sums finished by one launch); a = S[S_ALPHA], or
+// (pq_part) formed by every block from the partials of p.q.  The two
+// reductions must not touch each other's scalars: rz's post-operation reads
+// S_RZ only.
 __global__ __launch_bounds__(VB) void k_cg_update_jac(Box bx, double* __restrict__ x,
                                                       double* __restrict__ r,
                                                       const double* __restrict__ p,
                                                       const double* __restrict__ q,
                                                       const double* __restrict__ dinv,
                                                       double* __restrict__ z,
-                                                      const double* __restrict__ S, Red rr,
-                                                      Red rz) {
-  const double a = S[S_ALPHA];
+                                                      const double* __restrict__ S,
+                                                      const double* __restrict__ pq_part,
+                                                      int pq_nb, Red rr, Red rz) {
+  const double a = pq_part ? cg_alpha_from_parts(pq_part, pq_nb, S) : S[S_ALPHA];
   double arr = 0.0, arz = 0.0;
   GRID_STRIDE(qq, bx.n) {
     const int64_t k = box_index(bx, qq);
@@ -137,9 +163,9 @@ __global__ __launch_bounds__(VB) void k_cg_update_jac(Box bx, double* __restrict
 
 void launch_cg_update_jac(hipStream_t st, const Box& bx, double* x, double* r, const double* p,
                           const double* q, const double* dinv, double* z, const double* S, Red rr,
-                          Red rz) {
+                          Red rz, const double* pq_part, int pq_nb) {
   hipLaunchKernelGGL(k_cg_update_jac, dim3(vgrid(bx.n)), dim3(VB), 0, st, bx, x, r, p, q, dinv, z,
-                     S, rr, rz);
+                     S, pq_part, pq_nb, rr, rz);
   hipLaunchKernelGGL(k_finish2, dim3(2), dim3(FB), 0, st, rr, rz, vgrid(bx.n));
 }
 
