@@ -102,3 +102,30 @@ def test_3d_shapes_and_validation():
     assert fracture.fracture_workspace_bytes(bad) == 0
     bad = fracture.make_params(**dict(w.thermal(16, 8, 4), load_kind=0))
     assert fracture.fracture_workspace_bytes(bad) == 0
+
+
+def test_deflation_parameters():
+    """Crack-aware deflation: documented defaults, rejected combinations and
+    the workspace it adds (three node-sized integer arrays and the small
+    coarse-space buffers); the fragment entry points reject a null handle
+    before any device work."""
+    p = fracture.fracture_default_params(64, 64)
+    assert (p.deflate, p.deflate_theta, p.deflate_min_nodes, p.deflate_max_fragments) == (0, 0.5, 64, 8)
+    base = workloads.tension(64, 0.05)
+    plain = fracture.fracture_workspace_bytes(fracture.make_params(**base))
+    defl = fracture.fracture_workspace_bytes(fracture.make_params(**dict(base, deflate=1)))
+    assert defl >= plain + 3 * 65 * 65 * 4
+    for bad in (dict(deflate=2), dict(deflate=1, precision=fracture.FRACTURE_MIXED),
+                dict(deflate=1, deflate_theta=0.0), dict(deflate=1, deflate_theta=1.5),
+                dict(deflate=1, deflate_min_nodes=0), dict(deflate=1, deflate_max_fragments=0),
+                dict(deflate=1, deflate_max_fragments=9)):
+        q = fracture.make_params(**dict(base, **bad))
+        assert fracture.fracture_workspace_bytes(q) == 0, bad
+    th = workloads.thermal(16, 16, 4)
+    assert fracture.fracture_workspace_bytes(fracture.make_params(**th)) > 0
+    assert fracture.fracture_workspace_bytes(fracture.make_params(**dict(th, deflate=1))) == 0
+    lib = fracture.load_library()
+    n = ctypes.c_int()
+    assert lib.fracture_fragments(None, ctypes.byref(n), None) == fracture.FRACTURE_EINVAL
+    E = (ctypes.c_double * 576)()
+    assert lib.fracture_deflation_matrix(None, ctypes.byref(n), E) == fracture.FRACTURE_EINVAL
