@@ -307,10 +307,10 @@ void launch_restrict_smooth2d(hipStream_t st, const Grid& gf, const Grid& gc, co
 
 // The prolongation x += P x_c folded into the first post-smoothing step,
 // which starts from it: x_out = x + P x_c + cr D^{-1} (b - K (x + P x_c)),
-// d_out = that step.  Same arithmetic as k_prolong2d followed by the
-// smoothing kernel of the level (k_node2d or k_col2d <SMOOTH>, with x and no
-// d_in); x + P x_c itself is not stored.  FA: coefficients from alpha (finest
-// level) or element averages.
+// d_out = that step.  Same arithmetic as the prolongation (prolong_node2d)
+// followed by the smoothing kernel of the level (k_node2d or k_col2d
+// <SMOOTH>, with x and no d_in); x + P x_c itself is not stored.  FA:
+// coefficients from alpha (finest level) or element averages.
 template <bool FA, class T>
 __global__ __launch_bounds__(NB) void k_prol_smooth2d(Grid g, Grid gc, Mat m,
                                                       const T* __restrict__ coef, T kell,
@@ -396,23 +396,6 @@ void launch_prol_smooth2d(hipStream_t st, const Grid& g, const Grid& gc, const M
   }
 }
 
-// x_f += P x_c.
-template <class T>
-__global__ __launch_bounds__(NB) void k_prolong2d(Grid gf, Grid gc, const T* __restrict__ xc,
-                                                  T* __restrict__ xf) {
-  const int i = blockIdx.x * NB_X + threadIdx.x;
-  const int j = blockIdx.y * NB_Y + threadIdx.y;
-  if (i > gf.nx || j > gf.ny) return;
-  prolong_node2d(gf, gc, xc, xf, i, j);
-}
-
-template <class T>
-void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* xc, T* xf) {
-  if (gf.dim == 3) return launch_prolong3d<T>(st, gf, gc, xc, xf);
-  dim3 gr(node_grid2(gf)), bl(NB_X, NB_Y);
-  hipLaunchKernelGGL((k_prolong2d<T>), gr, bl, 0, st, gf, gc, xc, xf);
-}
-
 #define INST(T)                                                                                  \
   template void launch_apply2d<T>(hipStream_t, const Grid&, const Mat&, bool, const T*, double,   \
                                   const T*, T*, const ND<T>*, int, int, Red);                         \
@@ -425,8 +408,7 @@ void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* x
                                             const T*, double, const T*, T*, T*, T*, double);       \
   template void launch_prol_smooth2d<T>(hipStream_t, const Grid&, const Grid&, const Mat&, bool,   \
                                         const T*, double, const T*, const T*, T*, const T*, T*,   \
-                                        double);                                                  \
-  template void launch_prolong2d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);
+                                        double);
 INST(float)
 INST(double)
 #undef INST

@@ -32,8 +32,6 @@ void launch_prol_smooth2d(hipStream_t st, const Grid& g, const Grid& gc, const M
                           const T* coef, double kell, const T* x, const T* xc, T* y, const T* b,
                           T* dout, double cr);
 
-template <class T>
-void launch_prolong2d(hipStream_t st, const Grid& gf, const Grid& gc, const T* xc, T* xf);
 void launch_lift2d(hipStream_t st, const Grid& g, double* u, double t, const Load2D& ld);
 void launch_w2_2d(hipStream_t st, const Grid& g, const Mat& m, const double* u, double* w2);
 void launch_vi_eval2d(hipStream_t st, const Grid& g, double cL, double cM, double cm,

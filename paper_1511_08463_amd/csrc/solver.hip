@@ -613,7 +613,7 @@ T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr, bool first_d
   T* xc = vcycle_t<T>(h, l + 1, c.b, nullptr, fuse);
   // in 2D the prolongation rides in the first post-smoothing step
   const bool prol_fused = g.dim == 2;
-  if (!prol_fused) launch_prolong2d<T>(h->st, g, h->lv[l + 1].g, xc, cur);
+  if (!prol_fused) launch_prolong3d<T>(h->st, g, h->lv[l + 1].g, xc, cur);
   // post-smoothing (same polynomial: the V-cycle is symmetric)
   for (int s = 0; s < k; ++s) {
     T* out = (cur == v.xa) ? v.xb : v.xa;
