@@ -177,3 +177,69 @@ def test_deflated_and_plain_cg_agree_on_broken_specimen():
     (u1, a1, _), st1 = res[1]
     assert st0["converged"] and st1["converged"]
     assert _rel(u1, u0) < 1e-8 and _rel(a1, a0) < 1e-8
+
+
+def test_degenerate_fragment_sets():
+    """No undamaged node: no fragment, and the deflated solve is the plain one
+    bit for bit.  No damage: one fragment, the whole body, E against the
+    oracle."""
+    n = 40
+    p = workloads.tension(n, 0.1, "AT1")
+    print("[deflation] degenerate fragment sets", flush=True)
+    P = problems.tension_2d(n, n, **workloads.oracle_kwargs(p))
+    M = P.model
+    N = M.N
+    ones = np.ones(N)
+    states = []
+    for dfl in (0, 1):
+        s = _solver(p, deflate=dfl, am_tol=1e-9, pcg_rtol=1e-12)
+        s.set_state(u=np.zeros(2 * N), alpha=ones, alpha_prev=ones)
+        if dfl:
+            nf, fid = s.fragments()
+            assert nf == 0 and np.all(fid == -1)
+            assert s.deflation_matrix().shape == (0, 0)
+        s.set_load(0.3)
+        s.solve_step()
+        states.append(s.state()[0])
+        s.close()
+    assert np.array_equal(states[0], states[1])
+    s = _solver(p, deflate=1)
+    s.set_state(u=np.zeros(2 * N), alpha=np.zeros(N), alpha_prev=np.zeros(N))
+    nf, fid = s.fragments()
+    E = s.deflation_matrix()
+    s.close()
+    assert nf == 1 and np.all(fid == 0)
+    W = deflation.rigid_modes(M.X, P.fixed, np.zeros(N, dtype=np.int64), 1, 1.0, 1.0)
+    want = deflation.coarse_matrix(M.K(np.zeros(N)), W)
+    assert np.max(np.abs(E - want)) <= OPS_TOL * np.max(np.abs(want))
+
+
+def test_fragment_held_entirely_by_dirichlet_dofs():
+    """Surfing slab (every boundary DOF fixed): damaging the row below the
+    top edge leaves the top row as a fragment whose three modes vanish on
+    every DOF; the factorisation drops them and the deflated load step
+    reaches the plain one's state."""
+    p, notch, _ = workloads.surfing(0.1)
+    nx, ny = p["nx"], p["ny"]
+    print(f"[deflation] Dirichlet-held fragment {nx}x{ny}", flush=True)
+    N = (nx + 1) * (ny + 1)
+    alpha = np.zeros(N)
+    alpha[(ny - 1) * (nx + 1): ny * (nx + 1)] = 1.0
+    states, stats = [], []
+    for dfl in (0, 1):
+        s = _solver(p, notch, deflate=dfl, deflate_min_nodes=8, newton=1, final_tol=1e-9,
+                    pcg_rtol=1e-12, vi_cg_rtol=1e-12)
+        s.set_state(u=np.zeros(2 * N), alpha=alpha, alpha_prev=alpha)
+        if dfl:
+            nf, fid = s.fragments()
+            assert nf == 2 and int((fid == 1).sum()) == nx + 1
+            E = s.deflation_matrix()
+            assert np.all(E[3:, :] == 0.0) and np.all(E[:, 3:] == 0.0)
+        s.set_load(0.1)
+        st = s.solve_step()
+        assert st["converged"]
+        states.append(s.state())
+        stats.append(st)
+        s.close()
+    print(f"  pcg plain/deflated {stats[0]['pcg_iters']}/{stats[1]['pcg_iters']}", flush=True)
+    assert _rel(states[1][0], states[0][0]) < 1e-7 and _rel(states[1][1], states[0][1]) < 1e-7
