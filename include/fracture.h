@@ -357,7 +357,9 @@ int fracture_kernel_timing_read(fracture_t h, int* count, double* total_ms, doub
    Fragments are the connected components of the nodes with alpha <
    deflate_theta in the graph of the element edges; those of at least
    deflate_min_nodes nodes are kept, at most deflate_max_fragments of them,
-   the largest first, ties by the smaller least node index.
+   the largest first, ties by the smaller least node index (with more than
+   256 components of at least deflate_min_nodes nodes, which of them are
+   considered is unspecified).
    fracture_fragments labels the current alpha: d_fid (device, N ints)
    receives each node's fragment index, or -1 (damaged, or in a component
    not kept); *nfrag (host) the number kept.
