@@ -129,3 +129,16 @@ def test_deflation_parameters():
     assert lib.fracture_fragments(None, ctypes.byref(n), None) == fracture.FRACTURE_EINVAL
     E = (ctypes.c_double * 576)()
     assert lib.fracture_deflation_matrix(None, ctypes.byref(n), E) == fracture.FRACTURE_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; --gpus N > 1 exits with a message before
+    touching a device."""
+    import json
+    import subprocess
+    import sys
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert out.returncode == 2
+    msg = json.loads(out.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
