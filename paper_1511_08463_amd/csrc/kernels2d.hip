@@ -318,21 +318,34 @@ __global__ __launch_bounds__(NB) void k_prol_smooth2d(Grid g, Grid gc, Mat m,
                                                       const T* __restrict__ xc,
                                                       T* __restrict__ y, const T* __restrict__ b,
                                                       T* __restrict__ dout, T cr) {
+  constexpr int PH = NB_Y / 2 + 2;
+  static_assert(NB_Y % 2 == 0 && NB_X % 2 == 0, "tiles start on even rows and columns");
+  __shared__ T sx[PH * PROL_PW], sy[PH * PROL_PW];
   const int nbx = gridDim.x, total = gridDim.x * gridDim.y;
   const int tt = xcd_tile(blockIdx.x + nbx * blockIdx.y, total);
-  const int i = (tt % nbx) * NB_X + threadIdx.x;
-  const int j = (tt / nbx) * NB_Y + threadIdx.y;
+  const int i0 = (tt % nbx) * NB_X, j0 = (tt / nbx) * NB_Y;
+  const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
+  // the coarse nodes of fine columns i0 - 1 .. i0 + NB_X, rows j0 - 1 .. j0 + NB_Y
+  const int cc0 = (i0 >> 1) - 1, cr0 = (j0 >> 1) - 1, Wc = gc.nx + 1;
+  for (int q = threadIdx.x + NB_X * threadIdx.y; q < PH * PROL_PW; q += NB) {
+    const int cy = cr0 + q / PROL_PW, cx = cc0 + q % PROL_PW;
+    const bool ok = cy >= 0 && cy <= gc.ny && cx >= 0 && cx <= gc.nx;
+    sx[q] = ok ? xc[cx + Wc * cy] : T(0);
+    sy[q] = ok ? xc[gc.N + cx + Wc * cy] : T(0);
+  }
+  __syncthreads();
   if (i > g.nx || j > g.ny) return;
   const int N = g.N, n = i + (g.nx + 1) * j;
+  const AddProl<T> pr{sx, sy, cc0, cr0};
   T c[6];
   coef6<FA>(g, coef, kell, i, j, c);
   T fx, fy, dx, dy;
-  node_force2d<true, true, false, true>(g, m, c, x, x + N, i, j, fx, fy, dx, dy, &gc, xc);
-  T px, py;
-  prol_value(g, gc, xc, i, j, px, py);
+  node_force2d<true, true, false, true>(g, m, c, x, x + N, i, j, fx, fy, dx, dy, &pr);
+  T xn = x[n], yn = x[n + N];
+  add_prol(g, pr, i, j, xn, yn);
   double acc = 0.0;
-  node_out2d<M_SMOOTH, R_NONE>(g, i, j, fx, fy, dx, dy, x[n] + px, x[n + N] + py, y, b,
-                               (const T*)nullptr, dout, T(0), cr, 1, acc);
+  node_out2d<M_SMOOTH, R_NONE>(g, i, j, fx, fy, dx, dy, xn, yn, y, b, (const T*)nullptr, dout,
+                               T(0), cr, 1, acc);
 }
 
 // Column-tiled form: the coarse nodes the tile's rows j0 - 1 .. j0 + ROWS

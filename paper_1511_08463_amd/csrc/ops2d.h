@@ -82,29 +82,46 @@ __device__ __forceinline__ void coef6(const Grid& g, const T* __restrict__ coef,
   }
 }
 
+// What the operator loads add to x: nothing (NoProl), or the coarse
+// correction P x_c interpolated on the fly (AddProl), as after the V-cycle's
+// prolongation: at fine node (i, j), half the sum of coarse nodes
+// (i >> 1, j >> 1) and ((i + 1) >> 1, (j + 1) >> 1) (the nested P1
+// interpolation of the right-diagonal triangles, prolong_node2d), zero on
+// Dirichlet DOFs.  AddProl reads x_c from a block of coarse nodes staged in
+// LDS: sx, sy hold the two components of coarse columns cc0 .. cc0 +
+// PROL_PW - 1 of rows cr0, cr0 + 1, ... (row pitch PROL_PW), the coarse
+// nodes that a tile NB_X fine columns wide touches.
+constexpr int PROL_PW = NB_X / 2 + 2;
+struct NoProl {};
+template <class T>
+struct AddProl {
+  const T* sx;
+  const T* sy;
+  int cc0, cr0;
+};
+template <class T>
+__device__ __forceinline__ void add_prol(const Grid&, const NoProl&, int, int, T&, T&) {}
+template <class T>
+__device__ __forceinline__ void add_prol(const Grid& g, const AddProl<T>& pr, int i, int j, T& vx,
+                                         T& vy) {
+  const int a = ((j >> 1) - pr.cr0) * PROL_PW + ((i >> 1) - pr.cc0);
+  const int b = (((j + 1) >> 1) - pr.cr0) * PROL_PW + (((i + 1) >> 1) - pr.cc0);
+  vx += fixed_x2(g, i, j) ? T(0) : T(0.5) * (pr.sx[a] + pr.sx[b]);
+  vy += fixed_y2(g, i, j) ? T(0) : T(0.5) * (pr.sy[a] + pr.sy[b]);
+}
+
 // Force (fx, fy) = (K x) at node (i, j) and, when DIAG, the diagonal entries
 // (dx, dy) of K for the node's two DOFs.
 //
 // EIG (thermal shock, finest level): the forces of the effective strain
 // eps(x) - eps0, i.e. K x - f with f the eigenstrain load of eq.
 // (energytshock).
-// PROL: x is taken as x + P x_c, the coarse correction of level gc
-// interpolated on the fly (prol_value), as after the V-cycle's prolongation.
-template <class T>
-__device__ __forceinline__ void prol_value(const Grid& gf, const Grid& gc, const T* __restrict__ xc,
-                                           int i, int j, T& px, T& py) {
-  const int Wc = gc.nx + 1;
-  const int a = (i >> 1) + Wc * (j >> 1), b = ((i + 1) >> 1) + Wc * ((j + 1) >> 1);
-  px = fixed_x2(gf, i, j) ? T(0) : T(0.5) * (xc[a] + xc[b]);
-  py = fixed_y2(gf, i, j) ? T(0) : T(0.5) * (xc[gc.N + a] + xc[gc.N + b]);
-}
-
+// PROL: x is taken as x + P x_c (*pr), as after the V-cycle's prolongation.
 template <bool HASX, bool DIAG, bool EIG = false, bool PROL = false, class T>
 __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const T c[6],
                                              const T* __restrict__ ux, const T* __restrict__ uy,
                                              int i, int j, T& fx, T& fy, T& dx, T& dy,
-                                             const Grid* gc = nullptr,
-                                             const T* __restrict__ xc = nullptr) {
+                                             const AddProl<T>* pr = nullptr) {
   const int W = g.nx + 1, n = i + W * j;
   const bool L = i > 0, R = i < g.nx, D = j > 0, U = j < g.ny;
   const T ihx = T(1.0 / g.hx), ihy = T(1.0 / g.hy), area = T(0.5 * g.hx * g.hy);
@@ -122,14 +139,13 @@ __device__ __forceinline__ void node_force2d(const Grid& g, const Mat& m, const 
     if (D) { sx = ux[n - W]; sy = uy[n - W]; }
   }
   if (PROL) {
-    T px, py;
-    prol_value(g, *gc, xc, i, j, px, py); cx += px; cy += py;
-    if (R) { prol_value(g, *gc, xc, i + 1, j, px, py); ex += px; ey += py; }
-    if (R && U) { prol_value(g, *gc, xc, i + 1, j + 1, px, py); nex += px; ney += py; }
-    if (U) { prol_value(g, *gc, xc, i, j + 1, px, py); nnx += px; nny += py; }
-    if (L) { prol_value(g, *gc, xc, i - 1, j, px, py); wx += px; wy += py; }
-    if (L && D) { prol_value(g, *gc, xc, i - 1, j - 1, px, py); swx += px; swy += py; }
-    if (D) { prol_value(g, *gc, xc, i, j - 1, px, py); sx += px; sy += py; }
+    add_prol(g, *pr, i, j, cx, cy);
+    if (R) add_prol(g, *pr, i + 1, j, ex, ey);
+    if (R && U) add_prol(g, *pr, i + 1, j + 1, nex, ney);
+    if (U) add_prol(g, *pr, i, j + 1, nnx, nny);
+    if (L) add_prol(g, *pr, i - 1, j, wx, wy);
+    if (L && D) add_prol(g, *pr, i - 1, j - 1, swx, swy);
+    if (D) add_prol(g, *pr, i, j - 1, sx, sy);
   }
   fx = fy = dx = dy = T(0);
   const T hxx = ihx * ihx, hyy = ihy * ihy;
@@ -274,32 +290,6 @@ template <class T>
 struct Row3 {
   T ux[3], uy[3], a[3];
 };
-
-// What the row loads of column2d add to x: nothing (NoProl), or the coarse
-// correction P x_c of level gc interpolated on the fly (AddProl), as after
-// the V-cycle's prolongation.  AddProl reads x_c from a block of coarse
-// nodes staged in LDS: sx, sy hold the two components of coarse columns
-// cc0 .. cc0 + PROL_PW - 1 of rows cr0, cr0 + 1, ... (row pitch PROL_PW), the
-// coarse nodes that a column tile NB_X fine columns wide touches.
-constexpr int PROL_PW = NB_X / 2 + 2;
-struct NoProl {};
-template <class T>
-struct AddProl {
-  const T* sx;
-  const T* sy;
-  int cc0, cr0;
-};
-template <class T>
-__device__ __forceinline__ void add_prol(const Grid&, const NoProl&, int, int, T&, T&) {}
-// Same arithmetic as prol_value on the staged copy.
-template <class T>
-__device__ __forceinline__ void add_prol(const Grid& g, const AddProl<T>& pr, int i, int j, T& vx,
-                                         T& vy) {
-  const int a = ((j >> 1) - pr.cr0) * PROL_PW + ((i >> 1) - pr.cc0);
-  const int b = (((j + 1) >> 1) - pr.cr0) * PROL_PW + (((i + 1) >> 1) - pr.cc0);
-  vx += fixed_x2(g, i, j) ? T(0) : T(0.5) * (pr.sx[a] + pr.sx[b]);
-  vy += fixed_y2(g, i, j) ? T(0) : T(0.5) * (pr.sy[a] + pr.sy[b]);
-}
 
 template <bool FA, bool HASX, class T, class PR = NoProl>
 __device__ __forceinline__ void load_row3(const Grid& g, const T* __restrict__ x,
