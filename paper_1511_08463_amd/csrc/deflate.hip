@@ -5,13 +5,14 @@
 // {alpha < theta} in the graph of the element edges (horizontal, vertical and
 // the (i, j)-(i+1, j+1) diagonal of the right-diagonal triangles).  They are
 // found by a lock-free union-find over the grid:
-//   k_cc_init     parent[n] = n on undamaged nodes, -1 elsewhere;
-//   k_cc_link     each node unites itself with its undamaged neighbours
-//                 (i+1, j), (i, j+1), (i+1, j+1): the larger of two roots is
-//                 linked under the smaller by compare-and-swap, so parent
-//                 indices only decrease along a path and the root of every
-//                 final tree is its component's smallest node index -- the
-//                 same labels whatever the order in which threads run;
+//   k_cc_init     parent[n] = -1 on damaged nodes; runs of undamaged nodes
+//                 along a row within one wavefront become one tree each;
+//   k_cc_link     the unions left (across wavefront segments, and between
+//                 rows): the larger of two roots is linked under the smaller
+//                 by compare-and-swap, so parent indices only decrease along
+//                 a path and the root of every final tree is its component's
+//                 smallest node index -- the same labels whatever the order
+//                 in which threads run;
 //   k_cc_flatten  label[n] = root of n;
 //   k_cc_count    component sizes (atomic adds, one per run of equal labels
 //                 in a wavefront); the add that takes a component to
@@ -79,22 +80,50 @@ __device__ __forceinline__ void rigid2d(const Grid& g, int t, int i, int j, doub
   else { vx = -(j * g.hy - 0.5 * ly) * s; vy = (i * g.hx - 0.5 * lx) * s; }
 }
 
-__global__ __launch_bounds__(VB) void k_cc_init(int N, const double* __restrict__ alpha,
+// parent[n] = -1 on damaged nodes; on undamaged ones, the first node of its
+// run of undamaged nodes in the same grid row within the same 64-node
+// wavefront (runs break at damaged nodes, row starts and wavefront edges),
+// so every run is one tree whose root is its smallest index.
+__global__ __launch_bounds__(VB) void k_cc_init(Grid g, const double* __restrict__ alpha,
                                                 double theta, int* __restrict__ parent,
                                                 int* __restrict__ meta) {
-  const int n = blockIdx.x * VB + threadIdx.x;
+  static_assert(VB % WAVE == 0, "wavefronts cover aligned 64-node segments");
+  const int n = blockIdx.x * VB + threadIdx.x, N = g.N, W = g.nx + 1;
   if (n == 0) meta[DFL_META_NCAND] = 0;
-  if (n < N) parent[n] = alpha[n] < theta ? n : -1;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const bool solid = n < N && alpha[n] < theta;
+  const unsigned long long sm = __ballot(solid);
+  const bool prev = lane > 0 && ((sm >> (lane - 1)) & 1ull);
+  const unsigned long long st = __ballot(solid && (!prev || n % W == 0));
+  if (n >= N) return;
+  if (!solid) {
+    parent[n] = -1;
+    return;
+  }
+  const unsigned long long upto = lane == WAVE - 1 ? ~0ull : ((2ull << lane) - 1);
+  parent[n] = n - (lane - (WAVE - 1 - __builtin_clzll(st & upto)));
 }
 
+// The unions the runs of k_cc_init leave: horizontal edges across 64-node
+// segments; vertical edges once per stretch of columns where both rows are
+// undamaged (the rest of the stretch is joined through the two runs);
+// diagonal edges (i, j)-(i+1, j+1) only where neither (i+1, j) nor (i, j+1)
+// is undamaged (otherwise a horizontal and a vertical edge join them).  The
+// components, hence the labels, are those of all element edges.  A node is
+// undamaged exactly when its parent entry is not negative.
 __global__ __launch_bounds__(NB) void k_cc_link(Grid g, int* parent) {
   const int i = blockIdx.x * NB_X + threadIdx.x, j = blockIdx.y * NB_Y + threadIdx.y;
   if (i > g.nx || j > g.ny) return;
   const int W = g.nx + 1, n = i + W * j;
   if (ld_agent(parent + n) < 0) return;           // damaged: never linked
-  if (i < g.nx && ld_agent(parent + n + 1) >= 0) uf_union(parent, n, n + 1);
-  if (j < g.ny && ld_agent(parent + n + W) >= 0) uf_union(parent, n, n + W);
-  if (i < g.nx && j < g.ny && ld_agent(parent + n + W + 1) >= 0) uf_union(parent, n, n + W + 1);
+  const bool right = i < g.nx && ld_agent(parent + n + 1) >= 0;
+  if (right && ((n + 1) & (WAVE - 1)) == 0) uf_union(parent, n, n + 1);
+  if (j == g.ny) return;
+  const bool up = ld_agent(parent + n + W) >= 0;
+  if (up && !(i > 0 && ld_agent(parent + n - 1) >= 0 && ld_agent(parent + n + W - 1) >= 0))
+    uf_union(parent, n, n + W);
+  if (i < g.nx && !up && !right && ld_agent(parent + n + W + 1) >= 0)
+    uf_union(parent, n, n + W + 1);
 }
 
 // The forest is final here: plain reads follow each path to its root.
@@ -318,7 +347,7 @@ int dfl_part_blocks(int64_t N) {
 void launch_fragments2d(hipStream_t st, const Grid& g, const double* alpha, double theta,
                         int min_nodes, int fmax, int* parent, int* label, int* fid, int* meta) {
   const int N = g.N;
-  hipLaunchKernelGGL(k_cc_init, dim3(vblocks(N)), dim3(VB), 0, st, N, alpha, theta, parent, meta);
+  hipLaunchKernelGGL(k_cc_init, dim3(vblocks(N)), dim3(VB), 0, st, g, alpha, theta, parent, meta);
   hipLaunchKernelGGL(k_cc_link, nodes2(g), dim3(NB_X, NB_Y), 0, st, g, parent);
   hipLaunchKernelGGL(k_cc_flatten, dim3(vblocks(N)), dim3(VB), 0, st, N, parent, label);
   hipLaunchKernelGGL(k_fill_int, dim3(vblocks(N)), dim3(VB), 0, st, N, parent, 0);
