@@ -14,9 +14,10 @@
 //                 smallest node index -- the same labels whatever the order
 //                 in which threads run;
 //   k_cc_flatten  label[n] = root of n;
-//   k_cc_count    component sizes (atomic adds, one per run of equal labels
-//                 in a wavefront); the add that takes a component to
-//                 min_nodes records its root in a candidate list;
+//   k_cc_count    component sizes (atomic adds: one for the lanes of a
+//                 wavefront that share lane 0's label, one per other lane);
+//                 the add that takes a component to min_nodes records its
+//                 root in a candidate list;
 //   k_cc_select   keeps at most max_fragments candidates, the largest first,
 //                 ties by the smaller root;
 //   k_cc_fid      fid[n] = fragment of node n, -1 when none.
