@@ -6,18 +6,21 @@ alternate minimisation: elastic PCG with multigrid, damage box-QP active set,
 relaxation) and its composition with reduced-space Newton (Algorithm 3) to
 the stop test, commit alpha_prev.  The workload is the 2048^2 plane-strain
 unit square with a seeded edge notch (height and length drawn from
-U[0.1, 0.4]), ell = 4h, k_ell = 1e-6, loads t = 0.1 k.  W warm-up load steps
-run untimed (default 1: the notch forms its damage profile), then K load
-steps are timed (HIP-synchronised on both sides); value = K / seconds.  The
-default K = 13 covers the elastic loading, crack initiation (t = 1.0) and
-stable growth up to t = 1.4; the unstable propagation at t = 1.5 is not
-timed (ORAM advances that crack about one element per sweep).
+U[0.1, 0.4]), ell = 4h, k_ell = 1e-6, loads t = 0.1 k, k = 1..20.  W warm-up
+load steps run first on a separate instance, which is then discarded; a
+fresh instance then runs load steps 1..K, all timed (HIP-synchronised on
+both sides); value = K / seconds.  The default K = 20 is the whole load
+path: elastic loading, crack initiation (t = 1.0), stable growth, the
+unstable propagation through the specimen (t = 1.5, thousands of ORAM
+sweeps) and the separated body.
 
-Also reported: PCG DOF-iterations per second, the same steps in mixed
-precision and at omega = 1.4, 1.8 (shorter), the roofline of the dominant
-kernel (algorithmic bytes per launch over its mean duration, measured with
-HIP events on the solver's stream) with its measured HBM traffic, the served
-stream (p50/p99 step latency) and the CPU oracle timed on a bounded sample.
+Also reported: PCG DOF-iterations per second, per-step latency (p50/p99),
+the same steps in mixed precision (with its distance to the FP64 result),
+the roofline of the dominant kernel (algorithmic bytes per launch over its
+mean duration, measured with HIP events on the solver's stream) with its
+measured HBM traffic, and the CPU oracle on the same load steps at a small
+size.  Optional samples (--omega-sweep, --with-serve, --with-surfing,
+--with-tshock, --with-deflation) add the other workloads to the same line.
 """
 
 import argparse
@@ -37,31 +40,37 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_sample=256, n_full=2048, model="AT1"):
+def cpu_baseline(n_sample, steps, model="AT1"):
     """The oracle (assembled sparse FE, exact LU solves, exact box-QP active
-    set) on the same recipe at n_sample^2, load step 1; its time per load step
-    is scaled by the node ratio to the n_full^2 workload."""
-    import numpy as np
+    set, exact-LU reduced Newton) on the same recipe and the same load steps
+    as the GPU leg, ORAM-N at omega = 1 with the same switch and stop
+    tolerances, at n_sample^2: its own load steps/s at that size, with no
+    extrapolation to the GPU's size."""
     from oracle import am, problems
     from paper_1511_08463_amd import workloads
-    p, notch, _ = workloads.small_tension(n_sample, model)
+    p, notch, loads, _ = workloads.config2(model, 1.0, seed=0, n=n_sample)
     P = problems.tension_2d(n_sample, n_sample, **workloads.oracle_kwargs(p))
     st = am.initial_state(P, notch.astype(bool))
+    sweeps = 0
     t0 = time.perf_counter()
-    o = am.solve_load_step(P, st, 0.1, omega=1.0, am_tol=1e-5)
+    for t in loads[:steps]:
+        o = am.solve_load_step(P, st, t, omega=1.0, newton_on=True, switch_tol=1e-3,
+                               final_tol=1e-7, max_am=20000)
+        sweeps += o["sweeps"]
     dt = time.perf_counter() - t0
-    ratio = ((n_full + 1) / (n_sample + 1)) ** 2
     threads = os.environ.get("OMP_NUM_THREADS", "unset")
     return {
-        "value": 1.0 / (dt * ratio),
-        "unit": "load steps/s",
+        "value": steps / dt,
+        "unit": f"load steps/s at {n_sample}x{n_sample}",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"oracle load step 1 (t=0.1, {o['sweeps']} AM sweeps to ||dalpha||inf<1e-5) of the "
-                   f"same recipe at {n_sample}x{n_sample}: {dt:.2f} s, scaled x{ratio:.1f} by node count "
-                   f"to {n_full}x{n_full} (linear-cost assumption; sparse LU grows faster). "
-                   f"SciPy SuperLU and sparse matvec are single-threaded; host cpu_count="
-                   f"{os.cpu_count()}, affinity={len(os.sched_getaffinity(0))}, OMP_NUM_THREADS={threads}"),
+        "sample": (f"oracle ORAM-N (omega=1, switch ||Phi||2<1e-3, stop ||Phi||2<1e-7, exact LU "
+                   f"solves) over load steps 1..{steps} (t=0.1..{0.1 * steps:.1f}, through crack "
+                   f"initiation and the unstable propagation) of the same recipe at "
+                   f"{n_sample}x{n_sample} cells: {sweeps} sweeps in {dt:.2f} s; not scaled to the "
+                   f"GPU's size. SciPy SuperLU and sparse matvec are single-threaded; host "
+                   f"cpu_count={os.cpu_count()}, affinity={len(os.sched_getaffinity(0))}, "
+                   f"OMP_NUM_THREADS={threads}"),
         "seconds": dt,
     }
 
@@ -118,7 +127,7 @@ def thermal(args):
 
 
 KERNELS = ("smooth", "apply", "vi_eval", "helm", "copy")
-LIVE_CAP = 4096   # finest-level Chebyshev steps timed (every fifth of the ~4900 of the timed region)
+LIVE_CAP = 16384  # finest-level Chebyshev steps timed (every fifth, from the start of the timed region)
 
 
 def roofline(live, dom, traffic, rl):
@@ -347,18 +356,20 @@ def deflation(args):
     return out
 
 
-def main():
+def parse_args(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=13, help="timed load steps")
-    ap.add_argument("--warmup", type=int, default=1, help="untimed load steps first")
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed load steps: steps 1..K of the 20-step load path")
+    ap.add_argument("--warmup", type=int, default=1,
+                    help="untimed load steps run first on a separate instance that is then discarded")
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--model", default="AT1")
     ap.add_argument("--omega", type=float, default=1.0)
     ap.add_argument("--omega-auto", action="store_true",
                     help="per-step omega from the measured AM convergence factor (cap: --omega)")
     ap.add_argument("--am-tol", type=float, default=1e-5)
-    ap.add_argument("--max-am", type=int, default=5000, help="sweep limit per load step")
+    ap.add_argument("--max-am", type=int, default=30000, help="sweep limit per load step")
     ap.add_argument("--pcg-rtol", type=float, default=1e-8)
     ap.add_argument("--newton", type=int, default=1, help="ORAM-N (1) or ORAM alone (0)")
     ap.add_argument("--switch-tol", type=float, default=1e-3)
@@ -380,46 +391,87 @@ def main():
     ap.add_argument("--forcing-mode", type=int, default=1,
                     help="1: Eisenstat-Walker forcing terms; 0: the final-tolerance target")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--cpu-n", type=int, default=32,
+                    help="mesh of the oracle's CPU baseline (same recipe and load steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--mixed-budget", type=float, default=300.0,
+                    help="skip the mixed leg when the FP64 leg took longer than this (s), so the "
+                         "default run stays within minutes")
+    ap.add_argument("--snap-step", type=int, default=9,
+                    help="load step whose state the mixed leg is also compared at (9: t = 0.9, "
+                         "before initiation); 0 for none")
+    ap.add_argument("--deflate", action="store_true",
+                    help="deflate the elastic CG of the headline legs by the fragments' rigid modes")
+    # optional samples of the other workloads in the same JSON line
+    ap.add_argument("--omega-sweep", action="store_true",
+                    help="also time the same steps at omega = 1.4 and 1.8")
+    ap.add_argument("--with-serve", action="store_true", help="also run the served-stream sample")
+    ap.add_argument("--with-surfing", action="store_true", help="also run the surfing sample")
+    ap.add_argument("--with-tshock", action="store_true", help="also run the thermal shock sample")
+    ap.add_argument("--with-deflation", action="store_true", help="also run the deflation sample")
+    # one workload alone
     ap.add_argument("--serve", action="store_true", help="run only the served stream")
     ap.add_argument("--thermal", action="store_true", help="run only the 3D thermal slab (config 3)")
     ap.add_argument("--dt-factor", type=float, default=16.0, help="thermal ramp end in units of DT_c")
     ap.add_argument("--surfing", action="store_true", help="run only the surfing slab (Sec. 4.1)")
     ap.add_argument("--surf-ell", type=float, default=1.0 / 128)
-    ap.add_argument("--no-surfing", action="store_true", help="skip the surfing sample")
     ap.add_argument("--tshock", action="store_true",
                     help="run only the 2D thermal shock omega sweep (Sec. 4.3, Table 3)")
-    ap.add_argument("--no-tshock", action="store_true", help="skip the thermal shock sample")
     ap.add_argument("--tshock-n", type=int, default=256, help="thermal shock cells along the slab")
     ap.add_argument("--tshock-tau", type=float, default=2.0, help="last tau of the thermal shock")
     ap.add_argument("--tshock-max-am", type=int, default=20000, help="sweep limit per thermal shock step")
-    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream sample")
     ap.add_argument("--deflation", action="store_true",
                     help="run only the deflated vs plain elastic CG comparison")
-    ap.add_argument("--no-deflation", action="store_true", help="skip the deflation sample")
-    ap.add_argument("--deflate", action="store_true",
-                    help="deflate the elastic CG of the headline legs by the fragments' rigid modes")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
-    ap.add_argument("--no-omega", action="store_true", help="skip the omega = 1.4, 1.8 legs")
-    ap.add_argument("--omega-steps", type=int, default=4,
-                    help="timed load steps of the omega = 1.4, 1.8 legs (after the same warm-up)")
-    ap.add_argument("--snap-step", type=int, default=9,
-                    help="load step whose state the mixed leg is also compared at (9: t = 0.9, "
-                         "before initiation); 0 for none")
     ap.add_argument("--kernels-only", action="store_true",
                     help="time the hot kernels only (no solve), e.g. under hardware counters")
     ap.add_argument("--instances", type=int, default=48)
     ap.add_argument("--budget-gb", type=float, default=4.0)
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--slots", type=int, default=32)
-    args = ap.parse_args()
+    ap.add_argument("--dry-run", action="store_true",
+                    help="validate the arguments, print the plan as JSON and exit (no GPU)")
+    return ap.parse_args(argv)
 
+
+NSTEPS = 20   # the load path of the workload: t = 0.1 k, k = 1..20
+
+
+def plan(args):
+    """Validated run plan, or (None, message) for an invalid request."""
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the multi-GPU decomposition is a design, not built)"}))
+        return None, ("this build runs on one GPU only; --gpus must be 1 "
+                      "(the multi-GPU decomposition is a design, not built)")
+    if not 1 <= args.steps <= NSTEPS:
+        return None, f"--steps must be in 1..{NSTEPS} (the load path has {NSTEPS} steps)"
+    if args.warmup < 0:
+        return None, "--warmup must be >= 0"
+    return {"timed_steps": list(range(1, args.steps + 1)),
+            "warmup_steps": list(range(1, min(args.warmup, NSTEPS) + 1)),
+            "warmup_instance": "separate, discarded before the timed instance is created",
+            "legs": (["fp64" if args.precision == "fp64" else "mixed"]
+                     + (["mixed"] if args.precision == "fp64" and not args.no_mixed else [])
+                     + (["omega 1.4", "omega 1.8"] if args.omega_sweep else [])
+                     + (["serve"] if args.with_serve else []) + (["surfing"] if args.with_surfing else [])
+                     + (["tshock"] if args.with_tshock else [])
+                     + (["deflation"] if args.with_deflation else [])
+                     + ([] if args.no_cpu_baseline else [f"cpu_baseline {args.cpu_n}^2"]))}, None
+
+
+def pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=float), q)) if len(v) else None
+
+
+def main():
+    args = parse_args()
+    pl, err = plan(args)
+    if pl is None:
+        print(json.dumps({"error": err}), flush=True)
         sys.exit(2)
-    if args.warmup + max(args.steps, args.omega_steps) > 20:
-        sys.exit("warmup + steps must be <= 20 (the load sequence has 20 steps)")
+    if args.dry_run:
+        print(json.dumps({"plan": pl}), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -475,30 +527,27 @@ def main():
 
     free_dofs = 2 * (args.n + 1) ** 2 - (args.n + 1) * 2 - 1
 
-    def leg(precision, omega=None, steps=None, live=False):
-        """W untimed + K timed load steps of one solver instance.  live: time
-        every finest-level Chebyshev step of the timed region with HIP events
-        on the solver's stream (the roofline's kernel)."""
+    def leg(precision, omega=None, live=False):
+        """W untimed load steps on a discarded instance, then load steps
+        1..K of a fresh instance, timed.  live: time the finest-level
+        Chebyshev steps of the timed region with HIP events on the solver's
+        stream (the roofline's kernel)."""
         om = args.omega if omega is None else omega
-        nsteps = args.steps if steps is None else steps
         log(f"[bench] {precision} {args.n}^2 {args.model} omega={om} notch y0={y0:.4f} "
-            f"a={a:.4f} warmup={args.warmup} steps={nsteps}")
-        solver = make_solver(precision, om)
+            f"a={a:.4f} warmup={args.warmup} (discarded instance) steps={args.steps}")
         last = [time.perf_counter()]
 
         def monitor(sweep, da, phi):
-            # progress every few seconds (the call that carries ||Phi|| when there is one)
+            # progress every few seconds
             now = time.perf_counter()
-            if now - last[0] > 5.0 and (phi >= 0.0 or not args.newton):
+            if now - last[0] > 10.0:
                 last[0] = now
                 log(f"[bench]   ... sweep/newton {sweep} dalpha={da:.2e} phi={phi:.2e}")
 
-        solver.set_monitor(monitor)
-
-        def run(k):
+        def run(solver, k, tag):
             solver.set_load(loads[k])
             st = solver.solve_step()
-            log(f"[bench] {precision} step {k + 1} t={loads[k]:.2f} sweeps={st['sweeps']} "
+            log(f"[bench] {precision} {tag} step {k + 1} t={loads[k]:.2f} sweeps={st['sweeps']} "
                 f"pcg={st['pcg_iters']} vi={st['vi_iters']} vi_cg={st['vi_cg_iters']} "
                 f"newton={st['newton_iters']} minres={st['minres_iters']} "
                 f"fails={st['newton_failures']} dalpha={st['dalpha_inf']:.2e} phi={st['phi_l2']:.2e} "
@@ -506,15 +555,25 @@ def main():
                 f"newton {st['ms_newton']:.1f})")
             return st
 
-        for k in range(args.warmup):
-            run(k)
+        if args.warmup:
+            warm = make_solver(precision, om)
+            warm.set_monitor(monitor)
+            for k in range(min(args.warmup, NSTEPS)):
+                run(warm, k, "warm-up")
+            torch.cuda.synchronize()
+            warm.close()
+            del warm
+        solver = make_solver(precision, om)
+        solver.set_monitor(monitor)
         if live:
             fracture.fracture_kernel_timing(solver.h, fracture.FRACTURE_KERNEL_SMOOTH, LIVE_CAP)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        stats, snap, paused = [], None, 0.0
-        for k in range(args.warmup, args.warmup + nsteps):
-            stats.append(run(k))
+        stats, snap, paused, step_s = [], None, 0.0, []
+        for k in range(args.steps):
+            ts = time.perf_counter()
+            stats.append(run(solver, k, "timed"))
+            step_s.append(time.perf_counter() - ts)
             if k + 1 == args.snap_step:
                 # the state before crack initiation, copied out untimed
                 torch.cuda.synchronize()
@@ -535,15 +594,20 @@ def main():
                     f"{live_stats['gbs']:.0f} GB/s")
         pcg_iters = sum(s["pcg_iters"] for s in stats)
         pcg_s = sum(s["ms_pcg"] for s in stats) / 1e3
+        step_ms = [round(s["ms_total"], 2) for s in stats]
         res = {
-            "value": nsteps / elapsed,
-            "ms_per_step": 1e3 * elapsed / nsteps,
+            "value": args.steps / elapsed,
+            "ms_per_step": 1e3 * elapsed / args.steps,
+            "seconds": elapsed,
             "pcg_dof_iter_per_s": free_dofs * pcg_iters / pcg_s if pcg_s > 0 else None,
             "sweeps": sum(s["sweeps"] for s in stats),
             "pcg_iters": pcg_iters,
+            "vi_cg_iters": sum(s["vi_cg_iters"] for s in stats),
             "newton_iters": sum(s["newton_iters"] for s in stats),
             "minres_iters": sum(s["minres_iters"] for s in stats),
-            "step_ms": [round(s["ms_total"], 2) for s in stats],
+            "step_ms": step_ms,
+            "step_sweeps": [s["sweeps"] for s in stats],
+            "p50_step_ms": pct(step_ms, 50), "p99_step_ms": pct(step_ms, 99),
             "live": live_stats,
         }
         state = solver.state()
@@ -555,6 +619,7 @@ def main():
     solver.close()
     dom = rl["smooth"]
     traffic = recorded_traffic()
+    precision_note = ("f64" if args.precision == "fp64" else "f32 operator and multigrid inside f64 refinement")
     out = {
         "metric": METRIC,
         "value": res["value"],
@@ -566,12 +631,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32 inside f64 refinement",
+        "dtype": precision_note,
         "data": "synthetic",
         "config": {
             "workload": (f"{args.n}x{args.n} plane-strain unit square, P1 right-diagonal triangles, "
                          f"{args.model}, ell=4h, k_ell=1e-6, seeded edge notch (y0={y0:.4f}, a={a:.4f}), "
-                         f"tension load steps t=0.1k, k={args.warmup + 1}..{args.warmup + args.steps} timed; "
+                         f"tension load steps t=0.1k, k=1..{args.steps} of {NSTEPS} all timed "
+                         f"(elastic loading, crack initiation, stable growth, the unstable "
+                         f"propagation through the specimen and the separated body); "
                          + (f"ORAM omega={args.omega} switching to reduced-space Newton at ||Phi||2<{args.switch_tol:g}, "
                             f"stop ||Phi||2<{args.final_tol:g}, MINRES forcing "
                             + ((("Eisenstat-Walker, " if args.forcing_mode == 1 else "")
@@ -582,54 +649,67 @@ def main():
                             f"ORAM omega={args.omega} to ||dalpha||inf<{args.am_tol:g}")
                          + f", PCG rtol {args.pcg_rtol:g}"
                          + (f" (ORAM sweeps: or {args.pcg_reduction:g} x warm-start residual)"
-                            if args.newton and args.pcg_reduction > 0 else "")),
+                            if args.newton and args.pcg_reduction > 0 else "")
+                         + f"; {args.warmup} warm-up load step(s) on a separate, discarded instance"),
             "precision": args.precision,
             "newton": bool(args.newton),
             "deflate": bool(args.deflate),
         },
+        "seconds": res["seconds"],
         "pcg_dof_iter_per_s": res["pcg_dof_iter_per_s"],
         "sweeps": res["sweeps"],
         "pcg_iters": res["pcg_iters"],
+        "vi_cg_iters": res["vi_cg_iters"],
         "newton_iters": res["newton_iters"],
         "minres_iters": res["minres_iters"],
         "step_ms": res["step_ms"],
+        "step_sweeps": res["step_sweeps"],
+        "p50_step_ms": res["p50_step_ms"],
+        "p99_step_ms": res["p99_step_ms"],
         "roofline": roofline(res["live"], dom, traffic, rl),
     }
-    if not args.no_omega and args.precision == "fp64":
+    if args.omega_sweep and args.precision == "fp64":
         # the other over-relaxation factors of the workload, same load steps
         out["omega_sweep"] = {}
         for om in (1.4, 1.8):
             if om == args.omega:
                 continue
-            s_om, r_om, _, _ = leg(args.precision, omega=om, steps=args.omega_steps)
+            s_om, r_om, _, _ = leg(args.precision, omega=om)
             s_om.close()
             out["omega_sweep"][f"{om:g}"] = {k: r_om[k] for k in ("value", "ms_per_step", "sweeps",
                                                                   "pcg_iters", "newton_iters",
-                                                                  "minres_iters")}
-            out["omega_sweep"][f"{om:g}"]["load_steps"] = (
-                f"{args.warmup + 1}..{args.warmup + args.omega_steps}")
+                                                                  "minres_iters", "step_sweeps")}
     if not args.no_mixed and args.precision == "fp64":
-        # the same load steps with the float32 operator and multigrid inside
-        # float64 refinement, against the float64 run just made
-        s32, r32, (state32, snap32), energy32 = leg("mixed")
-        s32.close()
-        rel = lambda a_, b_: float(np.linalg.norm(a_ - b_) / max(np.linalg.norm(b_), 1e-300))
-        out["mixed"] = {
-            "value": r32["value"], "unit": "load steps/s", "ms_per_step": r32["ms_per_step"],
-            "pcg_dof_iter_per_s": r32["pcg_dof_iter_per_s"], "pcg_iters": r32["pcg_iters"],
-            "minres_iters": r32["minres_iters"], "speedup_vs_fp64": r32["value"] / res["value"],
-            "rel_l2_u_vs_fp64": rel(state32[0], state64[0]),
-            "rel_l2_alpha_vs_fp64": rel(state32[1], state64[1]),
-            "rel_energy_vs_fp64": abs(sum(energy32) - sum(energy64)) / abs(sum(energy64)),
-        }
-        if snap32 is not None and snap64 is not None:
-            # before initiation the two runs track one solution branch; at
-            # initiation each may select a different one (the crack path is a
-            # bifurcation), so the distance after it is not a rounding measure
-            out["mixed"][f"rel_l2_u_vs_fp64_t{loads[args.snap_step - 1]:.1f}"] = rel(snap32[0], snap64[0])
-            out["mixed"][f"rel_l2_alpha_vs_fp64_t{loads[args.snap_step - 1]:.1f}"] = rel(snap32[1],
-                                                                                      snap64[1])
-    if not args.no_serve:
+        if res["seconds"] > args.mixed_budget:
+            out["mixed"] = {"skipped": f"the FP64 leg took {res['seconds']:.0f} s > --mixed-budget "
+                                       f"{args.mixed_budget:g} s"}
+        else:
+            # the same load steps with the float32 operator and multigrid inside
+            # float64 refinement, against the float64 run just made
+            s32, r32, (state32, snap32), energy32 = leg("mixed")
+            s32.close()
+            rel = lambda a_, b_: float(np.linalg.norm(a_ - b_) / max(np.linalg.norm(b_), 1e-300))
+            out["mixed"] = {
+                "value": r32["value"], "unit": "load steps/s", "ms_per_step": r32["ms_per_step"],
+                "pcg_dof_iter_per_s": r32["pcg_dof_iter_per_s"], "pcg_iters": r32["pcg_iters"],
+                "sweeps": r32["sweeps"], "step_sweeps": r32["step_sweeps"],
+                "minres_iters": r32["minres_iters"], "speedup_vs_fp64": r32["value"] / res["value"],
+                "p50_step_ms": r32["p50_step_ms"], "p99_step_ms": r32["p99_step_ms"],
+                "rel_l2_u_vs_fp64": rel(state32[0], state64[0]),
+                "rel_l2_alpha_vs_fp64": rel(state32[1], state64[1]),
+                "rel_energy_vs_fp64": abs(sum(energy32) - sum(energy64)) / abs(sum(energy64)),
+                "rel_surface_energy_vs_fp64": abs(energy32[1] - energy64[1]) / abs(energy64[1]),
+                "iou_crack_vs_fp64": float(np.sum((state32[1] > 0.5) & (state64[1] > 0.5))
+                                           / max(np.sum((state32[1] > 0.5) | (state64[1] > 0.5)), 1)),
+            }
+            if snap32 is not None and snap64 is not None:
+                # before initiation the two runs track one solution branch; at
+                # initiation each may select a different one (the crack path is a
+                # bifurcation), so the distance after it is not a rounding measure
+                out["mixed"][f"rel_l2_u_vs_fp64_t{loads[args.snap_step - 1]:.1f}"] = rel(snap32[0], snap64[0])
+                out["mixed"][f"rel_l2_alpha_vs_fp64_t{loads[args.snap_step - 1]:.1f}"] = rel(snap32[1],
+                                                                                          snap64[1])
+    if args.with_serve:
         sv = serve(args)
         out["serving"] = {k: sv[k] for k in ("instances", "steps", "wall_s", "steps_per_s",
                                              "instances_per_s", "p50_ms", "p99_ms",
@@ -638,23 +718,24 @@ def main():
                                       f"(n in 64..1024, ell in [0.01,0.05], h=ell/4, 10-30 steps, "
                                       f"Poisson 50/s), mixed precision, budget {args.budget_gb} GB, "
                                       f"{args.workers} workers")
-    if not args.no_surfing:
-        # the second workload: the surfing slab at ell = 1/64, ORAM-N with the
-        # automatic over-relaxation factor (cap 1.9)
+    if args.with_surfing:
+        # the surfing slab at ell = 1/64, ORAM-N with the automatic
+        # over-relaxation factor (cap 1.9)
         sargs = argparse.Namespace(**vars(args))
         sargs.surf_ell, sargs.omega, sargs.precision, sargs.newton = 1.0 / 64, 1.9, "fp64", 1
         sargs.omega_auto = True
         sargs.forcing_mode = 0
+        sargs.max_am = 5000
         out["surfing"] = surfing(sargs)
-    if not args.no_tshock:
-        # the third workload: the 2D thermal shock at DT = 4 DT_c, plain ORAM at
-        # omega = 1 and at the paper's best over-relaxation 1.6
+    if args.with_tshock:
+        # the 2D thermal shock at DT = 4 DT_c, plain ORAM at omega = 1 and at
+        # the paper's best over-relaxation 1.6
         out["tshock"] = tshock(args, ratios=(4.0,), omegas=(1.0, 1.6))
-    if not args.no_deflation:
+    if args.with_deflation:
         out["deflation"] = deflation(args)
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(256, args.n, args.model)
+        log(f"[bench] cpu baseline (oracle, {args.cpu_n}^2, load steps 1..{args.steps}) ...")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.steps, args.model)
         log(f"[bench] cpu baseline {out['cpu_baseline']['seconds']:.1f} s")
     print(json.dumps(out), flush=True)
 

@@ -142,3 +142,25 @@ def test_bench_refuses_more_than_one_gpu():
     assert out.returncode == 2
     msg = json.loads(out.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+def test_bench_accepts_the_drivers_command():
+    """`bench.py --gpus 1 --steps 20 --warmup 5` is a valid request: all 20
+    load steps are timed, the warm-up runs on a separate instance."""
+    import json
+    import subprocess
+    import sys
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "1", "--steps", "20",
+                          "--warmup", "5", "--dry-run"], capture_output=True, text=True, timeout=120,
+                         cwd=ROOT)
+    assert out.returncode == 0, out.stderr
+    pl = json.loads(out.stdout.strip().splitlines()[-1])["plan"]
+    assert pl["timed_steps"] == list(range(1, 21))
+    assert pl["warmup_steps"] == [1, 2, 3, 4, 5]
+    assert "separate" in pl["warmup_instance"]
+    assert pl["legs"][0] == "fp64" and "mixed" in pl["legs"]
+    # the default run is the same plan with one warm-up step
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--dry-run"],
+                         capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert out.returncode == 0
+    assert json.loads(out.stdout.strip().splitlines()[-1])["plan"]["timed_steps"] == list(range(1, 21))
