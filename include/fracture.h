@@ -49,6 +49,8 @@ extern "C" {
 #define FRACTURE_ENOTCONV   -3  /* iteration limit hit; state rolled back      */
 #define FRACTURE_ENONFINITE -4  /* NaN/Inf met in a reduction; state rolled back */
 #define FRACTURE_EDEVICE    -5  /* a HIP runtime call failed                   */
+#define FRACTURE_ESCRATCH   -6  /* problem needs more than the static scratch of
+                                   fracture_energy_noalloc                     */
 
 /* ---- enumerations ------------------------------------------------------ */
 #define FRACTURE_AT1 1          /* w(alpha) = alpha,   c_w = 8/3 (Sec. 1.1)     */
@@ -264,6 +266,32 @@ int fracture_set_monitor(fracture_t h, fracture_monitor_fn fn, void* user);
 /* Elastic and surface parts of eq. (regenergy) at the current state
    (host outputs). */
 int fracture_energy(fracture_t h, double* elastic, double* surface);
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc): the energies of
+   fracture_energy for a state given by the caller, with no handle and no
+   allocation of any kind.
+   p:        problem parameters (validated as by fracture_create).
+   load:     the load of the state (t, DT or tau; it sets the eigenstrain of
+             the thermal loads and is ignored by the tension and surfing
+             loads).
+   d_u:      device, dim*N doubles, blocked layout; d_alpha: device, N doubles.
+   hip_stream: the stream the kernels and the copy are queued on; it must
+             belong to the current device.  Nothing is synchronised: the
+             result is ready when the stream reaches this point.
+   d_out:    device, 2 doubles: [elastic, surface] as fracture_energy returns.
+   The partial sums, scalars and (3D) per-tetrahedron energies live in one
+   32 MiB static device array per device, kept until the process ends.  2D
+   meshes of any accepted size fit; 3D meshes fit up to about 690,000
+   hexahedra (6 tetrahedra x 8 bytes each), larger ones return
+   FRACTURE_ESCRATCH before anything is queued.  Every call on a device
+   shares that device's array: calls that overlap on one device (on
+   different streams, or from different threads) race and corrupt each
+   other's result; serialise them.  The array needs no clearing between
+   calls (every entry a call reads, it wrote first).
+   Errors: EINVAL (bad parameters or NULL pointers), ESCRATCH, EDEVICE. */
+int fracture_energy_noalloc(const fracture_params* p, double load, const double* d_u,
+                            const double* d_alpha, void* hip_stream, double* d_out);
 
 /* Copy the state out of / into the handle.  Pointers may be host or device
    (detected with hipPointerGetAttributes); lengths dim*N, N, N.  Any pointer

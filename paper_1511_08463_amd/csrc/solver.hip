@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <utility>
@@ -215,6 +216,19 @@ int bc_kind2d(int load_kind) {
   return BC_TENSION_2D;
 }
 
+// One structured level of the problem p with the given cells and spacings
+// (no eigenstrain: with_load adds the load's).
+Grid make_grid(const fracture_params* p, int nx, int ny, int nz, double hx, double hy, double hz) {
+  Grid g{};
+  g.nx = nx; g.ny = ny; g.nz = nz; g.hx = hx; g.hy = hy; g.hz = hz;
+  g.N = (nx + 1) * (ny + 1) * (p->dim == 3 ? nz + 1 : 1);
+  g.bc = p->dim == 3 ? BC_THERMAL_3D : bc_kind2d(p->load_kind);
+  g.dim = p->dim;
+  g.eig_dT = 0.0;
+  g.eig_depth = p->thermal_depth;
+  return g;
+}
+
 // Level shapes: halve both axes while they stay even and the level has more
 // DOFs than coarse_max_dofs (at least once, so there is always a coarse level).
 int level_shapes(const fracture_params* p, Grid* out) {
@@ -222,18 +236,11 @@ int level_shapes(const fracture_params* p, Grid* out) {
   int nx = p->nx, ny = p->ny, nz = dim == 3 ? p->nz : 0, L = 0;
   double hx = p->lx / nx, hy = p->ly / ny, hz = dim == 3 ? p->lz / nz : 0.0;
   for (;;) {
-    Grid g{};
-    g.nx = nx; g.ny = ny; g.nz = nz; g.hx = hx; g.hy = hy; g.hz = hz;
-    g.N = (nx + 1) * (ny + 1) * (dim == 3 ? nz + 1 : 1);
-    g.bc = dim == 3 ? BC_THERMAL_3D : bc_kind2d(p->load_kind);
-    g.dim = dim;
-    g.eig_dT = 0.0;
-    g.eig_depth = p->thermal_depth;
-    out[L++] = g;
+    out[L++] = make_grid(p, nx, ny, nz, hx, hy, hz);
     bool can = (nx % 2 == 0) && (ny % 2 == 0) && L < MAXLEV;
     if (dim == 2) can = can && nx >= 4 && ny >= 4;
     else can = can && (nz % 2 == 0) && nx >= 2 && ny >= 2 && nz >= 2;
-    if (!can || (L >= 2 && dim * g.N <= p->coarse_max_dofs)) break;
+    if (!can || (L >= 2 && dim * out[L - 1].N <= p->coarse_max_dofs)) break;
     nx /= 2; ny /= 2; hx *= 2; hy *= 2;
     if (dim == 3) { nz /= 2; hz *= 2; }
   }
@@ -440,18 +447,19 @@ double chebyshev_bound3d(const Grid& g, const Mat& m) {
 // load is DT; 2D thermal shock: the load is the time tau, the erfc length
 // ell tau); the residual, W2, energy and coupling blocks of the actual
 // problem use it, operator actions on error equations use the plain grid.
-Grid load_grid(const fracture* h) {
-  Grid g = h->lv[0].g;
+Grid with_load(Grid g, const fracture_params& p, double load) {
   if (g.dim == 3) {
-    g.eig_dT = h->load;
-  } else if (g.bc == BC_TSHOCK_2D && h->load > 0.0) {
-    g.eig_dT = h->p.thermal_dT;
-    g.eig_depth = h->p.ell * h->load;
+    g.eig_dT = load;
+  } else if (g.bc == BC_TSHOCK_2D && load > 0.0) {
+    g.eig_dT = p.thermal_dT;
+    g.eig_depth = p.ell * load;
   } else {
     g.eig_dT = 0.0;
   }
   return g;
 }
+
+Grid load_grid(const fracture* h) { return with_load(h->lv[0].g, h->p, h->load); }
 
 Red red(fracture* h, int cslot, int sslot, int post = P_STORE) {
   return Red{h->part + (size_t)cslot * h->part_n, h->S, sslot, post};
@@ -1405,6 +1413,57 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Static scratch of the no-allocation entry point (fracture_energy_noalloc)
+// ---------------------------------------------------------------------------
+//
+// Callers that cannot allocate (graph capture, serving loops) get their
+// reduction partials, scalars and (3D) element energies from this array
+// instead of a handle's workspace.  Each device that loads the library holds
+// its own copy until the process ends.  Host code never uses the symbol's
+// name as an address: scratch_base() looks up the device address once per
+// device with hipGetSymbolAddress and keeps it.
+
+namespace {
+
+constexpr size_t SCRATCH_BYTES = (size_t)32 << 20;
+constexpr size_t SCRATCH_S_BYTES = 1024;                          // S_COUNT doubles, padded
+constexpr size_t SCRATCH_PART_BYTES = 2 * VGRID * sizeof(double);  // two partial-sum slots
+static_assert(S_COUNT * sizeof(double) <= SCRATCH_S_BYTES, "scalar block");
+
+size_t scratch_energy_bytes(const Grid& g) {
+  size_t b = SCRATCH_S_BYTES + SCRATCH_PART_BYTES;
+  if (g.dim == 3) b += (size_t)6 * g.nx * g.ny * g.nz * sizeof(double);   // W2 per tetrahedron
+  return b;
+}
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+namespace {
+
+// Device address of the current device's scratch (looked up once per device).
+int scratch_base(char** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+    return FRACTURE_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FRACTURE_EDEVICE;
+    g_scratch_ptr[dev] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FRACTURE_OK;
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1640,6 +1699,42 @@ int fracture_energy(fracture_t h, double* elastic, double* surface) {
   return FRACTURE_OK;
 }
 
+int fracture_energy_noalloc(const fracture_params* p, double load, const double* d_u,
+                            const double* d_alpha, void* hip_stream, double* d_out) {
+  if (!d_u || !d_alpha || !d_out || !std::isfinite(load)) return FRACTURE_EINVAL;
+  int rc = validate(p);
+  if (rc) return rc;
+  // the fine grid and its element count decide the scratch it needs
+  const int nz = p->dim == 3 ? p->nz : 0;
+  const Grid g = with_load(make_grid(p, p->nx, p->ny, nz, p->lx / p->nx, p->ly / p->ny,
+                                     p->dim == 3 ? p->lz / nz : 0.0),
+                           *p, load);
+  const size_t need = scratch_energy_bytes(g);
+  if (need > SCRATCH_BYTES) return FRACTURE_ESCRATCH;
+  char* base = nullptr;
+  rc = scratch_base(&base);
+  if (rc) return rc;
+  double* S = (double*)base;
+  double* part = (double*)(base + SCRATCH_S_BYTES);
+  const Red rel{part, S, S_EL, P_STORE}, rsu{part + VGRID, S, S_SURF, P_STORE};
+  const hipStream_t st = (hipStream_t)hip_stream;
+  const Mat m = make_mat(p);
+  const double gc_cw = p->Gc / (p->model == FRACTURE_AT1 ? 8.0 / 3.0 : 2.0);
+  const int at2 = p->model == FRACTURE_AT2;
+  if (p->dim == 3) {
+    double* w2 = (double*)(base + SCRATCH_S_BYTES + SCRATCH_PART_BYTES);
+    launch_w2_3d(st, g, m, d_u, w2);
+    Grid gp = g;
+    gp.eig_dT = 0.0;
+    launch_energy3d(st, gp, m, p->k_ell, gc_cw, p->ell, at2, w2, d_alpha, rel, rsu);
+  } else {
+    launch_energy2d(st, g, m, p->k_ell, gc_cw, p->ell, at2, d_u, d_alpha, rel, rsu);
+  }
+  // S[S_EL], S[S_SURF] are adjacent: one device-to-device copy into the output
+  HIPCHK(hipMemcpyAsync(d_out, S + S_EL, 2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  return hip_ok(hipGetLastError());
+}
+
 int fracture_get_state(fracture_t h, double* u, double* alpha, double* alpha_prev) {
   if (!h) return FRACTURE_EINVAL;
   if (u) HIPCHK(hipMemcpyAsync(u, h->u, h->n2 * sizeof(double), hipMemcpyDefault, h->st));
@@ -1834,6 +1929,7 @@ const char* fracture_strerror(int code) {
     case FRACTURE_ENOTCONV: return "iteration limit reached (state rolled back)";
     case FRACTURE_ENONFINITE: return "non-finite value (state rolled back)";
     case FRACTURE_EDEVICE: return "HIP runtime error";
+    case FRACTURE_ESCRATCH: return "problem larger than the static scratch of the no-allocation entry point";
     default: return "unknown error";
   }
 }

@@ -21,6 +21,7 @@ FRACTURE_ENOMEM = -2
 FRACTURE_ENOTCONV = -3
 FRACTURE_ENONFINITE = -4
 FRACTURE_EDEVICE = -5
+FRACTURE_ESCRATCH = -6
 
 FRACTURE_AT1 = 1
 FRACTURE_AT2 = 2
@@ -99,7 +100,7 @@ EXPORTS = [
     "fracture_gradient", "fracture_levels", "fracture_level_shape", "fracture_strerror",
     "fracture_time_kernel", "fracture_kernel_timing", "fracture_kernel_timing_read",
     "fracture_set_monitor", "fracture_fragments", "fracture_deflation_matrix",
-    "fracture_destroy",
+    "fracture_destroy", "fracture_energy_noalloc",
 ]
 
 MONITOR_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double)
@@ -131,6 +132,7 @@ def load_library(path=LIB_PATH):
         "fracture_solve_step": (ctypes.c_int, [vp, P(fracture_stats)]),
         "fracture_solve_steps": (ctypes.c_int, [P(vp), ctypes.c_int, P(fracture_stats), P(ctypes.c_int)]),
         "fracture_energy": (ctypes.c_int, [vp, dp, dp]),
+        "fracture_energy_noalloc": (ctypes.c_int, [P(fracture_params), ctypes.c_double, vp, vp, vp, vp]),
         "fracture_get_state": (ctypes.c_int, [vp, vp, vp, vp]),
         "fracture_set_state": (ctypes.c_int, [vp, vp, vp, vp]),
         "fracture_apply": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, vp]),
@@ -236,6 +238,13 @@ def fracture_solve_steps(hs):
     codes = (ctypes.c_int * n)()
     load_library().fracture_solve_steps(arr, n, stats, codes)
     return list(codes), [s.as_dict() for s in stats]
+
+
+def fracture_energy_noalloc(p, load, d_u, d_alpha, stream, d_out):
+    """Energies of the state (d_u, d_alpha) into d_out[0:2] (device pointers,
+    as ints), queued on ``stream`` without any allocation."""
+    _check(load_library().fracture_energy_noalloc(ctypes.byref(p), float(load), d_u, d_alpha,
+                                                  stream, d_out), "fracture_energy_noalloc")
 
 
 def fracture_energy(h):

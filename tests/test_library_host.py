@@ -144,6 +144,26 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU" in msg["error"]
 
 
+def test_energy_noalloc_rejects_before_device_work():
+    """NULL pointers, bad parameters and 3D meshes beyond the static scratch
+    are refused before anything touches a device."""
+    lib = fracture.load_library()
+    fake = ctypes.c_void_p(1 << 20)           # never dereferenced: checks come first
+    p = fracture.make_params(**workloads.tension(64, 0.05))
+    rc = lib.fracture_energy_noalloc(ctypes.byref(p), 0.1, None, fake, None, fake)
+    assert rc == fracture.FRACTURE_EINVAL
+    rc = lib.fracture_energy_noalloc(ctypes.byref(p), float("nan"), fake, fake, None, fake)
+    assert rc == fracture.FRACTURE_EINVAL
+    p.nu = 0.5
+    rc = lib.fracture_energy_noalloc(ctypes.byref(p), 0.1, fake, fake, None, fake)
+    assert rc == fracture.FRACTURE_EINVAL
+    # 3D: 6 tetrahedra x 8 bytes per hexahedron must fit in 32 MiB
+    q = fracture.make_params(**workloads.thermal(128, 128, 64))
+    rc = lib.fracture_energy_noalloc(ctypes.byref(q), 1.0, fake, fake, None, fake)
+    assert rc == fracture.FRACTURE_ESCRATCH
+    assert "scratch" in lib.fracture_strerror(fracture.FRACTURE_ESCRATCH).decode()
+
+
 def test_bench_accepts_the_drivers_command():
     """`bench.py --gpus 1 --steps 20 --warmup 5` is a valid request: all 20
     load steps are timed, the warm-up runs on a separate instance."""
