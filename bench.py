@@ -48,14 +48,15 @@ def cpu_baseline(n_sample, steps, model="AT1"):
     extrapolation to the GPU's size."""
     from oracle import am, problems
     from paper_1511_08463_amd import workloads
+    S = workloads.CONFIG2_SOLVER
     p, notch, loads, _ = workloads.config2(model, 1.0, seed=0, n=n_sample)
     P = problems.tension_2d(n_sample, n_sample, **workloads.oracle_kwargs(p))
     st = am.initial_state(P, notch.astype(bool))
     sweeps = 0
     t0 = time.perf_counter()
     for t in loads[:steps]:
-        o = am.solve_load_step(P, st, t, omega=1.0, newton_on=True, switch_tol=1e-3,
-                               final_tol=1e-7, max_am=20000)
+        o = am.solve_load_step(P, st, t, omega=1.0, newton_on=True, switch_tol=S["switch_tol"],
+                               final_tol=S["final_tol"], max_am=20000)
         sweeps += o["sweeps"]
     dt = time.perf_counter() - t0
     threads = os.environ.get("OMP_NUM_THREADS", "unset")
@@ -64,7 +65,8 @@ def cpu_baseline(n_sample, steps, model="AT1"):
         "unit": f"load steps/s at {n_sample}x{n_sample}",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"oracle ORAM-N (omega=1, switch ||Phi||2<1e-3, stop ||Phi||2<1e-7, exact LU "
+        "sample": (f"oracle ORAM-N (omega=1, switch ||Phi||2<{S['switch_tol']:g}, stop ||Phi||2<"
+                   f"{S['final_tol']:g}, exact LU "
                    f"solves) over load steps 1..{steps} (t=0.1..{0.1 * steps:.1f}, through crack "
                    f"initiation and the unstable propagation) of the same recipe at "
                    f"{n_sample}x{n_sample} cells: {sweeps} sweeps in {dt:.2f} s; not scaled to the "
@@ -357,6 +359,7 @@ def deflation(args):
 
 
 def parse_args(argv=None):
+    from paper_1511_08463_amd.workloads import CONFIG2_SOLVER as S
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20,
@@ -368,27 +371,29 @@ def parse_args(argv=None):
     ap.add_argument("--omega", type=float, default=1.0)
     ap.add_argument("--omega-auto", action="store_true",
                     help="per-step omega from the measured AM convergence factor (cap: --omega)")
-    ap.add_argument("--am-tol", type=float, default=1e-5)
-    ap.add_argument("--max-am", type=int, default=30000, help="sweep limit per load step")
-    ap.add_argument("--pcg-rtol", type=float, default=1e-8)
-    ap.add_argument("--newton", type=int, default=1, help="ORAM-N (1) or ORAM alone (0)")
-    ap.add_argument("--switch-tol", type=float, default=1e-3)
-    ap.add_argument("--final-tol", type=float, default=1e-7)
-    ap.add_argument("--minres-rtol", type=float, default=1e-6)
+    ap.add_argument("--am-tol", type=float, default=S["am_tol"])
+    ap.add_argument("--max-am", type=int, default=S["max_am"], help="sweep limit per load step")
+    ap.add_argument("--pcg-rtol", type=float, default=S["pcg_rtol"])
+    ap.add_argument("--newton", type=int, default=S["newton"], help="ORAM-N (1) or ORAM alone (0)")
+    ap.add_argument("--switch-tol", type=float, default=S["switch_tol"])
+    ap.add_argument("--final-tol", type=float, default=S["final_tol"])
+    ap.add_argument("--minres-rtol", type=float, default=S["minres_rtol"])
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--newton-vcycles", type=int, default=1,
+    ap.add_argument("--newton-vcycles", type=int, default=S["newton_vcycles"],
                     help="V-cycles per action of A^-1 in the Newton block preconditioner")
     ap.add_argument("--no-graphs", action="store_true", help="launch eagerly (no HIP graph replay)")
-    ap.add_argument("--cheb-degree", type=int, default=2, help="Chebyshev steps per V-cycle side")
-    ap.add_argument("--newton-precond", type=int, default=1,
+    ap.add_argument("--cheb-degree", type=int, default=S["cheb_degree"], help="Chebyshev steps per V-cycle side")
+    ap.add_argument("--newton-precond", type=int, default=S["newton_precond"],
                     help="0: symmetric block preconditioner (paper), 1: block diagonal")
-    ap.add_argument("--newton-forcing", type=float, default=0.1,
+    ap.add_argument("--newton-forcing", type=float, default=S["newton_forcing"],
                     help="adaptive Newton forcing factor (0: fixed --minres-rtol)")
-    ap.add_argument("--vi-cg-rtol", type=float, default=1e-4,
+    ap.add_argument("--vi-cg-rtol", type=float, default=S["vi_cg_rtol"],
                     help="relative tolerance of the damage CG inside the active-set method")
-    ap.add_argument("--pcg-reduction", type=float, default=0.01,
+    ap.add_argument("--pcg-reduction", type=float, default=S["pcg_reduction"],
                     help="ORAM-N: elastic solves of ORAM sweeps stop at this reduction of the warm-start residual")
-    ap.add_argument("--forcing-mode", type=int, default=1,
+    ap.add_argument("--vi-reduction", type=float, default=S["vi_reduction"],
+                    help="ORAM-N: damage solves of ORAM sweeps stop at this reduction of their starting max |Phi|")
+    ap.add_argument("--forcing-mode", type=int, default=S["newton_forcing_mode"],
                     help="1: Eisenstat-Walker forcing terms; 0: the final-tolerance target")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--cpu-n", type=int, default=32,
@@ -507,6 +512,7 @@ def main():
                                       newton_forcing=args.newton_forcing,
                                       newton_forcing_mode=args.forcing_mode,
                                       pcg_reduction=args.pcg_reduction,
+                                      vi_reduction=args.vi_reduction,
                                       cheb_degree=args.cheb_degree,
                                       newton_precond=args.newton_precond,
                                       omega_auto=1 if args.omega_auto else 0,
@@ -648,7 +654,8 @@ def main():
                             if args.newton else
                             f"ORAM omega={args.omega} to ||dalpha||inf<{args.am_tol:g}")
                          + f", PCG rtol {args.pcg_rtol:g}"
-                         + (f" (ORAM sweeps: or {args.pcg_reduction:g} x warm-start residual)"
+                         + (f" (ORAM sweeps: or {args.pcg_reduction:g} x warm-start residual; damage "
+                            f"solve to {args.vi_reduction:g} x its starting max |Phi|)"
                             if args.newton and args.pcg_reduction > 0 else "")
                          + f"; {args.warmup} warm-up load step(s) on a separate, discarded instance"),
             "precision": args.precision,

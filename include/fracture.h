@@ -196,6 +196,13 @@ typedef struct {
                                default 64                                     */
   int deflate_max_fragments;/* most fragments kept (1..8), the largest first;
                                default 8                                      */
+  double vi_reduction;      /* ORAM-N only (newton = 1): the damage solve of
+                               an ORAM sweep may stop once max |Phi| of its
+                               box QP has fallen by this factor from the
+                               sweep's starting alpha (or at vi_tol,
+                               whichever is looser); the Newton phase
+                               enforces the final accuracy.  In [0, 1);
+                               0 (default): always vi_tol.                    */
 } fracture_params;
 
 /* Fill *p with the documented defaults for a 2D tension problem on an
@@ -312,6 +319,9 @@ int fracture_set_state(fracture_t h, const double* u, const double* alpha,
  *   COUPLING_T   its transpose: dim*N -> N (B^T x).
  *   PRECOND      one multigrid V-cycle (the PCG preconditioner) on the
  *                finest level, Dirichlet rows zero: dim*N -> dim*N.
+ *   RESIDUAL     -K(alpha) x on the free rows, Dirichlet rows zero: the
+ *                residual f - K x that the elastic PCG forms, for a zero
+ *                load f (its kernel): dim*N -> dim*N.
  */
 #define FRACTURE_OP_ELASTICITY  0
 #define FRACTURE_OP_LEVEL       1
@@ -319,6 +329,7 @@ int fracture_set_state(fracture_t h, const double* u, const double* alpha,
 #define FRACTURE_OP_COUPLING    3
 #define FRACTURE_OP_COUPLING_T  4
 #define FRACTURE_OP_PRECOND     5
+#define FRACTURE_OP_RESIDUAL    6
 int fracture_apply(fracture_t h, int op, int level, const double* d_x, double* d_y);
 
 /* Refresh the multigrid coefficients (level averages of a(alpha) and the

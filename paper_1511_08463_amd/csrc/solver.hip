@@ -197,6 +197,7 @@ int validate(const fracture_params* p) {
   if (p->omega_auto != 0 && p->omega_auto != 1) return FRACTURE_EINVAL;
   if (p->newton_forcing_mode != 0 && p->newton_forcing_mode != 1) return FRACTURE_EINVAL;
   if (!(p->pcg_reduction >= 0 && p->pcg_reduction < 1)) return FRACTURE_EINVAL;
+  if (!(p->vi_reduction >= 0 && p->vi_reduction < 1)) return FRACTURE_EINVAL;
   if (!(p->newton_stall > 0 && p->newton_stall <= 1)) return FRACTURE_EINVAL;
   if (p->deflate != 0 && p->deflate != 1) return FRACTURE_EINVAL;
   if (p->deflate &&
@@ -897,11 +898,14 @@ int line_search(fracture* h, double psi0, double slope, bool* accepted) {
   return FRACTURE_OK;
 }
 
+// Under ORAM-N the damage solve of a sweep may stop at vi_reduction times
+// its starting max |Phi| (the Newton phase enforces the final accuracy).
 int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
   const Grid& g = h->lv[0].g;
   hipStream_t st = h->st;
   const int64_t N = h->N;
   HIPCHK(hipMemcpyAsync(h->atil, h->alpha, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  double stop = h->p.vi_tol;
   for (int it = 0;; ++it) {
     launch_vi_eval2d(st, g, h->cL, h->cM, h->cm, h->w2, h->atil, nullptr, h->alpha_prev, h->S,
                      S_MU, 1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2),
@@ -911,7 +915,9 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
     if (rc) return rc;
     const double phimax = h->hS[S_PHIMAX], phi2 = h->hS[S_PHI2];
     if (!std::isfinite(phimax) || !std::isfinite(phi2)) return FRACTURE_ENONFINITE;
-    if (phimax <= h->p.vi_tol) return FRACTURE_OK;
+    if (it == 0 && h->p.newton && h->p.vi_reduction > 0)
+      stop = std::fmax(h->p.vi_tol, h->p.vi_reduction * phimax);
+    if (phimax <= stop) return FRACTURE_OK;
     if (it >= h->p.max_vi) return FRACTURE_ENOTCONV;
     ++*vi_iters;
     // reduced Newton step: H_NN d_N = -F_N (Jacobi CG), d_A = 0.  The CG runs
@@ -1313,6 +1319,15 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
   fracture_stats loc{};
   loc.phi_l2 = -1.0;
   HIPCHK(hipEventRecord(h->ev[0], st));
+  // the coarsest inverse is formed anew from the state at the start of every
+  // load step (NaN reference coefficients), so a step depends on (u, alpha,
+  // alpha_prev, load) alone and a handle resumed from get_state/set_state
+  // continues bit for bit
+  {
+    const Grid& gc = h->lv[h->nlev - 1].g;
+    const size_t ne = (size_t)gc.nx * gc.ny * (gc.dim == 3 ? 6 * (size_t)gc.nz : 2);
+    HIPCHK(hipMemsetAsync(h->dref, 0xFF, ne * sizeof(double), st));
+  }
   HIPCHK(hipMemcpyAsync(h->u_entry, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(h->alpha_entry, h->alpha, N * sizeof(double), hipMemcpyDeviceToDevice, st));
   int rc = FRACTURE_OK;
@@ -1526,6 +1541,7 @@ void fracture_default_params(fracture_params* p, int nx, int ny) {
   p->deflate_theta = 0.5;
   p->deflate_min_nodes = 64;
   p->deflate_max_fragments = DFL_FMAX;
+  p->vi_reduction = 0.0;
 }
 
 size_t fracture_workspace_bytes(const fracture_params* p) {
@@ -1794,6 +1810,10 @@ int fracture_apply(fracture_t h, int op, int level, const double* d_x, double* d
         launch_jac2d(h->st, gl, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask,
                      d_x, nullptr, nullptr, d_y, false, none, none, nullptr);
     } break;
+    case FRACTURE_OP_RESIDUAL:
+      // the elastic PCG's residual kernel with a zero load: -K x on free rows
+      launch_resid2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, d_x, d_y, nullptr, false, none);
+      break;
     case FRACTURE_OP_PRECOND: {
       if (!h->coef_valid) update_coefficients(h);
       double* z = vcycle(h, 0, d_x);

@@ -43,6 +43,7 @@ FRACTURE_OP_DAMAGE_HESS = 2
 FRACTURE_OP_COUPLING = 3
 FRACTURE_OP_COUPLING_T = 4
 FRACTURE_OP_PRECOND = 5
+FRACTURE_OP_RESIDUAL = 6
 
 FRACTURE_KERNEL_APPLY = 0
 FRACTURE_KERNEL_SMOOTH = 1
@@ -76,6 +77,7 @@ class fracture_params(ctypes.Structure):
         ("thermal_dT", ctypes.c_double),
         ("deflate", ctypes.c_int), ("deflate_theta", ctypes.c_double),
         ("deflate_min_nodes", ctypes.c_int), ("deflate_max_fragments", ctypes.c_int),
+        ("vi_reduction", ctypes.c_double),
     ]
 
 

@@ -87,6 +87,24 @@ def config2(model="AT1", omega=1.0, seed=0, n=2048):
     return p, notch, loads, (y0, a)
 
 
+# Solver settings of the config-2 benchmark (bench.py's defaults): ORAM-N at
+# omega = 1, switching to Newton at ||Phi||_2 < 1e-3 and stopping at 1e-9;
+# inside ORAM sweeps the elastic PCG stops at 0.3 of its warm-start residual
+# (or 1e-8 of the load) and the damage solve at 0.3 of its starting max |Phi|,
+# since the Newton phase enforces the final accuracy; damage CG to 1e-4,
+# Eisenstat-Walker MINRES forcing, one V-cycle per action of A^-1 and the
+# block-diagonal Newton preconditioner.  The stop tolerance is tighter than
+# the 1e-7 the paper's experiments use: once the specimen is cut, the
+# translation of the upper piece is held only by the k_ell stiffness of the
+# crack band, so a residual of 1e-7 leaves that soft mode, and u, uncertain
+# beyond 1e-6 relative.  The parity test of the benchmarked path runs with
+# exactly these settings.
+CONFIG2_SOLVER = dict(am_tol=1e-5, pcg_rtol=1e-8, vi_cg_rtol=1e-4, max_am=30000, newton=1,
+                      switch_tol=1e-3, final_tol=1e-9, minres_rtol=1e-6, newton_vcycles=1,
+                      newton_forcing=0.1, newton_forcing_mode=1, pcg_reduction=0.3,
+                      vi_reduction=0.3, cheb_degree=2, newton_precond=1)
+
+
 def small_tension(n, model="AT1", omega=1.0, seed=0, ell=None):
     h = 1.0 / n
     p = tension(n, ell if ell is not None else 4 * h, model, omega)

@@ -83,6 +83,88 @@ def test_full_size_operator_rows():
     s.close()
 
 
+def test_full_size_residual_rows():
+    """The elastic PCG's residual kernel at 2048^2 (the column-tiled form the
+    finest level runs): -K(alpha) x on free rows and zero on Dirichlet rows,
+    at sampled nodes (corners, edges, the notch row and random nodes),
+    against the oracle's assembly of each node's element patch (eq.
+    (elasticity))."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    p, notch, _, (y0, _) = workloads.config2()
+    n, h = N_SIDE, 1.0 / N_SIDE
+    s = fracture.Fracture(fracture.make_params(**p, newton=1), notch, device="cuda:0")
+    N = s.N
+    rng = np.random.default_rng(21)
+    u = rng.standard_normal(2 * N) * 1e-3
+    alpha = rng.uniform(0, 1, N)
+    alpha[notch.astype(bool)] = 1.0
+    s.set_state(u=u, alpha=alpha, alpha_prev=np.zeros(N))
+    r = s.apply(fracture.FRACTURE_OP_RESIDUAL, u)
+    jn = int(round(y0 / h))
+    pts = _samples(n, rng) + [(i, jn) for i in range(0, n + 1, 97)] + [(5, 0), (7, n), (0, 9)]
+    worst = 0.0
+    for (i, j) in pts:
+        X, T, gid, loc = _patch(i, j, n, h)
+        M = _model(p, X, T)
+        up = np.concatenate([u[gid], u[N + gid]])
+        Kp = M.K(alpha[gid])
+        row = Kp @ up
+        g = i + (n + 1) * j
+        m = len(gid)
+        # Dirichlet DOFs: u_y on the bottom and top rows, u_x at node (0, 0)
+        fixed_x = i == 0 and j == 0
+        fixed_y = j == 0 or j == n
+        want = np.array([0.0 if fixed_x else -row[loc], 0.0 if fixed_y else -row[m + loc]])
+        got = np.array([r[g], r[N + g]])
+        if fixed_x:
+            assert got[0] == 0.0
+        if fixed_y:
+            assert got[1] == 0.0
+        scale = np.max(np.abs(Kp.toarray()[[loc, m + loc]])) * np.max(np.abs(up))
+        worst = max(worst, np.max(np.abs(got - want)) / scale)
+    assert worst < 1e-12, worst
+    s.close()
+
+
+def test_full_size_vcycle_symmetric_positive():
+    """The V-cycle at 2048^2 (column-tiled finest-level smoothing, residual
+    and prolongation-fused steps, per-node coarse levels, the LDS tail and
+    the dense coarsest solve) is a symmetric positive definite operator, as
+    the PCG needs: y.Mx = x.My and x.Mx > 0 for random x, y (zero on
+    Dirichlet DOFs), with a cracked damage field."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    p, notch, _, _ = workloads.config2()
+    n = N_SIDE
+    s = fracture.Fracture(fracture.make_params(**p, newton=1), notch, device="cuda:0")
+    N = s.N
+    yy = np.repeat(np.arange(n + 1) / n, n + 1)
+    xx = np.tile(np.arange(n + 1) / n, n + 1)
+    # an AT1 damage band (half-width 2 ell) along y = 0.5 over x < 0.7
+    alpha = np.where(xx < 0.7, np.clip(1.0 - np.abs(yy - 0.5) / (8.0 / n), 0.0, 1.0) ** 2, 0.0)
+    s.set_state(u=np.zeros(2 * N), alpha=alpha, alpha_prev=alpha)
+    fracture.fracture_update_coefficients(s.h)
+    rng = np.random.default_rng(4)
+    free = np.ones(2 * N, bool)
+    free[0] = False                                     # u_x at (0, 0)
+    free[N:N + n + 1] = False                           # u_y on the bottom row
+    free[N + n * (n + 1):] = False                      # u_y on the top row
+    x = np.where(free, rng.standard_normal(2 * N), 0.0)
+    y = np.where(free, rng.standard_normal(2 * N), 0.0)
+    Mx = s.apply(fracture.FRACTURE_OP_PRECOND, x)
+    My = s.apply(fracture.FRACTURE_OP_PRECOND, y)
+    assert np.all(Mx[~free] == 0.0) and np.all(My[~free] == 0.0)
+    a, b = y @ Mx, x @ My
+    scale = np.linalg.norm(x) * np.linalg.norm(Mx) + np.linalg.norm(y) * np.linalg.norm(My)
+    print(f"[vcycle 2048] y.Mx={a:.12e} x.My={b:.12e} rel={abs(a - b) / scale:.2e}", flush=True)
+    assert abs(a - b) <= 1e-10 * scale
+    assert x @ Mx > 0 and y @ My > 0
+    s.close()
+
+
 def test_ragged_large_grid_operator_rows():
     """A grid large enough for the column-tiled operator kernels, with a
     one-node ragged tail in both directions (1537 columns: 24 whole 64-wide
