@@ -204,25 +204,60 @@ def newton(problem, state, tol, max_it=10, zeta=1e-12):
 # one load step
 # ----------------------------------------------------------------------------
 
+# Automatic over-relaxation (an extension: the paper conjectures that the best
+# omega minimises the spectral radius of the over-relaxed iteration, as in SOR
+# theory (Sec. 2.2), and leaves its automatic choice to future work).  A load
+# step starts at omega = 1; every OMEGA_PROBE + 1 sweeps at omega = 1 the
+# convergence factor rho of plain alternate minimisation is estimated from the
+# geometric mean of the OMEGA_PROBE successive ratios of ||dalpha||_inf, and
+# once 0 < rho < 1 the step continues at Young's optimum for SOR,
+# 2 / (1 + sqrt(1 - rho)), capped at the given omega.
+OMEGA_PROBE = 4
+
+
+def young_omega(dalpha_window, cap):
+    """Young's optimal factor from OMEGA_PROBE + 1 successive ||dalpha||_inf
+    values at omega = 1, capped at ``cap``; None when the window does not
+    show a contraction (rho outside (0, 1))."""
+    d0, dk = dalpha_window[0], dalpha_window[-1]
+    if not d0 > 0:
+        return None
+    rho = (dk / d0) ** (1.0 / (len(dalpha_window) - 1))
+    if not 0.0 < rho < 1.0:
+        return None
+    return min(cap, 2.0 / (1.0 + np.sqrt(1.0 - rho)))
+
+
 def solve_load_step(problem, state, load, omega=1.0, relax="project", newton_on=False,
                     am_tol=1e-5, am_stop="dalpha", max_am=1000, switch_tol=1e-3,
                     switch_rel=1e-1, final_tol=1e-7, max_newton=10, qp_tol=None,
-                    trace=None):
+                    trace=None, omega_auto=False):
     """Minimise at load ``load`` starting from ``state`` (which holds
     u_{i-1}, alpha_{i-1}); commit alpha_prev <- alpha at the end.
 
     am_stop: "dalpha" stops ORAM on ||alpha^k - alpha^{k-1}||_inf < am_tol;
     "phi" stops on ||Phi||_2 <= final_tol.  With newton_on the stop is always
-    ||Phi||_2 <= final_tol.
+    ||Phi||_2 <= final_tol.  omega_auto: the factor of each sweep follows the
+    automatic rule above, with ``omega`` as its cap.
     """
     set_load(problem, state, load)
     stats = {"sweeps": 0, "newton_its": 0, "newton_failures": 0, "converged": False,
-             "dalpha_inf": [], "phi": []}
+             "dalpha_inf": [], "phi": [], "omega": []}
     threshold = switch_tol
+    om = 1.0 if omega_auto else omega
+    window = []
     while stats["sweeps"] < max_am:
-        dinf, _ = oram_sweep(problem, state, omega, relax, qp_tol=qp_tol, trace=trace)
+        dinf, _ = oram_sweep(problem, state, om, relax, qp_tol=qp_tol, trace=trace)
         stats["sweeps"] += 1
         stats["dalpha_inf"].append(dinf)
+        stats["omega"].append(om)
+        if omega_auto and om == 1.0:
+            window.append(dinf)
+            if len(window) == OMEGA_PROBE + 1:
+                w = young_omega(window, omega)
+                if w is not None:
+                    om = w
+                window = []
         if not newton_on and am_stop == "dalpha":
             if dinf < am_tol:
                 stats["converged"] = True

@@ -116,3 +116,29 @@ def test_surfing_over_relaxation_trend():
     assert sweeps["auto"] <= 0.6 * sweeps[1.0]
     for om in (1.4, 1.8, "auto"):
         assert _rel(states[om][1], states[1.0][1]) < 1e-3
+
+
+def test_auto_omega_load_path_matches_oracle():
+    """The automatic over-relaxation factor (omega = 1 for a probe window,
+    then Young's optimum from the measured convergence factor, cap 1.9) on
+    the GPU and in the oracle, on the surfing slab at ell = 0.1, t = 0 ..
+    0.3, plain ORAM to ||dalpha||_inf < 1e-9: both pick the same factors and
+    reach the same states (1e-6 relative L2 in u and alpha)."""
+    p, notch, loads = workloads.surfing(0.1, steps=4)
+    print("[surf] automatic omega vs oracle", flush=True)
+    s = _solver(p, notch, omega=1.9, omega_auto=1, am_tol=1e-9, max_am=5000, pcg_rtol=1e-13,
+                vi_cg_rtol=1e-13)
+    P = problems.surfing_2d(p["nx"], p["ny"], **workloads.oracle_kwargs_surfing(p))
+    st = am.initial_state(P, notch.astype(bool))
+    for t in loads:
+        s.set_load(t)
+        g = s.solve_step()
+        o = am.solve_load_step(P, st, t, omega=1.9, omega_auto=True, am_tol=1e-9, max_am=5000)
+        u, a, _ = s.state()
+        eu, ea = _rel(u, st.u), _rel(a, st.alpha)
+        print(f"  t={t:.1f} sweeps gpu/oracle={g['sweeps']}/{o['sweeps']} omega(oracle)="
+              f"{sorted(set(o['omega']))} rel_u={eu:.2e} rel_a={ea:.2e}", flush=True)
+        assert g["converged"] and o["converged"]
+        assert abs(g["sweeps"] - o["sweeps"]) <= 2
+        assert eu < 1e-6 and ea < 1e-6
+    s.close()

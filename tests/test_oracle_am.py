@@ -236,3 +236,66 @@ def test_block_preconditioner_identity():
     assert np.allclose(expanded @ x, np.linalg.solve(P, x))
     # and it is symmetric positive definite
     assert np.allclose(expanded, expanded.T) and np.linalg.eigvalsh(expanded).min() > 0
+
+
+def test_young_omega_matches_sor_theory():
+    """The automatic factor is Young's optimum for SOR: for a consistently
+    ordered matrix (the 1D Laplacian) with Gauss-Seidel convergence factor
+    rho, the SOR iteration matrix at young_omega has the smallest spectral
+    radius over omega, and that radius is omega - 1.  The window is the
+    ||dalpha|| history a contraction by rho leaves."""
+    n = 24
+    A = 2.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    D = np.diag(np.diag(A))
+    L = -np.tril(A, -1)
+    U = -np.triu(A, 1)
+
+    def sor_radius(w):
+        T = np.linalg.solve(D - w * L, (1 - w) * D + w * U)
+        return np.max(np.abs(np.linalg.eigvals(T)))
+
+    rho = sor_radius(1.0)                       # Gauss-Seidel
+    window = [rho ** k for k in range(am.OMEGA_PROBE + 1)]
+    w = am.young_omega(window, 1.99)
+    grid = np.linspace(1.0, 1.99, 397)
+    best = grid[np.argmin([sor_radius(x) for x in grid])]
+    assert abs(w - best) < 0.01
+    assert abs(sor_radius(w) - (w - 1.0)) < 1e-3
+    assert sor_radius(w) <= min(sor_radius(x) for x in grid) + 1e-3
+    # closed form at rho = 0.81 and the cap
+    assert abs(am.young_omega([0.81 ** k for k in range(5)], 1.9) - 2.0 / (1.0 + math.sqrt(0.19))) < 1e-12
+    assert am.young_omega([0.99 ** k for k in range(5)], 1.5) == 1.5
+    # no contraction, no estimate
+    assert am.young_omega([1.0, 1.0, 1.0, 1.0, 2.0], 1.9) is None
+    assert am.young_omega([0.0, 0.0, 0.0, 0.0, 0.0], 1.9) is None
+
+
+def test_auto_omega_load_step():
+    """Automatic over-relaxation on the surfing slab (ell = 0.1, the step
+    from t = 0 to t = 0.1): omega stays 1 for the first probe window, then
+    takes one value in (1, cap]; the step reaches the state of plain
+    alternate minimisation in fewer sweeps.  A step that converges within
+    the first window runs exactly as at omega = 1."""
+    from paper_1511_08463_amd import workloads
+    p, notch, _ = workloads.surfing(0.1, steps=4)
+    P = problems.surfing_2d(p["nx"], p["ny"], **workloads.oracle_kwargs_surfing(p))
+    ref = am.initial_state(P, notch.astype(bool))
+    am.solve_load_step(P, ref, 0.0, am_tol=1e-8, max_am=3000)
+    st = ref.copy()
+    o1 = am.solve_load_step(P, ref, 0.1, am_tol=1e-9, max_am=3000)
+    oa = am.solve_load_step(P, st, 0.1, omega=1.9, omega_auto=True, am_tol=1e-9, max_am=3000)
+    assert o1["converged"] and oa["converged"]
+    k = am.OMEGA_PROBE + 1
+    assert oa["omega"][:k] == [1.0] * k
+    later = set(oa["omega"][k:])
+    assert len(later) == 1 and 1.0 < later.pop() <= 1.9
+    assert oa["sweeps"] < 0.85 * o1["sweeps"]
+    assert np.max(np.abs(st.alpha - ref.alpha)) < 1e-7
+    assert np.linalg.norm(st.u - ref.u) < 1e-6 * np.linalg.norm(ref.u)
+    # an undamaged bar below the elastic limit converges before any estimate
+    B = problems.tension_2d(8, 8, ell=0.1, model="AT1")
+    s1, s2 = am.initial_state(B), am.initial_state(B)
+    q1 = am.solve_load_step(B, s1, 0.05, am_tol=1e-10)
+    q2 = am.solve_load_step(B, s2, 0.05, omega=1.9, omega_auto=True, am_tol=1e-10)
+    assert q1["sweeps"] <= am.OMEGA_PROBE and q2["omega"] == [1.0] * q2["sweeps"]
+    assert np.array_equal(s1.alpha, s2.alpha) and np.array_equal(s1.u, s2.u)
