@@ -810,6 +810,7 @@ int pcg(fracture* h, double tol, int* iters) {
 // float32.  The float64 residual r = f - K x is recomputed before every
 // inner solve, which sees it normalised to unit length.
 constexpr double MIXED_INNER_RTOL = 1e-4;
+constexpr double MIXED_LOOSE = 0.05;
 constexpr int MIXED_MAX_OUTER = 30;
 
 int pcg_mixed(fracture* h, double tol, int* iters) {
@@ -832,7 +833,11 @@ int pcg_mixed(fracture* h, double tol, int* iters) {
     // inner solve of K e = r / |r| in float32
     launch_to_float(st, n2, h->r, h->fr32, 1.0 / rn);
     HIPCHK(hipMemsetAsync(h->fe32, 0, n2 * sizeof(float), st));
-    const double tin = std::fmax(MIXED_INNER_RTOL, 0.5 * tol / rn);
+    // the inner float32 recurrence tracks the true residual to about 1e-4
+    // relative: a loose outer target (an ORAM sweep's reduction) is asked of
+    // the inner solve almost as is, a tight one with a factor 2 to spare
+    const double want = tol / rn;
+    const double tin = std::fmax(MIXED_INNER_RTOL, (want >= MIXED_LOOSE ? 0.9 : 0.5) * want);
     float* z = vcycle0f(h, h->fr32);
     HIPCHK(hipMemcpyAsync(h->fp32, z, n2 * sizeof(float), hipMemcpyDeviceToDevice, st));
     for (int it = 0;; ++it) {

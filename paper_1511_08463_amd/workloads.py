@@ -88,20 +88,21 @@ def config2(model="AT1", omega=1.0, seed=0, n=2048):
 
 
 # Solver settings of the config-2 benchmark (bench.py's defaults): ORAM-N at
-# omega = 1, switching to Newton at ||Phi||_2 < 1e-3 and stopping at 1e-9;
-# inside ORAM sweeps the elastic PCG stops at 0.3 of its warm-start residual
-# (or 1e-8 of the load) and the damage solve at 0.3 of its starting max |Phi|,
-# since the Newton phase enforces the final accuracy; damage CG to 1e-4,
-# Eisenstat-Walker MINRES forcing, one V-cycle per action of A^-1 and the
-# block-diagonal Newton preconditioner.  The stop tolerance is tighter than
-# the 1e-7 the paper's experiments use: once the specimen is cut, the
-# translation of the upper piece is held only by the k_ell stiffness of the
-# crack band, so a residual of 1e-7 leaves that soft mode, and u, uncertain
-# beyond 1e-6 relative.  The parity test of the benchmarked path runs with
-# exactly these settings.
-CONFIG2_SOLVER = dict(am_tol=1e-5, pcg_rtol=1e-8, vi_cg_rtol=1e-4, max_am=30000, newton=1,
+# omega = 1, switching to Newton at ||Phi||_2 < 1e-3 and stopping at 1e-9.
+# Inside ORAM sweeps the subproblems are solved inexactly, since the Newton
+# phase's stop test fixes the accuracy of the converged state: the elastic
+# PCG stops at 0.9 of its warm-start residual (or 1e-8 of the load), the
+# damage active-set iteration at 0.3 of its starting max |Phi|, and each of
+# its reduced CG solves at 0.1 relative.  MINRES forcing by Eisenstat-Walker,
+# one V-cycle per action of A^-1, the block-diagonal Newton preconditioner.
+# The stop tolerance is tighter than the 1e-7 the paper's experiments use:
+# once the specimen is cut, the translation of the upper piece is held only by
+# the k_ell stiffness of the crack band, so a residual of 1e-7 leaves that soft
+# mode, and u, uncertain beyond 1e-6 relative.  The parity test of the
+# benchmarked path runs with exactly these settings.
+CONFIG2_SOLVER = dict(am_tol=1e-5, pcg_rtol=1e-8, vi_cg_rtol=0.1, max_am=30000, newton=1,
                       switch_tol=1e-3, final_tol=1e-9, minres_rtol=1e-6, newton_vcycles=1,
-                      newton_forcing=0.1, newton_forcing_mode=1, pcg_reduction=0.3,
+                      newton_forcing=0.1, newton_forcing_mode=1, pcg_reduction=0.9,
                       vi_reduction=0.3, cheb_degree=2, newton_precond=1)
 
 

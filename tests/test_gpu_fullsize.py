@@ -208,6 +208,71 @@ def test_ragged_large_grid_operator_rows():
     s.close()
 
 
+def _kkt_at_samples(p, s, notch, pts, bound, n, h):
+    """Every component of Phi at the sampled nodes is within bound."""
+    u, a, ap = s.state()
+    N = s.N
+    for (i, j) in pts:
+        if not (0 <= i <= n and 0 <= j <= n):
+            continue
+        X, T, gid, loc = _patch(i, j, n, h)
+        M = _model(p, X, T)
+        up = np.concatenate([u[gid], u[N + gid]])
+        m = len(gid)
+        Eu = M.K(a[gid]) @ up
+        g = i + (n + 1) * j
+        if not (i == 0 and j == 0):
+            assert abs(Eu[loc]) <= bound, (i, j, Eu[loc], bound)
+        if 0 < j < n:
+            assert abs(Eu[m + loc]) <= bound, (i, j, Eu[m + loc], bound)
+        Fa = M.grad_alpha(up, a[gid])[loc]
+        phi = vi.mcp_residual(np.array([a[g]]), np.array([Fa]), np.array([ap[g]]),
+                              np.array([1.0]))[0]
+        assert abs(phi) <= bound, (i, j, phi, a[g], Fa, bound)
+
+
+def test_full_size_bench_path_kkt_through_propagation():
+    """The benchmarked path itself (2048^2, the bench's solver settings):
+    load steps 1..15 through crack initiation (t = 1.0) and the unstable
+    propagation (t = 1.5).  After t = 1.0 and after t = 1.5 the bounds hold
+    at every node, the crack has grown (and after t = 1.5 cut the specimen),
+    and every component of Phi at sampled nodes, many along the crack, is
+    within the reported ||Phi||_2 (eq. (kkt), Algorithm 3's stop test)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    p, notch, loads, (y0, _) = workloads.config2()
+    n, h = N_SIDE, 1.0 / N_SIDE
+    s = fracture.Fracture(fracture.make_params(**p, **workloads.CONFIG2_SOLVER), notch,
+                          device="cuda:0")
+    rng = np.random.default_rng(11)
+    jn = int(round(y0 / h))
+    for k, t in enumerate(loads[:15]):
+        s.set_load(t)
+        st = s.solve_step()
+        assert st["converged"], (k + 1, st)
+        if k + 1 not in (10, 15):
+            continue
+        print(f"[fullsize] t={t:.1f}: sweeps={st['sweeps']} phi={st['phi_l2']:.2e}", flush=True)
+        u, a, ap = s.state()
+        assert np.all(a >= ap) and np.all(a <= 1.0) and np.all(a[notch.astype(bool)] == 1.0)
+        cols = (a.reshape(n + 1, n + 1) > 0.5).any(axis=0)
+        if k + 1 == 15:
+            assert np.all(cols)                       # the specimen is cut
+        else:
+            assert np.count_nonzero(a > 0.5) > np.count_nonzero(notch)
+        # sample along the crack band and at random nodes
+        rows = np.flatnonzero((a.reshape(n + 1, n + 1) > 0.1).any(axis=1))
+        pts = _samples(n, rng, 80)
+        for i in range(0, n + 1, 128):
+            col = a.reshape(n + 1, n + 1)[:, i]
+            jc = int(np.argmax(col)) if col.max() > 0.1 else jn
+            pts += [(i, jc + dj) for dj in (-12, -6, -2, 0, 2, 6, 12)]
+        assert rows.size > 0
+        _kkt_at_samples(p, s, notch, pts, st["phi_l2"] * (1 + 1e-6) + 1e-13, n, h)
+    s.close()
+
+
 def test_full_size_load_step_kkt():
     """The first two bench load steps (ORAM-N): the bounds hold at every node
     and, at sampled nodes, every component of the residual Phi (the free rows

@@ -620,3 +620,33 @@ def test_thermal_3d_load_path_parity(precision):
         grew = grew or a.max() > 0.05
     assert grew
     s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_thermal_3d_developed_crack_parity(precision):
+    """The 3D thermal load driven until the damage reaches its upper bound
+    (a developed surface crack, alpha = 1 on a set of nodes): a 16x4x2 slab
+    (ell = 4h) heated to 80 DT_c in seven AM load steps, FP64 and mixed
+    precision (where float32 coefficients meet (1 - alpha)^2 -> 0 inside the
+    crack), against the oracle at 1e-6 per step."""
+    p = workloads.thermal(16, 4, 2, 1.0, 0.25, 0.125)
+    dtc = workloads.thermal_dtc(p)
+    loads = [f * dtc for f in (4.0, 10.0, 20.0, 30.0, 45.0, 60.0, 80.0)]
+    print(f"[thermal3d crack] precision={precision}", flush=True)
+    s = _solver(p, None, precision=precision, am_tol=1e-10, pcg_rtol=1e-13, vi_cg_rtol=1e-13,
+                max_am=3000)
+    P = _problem3(p)
+    st = am.initial_state(P)
+    for t in loads:
+        s.set_load(t)
+        stats = s.solve_step()
+        am.solve_load_step(P, st, t, am_tol=1e-10, max_am=3000)
+        u, a, ap = s.state()
+        eu, ea = _rel(u, st.u), _rel(a, st.alpha)
+        print(f"  dT={t / dtc:.0f} DT_c sweeps={stats['sweeps']} max_alpha={a.max():.4f} "
+              f"at_bound={int(np.sum(a == 1.0))} rel_u={eu:.2e} rel_a={ea:.2e}", flush=True)
+        assert eu < STEP_TOL and ea < STEP_TOL
+        assert np.all(a >= ap) and np.all(a <= 1.0)
+    # the crack is developed: nodes at the upper bound, in the oracle and here
+    assert np.sum(st.alpha >= 1.0 - 1e-12) >= 10 and np.sum(a >= 1.0 - 1e-12) >= 10
+    s.close()
