@@ -84,7 +84,8 @@ def serve(args):
     reqs = [serving.Request(r["rid"], r["params"], r["notch"], r["loads"], r["arrival"])
             for r in workloads.config5(n_instances=args.instances)]
     budget = int(args.budget_gb * 1e9)
-    log(f"[serve] {len(reqs)} requests, budget {args.budget_gb} GB, {args.workers} workers")
+    log(f"[serve] {len(reqs)} requests, budget {args.budget_gb} GB, {args.workers} workers, "
+        f"GPU_MAX_HW_QUEUES={os.environ.get('GPU_MAX_HW_QUEUES', 'default')}")
     svc = serving.Service(budget, max_slots=args.slots, workers=args.workers)
     summary, _ = svc.run(reqs)
     log(f"[serve] {summary}")
@@ -430,7 +431,10 @@ def parse_args(argv=None):
                     help="run only the deflated vs plain elastic CG comparison")
     ap.add_argument("--kernels-only", action="store_true",
                     help="time the hot kernels only (no solve), e.g. under hardware counters")
-    ap.add_argument("--instances", type=int, default=48)
+    ap.add_argument("--instances", type=int, default=256, help="served stream: requests run")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="served stream: hardware queues of the process (GPU_MAX_HW_QUEUES, at most "
+                         "32), so that the instances' streams do not share four queues")
     ap.add_argument("--budget-gb", type=float, default=4.0)
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--slots", type=int, default=32)
@@ -477,6 +481,9 @@ def main():
     if args.dry_run:
         print(json.dumps({"plan": pl}), flush=True)
         return
+    if args.serve or args.with_serve:
+        # read by the HIP runtime when it initialises (no device call has been made yet)
+        os.environ["GPU_MAX_HW_QUEUES"] = str(max(1, min(args.hw_queues, 32)))
 
     import numpy as np
     import torch
@@ -724,7 +731,7 @@ def main():
         out["serving"]["workload"] = (f"first {args.instances} requests of the seeded config-5 stream "
                                       f"(n in 64..1024, ell in [0.01,0.05], h=ell/4, 10-30 steps, "
                                       f"Poisson 50/s), mixed precision, budget {args.budget_gb} GB, "
-                                      f"{args.workers} workers")
+                                      f"{args.workers} workers, {args.hw_queues} hardware queues")
     if args.with_surfing:
         # the surfing slab at ell = 1/64, ORAM-N with the automatic
         # over-relaxation factor (cap 1.9)

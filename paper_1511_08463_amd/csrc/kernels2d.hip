@@ -1035,6 +1035,9 @@ void launch_jac2d(hipStream_t st, const Grid& g, const Mat& m, double kell, doub
                   const double* alpha, const double* u, const double* w2, const uint8_t* mask,
                   const double* xu, const double* xa, double* yu, double* ya, bool dot, Red ru,
                   Red ra, const double* band) {
+  if (g.dim == 3)
+    return launch_jac3d(st, g, m, kell, cL, cM, alpha, u, w2, mask, xu, xa, yu, ya, dot, ru, ra,
+                        band);
   dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
   Helm hp{cL, cM, 0.0};
   // the coupling blocks carry the stress of u's effective strain: the
@@ -1103,6 +1106,7 @@ __global__ __launch_bounds__(NB) void k_couple_u2d(Grid g, Mat m, const double* 
 void launch_couple_u2d(hipStream_t st, const Grid& g, const Mat& m, const double* alpha,
                        const double* u, const double* xu, const double* xa, const uint8_t* mask,
                        double* yu, int r0, int r1, Red r) {
+  if (g.dim == 3) return launch_couple_u3d(st, g, m, alpha, u, xu, xa, mask, yu, r0, r1, r);
   if (r0 < 0) r0 = 0;
   if (r1 > g.ny) r1 = g.ny;
   if (r1 < r0) return;
@@ -1148,6 +1152,8 @@ __global__ __launch_bounds__(NB) void k_cheb_helm2d(Grid g, Helm hp, const doubl
 void launch_cheb_helm2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
                         const uint8_t* mask, const double* x_in, double* x_out, const double* b,
                         const double* d_in, double* d_out, double cd, double cr) {
+  if (g.dim == 3)
+    return launch_cheb_helm3d(st, g, cL, cM, w2, mask, x_in, x_out, b, d_in, d_out, cd, cr);
   Helm hp{cL, cM, 0.0};
   dim3 gr = node_grid2(g), bl(NB_X, NB_Y);
   hipLaunchKernelGGL(k_cheb_helm2d, gr, bl, 0, st, g, hp, w2, mask, x_in, x_out, b, d_in, d_out, cd, cr);

@@ -635,6 +635,335 @@ void launch_dense_assemble3d(hipStream_t st, const Grid& g, const Mat& m, const 
   hipLaunchKernelGGL(k_dense_assemble3d, dim3(1), dim3(1024), 0, st, g, m, abar, A, S);
 }
 
+// ---------------------------------------------------------------------------
+// coupled Jacobian blocks (Newton step of Algorithm 3 / 4), 3D
+// ---------------------------------------------------------------------------
+//
+// E_ualpha of eq. (offdiag) with a'(alpha) = -2 (1 - alpha), integrated
+// exactly with P1 alpha on a tetrahedron:
+//   B[v, j] = sum_e -2 |T| (B_e^T D eps_e(u))_v (M_ref b_e)_j,
+// b = 1 - alpha, M_ref = (1 + delta_ab)/20 (the consistent P1 mass of a
+// tetrahedron over |T|).  u's strain is its effective strain (eps(u) - eps0)
+// under the thermal load.
+//
+// k_jac_u3d:  y_u = A x_u + B x_a   (A = K(alpha), Dirichlet rows zero)
+// k_jac_a3d:  y_a = B^T x_u + C x_a (C = H, rows and columns of active nodes removed)
+// The 24 (hex offset, tetrahedron, local vertex) incidences of a node are
+// walked from the runtime table c_tets3.
+
+// w^T M_ref b over a tetrahedron's four vertices.
+__device__ __forceinline__ double mref_pair4(const double w[4], const double b[4]) {
+  double wb = 0.0, sw = 0.0, sb = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    wb += w[q] * b[q];
+    sw += w[q];
+    sb += b[q];
+  }
+  return (wb + sw * sb) * (1.0 / 20.0);
+}
+
+// Node indices of tetrahedron p of hex (ci, cj, ck) and the axis of each path
+// step o_s -> o_{s+1}.
+__device__ __forceinline__ void tet_nodes3(const Grid& g, int ci, int cj, int ck, int p, int nd[4],
+                                           int ax[3]) {
+  const int W = g.nx + 1, H = g.ny + 1;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    nd[v] = (ci + c_kuhn_off[p][v][0]) + W * ((cj + c_kuhn_off[p][v][1]) + H * (ck + c_kuhn_off[p][v][2]));
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+    for (int a = 0; a < 3; ++a)
+      if (c_kuhn_off[p][s + 1][a] != c_kuhn_off[p][s][a]) ax[s] = a;
+}
+
+// Displacement gradient G[comp][axis] of the blocked field x on the tetrahedron.
+__device__ __forceinline__ void tet_gradient3(const Grid& g, const double* __restrict__ x,
+                                              const int nd[4], const int ax[3], const double ih[3],
+                                              double G[3][3]) {
+  const int N = g.N;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int s = 0; s < 3; ++s) G[c][ax[s]] = (x[nd[s + 1] + c * N] - x[nd[s] + c * N]) * ih[ax[s]];
+}
+
+// Stress of u on tetrahedron p of hex (ci, cj, ck): sigma = D (eps(u) - eps0).
+template <bool EIG>
+__device__ __forceinline__ void tet_stress3(const Grid& g, const Mat& m, const double* __restrict__ u,
+                                            const int nd[4], const int ax[3], const double ih[3],
+                                            int ci, int p, double S[3][3]) {
+  double G[3][3];
+  tet_gradient3(g, u, nd, ax, ih, G);
+  double e0 = G[0][0], e1 = G[1][1], e2 = G[2][2];
+  if (EIG) {
+    const double xc = (ci + 0.25 * (c_kuhn_off[p][1][0] + c_kuhn_off[p][2][0] + 1)) * g.hx;
+    const double s = -g.eig_dT * exp(-xc / g.eig_depth);
+    e0 -= s; e1 -= s; e2 -= s;
+  }
+  const double tr = e0 + e1 + e2;
+  S[0][0] = m.lam * tr + 2.0 * m.mu * e0;
+  S[1][1] = m.lam * tr + 2.0 * m.mu * e1;
+  S[2][2] = m.lam * tr + 2.0 * m.mu * e2;
+  S[0][1] = S[1][0] = m.mu * (G[0][1] + G[1][0]);
+  S[0][2] = S[2][0] = m.mu * (G[0][2] + G[2][0]);
+  S[1][2] = S[2][1] = m.mu * (G[1][2] + G[2][1]);
+}
+
+// (B x_a) at node (i, j, k): per incident tetrahedron the coefficient
+// -2 w^T M_ref b (w = x_a on inactive nodes, zero on active ones) times the
+// tetrahedron's force sigma(u) grad(phi_v) |T|.
+template <bool EIG>
+__device__ __forceinline__ void coupling_force3d(const Grid& g, const Mat& m,
+                                                 const double* __restrict__ alpha,
+                                                 const double* __restrict__ u,
+                                                 const double* __restrict__ xa,
+                                                 const uint8_t* __restrict__ mask, int i, int j,
+                                                 int k, double f[3]) {
+  const double ih[3] = {1.0 / g.hx, 1.0 / g.hy, 1.0 / g.hz};
+  const double vol = g.hx * g.hy * g.hz / 6.0;
+  f[0] = f[1] = f[2] = 0.0;
+  for (int t = 0; t < 24; ++t) {
+    const int ci = i + c_tets3[t][0], cj = j + c_tets3[t][1], ck = k + c_tets3[t][2];
+    if (ci < 0 || cj < 0 || ck < 0 || ci >= g.nx || cj >= g.ny || ck >= g.nz) continue;
+    const int p = c_tets3[t][3], v = c_tets3[t][4];
+    int nd[4], ax[3];
+    tet_nodes3(g, ci, cj, ck, p, nd, ax);
+    double w[4], b[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      w[q] = mask[nd[q]] ? 0.0 : xa[nd[q]];
+      b[q] = 1.0 - alpha[nd[q]];
+    }
+    const double c = -2.0 * mref_pair4(w, b) * vol;
+    if (c == 0.0) continue;
+    double S[3][3], gv[3];
+    tet_stress3<EIG>(g, m, u, nd, ax, ih, ci, p, S);
+    kuhn_grad(p, v, ih, gv);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) f[a] += c * (S[a][0] * gv[0] + S[a][1] * gv[1] + S[a][2] * gv[2]);
+  }
+}
+
+template <bool HAS_XU, bool HAS_XA, bool DOT, bool EIG>
+__global__ __launch_bounds__(NB) void k_jac_u3d(Grid g, Mat m, double kell,
+                                                const double* __restrict__ alpha,
+                                                const double* __restrict__ u,
+                                                const double* __restrict__ xu,
+                                                const double* __restrict__ xa,
+                                                const uint8_t* __restrict__ mask,
+                                                double* __restrict__ yu, Red r,
+                                                const double* __restrict__ band) {
+  const int i = blockIdx.x * NB_X + threadIdx.x, j = blockIdx.y * NB_Y + threadIdx.y, k = blockIdx.z;
+  double acc = 0.0;
+  // B x_a reaches only rows (j, k) within one cell of an inactive node: with
+  // band = (-r_lo, r_hi) of the inactive row indices j + (ny + 1) k, the rows
+  // r_lo - (ny + 2) .. r_hi + (ny + 2) (band == nullptr: every row)
+  bool couple = HAS_XA;
+  if (HAS_XA && band) {
+    const double rlo = -band[0], rhi = band[1], row = (double)(j + (g.ny + 1) * k);
+    const double pad = (double)(g.ny + 2);
+    couple = rlo <= rhi && row >= rlo - pad && row <= rhi + pad;
+  }
+  if (i <= g.nx && j <= g.ny) {
+    const int N = g.N, n = i + (g.nx + 1) * (j + (g.ny + 1) * k);
+    double f[3] = {0.0, 0.0, 0.0}, d[3];
+    if (HAS_XU) node_force3d<true, true, false, false>(g, m, alpha, kell, xu, i, j, k, f, d);
+    if (couple) {
+      double gc[3];
+      coupling_force3d<EIG>(g, m, alpha, u, xa, mask, i, j, k, gc);
+      f[0] += gc[0]; f[1] += gc[1]; f[2] += gc[2];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double yv = fixed3(g, c, i, j, k) ? 0.0 : f[c];
+      yu[n + c * N] = yv;
+      if (DOT) acc += xu[n + c * N] * yv;
+    }
+  }
+  if (DOT)
+    block_reduce<NB, false>(acc, r, gridDim.x * gridDim.y * gridDim.z,
+                            blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                            threadIdx.x + NB_X * threadIdx.y);
+}
+
+template <bool HAS_XU, bool HAS_XA, bool DOT, bool EIG>
+__global__ __launch_bounds__(NB) void k_jac_a3d(Grid g, Mat m, Helm3 hp,
+                                                const double* __restrict__ alpha,
+                                                const double* __restrict__ u,
+                                                const double* __restrict__ w2,
+                                                const double* __restrict__ xu,
+                                                const double* __restrict__ xa,
+                                                const uint8_t* __restrict__ mask,
+                                                double* __restrict__ ya, Red r) {
+  const int i = blockIdx.x * NB_X + threadIdx.x, j = blockIdx.y * NB_Y + threadIdx.y, k = blockIdx.z;
+  double acc = 0.0;
+  if (i <= g.nx && j <= g.ny) {
+    const int n = i + (g.nx + 1) * (j + (g.ny + 1) * k);
+    double y = 0.0;
+    if (!mask[n]) {
+      if (HAS_XA) {
+        double Hx, gv, Hd;
+        helm_node3d<false, true>(g, hp, w2, xa, nullptr, nullptr, 0.0, mask, i, j, k, Hx, gv, Hd);
+        y += Hx;
+      }
+      if (HAS_XU) {
+        const double ih[3] = {1.0 / g.hx, 1.0 / g.hy, 1.0 / g.hz};
+        const double vol = g.hx * g.hy * g.hz / 6.0;
+        for (int t = 0; t < 24; ++t) {
+          const int ci = i + c_tets3[t][0], cj = j + c_tets3[t][1], ck = k + c_tets3[t][2];
+          if (ci < 0 || cj < 0 || ck < 0 || ci >= g.nx || cj >= g.ny || ck >= g.nz) continue;
+          const int p = c_tets3[t][3], v = c_tets3[t][4];
+          int nd[4], ax[3];
+          tet_nodes3(g, ci, cj, ck, p, nd, ax);
+          double S[3][3], G[3][3];
+          tet_stress3<EIG>(g, m, u, nd, ax, ih, ci, p, S);
+          tet_gradient3(g, xu, nd, ax, ih, G);
+          // sigma(u) : eps(x_u), eps the symmetric part of G
+          double s = 0.0;
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s += S[a][c] * 0.5 * (G[a][c] + G[c][a]);
+          double bs = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bs += 1.0 - alpha[nd[q]];
+          const double mb = ((1.0 - alpha[nd[v]]) + bs) * (1.0 / 20.0);
+          y += -2.0 * vol * s * mb;
+        }
+      }
+    }
+    ya[n] = y;
+    if (DOT) acc = (HAS_XA && !mask[n]) ? xa[n] * y : 0.0;
+  }
+  if (DOT)
+    block_reduce<NB, false>(acc, r, gridDim.x * gridDim.y * gridDim.z,
+                            blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                            threadIdx.x + NB_X * threadIdx.y);
+}
+
+void launch_jac3d(hipStream_t st, const Grid& g, const Mat& m, double kell, double cL, double cM,
+                  const double* alpha, const double* u, const double* w2, const uint8_t* mask,
+                  const double* xu, const double* xa, double* yu, double* ya, bool dot, Red ru,
+                  Red ra, const double* band) {
+  dim3 gr = node_grid3(g), bl(NB_X, NB_Y);
+  Helm3 hp{cL, cM, 0.0};
+  const bool eig = g.eig_dT != 0.0;
+  if (yu) {
+#define JU3(A, B, D)                                                                                \
+  do {                                                                                              \
+    if (eig && B)                                                                                   \
+      hipLaunchKernelGGL((k_jac_u3d<A, B, D, true>), gr, bl, 0, st, g, m, kell, alpha, u, xu, xa,   \
+                         mask, yu, ru, band);                                                       \
+    else                                                                                            \
+      hipLaunchKernelGGL((k_jac_u3d<A, B, D, false>), gr, bl, 0, st, g, m, kell, alpha, u, xu, xa,  \
+                         mask, yu, ru, band);                                                       \
+  } while (0)
+    if (xu && xa) { if (dot) JU3(true, true, true); else JU3(true, true, false); }
+    else if (xu) { if (dot) JU3(true, false, true); else JU3(true, false, false); }
+    else JU3(false, true, false);
+#undef JU3
+    if (dot && xu) launch_finish(st, ru, (int)(gr.x * gr.y * gr.z), false);
+  }
+  if (ya) {
+#define JA3(A, B, D)                                                                                \
+  do {                                                                                              \
+    if (eig && A)                                                                                   \
+      hipLaunchKernelGGL((k_jac_a3d<A, B, D, true>), gr, bl, 0, st, g, m, hp, alpha, u, w2, xu, xa, \
+                         mask, ya, ra);                                                             \
+    else                                                                                            \
+      hipLaunchKernelGGL((k_jac_a3d<A, B, D, false>), gr, bl, 0, st, g, m, hp, alpha, u, w2, xu,    \
+                         xa, mask, ya, ra);                                                         \
+  } while (0)
+    if (xu && xa) { if (dot) JA3(true, true, true); else JA3(true, true, false); }
+    else if (xa) { if (dot) JA3(false, true, true); else JA3(false, true, false); }
+    else JA3(true, false, false);
+#undef JA3
+    if (dot && xa) launch_finish(st, ra, (int)(gr.x * gr.y * gr.z), false);
+  }
+}
+
+// y_u += B x_a on the rows (j, k) whose index j + (ny + 1) k lies in r0..r1,
+// Dirichlet DOFs left alone; partial sums of x_u . B x_a.
+template <bool EIG>
+__global__ __launch_bounds__(NB) void k_couple_u3d(Grid g, Mat m, const double* __restrict__ alpha,
+                                                   const double* __restrict__ u,
+                                                   const double* __restrict__ xu,
+                                                   const double* __restrict__ xa,
+                                                   const uint8_t* __restrict__ mask,
+                                                   double* __restrict__ yu, int r0, int r1, Red r) {
+  const int i = blockIdx.x * NB_X + threadIdx.x;
+  const int row = r0 + blockIdx.y * NB_Y + threadIdx.y;
+  double acc = 0.0;
+  if (i <= g.nx && row <= r1) {
+    const int j = row % (g.ny + 1), k = row / (g.ny + 1);
+    const int N = g.N, n = i + (g.nx + 1) * row;
+    double f[3];
+    coupling_force3d<EIG>(g, m, alpha, u, xa, mask, i, j, k, f);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double gc = fixed3(g, c, i, j, k) ? 0.0 : f[c];
+      yu[n + c * N] += gc;
+      acc += xu[n + c * N] * gc;
+    }
+  }
+  block_reduce<NB, false>(acc, r, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y,
+                          threadIdx.x + NB_X * threadIdx.y);
+}
+
+void launch_couple_u3d(hipStream_t st, const Grid& g, const Mat& m, const double* alpha,
+                       const double* u, const double* xu, const double* xa, const uint8_t* mask,
+                       double* yu, int r0, int r1, Red r) {
+  const int rows = (g.ny + 1) * (g.nz + 1);
+  if (r0 < 0) r0 = 0;
+  if (r1 >= rows) r1 = rows - 1;
+  if (r1 < r0) return;
+  dim3 gr((g.nx + 1 + NB_X - 1) / NB_X, (r1 - r0 + 1 + NB_Y - 1) / NB_Y), bl(NB_X, NB_Y);
+  if (g.eig_dT != 0.0)
+    hipLaunchKernelGGL((k_couple_u3d<true>), gr, bl, 0, st, g, m, alpha, u, xu, xa, mask, yu, r0,
+                       r1, r);
+  else
+    hipLaunchKernelGGL((k_couple_u3d<false>), gr, bl, 0, st, g, m, alpha, u, xu, xa, mask, yu, r0,
+                       r1, r);
+  launch_finish(st, r, (int)(gr.x * gr.y), false);
+}
+
+// Jacobi-preconditioned Chebyshev step on C = H_NN in 3D:
+// d_new = cd d_in + cr D^{-1} (b - C x_in); x_out = x_in + d_new.
+__global__ __launch_bounds__(NB) void k_cheb_helm3d(Grid g, Helm3 hp, const double* __restrict__ w2,
+                                                    const uint8_t* __restrict__ mask,
+                                                    const double* __restrict__ x_in,
+                                                    double* __restrict__ x_out,
+                                                    const double* __restrict__ b,
+                                                    const double* __restrict__ d_in,
+                                                    double* __restrict__ d_out, double cd,
+                                                    double cr) {
+  const int i = blockIdx.x * NB_X + threadIdx.x, j = blockIdx.y * NB_Y + threadIdx.y, k = blockIdx.z;
+  if (i > g.nx || j > g.ny) return;
+  const int n = i + (g.nx + 1) * (j + (g.ny + 1) * k);
+  if (mask[n]) {
+    x_out[n] = 0.0;
+    if (d_out) d_out[n] = 0.0;
+    return;
+  }
+  double Hx = 0.0, gv, Hd;
+  helm_node3d<false, true>(g, hp, w2, x_in ? x_in : b, nullptr, nullptr, 0.0, mask, i, j, k, Hx, gv,
+                           Hd);
+  if (!x_in) Hx = 0.0;
+  double dn = cr * (b[n] - Hx) / Hd;
+  if (d_in) dn += cd * d_in[n];
+  x_out[n] = (x_in ? x_in[n] : 0.0) + dn;
+  if (d_out) d_out[n] = dn;
+}
+
+void launch_cheb_helm3d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                        const uint8_t* mask, const double* x_in, double* x_out, const double* b,
+                        const double* d_in, double* d_out, double cd, double cr) {
+  Helm3 hp{cL, cM, 0.0};
+  hipLaunchKernelGGL(k_cheb_helm3d, node_grid3(g), dim3(NB_X, NB_Y), 0, st, g, hp, w2, mask, x_in,
+                     x_out, b, d_in, d_out, cd, cr);
+}
+
 #define INST3(T)                                                                                \
   template void launch_apply3d<T>(hipStream_t, const Grid&, const Mat&, bool, const T*, double,  \
                                   const T*, T*, const ND<T>*, int, int, Red);                    \

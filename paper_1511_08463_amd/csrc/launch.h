@@ -51,6 +51,18 @@ void launch_jac2d(hipStream_t st, const Grid& g, const Mat& m, double kell, doub
                   const double* xu, const double* xa, double* yu, double* ya, bool dot, Red ru,
                   Red ra, const double* band);
 void launch_irange3d(hipStream_t st, const Grid& g, const uint8_t* mask, Red rlo, Red rhi);
+// 3D forms of the coupled Jacobian blocks (kernels3d.hip); the 2D launchers
+// dispatch to them.  Rows of a 3D band are the indices j + (ny + 1) k.
+void launch_jac3d(hipStream_t st, const Grid& g, const Mat& m, double kell, double cL, double cM,
+                  const double* alpha, const double* u, const double* w2, const uint8_t* mask,
+                  const double* xu, const double* xa, double* yu, double* ya, bool dot, Red ru,
+                  Red ra, const double* band);
+void launch_couple_u3d(hipStream_t st, const Grid& g, const Mat& m, const double* alpha,
+                       const double* u, const double* xu, const double* xa, const uint8_t* mask,
+                       double* yu, int r0, int r1, Red r);
+void launch_cheb_helm3d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                        const uint8_t* mask, const double* x_in, double* x_out, const double* b,
+                        const double* d_in, double* d_out, double cd, double cr);
 void launch_couple_u2d(hipStream_t st, const Grid& g, const Mat& m, const double* alpha,
                        const double* u, const double* xu, const double* xa, const uint8_t* mask,
                        double* yu, int r0, int r1, Red r);

@@ -184,7 +184,6 @@ int validate(const fracture_params* p) {
       (!std::isfinite(p->surf_ki) || !std::isfinite(p->surf_v) || !std::isfinite(p->surf_lc)))
     return FRACTURE_EINVAL;
   if (p->dim == 3 && p->load_kind != FRACTURE_LOAD_THERMAL_3D) return FRACTURE_EINVAL;
-  if (p->dim == 3 && p->newton) return FRACTURE_EINVAL;   // coupled Newton blocks are 2D only
   if (p->precision != FRACTURE_FP64 && p->precision != FRACTURE_MIXED) return FRACTURE_EINVAL;
   if (p->newton && !(p->minres_rtol > 0 && p->max_minres >= 1 && p->max_newton >= 1)) return FRACTURE_EINVAL;
   if (p->max_am < 1 || p->max_pcg < 1 || p->max_vi < 1 || p->max_vi_cg < 1) return FRACTURE_EINVAL;
@@ -322,7 +321,7 @@ size_t layout(const fracture_params* p, fracture* h, void* ws) {
     t->fq32 = c.take<float>(n2);
   }
   if (p->newton) {
-    const int64_t n3 = 3 * N;
+    const int64_t n3 = n2 + N;   // [u block | alpha]
     t->nv_prev = c.take<double>(n3);
     t->nv = c.take<double>(n3);
     t->naz = c.take<double>(n3);
@@ -1156,9 +1155,12 @@ void apply_J(fracture* h, const double* x, double* y) {
   launch_apply2d(h->st, h->lv[0].g, h->mat, true, h->alpha, h->p.k_ell, x, y, nullptr, 1,
                  1 /* dot */, red(h, 7, S_TMP0));
   const double jlo = -h->hS[S_JLO], jhi = h->hS[S_JHI];
+  // B x_a reaches the rows within one cell of an inactive node: rows j +- 1
+  // in 2D, row indices j + (ny + 1) k within +- (ny + 2) in 3D
+  const int pad = h->dim == 3 ? g.ny + 2 : 1;
   if (std::isfinite(jlo) && std::isfinite(jhi) && jhi >= jlo)
-    launch_couple_u2d(h->st, g, h->mat, h->alpha, h->u, x, x + n2, h->mask, y, (int)jlo - 1,
-                      (int)jhi + 1, red(h, 14, S_TMP0, P_ADD));
+    launch_couple_u2d(h->st, g, h->mat, h->alpha, h->u, x, x + n2, h->mask, y, (int)jlo - pad,
+                      (int)jhi + pad, red(h, 14, S_TMP0, P_ADD));
   launch_jac2d(h->st, g, h->mat, h->p.k_ell, h->cL, h->cM, h->alpha, h->u, h->w2, h->mask, x,
                x + n2, nullptr, y + n2, true, red(h, 7, S_TMP0), red(h, 8, S_TMP1), h->S + S_JLO);
 }
@@ -1171,7 +1173,7 @@ void apply_J(fracture* h, const double* x, double* y) {
 // the test passes).
 int minres(fracture* h, double rtol, int* iters) {
   hipStream_t st = h->st;
-  const int64_t n3 = 3 * h->N;
+  const int64_t n3 = h->n2 + h->N;   // [u block | alpha]
   HIPCHK(hipMemsetAsync(h->nx, 0, n3 * sizeof(double), st));
   HIPCHK(hipMemsetAsync(h->nv_prev, 0, n3 * sizeof(double), st));
   HIPCHK(hipMemsetAsync(h->nw_prev, 0, n3 * sizeof(double), st));
@@ -1803,7 +1805,6 @@ int fracture_apply(fracture_t h, int op, int level, const double* d_x, double* d
       break;
     case FRACTURE_OP_COUPLING:
     case FRACTURE_OP_COUPLING_T: {
-      if (h->dim != 2) return FRACTURE_EINVAL;
       // the full coupling block (no active set): mask cleared
       const Grid gl = load_grid(h);
       launch_w2_2d(h->st, gl, h->mat, h->u, h->w2);

@@ -76,7 +76,8 @@ static void invalid_cases(void) {
     EXPECT(h == NULL);
   }
   fracture_params q = thermal(16, 16, 4);
-  q.newton = 1;                                  /* the coupled Newton blocks are 2D */
+  q.newton = 1;
+  q.minres_rtol = -1.0;                          /* Newton needs a positive MINRES tolerance */
   EXPECT(fracture_workspace_bytes(&q) == 0);
 }
 

@@ -650,3 +650,65 @@ def test_thermal_3d_developed_crack_parity(precision):
     # the crack is developed: nodes at the upper bound, in the oracle and here
     assert np.sum(st.alpha >= 1.0 - 1e-12) >= 10 and np.sum(a >= 1.0 - 1e-12) >= 10
     s.close()
+
+
+def test_coupling_blocks_3d_match_assembled():
+    """E_ualpha (eq. (offdiag)) and its transpose in 3D with the thermal
+    eigenstrain (the stress of u's effective strain), matrix-free vs the
+    oracle's assembly, on a 12x10x6 Kuhn slab."""
+    p = workloads.thermal(12, 10, 6, 1.0, 0.8, 0.5)
+    s = _solver(p, None, newton=1)
+    P = _problem3(p)
+    N = P.model.N
+    u, alpha = workloads.random_fields(N, 3 * N, seed=15)
+    u *= 0.02
+    u[P.fixed] = 0.0
+    dT = 1.3
+    s.set_load(dT)
+    s.set_state(u=u, alpha=alpha, alpha_prev=np.zeros(N))
+    B = P.model.coupling(u, alpha, P.eps0(dT))
+    rng = np.random.default_rng(8)
+    w = rng.standard_normal(N)
+    y = s.apply(fracture.FRACTURE_OP_COUPLING, w, out_len=3 * N)
+    want = B @ w
+    want[P.fixed] = 0.0
+    assert np.max(np.abs(y - want)) / np.max(np.abs(want)) < OPS_TOL
+    v = rng.standard_normal(3 * N) * P.free
+    y = s.apply(fracture.FRACTURE_OP_COUPLING_T, v, out_len=N)
+    want = B.T @ v
+    assert np.max(np.abs(y - want)) / np.max(np.abs(want)) < OPS_TOL
+    s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_thermal_3d_oram_n_parity(precision):
+    """ORAM-N (Algorithm 3) in 3D: the 16x4x2 slab heated to 80 DT_c, the
+    Newton phase on the coupled system [u_x | u_y | u_z | alpha] with MINRES
+    and the block preconditioner, FP64 and mixed, against the oracle's
+    ORAM-N with exact solves, 1e-6 per step, through a developed crack."""
+    p = workloads.thermal(16, 4, 2, 1.0, 0.25, 0.125)
+    dtc = workloads.thermal_dtc(p)
+    loads = [f * dtc for f in (4.0, 10.0, 20.0, 30.0, 45.0, 60.0, 80.0)]
+    print(f"[thermal3d oram-n] precision={precision}", flush=True)
+    s = _solver(p, None, precision=precision, newton=1, switch_tol=1e-3, final_tol=1e-11,
+                pcg_rtol=1e-13, vi_cg_rtol=1e-13, max_am=3000)
+    P = _problem3(p)
+    st = am.initial_state(P)
+    newton_used = 0
+    for t in loads:
+        s.set_load(t)
+        stats = s.solve_step()
+        o = am.solve_load_step(P, st, t, newton_on=True, switch_tol=1e-3, final_tol=1e-11,
+                               max_am=3000)
+        u, a, ap = s.state()
+        eu, ea = _rel(u, st.u), _rel(a, st.alpha)
+        newton_used += stats["newton_iters"]
+        print(f"  dT={t / dtc:.0f} DT_c sweeps gpu/oracle={stats['sweeps']}/{o['sweeps']} "
+              f"newton={stats['newton_iters']}/{o['newton_its']} minres={stats['minres_iters']} "
+              f"max_alpha={a.max():.4f} rel_u={eu:.2e} rel_a={ea:.2e}", flush=True)
+        assert stats["converged"] and o["converged"]
+        assert eu < STEP_TOL and ea < STEP_TOL
+        assert np.all(a >= ap) and np.all(a <= 1.0)
+    assert newton_used > 0
+    assert np.sum(a >= 1.0 - 1e-12) >= 10
+    s.close()

@@ -98,8 +98,12 @@ def test_3d_shapes_and_validation():
     for shape in [(4, 4, 2), (12, 10, 6), (70, 4, 2), (32, 8, 4), (16, 8, 4)]:
         q = fracture.make_params(**w.thermal(*shape))
         assert fracture.fracture_workspace_bytes(q) > 0, shape
-    bad = fracture.make_params(**dict(w.thermal(16, 8, 4), newton=1))
-    assert fracture.fracture_workspace_bytes(bad) == 0
+    # ORAM-N in 3D: the Newton block vectors [u_x | u_y | u_z | alpha] (4 N)
+    # add to the workspace
+    nw = fracture.make_params(**dict(w.thermal(16, 8, 4), newton=1))
+    assert (fracture.fracture_workspace_bytes(nw)
+            > fracture.fracture_workspace_bytes(fracture.make_params(**w.thermal(16, 8, 4)))
+            + 7 * 4 * 17 * 9 * 5 * 8)
     bad = fracture.make_params(**dict(w.thermal(16, 8, 4), load_kind=0))
     assert fracture.fracture_workspace_bytes(bad) == 0
 
