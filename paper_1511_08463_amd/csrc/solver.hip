@@ -139,6 +139,10 @@ struct fracture {
   double bnorm = 0.0;
   Load2D load2d{};
   double omega_cur = 1.0;   // over-relaxation factor of the current sweep
+  // sum of Phi^2 of the damage solve's final iterate (the box FB residual at
+  // the sweep's u), valid until the next damage solve starts
+  double vi_phi2 = 0.0;
+  bool vi_phi2_valid = false;
   fracture_monitor_fn monitor = nullptr;
   void* monitor_user = nullptr;
   bool coef_valid = false;
@@ -751,13 +755,18 @@ void dfl_correct(fracture* h, const double* z, double* v, double sign) {
 // params.deflate, deflated CG (Saad, Yeung, Erhel and Guyomarc'h, 2000):
 // the start is corrected by W E^{-1} W^T r and every direction loses
 // W E^{-1} W^T K z, which keeps W^T r = 0 at every iterate.
+// The iterate: u itself at omega = 1 (the sweep keeps the elastic solution
+// as is), else the separate x that the relaxation then blends into u.
+double* pcg_iterate(fracture* h) { return h->omega_cur == 1.0 ? h->u : h->x; }
+
 int pcg(fracture* h, double tol, int* iters) {
   const Grid& g = h->lv[0].g;
   const int64_t n2 = h->n2;
   hipStream_t st = h->st;
-  HIPCHK(hipMemcpyAsync(h->x, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  double* x = pcg_iterate(h);
+  if (x != h->u) HIPCHK(hipMemcpyAsync(x, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
   const Grid gl = load_grid(h);
-  launch_resid2d(st, gl, h->mat, true, h->alpha, h->p.k_ell, h->x, h->r, nullptr, true,
+  launch_resid2d(st, gl, h->mat, true, h->alpha, h->p.k_ell, x, h->r, nullptr, true,
                  red(h, 0, S_RR));
   int rc = read_scalars(h);
   if (rc) return rc;
@@ -772,8 +781,8 @@ int pcg(fracture* h, double tol, int* iters) {
     if (rc) return rc;
   }
   if (m) {
-    dfl_correct(h, h->r, h->x, 1.0);
-    launch_resid2d(st, gl, h->mat, true, h->alpha, h->p.k_ell, h->x, h->r, nullptr, true,
+    dfl_correct(h, h->r, x, 1.0);
+    launch_resid2d(st, gl, h->mat, true, h->alpha, h->p.k_ell, x, h->r, nullptr, true,
                    red(h, 0, S_RR));
     rc = read_scalars(h);
     if (rc) return rc;
@@ -788,7 +797,7 @@ int pcg(fracture* h, double tol, int* iters) {
   for (int it = 1; it <= h->p.max_pcg; ++it) {
     launch_apply2d(st, g, h->mat, true, h->alpha, h->p.k_ell, h->pv, h->q, nullptr, 1, 1,
                    red(h, 2, S_PQ, P_CG_ALPHA));
-    launch_cg_update(st, n2, h->x, h->r, h->pv, h->q, h->S, red(h, 3, S_RR));
+    launch_cg_update(st, n2, x, h->r, h->pv, h->q, h->S, red(h, 3, S_RR));
     rc = read_scalars(h);
     if (rc) return rc;
     rr = h->hS[S_RR];
@@ -817,9 +826,10 @@ int pcg_mixed(fracture* h, double tol, int* iters) {
   const int64_t n2 = h->n2;
   hipStream_t st = h->st;
   *iters = 0;
-  HIPCHK(hipMemcpyAsync(h->x, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  double* x = pcg_iterate(h);
+  if (x != h->u) HIPCHK(hipMemcpyAsync(x, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
   for (int outer = 0;; ++outer) {
-    launch_resid2d<double>(st, load_grid(h), h->mat, true, h->alpha, h->p.k_ell, h->x, h->r, nullptr, true,
+    launch_resid2d<double>(st, load_grid(h), h->mat, true, h->alpha, h->p.k_ell, x, h->r, nullptr, true,
                            red(h, 0, S_RR));
     int rc = read_scalars(h);
     if (rc) return rc;
@@ -856,7 +866,7 @@ int pcg_mixed(fracture* h, double tol, int* iters) {
       if (!std::isfinite(rin)) return FRACTURE_ENONFINITE;
       if (std::sqrt(rin) <= tin || *iters >= h->p.max_pcg) break;
     }
-    launch_add_scaled_f(st, n2, h->x, h->fe32, rn);
+    launch_add_scaled_f(st, n2, x, h->fe32, rn);
   }
 }
 
@@ -879,7 +889,9 @@ int load_norm(fracture* h, double* out) {
 // ---------------------------------------------------------------------------
 
 // Projected Armijo search along vd on psi = 1/2 ||Phi||^2.  slope < 0.
-int line_search(fracture* h, double psi0, double slope, bool* accepted) {
+// *phimax receives max |Phi| of the accepted point (its trial evaluation is
+// that of the point the projected step then stores).
+int line_search(fracture* h, double psi0, double slope, bool* accepted, double* phimax) {
   const Grid& g = h->lv[0].g;
   double mu = 1.0;
   *accepted = false;
@@ -895,6 +907,7 @@ int line_search(fracture* h, double psi0, double slope, bool* accepted) {
     if (psi <= psi0 + ARMIJO_SIGMA * mu * slope) {
       launch_proj_step(h->st, h->N, h->atil, h->vd, h->alpha_prev, h->S);
       *accepted = true;
+      *phimax = h->hS[S_TMP1];
       return FRACTURE_OK;
     }
     mu *= 0.5;
@@ -910,6 +923,7 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
   const int64_t N = h->N;
   HIPCHK(hipMemcpyAsync(h->atil, h->alpha, N * sizeof(double), hipMemcpyDeviceToDevice, st));
   double stop = h->p.vi_tol;
+  h->vi_phi2_valid = false;
   for (int it = 0;; ++it) {
     launch_vi_eval2d(st, g, h->cL, h->cM, h->cm, h->w2, h->atil, nullptr, h->alpha_prev, h->S,
                      S_MU, 1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2),
@@ -921,7 +935,11 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
     if (!std::isfinite(phimax) || !std::isfinite(phi2)) return FRACTURE_ENONFINITE;
     if (it == 0 && h->p.newton && h->p.vi_reduction > 0)
       stop = std::fmax(h->p.vi_tol, h->p.vi_reduction * phimax);
-    if (phimax <= stop) return FRACTURE_OK;
+    if (phimax <= stop) {
+      h->vi_phi2 = phi2;
+      h->vi_phi2_valid = true;
+      return FRACTURE_OK;
+    }
     if (it >= h->p.max_vi) return FRACTURE_ENOTCONV;
     ++*vi_iters;
     // reduced Newton step: H_NN d_N = -F_N (Jacobi CG), d_A = 0.  The CG runs
@@ -980,8 +998,9 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
       // an inexact step is still tried: the line search decides
     }
     bool ok = false;
+    double phimax_new = INFINITY;
     const double psi0 = 0.5 * phi2;
-    rc = line_search(h, psi0, -2.0 * psi0, &ok);
+    rc = line_search(h, psi0, -2.0 * psi0, &ok, &phimax_new);
     if (rc) return rc;
     if (!ok) {
       // steepest descent on psi: d = -(ca Phi + H (cf Phi))
@@ -991,9 +1010,15 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
       launch_neg_sum(st, N, h->vt2, h->vq, h->vd, red(h, 7, S_GG));
       rc = read_scalars(h);
       if (rc) return rc;
-      rc = line_search(h, psi0, -h->hS[S_GG], &ok);
+      rc = line_search(h, psi0, -h->hS[S_GG], &ok, &phimax_new);
       if (rc) return rc;
       if (!ok) return FRACTURE_ENOTCONV;
+    }
+    // the accepted point already meets the stop test: no evaluation more
+    if (phimax_new <= stop) {
+      h->vi_phi2 = h->hS[S_TMP0];
+      h->vi_phi2_valid = true;
+      return FRACTURE_OK;
     }
   }
 }
@@ -1002,10 +1027,19 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
 // residual of the optimality conditions, ||Phi||_2
 // ---------------------------------------------------------------------------
 
+// At omega = 1 the sweep's alpha is the damage solve's final iterate, whose
+// FB residual (at the same u) that solve has just evaluated: only the
+// elastic part is formed here.
 int residual_norm(fracture* h, double* out) {
   const Grid g = load_grid(h);
   launch_apply2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, h->u, h->q, nullptr, 0, 2,
                  red(h, 0, S_EU2));
+  if (h->omega_cur == 1.0 && h->vi_phi2_valid) {
+    int rc = read_scalars(h);
+    if (rc) return rc;
+    *out = std::sqrt(h->hS[S_EU2] + h->vi_phi2);
+    return FRACTURE_OK;
+  }
   launch_w2_2d(h->st, g, h->mat, h->u, h->w2);
   launch_vi_eval2d(h->st, g, h->cL, h->cM, h->cm, h->w2, h->alpha, nullptr, h->alpha_prev, h->S,
                    S_MU, 1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2),
@@ -1359,10 +1393,8 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
     rc = h->mixed ? pcg_mixed(h, tol, &it) : pcg(h, tol, &it);
     loc.pcg_iters += it;
     if (rc) break;
-    if (h->omega_cur == 1.0)
-      HIPCHK(hipMemcpyAsync(h->u, h->x, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
-    else
-      launch_relax_u(st, n2, h->u, h->x, h->omega_cur);
+    // at omega = 1 the PCG iterated on u itself
+    if (h->omega_cur != 1.0) launch_relax_u(st, n2, h->u, h->x, h->omega_cur);
     HIPCHK(hipEventRecord(h->ev[2], st));
     // damage substep
     launch_w2_2d(st, load_grid(h), h->mat, h->u, h->w2);

@@ -447,7 +447,9 @@ __global__ __launch_bounds__(VB) void k_relax_alpha(int64_t n, double* __restric
   double acc = 0.0;
   GRID_STRIDE(k, n) {
     const double old = a[k];
-    const double nv = fmin(fmax(old + w * (at[k] - old), lo[k]), 1.0);
+    // at omega = 1 the damage iterate itself (feasible by construction), so
+    // that the new alpha is exactly the point the damage solve evaluated
+    const double nv = w == 1.0 ? at[k] : fmin(fmax(old + w * (at[k] - old), lo[k]), 1.0);
     a[k] = nv;
     acc = fmax(acc, nan_to_inf(fabs(nv - old)));
   }

@@ -171,7 +171,8 @@ def test_ragged_large_grid_operator_rows():
     tiles and one node; 1409 rows: one row past any tile height the kernels
     use; both axes still halve down to a dense coarsest level) and unequal
     cell sides: operator rows at tile seams, the last rows and columns, and
-    random nodes match the oracle's patch assembly."""
+    random nodes match the oracle's patch assembly, and so do the damage
+    gradient's rows (E_alpha from the column-walking VI evaluation)."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -185,6 +186,8 @@ def test_ragged_large_grid_operator_rows():
     alpha = rng.uniform(0, 1, N)
     s.set_state(u=u, alpha=alpha, alpha_prev=np.zeros(N))
     y = s.apply(fracture.FRACTURE_OP_ELASTICITY, u)
+    # the damage VI evaluation (column-walking on this grid): E_alpha rows
+    _, Ea = s.gradient()
     js = sorted({0, 1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 32, 33, ny - 2, ny - 1, ny,
                  ny - ny % 16, ny - ny % 8, ny - ny % 4, ny - ny % 16 - 1, ny - ny % 8 - 1}
                 | {int(v) for v in rng.integers(0, ny + 1, 12)})
@@ -204,6 +207,9 @@ def test_ragged_large_grid_operator_rows():
             err = max(abs(y[g] - row[loc]), abs(y[N + g] - row[m + loc])) / scale
             worst = max(worst, err)
             assert err < 1e-12, (i, j, err)
+            ga = M.grad_alpha(up, alpha[gid])
+            assert abs(Ea[g] - ga[loc]) <= 1e-11 * max(abs(ga[loc]), np.max(np.abs(M.damage_linear(up))),
+                                                       1e-300), (i, j)
     print(f"[ragged-large] {len(js)}x{len(ii)} nodes, worst {worst:.2e}", flush=True)
     s.close()
 
