@@ -112,7 +112,10 @@ def thermal(args):
     t0 = time.perf_counter()
     for k, t in enumerate(loads[: args.warmup + args.steps]):
         solver.set_load(t)
-        st = solver.solve_step()
+        st = solver.solve_step(raise_on_error=False)
+        if st["code"] != fracture.FRACTURE_OK:
+            log(f"[thermal] step {k + 1} DT={t:.3f} failed: {st}")
+            raise fracture.FractureError(st["code"], "fracture_solve_step")
         stats.append(st)
         el, su = solver.energy()
         log(f"[thermal] step {k + 1} DT={t:.3f} sweeps={st['sweeps']} pcg={st['pcg_iters']} "

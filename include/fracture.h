@@ -221,7 +221,18 @@ typedef struct {
   double dalpha_inf;        /* last ||alpha^k - alpha^{k-1}||_inf              */
   double phi_l2;            /* last ||Phi||_2 (when computed, else -1)         */
   double ms_total, ms_pcg, ms_vi, ms_newton;  /* device time, HIP events      */
+  int stopped_in;           /* a failed step's stage (FRACTURE_STAGE_*), else
+                               FRACTURE_STAGE_NONE                            */
 } fracture_stats;
+
+/* stats.stopped_in: where a step that did not return FRACTURE_OK stopped */
+#define FRACTURE_STAGE_NONE        0
+#define FRACTURE_STAGE_PCG         1  /* elastic PCG: max_pcg or non-finite      */
+#define FRACTURE_STAGE_VI          2  /* damage VI: max_vi active-set iterations */
+#define FRACTURE_STAGE_VI_SEARCH   3  /* damage VI: no acceptable line-search step */
+#define FRACTURE_STAGE_NEWTON      4  /* Newton phase (MINRES or its line search) */
+#define FRACTURE_STAGE_SWEEPS      5  /* max_am sweeps without the stop test     */
+#define FRACTURE_STAGE_OTHER       6  /* device error, non-finite update         */
 
 typedef struct fracture* fracture_t;   /* opaque; owned by the library          */
 

@@ -143,6 +143,8 @@ struct fracture {
   // the sweep's u), valid until the next damage solve starts
   double vi_phi2 = 0.0;
   bool vi_phi2_valid = false;
+  int vi_stop = FRACTURE_STAGE_VI;        // which VI limit ended a failed damage solve
+  bool phi_reused = false;   // the last residual_launch took vi_phi2
   fracture_monitor_fn monitor = nullptr;
   void* monitor_user = nullptr;
   bool coef_valid = false;
@@ -940,7 +942,10 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
       h->vi_phi2_valid = true;
       return FRACTURE_OK;
     }
-    if (it >= h->p.max_vi) return FRACTURE_ENOTCONV;
+    if (it >= h->p.max_vi) {
+      h->vi_stop = FRACTURE_STAGE_VI;
+      return FRACTURE_ENOTCONV;
+    }
     ++*vi_iters;
     // reduced Newton step: H_NN d_N = -F_N (Jacobi CG), d_A = 0.  The CG runs
     // on the row range that holds every inactive node (its vectors are zero
@@ -1012,7 +1017,10 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
       if (rc) return rc;
       rc = line_search(h, psi0, -h->hS[S_GG], &ok, &phimax_new);
       if (rc) return rc;
-      if (!ok) return FRACTURE_ENOTCONV;
+      if (!ok) {
+        h->vi_stop = FRACTURE_STAGE_VI_SEARCH;
+        return FRACTURE_ENOTCONV;
+      }
     }
     // the accepted point already meets the stop test: no evaluation more
     if (phimax_new <= stop) {
@@ -1030,24 +1038,22 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
 // At omega = 1 the sweep's alpha is the damage solve's final iterate, whose
 // FB residual (at the same u) that solve has just evaluated: only the
 // elastic part is formed here.
-int residual_norm(fracture* h, double* out) {
+// residual_launch queues the reductions, residual_value reads ||Phi||_2 from
+// the scalars once the caller has read them (one read for the sweep).
+void residual_launch(fracture* h) {
   const Grid g = load_grid(h);
   launch_apply2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, h->u, h->q, nullptr, 0, 2,
                  red(h, 0, S_EU2));
-  if (h->omega_cur == 1.0 && h->vi_phi2_valid) {
-    int rc = read_scalars(h);
-    if (rc) return rc;
-    *out = std::sqrt(h->hS[S_EU2] + h->vi_phi2);
-    return FRACTURE_OK;
-  }
+  h->phi_reused = h->omega_cur == 1.0 && h->vi_phi2_valid;
+  if (h->phi_reused) return;
   launch_w2_2d(h->st, g, h->mat, h->u, h->w2);
   launch_vi_eval2d(h->st, g, h->cL, h->cM, h->cm, h->w2, h->alpha, nullptr, h->alpha_prev, h->S,
                    S_MU, 1e-12, h->F, h->phi, h->mask, h->hdinv, red(h, 5, S_PHI2),
                    red(h, 6, S_PHIMAX), red(h, 12, S_JLO), red(h, 13, S_JHI), false);
-  int rc = read_scalars(h);
-  if (rc) return rc;
-  *out = std::sqrt(h->hS[S_EU2] + h->hS[S_PHI2]);
-  return FRACTURE_OK;
+}
+
+double residual_value(const fracture* h) {
+  return std::sqrt(h->hS[S_EU2] + (h->phi_reused ? h->vi_phi2 : h->hS[S_PHI2]));
 }
 
 // ---------------------------------------------------------------------------
@@ -1392,18 +1398,23 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
     const double tol = h->p.pcg_rtol * (h->bnorm > 0 ? h->bnorm : 1.0);
     rc = h->mixed ? pcg_mixed(h, tol, &it) : pcg(h, tol, &it);
     loc.pcg_iters += it;
-    if (rc) break;
+    if (rc) { loc.stopped_in = FRACTURE_STAGE_PCG; break; }
     // at omega = 1 the PCG iterated on u itself
     if (h->omega_cur != 1.0) launch_relax_u(st, n2, h->u, h->x, h->omega_cur);
     HIPCHK(hipEventRecord(h->ev[2], st));
     // damage substep
     launch_w2_2d(st, load_grid(h), h->mat, h->u, h->w2);
+    h->vi_stop = FRACTURE_STAGE_VI;
     rc = damage_qp(h, &loc.vi_iters, &loc.vi_cg_iters);
-    if (rc) break;
+    if (rc) { loc.stopped_in = h->vi_stop; break; }
     rc = relax_alpha(h);
     if (rc) break;
     HIPCHK(hipEventRecord(h->ev[3], st));
     loc.sweeps = sweep;
+    // the sweep's residual ||Phi||_2 (the stop and switch tests) is queued
+    // before the one read of the sweep's scalars
+    const bool want_phi = h->p.newton || h->p.am_stop != FRACTURE_STOP_DALPHA;
+    if (want_phi) residual_launch(h);
     rc = read_scalars(h);
     if (rc) break;
     ms_pcg += elapsed(h->ev[1], h->ev[2]);
@@ -1425,9 +1436,7 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
     if (!h->p.newton && h->p.am_stop == FRACTURE_STOP_DALPHA) {
       if (loc.dalpha_inf < h->p.am_tol) { loc.converged = 1; break; }
     } else {
-      double nphi = 0;
-      rc = residual_norm(h, &nphi);
-      if (rc) break;
+      double nphi = residual_value(h);
       loc.phi_l2 = nphi;
       if (!std::isfinite(nphi)) { rc = FRACTURE_ENONFINITE; break; }
       if (h->monitor) h->monitor(h->monitor_user, sweep, loc.dalpha_inf, nphi);
@@ -1439,7 +1448,7 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
         HIPCHK(hipEventRecord(h->ev[2], st));
         HIPCHK(hipEventSynchronize(h->ev[2]));
         ms_newton += elapsed(h->ev[1], h->ev[2]);
-        if (rc) break;
+        if (rc) { loc.stopped_in = FRACTURE_STAGE_NEWTON; break; }
         loc.phi_l2 = nphi;
         if (conv) { loc.converged = 1; break; }
         ++loc.newton_failures;
@@ -1447,7 +1456,11 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
       }
     }
   }
-  if (rc == FRACTURE_OK && !loc.converged) rc = FRACTURE_ENOTCONV;
+  if (rc == FRACTURE_OK && !loc.converged) {
+    rc = FRACTURE_ENOTCONV;
+    loc.stopped_in = FRACTURE_STAGE_SWEEPS;
+  }
+  if (rc != FRACTURE_OK && loc.stopped_in == FRACTURE_STAGE_NONE) loc.stopped_in = FRACTURE_STAGE_OTHER;
   if (rc == FRACTURE_OK) {
     HIPCHK(hipMemcpyAsync(h->alpha_prev, h->alpha, N * sizeof(double), hipMemcpyDeviceToDevice, st));
   } else if (rc == FRACTURE_ENOTCONV || rc == FRACTURE_ENONFINITE) {

@@ -37,6 +37,14 @@ FRACTURE_STOP_PHI = 1
 FRACTURE_FP64 = 0
 FRACTURE_MIXED = 1
 
+FRACTURE_STAGE_NONE = 0
+FRACTURE_STAGE_PCG = 1
+FRACTURE_STAGE_VI = 2
+FRACTURE_STAGE_VI_SEARCH = 3
+FRACTURE_STAGE_NEWTON = 4
+FRACTURE_STAGE_SWEEPS = 5
+FRACTURE_STAGE_OTHER = 6
+
 FRACTURE_OP_ELASTICITY = 0
 FRACTURE_OP_LEVEL = 1
 FRACTURE_OP_DAMAGE_HESS = 2
@@ -88,7 +96,7 @@ class fracture_stats(ctypes.Structure):
         ("newton_failures", ctypes.c_int), ("minres_iters", ctypes.c_int),
         ("converged", ctypes.c_int), ("dalpha_inf", ctypes.c_double), ("phi_l2", ctypes.c_double),
         ("ms_total", ctypes.c_double), ("ms_pcg", ctypes.c_double), ("ms_vi", ctypes.c_double),
-        ("ms_newton", ctypes.c_double),
+        ("ms_newton", ctypes.c_double), ("stopped_in", ctypes.c_int),
     ]
 
     def as_dict(self):
