@@ -86,7 +86,11 @@ def serve(args):
     budget = int(args.budget_gb * 1e9)
     log(f"[serve] {len(reqs)} requests, budget {args.budget_gb} GB, {args.workers} workers, "
         f"GPU_MAX_HW_QUEUES={os.environ.get('GPU_MAX_HW_QUEUES', 'default')}")
-    svc = serving.Service(budget, max_slots=args.slots, workers=args.workers)
+    def progress(done, total, t):
+        if done % 16 == 0 or done == total:
+            log(f"[serve] {done}/{total} requests finished at {t:.1f} s")
+
+    svc = serving.Service(budget, max_slots=args.slots, workers=args.workers, progress=progress)
     summary, _ = svc.run(reqs)
     log(f"[serve] {summary}")
     return summary

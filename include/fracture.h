@@ -203,6 +203,12 @@ typedef struct {
                                whichever is looser); the Newton phase
                                enforces the final accuracy.  In [0, 1);
                                0 (default): always vi_tol.                    */
+  int elem3d_min_nodes;     /* 3D: multigrid levels with at least this many
+                               nodes apply K with the element-centric kernels
+                               (each tetrahedron formed once per block), the
+                               smaller ones with one thread per node (more
+                               workgroups).  >= 0; default 262144; 0: every
+                               level.  Results agree to rounding.            */
 } fracture_params;
 
 /* Fill *p with the documented defaults for a 2D tension problem on an

@@ -83,6 +83,7 @@ struct Grid {
   // bc == BC_TSHOCK_2D); eig_dT is zero for operator actions on error
   // equations
   double eig_dT, eig_depth;
+  int elem_min;   // 3D: levels of at least this many nodes use the element kernels
 };
 
 // Isotropic A0 in the form the element kernels use: sigma_xx = l2m e_xx +

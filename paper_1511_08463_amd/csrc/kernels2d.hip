@@ -183,8 +183,7 @@ template <class T>
 void launch_smooth2d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
                      double kell, const ND<T>* x_in, T* x_out, const T* b, const ND<T>* d_in, ND<T>* d_out,
                      double cd, double cr) {
-  if (g.dim == 3)
-    return launch_smooth3d<T>(st, g, m, fine, coef, kell, x_in, x_out, b, d_in, d_out, cd, cr);
+  // (3D levels: launch_smooth3d, with the level's stored diagonal)
   const bool col = use_col2d(g);
   const dim3 gr = op_grid2(g, col, col_rows<M_SMOOTH>());
   Red none{};
@@ -786,6 +785,98 @@ __global__ __launch_bounds__(NB_X) void k_vi_eval_col2d(Grid g, Helm hp,
   }
 }
 
+// LDS-staged form for large grids: a block of 256 threads takes a 64 x 16
+// node tile, first loads the tile's field (with a one-node halo) and the W2
+// of its cells (cell columns i-1 and i of every node) into LDS with all loads
+// in flight together, then each thread evaluates four nodes of one column
+// from LDS.  Each field row and cell row is read from HBM once per tile (18
+// of 16 rows, 17 of 16 cell rows).  Per node the same arithmetic as
+// k_vi_eval2d (helm_node2d's six triangles in the same order).
+constexpr int VL_ROWS = 16;
+constexpr int VL_W = NB_X + 2;             // field tile width (halo on both sides)
+constexpr int VL_CW = NB_X + 1;            // cell columns (i0 - 1 .. i0 + 63)
+
+template <bool TRIAL>
+__global__ __launch_bounds__(NB) void k_vi_eval_lds2d(Grid g, Helm hp, const double* __restrict__ w2,
+                                                      const double* __restrict__ a,
+                                                      const double* __restrict__ d,
+                                                      const double* __restrict__ lo,
+                                                      const double* __restrict__ S, int mu_slot,
+                                                      double zeta, double* __restrict__ F,
+                                                      double* __restrict__ phi,
+                                                      uint8_t* __restrict__ mask,
+                                                      double* __restrict__ hdinv, Red r2, Red rm,
+                                                      Red rlo, Red rhi) {
+  __shared__ double sa[VL_ROWS + 2][VL_W];         // field rows j0-1 .. j0+16
+  __shared__ double sw[VL_ROWS + 1][VL_CW][2];     // W2 of cell rows j0-1 .. j0+15
+  const int nbx = gridDim.x, total = gridDim.x * gridDim.y;
+  const int t = xcd_tile(blockIdx.x + nbx * blockIdx.y, total);
+  const int i0 = (t % nbx) * NB_X, j0 = (t / nbx) * VL_ROWS;
+  const int tid = threadIdx.x + NB_X * threadIdx.y;
+  const int W = g.nx + 1, nx = g.nx;
+  const double mu = TRIAL ? S[mu_slot] : 0.0;
+  for (int e = tid; e < (VL_ROWS + 2) * VL_W; e += NB) {
+    const int rr = e / VL_W, cc = e % VL_W;
+    const int ii = i0 - 1 + cc, r = j0 - 1 + rr;
+    double v = 0.0;
+    if (ii >= 0 && ii <= g.nx && r >= 0 && r <= g.ny) {
+      const int q = ii + W * r;
+      v = TRIAL ? fmin(fmax(a[q] + mu * d[q], lo[q]), 1.0) : a[q];
+    }
+    sa[rr][cc] = v;
+  }
+  for (int e = tid; e < (VL_ROWS + 1) * VL_CW * 2; e += NB) {
+    const int rr = e / (2 * VL_CW), rem = e % (2 * VL_CW);
+    const int cc = rem / 2, tt = rem % 2;
+    const int ci = i0 - 1 + cc, cj = j0 - 1 + rr;
+    sw[rr][cc][tt] = (ci < 0 || cj < 0 || ci >= g.nx || cj >= g.ny) ? 0.0 : w2[2 * (ci + nx * cj) + tt];
+  }
+  __syncthreads();
+  const int tx = threadIdx.x, i = i0 + tx;
+  const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy, area = 0.5 * g.hx * g.hy;
+  double p2 = 0.0, pm = 0.0, jlo = -INFINITY, jhi = -INFINITY;
+  if (i <= g.nx) {
+    for (int s = 0; s < VL_ROWS / NB_Y; ++s) {
+      const int rl = threadIdx.y * (VL_ROWS / NB_Y) + s;   // tile row of the node
+      const int j = j0 + rl;
+      if (j > g.ny) break;
+      // the 3x3 neighbourhood in helm_node2d's slot order: (dx + 1) + 3 (dy + 1)
+      const double av[9] = {sa[rl][tx], sa[rl][tx + 1], sa[rl][tx + 2],
+                            sa[rl + 1][tx], sa[rl + 1][tx + 1], sa[rl + 1][tx + 2],
+                            sa[rl + 2][tx], sa[rl + 2][tx + 1], sa[rl + 2][tx + 2]};
+      // cells (i-1, j-1), (i, j-1) in cell row rl, (i-1, j), (i, j) in rl + 1
+      double Ha = 0.0, gvv = 0.0, Hd = 0.0;
+      tri_helm2v<0>(g, hp, sw[rl + 1][tx + 1][0], av, i, j, ihx, ihy, area, Ha, gvv, Hd);
+      tri_helm2v<1>(g, hp, sw[rl + 1][tx + 1][1], av, i, j, ihx, ihy, area, Ha, gvv, Hd);
+      tri_helm2v<2>(g, hp, sw[rl + 1][tx][0], av, i, j, ihx, ihy, area, Ha, gvv, Hd);
+      tri_helm2v<3>(g, hp, sw[rl][tx][0], av, i, j, ihx, ihy, area, Ha, gvv, Hd);
+      tri_helm2v<4>(g, hp, sw[rl][tx][1], av, i, j, ihx, ihy, area, Ha, gvv, Hd);
+      tri_helm2v<5>(g, hp, sw[rl][tx + 1][1], av, i, j, ihx, ihy, area, Ha, gvv, Hd);
+      const int n = i + W * j;
+      const double x = av[4];
+      const double l = lo[n];
+      const double Fv = Ha - gvv;
+      const double ph = mcp_fb(x, Fv, l, 1.0);
+      p2 += ph * ph;
+      pm = fmax(pm, nan_to_inf(fabs(ph)));
+      if (!TRIAL) {
+        F[n] = Fv;
+        phi[n] = ph;
+        const bool act = (x - l <= zeta && Fv > 0.0) || (1.0 - x <= zeta && Fv < 0.0) || (l >= 1.0);
+        mask[n] = act ? 1 : 0;
+        hdinv[n] = act ? 0.0 : 1.0 / Hd;
+        if (!act) { jlo = fmax(jlo, -(double)j); jhi = fmax(jhi, (double)j); }
+      }
+    }
+  }
+  block_reduce<NB, false>(p2, r2, total, t, tid);
+  block_reduce<NB, true>(pm, rm, total, t, tid);
+  if (!TRIAL) {
+    block_reduce<NB, true>(jlo, rlo, total, t, tid);
+    block_reduce<NB, true>(jhi, rhi, total, t, tid);
+  }
+}
+
 void launch_vi_eval2d(hipStream_t st, const Grid& g, double cL, double cM, double cm,
                       const double* w2, const double* a, const double* d, const double* lo,
                       const double* S, int mu_slot, double zeta, double* F, double* phi,
@@ -795,13 +886,14 @@ void launch_vi_eval2d(hipStream_t st, const Grid& g, double cL, double cM, doubl
                             r2, rm, rlo, rhi, trial);
   Helm hp{cL, cM, cm};
   if (use_col2d(g)) {
-    const dim3 gr((g.nx + 1 + NB_X - 1) / NB_X, (g.ny + 1 + VI_ROWS - 1) / VI_ROWS);
+    static_assert(VL_ROWS % NB_Y == 0, "whole rows per thread");
+    const dim3 gr((g.nx + 1 + NB_X - 1) / NB_X, (g.ny + 1 + VL_ROWS - 1) / VL_ROWS);
     if (trial)
-      hipLaunchKernelGGL((k_vi_eval_col2d<true>), gr, dim3(NB_X), 0, st, g, hp, w2, a, d, lo, S,
-                         mu_slot, zeta, F, phi, mask, hdinv, r2, rm, rlo, rhi);
+      hipLaunchKernelGGL((k_vi_eval_lds2d<true>), gr, dim3(NB_X, NB_Y), 0, st, g, hp, w2, a, d, lo,
+                         S, mu_slot, zeta, F, phi, mask, hdinv, r2, rm, rlo, rhi);
     else
-      hipLaunchKernelGGL((k_vi_eval_col2d<false>), gr, dim3(NB_X), 0, st, g, hp, w2, a, d, lo, S,
-                         mu_slot, zeta, F, phi, mask, hdinv, r2, rm, rlo, rhi);
+      hipLaunchKernelGGL((k_vi_eval_lds2d<false>), gr, dim3(NB_X, NB_Y), 0, st, g, hp, w2, a, d, lo,
+                         S, mu_slot, zeta, F, phi, mask, hdinv, r2, rm, rlo, rhi);
     const FinishSet fs{{r2, rm, rlo, rhi}, 0b1110, trial ? 2 : 4};
     launch_finish_multi(st, fs, (int)(gr.x * gr.y));
     return;
@@ -905,10 +997,9 @@ int launch_helm_cg2d(hipStream_t st, const Grid& g, double cL, double cM, const 
                      const double* z, const double* p_old, const uint8_t* mask, double* p_new,
                      double* q, int j0, int j1, int i0, int i1, const double* S, bool first,
                      Red r, bool finish) {
-  if (g.dim == 3) {
-    launch_helm_cg3d(st, g, cL, cM, w2, z, p_old, mask, p_new, q, j0, j1, i0, i1, S, first, r);
-    return 0;
-  }
+  if (g.dim == 3)
+    return launch_helm_cg3d(st, g, cL, cM, w2, z, p_old, mask, p_new, q, j0, j1, i0, i1, S, first, r,
+                            finish);
   Helm hp{cL, cM, 0.0};
   if (j0 < 0) j0 = 0;
   if (j1 < 0 || j1 > g.ny) j1 = g.ny;

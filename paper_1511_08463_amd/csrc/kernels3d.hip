@@ -12,6 +12,8 @@
 // at compile time (template parameters) so every stencil index is a
 // constant.  The eigenstrain of the thermal load enters as
 // eps_eff = eps(u) - s I with s = -DT exp(-x_c/depth) at the element centroid.
+#include <algorithm>
+
 #include "common.h"
 #include "launch.h"
 #include "ops3d.h"
@@ -19,17 +21,293 @@
 namespace frac {
 
 // ---------------------------------------------------------------------------
-// node kernels (apply / residual / Chebyshev step), value type T
+// element-centric operator kernels (apply / residual / Chebyshev step)
 // ---------------------------------------------------------------------------
+//
+// A block owns a 15 x 15 x E3_KZ box of nodes.  Each of its 16 x 16 threads
+// takes one column of hexahedra (the box's columns and one more on the low
+// side in x and y, so every owned node has all eight of its hexahedra) and
+// walks the hexahedron layers from one below the box to its top plane.  Per
+// layer a thread forms the six tetrahedra of its hexahedron once and adds
+// their nodal forces (or, for the diagonal pass, their diagonal entries of K)
+// into LDS sums of the layer's two node planes.  A node receives from the four hexahedra of
+// a layer that share it in four phases, one per vertex position in the x-y
+// plane, so no two threads write one sum at once and the order of every sum
+// is fixed: the result is bitwise reproducible.  Three node planes of u and
+// alpha and two planes of sums are resident; every node is read from HBM once
+// apart from the tile halo.  Each tetrahedron is formed once per layer walk
+// (1.14 x 1.25 times on average with the halos) instead of once for each of
+// its four vertices by a node-centric kernel.
+//
+// The diagonal of K depends on the coefficients alone, so it is formed once
+// per coefficient update (M3_DIAG) and the Chebyshev steps read it (three
+// more reads per node instead of a second set of sums and the registers to
+// form it in every step).
 
-enum { M3_APPLY = 0, M3_RESID = 1, M3_SMOOTH = 2 };
+enum { M3_APPLY = 0, M3_RESID = 1, M3_SMOOTH = 2, M3_DIAG = 3 };
 enum { R3_NONE = 0, R3_DOT = 1, R3_FREE2 = 2 };
 
+constexpr int E3_T = 16;             // hexahedron columns per block edge (16 x 16 threads)
+constexpr int E3_O = E3_T - 1;       // owned nodes per block edge
+constexpr int E3_P = E3_T + 1;       // node tile edge: the owned nodes and a halo on each side
+constexpr int E3_PN = E3_P * E3_P;   // nodes of one tile plane
+constexpr int E3_KZ = 4;             // owned node planes per block
+static_assert(E3_T * E3_T == NB, "one thread per hexahedron column");
+
+// local vertex (dx + 2 dy + 4 dz) of vertex W of tetrahedron P
+template <int P, int W>
+struct HexV {
+  static constexpr int v = VOff<P, W, 0>::v + 2 * VOff<P, W, 1>::v + 4 * VOff<P, W, 2>::v;
+};
+
+// Forces (HASX) and diagonal entries (DIAG) of tetrahedron P of a hexahedron
+// added to its vertices.  u, a: the hexahedron's eight vertices; c: the
+// degradation coefficient (FA: from a, else given); seig: the eigenstrain
+// offset of the tetrahedron (EIG).
+template <int P, bool FA, bool HASX, bool DIAG, bool EIG, class T>
+__device__ __forceinline__ void hex_tet3(const Mat& m, const T (&u)[8][3], const T (&a)[8], T cgiven,
+                                         T kell, T seig, const T ih[3], T vol, T (&fv)[8][3],
+                                         T (&dv)[8][3]) {
+  constexpr int A = Perm3<P>::a, B = Perm3<P>::b, C = Perm3<P>::c;
+  constexpr int v0 = HexV<P, 0>::v, v1 = HexV<P, 1>::v, v2 = HexV<P, 2>::v, v3 = HexV<P, 3>::v;
+  const T c = FA ? abar4(a[v0], a[v1], a[v2], a[v3], kell) : cgiven;
+  const T w = c * vol;
+  const T lam = T(m.lam), mu = T(m.mu);
+  if (HASX) {
+    T G[3][3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      G[q][A] = (u[v1][q] - u[v0][q]) * ih[A];
+      G[q][B] = (u[v2][q] - u[v1][q]) * ih[B];
+      G[q][C] = (u[v3][q] - u[v2][q]) * ih[C];
+    }
+    T e0 = G[0][0], e1 = G[1][1], e2 = G[2][2];
+    if (EIG) { e0 -= seig; e1 -= seig; e2 -= seig; }
+    const T tr = e0 + e1 + e2;
+    T S[3][3];
+    S[0][0] = lam * tr + T(2) * mu * e0;
+    S[1][1] = lam * tr + T(2) * mu * e1;
+    S[2][2] = lam * tr + T(2) * mu * e2;
+    S[0][1] = S[1][0] = mu * (G[0][1] + G[1][0]);
+    S[0][2] = S[2][0] = mu * (G[0][2] + G[2][0]);
+    S[1][2] = S[2][1] = mu * (G[1][2] + G[2][1]);
+    // vertex gradients: g0 = -e_A/h_A, g1 = e_A/h_A - e_B/h_B, g2 = e_B/h_B - e_C/h_C, g3 = e_C/h_C
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const T tA = w * S[q][A] * ih[A], tB = w * S[q][B] * ih[B], tC = w * S[q][C] * ih[C];
+      fv[v0][q] -= tA;
+      fv[v1][q] += tA - tB;
+      fv[v2][q] += tB - tC;
+      fv[v3][q] += tC;
+    }
+  }
+  if (DIAG) {
+    const T lm = lam + mu;
+    const T gA = ih[A] * ih[A], gB = ih[B] * ih[B], gC = ih[C] * ih[C];
+    // |g_W|^2 and its per-axis squares, as above
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const T s0 = q == A ? gA : T(0);
+      const T s1 = q == A ? gA : (q == B ? gB : T(0));
+      const T s2 = q == B ? gB : (q == C ? gC : T(0));
+      const T s3 = q == C ? gC : T(0);
+      dv[v0][q] += w * (lm * s0 + mu * gA);
+      dv[v1][q] += w * (lm * s1 + mu * (gA + gB));
+      dv[v2][q] += w * (lm * s2 + mu * (gB + gC));
+      dv[v3][q] += w * (lm * s3 + mu * gC);
+    }
+  }
+}
+
+template <int MODE, bool FA, bool HASX, int RED, bool EIG, class T>
+__global__ __launch_bounds__(NB) void k_elem3d(Grid g, Mat m, const T* __restrict__ coef, T kell,
+                                               const T* __restrict__ x, T* __restrict__ y,
+                                               const T* __restrict__ b, const T* __restrict__ dg,
+                                               const T* __restrict__ din, T* __restrict__ dout,
+                                               T cd, T cr, int mask, Red red) {
+  constexpr bool DIAG = MODE == M3_DIAG;
+  constexpr bool NEED_A = FA;
+  __shared__ T su[HASX ? 3 : 1][3][HASX ? E3_PN : 1];   // u: planes p % 3, components
+  __shared__ T sa[NEED_A ? 3 : 1][NEED_A ? E3_PN : 1];  // alpha: planes p % 3
+  __shared__ T sf[HASX ? 2 : 1][3][HASX ? E3_PN : 1];   // force sums: planes p & 1
+  __shared__ T sd[DIAG ? 2 : 1][3][DIAG ? E3_PN : 1];   // diagonal sums: planes p & 1
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + E3_T * ty;
+  const int i0 = blockIdx.x * E3_O, j0 = blockIdx.y * E3_O, k0 = blockIdx.z * E3_KZ;
+  const int W = g.nx + 1, H = g.ny + 1, N = g.N;
+  const int ke = min(k0 + E3_KZ - 1, g.nz);
+  const int ci = i0 - 1 + tx, cj = j0 - 1 + ty;
+  const bool col_ok = ci >= 0 && cj >= 0 && ci < g.nx && cj < g.ny;
+  const bool owner = tx < E3_O && ty < E3_O && i0 + tx <= g.nx && j0 + ty <= g.ny;
+  const int own = (tx + 1) + E3_P * (ty + 1);
+  const T ih[3] = {T(1.0 / g.hx), T(1.0 / g.hy), T(1.0 / g.hz)};
+  const T vol = T(g.hx * g.hy * g.hz / 6.0);
+  // eigenstrain offsets of the column's six tetrahedra (they depend on x only)
+  T seig[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+  if (EIG && col_ok) {
+#define SEIG(P) seig[P] = T(-g.eig_dT * exp(-((ci + tet_xc<P>()) * g.hx) / g.eig_depth));
+    SEIG(0) SEIG(1) SEIG(2) SEIG(3) SEIG(4) SEIG(5)
+#undef SEIG
+  }
+  auto load_plane = [&](int p) {
+    if (p < 0 || p > g.nz) return;
+    const int sl = p % 3;
+    for (int e = tid; e < E3_PN; e += NB) {
+      const int lx = e % E3_P, ly = e / E3_P;
+      const int gi = i0 - 1 + lx, gj = j0 - 1 + ly;
+      const bool ok = gi >= 0 && gj >= 0 && gi <= g.nx && gj <= g.ny;
+      const int n = gi + W * (gj + H * p);
+      if constexpr (HASX) {
+        su[sl][0][e] = ok ? x[n] : T(0);
+        su[sl][1][e] = ok ? x[n + N] : T(0);
+        su[sl][2][e] = ok ? x[n + 2 * N] : T(0);
+      }
+      if constexpr (NEED_A) sa[sl][e] = ok ? coef[n] : T(0);
+    }
+  };
+  for (int e = tid; e < E3_PN; e += NB) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      if constexpr (HASX) { sf[0][q][e] = T(0); sf[1][q][e] = T(0); }
+      if constexpr (DIAG) { sd[0][q][e] = T(0); sd[1][q][e] = T(0); }
+    }
+  }
+  load_plane(k0 - 1);
+  double acc = 0.0;
+  for (int ck = k0 - 1; ck <= ke; ++ck) {
+    load_plane(ck + 1);
+    __syncthreads();
+    T fv[8][3], dv[8][3];
+#pragma unroll
+    for (int v = 0; v < 8; ++v)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) fv[v][q] = dv[v][q] = T(0);
+    const bool hex_ok = col_ok && ck >= 0 && ck < g.nz;
+    if (hex_ok) {
+      T u[8][3], a[8];
+      const int s0 = ck % 3, s1 = (ck + 1) % 3;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int sl = (v & 4) ? s1 : s0;
+        const int e = (tx + (v & 1)) + E3_P * (ty + ((v >> 1) & 1));
+        if constexpr (HASX) {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) u[v][q] = su[sl][q][e];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) u[v][q] = T(0);
+        }
+        a[v] = T(0);
+        if constexpr (NEED_A) a[v] = sa[sl][e];
+      }
+      T cg[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+      if (!FA) {
+        const T* ab = coef + 6 * ((int64_t)ci + (int64_t)g.nx * (cj + (int64_t)g.ny * ck));
+#pragma unroll
+        for (int p = 0; p < 6; ++p) cg[p] = ab[p];
+      }
+#define HT(P) hex_tet3<P, FA, HASX, DIAG, EIG>(m, u, a, cg[P], kell, seig[P], ih, vol, fv, dv);
+      HT(0) HT(1) HT(2) HT(3) HT(4) HT(5)
+#undef HT
+    }
+    // the four vertex positions in the x-y plane, one phase each: bottom
+    // vertices into the sums of plane ck, top vertices into those of ck + 1
+    const bool bot = ck >= k0, top = ck + 1 <= ke;
+    const int fb0 = (ck + 2) & 1, fb1 = (ck + 3) & 1;
+#pragma unroll
+    for (int ph = 0; ph < 4; ++ph) {
+      if (hex_ok) {
+        const int e = (tx + (ph & 1)) + E3_P * (ty + (ph >> 1));
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          if constexpr (HASX) {
+            if (bot) sf[fb0][q][e] += fv[ph][q];
+            if (top) sf[fb1][q][e] += fv[ph + 4][q];
+          }
+          if constexpr (DIAG) {
+            if (bot) sd[fb0][q][e] += dv[ph][q];
+            if (top) sd[fb1][q][e] += dv[ph + 4][q];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (bot) {
+      // plane ck is complete: the owned nodes finish the operator
+      if (owner) {
+        const int n = (i0 + tx) + W * ((j0 + ty) + H * ck);
+        const int sl = ck % 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const bool fx = fixed3(g, c, i0 + tx, j0 + ty, ck);
+          const int q = n + c * N;
+          T f = T(0), xv = T(0);
+          if constexpr (HASX) {
+            f = sf[fb0][c][own];
+            xv = su[sl][c][own];
+          }
+          if (MODE == M3_APPLY) {
+            const T yv = (mask && fx) ? T(0) : f;
+            y[q] = yv;
+            if (RED == R3_DOT) acc += (double)xv * yv;
+            if (RED == R3_FREE2) {
+              const double r = (double)f - (b ? (double)b[q] : 0.0);
+              acc += fx ? 0.0 : r * r;
+            }
+          } else if (MODE == M3_RESID) {
+            const T r = fx ? T(0) : (b ? b[q] : T(0)) - f;
+            y[q] = r;
+            if (RED == R3_DOT) acc += (double)r * r;
+          } else if (MODE == M3_SMOOTH) {
+            const T r = (b ? b[q] : T(0)) - f;
+            T dd = cr * r / dg[q];
+            if (din) dd += cd * din[q];
+            T xo = xv + dd;
+            if (fx) { xo = T(0); dd = T(0); }
+            y[q] = xo;
+            if (dout) dout[q] = dd;
+          } else {
+            if constexpr (DIAG) y[q] = sd[fb0][c][own];
+          }
+        }
+      }
+      // the sums of plane ck are cleared for plane ck + 2: owners clear their
+      // own entries (read just above), the first threads the tile halo
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (tx < E3_O && ty < E3_O) {
+          if constexpr (HASX) sf[fb0][c][own] = T(0);
+          if constexpr (DIAG) sd[fb0][c][own] = T(0);
+        }
+      }
+      if (tid < 4 * E3_P - 4) {
+        // the 64 halo entries of the 17 x 17 plane (rows 0 and 16, columns 0 and 16)
+        int e;
+        if (tid < E3_P) e = tid;
+        else if (tid < 2 * E3_P) e = (E3_P - 1) * E3_P + (tid - E3_P);
+        else if (tid < 2 * E3_P + (E3_P - 2)) e = E3_P * (1 + tid - 2 * E3_P);
+        else e = E3_P * (1 + tid - 2 * E3_P - (E3_P - 2)) + E3_P - 1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if constexpr (HASX) sf[fb0][c][e] = T(0);
+          if constexpr (DIAG) sd[fb0][c][e] = T(0);
+        }
+      }
+    }
+  }
+  if (RED != R3_NONE)
+    block_reduce<NB, false>(acc, red, gridDim.x * gridDim.y * gridDim.z,
+                            blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), tid);
+}
+
+// One thread per node (64 x 4 x 1 node tiles): the coarser levels, where
+// the element kernel's 15 x 15 x 4 tiles would give too few workgroups.  The
+// node sums the forces (or diagonal entries) of its 24 tetrahedra.
 template <int MODE, bool FA, bool HASX, int RED, bool EIG, class T>
 __global__ __launch_bounds__(NB) void k_node3d(Grid g, Mat m, const T* __restrict__ coef, T kell,
                                                const T* __restrict__ x, T* __restrict__ y,
-                                               const T* __restrict__ b, const T* __restrict__ din,
-                                               T* __restrict__ dout, T cd, T cr, int mask, Red red) {
+                                               const T* __restrict__ b, const T* __restrict__ dg,
+                                               const T* __restrict__ din, T* __restrict__ dout,
+                                               T cd, T cr, int mask, Red red) {
   const int i = blockIdx.x * NB_X + threadIdx.x;
   const int j = blockIdx.y * NB_Y + threadIdx.y;
   const int k = blockIdx.z;
@@ -37,7 +315,7 @@ __global__ __launch_bounds__(NB) void k_node3d(Grid g, Mat m, const T* __restric
   if (i <= g.nx && j <= g.ny) {
     const int N = g.N, n = i + (g.nx + 1) * (j + (g.ny + 1) * k);
     T f[3], d[3];
-    node_force3d<FA, HASX, MODE == M3_SMOOTH, EIG>(g, m, coef, kell, x, i, j, k, f, d);
+    node_force3d<FA, HASX, MODE == M3_DIAG, EIG>(g, m, coef, kell, x, i, j, k, f, d);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const bool fx = fixed3(g, c, i, j, k);
@@ -54,14 +332,16 @@ __global__ __launch_bounds__(NB) void k_node3d(Grid g, Mat m, const T* __restric
         const T r = fx ? T(0) : (b ? b[q] : T(0)) - f[c];
         y[q] = r;
         if (RED == R3_DOT) acc += (double)r * r;
-      } else {
+      } else if (MODE == M3_SMOOTH) {
         const T r = (b ? b[q] : T(0)) - f[c];
-        T dd = cr * r / d[c];
+        T dd = cr * r / dg[q];
         if (din) dd += cd * din[q];
         T xo = (HASX ? x[q] : T(0)) + dd;
         if (fx) { xo = T(0); dd = T(0); }
         y[q] = xo;
         if (dout) dout[q] = dd;
+      } else {
+        y[q] = d[c];
       }
     }
   }
@@ -71,24 +351,42 @@ __global__ __launch_bounds__(NB) void k_node3d(Grid g, Mat m, const T* __restric
                             threadIdx.x + NB_X * threadIdx.y);
 }
 
+// Levels with at least g.elem_min nodes use the element kernels.
+static bool use_elem3d(const Grid& g) { return g.N >= g.elem_min; }
+
 static dim3 node_grid3(const Grid& g) {
   return dim3((g.nx + 1 + NB_X - 1) / NB_X, (g.ny + 1 + NB_Y - 1) / NB_Y, g.nz + 1);
 }
 
+static dim3 elem_grid3(const Grid& g) {
+  return dim3((g.nx + 1 + E3_O - 1) / E3_O, (g.ny + 1 + E3_O - 1) / E3_O,
+              (g.nz + 1 + E3_KZ - 1) / E3_KZ);
+}
+
+// the most blocks a reducing 3D launch on g uses (node and element grids)
 int node_blocks3(const Grid& g) {
-  dim3 gr = node_grid3(g);
-  return (int)(gr.x * gr.y * gr.z);
+  const dim3 ge = elem_grid3(g), gn = node_grid3(g);
+  const int ne = (int)(ge.x * ge.y * ge.z), nn = (int)(gn.x * gn.y * gn.z);
+  return ne > nn ? ne : nn;
 }
 
 template <class T>
 void launch_apply3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
                     double kell, const T* x, T* y, const ND<T>* b, int mask, int red, Red r) {
-  dim3 gr = node_grid3(g), bl(NB_X, NB_Y);
+  const bool el = use_elem3d(g);
+  const dim3 gr = el ? elem_grid3(g) : node_grid3(g);
+  const dim3 bl = el ? dim3(E3_T, E3_T) : dim3(NB_X, NB_Y);
   const T k = T(kell);
   const bool eig = fine && g.eig_dT != 0.0;
-#define A3(FA, RD, EG) \
-  hipLaunchKernelGGL((k_node3d<M3_APPLY, FA, true, RD, EG, T>), gr, bl, 0, st, g, m, coef, k, x, y, b, \
-                     (const T*)nullptr, (T*)nullptr, T(0), T(0), mask, r)
+#define A3(FA, RD, EG)                                                                          \
+  do {                                                                                          \
+    if (el)                                                                                     \
+      hipLaunchKernelGGL((k_elem3d<M3_APPLY, FA, true, RD, EG, T>), gr, bl, 0, st, g, m, coef, k, x, \
+                         y, b, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, T(0), T(0), mask, r); \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_node3d<M3_APPLY, FA, true, RD, EG, T>), gr, bl, 0, st, g, m, coef, k, x, \
+                         y, b, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, T(0), T(0), mask, r); \
+  } while (0)
   if (fine && eig) {
     if (red == R3_NONE) A3(true, R3_NONE, true);
     else if (red == R3_DOT) A3(true, R3_DOT, true);
@@ -109,12 +407,20 @@ void launch_apply3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, cons
 template <class T>
 void launch_resid3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
                     double kell, const T* x, T* r, const ND<T>* b, bool red, Red rr) {
-  dim3 gr = node_grid3(g), bl(NB_X, NB_Y);
+  const bool el = use_elem3d(g);
+  const dim3 gr = el ? elem_grid3(g) : node_grid3(g);
+  const dim3 bl = el ? dim3(E3_T, E3_T) : dim3(NB_X, NB_Y);
   const T k = T(kell);
   const bool eig = fine && g.eig_dT != 0.0;
-#define R3(FA, RD, EG) \
-  hipLaunchKernelGGL((k_node3d<M3_RESID, FA, true, RD, EG, T>), gr, bl, 0, st, g, m, coef, k, x, r, b, \
-                     (const T*)nullptr, (T*)nullptr, T(0), T(0), 1, rr)
+#define R3(FA, RD, EG)                                                                          \
+  do {                                                                                          \
+    if (el)                                                                                     \
+      hipLaunchKernelGGL((k_elem3d<M3_RESID, FA, true, RD, EG, T>), gr, bl, 0, st, g, m, coef, k, x, \
+                         r, b, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, T(0), T(0), 1, rr); \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_node3d<M3_RESID, FA, true, RD, EG, T>), gr, bl, 0, st, g, m, coef, k, x, \
+                         r, b, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, T(0), T(0), 1, rr); \
+  } while (0)
   if (fine) {
     if (eig) { if (red) R3(true, R3_DOT, true); else R3(true, R3_NONE, true); }
     else { if (red) R3(true, R3_DOT, false); else R3(true, R3_NONE, false); }
@@ -125,19 +431,82 @@ void launch_resid3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, cons
   if (red) launch_finish(st, rr, (int)(gr.x * gr.y * gr.z), false);
 }
 
+// First Chebyshev step from x = 0: d = cd d_in + cr D^{-1} b, x_out = d
+// (no stencil); fixed DOFs zero.
+template <class T>
+__global__ __launch_bounds__(VB) void k_smooth0_3d(Grid g, const T* __restrict__ dg,
+                                                   const T* __restrict__ b,
+                                                   const T* __restrict__ din, T* __restrict__ x_out,
+                                                   T* __restrict__ dout, T cd, T cr) {
+  const int64_t N = g.N, W = g.nx + 1, H = g.ny + 1;
+  for (int64_t q = blockIdx.x * (int64_t)VB + threadIdx.x; q < 3 * N; q += (int64_t)gridDim.x * VB) {
+    const int c = (int)(q / N);
+    const int64_t n = q - c * N;
+    const int i = (int)(n % W), j = (int)((n / W) % H), k = (int)(n / (W * H));
+    T dd = cr * b[q] / dg[q];
+    if (din) dd += cd * din[q];
+    if (fixed3(g, c, i, j, k)) dd = T(0);
+    x_out[q] = dd;
+    if (dout) dout[q] = dd;
+  }
+}
+
+// One Jacobi-preconditioned Chebyshev step with the level's stored diagonal dg
+// (launch_diag3d): d_new = cd d_in + cr D^{-1} (b - K x_in), x_out = x_in + d_new.
 template <class T>
 void launch_smooth3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
-                     double kell, const ND<T>* x_in, T* x_out, const T* b, const ND<T>* d_in,
-                     ND<T>* d_out, double cd, double cr) {
-  dim3 gr = node_grid3(g), bl(NB_X, NB_Y);
+                     const T* dg, double kell, const ND<T>* x_in, T* x_out, const T* b,
+                     const ND<T>* d_in, ND<T>* d_out, double cd, double cr) {
+  if (!x_in) {
+    const int64_t n = 3 * (int64_t)g.N;
+    const int nb = (int)std::min<int64_t>((n + VB - 1) / VB, VGRID);
+    hipLaunchKernelGGL((k_smooth0_3d<T>), dim3(nb), dim3(VB), 0, st, g, dg, b, d_in, x_out, d_out,
+                       T(cd), T(cr));
+    return;
+  }
+  const bool el = use_elem3d(g);
+  const dim3 gr = el ? elem_grid3(g) : node_grid3(g);
+  const dim3 bl = el ? dim3(E3_T, E3_T) : dim3(NB_X, NB_Y);
   Red none{};
   const T k = T(kell);
-#define S3(FA, HX) \
-  hipLaunchKernelGGL((k_node3d<M3_SMOOTH, FA, HX, R3_NONE, false, T>), gr, bl, 0, st, g, m, coef, k, \
-                     x_in, x_out, b, d_in, d_out, T(cd), T(cr), 1, none)
-  if (fine) { if (x_in) S3(true, true); else S3(true, false); }
-  else { if (x_in) S3(false, true); else S3(false, false); }
+#define S3(FA)                                                                                  \
+  do {                                                                                          \
+    if (el)                                                                                     \
+      hipLaunchKernelGGL((k_elem3d<M3_SMOOTH, FA, true, R3_NONE, false, T>), gr, bl, 0, st, g, m, \
+                         coef, k, x_in, x_out, b, dg, d_in, d_out, T(cd), T(cr), 1, none);     \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_node3d<M3_SMOOTH, FA, true, R3_NONE, false, T>), gr, bl, 0, st, g, m, \
+                         coef, k, x_in, x_out, b, dg, d_in, d_out, T(cd), T(cr), 1, none);     \
+  } while (0)
+  if (fine) S3(true);
+  else S3(false);
 #undef S3
+}
+
+// dg = diag K on level g (fine: coefficients from nodal alpha; else the
+// per-element array)
+template <class T>
+void launch_diag3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
+                   double kell, T* dg) {
+  const bool el = use_elem3d(g);
+  const dim3 gr = el ? elem_grid3(g) : node_grid3(g);
+  const dim3 bl = el ? dim3(E3_T, E3_T) : dim3(NB_X, NB_Y);
+  Red none{};
+  const T k = T(kell);
+#define D3(FA)                                                                                  \
+  do {                                                                                          \
+    if (el)                                                                                     \
+      hipLaunchKernelGGL((k_elem3d<M3_DIAG, FA, false, R3_NONE, false, T>), gr, bl, 0, st, g, m,  \
+                         coef, k, (const T*)nullptr, dg, (const T*)nullptr, (const T*)nullptr,  \
+                         (const T*)nullptr, (T*)nullptr, T(0), T(0), 0, none);                  \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_node3d<M3_DIAG, FA, false, R3_NONE, false, T>), gr, bl, 0, st, g, m,  \
+                         coef, k, (const T*)nullptr, dg, (const T*)nullptr, (const T*)nullptr,  \
+                         (const T*)nullptr, (T*)nullptr, T(0), T(0), 0, none);                  \
+  } while (0)
+  if (fine) D3(true);
+  else D3(false);
+#undef D3
 }
 
 // ---------------------------------------------------------------------------
@@ -475,16 +844,20 @@ __global__ __launch_bounds__(NB) void k_helm_cg3d(Grid g, Helm3 hp, const double
                                                   const double* __restrict__ p_old,
                                                   const uint8_t* __restrict__ mask,
                                                   double* __restrict__ p_new,
-                                                  double* __restrict__ q, int r0, int r1,
-                                                  int i0, int i1, const double* __restrict__ S,
-                                                  Red r) {
-  const int i = i0 + blockIdx.x * NB_X + threadIdx.x, j = blockIdx.y * NB_Y + threadIdx.y;
-  const int k = blockIdx.z;
+                                                  double* __restrict__ q, Box bx,
+                                                  const double* __restrict__ S, Red r) {
+  // one node of the box per thread: the inactive set of a thermal crack is a
+  // layer a few nodes thick in x spanning every (j, k) row, so the box is
+  // walked as one flat range rather than in 64-wide x tiles
+  const int64_t qq = blockIdx.x * (int64_t)NB + threadIdx.x;
   const double beta = FIRST ? 0.0 : S[S_BETA];
   double acc = 0.0;
-  const int row = j + (g.ny + 1) * k;
-  if (i <= i1 && j <= g.ny && row >= r0 && row <= r1) {
-    const int n = i + (g.nx + 1) * row;
+  if (qq < bx.n) {
+    const int64_t n = box_index(bx, qq);
+    const int W = g.nx + 1, H = g.ny + 1;
+    const int i = (int)(n % W);
+    const int64_t row = n / W;
+    const int j = (int)(row % H), k = (int)(row / H);
     double Hx, gv, Hd;
     if (FIRST)
       helm_node3d<false, true>(g, hp, w2, z, nullptr, nullptr, 0.0, mask, i, j, k, Hx, gv, Hd);
@@ -497,31 +870,36 @@ __global__ __launch_bounds__(NB) void k_helm_cg3d(Grid g, Helm3 hp, const double
     q[n] = Hx;
     acc = pn * Hx;
   }
-  block_reduce<NB, false>(acc, r, gridDim.x * gridDim.y * gridDim.z,
-                          blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
-                          threadIdx.x + NB_X * threadIdx.y);
+  block_reduce<NB, false>(acc, r, gridDim.x, blockIdx.x, threadIdx.x);
 }
 
-void launch_helm_cg3d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
-                      const double* z, const double* p_old, const uint8_t* mask, double* p_new,
-                      double* q, int r0, int r1, int i0, int i1, const double* S, bool first,
-                      Red r) {
+// One damage-CG direction update and Hessian apply over the box of columns
+// [i0, i1] and (j, k) rows [r0, r1] (row = j + (ny+1) k); p.q goes to the
+// partials of r.  finish: reduce them here (returns 0), else return their
+// count for the CG update to reduce.
+int launch_helm_cg3d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                     const double* z, const double* p_old, const uint8_t* mask, double* p_new,
+                     double* q, int r0, int r1, int i0, int i1, const double* S, bool first,
+                     Red r, bool finish) {
   Helm3 hp{cL, cM, 0.0};
   const int rows = (g.ny + 1) * (g.nz + 1);
   if (r0 < 0) r0 = 0;
   if (r1 < 0 || r1 >= rows) r1 = rows - 1;
   if (i0 < 0) i0 = 0;
   if (i1 < 0 || i1 > g.nx) i1 = g.nx;
-  if (i1 < i0) return;
-  dim3 gr = node_grid3(g), bl(NB_X, NB_Y);
-  gr.x = (i1 - i0 + 1 + NB_X - 1) / NB_X;
+  if (i1 < i0 || r1 < r0) return 0;
+  const int64_t W = g.nx + 1, w = i1 - i0 + 1;
+  const Box bx{(int64_t)r0 * W + i0, W, w, (int64_t)(r1 - r0 + 1) * w};
+  const int nb = (int)((bx.n + NB - 1) / NB);
   if (first)
-    hipLaunchKernelGGL((k_helm_cg3d<true>), gr, bl, 0, st, g, hp, w2, z, p_old, mask, p_new, q, r0,
-                       r1, i0, i1, S, r);
+    hipLaunchKernelGGL((k_helm_cg3d<true>), dim3(nb), dim3(NB), 0, st, g, hp, w2, z, p_old, mask,
+                       p_new, q, bx, S, r);
   else
-    hipLaunchKernelGGL((k_helm_cg3d<false>), gr, bl, 0, st, g, hp, w2, z, p_old, mask, p_new, q, r0,
-                       r1, i0, i1, S, r);
-  launch_finish(st, r, (int)(gr.x * gr.y * gr.z), false);
+    hipLaunchKernelGGL((k_helm_cg3d<false>), dim3(nb), dim3(NB), 0, st, g, hp, w2, z, p_old, mask,
+                       p_new, q, bx, S, r);
+  if (!finish) return nb;
+  launch_finish(st, r, nb, false);
+  return 0;
 }
 
 // -(smallest) and largest column index i of an inactive node (no inactive
@@ -969,9 +1347,11 @@ void launch_cheb_helm3d(hipStream_t st, const Grid& g, double cL, double cM, con
                                   const T*, T*, const ND<T>*, int, int, Red);                    \
   template void launch_resid3d<T>(hipStream_t, const Grid&, const Mat&, bool, const T*, double,  \
                                   const T*, T*, const ND<T>*, bool, Red);                        \
-  template void launch_smooth3d<T>(hipStream_t, const Grid&, const Mat&, bool, const T*, double, \
-                                   const ND<T>*, T*, const T*, const ND<T>*, ND<T>*, double,     \
-                                   double);                                                      \
+  template void launch_smooth3d<T>(hipStream_t, const Grid&, const Mat&, bool, const T*, const T*, \
+                                   double, const ND<T>*, T*, const T*, const ND<T>*, ND<T>*,     \
+                                   double, double);                                              \
+  template void launch_diag3d<T>(hipStream_t, const Grid&, const Mat&, bool, const T*, double,   \
+                                 T*);                                                            \
   template void launch_restrict3d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);       \
   template void launch_prolong3d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);
 INST3(float)

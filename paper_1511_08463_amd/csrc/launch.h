@@ -84,8 +84,11 @@ void launch_resid3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, cons
                     double kell, const T* x, T* r, const ND<T>* b, bool red, Red rr);
 template <class T>
 void launch_smooth3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
-                     double kell, const ND<T>* x_in, T* x_out, const T* b, const ND<T>* d_in,
-                     ND<T>* d_out, double cd, double cr);
+                     const T* dg, double kell, const ND<T>* x_in, T* x_out, const T* b,
+                     const ND<T>* d_in, ND<T>* d_out, double cd, double cr);
+template <class T>
+void launch_diag3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
+                   double kell, T* dg);
 void launch_coarsen3d(hipStream_t st, const Grid& gf, bool fine_is_alpha, const double* fine,
                       double kell, const Grid& gc, double* c64, float* c32);
 template <class T>
@@ -148,11 +151,12 @@ void launch_xpby(hipStream_t st, int64_t n, const double* z, double* p, const do
 void launch_cg_update_jac(hipStream_t st, const Box& bx, double* x, double* r, const double* p,
                           const double* q, const double* dinv, double* z, const double* S, Red rr,
                           Red rz, const double* pq_part = nullptr, int pq_nb = 0);
-void launch_helm_cg3d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
-                      const double* z, const double* p_old, const uint8_t* mask, double* p_new,
-                      double* q, int r0, int r1, int i0, int i1, const double* S, bool first, Red r);
-// Returns 0 after finishing the p.q reduction into S (3D, or finish set), else
-// the number of partials left for the consumer (2D with finish = false).
+int launch_helm_cg3d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
+                     const double* z, const double* p_old, const uint8_t* mask, double* p_new,
+                     double* q, int r0, int r1, int i0, int i1, const double* S, bool first, Red r,
+                     bool finish);
+// Returns 0 after finishing the p.q reduction into S (finish set), else the
+// number of partials left for the consumer (the CG update forms alpha).
 int launch_helm_cg2d(hipStream_t st, const Grid& g, double cL, double cM, const double* w2,
                      const double* z, const double* p_old, const uint8_t* mask, double* p_new,
                      double* q, int r0, int r1, int i0, int i1, const double* S, bool first, Red r,

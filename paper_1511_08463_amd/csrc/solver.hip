@@ -68,6 +68,9 @@ struct Level {
   // float32 copies for the mixed-precision multigrid
   float* abar32 = nullptr;
   float *b32 = nullptr, *xa32 = nullptr, *xb32 = nullptr, *d32 = nullptr, *r32 = nullptr;
+  // 3D smoothed levels: diag K(alpha) for the current coefficients
+  double* dg = nullptr;
+  float* dg32 = nullptr;
 };
 
 // Bump allocator over the caller's workspace (or a dry run that only counts).
@@ -144,6 +147,9 @@ struct fracture {
   double vi_phi2 = 0.0;
   bool vi_phi2_valid = false;
   int vi_stop = FRACTURE_STAGE_VI;        // which VI limit ended a failed damage solve
+  // absolute cap on the sub-solve tolerances of the current load step's
+  // sweeps (INFINITY: none); set once a sweep leaves the state unchanged
+  double sweep_cap = INFINITY;
   bool phi_reused = false;   // the last residual_launch took vi_phi2
   fracture_monitor_fn monitor = nullptr;
   void* monitor_user = nullptr;
@@ -203,6 +209,7 @@ int validate(const fracture_params* p) {
   if (p->newton_forcing_mode != 0 && p->newton_forcing_mode != 1) return FRACTURE_EINVAL;
   if (!(p->pcg_reduction >= 0 && p->pcg_reduction < 1)) return FRACTURE_EINVAL;
   if (!(p->vi_reduction >= 0 && p->vi_reduction < 1)) return FRACTURE_EINVAL;
+  if (p->elem3d_min_nodes < 0) return FRACTURE_EINVAL;
   if (!(p->newton_stall > 0 && p->newton_stall <= 1)) return FRACTURE_EINVAL;
   if (p->deflate != 0 && p->deflate != 1) return FRACTURE_EINVAL;
   if (p->deflate &&
@@ -232,6 +239,7 @@ Grid make_grid(const fracture_params* p, int nx, int ny, int nz, double hx, doub
   g.dim = p->dim;
   g.eig_dT = 0.0;
   g.eig_depth = p->thermal_depth;
+  g.elem_min = p->elem3d_min_nodes;
   return g;
 }
 
@@ -309,7 +317,10 @@ size_t layout(const fracture_params* p, fracture* h, void* ws) {
     v.xb = c.take<double>(m2);
     v.d = c.take<double>(m2);
     v.r = c.take<double>(m2);
+    const bool smoothed3 = dim == 3 && l < L - 1;
+    v.dg = smoothed3 ? c.take<double>(m2) : nullptr;
     if (p->precision == FRACTURE_MIXED) {
+      v.dg32 = smoothed3 ? c.take<float>(m2) : nullptr;
       v.abar32 = l > 0 ? c.take<float>(ne) : nullptr;
       v.b32 = c.take<float>(m2);
       v.xa32 = c.take<float>(m2);
@@ -509,6 +520,14 @@ void update_coefficients(fracture* h) {
     launch_coarsen2d(h->st, h->lv[l - 1].g, l == 1, level_coef(h, l - 1), h->p.k_ell, h->lv[l].g,
                      h->lv[l].abar, h->mixed ? h->lv[l].abar32 : nullptr);
   if (h->mixed) launch_to_float(h->st, h->N, h->alpha, h->alpha32, 1.0);
+  if (h->dim == 3)
+    for (int l = 0; l < h->nlev - 1; ++l) {
+      const Level& v = h->lv[l];
+      launch_diag3d<double>(h->st, v.g, h->mat, l == 0, l == 0 ? h->alpha : v.abar, h->p.k_ell, v.dg);
+      if (h->mixed)
+        launch_diag3d<float>(h->st, v.g, h->mat, l == 0, l == 0 ? h->alpha32 : v.abar32, h->p.k_ell,
+                             v.dg32);
+    }
   const int Lc = h->nlev - 1;
   if (Lc >= 1)
     launch_dense_setup(h->st, h->lv[Lc].g, h->mat, h->lv[Lc].abar, h->dA, h->dAinv, h->dref, h->S,
@@ -524,6 +543,7 @@ template <class T>
 struct LevelBufs {
   T *b, *xa, *xb, *d, *r;
   const T* coef;
+  const T* dg;   // 3D: the stored diagonal of K
 };
 
 template <class T>
@@ -532,13 +552,13 @@ LevelBufs<T> bufs(fracture* h, int l);
 template <>
 LevelBufs<double> bufs<double>(fracture* h, int l) {
   Level& v = h->lv[l];
-  return {v.b, v.xa, v.xb, v.d, v.r, l == 0 ? h->alpha : v.abar};
+  return {v.b, v.xa, v.xb, v.d, v.r, l == 0 ? h->alpha : v.abar, v.dg};
 }
 
 template <>
 LevelBufs<float> bufs<float>(fracture* h, int l) {
   Level& v = h->lv[l];
-  return {v.b32, v.xa32, v.xb32, v.d32, v.r32, l == 0 ? h->alpha32 : v.abar32};
+  return {v.b32, v.xa32, v.xb32, v.d32, v.r32, l == 0 ? h->alpha32 : v.abar32, v.dg32};
 }
 
 // One Jacobi-Chebyshev step of the V-cycle; while fracture_kernel_timing is
@@ -546,13 +566,15 @@ LevelBufs<float> bufs<float>(fracture* h, int l) {
 // events, with its algorithmic bytes (coefficients 8, b, x_in, a distinct
 // d_in, x_out, d_out per node).
 template <class T>
-void smooth_step(fracture* h, const Grid& g, bool fine, const T* coef, double kell, const T* x_in,
-                 T* x_out, const T* b, const T* din, T* dout, double cd, double cr,
+void smooth_step(fracture* h, const Grid& g, bool fine, const T* coef, const T* dg, double kell,
+                 const T* x_in, T* x_out, const T* b, const T* din, T* dout, double cd, double cr,
                  const Grid* gc = nullptr, const T* xc = nullptr) {
   const bool timed = fine && sizeof(T) == sizeof(double) && h->kt_cap > 0 &&
                      (h->kt_seen++ % KT_STRIDE == 0) && h->kt_used < h->kt_cap;
   if (timed) (void)hipEventRecord(h->kt_ev[2 * h->kt_used], h->st);
-  if (xc)
+  if (g.dim == 3)
+    launch_smooth3d<T>(h->st, g, h->mat, fine, coef, dg, kell, x_in, x_out, b, din, dout, cd, cr);
+  else if (xc)
     launch_prol_smooth2d<T>(h->st, g, *gc, h->mat, fine, coef, kell, x_in, xc, x_out, b, dout, cr);
   else
     launch_smooth2d<T>(h->st, g, h->mat, fine, coef, kell, x_in, x_out, b, din, dout, cd, cr);
@@ -560,7 +582,7 @@ void smooth_step(fracture* h, const Grid& g, bool fine, const T* coef, double ke
     (void)hipEventRecord(h->kt_ev[2 * h->kt_used + 1], h->st);
     const double dv = 8.0 * g.dim;
     h->kt_bytes += (double)g.N * (8.0 + dv + (x_in ? dv : 0.0) + (din && din != x_in ? dv : 0.0) +
-                                  dv + (dout ? dv : 0.0)) +
+                                  dv + (dout ? dv : 0.0) + (g.dim == 3 ? dv : 0.0)) +
                    (xc ? dv * gc->N : 0.0);
     ++h->kt_used;
   }
@@ -609,7 +631,8 @@ T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr, bool first_d
     }
     const T* din = s == 0 ? nullptr : (s == 1 ? cur : v.d);
     T* dout = (s < k - 1) ? v.d : nullptr;
-    smooth_step<T>(h, g, fine, v.coef, kell, cur, out, b, din, dout, h->cheb_cd[s], h->cheb_cr[s]);
+    smooth_step<T>(h, g, fine, v.coef, v.dg, kell, cur, out, b, din, dout, h->cheb_cd[s],
+                   h->cheb_cr[s]);
     cur = out;
   }
   // residual, restriction, coarse correction
@@ -635,8 +658,8 @@ T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr, bool first_d
     const T* din = s == 0 ? nullptr : v.d;
     T* dout = (s < k - 1) ? v.d : nullptr;
     const bool pr = s == 0 && prol_fused;
-    smooth_step<T>(h, g, fine, v.coef, kell, cur, out, b, din, dout, h->cheb_cd[s], h->cheb_cr[s],
-                   pr ? &h->lv[l + 1].g : nullptr, pr ? xc : nullptr);
+    smooth_step<T>(h, g, fine, v.coef, v.dg, kell, cur, out, b, din, dout, h->cheb_cd[s],
+                   h->cheb_cr[s], pr ? &h->lv[l + 1].g : nullptr, pr ? xc : nullptr);
     cur = out;
   }
   return cur;
@@ -708,10 +731,10 @@ float* vcycle0f(fracture* h, const float* b) {
 // Stopping tolerance of one elastic solve inside ORAM: the absolute
 // pcg_rtol * ||f||, or, under ORAM-N (whose Newton phase enforces the final
 // accuracy of u and alpha), the looser of that and pcg_reduction times the
-// residual at the warm start.
+// residual at the warm start; never looser than the step's sweep cap.
 double sweep_tol(const fracture* h, double tol, double r0) {
-  if (h->p.newton && h->p.pcg_reduction > 0) return std::fmax(tol, h->p.pcg_reduction * r0);
-  return tol;
+  if (h->p.newton && h->p.pcg_reduction > 0) tol = std::fmax(tol, h->p.pcg_reduction * r0);
+  return std::fmin(tol, h->sweep_cap);
 }
 
 // Crack-aware deflation: label the fragments of the current alpha and form
@@ -937,6 +960,7 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
     if (!std::isfinite(phimax) || !std::isfinite(phi2)) return FRACTURE_ENONFINITE;
     if (it == 0 && h->p.newton && h->p.vi_reduction > 0)
       stop = std::fmax(h->p.vi_tol, h->p.vi_reduction * phimax);
+    if (it == 0) stop = std::fmin(stop, h->sweep_cap);
     if (phimax <= stop) {
       h->vi_phi2 = phi2;
       h->vi_phi2_valid = true;
@@ -1384,6 +1408,7 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
   // plain alternate minimisation is measured, then Young's optimum
   // 2 / (1 + sqrt(1 - rho)) of SOR theory, capped at p.omega
   h->omega_cur = h->p.omega_auto ? 1.0 : h->p.omega;
+  h->sweep_cap = INFINITY;
   double da_hist[OMEGA_PROBE + 1] = {};
   for (int sweep = 1; sweep <= h->p.max_am; ++sweep) {
     update_coefficients(h);
@@ -1392,6 +1417,7 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
       if (rc) break;
     }
     HIPCHK(hipEventRecord(h->ev[1], st));
+    const int vi_before = loc.vi_iters;
     // elastic substep
     int it = 0;
     // tolerance: relative to the load vector; an absolute floor keeps zero loads finite
@@ -1441,6 +1467,12 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
       if (!std::isfinite(nphi)) { rc = FRACTURE_ENONFINITE; break; }
       if (h->monitor) h->monitor(h->monitor_user, sweep, loc.dalpha_inf, nphi);
       if (nphi <= h->p.final_tol) { loc.converged = 1; break; }
+      // a sweep whose sub-solves all stopped at once (their tolerances are
+      // looser than what is left of ||Phi||) changed nothing and every later
+      // sweep would repeat it: the step's sweeps solve to a tenth of the
+      // final tolerance from here on
+      if (it == 0 && loc.vi_iters == vi_before && loc.dalpha_inf == 0.0)
+        h->sweep_cap = 0.1 * h->p.final_tol;
       if (h->p.newton && nphi < threshold) {
         HIPCHK(hipEventRecord(h->ev[1], st));
         bool conv = false;
@@ -1594,6 +1626,7 @@ void fracture_default_params(fracture_params* p, int nx, int ny) {
   p->deflate_min_nodes = 64;
   p->deflate_max_fragments = DFL_FMAX;
   p->vi_reduction = 0.0;
+  p->elem3d_min_nodes = 1 << 18;
 }
 
 size_t fracture_workspace_bytes(const fracture_params* p) {
@@ -1956,8 +1989,12 @@ int fracture_time_kernel(fracture_t h, int kernel, int reps, double* avg_ms, dou
         launch_copy(st, n2, L0.xa, L0.xb);
         break;
       case FRACTURE_KERNEL_SMOOTH:
-        launch_smooth2d(st, g, h->mat, true, h->alpha, h->p.k_ell, L0.xa, L0.xb, L0.b, L0.d, L0.d,
-                        h->cheb_cd[1], h->cheb_cr[1]);
+        if (g.dim == 3)
+          launch_smooth3d<double>(st, g, h->mat, true, h->alpha, L0.dg, h->p.k_ell, L0.xa, L0.xb,
+                                  L0.b, L0.d, L0.d, h->cheb_cd[1], h->cheb_cr[1]);
+        else
+          launch_smooth2d(st, g, h->mat, true, h->alpha, h->p.k_ell, L0.xa, L0.xb, L0.b, L0.d, L0.d,
+                          h->cheb_cd[1], h->cheb_cr[1]);
         break;
       case FRACTURE_KERNEL_VI_EVAL:
         launch_vi_eval2d(st, g, h->cL, h->cM, h->cm, h->w2, h->alpha, nullptr, h->alpha_prev, h->S,
@@ -1976,7 +2013,7 @@ int fracture_time_kernel(fracture_t h, int kernel, int reps, double* avg_ms, dou
   const double w2b = 8.0 * (h->dim == 3 ? 6 : 2);  // W2 per node (elements per node)
   switch (kernel) {
     case FRACTURE_KERNEL_APPLY: b = (2 * dv + 8.0) * N; break;
-    case FRACTURE_KERNEL_SMOOTH: b = (5 * dv + 8.0) * N; break;
+    case FRACTURE_KERNEL_SMOOTH: b = (5 * dv + 8.0 + (h->dim == 3 ? dv : 0.0)) * N; break;
     case FRACTURE_KERNEL_VI_EVAL: b = (8.0 + 8.0 + w2b + 8.0 + 8.0 + 1.0 + 8.0) * N; break;
     case FRACTURE_KERNEL_HELM: b = (8.0 + w2b + 1.0 + 8.0) * N; break;
     case FRACTURE_KERNEL_COPY: b = 2.0 * dv * N; break;

@@ -85,7 +85,7 @@ class fracture_params(ctypes.Structure):
         ("thermal_dT", ctypes.c_double),
         ("deflate", ctypes.c_int), ("deflate_theta", ctypes.c_double),
         ("deflate_min_nodes", ctypes.c_int), ("deflate_max_fragments", ctypes.c_int),
-        ("vi_reduction", ctypes.c_double),
+        ("vi_reduction", ctypes.c_double), ("elem3d_min_nodes", ctypes.c_int),
     ]
 
 

@@ -68,7 +68,7 @@ def gpu_instance(req, device):
 
 class Service:
     def __init__(self, budget_bytes, max_slots=16, workers=4, device="cuda:0", keep_state=False,
-                 factory=None, size_of=footprint):
+                 factory=None, size_of=footprint, progress=None):
         self.budget = int(budget_bytes)
         self.max_slots = max_slots
         self.workers = workers
@@ -76,6 +76,7 @@ class Service:
         self.keep_state = keep_state
         self.factory = factory or gpu_instance
         self.size_of = size_of
+        self.progress = progress     # optional callable(finished, total, elapsed_s)
 
     def run(self, requests):
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -156,6 +157,8 @@ class Service:
                         del active[rid]
                         res.finished_at = done_t
                         finished[0] += 1
+                        if self.progress is not None:
+                            self.progress(finished[0], n_total, done_t)
                         if finished[0] >= n_total:
                             stop[0] = True
                         admit_locked()

@@ -502,20 +502,52 @@ def _problem3(p):
                                **workloads.oracle_kwargs3(p))
 
 
-SHAPES3 = [(4, 4, 2), (12, 10, 6), (70, 4, 2)]
+# the last shape spans several 15 x 15 x 4 node tiles of the element
+# kernels in every direction, with ragged tiles at the high ends
+SHAPES3 = [(4, 4, 2), (12, 10, 6), (70, 4, 2), (40, 32, 16)]
 
 
+# elem3d_min_nodes selecting each 3D kernel family on every level: the
+# element-centric kernels (0) and one thread per node (2^30)
+KERNELS3 = {"elem": 0, "node": 1 << 30}
+
+
+@pytest.mark.parametrize("kern", list(KERNELS3))
 @pytest.mark.parametrize("nx,ny,nz", SHAPES3)
-def test_elasticity_apply_3d_matches_assembled(nx, ny, nz):
+def test_elasticity_apply_3d_matches_assembled(nx, ny, nz, kern):
     p = workloads.thermal(nx, ny, nz, 1.0, 0.8, 0.5)
-    print(f"[apply3d] {nx}x{ny}x{nz}", flush=True)
-    s = _solver(p)
+    print(f"[apply3d] {nx}x{ny}x{nz} {kern}", flush=True)
+    s = _solver(p, elem3d_min_nodes=KERNELS3[kern])
     P = _problem3(p)
     u, alpha = workloads.random_fields(P.model.N, 3 * P.model.N, seed=nx + ny + nz)
     s.set_state(u=u, alpha=alpha)
     y = s.apply(fracture.FRACTURE_OP_ELASTICITY, u)
     want = P.model.K(alpha) @ u
     assert np.max(np.abs(y - want)) / np.max(np.abs(want)) < OPS_TOL
+    s.close()
+
+
+@pytest.mark.parametrize("kern", list(KERNELS3))
+def test_preconditioner_3d_is_symmetric_positive(kern):
+    """The 3D V-cycle (Chebyshev smoothing with the stored diagonal of K,
+    Galerkin coarse levels) is a symmetric positive operator on the free
+    DOFs, on a slab of several element tiles per direction, with either
+    kernel family."""
+    p = workloads.thermal(32, 32, 8, 1.0, 0.9, 0.25)
+    s = _solver(p, elem3d_min_nodes=KERNELS3[kern])
+    P = _problem3(p)
+    N = P.model.N
+    rng = np.random.default_rng(4)
+    alpha = np.clip(rng.uniform(-0.5, 1.0, N), 0, 1)
+    s.set_state(alpha=alpha)
+    fracture.fracture_update_coefficients(s.h)
+    x = rng.standard_normal(3 * N) * P.free
+    y = rng.standard_normal(3 * N) * P.free
+    Mx = s.apply(fracture.FRACTURE_OP_PRECOND, x)
+    My = s.apply(fracture.FRACTURE_OP_PRECOND, y)
+    assert np.all(Mx[P.fixed] == 0)
+    assert abs(x @ My - y @ Mx) <= 1e-10 * abs(x @ Mx)
+    assert x @ Mx > 0 and y @ My > 0
     s.close()
 
 
@@ -594,16 +626,17 @@ def test_gradients_3d_with_eigenstrain_match():
     s.close()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_thermal_3d_load_path_parity(precision):
+@pytest.mark.parametrize("precision,kern", [(0, "node"), (1, "node"), (0, "elem"), (1, "elem")])
+def test_thermal_3d_load_path_parity(precision, kern):
     """A 32x8x4 slab under a growing thermal shock: AM load steps against the
     oracle.  Here the heated layer (depth 0.05) is thinner than ell = 0.125, so
     damage starts near 8 DT_c rather than at the thick-layer estimate DT_c."""
     p = workloads.thermal(32, 8, 4, 1.0, 0.25, 0.125)
     dtc = workloads.thermal_dtc(p)
     loads = [2.0 * dtc, 8.5 * dtc, 10.0 * dtc]
-    print(f"[thermal3d] precision={precision} dtc={dtc:.3f}", flush=True)
-    s = _solver(p, None, precision=precision, am_tol=1e-10, pcg_rtol=1e-13, vi_cg_rtol=1e-13)
+    print(f"[thermal3d] precision={precision} kernels={kern} dtc={dtc:.3f}", flush=True)
+    s = _solver(p, None, precision=precision, am_tol=1e-10, pcg_rtol=1e-13, vi_cg_rtol=1e-13,
+                elem3d_min_nodes=KERNELS3[kern])
     P = _problem3(p)
     st = am.initial_state(P)
     grew = False
