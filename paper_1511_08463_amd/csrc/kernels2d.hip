@@ -585,8 +585,9 @@ __device__ __forceinline__ void tri_helm2(const Grid& g, const Helm& hp,
   const double gry = a0 * gy[0] + a1 * gy[1] + a2 * gy[2];
   const double lap = area * (gx[TK::v] * grx + gy[TK::v] * gry);  // (L_e a)_v
   Ha += (we + hp.cM) * mass + hp.cL * lap;
-  gv += (we - hp.cm) * area / 3.0;
-  Hd += (we + hp.cM) * area / 6.0 + hp.cL * area * (gx[TK::v] * gx[TK::v] + gy[TK::v] * gy[TK::v]);
+  // (constant factors grouped: the divisions are loop-invariant, one per thread)
+  gv += (we - hp.cm) * (area / 3.0);
+  Hd += (we + hp.cM) * (area / 6.0) + hp.cL * area * (gx[TK::v] * gx[TK::v] + gy[TK::v] * gy[TK::v]);
 }
 
 // (H a)_v, g_v and H_vv at node (i,j) for the damage field a; when TRIAL the
@@ -693,8 +694,9 @@ __device__ __forceinline__ void tri_helm2v(const Grid& g, const Helm& hp, double
   const double gry = a0 * gy[0] + a1 * gy[1] + a2 * gy[2];
   const double lap = area * (gx[TK::v] * grx + gy[TK::v] * gry);
   Ha += (we + hp.cM) * mass + hp.cL * lap;
-  gv += (we - hp.cm) * area / 3.0;
-  Hd += (we + hp.cM) * area / 6.0 + hp.cL * area * (gx[TK::v] * gx[TK::v] + gy[TK::v] * gy[TK::v]);
+  // (constant factors grouped: the divisions are loop-invariant, one per thread)
+  gv += (we - hp.cm) * (area / 3.0);
+  Hd += (we + hp.cM) * (area / 6.0) + hp.cL * area * (gx[TK::v] * gx[TK::v] + gy[TK::v] * gy[TK::v]);
 }
 
 // Column-walking form of k_vi_eval2d for large grids: one wavefront per

@@ -674,10 +674,16 @@ __device__ __forceinline__ void kuhn_grad(int p, int v, const double ih[3], doub
 // One tetrahedron's part of (H a)_v, g_v and H_vv for node v = (i, j, k): hex
 // offset (HX, HY, HZ), tetrahedron P, the node as local vertex V (all known
 // at compile time); av holds the field on the node's 15-point stencil.
+// Per-thread constants of tet_helm: the tetrahedron volume and its mass and
+// load factors, formed once (not once per tetrahedron).
+struct TetK {
+  double vol, m20, m4, m10;   // |T|, |T|/20, |T|/4, |T|/10
+};
+
 template <int HX, int HY, int HZ, int P, int V>
 __device__ __forceinline__ void tet_helm(const Grid& g, const Helm3& hp,
                                          const double* __restrict__ w2, const double (&av)[27],
-                                         int i, int j, int k, const double ih[3], double vol,
+                                         int i, int j, int k, const double ih[3], const TetK& tk,
                                          double& Ha, double& gv, double& Hd) {
   const int ci = i + HX, cj = j + HY, ck = k + HZ;
   if (ci < 0 || cj < 0 || ck < 0 || ci >= g.nx || cj >= g.ny || ck >= g.nz) return;
@@ -693,11 +699,11 @@ __device__ __forceinline__ void tet_helm(const Grid& g, const Helm3& hp,
   grad3<P, V>(ih, gvv);
   const double we = w2[6 * (ci + g.nx * (cj + g.ny * ck)) + P];
   const double aV = V == 0 ? a0 : (V == 1 ? a1 : (V == 2 ? a2 : a3));
-  const double mass = vol / 20.0 * (aV + a0 + a1 + a2 + a3);   // (M_e a)_v
-  const double lap = vol * (gvv[0] * grad[0] + gvv[1] * grad[1] + gvv[2] * grad[2]);
+  const double mass = tk.m20 * (aV + a0 + a1 + a2 + a3);   // (M_e a)_v
+  const double lap = tk.vol * (gvv[0] * grad[0] + gvv[1] * grad[1] + gvv[2] * grad[2]);
   Ha += (we + hp.cM) * mass + hp.cL * lap;
-  gv += (we - hp.cm) * vol / 4.0;
-  Hd += (we + hp.cM) * vol / 10.0 + hp.cL * vol * (gvv[0] * gvv[0] + gvv[1] * gvv[1] + gvv[2] * gvv[2]);
+  gv += (we - hp.cm) * tk.m4;
+  Hd += (we + hp.cM) * tk.m10 + hp.cL * tk.vol * (gvv[0] * gvv[0] + gvv[1] * gvv[1] + gvv[2] * gvv[2]);
 }
 
 // (H a)_v, g_v and H_vv at node (i,j,k) over its 24 tetrahedra, enumerated
@@ -715,6 +721,7 @@ __device__ __forceinline__ void helm_node3d(const Grid& g, const Helm3& hp,
   const int n = i + W * (j + H * k);
   const double ih[3] = {1.0 / g.hx, 1.0 / g.hy, 1.0 / g.hz};
   const double vol = g.hx * g.hy * g.hz / 6.0;
+  const TetK tk{vol, vol / 20.0, vol / 4.0, vol / 10.0};
   Ha = gv = Hd = 0.0;
   auto val = [&](int q) -> double {
     if (TRIAL) return fmin(fmax(a[q] + mu * d[q], lo[q]), 1.0);
@@ -730,7 +737,7 @@ __device__ __forceinline__ void helm_node3d(const Grid& g, const Helm3& hp,
   }
   FOR_STENCIL3(LOADH3)
 #undef LOADH3
-#define HELM3(HX, HY, HZ, P, V) tet_helm<HX, HY, HZ, P, V>(g, hp, w2, av, i, j, k, ih, vol, Ha, gv, Hd);
+#define HELM3(HX, HY, HZ, P, V) tet_helm<HX, HY, HZ, P, V>(g, hp, w2, av, i, j, k, ih, tk, Ha, gv, Hd);
   FOR_TETS3(HELM3)
 #undef HELM3
 }
