@@ -699,94 +699,6 @@ __device__ __forceinline__ void tri_helm2v(const Grid& g, const Helm& hp, double
   Hd += (we + hp.cM) * (area / 6.0) + hp.cL * area * (gx[TK::v] * gx[TK::v] + gy[TK::v] * gy[TK::v]);
 }
 
-// Column-walking form of k_vi_eval2d for large grids: one wavefront per
-// 64-column tile of VI_ROWS rows, thread i walking its column with a
-// three-row window of the field (columns i-1, i, i+1) and two cell rows of
-// W2 (cells i-1 and i, both triangles), so each row is loaded once per tile
-// instead of once per 64 x 4 node tile.  Per node the same arithmetic as
-// k_vi_eval2d (helm_node2d's six triangles in the same order).
-constexpr int VI_ROWS = 16;
-
-template <bool TRIAL>
-__global__ __launch_bounds__(NB_X) void k_vi_eval_col2d(Grid g, Helm hp,
-                                                        const double* __restrict__ w2,
-                                                        const double* __restrict__ a,
-                                                        const double* __restrict__ d,
-                                                        const double* __restrict__ lo,
-                                                        const double* __restrict__ S, int mu_slot,
-                                                        double zeta, double* __restrict__ F,
-                                                        double* __restrict__ phi,
-                                                        uint8_t* __restrict__ mask,
-                                                        double* __restrict__ hdinv, Red r2, Red rm,
-                                                        Red rlo, Red rhi) {
-  const int nbx = gridDim.x, total = gridDim.x * gridDim.y;
-  const int t = xcd_tile(blockIdx.x + nbx * blockIdx.y, total);
-  const int i = (t % nbx) * NB_X + threadIdx.x;
-  const int j0 = (t / nbx) * VI_ROWS;
-  const int W = g.nx + 1, nx = g.nx;
-  const double mu = TRIAL ? S[mu_slot] : 0.0;
-  const double ihx = 1.0 / g.hx, ihy = 1.0 / g.hy, area = 0.5 * g.hx * g.hy;
-  double p2 = 0.0, pm = 0.0, jlo = -INFINITY, jhi = -INFINITY;
-  if (i <= g.nx) {
-    // field value at node (ii, r), zero outside the grid
-    auto val = [&](int ii, int r) -> double {
-      if (ii < 0 || ii > g.nx || r < 0 || r > g.ny) return 0.0;
-      const int q = ii + W * r;
-      return TRIAL ? fmin(fmax(a[q] + mu * d[q], lo[q]), 1.0) : a[q];
-    };
-    // W2 of cell (ci, cj), triangle tt (unused outside the grid)
-    auto w2at = [&](int ci, int cj, int tt) -> double {
-      return (ci < 0 || cj < 0 || ci >= g.nx || cj >= g.ny) ? 0.0 : w2[2 * (ci + nx * cj) + tt];
-    };
-    double rlo_[3], rc_[3], rhi_[3];    // field rows j-1, j, j+1 at columns i-1, i, i+1
-    for (int q = 0; q < 3; ++q) {
-      rlo_[q] = val(i - 1 + q, j0 - 1);
-      rc_[q] = val(i - 1 + q, j0);
-    }
-    double wlo[4] = {w2at(i - 1, j0 - 1, 0), w2at(i - 1, j0 - 1, 1), w2at(i, j0 - 1, 0),
-                     w2at(i, j0 - 1, 1)};
-    for (int s = 0; s < VI_ROWS; ++s) {
-      const int j = j0 + s;
-      if (j > g.ny) break;
-      for (int q = 0; q < 3; ++q) rhi_[q] = val(i - 1 + q, j + 1);
-      const double wup[4] = {w2at(i - 1, j, 0), w2at(i - 1, j, 1), w2at(i, j, 0), w2at(i, j, 1)};
-      // the 3x3 neighbourhood in helm_node2d's slot order: (dx + 1) + 3 (dy + 1)
-      const double av[9] = {rlo_[0], rlo_[1], rlo_[2], rc_[0], rc_[1], rc_[2],
-                            rhi_[0], rhi_[1], rhi_[2]};
-      double Ha = 0.0, gvv = 0.0, Hd = 0.0;
-      tri_helm2v<0>(g, hp, wup[2], av, i, j, ihx, ihy, area, Ha, gvv, Hd);   // cell (i, j) T0
-      tri_helm2v<1>(g, hp, wup[3], av, i, j, ihx, ihy, area, Ha, gvv, Hd);   // cell (i, j) T1
-      tri_helm2v<2>(g, hp, wup[0], av, i, j, ihx, ihy, area, Ha, gvv, Hd);   // cell (i-1, j) T0
-      tri_helm2v<3>(g, hp, wlo[0], av, i, j, ihx, ihy, area, Ha, gvv, Hd);   // cell (i-1, j-1) T0
-      tri_helm2v<4>(g, hp, wlo[1], av, i, j, ihx, ihy, area, Ha, gvv, Hd);   // cell (i-1, j-1) T1
-      tri_helm2v<5>(g, hp, wlo[3], av, i, j, ihx, ihy, area, Ha, gvv, Hd);   // cell (i, j-1) T1
-      const int n = i + W * j;
-      const double x = rc_[1];
-      const double l = lo[n];
-      const double Fv = Ha - gvv;
-      const double ph = mcp_fb(x, Fv, l, 1.0);
-      p2 += ph * ph;
-      pm = fmax(pm, nan_to_inf(fabs(ph)));
-      if (!TRIAL) {
-        F[n] = Fv;
-        phi[n] = ph;
-        const bool act = (x - l <= zeta && Fv > 0.0) || (1.0 - x <= zeta && Fv < 0.0) || (l >= 1.0);
-        mask[n] = act ? 1 : 0;
-        hdinv[n] = act ? 0.0 : 1.0 / Hd;
-        if (!act) { jlo = fmax(jlo, -(double)j); jhi = fmax(jhi, (double)j); }
-      }
-      for (int q = 0; q < 3; ++q) { rlo_[q] = rc_[q]; rc_[q] = rhi_[q]; }
-      for (int q = 0; q < 4; ++q) wlo[q] = wup[q];
-    }
-  }
-  block_reduce<NB_X, false>(p2, r2, total, t, threadIdx.x);
-  block_reduce<NB_X, true>(pm, rm, total, t, threadIdx.x);
-  if (!TRIAL) {
-    block_reduce<NB_X, true>(jlo, rlo, total, t, threadIdx.x);
-    block_reduce<NB_X, true>(jhi, rhi, total, t, threadIdx.x);
-  }
-}
-
 // LDS-staged form for large grids: a block of 256 threads takes a 64 x 16
 // node tile, first loads the tile's field (with a one-node halo) and the W2
 // of its cells (cell columns i-1 and i of every node) into LDS with all loads
