@@ -148,20 +148,43 @@ __global__ __launch_bounds__(NB) void k_elem3d(Grid g, Mat m, const T* __restric
     SEIG(0) SEIG(1) SEIG(2) SEIG(3) SEIG(4) SEIG(5)
 #undef SEIG
   }
-  auto load_plane = [&](int p) {
-    if (p < 0 || p > g.nz) return;
-    const int sl = p % 3;
-    for (int e = tid; e < E3_PN; e += NB) {
+  // A node plane is fetched into registers one layer ahead (this thread's
+  // tile entries tid and tid + NB) and written to LDS after the layer's
+  // arithmetic, so no layer waits on its own global loads.
+  constexpr int PE = (E3_PN + NB - 1) / NB;
+  T pu[PE][3], pa[PE];
+  auto fetch_plane = [&](int p) {
+#pragma unroll
+    for (int r = 0; r < PE; ++r) {
+      const int e = tid + r * NB;
+      pu[r][0] = pu[r][1] = pu[r][2] = pa[r] = T(0);
       const int lx = e % E3_P, ly = e / E3_P;
       const int gi = i0 - 1 + lx, gj = j0 - 1 + ly;
-      const bool ok = gi >= 0 && gj >= 0 && gi <= g.nx && gj <= g.ny;
-      const int n = gi + W * (gj + H * p);
-      if constexpr (HASX) {
-        su[sl][0][e] = ok ? x[n] : T(0);
-        su[sl][1][e] = ok ? x[n + N] : T(0);
-        su[sl][2][e] = ok ? x[n + 2 * N] : T(0);
+      if (e < E3_PN && p >= 0 && p <= g.nz && gi >= 0 && gj >= 0 && gi <= g.nx && gj <= g.ny) {
+        const int n = gi + W * (gj + H * p);
+        if constexpr (HASX) {
+          pu[r][0] = x[n];
+          pu[r][1] = x[n + N];
+          pu[r][2] = x[n + 2 * N];
+        }
+        if constexpr (NEED_A) pa[r] = coef[n];
       }
-      if constexpr (NEED_A) sa[sl][e] = ok ? coef[n] : T(0);
+    }
+  };
+  auto store_plane = [&](int p) {
+    if (p < 0 || p > g.nz) return;
+    const int sl = p % 3;
+#pragma unroll
+    for (int r = 0; r < PE; ++r) {
+      const int e = tid + r * NB;
+      if (e < E3_PN) {
+        if constexpr (HASX) {
+          su[sl][0][e] = pu[r][0];
+          su[sl][1][e] = pu[r][1];
+          su[sl][2][e] = pu[r][2];
+        }
+        if constexpr (NEED_A) sa[sl][e] = pa[r];
+      }
     }
   };
   for (int e = tid; e < E3_PN; e += NB) {
@@ -171,10 +194,29 @@ __global__ __launch_bounds__(NB) void k_elem3d(Grid g, Mat m, const T* __restric
       if constexpr (DIAG) { sd[0][q][e] = T(0); sd[1][q][e] = T(0); }
     }
   }
-  load_plane(k0 - 1);
+  fetch_plane(k0 - 1);
+  store_plane(k0 - 1);
+  fetch_plane(k0);
+  store_plane(k0);
   double acc = 0.0;
   for (int ck = k0 - 1; ck <= ke; ++ck) {
-    load_plane(ck + 1);
+    // next layer's upper plane, and the owned node's inputs of this layer's
+    // finishing step, are in flight during the layer
+    if (ck < ke) fetch_plane(ck + 2);   // the upper plane of layer ck + 1
+    const bool bot = ck >= k0, top = ck + 1 <= ke;
+    T eb[3] = {T(0), T(0), T(0)}, ed[3] = {T(0), T(0), T(0)}, eg[3] = {T(1), T(1), T(1)};
+    if (bot && owner) {
+      const int n = (i0 + tx) + W * ((j0 + ty) + H * ck);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int q = n + c * N;
+        if (MODE != M3_DIAG && b) eb[c] = b[q];
+        if (MODE == M3_SMOOTH) {
+          eg[c] = dg[q];
+          if (din) ed[c] = din[q];
+        }
+      }
+    }
     __syncthreads();
     T fv[8][3], dv[8][3];
 #pragma unroll
@@ -211,7 +253,6 @@ __global__ __launch_bounds__(NB) void k_elem3d(Grid g, Mat m, const T* __restric
     }
     // the four vertex positions in the x-y plane, one phase each: bottom
     // vertices into the sums of plane ck, top vertices into those of ck + 1
-    const bool bot = ck >= k0, top = ck + 1 <= ke;
     const int fb0 = (ck + 2) & 1, fb1 = (ck + 3) & 1;
 #pragma unroll
     for (int ph = 0; ph < 4; ++ph) {
@@ -250,17 +291,17 @@ __global__ __launch_bounds__(NB) void k_elem3d(Grid g, Mat m, const T* __restric
             y[q] = yv;
             if (RED == R3_DOT) acc += (double)xv * yv;
             if (RED == R3_FREE2) {
-              const double r = (double)f - (b ? (double)b[q] : 0.0);
+              const double r = (double)f - (double)eb[c];
               acc += fx ? 0.0 : r * r;
             }
           } else if (MODE == M3_RESID) {
-            const T r = fx ? T(0) : (b ? b[q] : T(0)) - f;
+            const T r = fx ? T(0) : eb[c] - f;
             y[q] = r;
             if (RED == R3_DOT) acc += (double)r * r;
           } else if (MODE == M3_SMOOTH) {
-            const T r = (b ? b[q] : T(0)) - f;
-            T dd = cr * r / dg[q];
-            if (din) dd += cd * din[q];
+            const T r = eb[c] - f;
+            T dd = cr * r / eg[c];
+            if (din) dd += cd * ed[c];
             T xo = xv + dd;
             if (fx) { xo = T(0); dd = T(0); }
             y[q] = xo;
@@ -293,6 +334,7 @@ __global__ __launch_bounds__(NB) void k_elem3d(Grid g, Mat m, const T* __restric
         }
       }
     }
+    if (ck < ke) store_plane(ck + 2);
   }
   if (RED != R3_NONE)
     block_reduce<NB, false>(acc, red, gridDim.x * gridDim.y * gridDim.z,
