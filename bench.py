@@ -80,6 +80,7 @@ def cpu_baseline(n_sample, steps, model="AT1"):
 def serve(args):
     """The served stream (config 5): first --instances requests of the seeded
     Poisson stream, admitted under a device memory budget, run concurrently."""
+    import numpy as np
     from paper_1511_08463_amd import serving, workloads
     reqs = [serving.Request(r["rid"], r["params"], r["notch"], r["loads"], r["arrival"])
             for r in workloads.config5(n_instances=args.instances)]
@@ -90,9 +91,29 @@ def serve(args):
         if done % 16 == 0 or done == total:
             log(f"[serve] {done}/{total} requests finished at {t:.1f} s")
 
-    svc = serving.Service(budget, max_slots=args.slots, workers=args.workers, progress=progress)
-    summary, _ = svc.run(reqs)
+    # a sample of the stream (the first two requests of each side up to 512)
+    # is re-run alone afterwards and compared bit for bit with its result in
+    # the mix
+    sample, seen = [], {}
+    for r in reqs:
+        n = r.params["nx"]
+        if n <= 512 and seen.get(n, 0) < 2:
+            seen[n] = seen.get(n, 0) + 1
+            sample.append(r)
+    keep = {r.rid for r in sample} if args.serve_check else set()
+    svc = serving.Service(budget, max_slots=args.slots, workers=args.workers, keep_state=keep,
+                          progress=progress)
+    summary, results = svc.run(reqs)
     log(f"[serve] {summary}")
+    if args.serve_check:
+        equal = []
+        for r in sample:
+            alone, _ = serving.run_alone(r)
+            same = all(np.array_equal(a, b) for a, b in zip(alone, results[r.rid].state))
+            equal.append(same)
+            log(f"[serve] rid {r.rid} n={r.params['nx']} steps={len(r.loads)} alone == mixed: {same}")
+        summary["alone_equal"] = f"{sum(equal)}/{len(equal)}"
+        summary["alone_checked"] = [dict(rid=r.rid, n=r.params["nx"]) for r in sample]
     return summary
 
 
@@ -205,10 +226,10 @@ def time_kernels(solver, reps):
 # (sha256 over the files below: the kernels and the driver that sets each
 # launch's operands).
 TRAFFIC = {
-    # profiles/hbm_traffic_2048_at1.md: mean over 344 launches of load steps 1-3,
-    # FETCH x 1.9997 + WRITE x 1.0000 (88 B/node form back to back: 384.7 MB)
-    "bytes": 292243105,
-    "source_sha256": "7ba9f599038c54d5bdd825d809553c35a45f6ba03769ac491919d1aa78df205c",
+    # profiles/hbm_traffic_2048_at1.md: mean over the 570 launches of the
+    # warm-up step and load steps 1-3, FETCH x 1.9997 + WRITE x 1.0000
+    "bytes": 292161174,
+    "source_sha256": "a72fba16d3fafc4cfd4d3f63e8cf4897eb02c68fc7014ac72e5cb88d2aed69bc",
 }
 TRAFFIC_SOURCES = ("paper_1511_08463_amd/csrc/common.h", "paper_1511_08463_amd/csrc/ops2d.h",
                    "paper_1511_08463_amd/csrc/kernels2d.hip", "paper_1511_08463_amd/csrc/solver.hip")
@@ -455,6 +476,8 @@ def parse_args(argv=None):
                          "32), so that the instances' streams do not share four queues")
     ap.add_argument("--budget-gb", type=float, default=4.0)
     ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--no-serve-check", dest="serve_check", action="store_false",
+                    help="served stream: skip re-running a sample alone for the bitwise check")
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--dry-run", action="store_true",
                     help="validate the arguments, print the plan as JSON and exit (no GPU)")

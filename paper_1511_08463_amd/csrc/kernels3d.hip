@@ -623,6 +623,35 @@ void launch_restrict3d(hipStream_t st, const Grid& gf, const Grid& gc, const T* 
   hipLaunchKernelGGL((k_restrict3d<T>), node_grid3(gc), dim3(NB_X, NB_Y), 0, st, gf, gc, rf, bc);
 }
 
+// Restriction with the coarse level's first Chebyshev step from zero
+// (pointwise in 3D: x = d = cr D^{-1} b_c, fixed DOFs zero), one launch.
+template <class T>
+__global__ __launch_bounds__(NB) void k_restrict_smooth3d(Grid gf, Grid gc, const T* __restrict__ rf,
+                                                          T* __restrict__ bc,
+                                                          const T* __restrict__ dgc,
+                                                          T* __restrict__ xc, T* __restrict__ dc,
+                                                          T cr) {
+  const int I = blockIdx.x * NB_X + threadIdx.x, J = blockIdx.y * NB_Y + threadIdx.y, K = blockIdx.z;
+  if (I > gc.nx || J > gc.ny) return;
+  restrict_node3d(gf, gc, rf, bc, I, J, K);
+  const int nc = I + (gc.nx + 1) * (J + (gc.ny + 1) * K);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int q = nc + c * gc.N;
+    T dd = cr * bc[q] / dgc[q];   // bc[q]: the value this thread has just written
+    if (fixed3(gc, c, I, J, K)) dd = T(0);
+    xc[q] = dd;
+    if (dc) dc[q] = dd;
+  }
+}
+
+template <class T>
+void launch_restrict_smooth3d(hipStream_t st, const Grid& gf, const Grid& gc, const T* rf, T* bc,
+                              const T* dgc, T* xc, T* dc, double cr) {
+  hipLaunchKernelGGL((k_restrict_smooth3d<T>), node_grid3(gc), dim3(NB_X, NB_Y), 0, st, gf, gc, rf,
+                     bc, dgc, xc, dc, T(cr));
+}
+
 template <class T>
 __global__ __launch_bounds__(NB) void k_prolong3d(Grid gf, Grid gc, const T* __restrict__ xc,
                                                   T* __restrict__ xf) {
@@ -1402,6 +1431,8 @@ void launch_cheb_helm3d(hipStream_t st, const Grid& g, double cL, double cM, con
   template void launch_diag3d<T>(hipStream_t, const Grid&, const Mat&, bool, const T*, double,   \
                                  T*);                                                            \
   template void launch_restrict3d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);       \
+  template void launch_restrict_smooth3d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*,  \
+                                            const T*, T*, T*, double);                          \
   template void launch_prolong3d<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);
 INST3(float)
 INST3(double)

@@ -94,6 +94,9 @@ void launch_coarsen3d(hipStream_t st, const Grid& gf, bool fine_is_alpha, const 
 template <class T>
 void launch_restrict3d(hipStream_t st, const Grid& gf, const Grid& gc, const T* rf, T* bc);
 template <class T>
+void launch_restrict_smooth3d(hipStream_t st, const Grid& gf, const Grid& gc, const T* rf, T* bc,
+                              const T* dgc, T* xc, T* dc, double cr);
+template <class T>
 void launch_prolong3d(hipStream_t st, const Grid& gf, const Grid& gc, const T* xc, T* xf);
 void launch_lift3d(hipStream_t st, const Grid& g, double* u);
 void launch_w2_3d(hipStream_t st, const Grid& g, const Mat& m, const double* u, double* w2);

@@ -641,8 +641,11 @@ T* vcycle_t(fracture* h, int l, const T* b, T* final_out = nullptr, bool first_d
   LevelBufs<T> c = bufs<T>(h, l + 1);
   // a next level smoothed by per-level kernels takes its first step from
   // zero together with the restriction
-  const bool fuse = g.dim == 2 && l + 1 < h->nlev - 1 && !(h->p.vcycle_tail && l + 1 == tail);
-  if (fuse)
+  const bool fuse = l + 1 < h->nlev - 1 && !(h->p.vcycle_tail && l + 1 == tail);
+  if (fuse && g.dim == 3)
+    launch_restrict_smooth3d<T>(h->st, g, h->lv[l + 1].g, v.r, c.b, c.dg, c.xa,
+                                k > 1 ? c.d : nullptr, h->cheb_cr[0]);
+  else if (fuse)
     launch_restrict_smooth2d<T>(h->st, g, h->lv[l + 1].g, h->mat, c.coef, kell, v.r, c.b, c.xa,
                                 k > 1 ? c.d : nullptr, h->cheb_cr[0]);
   else

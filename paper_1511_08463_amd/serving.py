@@ -17,10 +17,11 @@ time.  The scheduler:
   lets waiting requests in.
 
 Each step's latency runs from the moment it becomes eligible (the request's
-arrival for its first step, the previous step's completion otherwise) to its
-completion, so queueing for admission and for a worker counts.  Results do
-not depend on the mix: every instance computes with its own buffers and
-fixed-order reductions.
+admission for its first step, the previous step's completion otherwise) to
+its completion, so waiting for a worker counts; the wait for admission
+(arrival to admission) is reported on its own.  Results do not depend on the
+mix: every instance computes with its own buffers and fixed-order
+reductions.
 """
 
 import dataclasses
@@ -49,6 +50,7 @@ class Result:
     stats: list
     state: tuple = None               # (u, alpha, alpha_prev) when kept
     admitted_at: float = 0.0
+    queue_wait: float = 0.0           # arrival to admission, seconds
     finished_at: float = 0.0
     codes: list = dataclasses.field(default_factory=list)
 
@@ -69,6 +71,8 @@ def gpu_instance(req, device):
 class Service:
     def __init__(self, budget_bytes, max_slots=16, workers=4, device="cuda:0", keep_state=False,
                  factory=None, size_of=footprint, progress=None):
+        """keep_state: True keeps every request's final (u, alpha, alpha_prev)
+        on the host, or a set of request ids keeps those only."""
         self.budget = int(budget_bytes)
         self.max_slots = max_slots
         self.workers = workers
@@ -114,9 +118,11 @@ class Service:
                 inst = self.factory(r, self.device)
                 used[0] += fp
                 peak[0] = max(peak[0], used[0])
-                active[r.rid] = dict(req=r, inst=inst, k=0, fp=fp, eligible=r.arrival)
-                results[r.rid].admitted_at = now()
-                heapq.heappush(ready, (r.arrival, r.rid))
+                t_adm = now()
+                active[r.rid] = dict(req=r, inst=inst, k=0, fp=fp, eligible=t_adm)
+                results[r.rid].admitted_at = t_adm
+                results[r.rid].queue_wait = max(0.0, t_adm - r.arrival)
+                heapq.heappush(ready, (t_adm, r.rid))
             lock.notify_all()
 
         def worker():
@@ -149,7 +155,8 @@ class Service:
                 with lock:
                     slot["k"] += 1
                     if slot["k"] >= len(req.loads) or st["code"] != fracture.FRACTURE_OK:
-                        if self.keep_state:
+                        keep = self.keep_state
+                        if keep is True or (keep and rid in keep):
                             res.state = inst.state()
                         inst.close()
                         del slot["inst"]
@@ -178,6 +185,7 @@ class Service:
         wall = now()
         lat = np.array([x for r in results.values() for x in r.latencies])
         steps = int(lat.size)
+        waits = np.array([r.queue_wait for r in results.values() if r.rid not in rejected])
         summary = {
             "peak_used_bytes": peak[0],
             "instances": n_total - len(rejected),
@@ -188,6 +196,8 @@ class Service:
             "instances_per_s": (n_total - len(rejected)) / wall if wall > 0 else 0.0,
             "p50_ms": float(np.percentile(lat, 50) * 1e3) if steps else None,
             "p99_ms": float(np.percentile(lat, 99) * 1e3) if steps else None,
+            "queue_wait_p50_s": float(np.percentile(waits, 50)) if waits.size else None,
+            "queue_wait_p99_s": float(np.percentile(waits, 99)) if waits.size else None,
             "failed_steps": int(sum(c != 0 for r in results.values() for c in r.codes)),
         }
         return summary, results
