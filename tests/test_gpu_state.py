@@ -92,3 +92,55 @@ def test_nonfinite_damage_rolls_back():
     u, al, ap = s.state()
     assert np.all(np.isfinite(u)) and np.all(np.isfinite(al)) and np.all(al >= ap)
     s.close()
+
+
+def test_idle_sweep_tightens_and_converges():
+    """Sub-solve tolerances looser than the stop test (PCG and damage solve to
+    1e-3, stop at ||Phi||_2 < 1e-9): a sweep whose solves stop at once leaves
+    the state unchanged, after which the step's sub-solves are tightened
+    (instead of the idle sweep repeating to max_am) and every step reaches
+    the oracle's converged state."""
+    _torch()
+    from oracle import am, problems
+    n = 32
+    p, notch, loads, _ = workloads.config2("AT1", 1.0, seed=0, n=n)
+    params = fracture.make_params(**p, newton=0, am_stop=fracture.FRACTURE_STOP_PHI, final_tol=1e-9,
+                                  pcg_rtol=1e-3, vi_tol=1e-3, max_am=3000)
+    s = fracture.Fracture(params, notch, device="cuda:0")
+    P = problems.tension_2d(n, n, p["lx"], p["ly"], **workloads.oracle_kwargs(p))
+    st = am.initial_state(P, notch.astype(bool))
+    for t in loads[:11]:
+        s.set_load(t)
+        r = s.solve_step()
+        am.solve_load_step(P, st, t, am_tol=1e-10, max_am=3000)
+        u, a, _ = s.state()
+        eu = np.linalg.norm(u - st.u) / np.linalg.norm(st.u)
+        ea = np.linalg.norm(a - st.alpha) / max(np.linalg.norm(st.alpha), 1e-300)
+        print(f"  t={t:.1f} sweeps={r['sweeps']} pcg={r['pcg_iters']} phi={r['phi_l2']:.1e} "
+              f"rel_u={eu:.1e} rel_a={ea:.1e}", flush=True)
+        assert r["converged"] and r["phi_l2"] <= 1e-9 and r["sweeps"] < 3000
+        assert eu < 1e-6 and ea < 1e-6
+    s.close()
+
+
+def test_failed_step_names_its_stage():
+    """stats.stopped_in: the elastic PCG's iteration limit and the sweep limit
+    are told apart (and the state is rolled back either way)."""
+    _torch()
+    n = 32
+    p, notch, loads, _ = workloads.config2("AT1", 1.0, seed=0, n=n)
+    s = fracture.Fracture(fracture.make_params(**p, max_pcg=1, pcg_rtol=1e-13), notch,
+                          device="cuda:0")
+    s.set_load(loads[0])
+    r = s.solve_step(raise_on_error=False)
+    assert r["code"] == fracture.FRACTURE_ENOTCONV and r["stopped_in"] == fracture.FRACTURE_STAGE_PCG
+    s.close()
+    s = fracture.Fracture(fracture.make_params(**p, max_am=1, am_tol=1e-12), notch, device="cuda:0")
+    entry = s.state()
+    s.set_load(loads[11])
+    r = s.solve_step(raise_on_error=False)
+    assert r["code"] == fracture.FRACTURE_ENOTCONV
+    assert r["stopped_in"] == fracture.FRACTURE_STAGE_SWEEPS
+    for va, vb in zip(entry[1:], s.state()[1:]):
+        assert np.array_equal(_bits(va), _bits(vb))
+    s.close()
