@@ -236,7 +236,7 @@ typedef struct {
 #define FRACTURE_STAGE_PCG         1  /* elastic PCG: max_pcg or non-finite      */
 #define FRACTURE_STAGE_VI          2  /* damage VI: max_vi active-set iterations */
 #define FRACTURE_STAGE_VI_SEARCH   3  /* damage VI: no acceptable line-search step */
-#define FRACTURE_STAGE_NEWTON      4  /* Newton phase (MINRES or its line search) */
+#define FRACTURE_STAGE_NEWTON      4  /* Newton phase: non-finite MINRES or residual */
 #define FRACTURE_STAGE_SWEEPS      5  /* max_am sweeps without the stop test     */
 #define FRACTURE_STAGE_OTHER       6  /* device error, non-finite update         */
 

@@ -28,6 +28,17 @@ def test_library_exports_every_declared_symbol():
     assert sorted(fracture.EXPORTS) == declared
 
 
+def test_header_constants_match_the_binding():
+    """Every FRACTURE_* integer constant of the header has the same value in
+    the Python binding (error codes, loads, modes, operator and kernel ids,
+    failed-step stages)."""
+    src = open(os.path.join(ROOT, "include", "fracture.h")).read()
+    defs = dict((k, int(v)) for k, v in re.findall(r"#define\s+(FRACTURE_[A-Z0-9_]+)\s+(-?\d+)\b", src))
+    assert len(defs) >= 30
+    for k, v in defs.items():
+        assert getattr(fracture, k) == v, k
+
+
 def test_params_struct_matches_defaults():
     p = fracture.fracture_default_params(64, 32)
     assert (p.dim, p.nx, p.ny) == (2, 64, 32)
