@@ -194,6 +194,7 @@ void launch_dot_f(hipStream_t st, int64_t n, const float* a, const float* b, Red
 void launch_to_float(hipStream_t st, int64_t n, const double* x, float* y, double scale);
 void launch_add_scaled_f(hipStream_t st, int64_t n, double* x, const float* e, double scale);
 void launch_copy(hipStream_t st, int64_t n, const double* x, double* y);
+void launch_scalars_out(hipStream_t st, const double* S, double* host);
 void launch_minres_init(hipStream_t st, double* S);
 void launch_minres_a(hipStream_t st, double* S);
 void launch_minres_b(hipStream_t st, double* S, double* host);

@@ -482,9 +482,12 @@ Red red(fracture* h, int cslot, int sslot, int post = P_STORE) {
   return Red{h->part + (size_t)cslot * h->part_n, h->S, sslot, post};
 }
 
+// The device scalars into h->hS (pinned), then wait for the stream.  A small
+// kernel writes them to host memory itself, which costs less than a runtime
+// device-to-host copy on every convergence test.
 int read_scalars(fracture* h) {
   if (h->graph_error) return FRACTURE_EDEVICE;
-  HIPCHK(hipMemcpyAsync(h->hS, h->S, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, h->st));
+  launch_scalars_out(h->st, h->S, h->hS);
   HIPCHK(hipStreamSynchronize(h->st));
   return FRACTURE_OK;
 }

@@ -249,6 +249,17 @@ __global__ __launch_bounds__(VB) void k_copy(int64_t n, const double* __restrict
   GRID_STRIDE(k, n) y[k] = x[k];
 }
 
+// The scalar array into pinned host memory, written by the kernel itself (one
+// small launch instead of a runtime copy).
+__global__ __launch_bounds__(WAVE) void k_scalars_out(const double* __restrict__ S,
+                                                      double* __restrict__ out) {
+  for (int q = threadIdx.x; q < S_COUNT; q += WAVE) out[q] = S[q];
+}
+
+void launch_scalars_out(hipStream_t st, const double* S, double* host) {
+  hipLaunchKernelGGL(k_scalars_out, dim3(1), dim3(WAVE), 0, st, S, host);
+}
+
 void launch_copy(hipStream_t st, int64_t n, const double* x, double* y) {
   hipLaunchKernelGGL(k_copy, dim3(vgrid(n)), dim3(VB), 0, st, n, x, y);
 }
