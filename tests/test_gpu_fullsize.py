@@ -83,6 +83,69 @@ def test_full_size_operator_rows():
     s.close()
 
 
+def _patch3(i, j, k, nx, ny, nz, hx, hy, hz):
+    """Hexahedra around node (i, j, k) of the structured Kuhn mesh, clipped
+    to the domain: (X, T, global ids, local id)."""
+    i0, i1 = max(i - 1, 0), min(i + 1, nx)
+    j0, j1 = max(j - 1, 0), min(j + 1, ny)
+    k0, k1 = max(k - 1, 0), min(k + 1, nz)
+    X, T = mesh.structured_mesh_3d(i1 - i0, j1 - j0, k1 - k0, (i1 - i0) * hx, (j1 - j0) * hy,
+                                   (k1 - k0) * hz)
+    X = X + np.array([i0 * hx, j0 * hy, k0 * hz])
+    kk, jj, ii = np.meshgrid(np.arange(k0, k1 + 1), np.arange(j0, j1 + 1), np.arange(i0, i1 + 1),
+                             indexing="ij")
+    gid = (ii + (nx + 1) * (jj + (ny + 1) * kk)).ravel()
+    loc = (i - i0) + (i1 - i0 + 1) * ((j - j0) + (j1 - j0 + 1) * (k - k0))
+    return X, T, gid, loc
+
+
+def test_full_size_3d_operator_rows():
+    """The 3D operator on the 128 x 128 x 32 slab (config 3) as the bench runs
+    it: the element-centric kernels on the finest level (15 x 15 x 4-node
+    tiles).  Rows of K(alpha) u at sampled nodes (corners, edges, tile seams
+    in x, y and z, random nodes) against the oracle's assembly of each node's
+    hexahedron patch (eq. (elasticity)), and the two kernel families'
+    results against each other on the whole grid."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    p, _ = workloads.config3()
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    hx, hy, hz = p["lx"] / nx, p["ly"] / ny, p["lz"] / nz
+    rng = np.random.default_rng(33)
+    out = {}
+    for kern, m in (("elem", 1 << 18), ("node", 1 << 30)):
+        s = fracture.Fracture(fracture.make_params(**p, elem3d_min_nodes=m), None, device="cuda:0")
+        N = s.N
+        if kern == "elem":
+            u = rng.standard_normal(3 * N) * 1e-3
+            alpha = rng.uniform(0, 1, N)
+        s.set_state(u=u, alpha=alpha, alpha_prev=np.zeros(N))
+        out[kern] = s.apply(fracture.FRACTURE_OP_ELASTICITY, u)
+        s.close()
+    y = out["elem"]
+    assert np.max(np.abs(y - out["node"])) <= 1e-12 * np.max(np.abs(y))
+    pts = {(0, 0, 0), (nx, ny, nz), (0, ny, 0), (nx, 0, nz), (14, 15, 3), (15, 14, 4), (16, 30, 7),
+           (29, 31, 8), (nx, 60, 16), (64, ny, 0)}
+    while len(pts) < 60:
+        pts.add((int(rng.integers(0, nx + 1)), int(rng.integers(0, ny + 1)), int(rng.integers(0, nz + 1))))
+    worst = 0.0
+    for (i, j, k) in sorted(pts):
+        X, T, gid, loc = _patch3(i, j, k, nx, ny, nz, hx, hy, hz)
+        M = fem.Model(X, T, E=p["E"], nu=p["nu"], Gc=p["Gc"], ell=p["ell"], k_ell=p["k_ell"],
+                      model=p["model"])
+        up = np.concatenate([u[gid], u[N + gid], u[2 * N + gid]])
+        Kp = M.K(alpha[gid])
+        row = Kp @ up
+        mloc = len(gid)
+        g = i + (nx + 1) * (j + (ny + 1) * k)
+        want = np.array([row[loc], row[mloc + loc], row[2 * mloc + loc]])
+        got = np.array([y[g], y[N + g], y[2 * N + g]])
+        scale = np.max(np.abs(Kp.toarray()[[loc, mloc + loc, 2 * mloc + loc]])) * np.max(np.abs(up))
+        worst = max(worst, np.max(np.abs(got - want)) / scale)
+    assert worst < 1e-12, worst
+
+
 def test_full_size_residual_rows():
     """The elastic PCG's residual kernel at 2048^2 (the column-tiled form the
     finest level runs): -K(alpha) x on free rows and zero on Dirichlet rows,
