@@ -82,13 +82,8 @@ def serve(args):
     Poisson stream, admitted under a device memory budget, run concurrently."""
     import numpy as np
     from paper_1511_08463_amd import serving, workloads
-    extra = {}
-    if args.serve_solver == "oramn":
-        # ORAM-N with the 2048^2 benchmark's inexact sweeps (mixed precision kept)
-        extra = dict(workloads.CONFIG2_SOLVER, max_am=2000)
-    reqs = [serving.Request(r["rid"], dict(r["params"], **extra), r["notch"], r["loads"],
-                            r["arrival"])
-            for r in workloads.config5(n_instances=args.instances)]
+    reqs = [serving.Request(r["rid"], r["params"], r["notch"], r["loads"], r["arrival"])
+            for r in workloads.config5(n_instances=args.instances, solver=args.serve_solver)]
     budget = int(args.budget_gb * 1e9)
     log(f"[serve] {len(reqs)} requests, budget {args.budget_gb} GB, {args.workers} workers, "
         f"GPU_MAX_HW_QUEUES={os.environ.get('GPU_MAX_HW_QUEUES', 'default')}")
@@ -476,9 +471,9 @@ def parse_args(argv=None):
     ap.add_argument("--kernels-only", action="store_true",
                     help="time the hot kernels only (no solve), e.g. under hardware counters")
     ap.add_argument("--instances", type=int, default=256, help="served stream: requests run")
-    ap.add_argument("--serve-solver", choices=("am", "oramn"), default="am",
-                    help="served stream: alternate minimisation (the recipe's) or ORAM-N with the "
-                         "benchmark's inexact sweeps")
+    ap.add_argument("--serve-solver", choices=("am", "oramn"), default="oramn",
+                    help="served stream: ORAM-N with the benchmark's inexact sweeps (default) or "
+                         "alternate minimisation")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="served stream: hardware queues of the process (GPU_MAX_HW_QUEUES, at most "
                          "32), so that the instances' streams do not share four queues")

@@ -130,8 +130,17 @@ def oracle_kwargs(p):
 
 
 def config5(n_instances=256, seed=1, sizes=(64, 128, 256, 512, 1024), rate=50.0,
-            max_am=400, load_scale=1.0):
-    """Requests of the served stream: (rid, params, notch, loads, arrival)."""
+            max_am=None, load_scale=1.0, solver="oramn"):
+    """Requests of the served stream: (rid, params, notch, loads, arrival).
+    solver "oramn": ORAM-N with the 2048^2 benchmark's inexact sweeps
+    (CONFIG2_SOLVER; up to 2000 sweeps per step); "am": alternate
+    minimisation to ||dalpha||_inf < 1e-5 (up to 400 sweeps per step)."""
+    if solver == "oramn":
+        extra = dict(CONFIG2_SOLVER, max_am=2000 if max_am is None else max_am)
+    elif solver == "am":
+        extra = dict(max_am=400 if max_am is None else max_am)
+    else:
+        raise ValueError(solver)
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
@@ -144,7 +153,7 @@ def config5(n_instances=256, seed=1, sizes=(64, 128, 256, 512, 1024), rate=50.0,
         y0 = round(rng.uniform(0.1, 0.4) * n) * h
         a = round(rng.uniform(0.1, 0.4) * n) * h
         t += float(rng.exponential(1.0 / rate))
-        p = tension(n, ell, "AT1", 1.0, lx=L, ly=L, precision=1, max_am=max_am)
+        p = tension(n, ell, "AT1", 1.0, lx=L, ly=L, precision=1, **extra)
         notch = notch_mask_2d(n, n, y0, a, L, L)
         loads = [k * (load_scale * np.sqrt(L)) / steps for k in range(1, steps + 1)]
         out.append(dict(rid=rid, params=p, notch=notch, loads=loads, arrival=t))
