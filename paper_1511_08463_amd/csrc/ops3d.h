@@ -181,44 +181,8 @@ __device__ __forceinline__ void node_force3d(const Grid& g, const Mat& m, const 
 static __device__ __constant__ int c_kuhn_dir[7][3] = {{1,0,0},{0,1,0},{0,0,1},{1,1,0},{1,0,1},{0,1,1},{1,1,1}};
 
 // ---------------------------------------------------------------------------
-// per-node multigrid updates (node (i, j, k) of level g)
+// per-node transfers between levels (node of the coarse or the fine level)
 // ---------------------------------------------------------------------------
-
-template <bool FA, class T>
-__device__ __forceinline__ void smooth_node3d(const Grid& g, const Mat& m, const T* __restrict__ coef,
-                                              T kell, const T* __restrict__ x_in,
-                                              T* __restrict__ x_out, const T* __restrict__ b,
-                                              const T* __restrict__ d_in, T* __restrict__ d_out,
-                                              T cd, T cr, int i, int j, int k) {
-  const int N = g.N, n = i + (g.nx + 1) * (j + (g.ny + 1) * k);
-  T f[3], d[3];
-  if (x_in) node_force3d<FA, true, true, false>(g, m, coef, kell, x_in, i, j, k, f, d);
-  else node_force3d<FA, false, true, false>(g, m, coef, kell, x_in, i, j, k, f, d);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const int q = n + c * N;
-    T dd = cr * (b[q] - f[c]) / d[c];
-    if (d_in) dd += cd * d_in[q];
-    T xo = (x_in ? x_in[q] : T(0)) + dd;
-    if (fixed3(g, c, i, j, k)) { xo = T(0); dd = T(0); }
-    x_out[q] = xo;
-    if (d_out) d_out[q] = dd;
-  }
-}
-
-template <bool FA, class T>
-__device__ __forceinline__ void resid_node3d(const Grid& g, const Mat& m, const T* __restrict__ coef,
-                                             T kell, const T* __restrict__ x, T* __restrict__ r,
-                                             const T* __restrict__ b, int i, int j, int k) {
-  const int N = g.N, n = i + (g.nx + 1) * (j + (g.ny + 1) * k);
-  T f[3], d[3];
-  node_force3d<FA, true, false, false>(g, m, coef, kell, x, i, j, k, f, d);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const int q = n + c * N;
-    r[q] = fixed3(g, c, i, j, k) ? T(0) : b[q] - f[c];
-  }
-}
 
 template <class T>
 __device__ __forceinline__ void restrict_node3d(const Grid& gf, const Grid& gc,
