@@ -93,14 +93,14 @@ def config2(model="AT1", omega=1.0, seed=0, n=2048):
 # phase's stop test fixes the accuracy of the converged state: the elastic
 # PCG stops at 0.95 of its warm-start residual (or 1e-8 of the load), the
 # damage active-set iteration at 0.3 of its starting max |Phi|, and each of
-# its reduced CG solves at 0.3 relative.  MINRES forcing by Eisenstat-Walker,
+# its reduced CG solves at 0.1 relative.  MINRES forcing by Eisenstat-Walker,
 # one V-cycle per action of A^-1, the block-diagonal Newton preconditioner.
 # The stop tolerance is tighter than the 1e-7 the paper's experiments use:
 # once the specimen is cut, the translation of the upper piece is held only by
 # the k_ell stiffness of the crack band, so a residual of 1e-7 leaves that soft
 # mode, and u, uncertain beyond 1e-6 relative.  The parity test of the
 # benchmarked path runs with exactly these settings.
-CONFIG2_SOLVER = dict(am_tol=1e-5, pcg_rtol=1e-8, vi_cg_rtol=0.3, max_am=30000, newton=1,
+CONFIG2_SOLVER = dict(am_tol=1e-5, pcg_rtol=1e-8, vi_cg_rtol=0.1, max_am=30000, newton=1,
                       switch_tol=1e-3, final_tol=1e-9, minres_rtol=1e-6, newton_vcycles=1,
                       newton_forcing=0.1, newton_forcing_mode=1, pcg_reduction=0.95,
                       vi_reduction=0.3, cheb_degree=2, newton_precond=1)
