@@ -223,7 +223,7 @@ def time_kernels(solver, reps):
 # the prolongation), from rocprofv3 FETCH_SIZE and WRITE_SIZE of the headline leg,
 # each scaled by the factor that maps the same counter on the plain copy
 # kernel to its known bytes.  Valid only for the sources they were taken on
-# (sha256 over the files below: the kernels and the driver that sets each
+# (sha256 over the files below: the kernels and the host code that sets each
 # launch's operands).
 TRAFFIC = {
     # profiles/hbm_traffic_2048_at1.md: mean over the 570 launches of the
@@ -493,8 +493,8 @@ NSTEPS = 20   # the load path of the workload: t = 0.1 k, k = 1..20
 def plan(args):
     """Validated run plan, or (None, message) for an invalid request."""
     if args.gpus != 1:
-        return None, ("this build runs on one GPU only; --gpus must be 1 "
-                      "(the multi-GPU decomposition is a design, not built)")
+        return None, ("the benchmark runs on one GPU only; --gpus must be 1 "
+                      "(the multi-GPU decomposition is designed, not implemented)")
     if not 1 <= args.steps <= NSTEPS:
         return None, f"--steps must be in 1..{NSTEPS} (the load path has {NSTEPS} steps)"
     if args.warmup < 0:
