@@ -724,6 +724,7 @@ def main():
         "step_sweeps": res["step_sweeps"],
         "p50_step_ms": res["p50_step_ms"],
         "p99_step_ms": res["p99_step_ms"],
+        "final_energy": {"elastic": energy64[0], "surface": energy64[1]},
         "roofline": roofline(res["live"], dom, traffic, rl),
     }
     if args.omega_sweep and args.precision == "fp64":
@@ -732,11 +733,17 @@ def main():
         for om in (1.4, 1.8):
             if om == args.omega:
                 continue
-            s_om, r_om, _, _ = leg(args.precision, omega=om)
+            s_om, r_om, (st_om, _), e_om = leg(args.precision, omega=om)
             s_om.close()
-            out["omega_sweep"][f"{om:g}"] = {k: r_om[k] for k in ("value", "ms_per_step", "sweeps",
-                                                                  "pcg_iters", "newton_iters",
-                                                                  "minres_iters", "step_sweeps")}
+            o_om = {k: r_om[k] for k in ("value", "ms_per_step", "sweeps", "pcg_iters",
+                                         "newton_iters", "minres_iters", "step_sweeps")}
+            # the converged end state against omega's: the same crack?
+            a1, a0 = st_om[1], state64[1]
+            o_om["final_energy"] = {"elastic": e_om[0], "surface": e_om[1]}
+            o_om["rel_surface_energy_vs_omega"] = abs(e_om[1] - energy64[1]) / abs(energy64[1])
+            o_om["iou_crack_vs_omega"] = float(np.sum((a1 > 0.5) & (a0 > 0.5)) /
+                                               max(np.sum((a1 > 0.5) | (a0 > 0.5)), 1))
+            out["omega_sweep"][f"{om:g}"] = o_om
     if not args.no_mixed and args.precision == "fp64":
         if res["seconds"] > args.mixed_budget:
             out["mixed"] = {"skipped": f"the FP64 leg took {res['seconds']:.0f} s > --mixed-budget "

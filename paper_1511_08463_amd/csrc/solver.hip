@@ -35,6 +35,11 @@ namespace {
 
 constexpr int MAXLEV = 16;
 constexpr int DENSE_MAX = 1024;   // largest coarsest-level system inverted densely
+// stalled ORAM sweeps (solve_step_impl): ||dalpha||_inf below STALL_DALPHA and
+// no cut of ||Phi||_2 by the factor STALL_CUT within STALL_SWEEPS sweeps
+constexpr double STALL_DALPHA = 1e-6;
+constexpr double STALL_CUT = 0.9;
+constexpr int STALL_SWEEPS = 50;
 // The coarsest system is re-assembled and re-inverted once its coefficients
 // drift by more than this relative amount from those of the current inverse.
 constexpr double COARSE_DRIFT = 0.02;
@@ -1410,6 +1415,8 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
   int rc = FRACTURE_OK;
   double ms_pcg = 0, ms_vi = 0, ms_newton = 0;
   double threshold = h->p.switch_tol;
+  double best_phi = INFINITY;   // smallest ||Phi||_2 of the step's sweeps so far
+  int best_sweep = 0;           // the sweep that last cut it by STALL_CUT
   // omega: fixed, or (omega_auto) 1 until the convergence factor rho of the
   // plain alternate minimisation is measured, then Young's optimum
   // 2 / (1 + sqrt(1 - rho)) of SOR theory, capped at p.omega
@@ -1479,6 +1486,15 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
       // final tolerance from here on
       if (it == 0 && loc.vi_iters == vi_before && loc.dalpha_inf == 0.0)
         h->sweep_cap = 0.1 * h->p.final_tol;
+      // the same when sweeps still move alpha, but only by a trace, and have
+      // not cut ||Phi|| for STALL_SWEEPS sweeps: the sub-solves' errors (which
+      // over-relaxation amplifies) hold ||Phi|| above the stop test
+      if (nphi < STALL_CUT * best_phi) {
+        best_phi = nphi;
+        best_sweep = sweep;
+      } else if (loc.dalpha_inf < STALL_DALPHA && sweep - best_sweep >= STALL_SWEEPS) {
+        h->sweep_cap = 0.1 * h->p.final_tol;
+      }
       if (h->p.newton && nphi < threshold) {
         HIPCHK(hipEventRecord(h->ev[1], st));
         bool conv = false;
