@@ -396,6 +396,50 @@ def deflation(args):
     return out
 
 
+def shard(args):
+    """One GPU's share of a slab decomposition of the --n x --n square over R
+    GPUs: the --n x --n/R slab with the same h, ell = 4h and tension strain,
+    alpha = 0.  One ORAM load step from u = 0 (a full elastic PCG solve to
+    --pcg-rtol, then the damage step) per R; reports the PCG's time per
+    iteration and the back-to-back finest-level Chebyshev step on the slab.
+    Halo exchanges and all-reduces are not part of it (one GPU)."""
+    import torch
+    from paper_1511_08463_amd import fracture, workloads
+    n = args.n
+    rows = []
+    for r in (1, 2, 4, 8):
+        if n % r or (n // r) % 16:
+            continue
+        ny = n // r
+        p = dict(workloads.tension(n, 4.0 / n, args.model), ny=ny, ly=ny / n)
+        params = fracture.make_params(**p, newton=0, am_tol=args.am_tol, pcg_rtol=args.pcg_rtol,
+                                      vi_cg_rtol=args.vi_cg_rtol, max_am=args.max_am,
+                                      cheb_degree=args.cheb_degree,
+                                      use_graphs=0 if args.no_graphs else 1)
+        solver = fracture.Fracture(params, None, device="cuda:0")
+        solver.set_load(0.1 * ny / n)              # the headline's first strain, u_y = 0.1 at y = 1
+        torch.cuda.synchronize()
+        st = solver.solve_step()
+        torch.cuda.synchronize()
+        ms, nbytes = fracture.fracture_time_kernel(solver.h, fracture.FRACTURE_KERNEL_SMOOTH,
+                                                   args.kernel_reps)
+        solver.close()
+        dofs = 2 * (n + 1) * (ny + 1)
+        it_ms = st["ms_pcg"] / max(st["pcg_iters"], 1)
+        rows.append({"gpus": r, "slab": f"{n}x{ny}", "dofs": dofs, "pcg_iters": st["pcg_iters"],
+                     "pcg_ms_per_iter": round(it_ms, 4),
+                     "dof_iter_per_s": round(dofs / (it_ms * 1e-3), 1),
+                     "smooth_us": round(ms * 1e3, 2),
+                     "smooth_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)})
+        log(f"[shard] {n}x{ny} ({r} GPUs): {st['pcg_iters']} PCG iterations, "
+            f"{it_ms:.3f} ms each ({rows[-1]['dof_iter_per_s'] / 1e9:.2f} G DOF-it/s), "
+            f"Chebyshev step {ms * 1e3:.1f} us ({rows[-1]['smooth_gbs']:.0f} GB/s)")
+    return {"workload": (f"{n} x {n}/R slabs of the {n}^2 square (h = 1/{n}, ell = 4h, "
+                         f"{args.model}, alpha = 0), one ORAM load step from u = 0, PCG rtol "
+                         f"{args.pcg_rtol:g}; no halo exchange or all-reduce"),
+            "slabs": rows}
+
+
 def parse_args(argv=None):
     from paper_1511_08463_amd.workloads import CONFIG2_SOLVER as S
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -468,6 +512,8 @@ def parse_args(argv=None):
     ap.add_argument("--tshock-max-am", type=int, default=20000, help="sweep limit per thermal shock step")
     ap.add_argument("--deflation", action="store_true",
                     help="run only the deflated vs plain elastic CG comparison")
+    ap.add_argument("--shard", action="store_true",
+                    help="run only the per-GPU slabs of a 1/2/4/8-GPU row decomposition")
     ap.add_argument("--kernels-only", action="store_true",
                     help="time the hot kernels only (no solve), e.g. under hardware counters")
     ap.add_argument("--instances", type=int, default=256, help="served stream: requests run")
@@ -550,6 +596,9 @@ def main():
         return
     if args.deflation:
         print(json.dumps({"deflation": deflation(args)}), flush=True)
+        return
+    if args.shard:
+        print(json.dumps({"shard": shard(args)}), flush=True)
         return
     p, notch, loads, (y0, a) = workloads.config2(args.model, args.omega, seed=0, n=args.n)
 
