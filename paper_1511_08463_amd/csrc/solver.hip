@@ -156,6 +156,11 @@ struct fracture {
   // sweeps (INFINITY: none); set once a sweep leaves the state unchanged
   double sweep_cap = INFINITY;
   bool phi_reused = false;   // the last residual_launch took vi_phi2
+  // r holds b - K(alpha) u (free rows; 0 on Dirichlet rows) at the current
+  // u, alpha and load, and r_rr its squared norm: left by the last sweep's
+  // residual for the next sweep's PCG, which then starts from it
+  bool r_valid = false;
+  double r_rr = 0.0;
   fracture_monitor_fn monitor = nullptr;
   void* monitor_user = nullptr;
   bool coef_valid = false;
@@ -802,11 +807,16 @@ int pcg(fracture* h, double tol, int* iters) {
   double* x = pcg_iterate(h);
   if (x != h->u) HIPCHK(hipMemcpyAsync(x, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
   const Grid gl = load_grid(h);
-  launch_resid2d(st, gl, h->mat, true, h->alpha, h->p.k_ell, x, h->r, nullptr, true,
-                 red(h, 0, S_RR));
-  int rc = read_scalars(h);
-  if (rc) return rc;
-  double rr = h->hS[S_RR];
+  int rc = FRACTURE_OK;
+  double rr = h->r_rr;
+  if (!h->r_valid) {
+    launch_resid2d(st, gl, h->mat, true, h->alpha, h->p.k_ell, x, h->r, nullptr, true,
+                   red(h, 0, S_RR));
+    rc = read_scalars(h);
+    if (rc) return rc;
+    rr = h->hS[S_RR];
+  }
+  h->r_valid = false;
   if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
   *iters = 0;
   tol = sweep_tol(h, tol, std::sqrt(rr));
@@ -858,6 +868,7 @@ constexpr double MIXED_LOOSE = 0.05;
 constexpr int MIXED_MAX_OUTER = 30;
 
 int pcg_mixed(fracture* h, double tol, int* iters) {
+  h->r_valid = false;   // r is recomputed before every inner solve
   const Grid& g = h->lv[0].g;
   const int64_t n2 = h->n2;
   hipStream_t st = h->st;
@@ -1077,7 +1088,8 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
 // the scalars once the caller has read them (one read for the sweep).
 void residual_launch(fracture* h) {
   const Grid g = load_grid(h);
-  launch_apply2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, h->u, h->q, nullptr, 0, 2,
+  // -E_u on the free rows, kept in r for the next sweep's PCG
+  launch_resid2d(h->st, g, h->mat, true, h->alpha, h->p.k_ell, h->u, h->r, nullptr, true,
                  red(h, 0, S_EU2));
   h->phi_reused = h->omega_cur == 1.0 && h->vi_phi2_valid;
   if (h->phi_reused) return;
@@ -1422,6 +1434,7 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
   // 2 / (1 + sqrt(1 - rho)) of SOR theory, capped at p.omega
   h->omega_cur = h->p.omega_auto ? 1.0 : h->p.omega;
   h->sweep_cap = INFINITY;
+  h->r_valid = false;
   double da_hist[OMEGA_PROBE + 1] = {};
   for (int sweep = 1; sweep <= h->p.max_am; ++sweep) {
     update_coefficients(h);
@@ -1456,6 +1469,8 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
     if (want_phi) residual_launch(h);
     rc = read_scalars(h);
     if (rc) break;
+    h->r_valid = want_phi;
+    h->r_rr = h->hS[S_EU2];
     ms_pcg += elapsed(h->ev[1], h->ev[2]);
     ms_vi += elapsed(h->ev[2], h->ev[3]);
     loc.dalpha_inf = h->hS[S_DAMAX];
@@ -1496,6 +1511,7 @@ int solve_step_impl(fracture* h, fracture_stats* s) {
         h->sweep_cap = 0.1 * h->p.final_tol;
       }
       if (h->p.newton && nphi < threshold) {
+        h->r_valid = false;   // the Newton phase moves u and alpha
         HIPCHK(hipEventRecord(h->ev[1], st));
         bool conv = false;
         rc = newton_phase(h, &loc, &nphi, &conv);
