@@ -838,18 +838,29 @@ int pcg(fracture* h, double tol, int* iters) {
   }
   double* z = vcycle0(h, h->r);
   launch_dot(st, n2, h->r, z, red(h, 1, S_RZ));
-  HIPCHK(hipMemcpyAsync(h->pv, z, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
-  if (m) dfl_correct(h, z, h->pv, -1.0);
+  // the first direction is z itself: it is copied into p only when a second
+  // iteration needs the buffer that the next V-cycle overwrites (most
+  // solves inside the sweeps stop after one)
+  const double* p = z;
+  if (m) {
+    HIPCHK(hipMemcpyAsync(h->pv, z, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    dfl_correct(h, z, h->pv, -1.0);
+    p = h->pv;
+  }
   for (int it = 1; it <= h->p.max_pcg; ++it) {
-    launch_apply2d(st, g, h->mat, true, h->alpha, h->p.k_ell, h->pv, h->q, nullptr, 1, 1,
+    launch_apply2d(st, g, h->mat, true, h->alpha, h->p.k_ell, p, h->q, nullptr, 1, 1,
                    red(h, 2, S_PQ, P_CG_ALPHA));
-    launch_cg_update(st, n2, x, h->r, h->pv, h->q, h->S, red(h, 3, S_RR));
+    launch_cg_update(st, n2, x, h->r, p, h->q, h->S, red(h, 3, S_RR));
     rc = read_scalars(h);
     if (rc) return rc;
     rr = h->hS[S_RR];
     *iters = it;
     if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
     if (std::sqrt(rr) <= tol) return FRACTURE_OK;
+    if (p != h->pv) {
+      HIPCHK(hipMemcpyAsync(h->pv, p, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+      p = h->pv;
+    }
     z = vcycle0(h, h->r);
     launch_dot(st, n2, h->r, z, red(h, 4, S_RZNEW, P_CG_BETA));
     launch_xpby(st, n2, z, h->pv, h->S);
@@ -1016,15 +1027,17 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
     // finishes p.q itself, so an iteration is two kernels and one finishing
     // launch; the CG scalars live on the device and the host tests ||r|| one
     // iteration late (lag_mark / lag_get)
+    // ||r_0||^2 reaches the host with the first lagged read (the second word
+    // of iteration 1's slot), so no read stands between the start and the
+    // first iterations; a zero r_0 makes those iterations leave d = 0
     if (any_inactive) {
-      launch_norm2_box(st, bx, h->vr, red(h, 7, S_TMP2));
+      Red r0r = red(h, 7, S_TMP2);
+      r0r.host = lag_slot(h, 1) + 1;
+      launch_norm2_box(st, bx, h->vr, r0r);
       launch_jacobi_dot(st, bx, h->vr, h->hdinv, h->vz, red(h, 1, S_RZ));
-      rc = read_scalars(h);
-      if (rc) return rc;
     }
-    const double r0 = any_inactive ? std::sqrt(h->hS[S_TMP2]) : 0.0;
-    const double tol = h->p.vi_cg_rtol * r0;
-    if (r0 > 0) {
+    double tol = 0.0;
+    if (any_inactive) {
       double* pb[2] = {h->vp, h->vt1};
       for (int k = 1; k <= h->p.max_vi_cg; ++k) {
         double* pn = pb[k & 1];
@@ -1039,11 +1052,12 @@ int damage_qp(fracture* h, int* vi_iters, int* cg_iters) {
         ++*cg_iters;
         lag_mark(h, k);
         if (k > 1) {
-          double rr = 0;
-          rc = lag_get(h, k - 1, 1, &rr);
+          double v[2] = {0.0, 0.0};
+          rc = lag_get(h, k - 1, k == 2 ? 2 : 1, v);
           if (rc) return rc;
-          if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
-          if (std::sqrt(rr) <= tol) break;
+          if (k == 2) tol = h->p.vi_cg_rtol * std::sqrt(v[1]);
+          if (!std::isfinite(v[0]) || !std::isfinite(tol)) return FRACTURE_ENONFINITE;
+          if (std::sqrt(v[0]) <= tol) break;
         }
       }
       // an inexact step is still tried: the line search decides
