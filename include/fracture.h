@@ -283,7 +283,8 @@ int fracture_solve_steps(fracture_t* hs, int n, fracture_stats* out, int* codes)
 
 /* Progress monitor: when set, fn(user, sweep, dalpha_inf, phi_l2) is called
    on the host after every ORAM sweep and Newton iteration of solve_step
-   (phi_l2 is -1 when not computed).  fn = NULL removes it. */
+   (phi_l2 is -1 when not computed).  fn = NULL removes it.  fn must not
+   call into the same handle: the solve keeps state between sweeps. */
 typedef void (*fracture_monitor_fn)(void* user, int sweep, double dalpha_inf, double phi_l2);
 int fracture_set_monitor(fracture_t h, fracture_monitor_fn fn, void* user);
 
