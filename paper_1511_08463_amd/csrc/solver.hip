@@ -879,7 +879,6 @@ constexpr double MIXED_LOOSE = 0.05;
 constexpr int MIXED_MAX_OUTER = 30;
 
 int pcg_mixed(fracture* h, double tol, int* iters) {
-  h->r_valid = false;   // r is recomputed before every inner solve
   const Grid& g = h->lv[0].g;
   const int64_t n2 = h->n2;
   hipStream_t st = h->st;
@@ -887,11 +886,17 @@ int pcg_mixed(fracture* h, double tol, int* iters) {
   double* x = pcg_iterate(h);
   if (x != h->u) HIPCHK(hipMemcpyAsync(x, h->u, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
   for (int outer = 0;; ++outer) {
-    launch_resid2d<double>(st, load_grid(h), h->mat, true, h->alpha, h->p.k_ell, x, h->r, nullptr, true,
-                           red(h, 0, S_RR));
-    int rc = read_scalars(h);
-    if (rc) return rc;
-    const double rr = h->hS[S_RR];
+    // the first residual may be the one the last sweep left in r
+    int rc = FRACTURE_OK;
+    double rr = h->r_rr;
+    if (outer > 0 || !h->r_valid) {
+      launch_resid2d<double>(st, load_grid(h), h->mat, true, h->alpha, h->p.k_ell, x, h->r, nullptr,
+                             true, red(h, 0, S_RR));
+      rc = read_scalars(h);
+      if (rc) return rc;
+      rr = h->hS[S_RR];
+    }
+    h->r_valid = false;
     if (!std::isfinite(rr)) return FRACTURE_ENONFINITE;
     const double rn = std::sqrt(rr);
     if (outer == 0) tol = sweep_tol(h, tol, rn);
@@ -905,18 +910,24 @@ int pcg_mixed(fracture* h, double tol, int* iters) {
     // the inner solve almost as is, a tight one with a factor 2 to spare
     const double want = tol / rn;
     const double tin = std::fmax(MIXED_INNER_RTOL, (want >= MIXED_LOOSE ? 0.9 : 0.5) * want);
+    // the first direction is z itself, copied into p only when a second
+    // iteration needs the buffer that the next V-cycle overwrites
     float* z = vcycle0f(h, h->fr32);
-    HIPCHK(hipMemcpyAsync(h->fp32, z, n2 * sizeof(float), hipMemcpyDeviceToDevice, st));
+    float* p = z;
     for (int it = 0;; ++it) {
       if (it > 0) {
+        if (p != h->fp32) {
+          HIPCHK(hipMemcpyAsync(h->fp32, p, n2 * sizeof(float), hipMemcpyDeviceToDevice, st));
+          p = h->fp32;
+        }
         z = vcycle0f(h, h->fr32);
         launch_dot_f(st, n2, z, h->fq32, red(h, 1, S_TMP0, P_FCG_BETA));
         launch_xpby_f(st, n2, z, h->fp32, h->S);
       }
-      launch_apply2d<float>(st, g, h->mat, true, h->alpha32, h->p.k_ell, h->fp32, h->fq32, nullptr,
+      launch_apply2d<float>(st, g, h->mat, true, h->alpha32, h->p.k_ell, p, h->fq32, nullptr,
                             1, 1, red(h, 2, S_PQ));
-      launch_dot_f(st, n2, h->fp32, h->fr32, red(h, 4, S_TMP1, P_FCG_ALPHA));
-      launch_cg_update_f(st, n2, h->fe32, h->fr32, h->fp32, h->fq32, h->S, red(h, 3, S_RR));
+      launch_dot_f(st, n2, p, h->fr32, red(h, 4, S_TMP1, P_FCG_ALPHA));
+      launch_cg_update_f(st, n2, h->fe32, h->fr32, p, h->fq32, h->S, red(h, 3, S_RR));
       rc = read_scalars(h);
       if (rc) return rc;
       ++*iters;
