@@ -129,7 +129,7 @@ def thermal(args):
         params = fracture.make_params(**p, **S, precision=prec)
     else:
         params = fracture.make_params(**p, am_tol=args.am_tol, pcg_rtol=args.pcg_rtol, max_am=2000,
-                                      newton=0, precision=prec)
+                                      vi_cg_rtol=args.vi_cg_rtol, newton=0, precision=prec)
     solver = fracture.Fracture(params, None, device="cuda:0")
     log(f"[thermal] 128x128x32 Kuhn, {args.precision}, DT_c={workloads.thermal_dtc(p):.3f}")
     stats = []
