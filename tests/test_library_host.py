@@ -54,8 +54,11 @@ def test_workspace_size_and_validation():
     assert ws < 200 * N * 8
     big = fracture.make_params(**workloads.tension(2048, 4 / 2048))
     assert fracture.fracture_workspace_bytes(big) > 16 * ws
+    # out-of-range parameters and empty or inverted meshes are refused
     for bad in (dict(omega=0.0), dict(omega=2.0), dict(ell=0.0), dict(nu=0.5),
-                dict(model=3), dict(nx=5), dict(cheb_degree=0)):
+                dict(model=3), dict(nx=5), dict(cheb_degree=0), dict(nx=0), dict(ny=0),
+                dict(nx=-4), dict(lx=0.0), dict(ly=-1.0), dict(E=0.0), dict(Gc=0.0),
+                dict(k_ell=-1.0), dict(max_am=0), dict(elem3d_min_nodes=-1)):
         q = fracture.make_params(**dict(workloads.tension(64, 0.05), **bad))
         assert fracture.fracture_workspace_bytes(q) == 0, bad
 
