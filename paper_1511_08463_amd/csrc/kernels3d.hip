@@ -341,20 +341,35 @@ __global__ __launch_bounds__(NB) void k_elem3d(Grid g, Mat m, const T* __restric
                             blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), tid);
 }
 
-// One thread per node (64 x 4 x 1 node tiles): the coarser levels, where
-// the element kernel's 15 x 15 x 4 tiles would give too few workgroups.  The
-// node sums the forces (or diagonal entries) of its 24 tetrahedra.
+// Node of this thread in a one-dimensional launch of 256-thread blocks over
+// the N nodes of g (false past the last node).  Rows of the coarse levels are
+// 5 to 65 nodes long; walking the nodes flat keeps every lane of a wavefront
+// busy where 64-wide row tiles would leave up to half of them idle.
+__device__ __forceinline__ bool flat_node3(const Grid& g, int& i, int& j, int& k) {
+  const int n = blockIdx.x * NB + threadIdx.x + NB_X * threadIdx.y;
+  if (n >= g.N) return false;
+  const int W = g.nx + 1, H = g.ny + 1, r = n / W;
+  i = n - r * W;
+  j = r % H;
+  k = r / H;
+  return true;
+}
+
+static dim3 flat_grid3(const Grid& g) { return dim3((unsigned)((g.N + NB - 1) / NB)); }
+
+// One thread per node, walked flat: the coarser levels, where the element
+// kernel's 15 x 15 x 4 tiles would give too few workgroups.  The node sums
+// the forces (or diagonal entries) of its 24 tetrahedra.
 template <int MODE, bool FA, bool HASX, int RED, bool EIG, class T>
 __global__ __launch_bounds__(NB) void k_node3d(Grid g, Mat m, const T* __restrict__ coef, T kell,
                                                const T* __restrict__ x, T* __restrict__ y,
                                                const T* __restrict__ b, const T* __restrict__ dg,
                                                const T* __restrict__ din, T* __restrict__ dout,
                                                T cd, T cr, int mask, Red red) {
-  const int i = blockIdx.x * NB_X + threadIdx.x;
-  const int j = blockIdx.y * NB_Y + threadIdx.y;
-  const int k = blockIdx.z;
+  int i = 0, j = 0, k = 0;
+  const bool in = flat_node3(g, i, j, k);
   double acc = 0.0;
-  if (i <= g.nx && j <= g.ny) {
+  if (in) {
     const int N = g.N, n = i + (g.nx + 1) * (j + (g.ny + 1) * k);
     T f[3], d[3];
     node_force3d<FA, HASX, MODE == M3_DIAG, EIG>(g, m, coef, kell, x, i, j, k, f, d);
@@ -416,7 +431,7 @@ template <class T>
 void launch_apply3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
                     double kell, const T* x, T* y, const ND<T>* b, int mask, int red, Red r) {
   const bool el = use_elem3d(g);
-  const dim3 gr = el ? elem_grid3(g) : node_grid3(g);
+  const dim3 gr = el ? elem_grid3(g) : flat_grid3(g);
   const dim3 bl = el ? dim3(E3_T, E3_T) : dim3(NB_X, NB_Y);
   const T k = T(kell);
   const bool eig = fine && g.eig_dT != 0.0;
@@ -450,7 +465,7 @@ template <class T>
 void launch_resid3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
                     double kell, const T* x, T* r, const ND<T>* b, bool red, Red rr) {
   const bool el = use_elem3d(g);
-  const dim3 gr = el ? elem_grid3(g) : node_grid3(g);
+  const dim3 gr = el ? elem_grid3(g) : flat_grid3(g);
   const dim3 bl = el ? dim3(E3_T, E3_T) : dim3(NB_X, NB_Y);
   const T k = T(kell);
   const bool eig = fine && g.eig_dT != 0.0;
@@ -507,7 +522,7 @@ void launch_smooth3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, con
     return;
   }
   const bool el = use_elem3d(g);
-  const dim3 gr = el ? elem_grid3(g) : node_grid3(g);
+  const dim3 gr = el ? elem_grid3(g) : flat_grid3(g);
   const dim3 bl = el ? dim3(E3_T, E3_T) : dim3(NB_X, NB_Y);
   Red none{};
   const T k = T(kell);
@@ -531,7 +546,7 @@ template <class T>
 void launch_diag3d(hipStream_t st, const Grid& g, const Mat& m, bool fine, const T* coef,
                    double kell, T* dg) {
   const bool el = use_elem3d(g);
-  const dim3 gr = el ? elem_grid3(g) : node_grid3(g);
+  const dim3 gr = el ? elem_grid3(g) : flat_grid3(g);
   const dim3 bl = el ? dim3(E3_T, E3_T) : dim3(NB_X, NB_Y);
   Red none{};
   const T k = T(kell);
@@ -631,8 +646,8 @@ __global__ __launch_bounds__(NB) void k_restrict_smooth3d(Grid gf, Grid gc, cons
                                                           const T* __restrict__ dgc,
                                                           T* __restrict__ xc, T* __restrict__ dc,
                                                           T cr) {
-  const int I = blockIdx.x * NB_X + threadIdx.x, J = blockIdx.y * NB_Y + threadIdx.y, K = blockIdx.z;
-  if (I > gc.nx || J > gc.ny) return;
+  int I = 0, J = 0, K = 0;
+  if (!flat_node3(gc, I, J, K)) return;
   restrict_node3d(gf, gc, rf, bc, I, J, K);
   const int nc = I + (gc.nx + 1) * (J + (gc.ny + 1) * K);
 #pragma unroll
@@ -648,21 +663,21 @@ __global__ __launch_bounds__(NB) void k_restrict_smooth3d(Grid gf, Grid gc, cons
 template <class T>
 void launch_restrict_smooth3d(hipStream_t st, const Grid& gf, const Grid& gc, const T* rf, T* bc,
                               const T* dgc, T* xc, T* dc, double cr) {
-  hipLaunchKernelGGL((k_restrict_smooth3d<T>), node_grid3(gc), dim3(NB_X, NB_Y), 0, st, gf, gc, rf,
+  hipLaunchKernelGGL((k_restrict_smooth3d<T>), flat_grid3(gc), dim3(NB_X, NB_Y), 0, st, gf, gc, rf,
                      bc, dgc, xc, dc, T(cr));
 }
 
 template <class T>
 __global__ __launch_bounds__(NB) void k_prolong3d(Grid gf, Grid gc, const T* __restrict__ xc,
                                                   T* __restrict__ xf) {
-  const int i = blockIdx.x * NB_X + threadIdx.x, j = blockIdx.y * NB_Y + threadIdx.y, k = blockIdx.z;
-  if (i > gf.nx || j > gf.ny) return;
+  int i = 0, j = 0, k = 0;
+  if (!flat_node3(gf, i, j, k)) return;
   prolong_node3d(gf, gc, xc, xf, i, j, k);
 }
 
 template <class T>
 void launch_prolong3d(hipStream_t st, const Grid& gf, const Grid& gc, const T* xc, T* xf) {
-  hipLaunchKernelGGL((k_prolong3d<T>), node_grid3(gf), dim3(NB_X, NB_Y), 0, st, gf, gc, xc, xf);
+  hipLaunchKernelGGL((k_prolong3d<T>), flat_grid3(gf), dim3(NB_X, NB_Y), 0, st, gf, gc, xc, xf);
 }
 
 // Dirichlet values of the thermal problem are all zero.
