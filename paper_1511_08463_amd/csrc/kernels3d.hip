@@ -839,9 +839,12 @@ __global__ __launch_bounds__(NB) void k_vi_eval3d(Grid g, Helm3 hp, const double
                                                   uint8_t* __restrict__ mask,
                                                   double* __restrict__ hdinv, Red r2, Red rm,
                                                   Red rlo, Red rhi) {
-  const int i = blockIdx.x * NB_X + threadIdx.x, j = blockIdx.y * NB_Y + threadIdx.y, k = blockIdx.z;
+  // nodes walked flat: rows of 129 nodes would leave a third of the
+  // wavefronts of 64-wide row tiles with one busy lane
+  int i = 0, j = 0, k = 0;
+  const bool in = flat_node3(g, i, j, k);
   double p2 = 0.0, pm = 0.0, jlo = -INFINITY, jhi = -INFINITY;
-  if (i <= g.nx && j <= g.ny) {
+  if (in) {
     const int n = i + (g.nx + 1) * (j + (g.ny + 1) * k);
     const double mu = TRIAL ? S[mu_slot] : 0.0;
     double Ha, gv, Hd;
@@ -879,7 +882,7 @@ void launch_vi_eval3d(hipStream_t st, const Grid& g, double cL, double cM, doubl
                       const double* S, int mu_slot, double zeta, double* F, double* phi,
                       uint8_t* mask, double* hdinv, Red r2, Red rm, Red rlo, Red rhi, bool trial) {
   Helm3 hp{cL, cM, cm};
-  dim3 gr = node_grid3(g), bl(NB_X, NB_Y);
+  dim3 gr = flat_grid3(g), bl(NB_X, NB_Y);
   if (trial)
     hipLaunchKernelGGL((k_vi_eval3d<true>), gr, bl, 0, st, g, hp, w2, a, d, lo, S, mu_slot, zeta, F,
                        phi, mask, hdinv, r2, rm, rlo, rhi);
